@@ -1,0 +1,148 @@
+"""Independent restatements used to pin the oracle (tests only).
+
+Nothing here calls the oracle: the operator is assembled from Kronecker
+products as the paper writes it (Sec. 3.2, L = kron(I,T) + kron(T,I) with
+T = tridiag(-1, 2, -1)), the transfer operators from their 1D matrices, and
+the physics references from closed forms and the partial-wave expansion.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+from scipy import special
+from scipy.integrate import solve_ivp
+
+
+# ------------------------------------------------------------------ matrices
+
+def T1(m):
+    return sp.diags([-np.ones(m - 1), 2 * np.ones(m), -np.ones(m - 1)], [-1, 0, 1], format="csr")
+
+
+def I1(m):
+    return sp.identity(m, format="csr")
+
+
+def kron_operator(m, h, gamma, kappa):
+    """A = e^{-2ig} sum_k kron(..., T_k / h_k^2, ...) - diag(kappa), x fastest."""
+    dim = len(m)
+    rot = np.exp(-2j * gamma)
+    A = None
+    for k in range(dim):
+        mats = []
+        # x is the fastest index, so the x factor is the LAST kron factor
+        for ax in reversed(range(dim)):
+            mats.append(T1(m[ax]) / h[ax] ** 2 if ax == k else I1(m[ax]))
+        term = mats[0]
+        for mm in mats[1:]:
+            term = sp.kron(term, mm, format="csr")
+        A = term if A is None else A + term
+    return (rot * A - sp.diags(np.asarray(kappa).ravel())).tocsr()
+
+
+def fw_1d(mf):
+    """1D full weighting (1/4, 1/2, 1/4), coarse I <- fine 2I-1, 2I, 2I+1."""
+    mc = (mf - 1) // 2
+    R = np.zeros((mc, mf))
+    for I in range(mc):
+        f = 2 * I + 1
+        R[I, f - 1], R[I, f], R[I, f + 1] = 0.25, 0.5, 0.25
+    return R
+
+
+def kron_list(mats_x_first):
+    """kron with the x matrix last (x fastest)."""
+    out = None
+    for M in reversed(mats_x_first):
+        out = M if out is None else np.kron(out, M)
+    return out
+
+
+def fw(mf):
+    return kron_list([fw_1d(m) for m in mf])
+
+
+def prolong(mf):
+    """Linear interpolation is 2 x (1D full weighting)^T per axis."""
+    return kron_list([2.0 * fw_1d(m).T for m in mf])
+
+
+def inject_index(mf):
+    """Fine interior indices (x fastest, flattened) of the coarse nodes."""
+    mc = [(m - 1) // 2 for m in mf]
+    idx = [2 * np.arange(c) + 1 for c in mc]
+    grids = np.meshgrid(*idx[::-1], indexing="ij")[::-1]
+    flat = np.zeros_like(grids[0])
+    stride = 1
+    for k, gk in enumerate(grids):
+        flat = flat + gk * stride
+        stride *= mf[k]
+    return flat.ravel()
+
+
+def dense_vcycle(m, h, gamma, kappa, b, u, nu1, nu2, omega, coarsest_n=8):
+    """One V(nu1, nu2) cycle written with dense matrices."""
+    m = list(m)
+    A = kron_operator(m, h, gamma, kappa).toarray()
+    if min(mk + 1 for mk in m) <= coarsest_n:
+        return np.linalg.solve(A, b)
+    D = np.diag(A)
+    for _ in range(nu1):
+        u = u + omega * (b - A @ u) / D
+    r = b - A @ u
+    R = fw(m)
+    bc = R @ r
+    mc = [(mk - 1) // 2 for mk in m]
+    kc = np.asarray(kappa).ravel()[inject_index(m)]
+    ec = dense_vcycle(mc, [2 * hk for hk in h], gamma, kc, bc, np.zeros_like(bc),
+                      nu1, nu2, omega, coarsest_n)
+    u = u + prolong(m) @ ec
+    for _ in range(nu2):
+        u = u + omega * (b - A @ u) / D
+    return u
+
+
+# ------------------------------------------------------------------ physics
+
+def born_2d(k0, amp, sigma, alpha_dirs, eta):
+    """Fourier transform of k0^2 amp exp(-|x|^2/sigma^2) at k0 (alpha - eta):
+    k0^2 amp pi sigma^2 exp(-k0^2 sigma^2 |alpha - eta|^2 / 4)."""
+    d2 = np.sum((alpha_dirs - eta[None, :]) ** 2, axis=1)
+    return k0 ** 2 * amp * math.pi * sigma ** 2 * np.exp(-(k0 ** 2) * sigma ** 2 * d2 / 4.0)
+
+
+def born_nd(k0, amp, sigma, alpha_dirs, eta):
+    d = alpha_dirs.shape[1]
+    d2 = np.sum((alpha_dirs - eta[None, :]) ** 2, axis=1)
+    return k0 ** 2 * amp * (math.pi * sigma ** 2) ** (d / 2) * np.exp(-(k0 ** 2) * sigma ** 2 * d2 / 4.0)
+
+
+def partial_wave_2d(k0, chi, angles, mmax=25, r0=1e-3, r1=9.0):
+    """Far field of a radially symmetric real scatterer k^2 = k0^2 (1 + chi(r))
+    in the normalisation F = -4i sum_m t_m e^{i m phi}, with t_m from the
+    regular radial solution matched to J_m + t_m H_m^(1) at r1."""
+    def rhs(r, y, m):
+        R, dR = y[0] + 1j * y[1], y[2] + 1j * y[3]
+        ddR = -dR / r - (k0 ** 2 * (1.0 + chi(r)) - m * m / (r * r)) * R
+        return [dR.real, dR.imag, ddR.real, ddR.imag]
+
+    t = np.zeros(mmax + 1, dtype=np.complex128)
+    for m in range(mmax + 1):
+        # regular start R ~ r^m, scaled to R(r0) = 1 (only R'/R matters)
+        kap0 = k0 ** 2 * (1.0 + chi(r0))
+        dR0 = m / r0 if m > 0 else -0.5 * kap0 * r0
+        sol = solve_ivp(rhs, (r0, r1), [1.0, 0.0, dR0, 0.0], args=(m,), rtol=1e-12,
+                        atol=1e-14, method="DOP853")
+        R = sol.y[0, -1] + 1j * sol.y[1, -1]
+        dR = sol.y[2, -1] + 1j * sol.y[3, -1]
+        beta = dR / R
+        x = k0 * r1
+        J, dJ = special.jv(m, x), special.jvp(m, x)
+        H, dH = special.hankel1(m, x), special.h1vp(m, x)
+        t[m] = (k0 * dJ - beta * J) / (beta * H - k0 * dH)
+    F = np.zeros(len(angles), dtype=np.complex128)
+    for m in range(mmax + 1):
+        F += (1 if m == 0 else 2) * t[m] * np.cos(m * angles)
+    return -4j * F, t
