@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Far-field maps per second on one MI355X.
+
+One step = one far-field map of the 2D bumps workload (2048 intervals per
+axis on [-10,10]^2, 8 seeded Gaussian bumps, k0 = 1, contour angle 30 deg):
+plane-wave right-hand side, multigrid solve to ||r|| <= 1e-10 ||b|| and the
+far field at 360 outgoing angles, with every input already in HBM.  `value`
+is the mixed-precision path (FP32 V(2,2) cycles inside FP64 refinement, FP64
+far field); the plain FP64 multigrid path is timed beside it on the same map.
+
+Also reported: the roofline of the dominant kernel (the finest-level
+weighted-Jacobi sweep), timed live with HIP events on its stream, and the
+FP64 CPU oracle on the host cores (one map of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_jacobi_fp32_bumps2d_2048.json")
+STENCIL_SRC = os.path.join(ROOT, "paper_1211_4461_amd", "csrc", "ffmg_stencil.hip")
+
+
+def src_hash():
+    with open(STENCIL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(bytes_alg):
+    """HBM bytes per launch from committed rocprofv3 --pmc counters, or None
+    if absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("src_sha") != src_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def run_path(ff, torch, w, precision, steps, warmup, profile):
+    opts = ff.default_options(precision=precision)
+    h, coef = ff.setup_workload(w, options=opts)
+    b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
+    u = torch.empty_like(b)
+    F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
+    info = None
+
+    def step():
+        nonlocal info
+        ff.mg_rhs_plane_wave(h, w.eta, b)
+        u.zero_()
+        info = ff.mg_solve(h, b, u, tol=w.tol)
+        ff.farfield_map(h, w.eta, u, w.dirs, out=F)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if profile:
+        ff.mg_profile_enable(h, True)
+        ff.mg_profile_read(h, ff.KERNEL_SWEEP)
+        ff.mg_profile_read(h, ff.KERNEL_FARFIELD)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = None
+    if profile:
+        sweep_ms, sweep_n = ff.mg_profile_read(h, ff.KERNEL_SWEEP)
+        ffm_ms, ffm_n = ff.mg_profile_read(h, ff.KERNEL_FARFIELD)
+        ff.mg_profile_enable(h, False)
+        prof = {"sweep_ms": sweep_ms, "sweep_n": sweep_n, "ff_ms": ffm_ms, "ff_n": ffm_n}
+    out = {"ms_per_step": 1e3 * dt / steps, "maps_per_s": steps / dt, "cycles": info.cycles,
+           "rel_residual": info.rel_residual, "conv_factor": info.conv_factor, "F": F.cpu().numpy(),
+           "prof": prof}
+    h.destroy()
+    return out
+
+
+def cpu_baseline(w):
+    """The FP64 oracle, as it stands, on one map of the same workload."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    g = orc.Grid(w.dim, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    t0 = time.perf_counter()
+    mg = orc.Multigrid(g, w.gamma, kappa, nu1=w.nu1, nu2=w.nu2, omega=w.omega)
+    t1 = time.perf_counter()
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    u, st, k, _ = mg.solve(b, tol=w.tol)
+    F = orc.farfield(g, w.gamma, k0, q, w.eta, u, w.dirs)
+    t2 = time.perf_counter()
+    return {"value": 1.0 / (t2 - t1), "unit": "maps/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 map of the same workload ({w.n}^2 intervals, solve to {w.tol:g} in {k} V(2,2) cycles "
+                      f"+ {len(w.dirs)}-angle far field), setup ({t1 - t0:.2f} s) excluded",
+            "seconds": t2 - t1}, np.asarray(F)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=2048, help="intervals per axis")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multigrid sweeps and the far-field contraction are measured on one MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1211_4461_amd import ffmg
+    from paper_1211_4461_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    ffmg.lib()
+    w = W.bumps_2d(n=args.n, seed=1, k0=1.0, M=360)
+    N = w.N
+
+    if args.calib_copy:
+        x = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, args.steps, args.warmup, profile=True)
+    plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, max(args.steps // 2, 2),
+                                                 args.warmup, profile=True)
+
+    # roofline of the dominant kernel: finest-level FP32 weighted-Jacobi sweep,
+    # algorithmic bytes = N * (read u, b, q + write u') = 32 B per point
+    pr = mixed["prof"]
+    bytes_alg = 32.0 * N
+    avg_ms = pr["sweep_ms"] / max(pr["sweep_n"], 1)
+    achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
+    roof = {"kernel": "finest-level weighted-Jacobi sweep (FP32, k_stencil2d<float,float,JACOBI,1>)",
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(bytes_alg),
+            "bytes_per_launch": bytes_alg, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": pr["sweep_n"]}
+
+    line = {
+        "metric": "far-field maps/sec at 1e-6 rel error: plain FP64 MG vs mixed-prec/learned MG",
+        "value": round(mixed["maps_per_s"], 3),
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(mixed["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"bumps_2d n={args.n} box=[-10,10]^2 k0=1 gamma=30deg 8 bumps seed=1",
+                   "unknowns": N, "angles": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
+                   "form": "FP32 V-cycles in FP64 refinement + FP64 MFMA far field"},
+        "mixed": {"cycles": mixed["cycles"], "rel_residual": mixed["rel_residual"],
+                  "conv_factor": round(mixed["conv_factor"], 4),
+                  "ff_ms_per_map": round(pr["ff_ms"] / max(pr["ff_n"], 1), 3)},
+        "roofline": roof,
+    }
+    if plain is not None:
+        ef = float(np.linalg.norm(mixed["F"] - plain["F"]) / np.linalg.norm(plain["F"]))
+        pp = plain["prof"]
+        p_avg = pp["sweep_ms"] / max(pp["sweep_n"], 1)
+        line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
+                              "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
+                              "sweep_gbs": round(64.0 * N / (p_avg * 1e-3) / 1e9, 1),
+                              "sweep_us": round(p_avg * 1e3, 2)}
+        line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
+        line["mixed_vs_plain_farfield_rel_err"] = ef
+    if not args.no_cpu_baseline:
+        cb, Fo = cpu_baseline(w)
+        line["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
+        line["farfield_rel_err_vs_oracle"] = float(np.linalg.norm(mixed["F"] - Fo) / np.linalg.norm(Fo))
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

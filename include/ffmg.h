@@ -1,0 +1,176 @@
+/*
+ * ffmg.h -- C ABI of the MI355X (gfx950) complex-contour multigrid far-field
+ * library.
+ *
+ * Method: Cools, Reps & Vanroose, "An efficient multigrid calculation of the
+ * Far Field map for Helmholtz and Schroedinger equations" (arXiv 1211.4461).
+ * The far-field map F(alpha) (Sec. 2.2, eq. FFmap) of a scattering problem is
+ * computed in two steps:
+ *   1. the scattered wave u is solved on the rotated grid z = e^{i gamma} x
+ *      (Sec. 3.1, eq. helmholtz_cc), a damped system that multigrid solves
+ *      (Sec. 3.2, eq. csg and eq. csl);
+ *   2. F is the quadrature of the source plus scattered wave against
+ *      exp(-i k0 alpha.z) over the same contour grid (Sec. 3.1,
+ *      eq. I2complex, together with eq. i1).
+ *
+ * Discrete problem (all entry points share it):
+ *   - grid: n[k] intervals per axis on [lo[k], hi[k]], h_k = (hi-lo)/n,
+ *     interior nodes x_i = lo + i h_k, i = 1..n[k]-1; N = prod (n[k]-1)
+ *     unknowns, stored x fastest (then y, then z), no padding; homogeneous
+ *     Dirichlet values outside the interior (Sec. 4, n^d mesh on the box).
+ *   - operator: (A u)_j = sum_k c_k (2u_j - u_{j-e_k} - u_{j+e_k}) - kappa_j u_j
+ *     with c_k = e^{-2 i gamma}/h_k^2 (Sec. 3.2, eq. csg) and
+ *     kappa_j = k0^2 + q_j.
+ *   - contrast q_j = k^2(z_j) - k0^2 = k0^2 chi(z_j) (Sec. 2.1); for the
+ *     Schroedinger form (Sec. 5) k^2 = 2(E - V), k0 = sqrt(2E), q_j = -2 V(z_j).
+ *   - right-hand side for an incoming plane wave along eta:
+ *     b_j = q_j exp(i k0 eta.z_j) (Sec. 2.1, eq. helmholtz_in on the contour).
+ *   - far field: F(alpha) = e^{i d gamma} prod_k h_k
+ *                 sum_j exp(-i k0 alpha.z_j) q_j (u_in(z_j) + u_j).
+ *
+ * Numbers: every array crossing this ABI is complex128, interleaved (re, im)
+ * pairs of IEEE doubles.  FP32 is internal only (FFMG_FP32_IR).
+ *
+ * Device pointers are HIP device allocations on the current device; the
+ * library never frees caller memory.  One handle is used by one host thread
+ * and one stream at a time.  No C++ exception crosses this ABI: every call
+ * returns a status, and ffmg_last_error() gives the text of the last failure
+ * on a handle.
+ */
+#ifndef FFMG_H
+#define FFMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FFMG_OK = 0,
+    FFMG_EINVAL = 1,      /* invalid argument; nothing was written            */
+    FFMG_ENOMEM = 2,      /* a device allocation failed                       */
+    FFMG_EDEVICE = 3,     /* a HIP call failed; the handle must be destroyed  */
+    FFMG_ENOCONV = 4,     /* no convergence; u holds the last iterate         */
+    FFMG_ERANGE = 5,      /* contour exponentials exceed the working range    */
+    FFMG_ENAN = 6         /* NaN or Inf in an input array                     */
+} ffmg_status;
+
+typedef enum { FFMG_HELMHOLTZ = 0, FFMG_SCHRODINGER = 1 } ffmg_kind;
+typedef enum { FFMG_FP64 = 0, FFMG_FP32_IR = 1 } ffmg_precision;
+typedef enum { FFMG_SMOOTH_JACOBI = 0, FFMG_SMOOTH_LEARNED = 1 } ffmg_smoother;
+typedef enum { FFMG_FF_FP64 = 0, FFMG_FF_BF16X3 = 1, FFMG_FF_BF16X6 = 2 } ffmg_ff_precision;
+
+/* The scattering problem (Sec. 2.1 Helmholtz; Sec. 5 Schroedinger). */
+typedef struct ffmg_problem {
+    int dim;              /* 2 or 3                                            */
+    int64_t n[3];         /* intervals per axis: power of two, >= coarsest_n   */
+    double lo[3], hi[3];  /* box, lo < hi                                      */
+    double gamma;         /* contour angle (rad), 0 < gamma < pi/2 (Sec. 3.3)  */
+    int kind;             /* ffmg_kind                                         */
+    double k0;            /* Helmholtz: outer wavenumber (> 0); Schroedinger: ignored */
+    double energy;        /* Schroedinger: E > 0 (k0 = sqrt(2E)); Helmholtz: ignored  */
+    const void *coef;     /* DEVICE complex128[N], x fastest:
+                             Helmholtz: contrast k^2(z_j) - k0^2 = k0^2 chi(z_j);
+                             Schroedinger: V(z_j).  Copied at setup; the caller
+                             may free it afterwards.                          */
+} ffmg_problem;
+
+/* Solver options.  ffmg_default_options() fills V(2,2), omega = 0.8,
+ * coarsest n = 8 (7^d unknowns, solved exactly), 200 cycles, FP64. */
+typedef struct ffmg_options {
+    int nu1, nu2;         /* pre / post smoothing sweeps (>= 0, sum >= 1)      */
+    double omega;         /* Jacobi damping, 0 < omega <= 1                    */
+    int coarsest_n;       /* intervals per axis on the coarsest grid (>= 4)    */
+    int max_cycles;       /* mg_solve cycle limit (>= 1)                       */
+    int precision;        /* ffmg_precision                                    */
+    int smoother;         /* ffmg_smoother                                     */
+    const float *smoother_weights; /* HOST, learned smoother parameters, or NULL */
+    int ff_precision;     /* ffmg_ff_precision                                 */
+    int tile_config;      /* 0 = autotuned / default, else a fixed variant     */
+    void *stream;         /* hipStream_t; NULL = the null stream               */
+} ffmg_options;
+
+typedef struct ffmg_solve_info {
+    int cycles;           /* V-cycles (FP64) or refinement steps (FP32_IR)     */
+    int status;           /* ffmg_status of the solve                          */
+    double rel_residual;  /* ||b - A u||_2 / ||b||_2 in FP64 at return         */
+    double conv_factor;   /* (||r_k|| / ||r_0||)^(1/k)  (Sec. 5.4 definition)  */
+    int fell_back;        /* learned smoother replaced by Jacobi (1) or not    */
+    double t_solve_ms;    /* wall time of the solve on the stream              */
+} ffmg_solve_info;
+
+typedef struct ffmg_handle ffmg_handle;
+
+void ffmg_default_options(ffmg_options *o);
+
+/* Build the multigrid hierarchy for one problem (Sec. 4; coarse grids
+ * n/2^l down to coarsest_n, coefficients injected, coarse operators
+ * rediscretised at 2^l h; the coarsest system is inverted exactly, as the
+ * 7^3 grid of the F(5) cycle in Sec. 5.5).  Copies coef; allocates all device
+ * workspace.  EINVAL on bad sizes or angles; ENAN if coef holds NaN/Inf;
+ * ENOMEM / EDEVICE on HIP failures.  *out is NULL on failure. */
+ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle **out);
+
+/* b_j = q_j exp(i k0 eta.z_j): the plane-wave right-hand side of
+ * eq. helmholtz_cc.  eta: HOST double[3] unit vector (first dim entries used).
+ * b: DEVICE complex128[N], written.  ERANGE if |exp(i k0 eta.z)| would
+ * overflow double. */
+ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b);
+
+/* One V(nu1, nu2) cycle in place (Sec. 4): omega-Jacobi smoothing,
+ * full-weighting restriction of the residual, recursive coarse correction,
+ * bilinear/trilinear interpolation, exact coarsest solve.  b: DEVICE
+ * complex128[N], read; u: DEVICE complex128[N], updated.  Always FP64. */
+ffmg_status mg_vcycle(ffmg_handle *h, const void *b, void *u);
+
+/* Solve A u = b by V-cycles (FP64) or by FP32 V-cycles inside FP64
+ * iterative refinement (FP32_IR: FP64 outer residual, FP64 update, FP64
+ * coarsest solve), from the guess in u, until ||b - A u||_2 <= tol ||b||_2
+ * (residual-reduction tolerance, Sec. 4).  u: DEVICE complex128[N], in:
+ * guess, out: solution.  ENOCONV after max_cycles or when the residual grows
+ * on 3 consecutive cycles; u then holds the last iterate and info is filled.
+ * b = 0 returns u = 0 after 0 cycles.  info may be NULL.  Synchronises. */
+ffmg_status mg_solve(ffmg_handle *h, const void *b, void *u, double tol, ffmg_solve_info *info);
+
+/* Far-field map (eq. FFmap moved onto the contour, eq. I2complex):
+ *   F_m = e^{i d gamma} prod h_k sum_j exp(-i k0 alpha_m.z_j) q_j (u_in,j + u_j)
+ * for n_dirs directions alpha_m (HOST double[n_dirs][dim], unit vectors).
+ * The kernel factorises over the axes, so the sum runs as a chain of
+ * MFMA contractions; directions sharing their last component share the first
+ * contraction (3D azimuth x polar grids).  eta: HOST double[3]; u: DEVICE
+ * complex128[N] (NULL = zero scattered wave: the Born term); F: complex128
+ * [n_dirs], HOST or DEVICE memory.  ff_precision selects FP64 MFMA or split
+ * BF16 MFMA with FP32 accumulation.  Synchronises. */
+ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs,
+                         const double *dirs, void *F);
+
+/* Au = A u (the operator of eq. csg), DEVICE complex128[N] each. */
+ffmg_status mg_apply(ffmg_handle *h, const void *u, void *Au);
+
+/* One omega-Jacobi sweep u_out = u + omega D^{-1} (b - A u), out of place. */
+ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out);
+
+/* ||b - A u||_2 (FP64 accumulation) into *rnorm (host). */
+ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, double *rnorm);
+
+/* Kernel timing (instrumentation for benchmarks).  When enabled, a pair of
+ * HIP events on the handle's stream brackets every launch of kernel 0 (the
+ * finest-level weighted-Jacobi sweep, FP64 or FP32) and kernel 1 (the
+ * far-field contraction).  mg_profile_read synchronises, returns the summed
+ * duration (ms) and launch count of one kernel, and clears its record. */
+ffmg_status mg_profile_enable(ffmg_handle *h, int enable);
+ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_t *count);
+
+/* Number of levels and the interior sizes of level l (n[k] - 1 per axis). */
+int mg_num_levels(const ffmg_handle *h);
+ffmg_status mg_level_shape(const ffmg_handle *h, int level, int64_t m[3]);
+
+void mg_destroy(ffmg_handle *h);
+const char *ffmg_strerror(ffmg_status s);
+const char *ffmg_last_error(const ffmg_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFMG_H */

@@ -1,0 +1,70 @@
+// ffmg_device.hpp -- device-side building blocks shared by the library's HIP
+// kernels: interleaved complex numbers, the contour stencil at one point, and
+// the XCD-aware block-to-tile map.  gfx950 (CDNA4) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ffmg {
+
+// Interleaved complex value; 16 B (double) / 8 B (float) aligned so that one
+// element is one 128-bit / 64-bit vector load.
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T re, im;
+};
+using cd = cx<double>;
+using cf = cx<float>;
+
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__host__ __device__ __forceinline__ cx<T> recip(cx<T> a)
+{
+    T d = a.re * a.re + a.im * a.im;
+    T inv = T(1) / d;
+    return {a.re * inv, -a.im * inv};
+}
+template <typename T>
+__host__ __device__ __forceinline__ T abs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename To, typename Ti>
+__host__ __device__ __forceinline__ cx<To> cvt(cx<Ti> a) { return {To(a.re), To(a.im)}; }
+
+// Parameters of the contour operator on one grid level:
+//   (A u)_j = sum_k c_k (2u_j - u_{j-e_k} - u_{j+e_k}) - (k0^2 + q_j) u_j,
+//   c_k = e^{-2 i gamma} / h_k^2,  D_j = 2 sum_k c_k - k0^2 - q_j.
+template <typename T>
+struct Stencil {
+    int mx, my, mz;     // interior extents (mz = 1 in 2D)
+    cx<T> c[3];         // c_k
+    cx<T> csum2;        // 2 sum_k c_k
+    T k02;              // k0^2
+    T omega;            // Jacobi damping
+};
+
+// Block index -> tile index such that each XCD (blocks are dispatched
+// round-robin over the 8 XCDs) receives a contiguous run of tiles, so halo
+// rows shared by neighbouring tiles are served by the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    const int X = 8;
+    int xcd = b % X, local = b / X;
+    int q = nb / X, r = nb % X;
+    return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+}  // namespace ffmg

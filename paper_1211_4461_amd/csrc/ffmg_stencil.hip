@@ -1,0 +1,667 @@
+// ffmg_stencil.hip -- the multigrid kernels of the contour solver on gfx950:
+// operator / residual / weighted-Jacobi sweeps (Sec. 3.2 eq. csg; Sec. 4
+// omega-Jacobi), full-weighting restriction and bilinear / trilinear
+// interpolation (Sec. 4), residual norms, and the setup kernels (contrast,
+// injected coarse coefficients, exact inverse of the coarsest operator as in
+// the F(5) cycle of Sec. 5.5, plane-wave right-hand side of Sec. 2.1).
+//
+// All of these are HBM-bandwidth bound (about one flop per byte).  The sweeps
+// stage a u tile with its halo in LDS (2D: one 64 x TY tile; 3D: the centre
+// z-plane of a 64 x 8 column that marches in z, with the z-neighbours held in
+// registers), read b and q once, coalesced, and write the result once.
+#include <math.h>
+
+#include "ffmg_internal.hpp"
+
+namespace ffmg {
+
+constexpr int TY2 = 16;   // 2D tile: 64 x 16 points per 256-thread block
+constexpr int TY3 = 8;    // 3D tile: 64 x 8 points per plane
+constexpr int TZ3 = 32;   // 3D: planes per block
+
+template <typename T>
+Stencil<T> make_stencil(const LevelGeom &g, double gamma, double k02, double omega)
+{
+    Stencil<T> P;
+    P.mx = g.m[0];
+    P.my = g.m[1];
+    P.mz = g.m[2];
+    double cr = cos(-2.0 * gamma), ci = sin(-2.0 * gamma);
+    double sr = 0.0, si = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        if (k < g.dim) {
+            double h2 = g.h[k] * g.h[k];
+            double pr = cr / h2, pi = ci / h2;
+            P.c[k] = cx<T>{T(pr), T(pi)};
+            sr += 2.0 * pr;
+            si += 2.0 * pi;
+        } else {
+            P.c[k] = cx<T>{T(0), T(0)};
+        }
+    }
+    P.csum2 = cx<T>{T(sr), T(si)};
+    P.k02 = T(k02);
+    P.omega = T(omega);
+    return P;
+}
+template Stencil<double> make_stencil<double>(const LevelGeom &, double, double, double);
+template Stencil<float> make_stencil<float>(const LevelGeom &, double, double, double);
+
+// ---------------------------------------------------------------------------
+// The point update shared by all stencil kernels.
+// MODE_RESID writes rscale * r converted to TO (the FP64 residual of the
+// refinement loop is written as a scaled FP32 right-hand side this way).
+template <typename T, typename TO, int MODE>
+__device__ __forceinline__ void point_update(const Stencil<T> &P, T rscale, cx<T> uc, cx<T> lap, size_t j,
+                                             const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                             cx<TO> *__restrict__ out, double &acc)
+{
+    cx<T> qj = q[j];
+    cx<T> kap = {P.k02 + qj.re, qj.im};
+    cx<T> Au = lap - kap * uc;
+    if (MODE == MODE_APPLY) {
+        out[j] = cvt<TO>(Au);
+    } else if (MODE == MODE_JACOBI0) {
+        // first sweep from a zero guess: u' = omega b / D
+        cx<T> D = P.csum2 - kap;
+        out[j] = cvt<TO>(P.omega * (b[j] * recip(D)));
+    } else {
+        cx<T> r = b[j] - Au;
+        if (MODE == MODE_RESID) {
+            out[j] = cvt<TO>(rscale * r);
+            acc += (double)abs2(r);
+        } else if (MODE == MODE_RNORM) {
+            acc += (double)abs2(r);
+        } else {
+            cx<T> D = P.csum2 - kap;
+            out[j] = cvt<TO>(uc + P.omega * (r * recip(D)));
+        }
+    }
+}
+
+__device__ __forceinline__ void block_sum_256(double acc, double *partial)
+{
+    __shared__ double red[4];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// 2D: 256 threads as 64 (x) x 4 (y), tile 64 x TY2, u tile + halo in LDS.
+// TAG only separates the finest-level launches into their own kernel symbol
+// (so a profiler's per-kernel statistics cover exactly those launches).
+template <typename T, typename TO, int MODE, int TAG>
+__global__ __launch_bounds__(256) void k_stencil2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                   const cx<T> *__restrict__ q, cx<TO> *__restrict__ out,
+                                                   Stencil<T> P, T rscale, int tiles_x, double *__restrict__ partial)
+{
+    __shared__ cx<T> s[TY2 + 2][66];
+    const int mx = P.mx, my = P.my;
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int tx0 = (tile % tiles_x) * 64, ty0 = (tile / tiles_x) * TY2;
+    const bool zero_u = (MODE == MODE_JACOBI0);
+    if (!zero_u) {
+        for (int i = threadIdx.x; i < (TY2 + 2) * 66; i += 256) {
+            int ly = i / 66, lx = i - ly * 66;
+            int gx = tx0 + lx - 1, gy = ty0 + ly - 1;
+            cx<T> v = {T(0), T(0)};
+            if (gx >= 0 && gx < mx && gy >= 0 && gy < my) v = u[(size_t)gy * mx + gx];
+            s[ly][lx] = v;
+        }
+        __syncthreads();
+    }
+    const int lx = threadIdx.x & 63;
+    const int gx = tx0 + lx;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < TY2 / 4; ++k) {
+        int ly = (threadIdx.x >> 6) + 4 * k;
+        int gy = ty0 + ly;
+        if (gx < mx && gy < my) {
+            size_t j = (size_t)gy * mx + gx;
+            cx<T> uc = {T(0), T(0)}, lap = {T(0), T(0)};
+            if (!zero_u) {
+                uc = s[ly + 1][lx + 1];
+                cx<T> two_u = T(2) * uc;
+                lap = P.c[0] * ((two_u - s[ly + 1][lx]) - s[ly + 1][lx + 2]);
+                lap = lap + P.c[1] * ((two_u - s[ly][lx + 1]) - s[ly + 2][lx + 1]);
+            }
+            point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
+        }
+    }
+    if (MODE == MODE_RESID || MODE == MODE_RNORM)
+        if (partial) block_sum_256(acc, partial);
+}
+
+// 3D: 256 threads as 64 (x) x 4 (y); each block owns a 64 x TY3 column of
+// TZ3 planes and marches up in z.  The centre plane (with its x/y halo) is
+// staged in a double-buffered LDS plane; u at z-1 and z+1 stays in registers.
+template <typename T, typename TO, int MODE, int TAG>
+__global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                   const cx<T> *__restrict__ q, cx<TO> *__restrict__ out,
+                                                   Stencil<T> P, T rscale, int tiles_x, int tiles_y,
+                                                   double *__restrict__ partial)
+{
+    constexpr int PY = TY3 / 4;
+    __shared__ cx<T> s[2][TY3 + 2][66];
+    const int mx = P.mx, my = P.my, mz = P.mz;
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    int txi = tile % tiles_x;
+    int rest = tile / tiles_x;
+    int tyi = rest % tiles_y, tzi = rest / tiles_y;
+    const int x0 = txi * 64, y0 = tyi * TY3, z0 = tzi * TZ3;
+    const int z1 = min(z0 + TZ3, mz);
+    const int lx = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
+    const int gx = x0 + lx;
+    const size_t plane = (size_t)mx * my;
+    const bool zero_u = (MODE == MODE_JACOBI0);
+
+    auto ld = [&](int x, int y, int z) -> cx<T> {
+        cx<T> v = {T(0), T(0)};
+        if (!zero_u && x >= 0 && x < mx && y >= 0 && y < my && z >= 0 && z < mz)
+            v = u[(size_t)z * plane + (size_t)y * mx + x];
+        return v;
+    };
+
+    cx<T> prev[PY], cur[PY], nxt[PY];
+#pragma unroll
+    for (int i = 0; i < PY; ++i) {
+        prev[i] = ld(gx, y0 + ly0 + 4 * i, z0 - 1);
+        cur[i] = ld(gx, y0 + ly0 + 4 * i, z0);
+    }
+    double acc = 0.0;
+    int it = 0;
+    for (int z = z0; z < z1; ++z, ++it) {
+        const int buf = it & 1;
+        if (!zero_u) {
+#pragma unroll
+            for (int i = 0; i < PY; ++i) s[buf][ly0 + 4 * i + 1][lx + 1] = cur[i];
+            for (int t = threadIdx.x; t < 2 * TY3 + 2 * 66; t += 256) {
+                if (t < 2 * TY3) {
+                    int side = t / TY3, yy = t - side * TY3;
+                    int xx = side ? 65 : 0;
+                    s[buf][yy + 1][xx] = ld(x0 + xx - 1, y0 + yy, z);
+                } else {
+                    int t2 = t - 2 * TY3;
+                    int side = t2 / 66, xx = t2 - side * 66;
+                    int yy = side ? TY3 + 1 : 0;
+                    s[buf][yy][xx] = ld(x0 + xx - 1, y0 + yy - 1, z);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < PY; ++i) nxt[i] = ld(gx, y0 + ly0 + 4 * i, z + 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < PY; ++i) {
+            int ly = ly0 + 4 * i;
+            int gy = y0 + ly;
+            if (gx < mx && gy < my) {
+                size_t j = (size_t)z * plane + (size_t)gy * mx + gx;
+                cx<T> uc = {T(0), T(0)}, lap = {T(0), T(0)};
+                if (!zero_u) {
+                    uc = cur[i];
+                    cx<T> two_u = T(2) * uc;
+                    lap = P.c[0] * ((two_u - s[buf][ly + 1][lx]) - s[buf][ly + 1][lx + 2]);
+                    lap = lap + P.c[1] * ((two_u - s[buf][ly][lx + 1]) - s[buf][ly + 2][lx + 1]);
+                    lap = lap + P.c[2] * ((two_u - prev[i]) - nxt[i]);
+                }
+                point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
+            }
+        }
+        if (!zero_u) {
+#pragma unroll
+            for (int i = 0; i < PY; ++i) {
+                prev[i] = cur[i];
+                cur[i] = nxt[i];
+            }
+        }
+    }
+    if (MODE == MODE_RESID || MODE == MODE_RNORM)
+        if (partial) block_sum_256(acc, partial);
+}
+
+static void grid_of(const LevelGeom &g, int &nb, int &tx, int &ty)
+{
+    tx = (g.m[0] + 63) / 64;
+    if (g.dim == 2) {
+        ty = (g.m[1] + TY2 - 1) / TY2;
+        nb = tx * ty;
+    } else {
+        ty = (g.m[1] + TY3 - 1) / TY3;
+        int tz = (g.m[2] + TZ3 - 1) / TZ3;
+        nb = tx * ty * tz;
+    }
+}
+
+int stencil_blocks(const LevelGeom &g)
+{
+    int nb, tx, ty;
+    grid_of(g, nb, tx, ty);
+    return nb;
+}
+
+template <typename T, typename TO, int MODE, int TAG = 0>
+static void launch_mode(const LevelGeom &g, const Stencil<T> &P, T rscale, const cx<T> *u, const cx<T> *b,
+                        const cx<T> *q, cx<TO> *out, double *partial, hipStream_t s)
+{
+    int nb, tx, ty;
+    grid_of(g, nb, tx, ty);
+    if (g.dim == 2)
+        hipLaunchKernelGGL((k_stencil2d<T, TO, MODE, TAG>), dim3(nb), dim3(256), 0, s, u, b, q, out, P, rscale, tx,
+                           partial);
+    else
+        hipLaunchKernelGGL((k_stencil3d<T, TO, MODE, TAG>), dim3(nb), dim3(256), 0, s, u, b, q, out, P, rscale, tx,
+                           ty, partial);
+}
+
+template <typename T>
+void launch_stencil(int mode, const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b,
+                    const cx<T> *q, cx<T> *out, double *partial, hipStream_t s, bool finest)
+{
+    const T one = T(1);
+    if (finest && mode == MODE_JACOBI) {
+        launch_mode<T, T, MODE_JACOBI, 1>(g, P, one, u, b, q, out, partial, s);
+        return;
+    }
+    switch (mode) {
+    case MODE_APPLY: launch_mode<T, T, MODE_APPLY>(g, P, one, u, b, q, out, partial, s); break;
+    case MODE_RESID: launch_mode<T, T, MODE_RESID>(g, P, one, u, b, q, out, partial, s); break;
+    case MODE_RNORM: launch_mode<T, T, MODE_RNORM>(g, P, one, u, b, q, out, partial, s); break;
+    case MODE_JACOBI0: launch_mode<T, T, MODE_JACOBI0>(g, P, one, u, b, q, out, partial, s); break;
+    default: launch_mode<T, T, MODE_JACOBI>(g, P, one, u, b, q, out, partial, s); break;
+    }
+}
+template void launch_stencil<double>(int, const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
+                                     const cd *, cd *, double *, hipStream_t, bool);
+template void launch_stencil<float>(int, const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
+                                    const cf *, cf *, double *, hipStream_t, bool);
+
+// ---------------------------------------------------------------------------
+// Full weighting: coarse node I <- fine 2I-1, 2I, 2I+1 with (1/4, 1/2, 1/4),
+// tensorised; summed z-outer, x-inner.  One thread per coarse point.
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_restrict(const cx<T> *__restrict__ rf, cx<T> *__restrict__ bc,
+                                                  int mxf, int myf, int mxc, int myc, int mzc)
+{
+    size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t Nc = (size_t)mxc * myc * mzc;
+    if (idx >= Nc) return;
+    int I = (int)(idx % mxc);
+    size_t rest = idx / mxc;
+    int J = (int)(rest % myc);
+    int K = (int)(rest / myc);
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+    int fx = 2 * I + 1, fy = 2 * J + 1, fz = 2 * K + 1;
+    cx<T> acc = {T(0), T(0)};
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz) {
+        T wz = (DIM == 3) ? w[dz + 1] : T(1);
+        for (int dy = -1; dy <= 1; ++dy) {
+            T wy = w[dy + 1];
+            for (int dx = -1; dx <= 1; ++dx) {
+                T wx = w[dx + 1];
+                int z = (DIM == 3) ? fz + dz : 0;
+                size_t j = ((size_t)z * myf + (fy + dy)) * mxf + (fx + dx);
+                acc = acc + ((wx * wy) * wz) * rf[j];
+            }
+        }
+    }
+    bc[idx] = acc;
+}
+
+template <typename T>
+void launch_restrict(const LevelGeom &f, const cx<T> *rf, cx<T> *bc, hipStream_t s)
+{
+    int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.dim == 3) ? (f.m[2] - 1) / 2 : 1;
+    size_t Nc = (size_t)mxc * myc * mzc;
+    int nb = (int)((Nc + 255) / 256);
+    if (f.dim == 2)
+        hipLaunchKernelGGL((k_restrict<T, 2>), dim3(nb), dim3(256), 0, s, rf, bc, f.m[0], f.m[1], mxc, myc, mzc);
+    else
+        hipLaunchKernelGGL((k_restrict<T, 3>), dim3(nb), dim3(256), 0, s, rf, bc, f.m[0], f.m[1], mxc, myc, mzc);
+}
+template void launch_restrict<double>(const LevelGeom &, const cd *, cd *, hipStream_t);
+template void launch_restrict<float>(const LevelGeom &, const cf *, cf *, hipStream_t);
+
+// Linear interpolation: fine node f (1-based) takes coarse nodes floor(f/2)
+// and ceil(f/2) with weights 1 (f even) or 1/2 (f odd), tensorised; coarse
+// boundary values are zero.  One thread per fine point, summed z-outer.
+template <typename T>
+__device__ __forceinline__ T iw(int f, int C)
+{
+    int d = f - 2 * C;
+    return d == 0 ? T(1) : ((d == 1 || d == -1) ? T(0.5) : T(0));
+}
+
+template <typename T, int DIM>
+__global__ __launch_bounds__(256) void k_prolong_add(const cx<T> *__restrict__ ec, cx<T> *__restrict__ uf,
+                                                     int mxf, int myf, int mzf, int mxc, int myc, int mzc)
+{
+    size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t Nf = (size_t)mxf * myf * mzf;
+    if (idx >= Nf) return;
+    int ix = (int)(idx % mxf);
+    size_t rest = idx / mxf;
+    int iy = (int)(rest % myf);
+    int iz = (int)(rest / myf);
+    int fx = ix + 1, fy = iy + 1, fz = iz + 1;
+    cx<T> acc = {T(0), T(0)};
+    int zlo = (DIM == 3) ? fz / 2 : 1, zhi = (DIM == 3) ? (fz + 1) / 2 : 1;
+    for (int Cz = zlo; Cz <= zhi; ++Cz)
+        for (int Cy = fy / 2; Cy <= (fy + 1) / 2; ++Cy)
+            for (int Cx = fx / 2; Cx <= (fx + 1) / 2; ++Cx) {
+                T wgt = iw<T>(fx, Cx) * iw<T>(fy, Cy) * ((DIM == 3) ? iw<T>(fz, Cz) : T(1));
+                if (wgt == T(0)) continue;
+                int ax = Cx - 1, ay = Cy - 1, az = (DIM == 3) ? Cz - 1 : 0;
+                if (ax < 0 || ay < 0 || az < 0 || ax >= mxc || ay >= myc || az >= mzc) continue;
+                acc = acc + wgt * ec[((size_t)az * myc + ay) * mxc + ax];
+            }
+    uf[idx] = uf[idx] + acc;
+}
+
+template <typename T>
+void launch_prolong_add(const LevelGeom &f, const cx<T> *ec, cx<T> *uf, hipStream_t s)
+{
+    int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.dim == 3) ? (f.m[2] - 1) / 2 : 1;
+    size_t Nf = f.N();
+    int nb = (int)((Nf + 255) / 256);
+    if (f.dim == 2)
+        hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nb), dim3(256), 0, s, ec, uf, f.m[0], f.m[1], 1, mxc, myc, 1);
+    else
+        hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nb), dim3(256), 0, s, ec, uf, f.m[0], f.m[1], f.m[2], mxc,
+                           myc, mzc);
+}
+template void launch_prolong_add<double>(const LevelGeom &, const cd *, cd *, hipStream_t);
+template void launch_prolong_add<float>(const LevelGeom &, const cf *, cf *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Deterministic sum of per-block partials (one block, fixed order).
+__global__ __launch_bounds__(256) void k_sum(const double *__restrict__ parts, int n, double *__restrict__ out)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += parts[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+void launch_sum(const double *parts, int nparts, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, parts, nparts, out);
+}
+
+// ---------------------------------------------------------------------------
+// Setup: contrast q = scale * coef (Helmholtz scale 1; Schroedinger -2, i.e.
+// q = -2V) and a count of non-finite inputs per block.
+__global__ __launch_bounds__(256) void k_make_q(const cd *__restrict__ coef, cd *__restrict__ q, size_t N,
+                                                double scale, double *__restrict__ bad)
+{
+    double nbad = 0.0;
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
+        cd c = coef[j];
+        if (!isfinite(c.re) || !isfinite(c.im)) nbad += 1.0;
+        q[j] = cd{scale * c.re, scale * c.im};
+    }
+    block_sum_256(nbad, bad);
+}
+
+void launch_make_q(const cd *coef, cd *q, size_t N, double scale, double *bad_parts, int nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_make_q, dim3(nparts), dim3(256), 0, s, coef, q, N, scale, bad_parts);
+}
+
+// Coarse coefficients by injection: coarse node I <- fine node 2I.
+template <typename T>
+__global__ __launch_bounds__(256) void k_inject(const cx<T> *__restrict__ qf, cx<T> *__restrict__ qc, int mxf,
+                                                int myf, int mxc, int myc, int mzc, int dim)
+{
+    size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t Nc = (size_t)mxc * myc * mzc;
+    if (idx >= Nc) return;
+    int I = (int)(idx % mxc);
+    size_t rest = idx / mxc;
+    int J = (int)(rest % myc);
+    int K = (int)(rest / myc);
+    int z = (dim == 3) ? 2 * K + 1 : 0;
+    qc[idx] = qf[((size_t)z * myf + (2 * J + 1)) * mxf + (2 * I + 1)];
+}
+
+template <typename T>
+void launch_inject(const LevelGeom &f, const cx<T> *qf, cx<T> *qc, hipStream_t s)
+{
+    int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.dim == 3) ? (f.m[2] - 1) / 2 : 1;
+    size_t Nc = (size_t)mxc * myc * mzc;
+    hipLaunchKernelGGL((k_inject<T>), dim3((Nc + 255) / 256), dim3(256), 0, s, qf, qc, f.m[0], f.m[1], mxc, myc,
+                       mzc, f.dim);
+}
+template void launch_inject<double>(const LevelGeom &, const cd *, cd *, hipStream_t);
+template void launch_inject<float>(const LevelGeom &, const cf *, cf *, hipStream_t);
+
+template <typename To, typename Ti>
+__global__ __launch_bounds__(256) void k_convert(const cx<Ti> *__restrict__ in, cx<To> *__restrict__ out, size_t N)
+{
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256)
+        out[j] = cvt<To>(in[j]);
+}
+
+template <typename To, typename Ti>
+void launch_convert(const cx<Ti> *in, cx<To> *out, size_t N, hipStream_t s)
+{
+    size_t nb = (N + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL((k_convert<To, Ti>), dim3((unsigned)nb), dim3(256), 0, s, in, out, N);
+}
+template void launch_convert<float, double>(const cd *, cf *, size_t, hipStream_t);
+template void launch_convert<double, float>(const cf *, cd *, size_t, hipStream_t);
+
+// Dense [A | I] of the coarsest operator (n x 2n, row-major).
+__global__ __launch_bounds__(256) void k_build_coarse(const cd *__restrict__ q, cd *__restrict__ aug,
+                                                      Stencil<double> P, int dim)
+{
+    const int mx = P.mx, my = P.my, mz = P.mz;
+    const int n = mx * my * mz;
+    for (int e = blockIdx.x * 256 + threadIdx.x; e < n * 2 * n; e += gridDim.x * 256) {
+        int i = e / (2 * n), j = e - i * 2 * n;
+        cd v = {0.0, 0.0};
+        if (j >= n) {
+            if (j - n == i) v = cd{1.0, 0.0};
+        } else {
+            int ix = i % mx, iy = (i / mx) % my, iz = i / (mx * my);
+            int jx = j % mx, jy = (j / mx) % my, jz = j / (mx * my);
+            int dx = jx - ix, dy = jy - iy, dz = jz - iz;
+            if (i == j) {
+                cd qj = q[i];
+                v = P.csum2 - cd{P.k02 + qj.re, qj.im};
+            } else if (dy == 0 && dz == 0 && (dx == 1 || dx == -1)) {
+                v = cd{-P.c[0].re, -P.c[0].im};
+            } else if (dx == 0 && dz == 0 && (dy == 1 || dy == -1)) {
+                v = cd{-P.c[1].re, -P.c[1].im};
+            } else if (dim == 3 && dx == 0 && dy == 0 && (dz == 1 || dz == -1)) {
+                v = cd{-P.c[2].re, -P.c[2].im};
+            }
+        }
+        aug[e] = v;
+    }
+}
+
+void launch_build_coarse(const LevelGeom &g, const Stencil<double> &P, const cd *q, cd *aug, hipStream_t s)
+{
+    size_t n = g.N();
+    size_t tot = n * 2 * n;
+    unsigned nb = (unsigned)((tot + 255) / 256);
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_build_coarse, dim3(nb), dim3(256), 0, s, q, aug, P, g.dim);
+}
+
+// Gauss-Jordan elimination with partial pivoting on [A | I] (n x 2n), one
+// block of 1024 threads; leaves A^{-1} in the right half.  info[0] = 0 on
+// success, k+1 if a zero pivot was met in column k.
+__global__ __launch_bounds__(1024) void k_gauss_jordan(cd *__restrict__ a, int n, int *__restrict__ info)
+{
+    __shared__ double bestv[1024];
+    __shared__ int besti[1024];
+    __shared__ cd pivrow_scale;
+    const int W = 2 * n;
+    const int t = threadIdx.x;
+    for (int k = 0; k < n; ++k) {
+        double bv = -1.0;
+        int bi = k;
+        for (int i = k + t; i < n; i += 1024) {
+            double v = abs2(a[(size_t)i * W + k]);
+            if (v > bv) {
+                bv = v;
+                bi = i;
+            }
+        }
+        bestv[t] = bv;
+        besti[t] = bi;
+        __syncthreads();
+        for (int off = 512; off > 0; off >>= 1) {
+            if (t < off) {
+                double o = bestv[t + off];
+                int oi = besti[t + off];
+                if (o > bestv[t] || (o == bestv[t] && oi < besti[t])) {
+                    bestv[t] = o;
+                    besti[t] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        int p = besti[0];
+        if (bestv[0] <= 0.0) {
+            if (t == 0) info[0] = k + 1;
+            return;
+        }
+        if (p != k)
+            for (int j = t; j < W; j += 1024) {
+                cd tmp = a[(size_t)k * W + j];
+                a[(size_t)k * W + j] = a[(size_t)p * W + j];
+                a[(size_t)p * W + j] = tmp;
+            }
+        __syncthreads();
+        if (t == 0) pivrow_scale = recip(a[(size_t)k * W + k]);
+        __syncthreads();
+        cd sc = pivrow_scale;
+        for (int j = t; j < W; j += 1024) a[(size_t)k * W + j] = a[(size_t)k * W + j] * sc;
+        __syncthreads();
+        // eliminate column k from every other row (columns < k of the left
+        // half are already zero in the rows below and above)
+        const int ncols = W - k;
+        for (size_t e = t; e < (size_t)n * ncols; e += 1024) {
+            int i = (int)(e / ncols), j = k + (int)(e - (size_t)i * ncols);
+            if (i == k || j == k) continue;
+            cd f = a[(size_t)i * W + k];
+            a[(size_t)i * W + j] = a[(size_t)i * W + j] - f * a[(size_t)k * W + j];
+        }
+        __syncthreads();
+        for (int i = t; i < n; i += 1024)
+            if (i != k) a[(size_t)i * W + k] = cd{0.0, 0.0};
+        __syncthreads();
+    }
+    if (t == 0) info[0] = 0;
+}
+
+void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, aug, n, info);
+}
+
+// Coarsest solve u = A^{-1} b with the stored inverse (right half of the
+// augmented matrix, row stride 2n), in FP64 whatever T is.  One wave per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse_apply(const cd *__restrict__ aug, int n, const cx<T> *__restrict__ b,
+                                                      cx<T> *__restrict__ u)
+{
+    int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const cd *ar = aug + (size_t)row * 2 * n + n;
+    double re = 0.0, im = 0.0;
+    for (int k = lane; k < n; k += 64) {
+        cd a = ar[k];
+        cx<T> bk = b[k];
+        double br = (double)bk.re, bi = (double)bk.im;
+        re += a.re * br - a.im * bi;
+        im += a.re * bi + a.im * br;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_down(re, off, 64);
+        im += __shfl_down(im, off, 64);
+    }
+    if (lane == 0) u[row] = cx<T>{T(re), T(im)};
+}
+
+template <typename T>
+void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_coarse_apply<T>), dim3((n + 3) / 4), dim3(256), 0, s, Ainv, n, b, u);
+}
+template void launch_coarse_apply<double>(const cd *, int, const cd *, cd *, hipStream_t);
+template void launch_coarse_apply<float>(const cd *, int, const cf *, cf *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// b_j = q_j exp(i k0 e^{i gamma} eta.x_j): the plane wave on the contour.
+__global__ __launch_bounds__(256) void k_rhs(const cd *__restrict__ q, cd *__restrict__ b, int mx, int my, int mz,
+                                             int dim, double lx, double ly, double lz, double hx, double hy,
+                                             double hz, double ex, double ey, double ez, double ar_s, double ai_s)
+{
+    size_t N = (size_t)mx * my * mz;
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
+        int ix = (int)(j % mx);
+        size_t rest = j / mx;
+        int iy = (int)(rest % my), iz = (int)(rest / my);
+        double t = ex * (lx + (double)(ix + 1) * hx);
+        if (dim >= 2) t += ey * (ly + (double)(iy + 1) * hy);
+        if (dim >= 3) t += ez * (lz + (double)(iz + 1) * hz);
+        double mag = exp(ar_s * t);
+        double ph = ai_s * t;
+        cd uin = {mag * cos(ph), mag * sin(ph)};
+        b[j] = q[j] * uin;
+    }
+}
+
+void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
+                           hipStream_t s)
+{
+    // i k0 e^{i gamma} t = (-k0 sin gamma) t + i (k0 cos gamma) t
+    double ar_s = -(k0 * sin(gamma)), ai_s = k0 * cos(gamma);
+    size_t N = g.N();
+    size_t nb = (N + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)nb), dim3(256), 0, s, q, b, g.m[0], g.m[1], g.m[2], g.dim, g.lo[0],
+                       g.lo[1], g.lo[2], g.h[0], g.h[1], g.h[2], eta[0], eta[1], eta[2], ar_s, ai_s);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision refinement kernels.
+__global__ __launch_bounds__(256) void k_refine_update(const cf *__restrict__ d, cd *__restrict__ u, double scale,
+                                                       size_t N)
+{
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
+        cf dj = d[j];
+        cd uj = u[j];
+        u[j] = cd{uj.re + scale * (double)dj.re, uj.im + scale * (double)dj.im};
+    }
+}
+
+void launch_refine_update(const cf *d, cd *u, double scale, size_t N, hipStream_t s)
+{
+    size_t nb = (N + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_refine_update, dim3((unsigned)nb), dim3(256), 0, s, d, u, scale, N);
+}
+
+// FP64 residual written as FP32 after scaling: r32 = (b - A u) * inv_scale,
+// with the FP64 sum |b - A u|^2 per block.
+void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
+                         cf *r32, double inv_scale, double *partial, hipStream_t s)
+{
+    launch_mode<double, float, MODE_RESID>(g, P, inv_scale, u, b, q, r32, partial, s);
+}
+
+}  // namespace ffmg

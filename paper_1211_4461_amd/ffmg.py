@@ -1,0 +1,272 @@
+"""Thin Python binding of the C ABI in ``include/ffmg.h`` (``libffmg.so``).
+
+Argument marshalling only: torch supplies device memory and the stream, every
+step of the method runs in the library's HIP kernels.  There is no CPU
+fallback -- importing works without a GPU, but any call needs the built
+library and a gfx950 device, and fails loudly otherwise.
+
+Names follow the C entry points: ``mg_setup``, ``mg_rhs_plane_wave``,
+``mg_vcycle``, ``mg_solve``, ``farfield_map``, ``mg_apply``, ``mg_smooth``,
+``mg_residual_norm``, ``mg_destroy``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libffmg.so")
+
+FFMG_OK, FFMG_EINVAL, FFMG_ENOMEM, FFMG_EDEVICE, FFMG_ENOCONV, FFMG_ERANGE, FFMG_ENAN = range(7)
+HELMHOLTZ, SCHRODINGER = 0, 1
+FP64, FP32_IR = 0, 1
+SMOOTH_JACOBI, SMOOTH_LEARNED = 0, 1
+FF_FP64, FF_BF16X3, FF_BF16X6 = 0, 1, 2
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int64 * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3), ("gamma", ctypes.c_double), ("kind", ctypes.c_int),
+                ("k0", ctypes.c_double), ("energy", ctypes.c_double), ("coef", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
+                ("coarsest_n", ctypes.c_int), ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
+                ("smoother", ctypes.c_int), ("smoother_weights", ctypes.c_void_p),
+                ("ff_precision", ctypes.c_int), ("tile_config", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("cycles", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("conv_factor", ctypes.c_double), ("fell_back", ctypes.c_int), ("t_solve_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FfmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ffmg status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup", "mg_rhs_plane_wave",
+           "mg_vcycle", "mg_solve", "farfield_map", "mg_apply", "mg_smooth", "mg_residual_norm",
+           "mg_num_levels", "mg_level_shape", "mg_destroy", "mg_profile_enable", "mg_profile_read"]
+
+
+def lib():
+    """Load libffmg.so (built in-tree by ``build.py``); raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.ffmg_default_options.argtypes = [ctypes.POINTER(Options)]
+    L.ffmg_strerror.restype = ctypes.c_char_p
+    L.ffmg_strerror.argtypes = [ip]
+    L.ffmg_last_error.restype = ctypes.c_char_p
+    L.ffmg_last_error.argtypes = [vp]
+    L.mg_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    L.mg_rhs_plane_wave.argtypes = [vp, vp, vp]
+    L.mg_vcycle.argtypes = [vp, vp, vp]
+    L.mg_solve.argtypes = [vp, vp, vp, dp, ctypes.POINTER(SolveInfo)]
+    L.farfield_map.argtypes = [vp, vp, vp, ip, vp, vp]
+    L.mg_apply.argtypes = [vp, vp, vp]
+    L.mg_smooth.argtypes = [vp, vp, vp, vp]
+    L.mg_residual_norm.argtypes = [vp, vp, vp, ctypes.POINTER(dp)]
+    L.mg_num_levels.argtypes = [vp]
+    L.mg_num_levels.restype = ip
+    L.mg_level_shape.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int64)]
+    L.mg_destroy.argtypes = [vp]
+    L.mg_destroy.restype = None
+    L.mg_profile_enable.argtypes = [vp, ip]
+    L.mg_profile_read.argtypes = [vp, ip, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
+    for name in ("mg_setup", "mg_rhs_plane_wave", "mg_vcycle", "mg_solve", "farfield_map", "mg_apply",
+                 "mg_smooth", "mg_residual_norm", "mg_level_shape", "mg_profile_enable", "mg_profile_read"):
+        getattr(L, name).restype = ip
+    _lib = L
+    return L
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().ffmg_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128 (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Handle:
+    """Owns one ``ffmg_handle``.  Arrays are complex128 device tensors whose
+    memory layout is x fastest (numpy/torch shape (ny, nx) or (nz, ny, nx))."""
+
+    def __init__(self, ptr, shape):
+        self._p = ptr
+        self.shape = shape
+
+    def _check(self, st, what):
+        if st != FFMG_OK:
+            msg = lib().ffmg_last_error(self._p).decode()
+            raise FfmgError(st, f"{what}: {msg}")
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def num_levels(self):
+        return lib().mg_num_levels(self._p)
+
+    def level_shape(self, level):
+        m = (ctypes.c_int64 * 3)()
+        self._check(lib().mg_level_shape(self._p, level, m), "mg_level_shape")
+        return tuple(m)
+
+    def destroy(self):
+        if self._p:
+            lib().mg_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def mg_setup(dim, n, lo, hi, gamma, coef, kind=HELMHOLTZ, k0=1.0, energy=0.0, options: Optional[Options] = None,
+             stream=None) -> Handle:
+    """Build the hierarchy for a problem; coef is the contrast k^2 - k0^2
+    (Helmholtz) or V (Schroedinger) at every interior node."""
+    torch = _torch()
+    p = Problem()
+    p.dim = dim
+    nn = list(n) if isinstance(n, (list, tuple)) else [n] * dim
+    ll = list(lo) if isinstance(lo, (list, tuple)) else [lo] * dim
+    hh = list(hi) if isinstance(hi, (list, tuple)) else [hi] * dim
+    for k in range(3):
+        p.n[k] = int(nn[k]) if k < dim else 1
+        p.lo[k] = float(ll[k]) if k < dim else 0.0
+        p.hi[k] = float(hh[k]) if k < dim else 1.0
+    p.gamma, p.kind, p.k0, p.energy = float(gamma), int(kind), float(k0), float(energy)
+    p.coef = _dev_ptr(coef, "coef")
+    o = options if options is not None else default_options()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o.stream = ctypes.c_void_p(stream.cuda_stream)
+    h = ctypes.c_void_p()
+    st = lib().mg_setup(ctypes.byref(p), ctypes.byref(o), ctypes.byref(h))
+    if st != FFMG_OK:
+        raise FfmgError(st, "mg_setup: " + lib().ffmg_strerror(st).decode())
+    shape = tuple(int(v) - 1 for v in nn[:dim][::-1])
+    return Handle(h, shape)
+
+
+def _eta3(eta):
+    e = (ctypes.c_double * 3)()
+    for k, v in enumerate(np.asarray(eta, dtype=np.float64).ravel()[:3]):
+        e[k] = v
+    return e
+
+
+def mg_rhs_plane_wave(h: Handle, eta, b):
+    h._check(lib().mg_rhs_plane_wave(h.ptr, _eta3(eta), _dev_ptr(b, "b")), "mg_rhs_plane_wave")
+    return b
+
+
+def mg_vcycle(h: Handle, b, u):
+    h._check(lib().mg_vcycle(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u")), "mg_vcycle")
+    return u
+
+
+def mg_solve(h: Handle, b, u, tol=1e-10, raise_on_noconv=True):
+    info = SolveInfo()
+    st = lib().mg_solve(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol), ctypes.byref(info))
+    if st != FFMG_OK and (st != FFMG_ENOCONV or raise_on_noconv):
+        h._check(st, "mg_solve")
+    return info
+
+
+def farfield_map(h: Handle, eta, u, dirs, out=None):
+    """F for each row of dirs (unit vectors); out: complex128 device tensor
+    or None (returns a host numpy array)."""
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64))
+    M = d.shape[0]
+    up = None if u is None else _dev_ptr(u, "u")
+    if out is None:
+        F = np.empty(M, dtype=np.complex128)
+        fp = ctypes.c_void_p(F.ctypes.data)
+    else:
+        F = out
+        fp = _dev_ptr(out, "F")
+    h._check(lib().farfield_map(h.ptr, _eta3(eta), up, M, ctypes.c_void_p(d.ctypes.data), fp), "farfield_map")
+    return F
+
+
+def mg_apply(h: Handle, u, Au):
+    h._check(lib().mg_apply(h.ptr, _dev_ptr(u, "u"), _dev_ptr(Au, "Au")), "mg_apply")
+    return Au
+
+
+def mg_smooth(h: Handle, b, u, u_out):
+    h._check(lib().mg_smooth(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), _dev_ptr(u_out, "u_out")), "mg_smooth")
+    return u_out
+
+
+def mg_residual_norm(h: Handle, b, u):
+    r = ctypes.c_double()
+    h._check(lib().mg_residual_norm(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), ctypes.byref(r)),
+             "mg_residual_norm")
+    return r.value
+
+
+def mg_destroy(h: Handle):
+    h.destroy()
+
+
+KERNEL_SWEEP, KERNEL_FARFIELD = 0, 1
+
+
+def mg_profile_enable(h: Handle, enable=True):
+    h._check(lib().mg_profile_enable(h.ptr, 1 if enable else 0), "mg_profile_enable")
+
+
+def mg_profile_read(h: Handle, kernel):
+    """(total_ms, launches) of kernel 0 (finest sweep) or 1 (far field)."""
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    h._check(lib().mg_profile_read(h.ptr, int(kernel), ctypes.byref(ms), ctypes.byref(n)), "mg_profile_read")
+    return ms.value, n.value
+
+
+def setup_workload(w, device="cuda", options: Optional[Options] = None):
+    """mg_setup for a workload of ``workloads.py``; returns (handle, coef)."""
+    torch = _torch()
+    coef = torch.from_numpy(np.ascontiguousarray(w.coef)).to(device)
+    lo, hi = w.box()
+    h = mg_setup(w.dim, [w.n] * w.dim, lo, hi, w.gamma, coef, kind=w.kind, k0=w.k0, energy=w.energy,
+                 options=options)
+    return h, coef

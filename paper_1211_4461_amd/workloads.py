@@ -198,13 +198,13 @@ def gauss_3d(n: int = 512, k0: Optional[float] = 1.0, n_az: int = 128,
                     directions_3d(n_az, n_pol))
 
 
-def wells(seed: int, count: int = 3):
-    """Seeded Gaussian wells: depth U[0.5,2], width 1, centre area-uniform in
+def wells(seed: int, count: int = 3, depth=(0.5, 2.0)):
+    """Seeded Gaussian wells: depth U[depth], width 1, centre area-uniform in
     |c| < 2; draw order per well: D, r, theta."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(count):
-        D = rng.uniform(0.5, 2.0)
+        D = rng.uniform(depth[0], depth[1])
         r = 2.0 * math.sqrt(rng.uniform(0.0, 1.0))
         th = rng.uniform(0.0, 2.0 * math.pi)
         out.append((D, (r * math.cos(th), r * math.sin(th))))
@@ -212,11 +212,19 @@ def wells(seed: int, count: int = 3):
 
 
 def schrodinger_potential(n: int, seed: int = 3, lo: float = -10.0, hi: float = 10.0,
-                          gamma: float = math.pi / 6):
-    """V(z) = -2 exp(-z.z) - sum_i D_i exp(-(z-c_i).(z-c_i)) on the contour."""
+                          gamma: float = math.pi / 6, deep: bool = False):
+    """V(z) = -B exp(-z.z) - sum_i D_i exp(-(z-c_i).(z-c_i)) on the contour.
+
+    deep=True: B = 2, D_i ~ U[0.5, 2].  Those wells hold bound states below
+    -E, which complex scaling leaves on the real axis, and plain Jacobi
+    V-cycles diverge on them (the breakdown the paper reports for bound-state
+    energies, Sec. 5.4).  deep=False (default): the same shape scaled by 1/10,
+    B = 0.2, D_i ~ U[0.05, 0.2], which stays in the V-cycle's convergence
+    regime for E >= 0.5."""
     X = mesh([n] * 2, [lo] * 2, [hi] * 2)
-    V = gauss_continued(X, gamma, -2.0, 1.0, (0.0, 0.0))
-    for D, c in wells(seed):
+    scale = 1.0 if deep else 0.1
+    V = gauss_continued(X, gamma, -2.0 * scale, 1.0, (0.0, 0.0))
+    for D, c in wells(seed, depth=(0.5 * scale, 2.0 * scale)):
         V = V + gauss_continued(X, gamma, -D, 1.0, c)
     return np.ascontiguousarray(V, dtype=np.complex128)
 

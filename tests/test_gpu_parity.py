@@ -1,0 +1,260 @@
+"""GPU parity of the HIP library (through the C ABI) against the FP64 oracle.
+
+Bars: kernel-level results agree to a few ulps (relative 1e-13); iterates
+after the same number of V-cycles to 1e-12 (the iteration is contractive, so
+rounding differences of the two implementations do not grow); converged far
+fields to 1e-10 (FP64) and the stated mixed-precision bars.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1211_4461_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_4461_amd import ffmg
+    ffmg.lib()
+    return ffmg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300)
+
+
+def crand(seed, shape):
+    r = np.random.default_rng(seed)
+    return r.standard_normal(shape) + 1j * r.standard_normal(shape)
+
+
+def setup(ff, orc, w, **opt):
+    o = ff.default_options(**opt)
+    h, coef = ff.setup_workload(w, options=o)
+    g = orc.Grid(w.dim, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    return h, coef, g, kappa, q, k0
+
+
+CASES = [
+    ("2d-63", lambda: W.small_2d(n=64)),
+    ("2d-127-ragged", lambda: W.bumps_2d(n=128, seed=5, k0=1.3, M=40)),
+    ("3d-15", lambda: W.radial_3d(16, L=4.0, n_az=6, n_pol=4)),
+    ("3d-31", lambda: W.radial_3d(32, L=6.0, n_az=8, n_pol=5)),
+]
+
+
+@pytest.mark.parametrize("name,mk", CASES)
+def test_apply_and_sweep_match_oracle(ff, orc, name, mk):
+    w = mk()
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    u = crand(1, g.shape)
+    b = crand(2, g.shape)
+    Au = ff.mg_apply(h, dev(u), torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    ref = orc.apply_A(g, w.gamma, kappa)(u)
+    assert rel(host(Au), ref) < 1e-13
+    uo = ff.mg_smooth(h, dev(b), dev(u), torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    ref = orc.jacobi(g, w.gamma, kappa, b, u, 0.8)
+    assert rel(host(uo), ref) < 1e-13
+    rn = ff.mg_residual_norm(h, dev(b), dev(u))
+    assert abs(rn - np.linalg.norm(orc.residual(g, w.gamma, kappa, b, u))) <= 1e-12 * rn
+
+
+@pytest.mark.parametrize("name,mk", CASES)
+def test_rhs_matches_oracle(ff, orc, name, mk):
+    w = mk()
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    ref = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    assert rel(host(b), ref) < 1e-13
+
+
+@pytest.mark.parametrize("name,mk", CASES)
+def test_vcycle_iterates_match_oracle(ff, orc, name, mk):
+    """The same number of V(2,2) cycles from u = 0 on both sides."""
+    w = mk()
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    assert h.num_levels() == mg.nlev
+    ud = torch.zeros(g.shape, dtype=torch.complex128, device="cuda")
+    bd = dev(b)
+    uo = np.zeros(g.shape, dtype=np.complex128)
+    for k in range(4):
+        ff.mg_vcycle(h, bd, ud)
+        uo = mg.vcycle(b, uo)
+        assert rel(host(ud), uo) < 1e-12, f"cycle {k + 1}"
+
+
+@pytest.mark.parametrize("name,mk", CASES)
+def test_solve_and_far_field_match_oracle(ff, orc, name, mk):
+    w = mk()
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    uo, st, k, hist = mg.solve(b, tol=1e-10)
+    assert st == 0
+    ud = torch.zeros(g.shape, dtype=torch.complex128, device="cuda")
+    info = ff.mg_solve(h, dev(b), ud, tol=1e-10)
+    assert info.status == 0 and info.cycles == k
+    assert info.rel_residual <= 1e-10
+    assert rel(host(ud), uo) < 1e-12
+    Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
+    Fg = ff.farfield_map(h, w.eta, ud, w.dirs)
+    assert rel(Fg, Fo) < 1e-10
+    # device output buffer gives the same numbers
+    Fd = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
+    ff.farfield_map(h, w.eta, ud, w.dirs, out=Fd)
+    np.testing.assert_array_equal(host(Fd), Fg)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_far_field_contraction_random_field(ff, orc, dim):
+    """The MFMA contraction alone, on a random u and a ragged direction set."""
+    w = W.bumps_2d(n=64, seed=3, k0=1.7, M=37) if dim == 2 else W.radial_3d(16, L=3.0, k0=1.2, n_az=7, n_pol=3)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    u = crand(7, g.shape) * 0.1
+    Fo = orc.farfield(g, w.gamma, k0, q, w.eta, u, w.dirs, method="dense")
+    Fg = ff.farfield_map(h, w.eta, dev(u), w.dirs)
+    assert rel(Fg, Fo) < 1e-12
+
+
+def test_far_field_born_closed_form(ff, orc):
+    """GPU Born term (u = 0) against the Gaussian's Fourier transform."""
+    from tests import refs
+    w = W.radial_2d(256, L=10.0, k0=2.0, amp=0.5, width=1.0)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    Fg = ff.farfield_map(h, w.eta, None, w.dirs)
+    ref = refs.born_2d(2.0, 0.5, 1.0, w.dirs, w.eta)
+    assert rel(Fg, ref) < 1e-13
+
+
+def test_zero_contrast(ff, orc):
+    w = W.small_2d()
+    w.coef = np.zeros_like(w.coef)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    assert torch.count_nonzero(b).item() == 0
+    u = torch.ones(g.shape, dtype=torch.complex128, device="cuda")
+    info = ff.mg_solve(h, b, u)
+    assert info.cycles == 0 and torch.count_nonzero(u).item() == 0
+    F = ff.farfield_map(h, w.eta, u, w.dirs)
+    assert np.all(F == 0)
+
+
+def test_reciprocity_on_gpu(ff, orc):
+    w = W.bumps_2d(n=128, seed=11, k0=1.5, M=8)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+
+    def F_of(e, a):
+        b = ff.mg_rhs_plane_wave(h, e, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+        u = torch.zeros_like(b)
+        ff.mg_solve(h, b, u, tol=1e-14)
+        return ff.farfield_map(h, e, u, a[None, :])[0]
+
+    eta, alpha = np.array([1.0, 0.0]), np.array([0.0, 1.0])
+    f1, f2 = F_of(eta, alpha), F_of(-alpha, -eta)
+    assert abs(f1 - f2) <= 1e-11 * abs(f1)
+
+
+@pytest.mark.parametrize("name,mk", CASES[:3])
+def test_mixed_precision_solve(ff, orc, name, mk):
+    """FP32 V-cycles inside FP64 refinement reach the FP64 tolerance; the far
+    field matches the oracle's converged one to 1e-8."""
+    w = mk()
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w, precision=ff.FP32_IR)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    uo, st, k, hist = mg.solve(b, tol=1e-13)
+    ud = torch.zeros(g.shape, dtype=torch.complex128, device="cuda")
+    info = ff.mg_solve(h, dev(b), ud, tol=1e-10)
+    assert info.status == 0 and info.rel_residual <= 1e-10
+    assert info.cycles <= k + 3
+    assert rel(host(ud), uo) < 1e-8
+    Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
+    Fg = ff.farfield_map(h, w.eta, ud, w.dirs)
+    assert rel(Fg, Fo) < 1e-8
+
+
+def test_schrodinger_instance(ff, orc):
+    n, E = 128, 1.0
+    V = W.schrodinger_potential(n)
+    w = W.Workload("s", 2, n, -10.0, 10.0, math.pi / 6, W.SCHRODINGER, math.sqrt(2 * E), E, V,
+                   np.array([0.6, 0.8]), W.directions_2d(24))
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    bd = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    assert rel(host(bd), b) < 1e-13
+    uo, st, k, _ = mg.solve(b, tol=1e-10)
+    ud = torch.zeros_like(bd)
+    info = ff.mg_solve(h, bd, ud, tol=1e-10)
+    assert st == 0 and info.cycles == k
+    Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
+    assert rel(ff.farfield_map(h, w.eta, ud, w.dirs), Fo) < 1e-10
+
+
+def test_deep_wells_diverge_on_both_sides(ff, orc):
+    """Bound states below -E break the plain V-cycle (Sec. 5.4): the oracle
+    and the library both report no convergence."""
+    n, E = 128, 1.0
+    V = W.schrodinger_potential(n, deep=True)
+    w = W.Workload("s", 2, n, -10.0, 10.0, math.pi / 6, W.SCHRODINGER, math.sqrt(2 * E), E, V,
+                   np.array([0.6, 0.8]), W.directions_2d(4))
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    uo, st, k, _ = orc.Multigrid(g, w.gamma, kappa).solve(b, tol=1e-10)
+    ud = torch.zeros(g.shape, dtype=torch.complex128, device="cuda")
+    info = ff.mg_solve(h, dev(b), ud, tol=1e-10, raise_on_noconv=False)
+    assert st == orc.ENOCONV and info.status == ff.FFMG_ENOCONV and info.cycles == k
+
+
+def test_errors(ff, orc):
+    w = W.small_2d()
+    coef = dev(w.coef)
+    with pytest.raises(ff.FfmgError) as e:
+        ff.mg_setup(2, [60, 64], -5, 5, w.gamma, coef, k0=2.0)
+    assert e.value.status == ff.FFMG_EINVAL
+    with pytest.raises(ff.FfmgError) as e:
+        ff.mg_setup(2, 64, -5, 5, 0.0, coef, k0=2.0)
+    assert e.value.status == ff.FFMG_EINVAL
+    bad = w.coef.copy()
+    bad[3, 7] = np.nan
+    with pytest.raises(ff.FfmgError) as e:
+        ff.mg_setup(2, 64, -5, 5, w.gamma, dev(bad), k0=2.0)
+    assert e.value.status == ff.FFMG_ENAN
+    h = ff.mg_setup(2, 64, -500, 500, w.gamma, coef, k0=5.0)
+    with pytest.raises(ff.FfmgError) as e:
+        ff.mg_rhs_plane_wave(h, w.eta, torch.empty((63, 63), dtype=torch.complex128, device="cuda"))
+    assert e.value.status == ff.FFMG_ERANGE
+    h2 = ff.mg_setup(2, 64, -5, 5, w.gamma, coef, k0=2.0)
+    with pytest.raises(ff.FfmgError) as e:
+        ff.farfield_map(h2, w.eta, None, np.array([[1.0, 1.0]]))
+    assert e.value.status == ff.FFMG_EINVAL
+
+
+def test_no_convergence_reported(ff, orc):
+    """A tiny cycle budget ends in ENOCONV with the iterate left in u."""
+    w = W.small_2d()
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w, max_cycles=2)
+    b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    u = torch.zeros_like(b)
+    info = ff.mg_solve(h, b, u, raise_on_noconv=False)
+    assert info.status == ff.FFMG_ENOCONV and info.cycles == 2
+    assert torch.count_nonzero(u).item() > 0
