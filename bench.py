@@ -8,9 +8,10 @@ far field at 360 outgoing angles, with every input already in HBM.  `value`
 is the mixed-precision path (FP32 V(2,2) cycles inside FP64 refinement, FP64
 far field); the plain FP64 multigrid path is timed beside it on the same map.
 
-Also reported: the roofline of the dominant kernel (the finest-level
-weighted-Jacobi sweep), timed live with HIP events on its stream, and the
-FP64 CPU oracle on the host cores (one map of the same workload).
+Also reported: the roofline of the dominant kernel (the timed kernel with the
+largest total time per map), timed live with HIP events on its stream during
+the timed region, and the FP64 CPU oracle on the host cores (one map of the
+same workload).
 """
 from __future__ import annotations
 
@@ -26,8 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_jacobi_fp32_bumps2d_2048.json")
-STENCIL_SRC = os.path.join(ROOT, "paper_1211_4461_amd", "csrc", "ffmg_stencil.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bumps2d_2048.json")
+STENCIL_SRC = os.path.join(ROOT, "paper_1211_4461_amd", "csrc", "ffmg_fused2d.hip")
 
 
 def src_hash():
@@ -35,20 +36,26 @@ def src_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(bytes_alg):
-    """HBM bytes per launch from committed rocprofv3 --pmc counters, or None
-    if absent or taken on a different kernel source."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from committed rocprofv3 --pmc
+    counters, or None if absent or taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("src_sha") != src_hash():
+    if t.get("src_sha") != src_hash() or t.get("kernel") != kernel:
         return None
     return t.get("bytes_per_launch")
 
 
-def run_path(ff, torch, w, precision, steps, warmup, profile):
+KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3))
+
+
+def run_path(ff, torch, w, precision, steps, warmup, bytes_per_point):
+    """Time `steps` maps.  The warm-up maps record every timed kernel; the one
+    with the largest total time is the dominant kernel, and inside the timed
+    region HIP events bracket only that kernel's launches."""
     opts = ff.default_options(precision=precision)
     h, coef = ff.setup_workload(w, options=opts)
     b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
@@ -63,28 +70,26 @@ def run_path(ff, torch, w, precision, steps, warmup, profile):
         info = ff.mg_solve(h, b, u, tol=w.tol)
         ff.farfield_map(h, w.eta, u, w.dirs, out=F)
 
+    def read_all():
+        return {name: ff.mg_profile_read(h, kid) for name, kid in KERNELS}
+
+    ff.mg_profile_enable(h, 0xF)
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    if profile:
-        ff.mg_profile_enable(h, True)
-        ff.mg_profile_read(h, ff.KERNEL_SWEEP)
-        ff.mg_profile_read(h, ff.KERNEL_FARFIELD)
+    allk = read_all()
+    dominant = max(bytes_per_point, key=lambda k: allk[k][0])
+    ff.mg_profile_enable(h, 1 << dict(KERNELS)[dominant])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = None
-    if profile:
-        sweep_ms, sweep_n = ff.mg_profile_read(h, ff.KERNEL_SWEEP)
-        ffm_ms, ffm_n = ff.mg_profile_read(h, ff.KERNEL_FARFIELD)
-        ff.mg_profile_enable(h, False)
-        prof = {"sweep_ms": sweep_ms, "sweep_n": sweep_n, "ff_ms": ffm_ms, "ff_n": ffm_n}
-    out = {"ms_per_step": 1e3 * dt / steps, "maps_per_s": steps / dt, "cycles": info.cycles,
+    live = read_all()[dominant]
+    ff.mg_profile_enable(h, 0)
+    out = {"ms_per_step": 1e3 * dt / steps, "maps_per_s": steps / dt, "cycles": info.cycles, "vcycles": info.vcycles,
            "rel_residual": info.rel_residual, "conv_factor": info.conv_factor, "F": F.cpu().numpy(),
-           "prof": prof}
+           "dominant": dominant, "live": live, "prof": allk}
     h.destroy()
     return out
 
@@ -147,20 +152,29 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, args.steps, args.warmup, profile=True)
+    # Algorithmic bytes per point of the timed kernels (FP32 complex 8 B, FP64 16 B):
+    #   pre    2 fused sweeps from a zero guess (FP32 inner cycle): read b, q; write u      = 24
+    #          (FP64 cycle, nonzero guess: read u, b, q; write u                          = 64)
+    #   post   interpolation + 2 fused sweeps: read u, b, q, e_c (N/4); write u          = 34 / 68
+    #   refine FP64 update + residual: read u, b, q (16 each), d (8); write u (16), r (8) = 80
+    bpp_mixed = {"pre": 24.0, "post": 34.0, "refine": 80.0}
+    bpp_plain = {"pre": 64.0, "post": 68.0}
+    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, args.steps, args.warmup, bpp_mixed)
     plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, max(args.steps // 2, 2),
-                                                 args.warmup, profile=True)
-
-    # roofline of the dominant kernel: finest-level FP32 weighted-Jacobi sweep,
-    # algorithmic bytes = N * (read u, b, q + write u') = 32 B per point
+                                                 args.warmup, bpp_plain)
+    names = {"pre": "finest-level pre-smoothing: 2 fused FP32 Jacobi sweeps from zero (k_smooth2d<float,2,true,false,1>)",
+             "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1>)",
+             "refine": "FP64 update + residual of the refinement loop (k_refine2d)"}
     pr = mixed["prof"]
-    bytes_alg = 32.0 * N
-    avg_ms = pr["sweep_ms"] / max(pr["sweep_n"], 1)
+    dom = mixed["dominant"]
+    avg_ms = mixed["live"][0] / max(mixed["live"][1], 1)
+    bytes_alg = bpp_mixed[dom] * N
     achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
-    roof = {"kernel": "finest-level weighted-Jacobi sweep (FP32, k_stencil2d<float,float,JACOBI,1>)",
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(bytes_alg),
-            "bytes_per_launch": bytes_alg, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": pr["sweep_n"]}
+    roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+            "bytes_per_launch": bytes_alg, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": mixed["live"][1],
+            "warmup_GBs": {k: round(bpp_mixed[k] * N / (pr[k][0] / max(pr[k][1], 1) * 1e-3) / 1e9, 1)
+                           for k in bpp_mixed if pr[k][1] > 0}}
 
     line = {
         "metric": "far-field maps/sec at 1e-6 rel error: plain FP64 MG vs mixed-prec/learned MG",
@@ -178,19 +192,19 @@ def main():
         "config": {"workload": f"bumps_2d n={args.n} box=[-10,10]^2 k0=1 gamma=30deg 8 bumps seed=1",
                    "unknowns": N, "angles": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
                    "form": "FP32 V-cycles in FP64 refinement + FP64 MFMA far field"},
-        "mixed": {"cycles": mixed["cycles"], "rel_residual": mixed["rel_residual"],
+        "mixed": {"refinement_steps": mixed["cycles"], "vcycles": mixed["vcycles"], "rel_residual": mixed["rel_residual"],
                   "conv_factor": round(mixed["conv_factor"], 4),
-                  "ff_ms_per_map": round(pr["ff_ms"] / max(pr["ff_n"], 1), 3)},
+                  "ff_ms_per_map": round(pr["ff"][0] / max(pr["ff"][1], 1), 3)},
         "roofline": roof,
     }
     if plain is not None:
         ef = float(np.linalg.norm(mixed["F"] - plain["F"]) / np.linalg.norm(plain["F"]))
         pp = plain["prof"]
-        p_avg = pp["sweep_ms"] / max(pp["sweep_n"], 1)
+        p_gbs = {k: round(b_ * N / (pp[k][0] / max(pp[k][1], 1) * 1e-3) / 1e9, 1)
+                 for k, b_ in bpp_plain.items() if pp[k][1] > 0}
         line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
                               "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
-                              "sweep_gbs": round(64.0 * N / (p_avg * 1e-3) / 1e9, 1),
-                              "sweep_us": round(p_avg * 1e3, 2)}
+                              "finest_kernels_GBs": p_gbs}
         line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
         line["mixed_vs_plain_farfield_rel_err"] = ef
     if not args.no_cpu_baseline:

@@ -87,12 +87,17 @@ typedef struct ffmg_options {
     int smoother;         /* ffmg_smoother                                     */
     const float *smoother_weights; /* HOST, learned smoother parameters, or NULL */
     int ff_precision;     /* ffmg_ff_precision                                 */
-    int tile_config;      /* 0 = autotuned / default, else a fixed variant     */
+    int tile_config;      /* 0 = fused 2D kernels + LDS tail (default), 1 = one
+                             operation per launch (reference), 2 = fused
+                             without the LDS tail                              */
+    int inner_cycles;     /* FP32_IR: V-cycles per FP64 refinement step
+                             (0 = default 2)                                   */
     void *stream;         /* hipStream_t; NULL = the null stream               */
 } ffmg_options;
 
 typedef struct ffmg_solve_info {
     int cycles;           /* V-cycles (FP64) or refinement steps (FP32_IR)     */
+    int vcycles;          /* V-cycles in total (FP32_IR: steps x inner_cycles) */
     int status;           /* ffmg_status of the solve                          */
     double rel_residual;  /* ||b - A u||_2 / ||b||_2 in FP64 at return         */
     double conv_factor;   /* (||r_k|| / ||r_0||)^(1/k)  (Sec. 5.4 definition)  */
@@ -154,12 +159,14 @@ ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out)
 /* ||b - A u||_2 (FP64 accumulation) into *rnorm (host). */
 ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, double *rnorm);
 
-/* Kernel timing (instrumentation for benchmarks).  When enabled, a pair of
- * HIP events on the handle's stream brackets every launch of kernel 0 (the
- * finest-level weighted-Jacobi sweep, FP64 or FP32) and kernel 1 (the
- * far-field contraction).  mg_profile_read synchronises, returns the summed
- * duration (ms) and launch count of one kernel, and clears its record. */
-ffmg_status mg_profile_enable(ffmg_handle *h, int enable);
+/* Kernel timing (instrumentation for benchmarks).  Bit k of mask enables a
+ * pair of HIP events on the handle's stream around every launch of kernel k:
+ * 0 finest-level pre-smoothing (the fused two-sweep kernel, or each sweep),
+ * 1 far-field contraction, 2 finest-level interpolation + post-smoothing,
+ * 3 FP64 update + residual of the mixed-precision refinement.  mask = 0
+ * disables.  mg_profile_read synchronises, returns the summed duration (ms)
+ * and launch count of one kernel, and clears its record. */
+ffmg_status mg_profile_enable(ffmg_handle *h, int mask);
 ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_t *count);
 
 /* Number of levels and the interior sizes of level l (n[k] - 1 per axis). */

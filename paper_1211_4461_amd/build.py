@@ -16,10 +16,10 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libffmg.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["ffmg_stencil.hip", "ffmg_farfield.hip", "ffmg_capi.hip"]
+SOURCES = ["ffmg_stencil.hip", "ffmg_fused2d.hip", "ffmg_farfield.hip", "ffmg_capi.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     "-Wno-unused-command-line-argument",

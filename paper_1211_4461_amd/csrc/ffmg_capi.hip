@@ -1,71 +1,25 @@
-// ffmg_capi.hip -- the handle, the multigrid driver and the C ABI declared in
-// include/ffmg.h.  Every arithmetic step runs in the library's HIP kernels;
-// the host only sequences launches, reads back one residual norm per cycle
-// and decides when to stop (Sec. 4: V-cycles to a residual-reduction
-// tolerance).
+// ffmg_capi.hip -- the multigrid driver and the C ABI declared in
+// include/ffmg.h.  Every arithmetic step runs in the library's HIP kernels.
+// The host sequences launches; the stopping test (Sec. 4: V-cycles to a
+// residual-reduction tolerance) runs on the device in k_ctl_update, so the
+// host enqueues several cycles at a time and reads the control block back
+// once per batch instead of once per cycle.
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
-#include <string>
-#include <vector>
 
-#include "../../include/ffmg.h"
-#include "ffmg_internal.hpp"
+#include "ffmg_handle.hpp"
 
 using namespace ffmg;
 
-namespace {
+namespace ffmg {
 
-struct Level {
-    LevelGeom g;
-    Stencil<double> P64;
-    Stencil<float> P32;
-    cd *q = nullptr;                 // contrast on this level
-    cd *u = nullptr, *b = nullptr;   // coarse correction / rhs (levels >= 1)
-    cd *r = nullptr, *t = nullptr;   // residual, ping-pong buffer
-    cf *q32 = nullptr;               // FP32 copies for the refinement inner cycle
-    cf *u32 = nullptr, *b32 = nullptr, *r32 = nullptr, *t32 = nullptr;
-};
-
-bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
-
-}  // namespace
-
-struct ffmg_handle {
-    ffmg_problem prob{};
-    ffmg_options opt{};
-    double k0 = 0.0, k02 = 0.0;
-    std::vector<Level> L;
-    cd *aug = nullptr;               // [A_c | A_c^{-1}] of the coarsest level
-    int nc = 0;
-    int *d_info = nullptr;
-    double *d_parts = nullptr;       // per-block partial sums
-    int nparts = 0;
-    double *d_scalar = nullptr;
-    double *h_scalar = nullptr;      // pinned
-    hipStream_t stream = nullptr;
-    FarFieldPlan *ff = nullptr;
-    cd *d_s = nullptr;               // far-field integrand
-    cd *d_E = nullptr;               // plane-wave axis factors
-    cd *d_F = nullptr;               // far-field staging
-    int d_F_cap = 0;
-    std::vector<void *> allocs;
-    std::string err;
-    // optional event timing of selected kernels (benchmark instrumentation)
-    bool profile = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
-};
-
-namespace {
-
-// Record the start of a timed launch of kernel id k (no-op unless enabled).
 int prof_begin(ffmg_handle *h, int k)
 {
-    if (!h->profile) return -1;
+    if (!(h->profile_mask & (1 << k))) return -1;
     std::pair<hipEvent_t, hipEvent_t> e;
     if (!h->ev_free.empty()) {
         e = h->ev_free.back();
@@ -97,33 +51,11 @@ ffmg_status fail(ffmg_handle *h, ffmg_status s, const char *fmt, ...)
     return s;
 }
 
-#define HIPCHK(h, x)                                                                                               \
-    do {                                                                                                           \
-        hipError_t e_ = (x);                                                                                       \
-        if (e_ != hipSuccess)                                                                                      \
-            return fail((h), e_ == hipErrorOutOfMemory ? FFMG_ENOMEM : FFMG_EDEVICE, "%s: %s (%s:%d)", #x,         \
-                        hipGetErrorString(e_), __FILE__, __LINE__);                                                \
-    } while (0)
+}  // namespace ffmg
 
-template <typename P>
-ffmg_status dalloc(ffmg_handle *h, P **p, size_t bytes)
-{
-    void *v = nullptr;
-    hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(h, FFMG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    }
-    h->allocs.push_back(v);
-    *p = (P *)v;
-    return FFMG_OK;
-}
+namespace {
 
-#define TRY(x)                                                                                                     \
-    do {                                                                                                           \
-        ffmg_status s_ = (x);                                                                                      \
-        if (s_ != FFMG_OK) return s_;                                                                              \
-    } while (0)
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // Sum of the first n partials -> host double (synchronises the stream).
 ffmg_status reduce_to_host(ffmg_handle *h, int n, double *out)
@@ -146,14 +78,13 @@ __global__ __launch_bounds__(256) void k_norm2(const cd *__restrict__ v, size_t 
     if (threadIdx.x == 0) parts[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// ||v||_2^2 into h->d_scalar (device) and *out (host).
 ffmg_status norm2_of(ffmg_handle *h, const cd *v, size_t N, double *out)
 {
     int nb = (int)std::min<size_t>((N + 255) / 256, 1024);
     hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, h->stream, v, N, h->d_parts);
     HIPCHK(h, hipGetLastError());
-    double s2;
-    TRY(reduce_to_host(h, nb, &s2));
-    *out = sqrt(s2);
+    TRY(reduce_to_host(h, nb, out));
     return FFMG_OK;
 }
 
@@ -179,6 +110,8 @@ struct LvlPtr<double> {
     static cd *r(Level &l) { return l.r; }
     static cd *t(Level &l) { return l.t; }
     static const Stencil<double> &P(Level &l) { return l.P64; }
+    static const TailParams<double> &tail(ffmg_handle *h) { return h->tail64; }
+    static size_t tail_lds(ffmg_handle *h) { return h->tail_lds[0]; }
 };
 template <>
 struct LvlPtr<float> {
@@ -188,12 +121,14 @@ struct LvlPtr<float> {
     static cf *r(Level &l) { return l.r32; }
     static cf *t(Level &l) { return l.t32; }
     static const Stencil<float> &P(Level &l) { return l.P32; }
+    static const TailParams<float> &tail(ffmg_handle *h) { return h->tail32; }
+    static size_t tail_lds(ffmg_handle *h) { return h->tail_lds[1]; }
 };
 
-// nu weighted-Jacobi sweeps in place on u (ping-pong through t).  With
-// zero_guess the incoming u is taken as 0 without being read.
+// nu weighted-Jacobi sweeps in place on u (ping-pong through t), one sweep
+// per launch.  With zero_guess the incoming u is taken as 0 without being read.
 template <typename T>
-void smooth(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, int nu, bool zero_guess)
+void smooth(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, int nu, bool zero_guess, const int *stop)
 {
     using LP = LvlPtr<T>;
     cx<T> *t = LP::t(lv);
@@ -203,36 +138,70 @@ void smooth(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, int nu, bool ze
     const bool finest = (&lv == &h->L[0]);
     for (int s = 0; s < nu; ++s) {
         int mode = (s == 0 && zero_guess) ? MODE_JACOBI0 : MODE_JACOBI;
-        int pi = (finest && mode == MODE_JACOBI) ? prof_begin(h, 0) : -1;
-        launch_stencil<T>(mode, lv.g, P, src, b, q, dst, nullptr, h->stream, finest);
-        prof_end(h, 0, pi);
+        int pi = (finest && mode == MODE_JACOBI) ? prof_begin(h, PROF_PRE) : -1;
+        launch_stencil<T>(mode, lv.g, P, src, b, q, dst, nullptr, h->stream, finest, stop);
+        prof_end(h, PROF_PRE, pi);
         std::swap(src, dst);
     }
-    if (src != u) (void)hipMemcpyAsync(u, src, lv.g.N() * sizeof(cx<T>), hipMemcpyDeviceToDevice, h->stream);
+    if (src != u) launch_copy<T>(src, u, lv.g.N(), h->stream, stop);
 }
 
-// One V(nu1, nu2) cycle on level l (Sec. 4): smoothing, restriction of the
-// residual, coarse correction (exact on the coarsest level), interpolation,
-// smoothing.
+// Fused 2D smoothing chain: nu sweeps from src (0 when zero; src + P ec when
+// ec is given) into dst, two sweeps per launch; tmp is a third buffer for
+// chains of more than one launch.
 template <typename T>
-void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess)
+void smooth_chain2d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src, cx<T> *dst, cx<T> *tmp, int nu,
+                    bool zero, const cx<T> *ec, int prof_id, const int *stop)
+{
+    using LP = LvlPtr<T>;
+    const bool finest = (&lv == &h->L[0]);
+    const cx<T> *cur = src;
+    int left = nu, kk = 0;
+    int nk = (nu + 1) / 2;
+    while (left > 0) {
+        int ns = left >= 2 ? 2 : 1;
+        left -= ns;
+        cx<T> *o = ((nk - 1 - kk) % 2 == 0) ? dst : tmp;   // the last launch lands in dst
+        int pi = finest ? prof_begin(h, prof_id) : -1;
+        launch_smooth2d<T>(lv.g, LP::P(lv), ns, zero, cur, ec, b, LP::q(lv), o, h->stream, finest && ns == 2, stop);
+        prof_end(h, prof_id, pi);
+        cur = o;
+        zero = false;
+        ec = nullptr;
+        ++kk;
+    }
+}
+
+// One V(nu1, nu2) cycle with the fused 2D kernels: pre-smoothing u -> t,
+// residual + restriction from t, coarse correction (the LDS tail kernel once
+// the levels are small), then interpolation fused into post-smoothing t -> u.
+template <typename T>
+void vcycle_fused2d(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop)
 {
     using LP = LvlPtr<T>;
     Level &lv = h->L[l];
-    const int last = (int)h->L.size() - 1;
-    if (l == last) {
-        launch_coarse_apply<T>(h->aug, h->nc, b, u, h->stream);
-        return;
-    }
-    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
-    if (nu1 > 0) smooth<T>(h, lv, b, u, nu1, zero_guess);
-    else if (zero_guess) (void)hipMemsetAsync(u, 0, lv.g.N() * sizeof(cx<T>), h->stream);
-    launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream);
     Level &lc = h->L[l + 1];
-    launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream);
-    vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true);
-    launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream);
-    if (nu2 > 0) smooth<T>(h, lv, b, u, nu2, false);
+    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+    cx<T> *t = LP::t(lv), *scratch = LP::r(lv);
+    cx<T> *cur = u;
+    if (nu1 > 0) {
+        smooth_chain2d<T>(h, lv, b, u, t, scratch, nu1, zero_guess, nullptr, PROF_PRE, stop);
+        cur = t;
+    } else if (zero_guess) {
+        launch_zero<T>(u, lv.g.N(), h->stream, stop);
+    }
+    launch_resid_restrict2d<T>(lv.g, LP::P(lv), cur, b, LP::q(lv), LP::b(lc), h->stream, stop);
+    const TailParams<T> &tp = LP::tail(h);
+    if (h->opt.tile_config == TILE_FUSED && tp.nt > 0 && l + 1 == (int)h->L.size() - tp.nt)
+        launch_tail2d<T>(tp, LP::tail_lds(h), LP::b(lc), LP::u(lc), h->stream, stop);
+    else
+        vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
+    if (nu2 > 0) {
+        smooth_chain2d<T>(h, lv, b, cur, u, scratch, nu2, false, LP::u(lc), PROF_POST, stop);
+    } else {
+        if (cur != u) launch_copy<T>(cur, u, lv.g.N(), h->stream, stop);
+        launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
+    }
 }
 
 ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_handle *tmp)
@@ -268,6 +237,8 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
     if (o->smoother != FFMG_SMOOTH_JACOBI) return fail(tmp, FFMG_EINVAL, "unsupported smoother %d", o->smoother);
     if (o->ff_precision != FFMG_FF_FP64)
         return fail(tmp, FFMG_EINVAL, "unsupported far-field precision %d", o->ff_precision);
+    if (o->tile_config < 0 || o->tile_config > 2) return fail(tmp, FFMG_EINVAL, "unknown tile_config");
+    if (o->inner_cycles < 0 || o->inner_cycles > 16) return fail(tmp, FFMG_EINVAL, "inner_cycles must be in [0, 16]");
     return FFMG_OK;
 }
 
@@ -281,6 +252,47 @@ double exponent_budget(const ffmg_handle *h)
         r2 += m * m;
     }
     return h->k0 * sin(h->prob.gamma) * sqrt(r2);
+}
+
+// Coarse levels handled by the one-workgroup LDS tail (2D): the longest
+// run of levels l >= 1 ending at the coarsest level whose b, u, t fit in LDS
+// and that hold at most 4096 points each.
+template <typename T>
+void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
+{
+    tp = TailParams<T>{};
+    lds = 0;
+    const int nl = (int)h->L.size();
+    if (h->prob.dim != 2 || h->opt.tile_config != TILE_FUSED || nl < 3) return;
+    const size_t budget = 144 * 1024;
+    size_t bytes = 0;
+    int top = nl;   // first tail level
+    for (int l = nl - 1; l >= 1; --l) {
+        const Level &lv = h->L[l];
+        size_t add = 3 * lv.g.N() * sizeof(cx<T>);
+        if (lv.g.N() > 4096 || bytes + add > budget || nl - l > TAIL_MAX_LEVELS) break;
+        bytes += add;
+        top = l;
+    }
+    int nt = nl - top;
+    if (nt < 2) return;   // the coarsest level alone is one matrix-vector product
+    tp.nt = nt;
+    tp.nu1 = h->opt.nu1;
+    tp.nu2 = h->opt.nu2;
+    tp.aug = h->aug;
+    tp.nc = h->nc;
+    int off = 0;
+    for (int i = 0; i < nt; ++i) {
+        Level &lv = h->L[top + i];
+        TailLevel<T> &t = tp.lv[i];
+        t.mx = lv.g.m[0];
+        t.my = lv.g.m[1];
+        t.off = off;
+        t.P = LvlPtr<T>::P(lv);
+        t.q = LvlPtr<T>::q(lv);
+        off += 3 * t.mx * t.my;
+    }
+    lds = bytes;
 }
 
 ffmg_status setup_impl(ffmg_handle *h)
@@ -314,6 +326,7 @@ ffmg_status setup_impl(ffmg_handle *h)
         Level &lv = h->L[l];
         size_t N = lv.g.N();
         maxparts = std::max<size_t>(maxparts, stencil_blocks(lv.g));
+        maxparts = std::max<size_t>(maxparts, fused2d_blocks(lv.g));
         TRY(dalloc(h, &lv.q, N * sizeof(cd)));
         TRY(dalloc(h, &lv.r, N * sizeof(cd)));
         TRY(dalloc(h, &lv.t, N * sizeof(cd)));
@@ -333,7 +346,9 @@ ffmg_status setup_impl(ffmg_handle *h)
     TRY(dalloc(h, &h->d_parts, maxparts * sizeof(double)));
     TRY(dalloc(h, &h->d_scalar, sizeof(double)));
     TRY(dalloc(h, &h->d_info, sizeof(int)));
+    TRY(dalloc(h, &h->d_ctl, sizeof(SolveCtl)));
     HIPCHK(h, hipHostMalloc((void **)&h->h_scalar, sizeof(double), hipHostMallocDefault));
+    HIPCHK(h, hipHostMalloc((void **)&h->h_ctl, sizeof(SolveCtl), hipHostMallocDefault));
 
     // contrast on the finest level (q = coef, or q = -2 V), non-finite check
     Level &l0 = h->L[0];
@@ -356,10 +371,70 @@ ffmg_status setup_impl(ffmg_handle *h)
     HIPCHK(h, hipMemcpyAsync(&info, h->d_info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     if (info != 0) return fail(h, FFMG_EINVAL, "coarsest operator is singular (zero pivot in column %d)", info - 1);
+    plan_tail<double>(h, h->tail64, h->tail_lds[0]);
+    if (ir) plan_tail<float>(h, h->tail32, h->tail_lds[1]);
     return FFMG_OK;
 }
 
+// Enqueue one cycle of the solve loop (V-cycle, residual / refinement step,
+// control update).  ucur/ualt: FP64 iterate ping-pong of the fused
+// refinement step (swapped by the caller).
+void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *stop)
+{
+    Level &l0 = h->L[0];
+    if (h->opt.precision == FFMG_FP64) {
+        vcycle<double>(h, 0, b, ucur, false, stop);
+        launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, ucur, b, l0.q, (cd *)nullptr, h->d_parts, h->stream, false,
+                               stop);
+        launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
+        return;
+    }
+    const int inner = h->opt.inner_cycles > 0 ? h->opt.inner_cycles : 2;
+    for (int c = 0; c < inner; ++c) vcycle<float>(h, 0, l0.b32, l0.u32, c == 0, stop);
+    if (l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE) {
+        int pi = prof_begin(h, PROF_REFINE);
+        launch_refine2d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
+        prof_end(h, PROF_REFINE, pi);
+        launch_ctl_update(h->d_ctl, h->d_parts, fused2d_blocks(l0.g), h->stream);
+    } else {
+        launch_refine_update(l0.u32, ucur, h->d_ctl, l0.g.N(), h->stream, stop);
+        launch_resid_to_f32_ctl(l0.g, l0.P64, ucur, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
+        launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
+    }
+}
+
 }  // namespace
+
+namespace ffmg {
+
+template <typename T>
+void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop)
+{
+    using LP = LvlPtr<T>;
+    Level &lv = h->L[l];
+    const int last = (int)h->L.size() - 1;
+    if (l == last) {
+        launch_coarse_apply<T>(h->aug, h->nc, b, u, h->stream, stop);
+        return;
+    }
+    if (lv.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE) {
+        vcycle_fused2d<T>(h, l, b, u, zero_guess, stop);
+        return;
+    }
+    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+    if (nu1 > 0) smooth<T>(h, lv, b, u, nu1, zero_guess, stop);
+    else if (zero_guess) launch_zero<T>(u, lv.g.N(), h->stream, stop);
+    launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
+    Level &lc = h->L[l + 1];
+    launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream, stop);
+    vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
+    launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
+    if (nu2 > 0) smooth<T>(h, lv, b, u, nu2, false, stop);
+}
+template void vcycle<double>(ffmg_handle *, int, const cd *, cd *, bool, const int *);
+template void vcycle<float>(ffmg_handle *, int, const cf *, cf *, bool, const int *);
+
+}  // namespace ffmg
 
 // =========================================================================
 extern "C" {
@@ -414,7 +489,6 @@ ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle *
         st = setup_impl(h);
     }
     if (st != FFMG_OK) {
-        // keep the message on stderr-free path: the caller gets only the code
         mg_destroy(h);
         return st;
     }
@@ -425,13 +499,13 @@ ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle *
 ffmg_status mg_profile_enable(ffmg_handle *h, int enable)
 {
     if (!h) return FFMG_EINVAL;
-    h->profile = enable != 0;
+    h->profile_mask = enable & ((1 << PROF_N) - 1);
     return FFMG_OK;
 }
 
 ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_t *count)
 {
-    if (!h || kernel < 0 || kernel > 1 || !total_ms || !count) return fail(h, FFMG_EINVAL, "bad argument");
+    if (!h || kernel < 0 || kernel >= PROF_N || !total_ms || !count) return fail(h, FFMG_EINVAL, "bad argument");
     HIPCHK(h, hipStreamSynchronize(h->stream));
     double tot = 0.0;
     for (auto &e : h->ev[kernel]) {
@@ -451,7 +525,7 @@ void mg_destroy(ffmg_handle *h)
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < PROF_N; ++k)
         for (auto &e : h->ev[k]) h->ev_free.push_back(e);
     for (auto &e : h->ev_free) {
         (void)hipEventDestroy(e.first);
@@ -460,6 +534,7 @@ void mg_destroy(ffmg_handle *h)
     if (h->ff) ff_plan_destroy(h->ff);
     for (void *p : h->allocs) (void)hipFree(p);
     if (h->h_scalar) (void)hipHostFree(h->h_scalar);
+    if (h->h_ctl) (void)hipHostFree(h->h_ctl);
     delete h;
 }
 
@@ -511,7 +586,7 @@ ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, doubl
 ffmg_status mg_vcycle(ffmg_handle *h, const void *b, void *u)
 {
     if (!h || !b || !u) return fail(h, FFMG_EINVAL, "null argument");
-    vcycle<double>(h, 0, (const cd *)b, (cd *)u, false);
+    vcycle<double>(h, 0, (const cd *)b, (cd *)u, false, nullptr);
     HIPCHK(h, hipGetLastError());
     return FFMG_OK;
 }
@@ -529,8 +604,7 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
     HIPCHK(h, hipEventRecord(e0, h->stream));
     Level &l0 = h->L[0];
     const size_t N = l0.g.N();
-    ffmg_status st = FFMG_OK;
-    double bn = 0.0, r0 = 0.0, rk = 0.0;
+    double bn2 = 0.0;
     auto finish = [&](ffmg_status s) {
         (void)hipEventRecord(e1, h->stream);
         (void)hipEventSynchronize(e1);
@@ -540,61 +614,64 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
         (void)hipEventDestroy(e1);
         inf.status = s;
         inf.t_solve_ms = ms;
-        inf.rel_residual = bn > 0 ? rk / bn : 0.0;
-        inf.conv_factor = (inf.cycles > 0 && r0 > 0) ? pow(rk / r0, 1.0 / inf.cycles) : 0.0;
         if (info) *info = inf;
         return s;
     };
-    if ((st = norm2_of(h, b, N, &bn)) != FFMG_OK) return finish(st);
-    if (bn == 0.0) {
+    ffmg_status st = norm2_of(h, b, N, &bn2);   // leaves ||b||^2 in h->d_scalar
+    if (st != FFMG_OK) return finish(st);
+    if (bn2 == 0.0) {
         (void)hipMemsetAsync(u, 0, N * sizeof(cd), h->stream);
         return finish(FFMG_OK);
     }
-    if (!isfinite(bn)) return finish(fail(h, FFMG_ENAN, "right-hand side holds non-finite values"));
-    int grow = 0;
+    if (!isfinite(bn2)) return finish(fail(h, FFMG_ENAN, "right-hand side holds non-finite values"));
+    const int maxc = h->opt.max_cycles;
+    launch_ctl_init(h->d_ctl, h->d_scalar, tol, N, maxc, h->stream);
+    const int *stop = &h->d_ctl->done;
+    // initial residual (cycle 0)
     if (h->opt.precision == FFMG_FP64) {
-        if ((st = resid_norm(h, b, u, &r0)) != FFMG_OK) return finish(st);
-        rk = r0;
-        double prev = r0;
-        if (r0 / bn <= tol) return finish(FFMG_OK);
-        for (int k = 1; k <= h->opt.max_cycles; ++k) {
-            vcycle<double>(h, 0, b, u, false);
-            if ((st = resid_norm(h, b, u, &rk)) != FFMG_OK) return finish(st);
-            inf.cycles = k;
-            if (!isfinite(rk)) return finish(fail(h, FFMG_ENOCONV, "residual became non-finite at cycle %d", k));
-            if (rk / bn <= tol) return finish(FFMG_OK);
-            grow = (rk >= prev) ? grow + 1 : 0;
-            if (grow >= 3) return finish(fail(h, FFMG_ENOCONV, "residual grew on 3 consecutive cycles"));
-            prev = rk;
+        launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
+        launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
+    } else {
+        launch_resid_to_f32_ctl(l0.g, l0.P64, u, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, nullptr);
+        launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
+    }
+    // cycles in batches; the control block decides on the device
+    cd *ua = u, *ub = l0.t;
+    int queued = 0;
+    int batch = h->last_cycles > 0 ? h->last_cycles : 4;
+    SolveCtl c{};
+    for (;;) {
+        int nb = std::min(batch, maxc - queued);
+        for (int i = 0; i < nb; ++i) {
+            enqueue_step(h, b, ua, ub, stop);
+            if (h->opt.precision == FFMG_FP32_IR && l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE)
+                std::swap(ua, ub);
         }
-        return finish(fail(h, FFMG_ENOCONV, "no convergence in %d cycles", h->opt.max_cycles));
+        queued += nb;
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipMemcpyAsync(h->h_ctl, h->d_ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        c = *h->h_ctl;
+        if (c.done || queued >= maxc) break;
+        batch = 2;
     }
-    // FP32 V-cycles inside FP64 iterative refinement.  The FP64 residual is
-    // written as FP32 scaled by the previous residual's rms value, the FP32
-    // cycle solves for the scaled correction, the update is applied in FP64.
-    const double sqN = sqrt((double)N);
-    double scale = bn / sqN;
-    double s2;
-    launch_resid_to_f32(l0.g, l0.P64, u, b, l0.q, l0.b32, 1.0 / scale, h->d_parts, h->stream);
-    if ((st = reduce_to_host(h, stencil_blocks(l0.g), &s2)) != FFMG_OK) return finish(st);
-    r0 = rk = sqrt(s2);
-    if (r0 / bn <= tol) return finish(FFMG_OK);
-    double prev = r0;
-    for (int k = 1; k <= h->opt.max_cycles; ++k) {
-        vcycle<float>(h, 0, l0.b32, l0.u32, true);
-        launch_refine_update(l0.u32, u, scale, N, h->stream);
-        scale = rk / sqN;
-        launch_resid_to_f32(l0.g, l0.P64, u, b, l0.q, l0.b32, 1.0 / scale, h->d_parts, h->stream);
-        if ((st = reduce_to_host(h, stencil_blocks(l0.g), &s2)) != FFMG_OK) return finish(st);
-        rk = sqrt(s2);
-        inf.cycles = k;
-        if (!isfinite(rk)) return finish(fail(h, FFMG_ENOCONV, "residual became non-finite at step %d", k));
-        if (rk / bn <= tol) return finish(FFMG_OK);
-        grow = (rk >= prev) ? grow + 1 : 0;
-        if (grow >= 3) return finish(fail(h, FFMG_ENOCONV, "residual grew on 3 consecutive steps"));
-        prev = rk;
+    // the fused refinement step alternates u between u and l0.t: after an odd
+    // number of completed steps the iterate is in l0.t
+    const bool pingpong = (h->opt.precision == FFMG_FP32_IR && l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE);
+    if (pingpong && (c.k % 2) == 1) HIPCHK(h, hipMemcpyAsync(u, l0.t, N * sizeof(cd), hipMemcpyDeviceToDevice, h->stream));
+    inf.cycles = std::max(c.k, 0);
+    inf.vcycles = inf.cycles * ((h->opt.precision == FFMG_FP32_IR)
+                                    ? (h->opt.inner_cycles > 0 ? h->opt.inner_cycles : 2) : 1);
+    const double bn = sqrt(bn2), rk = sqrt(c.rk2), r0 = sqrt(c.r0_2);
+    inf.rel_residual = rk / bn;
+    inf.conv_factor = (inf.cycles > 0 && r0 > 0) ? pow(rk / r0, 1.0 / inf.cycles) : 0.0;
+    h->last_cycles = inf.cycles;
+    switch (c.done) {
+    case 1: return finish(FFMG_OK);
+    case 2: return finish(fail(h, FFMG_ENOCONV, "residual grew on 3 consecutive cycles"));
+    case 4: return finish(fail(h, FFMG_ENOCONV, "residual became non-finite at cycle %d", c.k));
+    default: return finish(fail(h, FFMG_ENOCONV, "no convergence in %d cycles", maxc));
     }
-    return finish(fail(h, FFMG_ENOCONV, "no convergence in %d refinement steps", h->opt.max_cycles));
 }
 
 ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
@@ -646,9 +723,9 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
         }
         Fd = h->d_F;
     }
-    int pi = prof_begin(h, 1);
+    int pi = prof_begin(h, PROF_FF);
     HIPCHK(h, ff_plan_execute(h->ff, g, h->prob.gamma, Fd, h->stream));
-    prof_end(h, 1, pi);
+    prof_end(h, PROF_FF, pi);
     if (!on_device)
         HIPCHK(h, hipMemcpyAsync(F, Fd, (size_t)n_dirs * sizeof(cd), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));

@@ -50,11 +50,25 @@ __host__ __device__ __forceinline__ cx<To> cvt(cx<Ti> a) { return {To(a.re), To(
 template <typename T>
 struct Stencil {
     int mx, my, mz;     // interior extents (mz = 1 in 2D)
-    cx<T> c[3];         // c_k
+    cx<T> c[3];         // c_k = rot / h_k^2
+    cx<T> rot;          // e^{-2 i gamma}
+    T ih2[3];           // 1 / h_k^2 (0 for unused axes)
     cx<T> csum2;        // 2 sum_k c_k
     T k02;              // k0^2
     T omega;            // Jacobi damping
 };
+
+// p[j] where `in` holds, 0 elsewhere.  The load always goes to a valid
+// address (j or 0) and the value is selected afterwards: written as
+// `in ? p[j] : zero` the compiler may turn it into a load through a select of
+// the two addresses, which puts the zero on the stack and makes every load a
+// flat (generic) access.
+template <typename T>
+__device__ __forceinline__ cx<T> ld_masked(const cx<T> *__restrict__ p, size_t j, bool in)
+{
+    cx<T> v = p[in ? j : 0];
+    return in ? v : cx<T>{T(0), T(0)};
+}
 
 // Block index -> tile index such that each XCD (blocks are dispatched
 // round-robin over the 8 XCDs) receives a contiguous run of tiles, so halo

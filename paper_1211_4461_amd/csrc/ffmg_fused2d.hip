@@ -1,0 +1,586 @@
+// ffmg_fused2d.hip -- fused 2D multigrid kernels for gfx950.
+//
+// The V-cycle of Sec. 4 is, per level: nu1 omega-Jacobi sweeps, restriction
+// of the residual, coarse correction, interpolation, nu2 sweeps.  Done one
+// operation per launch it streams every field through HBM about 23 times per
+// level and pays ~7 launches.  These kernels run one level in 3 launches:
+//
+//   k_smooth2d<NS, ZERO, PROL>  NS (1 or 2) sweeps in one pass: the u tile is
+//       staged in LDS with an NS-deep halo, sweep 1 is computed on the tile
+//       plus an (NS-1) halo, sweep 2 on the tile.  ZERO: the incoming u is 0
+//       (coarse corrections), so sweep 1 is omega b / D and u is not read.
+//       PROL: u + P e_c (bilinear interpolation of the coarse correction) is
+//       formed while staging, i.e. the coarse-grid correction is fused into
+//       the first post-smoothing sweep.
+//   k_resid_restrict2d  r = b - A u on the fine points a coarse tile needs,
+//       kept in LDS, then full weighting (1/4, 1/2, 1/4)^2 to b_c.
+//   k_refine2d  the FP64 outer step of the mixed-precision solve: u' = u +
+//       s d (FP64 update of the FP32 correction), r = b - A u' in FP64,
+//       written as FP32 r / s' (the next scaled right-hand side) with the
+//       FP64 sum |r|^2 per block.
+//   k_tail2d  the coarse end of the cycle (all levels small enough for LDS and
+//       the exact coarsest solve) in one 1024-thread workgroup: on those
+//       levels a launch per operation would cost far more than the work.
+//
+// Per point the arithmetic is the same as the one-operation kernels in
+// ffmg_stencil.hip (same operation order, same reduction order in the
+// coarsest solve), so the fused path reproduces them bit for bit.
+#include <algorithm>
+
+#include "ffmg_internal.hpp"
+#include "ffmg_point.hpp"
+
+namespace ffmg {
+
+constexpr int FTX = 64;     // tile width (one wavefront of x)
+constexpr int FTY = 16;     // tile height
+constexpr int RCX = 32;     // resid_restrict: coarse tile 32 x 8 (one point per thread)
+constexpr int RCY = 8;
+
+// Interpolated coarse correction at fine interior point (ix, iy) (0-based):
+// coarse nodes floor(f/2), ceil(f/2) of fine node f = i + 1, weights 1 or 1/2,
+// summed y-outer / x-inner as in the one-operation kernel.  The coarse field
+// is read from ec[(ay - oy) * ld + (ax - ox)] (a tile of it, or all of it).
+template <typename T>
+__device__ __forceinline__ cx<T> interp2d(const cx<T> *ec, int ld, int ox, int oy, int mxc, int myc, int ix, int iy)
+{
+    int fx = ix + 1, fy = iy + 1;
+    cx<T> acc = {T(0), T(0)};
+    for (int Cy = fy / 2; Cy <= (fy + 1) / 2; ++Cy)
+        for (int Cx = fx / 2; Cx <= (fx + 1) / 2; ++Cx) {
+            int dx = fx - 2 * Cx, dy = fy - 2 * Cy;
+            T wx = dx == 0 ? T(1) : T(0.5), wy = dy == 0 ? T(1) : T(0.5);
+            T wgt = wx * wy * T(1);
+            int ax = Cx - 1, ay = Cy - 1;
+            if (ax < 0 || ay < 0 || ax >= mxc || ay >= myc) continue;
+            acc = acc + wgt * ec[(ay - oy) * ld + (ax - ox)];
+        }
+    return acc;
+}
+
+// Tile height of the smoothing kernel: 16 rows in FP32, 8 in FP64 (LDS
+// stays near 50 KB per block, three blocks per CU).
+template <typename T>
+constexpr int smooth_th()
+{
+    return sizeof(T) == 8 ? 8 : 16;
+}
+
+// k_smooth2d runs in four phases separated by barriers:
+//   1. every global load of the block is issued together (fully unrolled
+//      loops into LDS): the u tile with its NS-deep halo, b and q on the
+//      region the sweeps touch, and the coarse-correction tile (PROL);
+//   2. (PROL) u += P e_c in LDS;
+//   3. (NS = 2) sweep 1 on the tile plus a one-point halo;
+//   4. the last sweep on the tile, written to out.
+template <typename T, int NS, bool ZERO, bool PROL, int TAG>
+__global__ __launch_bounds__(256) void k_smooth2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
+                                                  const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                                  cx<T> *__restrict__ out, Stencil<T> P, int tiles_x,
+                                                  const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    constexpr int TH = smooth_th<T>();
+    constexpr int H = NS;                                  // halo depth of the staged u
+    constexpr int UW = FTX + 2 * H, UH = TH + 2 * H;
+    constexpr int BO = NS - 1;                             // b, q region: tile + (NS-1) halo
+    constexpr int BW = FTX + 2 * BO, BH = TH + 2 * BO;
+    constexpr int S1W = BW, S1H = BH;                      // sweep-1 values
+    constexpr int ECW = FTX / 2 + 4, ECH = TH / 2 + 4;     // coarse tile covering the u region
+    __shared__ cx<T> U0[ZERO ? 1 : UH][ZERO ? 1 : UW];
+    __shared__ cx<T> U1[NS == 2 ? S1H : 1][NS == 2 ? S1W : 1];
+    __shared__ cx<T> Bs[BH][BW];
+    __shared__ cx<T> Qs[BH][BW];
+    __shared__ cx<T> EC[PROL ? ECH : 1][PROL ? ECW : 1];
+    const int mx = P.mx, my = P.my;
+    const int mxc = (mx - 1) / 2, myc = (my - 1) / 2;
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % tiles_x) * FTX, y0 = (tile / tiles_x) * TH;
+    const int ecx0 = x0 / 2 - 2, ecy0 = y0 / 2 - 2;
+    const cx<T> zero = {T(0), T(0)};
+
+    // phase 1: loads, issued into registers first so that all of them are in
+    // flight together, then stored to LDS
+    constexpr int NU = ZERO ? 1 : (UH * UW + 255) / 256;
+    constexpr int NB = (BH * BW + 255) / 256;
+    constexpr int NE = PROL ? (ECH * ECW + 255) / 256 : 1;
+    cx<T> ru[NU], rb[NB], rq[NB], re[NE];
+    if (!ZERO) {
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            int i = threadIdx.x + 256 * k;
+            int ly = i / UW, lx = i - ly * UW;
+            int gx = x0 + lx - H, gy = y0 + ly - H;
+            bool in = i < UH * UW && gx >= 0 && gx < mx && gy >= 0 && gy < my;
+            ru[k] = ld_masked(u, (size_t)gy * mx + gx, in);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        int i = threadIdx.x + 256 * k;
+        int ly = i / BW, lx = i - ly * BW;
+        int gx = x0 + lx - BO, gy = y0 + ly - BO;
+        bool in = i < BH * BW && gx >= 0 && gx < mx && gy >= 0 && gy < my;
+        size_t j = (size_t)gy * mx + gx;
+        rb[k] = ld_masked(b, j, in);
+        rq[k] = ld_masked(q, j, in);
+    }
+    if (PROL) {
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            int i = threadIdx.x + 256 * k;
+            int ly = i / ECW, lx = i - ly * ECW;
+            int cx_ = ecx0 + lx, cy_ = ecy0 + ly;
+            bool in = i < ECH * ECW && cx_ >= 0 && cx_ < mxc && cy_ >= 0 && cy_ < myc;
+            re[k] = ld_masked(ec, (size_t)cy_ * mxc + cx_, in);
+        }
+    }
+    if (!ZERO) {
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            int i = threadIdx.x + 256 * k;
+            if (i < UH * UW) (&U0[0][0])[i] = ru[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        int i = threadIdx.x + 256 * k;
+        if (i < BH * BW) {
+            (&Bs[0][0])[i] = rb[k];
+            (&Qs[0][0])[i] = rq[k];
+        }
+    }
+    if (PROL) {
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            int i = threadIdx.x + 256 * k;
+            if (i < ECH * ECW) (&EC[0][0])[i] = re[k];
+        }
+    }
+    __syncthreads();
+    // phase 2: coarse-grid correction u += P e_c on the staged u.  Branch
+    // free: fine node f = g + 1 takes coarse interior nodes f/2 - 1 (weight 1
+    // if f is even, 1/2 if odd) and f/2 (weight 0 if even, 1/2 if odd); coarse
+    // nodes outside the grid are zero in EC.  The terms are summed in the
+    // order of the one-operation kernel; the extra zero-weight terms add 0.
+    if (PROL) {
+        for (int i = threadIdx.x; i < UH * UW; i += 256) {
+            int ly = i / UW, lx = i - ly * UW;
+            int gx = x0 + lx - H, gy = y0 + ly - H;
+            if (gx >= 0 && gx < mx && gy >= 0 && gy < my) {
+                int fx = gx + 1, fy = gy + 1;
+                int ex = (fx >> 1) - 1 - ecx0, ey = (fy >> 1) - 1 - ecy0;
+                T wx0 = (fx & 1) ? T(0.5) : T(1), wx1 = (fx & 1) ? T(0.5) : T(0);
+                T wy0 = (fy & 1) ? T(0.5) : T(1), wy1 = (fy & 1) ? T(0.5) : T(0);
+                cx<T> acc = {T(0), T(0)};
+                acc = acc + (wx0 * wy0 * T(1)) * EC[ey][ex];
+                acc = acc + (wx1 * wy0 * T(1)) * EC[ey][ex + 1];
+                acc = acc + (wx0 * wy1 * T(1)) * EC[ey + 1][ex];
+                acc = acc + (wx1 * wy1 * T(1)) * EC[ey + 1][ex + 1];
+                U0[ly][lx] = U0[ly][lx] + acc;
+            }
+        }
+        __syncthreads();
+    }
+    // phase 3: sweep 1 on the tile plus a one-point halo (zero outside the domain)
+    if (NS == 2) {
+        for (int i = threadIdx.x; i < S1H * S1W; i += 256) {
+            int sy = i / S1W, sx = i - sy * S1W;             // position in the b, q region
+            int gx = x0 + sx - BO, gy = y0 + sy - BO;
+            cx<T> v = zero;
+            if (gx >= 0 && gx < mx && gy >= 0 && gy < my) {
+                if (ZERO) {
+                    v = jacobi0_point<T>(P, Bs[sy][sx], Qs[sy][sx]);
+                } else {
+                    int ux = sx + 1, uy = sy + 1;            // same point in U0 (halo 2)
+                    v = jacobi_point<T>(P, U0[uy][ux], U0[uy][ux - 1], U0[uy][ux + 1], U0[uy - 1][ux],
+                                        U0[uy + 1][ux], Bs[sy][sx], Qs[sy][sx]);
+                }
+            }
+            U1[sy][sx] = v;
+        }
+        __syncthreads();
+    }
+    // phase 4: last sweep on the tile
+    const int lx = threadIdx.x & 63;
+    const int gx = x0 + lx;
+#pragma unroll
+    for (int k = 0; k < TH / 4; ++k) {
+        int ly = (threadIdx.x >> 6) + 4 * k;
+        int gy = y0 + ly;
+        if (gx < mx && gy < my) {
+            size_t j = (size_t)gy * mx + gx;
+            const int bx = lx + BO, by = ly + BO;
+            cx<T> v;
+            if (NS == 2) {
+                v = jacobi_point<T>(P, U1[by][bx], U1[by][bx - 1], U1[by][bx + 1], U1[by - 1][bx], U1[by + 1][bx],
+                                    Bs[by][bx], Qs[by][bx]);
+            } else if (ZERO) {
+                v = jacobi0_point<T>(P, Bs[by][bx], Qs[by][bx]);
+            } else {
+                int ax = lx + H, ay = ly + H;
+                v = jacobi_point<T>(P, U0[ay][ax], U0[ay][ax - 1], U0[ay][ax + 1], U0[ay - 1][ax], U0[ay + 1][ax],
+                                    Bs[by][bx], Qs[by][bx]);
+            }
+            out[j] = v;
+        }
+    }
+}
+
+// Residual + full weighting.  Coarse tile RCX x RCY; the fine residual is
+// needed at fine interior indices [2 I0, 2 (I0 + RCX)] x [2 J0, 2 (J0 + RCY)].
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                          const cx<T> *__restrict__ q, cx<T> *__restrict__ bc,
+                                                          Stencil<T> P, int ctiles_x, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    constexpr int RW = 2 * RCX + 1, RH = 2 * RCY + 1;   // residual region
+    constexpr int UW = RW + 2, UH = RH + 2;             // u region (one halo)
+    __shared__ cx<T> U[UH][UW];
+    __shared__ cx<T> R[RH][RW];
+    const int mx = P.mx, my = P.my;
+    const int mxc = (mx - 1) / 2, myc = (my - 1) / 2;
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int I0 = (tile % ctiles_x) * RCX, J0 = (tile / ctiles_x) * RCY;
+    const int fx0 = 2 * I0, fy0 = 2 * J0;               // first fine index of R
+    const cx<T> zero = {T(0), T(0)};
+    // all global loads of the block first: u with its halo, b and q on the
+    // residual region (fully unrolled so they are in flight together)
+    constexpr int NR = (RH * RW + 255) / 256;
+    cx<T> breg[NR], qreg[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        int i = threadIdx.x + 256 * k;
+        int ly = i / RW, lx = i - ly * RW;
+        int gx = fx0 + lx, gy = fy0 + ly;
+        bool in = i < RH * RW && gx < mx && gy < my;
+        size_t j = (size_t)gy * mx + gx;
+        breg[k] = ld_masked(b, j, in);
+        qreg[k] = ld_masked(q, j, in);
+    }
+#pragma unroll
+    for (int k = 0; k < (UH * UW + 255) / 256; ++k) {
+        int i = threadIdx.x + 256 * k;
+        if (i < UH * UW) {
+            int ly = i / UW, lx = i - ly * UW;
+            int gx = fx0 + lx - 1, gy = fy0 + ly - 1;
+            bool in = gx >= 0 && gx < mx && gy >= 0 && gy < my;
+            U[ly][lx] = ld_masked(u, (size_t)gy * mx + gx, in);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        int i = threadIdx.x + 256 * k;
+        if (i < RH * RW) {
+            int ly = i / RW, lx = i - ly * RW;
+            int gx = fx0 + lx, gy = fy0 + ly;
+            cx<T> r = zero;
+            if (gx < mx && gy < my)
+                r = resid_point<T>(P, U[ly + 1][lx + 1], U[ly + 1][lx], U[ly + 1][lx + 2], U[ly][lx + 1],
+                                   U[ly + 2][lx + 1], breg[k], qreg[k]);
+            R[ly][lx] = r;
+        }
+    }
+    __syncthreads();
+    const int ci = threadIdx.x % RCX, cj = threadIdx.x / RCX;
+    const int I = I0 + ci, J = J0 + cj;
+    if (I < mxc && J < myc) {
+        const T w[3] = {T(0.25), T(0.5), T(0.25)};
+        cx<T> acc = {T(0), T(0)};
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                T wgt = (w[dx + 1] * w[dy + 1]) * T(1);
+                acc = acc + wgt * R[2 * cj + 1 + dy][2 * ci + 1 + dx];
+            }
+        bc[(size_t)J * mxc + I] = acc;
+    }
+}
+
+// Mixed-precision outer step: u' = u + s d with s = ctl->scale_cur;
+// r = b - A u' (FP64); r32 = r / ctl->scale_next; per-block sum |r|^2.
+// Out of place in u.
+__global__ __launch_bounds__(256) void k_refine2d(const cd *__restrict__ u, const cf *__restrict__ d,
+                                                  const cd *__restrict__ b, const cd *__restrict__ q,
+                                                  cd *__restrict__ u_out, cf *__restrict__ r32,
+                                                  const SolveCtl *__restrict__ ctl, Stencil<double> P, int tiles_x,
+                                                  double *__restrict__ partial, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    const double s = ctl->scale_cur;
+    const double inv_scale = 1.0 / ctl->scale_next;
+    __shared__ cd U[FTY + 2][FTX + 2];
+    const int mx = P.mx, my = P.my;
+    int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int x0 = (tile % tiles_x) * FTX, y0 = (tile / tiles_x) * FTY;
+#pragma unroll
+    for (int k = 0; k < ((FTY + 2) * (FTX + 2) + 255) / 256; ++k) {
+        int i = threadIdx.x + 256 * k;
+        if (i < (FTY + 2) * (FTX + 2)) {
+            int ly = i / (FTX + 2), lx = i - ly * (FTX + 2);
+            int gx = x0 + lx - 1, gy = y0 + ly - 1;
+            bool in = gx >= 0 && gx < mx && gy >= 0 && gy < my;
+            size_t j = (size_t)gy * mx + gx;
+            cd uj = ld_masked(u, j, in);
+            cf dj = ld_masked(d, j, in);
+            U[ly][lx] = cd{uj.re + s * (double)dj.re, uj.im + s * (double)dj.im};
+        }
+    }
+    __syncthreads();
+    const int lx = threadIdx.x & 63;
+    const int gx = x0 + lx;
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < FTY / 4; ++k) {
+        int ly = (threadIdx.x >> 6) + 4 * k;
+        int gy = y0 + ly;
+        if (gx < mx && gy < my) {
+            size_t j = (size_t)gy * mx + gx;
+            cd uc = U[ly + 1][lx + 1];
+            cd r = resid_point<double>(P, uc, U[ly + 1][lx], U[ly + 1][lx + 2], U[ly][lx + 1], U[ly + 2][lx + 1],
+                                       b[j], q[j]);
+            u_out[j] = uc;
+            r32[j] = cvt<float>(inv_scale * r);
+            acc += abs2(r);
+        }
+    }
+    __shared__ double red[4];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------
+// The coarse end of the V-cycle in one workgroup.  Fields b, u, t of every
+// tail level live in LDS; q is read from global memory.  Level 0 of the tail
+// starts from a zero guess with b read from b_top; its correction is written
+// to u_top.  Steps are separated by workgroup barriers.
+template <typename T>
+struct TailView {
+    cx<T> *b, *u, *t;
+    int mx, my, N;
+};
+
+template <typename T>
+__device__ __forceinline__ TailView<T> tail_view(cx<T> *lds, const TailLevel<T> &L)
+{
+    TailView<T> v;
+    v.mx = L.mx;
+    v.my = L.my;
+    v.N = L.mx * L.my;
+    v.b = lds + L.off;
+    v.u = v.b + v.N;
+    v.t = v.u + v.N;
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> at2(const cx<T> *a, int mx, int my, int x, int y)
+{
+    return (x >= 0 && x < mx && y >= 0 && y < my) ? a[y * mx + x] : cx<T>{T(0), T(0)};
+}
+
+// nu sweeps on one tail level into v.u; zero: the incoming u is 0.
+template <typename T>
+__device__ void tail_smooth(const TailView<T> &v, const TailLevel<T> &L, int nu, bool zero)
+{
+    cx<T> *src = v.u, *dst = v.t;
+    for (int s = 0; s < nu; ++s) {
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
+            int x = j % v.mx, y = j / v.mx;
+            cx<T> bj = v.b[j], qj = L.q[j];
+            if (s == 0 && zero) {
+                dst[j] = jacobi0_point<T>(L.P, bj, qj);
+            } else {
+                dst[j] = jacobi_point<T>(L.P, src[j], at2(src, v.mx, v.my, x - 1, y), at2(src, v.mx, v.my, x + 1, y),
+                                         at2(src, v.mx, v.my, x, y - 1), at2(src, v.mx, v.my, x, y + 1), bj, qj);
+            }
+        }
+        __syncthreads();
+        cx<T> *tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    if (src != v.u) {
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) v.u[j] = src[j];
+        __syncthreads();
+    }
+    if (nu == 0 && zero) {
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) v.u[j] = cx<T>{T(0), T(0)};
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail2d(TailParams<T> tp, const cx<T> *__restrict__ b_top,
+                                                 cx<T> *__restrict__ u_top, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(tail_lds);
+    const int nt = tp.nt;
+    {
+        TailView<T> v0 = tail_view(lds, tp.lv[0]);
+        for (int j = threadIdx.x; j < v0.N; j += blockDim.x) v0.b[j] = b_top[j];
+        __syncthreads();
+    }
+    // down: smoothing from zero, residual, restriction
+    for (int i = 0; i + 1 < nt; ++i) {
+        const TailLevel<T> &L = tp.lv[i];
+        TailView<T> v = tail_view(lds, L);
+        tail_smooth<T>(v, L, tp.nu1, true);
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
+            int x = j % v.mx, y = j / v.mx;
+            v.t[j] = resid_point<T>(L.P, v.u[j], at2(v.u, v.mx, v.my, x - 1, y), at2(v.u, v.mx, v.my, x + 1, y),
+                                    at2(v.u, v.mx, v.my, x, y - 1), at2(v.u, v.mx, v.my, x, y + 1), v.b[j], L.q[j]);
+        }
+        __syncthreads();
+        TailView<T> c = tail_view(lds, tp.lv[i + 1]);
+        const T w[3] = {T(0.25), T(0.5), T(0.25)};
+        for (int J = threadIdx.x; J < c.N; J += blockDim.x) {
+            int I = J % c.mx, K = J / c.mx;
+            int fx = 2 * I + 1, fy = 2 * K + 1;
+            cx<T> acc = {T(0), T(0)};
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    T wgt = (w[dx + 1] * w[dy + 1]) * T(1);
+                    acc = acc + wgt * v.t[(fy + dy) * v.mx + (fx + dx)];
+                }
+            c.b[J] = acc;
+        }
+        __syncthreads();
+    }
+    // coarsest: u = A^{-1} b in FP64, one wave per row, lane-strided sums then
+    // a shuffle tree (the order of the one-operation kernel)
+    {
+        TailView<T> c = tail_view(lds, tp.lv[nt - 1]);
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        const int n = tp.nc;
+        for (int row = wave; row < n; row += nw) {
+            const cd *ar = tp.aug + (size_t)row * 2 * n + n;
+            double re = 0.0, im = 0.0;
+            for (int k = lane; k < n; k += 64) {
+                cd a = ar[k];
+                cx<T> bk = c.b[k];
+                double br = (double)bk.re, bi = (double)bk.im;
+                re += a.re * br - a.im * bi;
+                im += a.re * bi + a.im * br;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                re += __shfl_down(re, off, 64);
+                im += __shfl_down(im, off, 64);
+            }
+            if (lane == 0) c.u[row] = cx<T>{T(re), T(im)};
+        }
+        __syncthreads();
+    }
+    // up: interpolation of the correction, smoothing
+    for (int i = nt - 2; i >= 0; --i) {
+        const TailLevel<T> &L = tp.lv[i];
+        TailView<T> v = tail_view(lds, L);
+        TailView<T> c = tail_view(lds, tp.lv[i + 1]);
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
+            int x = j % v.mx, y = j / v.mx;
+            v.u[j] = v.u[j] + interp2d<T>(c.u, c.mx, 0, 0, c.mx, c.my, x, y);
+        }
+        __syncthreads();
+        tail_smooth<T>(v, L, tp.nu2, false);
+    }
+    TailView<T> v0 = tail_view(lds, tp.lv[0]);
+    for (int j = threadIdx.x; j < v0.N; j += blockDim.x) u_top[j] = v0.u[j];
+}
+
+// ---------------------------------------------------------------------------
+static int tiles2d(const LevelGeom &g, int &tx)
+{
+    tx = (g.m[0] + FTX - 1) / FTX;
+    return tx * ((g.m[1] + FTY - 1) / FTY);
+}
+
+int fused2d_blocks(const LevelGeom &g)
+{
+    int tx;
+    return tiles2d(g, tx);
+}
+
+template <typename T>
+void launch_smooth2d(const LevelGeom &g, const Stencil<T> &P, int nsweeps, bool zero, const cx<T> *u,
+                     const cx<T> *ec, const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
+                     const int *stop)
+{
+    const int tx = (g.m[0] + FTX - 1) / FTX;
+    const int nb = tx * ((g.m[1] + smooth_th<T>() - 1) / smooth_th<T>());
+    dim3 G(nb), B(256);
+#define SM(NS, Z, PR, TAG) \
+    hipLaunchKernelGGL((k_smooth2d<T, NS, Z, PR, TAG>), G, B, 0, s, u, ec, b, q, out, P, tx, stop)
+    const bool prol = (ec != nullptr);
+    if (nsweeps == 2) {
+        if (zero) {
+            if (finest) SM(2, true, false, 1); else SM(2, true, false, 0);
+        } else if (prol) {
+            if (finest) SM(2, false, true, 1); else SM(2, false, true, 0);
+        } else {
+            if (finest) SM(2, false, false, 1); else SM(2, false, false, 0);
+        }
+    } else {
+        if (zero) SM(1, true, false, 0);
+        else if (prol) SM(1, false, true, 0);
+        else SM(1, false, false, 0);
+    }
+#undef SM
+}
+template void launch_smooth2d<double>(const LevelGeom &, const Stencil<double> &, int, bool, const cd *, const cd *,
+                                      const cd *, const cd *, cd *, hipStream_t, bool, const int *);
+template void launch_smooth2d<float>(const LevelGeom &, const Stencil<float> &, int, bool, const cf *, const cf *,
+                                     const cf *, const cf *, cf *, hipStream_t, bool, const int *);
+
+template <typename T>
+void launch_resid_restrict2d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b,
+                             const cx<T> *q, cx<T> *bc, hipStream_t s, const int *stop)
+{
+    int mxc = (g.m[0] - 1) / 2, myc = (g.m[1] - 1) / 2;
+    int ctx = (mxc + RCX - 1) / RCX, cty = (myc + RCY - 1) / RCY;
+    hipLaunchKernelGGL((k_resid_restrict2d<T>), dim3(ctx * cty), dim3(256), 0, s, u, b, q, bc, P, ctx, stop);
+}
+template void launch_resid_restrict2d<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
+                                              const cd *, cd *, hipStream_t, const int *);
+template void launch_resid_restrict2d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
+                                             const cf *, cf *, hipStream_t, const int *);
+
+void launch_refine2d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
+                     const cd *q, cd *u_out, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t st,
+                     const int *stop)
+{
+    int tx;
+    int nb = tiles2d(g, tx);
+    hipLaunchKernelGGL(k_refine2d, dim3(nb), dim3(256), 0, st, u, d, b, q, u_out, r32, ctl, P, tx, partial, stop);
+}
+
+template <typename T>
+size_t tail2d_lds_bytes(const int *mx, const int *my, int nt)
+{
+    size_t n = 0;
+    for (int i = 0; i < nt; ++i) n += 3 * (size_t)mx[i] * my[i];
+    return n * sizeof(cx<T>);
+}
+template size_t tail2d_lds_bytes<double>(const int *, const int *, int);
+template size_t tail2d_lds_bytes<float>(const int *, const int *, int);
+
+template <typename T>
+void launch_tail2d(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top, cx<T> *u_top, hipStream_t s,
+                   const int *stop)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_tail2d<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_tail2d<T>), dim3(1), dim3(1024), lds_bytes, s, tp, b_top, u_top, stop);
+}
+template void launch_tail2d<double>(const TailParams<double> &, size_t, const cd *, cd *, hipStream_t, const int *);
+template void launch_tail2d<float>(const TailParams<float> &, size_t, const cf *, cf *, hipStream_t, const int *);
+
+}  // namespace ffmg

@@ -1,0 +1,103 @@
+// ffmg_handle.hpp -- the handle behind the C ABI and the driver entry points
+// shared by the library's translation units (single solve, batched solve,
+// learned smoother).
+#pragma once
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/ffmg.h"
+#include "ffmg_internal.hpp"
+
+namespace ffmg {
+
+struct Level {
+    LevelGeom g;
+    Stencil<double> P64;
+    Stencil<float> P32;
+    cd *q = nullptr;                 // contrast on this level
+    cd *u = nullptr, *b = nullptr;   // coarse correction / rhs (levels >= 1)
+    cd *r = nullptr, *t = nullptr;   // residual / scratch, ping-pong buffer
+    cf *q32 = nullptr;               // FP32 copies for the refinement inner cycle
+    cf *u32 = nullptr, *b32 = nullptr, *r32 = nullptr, *t32 = nullptr;
+};
+
+// tile_config values
+enum { TILE_FUSED = 0, TILE_REFERENCE = 1, TILE_FUSED_NO_TAIL = 2 };
+
+}  // namespace ffmg
+
+struct ffmg_handle {
+    ffmg_problem prob{};
+    ffmg_options opt{};
+    double k0 = 0.0, k02 = 0.0;
+    std::vector<ffmg::Level> L;
+    ffmg::cd *aug = nullptr;         // [A_c | A_c^{-1}] of the coarsest level
+    int nc = 0;
+    int *d_info = nullptr;
+    double *d_parts = nullptr;       // per-block partial sums
+    int nparts = 0;
+    double *d_scalar = nullptr;
+    double *h_scalar = nullptr;      // pinned
+    ffmg::SolveCtl *d_ctl = nullptr; // device solve control
+    ffmg::SolveCtl *h_ctl = nullptr; // pinned copy
+    int last_cycles = 0;             // cycles of the previous solve (batch sizing)
+    hipStream_t stream = nullptr;
+    // coarse end of the 2D cycle run by one workgroup in LDS (levels >= tail_l)
+    int tail_l = -1;
+    size_t tail_lds[2] = {0, 0};     // [FP64, FP32]
+    ffmg::TailParams<double> tail64{};
+    ffmg::TailParams<float> tail32{};
+    ffmg::FarFieldPlan *ff = nullptr;
+    ffmg::cd *d_s = nullptr;         // far-field integrand
+    ffmg::cd *d_E = nullptr;         // plane-wave axis factors
+    ffmg::cd *d_F = nullptr;         // far-field staging
+    int d_F_cap = 0;
+    std::vector<void *> allocs;
+    std::string err;
+    // optional event timing of selected kernels (benchmark instrumentation)
+    int profile_mask = 0;            // bit k: time kernel k (ffmg::ProfKernel)
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[ffmg::PROF_N];
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_free;
+};
+
+namespace ffmg {
+
+ffmg_status fail(ffmg_handle *h, ffmg_status s, const char *fmt, ...);
+template <typename P>
+ffmg_status dalloc(ffmg_handle *h, P **p, size_t bytes)
+{
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(h, FFMG_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    h->allocs.push_back(v);
+    *p = (P *)v;
+    return FFMG_OK;
+}
+
+// One V(nu1, nu2) cycle on level l; every launch carries `stop`.
+template <typename T>
+void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop);
+
+int prof_begin(ffmg_handle *h, int k);
+void prof_end(ffmg_handle *h, int k, int idx);
+
+}  // namespace ffmg
+
+#define HIPCHK(h, x)                                                                                                \
+    do {                                                                                                            \
+        hipError_t e_ = (x);                                                                                        \
+        if (e_ != hipSuccess)                                                                                       \
+            return ffmg::fail((h), e_ == hipErrorOutOfMemory ? FFMG_ENOMEM : FFMG_EDEVICE, "%s: %s (%s:%d)", #x,    \
+                              hipGetErrorString(e_), __FILE__, __LINE__);                                           \
+    } while (0)
+
+#define TRY(x)                                                                                                      \
+    do {                                                                                                            \
+        ffmg_status s_ = (x);                                                                                       \
+        if (s_ != FFMG_OK) return s_;                                                                               \
+    } while (0)

@@ -1,5 +1,11 @@
 // ffmg_internal.hpp -- host-side declarations shared by the library's
 // translation units (kernel launchers and the handle).
+//
+// Every launcher that runs inside the solve loop takes `stop`, a device int
+// (or null): when it is non-zero the kernel returns at entry.  The solve loop
+// enqueues several V-cycles ahead; once the control kernel (k_ctl_update)
+// has decided to stop, the cycles already queued cost only empty launches
+// and leave every result untouched.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,6 +18,31 @@
 namespace ffmg {
 
 enum StencilMode { MODE_APPLY = 0, MODE_RESID = 1, MODE_JACOBI = 2, MODE_RNORM = 3, MODE_JACOBI0 = 4 };
+
+// Kernels timed by the optional event instrumentation (mg_profile_*).
+enum ProfKernel {
+    PROF_PRE = 0,      // finest-level pre-smoothing (fused 2-sweep kernel, or each sweep)
+    PROF_FF = 1,       // far-field contraction
+    PROF_POST = 2,     // finest-level interpolation + post-smoothing (fused)
+    PROF_REFINE = 3,   // FP64 update + residual of the refinement loop (fused)
+    PROF_N = 4
+};
+
+// Device-resident state of one solve (residual-reduction stopping test of
+// Sec. 4, growth test, and the scales of the mixed-precision refinement).
+struct SolveCtl {
+    double tol2b2;     // (tol ||b||)^2
+    double inv_sqN;    // 1 / sqrt(N)
+    double r0_2;       // ||r_0||^2
+    double rk2;        // latest ||r_k||^2
+    double prev2;      // ||r_{k-1}||^2
+    double scale_cur;  // the FP32 right-hand side now in use is r / scale_cur
+    double scale_next; // the next one is written as r / scale_next
+    int done;          // 0 running, 1 converged, 2 residual grew 3 times, 3 cycle limit, 4 non-finite
+    int k;             // completed cycles / refinement steps
+    int grow;
+    int max_cycles;
+};
 
 // Geometry of one level (interior extents, spacings, origin).
 struct LevelGeom {
@@ -32,22 +63,32 @@ int stencil_blocks(const LevelGeom &g);
 // MODE_RESID and MODE_RNORM (may be null in MODE_RESID).
 // finest = true gives MODE_JACOBI launches their own kernel symbol.
 template <typename T>
-void launch_stencil(int mode, const LevelGeom &g, const Stencil<T> &P, const cx<T> *u,
-                    const cx<T> *b, const cx<T> *q, cx<T> *out, double *partial, hipStream_t s,
-                    bool finest = false);
+void launch_stencil(int mode, const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b,
+                    const cx<T> *q, cx<T> *out, double *partial, hipStream_t s, bool finest = false,
+                    const int *stop = nullptr);
 
 template <typename T>
-void launch_restrict(const LevelGeom &fine, const cx<T> *rf, cx<T> *bc, hipStream_t s);
+void launch_restrict(const LevelGeom &fine, const cx<T> *rf, cx<T> *bc, hipStream_t s, const int *stop = nullptr);
 
 template <typename T>
-void launch_prolong_add(const LevelGeom &fine, const cx<T> *ec, cx<T> *uf, hipStream_t s);
+void launch_prolong_add(const LevelGeom &fine, const cx<T> *ec, cx<T> *uf, hipStream_t s,
+                        const int *stop = nullptr);
+
+template <typename T>
+void launch_copy(const cx<T> *src, cx<T> *dst, size_t N, hipStream_t s, const int *stop);
+template <typename T>
+void launch_zero(cx<T> *dst, size_t N, hipStream_t s, const int *stop);
 
 // sum of nparts doubles -> *out (device), deterministic single-block reduce.
 void launch_sum(const double *parts, int nparts, double *out, hipStream_t s);
 
+// Solve control: init from ||b||^2 (device scalar), update from per-block
+// partial sums of ||r||^2 (same reduction order as launch_sum).
+void launch_ctl_init(SolveCtl *ctl, const double *bnorm2, double tol, size_t N, int max_cycles, hipStream_t s);
+void launch_ctl_update(SolveCtl *ctl, const double *parts, int nparts, hipStream_t s);
+
 // Setup kernels.
-void launch_make_q(const cd *coef, cd *q, size_t N, double scale, double *bad_parts, int nparts,
-                   hipStream_t s);
+void launch_make_q(const cd *coef, cd *q, size_t N, double scale, double *bad_parts, int nparts, hipStream_t s);
 template <typename T>
 void launch_inject(const LevelGeom &fine, const cx<T> *qf, cx<T> *qc, hipStream_t s);
 template <typename To, typename Ti>
@@ -55,14 +96,58 @@ void launch_convert(const cx<Ti> *in, cx<To> *out, size_t N, hipStream_t s);
 void launch_build_coarse(const LevelGeom &g, const Stencil<double> &P, const cd *q, cd *aug, hipStream_t s);
 void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s);
 template <typename T>
-void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s);
-void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const double eta[3],
-                           const cd *q, cd *b, hipStream_t s);
+void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s, const int *stop = nullptr);
+void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
+                           hipStream_t s);
 
-// Mixed-precision refinement: u64 += s * d32; r64 = b - A u64 -> r32 = r64 / scale.
-void launch_refine_update(const cf *d, cd *u, double scale, size_t N, hipStream_t s);
-void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b,
-                         const cd *q, cf *r32, double inv_scale, double *partial, hipStream_t s);
+// Mixed-precision refinement (one-operation form): u64 += s * d32 with
+// s = ctl->scale_cur; r64 = b - A u64 written as r64 / ctl->scale_next.
+void launch_refine_update(const cf *d, cd *u, const SolveCtl *ctl, size_t N, hipStream_t s, const int *stop);
+void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
+                         cf *r32, double inv_scale, double *partial, hipStream_t s);
+void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
+                             cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s, const int *stop);
+
+// Fused 2D level kernels (ffmg_fused2d.hip).  launch_smooth2d runs 1 or 2
+// sweeps from u (or from 0 when zero) into out; with ec != null the coarse
+// correction P ec is added to u first.
+int fused2d_blocks(const LevelGeom &g);
+template <typename T>
+void launch_smooth2d(const LevelGeom &g, const Stencil<T> &P, int nsweeps, bool zero, const cx<T> *u,
+                     const cx<T> *ec, const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
+                     const int *stop);
+template <typename T>
+void launch_resid_restrict2d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b,
+                             const cx<T> *q, cx<T> *bc, hipStream_t s, const int *stop);
+void launch_refine2d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
+                     const cd *q, cd *u_out, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t st,
+                     const int *stop);
+
+// The coarse end of a 2D V-cycle in one workgroup, all fields in LDS: the
+// levels lt .. L-1 of the hierarchy (small enough for LDS) and the exact
+// coarsest solve.  Reads b of level lt, writes its correction u (zero guess).
+constexpr int TAIL_MAX_LEVELS = 6;
+template <typename T>
+struct TailLevel {
+    int mx, my;
+    int off;               // element offset of this level's fields in LDS
+    Stencil<T> P;
+    const cx<T> *q;
+};
+template <typename T>
+struct TailParams {
+    int nt;                // tail levels including the coarsest
+    int nu1, nu2;
+    const cd *aug;         // [A | A^{-1}] of the coarsest level, row stride 2 nc
+    int nc;
+    TailLevel<T> lv[TAIL_MAX_LEVELS];
+};
+// LDS bytes the tail needs for the given levels (0 if it does not fit).
+template <typename T>
+size_t tail2d_lds_bytes(const int *mx, const int *my, int nt);
+template <typename T>
+void launch_tail2d(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top, cx<T> *u_top, hipStream_t s,
+                   const int *stop);
 
 // Far field (ffmg_farfield.hip).
 struct FarFieldPlan;

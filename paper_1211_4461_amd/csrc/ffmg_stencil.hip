@@ -11,7 +11,10 @@
 // registers), read b and q once, coalesced, and write the result once.
 #include <math.h>
 
+#include <algorithm>
+
 #include "ffmg_internal.hpp"
+#include "ffmg_point.hpp"
 
 namespace ffmg {
 
@@ -27,19 +30,20 @@ Stencil<T> make_stencil(const LevelGeom &g, double gamma, double k02, double ome
     P.my = g.m[1];
     P.mz = g.m[2];
     double cr = cos(-2.0 * gamma), ci = sin(-2.0 * gamma);
-    double sr = 0.0, si = 0.0;
+    double s2 = 0.0;
+    P.rot = cx<T>{T(cr), T(ci)};
     for (int k = 0; k < 3; ++k) {
         if (k < g.dim) {
-            double h2 = g.h[k] * g.h[k];
-            double pr = cr / h2, pi = ci / h2;
-            P.c[k] = cx<T>{T(pr), T(pi)};
-            sr += 2.0 * pr;
-            si += 2.0 * pi;
+            double ih2 = 1.0 / (g.h[k] * g.h[k]);
+            P.c[k] = cx<T>{T(cr * ih2), T(ci * ih2)};
+            P.ih2[k] = T(ih2);
+            s2 += 2.0 * ih2;
         } else {
             P.c[k] = cx<T>{T(0), T(0)};
+            P.ih2[k] = T(0);
         }
     }
-    P.csum2 = cx<T>{T(sr), T(si)};
+    P.csum2 = cx<T>{T(cr * s2), T(ci * s2)};
     P.k02 = T(k02);
     P.omega = T(omega);
     return P;
@@ -51,31 +55,23 @@ template Stencil<float> make_stencil<float>(const LevelGeom &, double, double, d
 // The point update shared by all stencil kernels.
 // MODE_RESID writes rscale * r converted to TO (the FP64 residual of the
 // refinement loop is written as a scaled FP32 right-hand side this way).
+// L = sum_k (2u - u_- - u_+)/h_k^2, the weighted second differences.
 template <typename T, typename TO, int MODE>
-__device__ __forceinline__ void point_update(const Stencil<T> &P, T rscale, cx<T> uc, cx<T> lap, size_t j,
+__device__ __forceinline__ void point_update(const Stencil<T> &P, T rscale, cx<T> uc, cx<T> L, size_t j,
                                              const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                              cx<TO> *__restrict__ out, double &acc)
 {
     cx<T> qj = q[j];
-    cx<T> kap = {P.k02 + qj.re, qj.im};
-    cx<T> Au = lap - kap * uc;
     if (MODE == MODE_APPLY) {
-        out[j] = cvt<TO>(Au);
+        out[j] = cvt<TO>(apply_point(P, L, uc, qj));
     } else if (MODE == MODE_JACOBI0) {
-        // first sweep from a zero guess: u' = omega b / D
-        cx<T> D = P.csum2 - kap;
-        out[j] = cvt<TO>(P.omega * (b[j] * recip(D)));
+        out[j] = cvt<TO>(jacobi0_from(P, b[j], qj));
+    } else if (MODE == MODE_JACOBI) {
+        out[j] = cvt<TO>(jacobi_from(P, L, uc, b[j], qj));
     } else {
-        cx<T> r = b[j] - Au;
-        if (MODE == MODE_RESID) {
-            out[j] = cvt<TO>(rscale * r);
-            acc += (double)abs2(r);
-        } else if (MODE == MODE_RNORM) {
-            acc += (double)abs2(r);
-        } else {
-            cx<T> D = P.csum2 - kap;
-            out[j] = cvt<TO>(uc + P.omega * (r * recip(D)));
-        }
+        cx<T> r = resid_from(P, L, uc, b[j], qj);
+        if (MODE == MODE_RESID) out[j] = cvt<TO>(rscale * r);
+        acc += (double)abs2(r);
     }
 }
 
@@ -95,8 +91,11 @@ __device__ __forceinline__ void block_sum_256(double acc, double *partial)
 template <typename T, typename TO, int MODE, int TAG>
 __global__ __launch_bounds__(256) void k_stencil2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
                                                    const cx<T> *__restrict__ q, cx<TO> *__restrict__ out,
-                                                   Stencil<T> P, T rscale, int tiles_x, double *__restrict__ partial)
+                                                   Stencil<T> P, T rscale, int tiles_x, double *__restrict__ partial,
+                                                   const SolveCtl *__restrict__ ctl, const int *__restrict__ stop)
 {
+    if (stop && *stop) return;
+    if (ctl) rscale = T(1.0 / ctl->scale_next);
     __shared__ cx<T> s[TY2 + 2][66];
     const int mx = P.mx, my = P.my;
     int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -106,9 +105,7 @@ __global__ __launch_bounds__(256) void k_stencil2d(const cx<T> *__restrict__ u, 
         for (int i = threadIdx.x; i < (TY2 + 2) * 66; i += 256) {
             int ly = i / 66, lx = i - ly * 66;
             int gx = tx0 + lx - 1, gy = ty0 + ly - 1;
-            cx<T> v = {T(0), T(0)};
-            if (gx >= 0 && gx < mx && gy >= 0 && gy < my) v = u[(size_t)gy * mx + gx];
-            s[ly][lx] = v;
+            s[ly][lx] = ld_masked(u, (size_t)gy * mx + gx, gx >= 0 && gx < mx && gy >= 0 && gy < my);
         }
         __syncthreads();
     }
@@ -124,9 +121,7 @@ __global__ __launch_bounds__(256) void k_stencil2d(const cx<T> *__restrict__ u, 
             cx<T> uc = {T(0), T(0)}, lap = {T(0), T(0)};
             if (!zero_u) {
                 uc = s[ly + 1][lx + 1];
-                cx<T> two_u = T(2) * uc;
-                lap = P.c[0] * ((two_u - s[ly + 1][lx]) - s[ly + 1][lx + 2]);
-                lap = lap + P.c[1] * ((two_u - s[ly][lx + 1]) - s[ly + 2][lx + 1]);
+                lap = lap_xy(P, uc, s[ly + 1][lx], s[ly + 1][lx + 2], s[ly][lx + 1], s[ly + 2][lx + 1]);
             }
             point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
         }
@@ -142,8 +137,11 @@ template <typename T, typename TO, int MODE, int TAG>
 __global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
                                                    const cx<T> *__restrict__ q, cx<TO> *__restrict__ out,
                                                    Stencil<T> P, T rscale, int tiles_x, int tiles_y,
-                                                   double *__restrict__ partial)
+                                                   double *__restrict__ partial, const SolveCtl *__restrict__ ctl,
+                                                   const int *__restrict__ stop)
 {
+    if (stop && *stop) return;
+    if (ctl) rscale = T(1.0 / ctl->scale_next);
     constexpr int PY = TY3 / 4;
     __shared__ cx<T> s[2][TY3 + 2][66];
     const int mx = P.mx, my = P.my, mz = P.mz;
@@ -158,11 +156,9 @@ __global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, 
     const size_t plane = (size_t)mx * my;
     const bool zero_u = (MODE == MODE_JACOBI0);
 
-    auto ld = [&](int x, int y, int z) -> cx<T> {
-        cx<T> v = {T(0), T(0)};
-        if (!zero_u && x >= 0 && x < mx && y >= 0 && y < my && z >= 0 && z < mz)
-            v = u[(size_t)z * plane + (size_t)y * mx + x];
-        return v;
+    auto ld = [=](int x, int y, int z) -> cx<T> {
+        bool in = !zero_u && x >= 0 && x < mx && y >= 0 && y < my && z >= 0 && z < mz;
+        return ld_masked(u, (size_t)z * plane + (size_t)y * mx + x, in);
     };
 
     cx<T> prev[PY], cur[PY], nxt[PY];
@@ -203,10 +199,9 @@ __global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, 
                 cx<T> uc = {T(0), T(0)}, lap = {T(0), T(0)};
                 if (!zero_u) {
                     uc = cur[i];
-                    cx<T> two_u = T(2) * uc;
-                    lap = P.c[0] * ((two_u - s[buf][ly + 1][lx]) - s[buf][ly + 1][lx + 2]);
-                    lap = lap + P.c[1] * ((two_u - s[buf][ly][lx + 1]) - s[buf][ly + 2][lx + 1]);
-                    lap = lap + P.c[2] * ((two_u - prev[i]) - nxt[i]);
+                    lap = lap_xy(P, uc, s[buf][ly + 1][lx], s[buf][ly + 1][lx + 2], s[buf][ly][lx + 1],
+                                 s[buf][ly + 2][lx + 1]);
+                    lap = lap_add_z(P, lap, uc, prev[i], nxt[i]);
                 }
                 point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
             }
@@ -245,47 +240,76 @@ int stencil_blocks(const LevelGeom &g)
 
 template <typename T, typename TO, int MODE, int TAG = 0>
 static void launch_mode(const LevelGeom &g, const Stencil<T> &P, T rscale, const cx<T> *u, const cx<T> *b,
-                        const cx<T> *q, cx<TO> *out, double *partial, hipStream_t s)
+                        const cx<T> *q, cx<TO> *out, double *partial, hipStream_t s, const SolveCtl *ctl = nullptr,
+                        const int *stop = nullptr)
 {
     int nb, tx, ty;
     grid_of(g, nb, tx, ty);
     if (g.dim == 2)
         hipLaunchKernelGGL((k_stencil2d<T, TO, MODE, TAG>), dim3(nb), dim3(256), 0, s, u, b, q, out, P, rscale, tx,
-                           partial);
+                           partial, ctl, stop);
     else
         hipLaunchKernelGGL((k_stencil3d<T, TO, MODE, TAG>), dim3(nb), dim3(256), 0, s, u, b, q, out, P, rscale, tx,
-                           ty, partial);
+                           ty, partial, ctl, stop);
 }
 
 template <typename T>
 void launch_stencil(int mode, const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b,
-                    const cx<T> *q, cx<T> *out, double *partial, hipStream_t s, bool finest)
+                    const cx<T> *q, cx<T> *out, double *partial, hipStream_t s, bool finest, const int *stop)
 {
     const T one = T(1);
     if (finest && mode == MODE_JACOBI) {
-        launch_mode<T, T, MODE_JACOBI, 1>(g, P, one, u, b, q, out, partial, s);
+        launch_mode<T, T, MODE_JACOBI, 1>(g, P, one, u, b, q, out, partial, s, nullptr, stop);
         return;
     }
     switch (mode) {
-    case MODE_APPLY: launch_mode<T, T, MODE_APPLY>(g, P, one, u, b, q, out, partial, s); break;
-    case MODE_RESID: launch_mode<T, T, MODE_RESID>(g, P, one, u, b, q, out, partial, s); break;
-    case MODE_RNORM: launch_mode<T, T, MODE_RNORM>(g, P, one, u, b, q, out, partial, s); break;
-    case MODE_JACOBI0: launch_mode<T, T, MODE_JACOBI0>(g, P, one, u, b, q, out, partial, s); break;
-    default: launch_mode<T, T, MODE_JACOBI>(g, P, one, u, b, q, out, partial, s); break;
+    case MODE_APPLY: launch_mode<T, T, MODE_APPLY>(g, P, one, u, b, q, out, partial, s, nullptr, stop); break;
+    case MODE_RESID: launch_mode<T, T, MODE_RESID>(g, P, one, u, b, q, out, partial, s, nullptr, stop); break;
+    case MODE_RNORM: launch_mode<T, T, MODE_RNORM>(g, P, one, u, b, q, out, partial, s, nullptr, stop); break;
+    case MODE_JACOBI0: launch_mode<T, T, MODE_JACOBI0>(g, P, one, u, b, q, out, partial, s, nullptr, stop); break;
+    default: launch_mode<T, T, MODE_JACOBI>(g, P, one, u, b, q, out, partial, s, nullptr, stop); break;
     }
 }
 template void launch_stencil<double>(int, const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
-                                     const cd *, cd *, double *, hipStream_t, bool);
+                                     const cd *, cd *, double *, hipStream_t, bool, const int *);
 template void launch_stencil<float>(int, const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
-                                    const cf *, cf *, double *, hipStream_t, bool);
+                                    const cf *, cf *, double *, hipStream_t, bool, const int *);
+
+// Copy / zero with the loop's stop flag.
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(const cx<T> *__restrict__ src, cx<T> *__restrict__ dst, size_t N,
+                                              const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256)
+        dst[j] = src ? src[j] : cx<T>{T(0), T(0)};
+}
+
+template <typename T>
+void launch_copy(const cx<T> *src, cx<T> *dst, size_t N, hipStream_t s, const int *stop)
+{
+    size_t nb = std::min<size_t>((N + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_copy<T>), dim3((unsigned)nb), dim3(256), 0, s, src, dst, N, stop);
+}
+template <typename T>
+void launch_zero(cx<T> *dst, size_t N, hipStream_t s, const int *stop)
+{
+    launch_copy<T>(nullptr, dst, N, s, stop);
+}
+template void launch_copy<double>(const cd *, cd *, size_t, hipStream_t, const int *);
+template void launch_copy<float>(const cf *, cf *, size_t, hipStream_t, const int *);
+template void launch_zero<double>(cd *, size_t, hipStream_t, const int *);
+template void launch_zero<float>(cf *, size_t, hipStream_t, const int *);
 
 // ---------------------------------------------------------------------------
 // Full weighting: coarse node I <- fine 2I-1, 2I, 2I+1 with (1/4, 1/2, 1/4),
 // tensorised; summed z-outer, x-inner.  One thread per coarse point.
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_restrict(const cx<T> *__restrict__ rf, cx<T> *__restrict__ bc,
-                                                  int mxf, int myf, int mxc, int myc, int mzc)
+                                                  int mxf, int myf, int mxc, int myc, int mzc,
+                                                  const int *__restrict__ stop)
 {
+    if (stop && *stop) return;
     size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     size_t Nc = (size_t)mxc * myc * mzc;
     if (idx >= Nc) return;
@@ -312,18 +336,20 @@ __global__ __launch_bounds__(256) void k_restrict(const cx<T> *__restrict__ rf, 
 }
 
 template <typename T>
-void launch_restrict(const LevelGeom &f, const cx<T> *rf, cx<T> *bc, hipStream_t s)
+void launch_restrict(const LevelGeom &f, const cx<T> *rf, cx<T> *bc, hipStream_t s, const int *stop)
 {
     int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.dim == 3) ? (f.m[2] - 1) / 2 : 1;
     size_t Nc = (size_t)mxc * myc * mzc;
     int nb = (int)((Nc + 255) / 256);
     if (f.dim == 2)
-        hipLaunchKernelGGL((k_restrict<T, 2>), dim3(nb), dim3(256), 0, s, rf, bc, f.m[0], f.m[1], mxc, myc, mzc);
+        hipLaunchKernelGGL((k_restrict<T, 2>), dim3(nb), dim3(256), 0, s, rf, bc, f.m[0], f.m[1], mxc, myc, mzc,
+                           stop);
     else
-        hipLaunchKernelGGL((k_restrict<T, 3>), dim3(nb), dim3(256), 0, s, rf, bc, f.m[0], f.m[1], mxc, myc, mzc);
+        hipLaunchKernelGGL((k_restrict<T, 3>), dim3(nb), dim3(256), 0, s, rf, bc, f.m[0], f.m[1], mxc, myc, mzc,
+                           stop);
 }
-template void launch_restrict<double>(const LevelGeom &, const cd *, cd *, hipStream_t);
-template void launch_restrict<float>(const LevelGeom &, const cf *, cf *, hipStream_t);
+template void launch_restrict<double>(const LevelGeom &, const cd *, cd *, hipStream_t, const int *);
+template void launch_restrict<float>(const LevelGeom &, const cf *, cf *, hipStream_t, const int *);
 
 // Linear interpolation: fine node f (1-based) takes coarse nodes floor(f/2)
 // and ceil(f/2) with weights 1 (f even) or 1/2 (f odd), tensorised; coarse
@@ -337,8 +363,10 @@ __device__ __forceinline__ T iw(int f, int C)
 
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_prolong_add(const cx<T> *__restrict__ ec, cx<T> *__restrict__ uf,
-                                                     int mxf, int myf, int mzf, int mxc, int myc, int mzc)
+                                                     int mxf, int myf, int mzf, int mxc, int myc, int mzc,
+                                                     const int *__restrict__ stop)
 {
+    if (stop && *stop) return;
     size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     size_t Nf = (size_t)mxf * myf * mzf;
     if (idx >= Nf) return;
@@ -362,23 +390,24 @@ __global__ __launch_bounds__(256) void k_prolong_add(const cx<T> *__restrict__ e
 }
 
 template <typename T>
-void launch_prolong_add(const LevelGeom &f, const cx<T> *ec, cx<T> *uf, hipStream_t s)
+void launch_prolong_add(const LevelGeom &f, const cx<T> *ec, cx<T> *uf, hipStream_t s, const int *stop)
 {
     int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.dim == 3) ? (f.m[2] - 1) / 2 : 1;
     size_t Nf = f.N();
     int nb = (int)((Nf + 255) / 256);
     if (f.dim == 2)
-        hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nb), dim3(256), 0, s, ec, uf, f.m[0], f.m[1], 1, mxc, myc, 1);
+        hipLaunchKernelGGL((k_prolong_add<T, 2>), dim3(nb), dim3(256), 0, s, ec, uf, f.m[0], f.m[1], 1, mxc, myc, 1,
+                           stop);
     else
         hipLaunchKernelGGL((k_prolong_add<T, 3>), dim3(nb), dim3(256), 0, s, ec, uf, f.m[0], f.m[1], f.m[2], mxc,
-                           myc, mzc);
+                           myc, mzc, stop);
 }
-template void launch_prolong_add<double>(const LevelGeom &, const cd *, cd *, hipStream_t);
-template void launch_prolong_add<float>(const LevelGeom &, const cf *, cf *, hipStream_t);
+template void launch_prolong_add<double>(const LevelGeom &, const cd *, cd *, hipStream_t, const int *);
+template void launch_prolong_add<float>(const LevelGeom &, const cf *, cf *, hipStream_t, const int *);
 
 // ---------------------------------------------------------------------------
 // Deterministic sum of per-block partials (one block, fixed order).
-__global__ __launch_bounds__(256) void k_sum(const double *__restrict__ parts, int n, double *__restrict__ out)
+__device__ __forceinline__ double sum_parts_256(const double *__restrict__ parts, int n)
 {
     __shared__ double red[4];
     double acc = 0.0;
@@ -387,7 +416,68 @@ __global__ __launch_bounds__(256) void k_sum(const double *__restrict__ parts, i
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     if (lane == 0) red[w] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_sum(const double *__restrict__ parts, int n, double *__restrict__ out)
+{
+    double s = sum_parts_256(parts, n);
+    if (threadIdx.x == 0) out[0] = s;
+}
+
+// Solve control.  Init: from ||b||^2.  Update (after each cycle's residual
+// norm, and once for the initial residual with k = 0): the stopping test
+// ||r_k|| <= tol ||b|| (Sec. 4), the growth test (3 consecutive increases),
+// the cycle limit, and the scales of the next FP32 right-hand side.
+__global__ void k_ctl_init(SolveCtl *ctl, const double *__restrict__ bnorm2, double tol, double inv_sqN,
+                           int max_cycles)
+{
+    if (threadIdx.x != 0) return;
+    double b2 = bnorm2[0];
+    SolveCtl c;
+    c.tol2b2 = tol * tol * b2;
+    c.inv_sqN = inv_sqN;
+    c.r0_2 = c.rk2 = c.prev2 = 0.0;
+    c.scale_cur = sqrt(b2) * inv_sqN;
+    c.scale_next = c.scale_cur;
+    c.done = 0;
+    c.k = -1;          // the first update is the initial residual
+    c.grow = 0;
+    c.max_cycles = max_cycles;
+    *ctl = c;
+}
+
+__global__ __launch_bounds__(256) void k_ctl_update(SolveCtl *ctl, const double *__restrict__ parts, int n)
+{
+    if (ctl->done) return;
+    double s2 = sum_parts_256(parts, n);
+    if (threadIdx.x != 0) return;
+    SolveCtl c = *ctl;
+    c.k += 1;
+    c.rk2 = s2;
+    c.scale_cur = c.scale_next;
+    c.scale_next = sqrt(s2) * c.inv_sqN;
+    if (c.k == 0) {
+        c.r0_2 = s2;
+    } else {
+        c.grow = (s2 >= c.prev2) ? c.grow + 1 : 0;
+    }
+    if (!isfinite(s2)) c.done = 4;
+    else if (s2 <= c.tol2b2) c.done = 1;
+    else if (c.grow >= 3) c.done = 2;
+    else if (c.k >= c.max_cycles) c.done = 3;
+    c.prev2 = s2;
+    *ctl = c;
+}
+
+void launch_ctl_init(SolveCtl *ctl, const double *bnorm2, double tol, size_t N, int max_cycles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, s, ctl, bnorm2, tol, 1.0 / sqrt((double)N), max_cycles);
+}
+
+void launch_ctl_update(SolveCtl *ctl, const double *parts, int nparts, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_update, dim3(1), dim3(256), 0, s, ctl, parts, nparts);
 }
 
 void launch_sum(const double *parts, int nparts, double *out, hipStream_t s)
@@ -575,8 +665,9 @@ void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s)
 // augmented matrix, row stride 2n), in FP64 whatever T is.  One wave per row.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse_apply(const cd *__restrict__ aug, int n, const cx<T> *__restrict__ b,
-                                                      cx<T> *__restrict__ u)
+                                                      cx<T> *__restrict__ u, const int *__restrict__ stop)
 {
+    if (stop && *stop) return;
     int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     int lane = threadIdx.x & 63;
     if (row >= n) return;
@@ -597,12 +688,12 @@ __global__ __launch_bounds__(256) void k_coarse_apply(const cd *__restrict__ aug
 }
 
 template <typename T>
-void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s)
+void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s, const int *stop)
 {
-    hipLaunchKernelGGL((k_coarse_apply<T>), dim3((n + 3) / 4), dim3(256), 0, s, Ainv, n, b, u);
+    hipLaunchKernelGGL((k_coarse_apply<T>), dim3((n + 3) / 4), dim3(256), 0, s, Ainv, n, b, u, stop);
 }
-template void launch_coarse_apply<double>(const cd *, int, const cd *, cd *, hipStream_t);
-template void launch_coarse_apply<float>(const cd *, int, const cf *, cf *, hipStream_t);
+template void launch_coarse_apply<double>(const cd *, int, const cd *, cd *, hipStream_t, const int *);
+template void launch_coarse_apply<float>(const cd *, int, const cf *, cf *, hipStream_t, const int *);
 
 // ---------------------------------------------------------------------------
 // b_j = q_j exp(i k0 e^{i gamma} eta.x_j): the plane wave on the contour.
@@ -638,10 +729,15 @@ void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const do
 }
 
 // ---------------------------------------------------------------------------
-// Mixed-precision refinement kernels.
-__global__ __launch_bounds__(256) void k_refine_update(const cf *__restrict__ d, cd *__restrict__ u, double scale,
-                                                       size_t N)
+// Mixed-precision refinement kernels (one-operation form).  The FP64 update
+// u += s d uses s = ctl->scale_cur, the scale of the FP32 right-hand side the
+// correction d was solved for.
+__global__ __launch_bounds__(256) void k_refine_update(const cf *__restrict__ d, cd *__restrict__ u,
+                                                       const SolveCtl *__restrict__ ctl, size_t N,
+                                                       const int *__restrict__ stop)
 {
+    if (stop && *stop) return;
+    const double scale = ctl->scale_cur;
     for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
         cf dj = d[j];
         cd uj = u[j];
@@ -649,11 +745,11 @@ __global__ __launch_bounds__(256) void k_refine_update(const cf *__restrict__ d,
     }
 }
 
-void launch_refine_update(const cf *d, cd *u, double scale, size_t N, hipStream_t s)
+void launch_refine_update(const cf *d, cd *u, const SolveCtl *ctl, size_t N, hipStream_t s, const int *stop)
 {
     size_t nb = (N + 255) / 256;
     if (nb > 65536) nb = 65536;
-    hipLaunchKernelGGL(k_refine_update, dim3((unsigned)nb), dim3(256), 0, s, d, u, scale, N);
+    hipLaunchKernelGGL(k_refine_update, dim3((unsigned)nb), dim3(256), 0, s, d, u, ctl, N, stop);
 }
 
 // FP64 residual written as FP32 after scaling: r32 = (b - A u) * inv_scale,
@@ -662,6 +758,13 @@ void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd 
                          cf *r32, double inv_scale, double *partial, hipStream_t s)
 {
     launch_mode<double, float, MODE_RESID>(g, P, inv_scale, u, b, q, r32, partial, s);
+}
+
+// The same with the scale 1 / ctl->scale_next read on the device.
+void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
+                             cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s, const int *stop)
+{
+    launch_mode<double, float, MODE_RESID>(g, P, 1.0, u, b, q, r32, partial, s, ctl, stop);
 }
 
 }  // namespace ffmg

@@ -37,11 +37,13 @@ class Options(ctypes.Structure):
     _fields_ = [("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double),
                 ("coarsest_n", ctypes.c_int), ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("smoother_weights", ctypes.c_void_p),
-                ("ff_precision", ctypes.c_int), ("tile_config", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("ff_precision", ctypes.c_int), ("tile_config", ctypes.c_int), ("inner_cycles", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
-    _fields_ = [("cycles", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
+    _fields_ = [("cycles", ctypes.c_int), ("vcycles", ctypes.c_int), ("status", ctypes.c_int),
+                ("rel_residual", ctypes.c_double),
                 ("conv_factor", ctypes.c_double), ("fell_back", ctypes.c_int), ("t_solve_ms", ctypes.c_double)]
 
     def as_dict(self):
@@ -251,8 +253,12 @@ def mg_destroy(h: Handle):
 KERNEL_SWEEP, KERNEL_FARFIELD = 0, 1
 
 
-def mg_profile_enable(h: Handle, enable=True):
-    h._check(lib().mg_profile_enable(h.ptr, 1 if enable else 0), "mg_profile_enable")
+PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE = 0, 1, 2, 3
+
+
+def mg_profile_enable(h: Handle, mask=0xF):
+    """Time kernel k when bit k of mask is set (0 disables)."""
+    h._check(lib().mg_profile_enable(h.ptr, int(mask)), "mg_profile_enable")
 
 
 def mg_profile_read(h: Handle, kernel):

@@ -258,3 +258,73 @@ def test_no_convergence_reported(ff, orc):
     info = ff.mg_solve(h, b, u, raise_on_noconv=False)
     assert info.status == ff.FFMG_ENOCONV and info.cycles == 2
     assert torch.count_nonzero(u).item() > 0
+
+
+@pytest.mark.parametrize("n", [64, 128, 256])
+def test_fused_2d_path_is_bitwise_identical(ff, orc, n):
+    """The fused 2D level kernels (two sweeps per launch, interpolation fused
+    into post-smoothing, residual fused with restriction, fused refinement
+    step) perform the same per-point arithmetic as the one-operation kernels:
+    iterates agree bit for bit, for FP64 V-cycles and FP32-in-FP64 solves,
+    on grids with ragged tiles."""
+    w = W.bumps_2d(n=n, seed=n, k0=1.1, M=8)
+    hf, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    hr, _, _, _, _, _ = setup(ff, orc, w, tile_config=1)
+    b = ff.mg_rhs_plane_wave(hf, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    uf, ur = torch.zeros_like(b), torch.zeros_like(b)
+    for _ in range(3):
+        ff.mg_vcycle(hf, b, uf)
+        ff.mg_vcycle(hr, b, ur)
+    torch.cuda.synchronize()
+    assert torch.equal(uf, ur)
+    for nu1, nu2 in [(1, 1), (3, 0), (0, 3)]:
+        hf2, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2)
+        hr2, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2, tile_config=1)
+        uf, ur = torch.zeros_like(b), torch.zeros_like(b)
+        for _ in range(2):
+            ff.mg_vcycle(hf2, b, uf)
+            ff.mg_vcycle(hr2, b, ur)
+        torch.cuda.synchronize()
+        assert torch.equal(uf, ur), (nu1, nu2)
+    for tc in (0, 2):   # fused with and without the one-workgroup LDS tail
+        hf3, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, tile_config=tc)
+        hr3, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, tile_config=1)
+        uf, ur = torch.zeros_like(b), torch.zeros_like(b)
+        i1 = ff.mg_solve(hf3, b, uf)
+        i2 = ff.mg_solve(hr3, b, ur)
+        assert i1.cycles == i2.cycles and i1.rel_residual == i2.rel_residual, tc
+        assert torch.equal(uf, ur), tc
+        hf4, _, _, _, _, _ = setup(ff, orc, w, tile_config=tc)
+        uf, ur = torch.zeros_like(b), torch.zeros_like(b)
+        for _ in range(2):
+            ff.mg_vcycle(hf4, b, uf)
+            ff.mg_vcycle(hr, b, ur) if tc == 0 else None
+        if tc == 0:
+            torch.cuda.synchronize()
+            ur2 = torch.zeros_like(b)
+            for _ in range(2):
+                ff.mg_vcycle(hr, b, ur2)
+            torch.cuda.synchronize()
+            assert torch.equal(uf, ur2)
+
+
+def test_repeated_solves_and_batches(ff, orc):
+    """The device-side stopping test with batched enqueueing: repeated solves
+    (whose batch size follows the previous cycle count) and a solve from a
+    converged guess give the oracle's cycle counts."""
+    w = W.small_2d(n=128)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    bd = dev(b)
+    for tol in (1e-6, 1e-10, 1e-8, 1e-12):
+        uo, st, k, _ = mg.solve(b, tol=tol)
+        ud = torch.zeros_like(bd)
+        info = ff.mg_solve(h, bd, ud, tol=tol)
+        assert info.cycles == k, tol
+        assert rel(host(ud), uo) < 1e-12
+    # a converged guess: zero cycles, u unchanged
+    before = ud.clone()
+    info = ff.mg_solve(h, bd, ud, tol=1e-6)
+    torch.cuda.synchronize()
+    assert info.cycles == 0 and torch.equal(ud, before)
