@@ -5,8 +5,9 @@ One step = one far-field map of the 2D bumps workload (2048 intervals per
 axis on [-10,10]^2, 8 seeded Gaussian bumps, k0 = 1, contour angle 30 deg):
 plane-wave right-hand side, multigrid solve to ||r|| <= 1e-10 ||b|| and the
 far field at 360 outgoing angles, with every input already in HBM.  `value`
-is the mixed-precision path (FP32 V(2,2) cycles inside FP64 refinement, FP64
-far field); the plain FP64 multigrid path is timed beside it on the same map.
+is the mixed-precision path (FP32 V(2,2) cycles inside FP64 refinement, far
+field as a split-BF16 MFMA contraction with FP32 accumulation); the plain FP64
+path (FP64 V-cycles, FP64 MFMA far field) is timed beside it on the same map.
 
 Also reported: the roofline of the dominant kernel (the timed kernel with the
 largest total time per map), timed live with HIP events on its stream during
@@ -49,15 +50,21 @@ def measured_traffic(kernel):
     return t.get("bytes_per_launch")
 
 
-KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3))
+KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3), ("ffgemm", 4))
 
 
-def run_path(ff, torch, w, precision, steps, warmup, bytes_per_point):
+def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point):
     """Time `steps` maps.  The warm-up maps record every timed kernel; the one
     with the largest total time is the dominant kernel, and inside the timed
     region HIP events bracket only that kernel's launches."""
-    opts = ff.default_options(precision=precision)
+    opts = ff.default_options(precision=precision, ff_precision=ff_precision)
     h, coef = ff.setup_workload(w, options=opts)
+    tune = None
+    if ff.mg_tune_variants(h, ff.TUNE_FF_GEMM) > 1:   # tile shape of the split GEMM, off the timed path
+        from paper_1211_4461_amd import autotune
+        v = autotune.tune_farfield(h, w.eta, None, w.dirs, ff_precision)
+        tune = {"variant": v, "cache": autotune.load().get(autotune.key(
+            autotune.device_arch(), ff.TUNE_FF_GEMM, w.dim, [w.n - 1] * w.dim, len(w.dirs), ff_precision))}
     b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
     u = torch.empty_like(b)
     F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
@@ -75,7 +82,7 @@ def run_path(ff, torch, w, precision, steps, warmup, bytes_per_point):
 
     step()                       # first map: cold launches, not ranked
     torch.cuda.synchronize()
-    ff.mg_profile_enable(h, 0xF)
+    ff.mg_profile_enable(h, 0x1F)
     read_all()
     for _ in range(max(warmup - 1, 1)):
         step()
@@ -92,9 +99,24 @@ def run_path(ff, torch, w, precision, steps, warmup, bytes_per_point):
     ff.mg_profile_enable(h, 0)
     out = {"ms_per_step": 1e3 * dt / steps, "maps_per_s": steps / dt, "cycles": info.cycles, "vcycles": info.vcycles,
            "rel_residual": info.rel_residual, "conv_factor": info.conv_factor, "F": F.cpu().numpy(),
-           "dominant": dominant, "live": live, "prof": allk}
+           "dominant": dominant, "live": live, "prof": allk, "tune": tune}
     h.destroy()
     return out
+
+
+def gemm_report(prof, w, prec, tune=None):
+    """MFMA rate of the far-field GEMM stage (2D: 8 M N flop per map as a
+    complex GEMM; a split precision issues `products` times as many)."""
+    t_ms, cnt = prof["ffgemm"]
+    if cnt == 0:
+        return None
+    t = t_ms / cnt * 1e-3
+    flop = 8.0 * len(w.dirs) * w.N
+    products, peak = {"bf16x6": (6, 2500.0), "bf16x3": (3, 2500.0), "fp64": (1, 78.6)}[prec]
+    issued = products * flop / t / 1e12
+    return {"us": round(t * 1e6, 1), "flop_per_map": flop, "products": products,
+            "complex_TFLOPs": round(flop / t / 1e12, 2), "mfma_TFLOPs": round(issued, 1),
+            "peak_TFLOPs": peak, "mfma_frac": round(issued / peak, 4), "tuned": tune}
 
 
 def cpu_baseline(w):
@@ -126,6 +148,8 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="intervals per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
+    ap.add_argument("--ff-precision", choices=("bf16x6", "bf16x3", "fp64"), default="bf16x6",
+                    help="far-field contraction of the mixed path")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -164,8 +188,9 @@ def main():
     # and the pair from a nonzero guess, 32 B) and is reported, not ranked.
     bpp_mixed = {"post": 34.0, "refine": 80.0}
     bpp_plain = {"post": 68.0}
-    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, args.steps, args.warmup, bpp_mixed)
-    plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, max(args.steps // 2, 2),
+    ffp = {"bf16x6": ffmg.FF_BF16X6, "bf16x3": ffmg.FF_BF16X3, "fp64": ffmg.FF_FP64}[args.ff_precision]
+    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed)
+    plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2),
                                                  args.warmup, bpp_plain)
     names = {"pre": "finest-level pre-smoothing: 2 fused FP32 Jacobi sweeps from zero (k_smooth2d<float,2,true,false,1>)",
              "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1>)",
@@ -196,10 +221,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"bumps_2d n={args.n} box=[-10,10]^2 k0=1 gamma=30deg 8 bumps seed=1",
                    "unknowns": N, "angles": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
-                   "form": "FP32 V-cycles in FP64 refinement + FP64 MFMA far field"},
+                   "form": "FP32 V-cycles in FP64 refinement + "
+                           + {"bf16x6": "split-BF16 (3 parts, 6 products) MFMA far field, FP32 accumulation",
+                              "bf16x3": "split-BF16 (2 parts, 3 products) MFMA far field, FP32 accumulation",
+                              "fp64": "FP64 MFMA far field"}[args.ff_precision]},
         "mixed": {"refinement_steps": mixed["cycles"], "vcycles": mixed["vcycles"], "rel_residual": mixed["rel_residual"],
                   "conv_factor": round(mixed["conv_factor"], 4),
-                  "ff_ms_per_map": round(pr["ff"][0] / max(pr["ff"][1], 1), 3)},
+                  "ff_ms_per_map": round(pr["ff"][0] / max(pr["ff"][1], 1), 3),
+                  "farfield_gemm": gemm_report(pr, w, args.ff_precision, mixed["tune"])},
         "roofline": roof,
     }
     if plain is not None:
@@ -209,7 +238,9 @@ def main():
                  for k, b_ in bpp_plain.items() if pp[k][1] > 0}
         line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
                               "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
-                              "finest_kernels_GBs": p_gbs}
+                              "finest_kernels_GBs": p_gbs,
+                              "ff_ms_per_map": round(pp["ff"][0] / max(pp["ff"][1], 1), 3),
+                              "farfield_gemm": gemm_report(pp, w, "fp64")}
         line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
         line["mixed_vs_plain_farfield_rel_err"] = ef
     if not args.no_cpu_baseline:

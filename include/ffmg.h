@@ -162,12 +162,32 @@ ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, doubl
 /* Kernel timing (instrumentation for benchmarks).  Bit k of mask enables a
  * pair of HIP events on the handle's stream around every launch of kernel k:
  * 0 finest-level pre-smoothing (the fused two-sweep kernel, or each sweep),
- * 1 far-field contraction, 2 finest-level interpolation + post-smoothing,
- * 3 FP64 update + residual of the mixed-precision refinement.  mask = 0
+ * 1 far-field map (integrand, contraction, final sum), 2 finest-level
+ * interpolation + post-smoothing, 3 FP64 update + residual of the
+ * mixed-precision refinement, 4 the far-field GEMM stages alone.  mask = 0
  * disables.  mg_profile_read synchronises, returns the summed duration (ms)
  * and launch count of one kernel, and clears its record. */
 ffmg_status mg_profile_enable(ffmg_handle *h, int mask);
 ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_t *count);
+
+/* Autotuning of kernel tile shapes.  A tunable is a family of kernel
+ * variants that compute the same result (bit for bit) with different tile
+ * shapes; the best one depends on the device, the grid and the number of
+ * directions.  FFMG_TUNE_FF_GEMM: the split-BF16 far-field GEMM (row tiles x
+ * column tiles per wave); with ff_precision FP64 it has one variant.
+ * mg_tune_variants returns the number of variants (0 for an unknown
+ * tunable); mg_tune_get / mg_tune_set read and select one (a cached choice).
+ * mg_tune_farfield builds the integrand of (eta, u) for the n_dirs
+ * directions, times every variant of the contraction `reps` times with HIP
+ * events on the handle's stream, selects the fastest and returns its index in
+ * *best and the mean time of variant v in times_ms[v] (v < n_times; times_ms
+ * may be NULL).  Synchronises. */
+typedef enum { FFMG_TUNE_FF_GEMM = 0 } ffmg_tunable;
+int mg_tune_variants(const ffmg_handle *h, int tunable);
+ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant);
+ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant);
+ffmg_status mg_tune_farfield(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
+                             int reps, double *times_ms, int n_times, int *best);
 
 /* Number of levels and the interior sizes of level l (n[k] - 1 per axis). */
 int mg_num_levels(const ffmg_handle *h);

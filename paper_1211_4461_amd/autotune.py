@@ -1,0 +1,74 @@
+"""Autotuning of kernel tile shapes, with a JSON cache.
+
+The library exposes tunable kernel families (``mg_tune_variants``); every
+variant of a family computes the same bits with a different tile shape, and
+which one is fastest depends on the device and on the problem's shapes.  This
+module keys a choice by (device architecture, tunable, dimension, interior
+extents, number of directions, precision), runs the library's own timing
+sweep (``mg_tune_farfield``) on a cache miss, and stores the winner.
+
+The cache is a flat JSON object ``{key: {"variant": v, "ms": [...]}}``; a
+missing or unreadable file is an empty cache.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Optional
+
+from . import ffmg
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ffmg", "autotune.json")
+
+
+def cache_path() -> str:
+    return os.environ.get("FFMG_TUNE_CACHE", DEFAULT_CACHE)
+
+
+def load(path: Optional[str] = None) -> dict:
+    try:
+        with open(path or cache_path()) as f:
+            c = json.load(f)
+        return c if isinstance(c, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def save(cache: dict, path: Optional[str] = None) -> None:
+    p = path or cache_path()
+    os.makedirs(os.path.dirname(p) or ".", exist_ok=True)
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def key(arch: str, tunable: int, dim: int, shape, n_dirs: int, precision: int) -> str:
+    ext = "x".join(str(int(m)) for m in shape)
+    return f"{arch}|tunable={int(tunable)}|d={int(dim)}|m={ext}|M={int(n_dirs)}|prec={int(precision)}"
+
+
+def device_arch() -> str:
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return getattr(p, "gcnArchName", p.name).split(":")[0]
+
+
+def tune_farfield(h: "ffmg.Handle", eta, u, dirs, ff_precision: int, path: Optional[str] = None,
+                  reps: int = 5, force: bool = False) -> int:
+    """Select the far-field GEMM variant for this handle: from the cache, or
+    by timing every variant (then cached).  Returns the variant."""
+    nv = ffmg.mg_tune_variants(h, ffmg.TUNE_FF_GEMM)
+    if nv <= 1:
+        return 0
+    shape = [m for m in h.level_shape(0) if m > 1]
+    k = key(device_arch(), ffmg.TUNE_FF_GEMM, len(shape), shape, len(dirs), ff_precision)
+    cache = load(path)
+    hit = cache.get(k)
+    if not force and isinstance(hit, dict) and isinstance(hit.get("variant"), int) and 0 <= hit["variant"] < nv:
+        ffmg.mg_tune_set(h, hit["variant"], ffmg.TUNE_FF_GEMM)
+        return hit["variant"]
+    best, times = ffmg.mg_tune_farfield(h, eta, u, dirs, reps=reps)
+    cache[k] = {"variant": best, "ms": [round(t, 5) for t in times]}
+    save(cache, path)
+    return best

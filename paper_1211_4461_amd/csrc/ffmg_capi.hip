@@ -235,8 +235,8 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
     if (o->precision != FFMG_FP64 && o->precision != FFMG_FP32_IR)
         return fail(tmp, FFMG_EINVAL, "unknown precision %d", o->precision);
     if (o->smoother != FFMG_SMOOTH_JACOBI) return fail(tmp, FFMG_EINVAL, "unsupported smoother %d", o->smoother);
-    if (o->ff_precision != FFMG_FF_FP64)
-        return fail(tmp, FFMG_EINVAL, "unsupported far-field precision %d", o->ff_precision);
+    if (o->ff_precision != FFMG_FF_FP64 && o->ff_precision != FFMG_FF_BF16X3 && o->ff_precision != FFMG_FF_BF16X6)
+        return fail(tmp, FFMG_EINVAL, "unknown far-field precision %d", o->ff_precision);
     if (o->tile_config < 0 || o->tile_config > 2) return fail(tmp, FFMG_EINVAL, "unknown tile_config");
     if (o->inner_cycles < 0 || o->inner_cycles > 16) return fail(tmp, FFMG_EINVAL, "inner_cycles must be in [0, 16]");
     return FFMG_OK;
@@ -674,10 +674,12 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
     }
 }
 
-ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
-                         void *F)
+// Validation, the plane-wave factors and the far-field plan for n_dirs
+// directions; then the integrand (inside the PROF_FF bracket started here).
+static ffmg_status ff_begin(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
+                            int *prof_idx)
 {
-    if (!h || !eta || !dirs || !F || n_dirs < 1) return fail(h, FFMG_EINVAL, "null argument or n_dirs < 1");
+    if (!h || !eta || !dirs || n_dirs < 1) return fail(h, FFMG_EINVAL, "null argument or n_dirs < 1");
     const int d = h->prob.dim;
     for (int i = 0; i < n_dirs; ++i) {
         double s = 0.0;
@@ -688,15 +690,19 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
         }
         if (fabs(s - 1.0) > 1e-6) return fail(h, FFMG_EINVAL, "direction %d is not a unit vector", i);
     }
-    // the integrand multiplies exp(+k0 sin g alpha.x) by exp(-k0 sin g eta.x)
+    // the integrand multiplies exp(+k0 sin g alpha.x) by exp(-k0 sin g eta.x);
+    // the split BF16 contraction forms that product in FP32
     if (2.0 * exponent_budget(h) > 700.0)
         return fail(h, FFMG_ERANGE, "contour exponentials exceed the FP64 range on this box");
+    if (h->opt.ff_precision != FFMG_FF_FP64 && 2.0 * exponent_budget(h) > 60.0)
+        return fail(h, FFMG_ERANGE, "contour exponentials exceed the FP32 range of the split BF16 contraction");
     Level &l0 = h->L[0];
     const LevelGeom &g = l0.g;
-    const size_t N = g.N();
-    if (!h->d_s) TRY(dalloc(h, &h->d_s, N * sizeof(cd)));
     if (!h->d_E) TRY(dalloc(h, &h->d_E, (size_t)(g.m[0] + g.m[1] + g.m[2]) * sizeof(cd)));
-    if (!h->ff) h->ff = ff_plan_create();
+    if (!h->ff) {
+        h->ff = ff_plan_create();
+        ff_plan_set_variant(h->ff, h->ff_variant);
+    }
     // plane-wave axis factors exp(i k0 e^{ig} eta_k x): c = -k0 sin g eta_k + i k0 cos g eta_k
     int off = 0;
     for (int k = 0; k < 3; ++k) {
@@ -705,9 +711,17 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
                         (h->k0 * cos(h->prob.gamma)) * ek, h->stream);
         off += g.m[k];
     }
-    launch_ff_integrand(g, l0.q, (const cd *)u, h->d_E, h->d_s, h->stream);
     HIPCHK(h, hipGetLastError());
-    HIPCHK(h, ff_plan_prepare(h->ff, g, h->k0, h->prob.gamma, n_dirs, dirs, h->d_s, h->stream));
+    HIPCHK(h, ff_plan_prepare(h->ff, g, h->k0, h->prob.gamma, n_dirs, dirs, h->opt.ff_precision, h->stream));
+    *prof_idx = prof_begin(h, PROF_FF);
+    HIPCHK(h, ff_plan_integrand(h->ff, g, l0.q, (const cd *)u, h->d_E, h->stream));
+    return FFMG_OK;
+}
+
+ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
+                         void *F)
+{
+    if (!F) return fail(h, FFMG_EINVAL, "F is null");
     // output: device pointer directly, host pointer through a staging buffer
     hipPointerAttribute_t attr;
     bool on_device = false;
@@ -716,19 +730,110 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
     else
         (void)hipGetLastError();
     cd *Fd = (cd *)F;
-    if (!on_device) {
+    if (!on_device && h && n_dirs > 0) {
         if (h->d_F_cap < n_dirs) {
             TRY(dalloc(h, &h->d_F, (size_t)n_dirs * sizeof(cd)));
             h->d_F_cap = n_dirs;
         }
         Fd = h->d_F;
     }
-    int pi = prof_begin(h, PROF_FF);
-    HIPCHK(h, ff_plan_execute(h->ff, g, h->prob.gamma, Fd, h->stream));
+    int pi = -1;
+    TRY(ff_begin(h, eta, u, n_dirs, dirs, &pi));
+    const LevelGeom &g = h->L[0].g;
+    int pg = prof_begin(h, PROF_FFGEMM);
+    HIPCHK(h, ff_plan_contract(h->ff, g, h->stream));
+    prof_end(h, PROF_FFGEMM, pg);
+    HIPCHK(h, ff_plan_finish(h->ff, g, h->prob.gamma, Fd, h->stream));
     prof_end(h, PROF_FF, pi);
     if (!on_device)
         HIPCHK(h, hipMemcpyAsync(F, Fd, (size_t)n_dirs * sizeof(cd), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
+    return FFMG_OK;
+}
+
+int mg_tune_variants(const ffmg_handle *h, int tunable)
+{
+    if (!h) return 0;
+    switch (tunable) {
+    case FFMG_TUNE_FF_GEMM: return (h->opt.ff_precision == FFMG_FF_FP64) ? 1 : ff_plan_variants();
+    default: return 0;
+    }
+}
+
+ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant)
+{
+    if (!h || !variant) return FFMG_EINVAL;
+    switch (tunable) {
+    case FFMG_TUNE_FF_GEMM:
+        *variant = (h->opt.ff_precision == FFMG_FF_FP64) ? 0
+                   : (h->ff_variant < 0)                 ? ff_plan_default_variant()
+                                                         : h->ff_variant;
+        return FFMG_OK;
+    default: return FFMG_EINVAL;
+    }
+}
+
+ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant)
+{
+    if (!h) return FFMG_EINVAL;
+    if (variant < 0 || variant >= mg_tune_variants(h, tunable))
+        return fail(h, FFMG_EINVAL, "variant %d out of range for tunable %d", variant, tunable);
+    switch (tunable) {
+    case FFMG_TUNE_FF_GEMM:
+        if (h->opt.ff_precision == FFMG_FF_FP64) return FFMG_OK;
+        h->ff_variant = variant;
+        if (h->ff) ff_plan_set_variant(h->ff, variant);
+        return FFMG_OK;
+    default: return fail(h, FFMG_EINVAL, "unknown tunable %d", tunable);
+    }
+}
+
+ffmg_status mg_tune_farfield(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
+                             int reps, double *times_ms, int n_times, int *best)
+{
+    if (!h || reps < 1) return fail(h, FFMG_EINVAL, "null handle or reps < 1");
+    int pi = -1;
+    TRY(ff_begin(h, eta, u, n_dirs, dirs, &pi));
+    prof_end(h, PROF_FF, pi);
+    const LevelGeom &g = h->L[0].g;
+    const int nv = mg_tune_variants(h, FFMG_TUNE_FF_GEMM);
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(h, FFMG_EDEVICE, "hipEventCreate failed");
+    }
+    int arg = 0;
+    double tbest = 0.0;
+    ffmg_status st = FFMG_OK;
+    for (int v = 0; v < nv && st == FFMG_OK; ++v) {
+        ff_plan_set_variant(h->ff, v);
+        hipError_t e = ff_plan_contract(h->ff, g, h->stream);   // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = ff_plan_contract(h->ff, g, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            st = fail(h, FFMG_EDEVICE, "variant %d: %s", v, hipGetErrorString(e));
+            break;
+        }
+        double t = ms / reps;
+        if (times_ms && v < n_times) times_ms[v] = t;
+        if (v == 0 || t < tbest) {
+            tbest = t;
+            arg = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FFMG_OK) return st;
+    if (nv > 1) {
+        h->ff_variant = arg;
+        ff_plan_set_variant(h->ff, arg);
+    }
+    if (best) *best = arg;
     return FFMG_OK;
 }
 

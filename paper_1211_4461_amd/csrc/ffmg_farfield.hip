@@ -16,6 +16,16 @@
 // A complex GEMM is run as one real GEMM: A' has rows (Re A[m], Im A[m]),
 // S' is S viewed as reals (re/im interleaved along n), and the epilogue
 // combines neighbouring rows/columns of C' = A' S' into Re/Im of C.
+//
+// Two number formats run the GEMMs:
+//  * FP64 MFMA (v_mfma_f64_16x16x4f64), the plain method;
+//  * split BF16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32 accumulation: every
+//    FP64 operand x is written as x0 + x1 (+ x2), each part a BF16 that holds
+//    the next 8 significant bits, and a product is the sum of the part
+//    products of order <= 1 (two parts, 3 products, about 16 bits) or <= 2
+//    (three parts, 6 products, about 24 bits).  The FP32 accumulator of one
+//    32-deep k-step is added into FP64 after every step, so the accumulation
+//    error does not grow with the contraction length.
 #include <math.h>
 
 #include <algorithm>
@@ -26,6 +36,58 @@
 namespace ffmg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned short us8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// BF16 splitting.  bf16_rne: round-to-nearest-even of a finite FP32 to the
+// upper 16 bits.  split_bf16: NS parts whose sum approximates x; each
+// residual r - part is exact in FP64.
+__device__ __forceinline__ unsigned short bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+template <int NS>
+__device__ __forceinline__ void split_bf16(double x, unsigned short (&o)[NS])
+{
+    double r = x;
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        unsigned short b = bf16_rne((float)r);
+        o[t] = b;
+        r -= (double)__uint_as_float((unsigned)b << 16);
+    }
+}
+
+// Split 8 consecutive-k complex values of one column n and store them in the
+// B-operand layout of v_mfma_f32_16x16x32_bf16: plane t holds, for k-block kb
+// (k = 8 kb + e) and real column c (2n: Re, 2n + 1: Im), the 8 values of e
+// contiguously (16 bytes), rows of ldP columns.
+template <int NS>
+__device__ __forceinline__ void store_split8(const cd (&v)[8], us8 *__restrict__ planes, long pstride, long row_off)
+{
+    us8 re[NS], im[NS];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        unsigned short a[NS], b[NS];
+        split_bf16<NS>(v[e].re, a);
+        split_bf16<NS>(v[e].im, b);
+#pragma unroll
+        for (int t = 0; t < NS; ++t) {
+            re[t][e] = a[t];
+            im[t][e] = b[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t) {
+        planes[t * pstride + row_off] = re[t];
+        planes[t * pstride + row_off + 1] = im[t];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Integrand: s_j = q_j (Ex[ix] Ey[iy] Ez[iz] + u_j), with the per-axis factors
@@ -44,6 +106,70 @@ __global__ __launch_bounds__(256) void k_ff_integrand(const cd *__restrict__ q, 
         if (mz > 1) uin = uin * Ez[iz];
         cd t = u ? uin + u[j] : uin;
         s[j] = q[j] * t;
+    }
+}
+
+// The same integrand written as NS BF16 planes for the split GEMM: the
+// slowest axis (y in 2D, z in 3D) is the contraction index k, the other axes
+// form the column n.  One thread produces the 8 values k = 8 kb .. 8 kb + 7 of
+// one column; rows k >= K and columns n >= Nc (padding) are zero.
+template <int NS>
+__global__ __launch_bounds__(256) void k_ff_integrand_split(const cd *__restrict__ q, const cd *__restrict__ u,
+                                                            const cd *__restrict__ E, us8 *__restrict__ planes,
+                                                            int mx, int my, int mz, int dim, int kb_tot,
+                                                            long ldP, long pstride)
+{
+    const cd *Ex = E, *Ey = E + mx, *Ez = E + mx + my;
+    const int K = (dim == 3) ? mz : my;
+    const long Nc = (dim == 3) ? (long)mx * my : mx;
+    const long ncols = ldP / 2;
+    const long tot = (long)kb_tot * ncols;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+        const long n = e % ncols;
+        const int kb = (int)(e / ncols);
+        const bool colin = n < Nc;
+        const int ix = (int)(colin ? n % mx : 0);
+        const int iy0 = (int)(colin ? n / mx : 0);   // 3D: y index of the column
+        cd v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 8 * kb + i;
+            const bool in = colin && k < K;
+            const size_t j = in ? (size_t)k * Nc + n : 0;
+            cd uin;
+            if (dim == 3) uin = (Ex[ix] * Ey[iy0]) * Ez[in ? k : 0];
+            else uin = Ex[ix] * Ey[in ? k : 0];
+            cd t = u ? uin + u[j] : uin;
+            cd sv = q[j] * t;
+            v[i] = in ? sv : cd{0.0, 0.0};
+        }
+        store_split8<NS>(v, planes, pstride, (long)kb * ldP + 2 * n);
+    }
+}
+
+// Split an FP64 complex field src[g][k][n] (K rows of Nc, group stride
+// gstride) into BF16 planes (group stride plane_gstride), as above.
+template <int NS>
+__global__ __launch_bounds__(256) void k_split_field(const cd *__restrict__ src, long gstride, int K, long Nc,
+                                                     us8 *__restrict__ planes, long plane_gstride, int kb_tot,
+                                                     long ldP, long pstride)
+{
+    const cd *S = src + (size_t)blockIdx.y * gstride;
+    us8 *P = planes + (size_t)blockIdx.y * plane_gstride;
+    const long ncols = ldP / 2;
+    const long tot = (long)kb_tot * ncols;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+        const long n = e % ncols;
+        const int kb = (int)(e / ncols);
+        cd v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 8 * kb + i;
+            const bool in = n < Nc && k < K;
+            cd x = S[in ? (size_t)k * Nc + n : 0];
+            v[i] = in ? x : cd{0.0, 0.0};
+        }
+        store_split8<NS>(v, P, pstride, (long)kb * ldP + 2 * n);
     }
 }
 
@@ -95,6 +221,55 @@ __global__ __launch_bounds__(256) void k_pack_factor(double *__restrict__ out, c
             v = c ? mag * sin(ph) : mag * cos(ph);
         }
         out[e] = v;
+    }
+}
+
+// Packed factor matrix for the A operand of v_mfma_f32_16x16x32_bf16, split
+// into NS BF16 planes.  That instruction reads A[i][k] from lane i + 16 (k / 8),
+// element k % 8, and returns D[i][j] in lane j + 16 (i / 4), register i % 4.
+// Tile row i holds direction m = 8 rt + 2 (i / 4) + (i / 2) % 2, part i % 2
+// (0: Re, 1: Im), so that registers (0, 1) and (2, 3) of a lane are the Re/Im
+// rows of two consecutive directions.  Layout per plane:
+// [row tile rt][k step ks (32)][lane (64)] of 8 BF16; zero outside M x K.
+__device__ __forceinline__ void tile_row_map_bf16(int i, int &mloc, int &c)
+{
+    mloc = 2 * (i >> 2) + ((i >> 1) & 1);
+    c = i & 1;
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_pack_factor_bf16(us8 *__restrict__ out, long sstride,
+                                                          const double *__restrict__ alpha, int M, int K,
+                                                          int rtiles, int ksteps, double lo, double h, double k0,
+                                                          double gamma)
+{
+    const long tot = (long)rtiles * ksteps * 64;
+    const double sg = k0 * sin(gamma), cg = k0 * cos(gamma);
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+        const int l = (int)(e % 64);
+        const long t = e / 64;
+        const int ks = (int)(t % ksteps), rt = (int)(t / ksteps);
+        int mloc, c;
+        tile_row_map_bf16(l % 16, mloc, c);
+        const int m = 8 * rt + mloc;
+        us8 v[NS];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 32 * ks + 8 * (l / 16) + i;
+            double val = 0.0;
+            if (m < M && k < K) {
+                double x = lo + (double)(k + 1) * h;
+                double a = alpha[m];
+                double mag = exp(sg * a * x), ph = -cg * a * x;
+                val = c ? mag * sin(ph) : mag * cos(ph);
+            }
+            unsigned short p[NS];
+            split_bf16<NS>(val, p);
+#pragma unroll
+            for (int s = 0; s < NS; ++s) v[s][i] = p[s];
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) out[s * sstride + e] = v[s];
     }
 }
 
@@ -186,6 +361,109 @@ __global__ __launch_bounds__(256) void k_ff_gemm_f64(const GemmGroup *__restrict
         }
 }
 
+// Split-BF16 MFMA contraction.  Group g: C_g = A_g S_g as above, with A_g
+// and S_g given as NS BF16 planes (padded: rtiles rows of tiles, K to a
+// multiple of 32, ldP real columns, all zero-filled, so the inner loop has no
+// bounds checks).  Each wave owns RT x CT tiles of 16 x 16 of C' (8 RT
+// directions x 8 CT complex columns); the block has 4 waves side by side in n.
+// The flat block index is mapped XCD-contiguously onto (column slab, row
+// block) with row blocks fastest, so the blocks that share one slab of the
+// integrand planes run on one XCD and share its L2.
+struct GemmGroupB {
+    const bf8 *A;     // factor planes [NS][rtiles][ksteps][64]
+    long a_split;     // plane stride of A (bf8 units)
+    const bf8 *S;     // integrand planes [NS][4 ksteps][ldP]
+    long s_split;     // plane stride of S (bf8 units)
+    cd *C;            // C : M rows of Nc complex (row stride ldC)
+    long ldC;
+    int M, Nc, rtiles;
+};
+
+template <int NS, int RT, int CT>
+__global__ __launch_bounds__(256) void k_ff_gemm_bf16(const GemmGroupB *__restrict__ groups, int ksteps, long ldP,
+                                                      int gx, int gy)
+{
+    const GemmGroupB G = groups[blockIdx.y];
+    const int t = xcd_tile(blockIdx.x, gx * gy);
+    const int bx = t / gy, by = t % gy;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rt0 = by * RT;
+    if (rt0 >= G.rtiles) return;
+    const long col0 = ((long)bx * 4 + wave) * (CT * 16);
+    const int lr = lane & 15, g = lane >> 4;
+
+    double acc[RT][CT][4];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.0;
+
+    const bf8 *Ab = G.A + (long)rt0 * ksteps * 64 + lane;
+    const bf8 *Sb = G.S + (long)g * ldP + col0 + lr;
+    for (int ks = 0; ks < ksteps; ++ks) {
+        bf8 a[RT][NS], b[CT][NS];
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) a[i][s] = Ab[s * G.a_split + ((long)i * ksteps + ks) * 64];
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+#pragma unroll
+            for (int s = 0; s < NS; ++s) b[j][s] = Sb[s * G.s_split + (long)ks * 4 * ldP + j * 16];
+        f4 c[RT][CT];
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int j = 0; j < CT; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        // part products, smallest first: orders 2 (NS = 3), 1, then 0
+        if constexpr (NS == 3) {
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int j = 0; j < CT; ++j) {
+                    c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][0], c[i][j], 0, 0, 0);
+                    c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][1], c[i][j], 0, 0, 0);
+                    c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][2], c[i][j], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int j = 0; j < CT; ++j) {
+                c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], c[i][j], 0, 0, 0);
+                c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], c[i][j], 0, 0, 0);
+                c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], c[i][j], 0, 0, 0);
+            }
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+            for (int j = 0; j < CT; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)c[i][j][v];
+    }
+    // Epilogue: lane (j, g) holds, for tile rt, C'[(m, Re)][c0 + j] and
+    // C'[(m, Im)][..] in registers 0, 1 and the same for m + 1 in 2, 3, with
+    // m = 8 rt + 2 g (see tile_row_map_bf16).  Columns 2n / 2n+1 are Re / Im
+    // of S[k][n]: the even lane writes C[m][n], the odd lane C[m + 1][n].
+    const bool odd = (lane & 1) != 0;
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < CT; ++j) {
+            const double m0 = acc[i][j][0], m1 = acc[i][j][1], m2 = acc[i][j][2], m3 = acc[i][j][3];
+            double p0 = __shfl_xor(m0, 1, 64), p1 = __shfl_xor(m1, 1, 64);
+            double p2 = __shfl_xor(m2, 1, 64), p3 = __shfl_xor(m3, 1, 64);
+            int m = 8 * (rt0 + i) + 2 * g + (odd ? 1 : 0);
+            long n = (col0 + j * 16 + lr) >> 1;
+            cd v;
+            if (!odd) v = cd{m0 - p1, p0 + m1};
+            else v = cd{p2 - m3, m2 + p3};
+            if (m < G.M && n < G.Nc) G.C[(size_t)m * G.ldC + n] = v;
+        }
+}
+
 // F_m = pre * sum_x P[m][x] T[m][x]; one wave per direction.
 __global__ __launch_bounds__(256) void k_ff_final(const cd *__restrict__ P, const cd *__restrict__ T, int M, int K,
                                                   cd pre, cd *__restrict__ F)
@@ -218,6 +496,7 @@ __global__ __launch_bounds__(256) void k_unpermute(const cd *__restrict__ Fs, co
 // ---------------------------------------------------------------------------
 // Host-side plan.
 static int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+static long round_up(long a, long b) { return (a + b - 1) / b * b; }
 
 constexpr int GEMM_RT = 2, GEMM_CT = 2;
 
@@ -235,38 +514,97 @@ static void launch_gemm(const GemmLaunch &L, hipStream_t s)
                        L.ldS, L.ldC);
 }
 
+// Split-GEMM tile variants (RT row tiles x CT column tiles per wave).  Row
+// tiles are padded to a multiple of BF_RT_PAD and columns to a multiple of
+// BF_COL_PAD, which every variant divides.
+struct BfVariant {
+    int rt, ct;
+};
+static const BfVariant BF_VARIANTS[] = {{2, 1}, {2, 2}, {4, 1}, {4, 2}, {2, 4}, {4, 4}};
+constexpr int BF_NVARIANTS = (int)(sizeof(BF_VARIANTS) / sizeof(BF_VARIANTS[0]));
+constexpr int BF_DEFAULT_VARIANT = 3;
+constexpr int BF_RT_PAD = 4;
+constexpr long BF_COL_PAD = 4 * 4 * 16;   // 4 waves x CT <= 4 tiles x 16 columns
+
+struct GemmLaunchB {
+    GemmGroupB *d_groups = nullptr;
+    int ngroups = 0, ksteps = 0, rtiles = 0;   // rtiles: the largest group's (padded)
+    long ldP = 0;
+};
+
+template <int NS>
+static void launch_gemm_bf16_ns(const GemmLaunchB &L, int variant, hipStream_t s)
+{
+    const BfVariant V = BF_VARIANTS[variant];
+    const int gx = (int)(L.ldP / (4L * V.ct * 16)), gy = ceil_div(L.rtiles, V.rt);
+    dim3 grid((unsigned)(gx * gy), (unsigned)L.ngroups);
+#define FF_BF_CASE(R, C)                                                                                             \
+    if (V.rt == R && V.ct == C) {                                                                                    \
+        hipLaunchKernelGGL((k_ff_gemm_bf16<NS, R, C>), grid, dim3(256), 0, s, L.d_groups, L.ksteps, L.ldP, gx, gy); \
+        return;                                                                                                      \
+    }
+    FF_BF_CASE(2, 1)
+    FF_BF_CASE(2, 2)
+    FF_BF_CASE(4, 1)
+    FF_BF_CASE(4, 2)
+    FF_BF_CASE(2, 4)
+    FF_BF_CASE(4, 4)
+#undef FF_BF_CASE
+}
+
+static void launch_gemm_bf16(const GemmLaunchB &L, int ns, int variant, hipStream_t s)
+{
+    if (ns == 3) launch_gemm_bf16_ns<3>(L, variant, s);
+    else launch_gemm_bf16_ns<2>(L, variant, s);
+}
+
+static unsigned grid_for(long work) { return (unsigned)std::max<long>(1, std::min<long>(65536, (work + 255) / 256)); }
+
 struct FarFieldPlan {
     int dim = 0;
     int M = 0;
-    const cd *s_field = nullptr;   // integrand buffer the groups point at
+    int prec = -1;                 // ffmg_ff_precision of the built factors
+    int ns = 0;                    // BF16 parts (split precisions)
+    int variant = BF_DEFAULT_VARIANT;
     std::vector<double> dirs;      // cache key
     std::vector<int> perm;         // sorted position -> direction index
     std::vector<int> gstart;       // group start in sorted order
     std::vector<double> gval;      // alpha_z per group
+    std::vector<void *> bufs;      // everything allocated for this plan
     double *d_alpha = nullptr;     // sorted alphas per axis [3][M], then group alphas
-    double *d_A1 = nullptr;        // packed Pz (3D): rows = groups
-    double *d_A2 = nullptr;        // packed Py, one block per group
+    cd *d_s = nullptr;             // FP64 integrand
     cd *d_Plast = nullptr;         // plain Px [M][mx], sorted order
     cd *d_T1 = nullptr, *d_T2 = nullptr, *d_F = nullptr;
     int *d_perm = nullptr;
-    GemmGroup *d_groups = nullptr; // [0]: stage 1 (3D), [1..]: last GEMM stage
-    GemmLaunch L1, L2;
+    GemmLaunch L1, L2;             // FP64 GEMM stages
+    // split BF16
+    us8 *d_S1b = nullptr;          // integrand planes
+    us8 *d_S2b = nullptr;          // 3D: stage-1 result planes, per group
+    int kb1 = 0, kb2 = 0;
+    long ldP1 = 0, ldP2 = 0, ps1 = 0, ps2 = 0, gs2 = 0;
+    GemmLaunchB B1, B2;
+    template <typename P>
+    hipError_t alloc(P **p, size_t bytes)
+    {
+        void *v = nullptr;
+        hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+        if (e != hipSuccess) return e;
+        bufs.push_back(v);
+        *p = (P *)v;
+        return hipSuccess;
+    }
     void release()
     {
-        (void)hipFree(d_alpha);
-        (void)hipFree(d_A1);
-        (void)hipFree(d_A2);
-        (void)hipFree(d_Plast);
-        (void)hipFree(d_T1);
-        (void)hipFree(d_T2);
-        (void)hipFree(d_F);
-        (void)hipFree(d_perm);
-        (void)hipFree(d_groups);
-        d_alpha = d_A1 = d_A2 = nullptr;
-        d_Plast = d_T1 = d_T2 = d_F = nullptr;
+        for (void *b : bufs) (void)hipFree(b);
+        bufs.clear();
+        d_alpha = nullptr;
+        d_s = d_Plast = d_T1 = d_T2 = d_F = nullptr;
         d_perm = nullptr;
-        d_groups = nullptr;
+        d_S1b = d_S2b = nullptr;
+        L1 = L2 = GemmLaunch{};
+        B1 = B2 = GemmLaunchB{};
         M = dim = 0;
+        prec = -1;
         dirs.clear();
     }
     ~FarFieldPlan() { release(); }
@@ -274,6 +612,10 @@ struct FarFieldPlan {
 
 FarFieldPlan *ff_plan_create() { return new FarFieldPlan(); }
 void ff_plan_destroy(FarFieldPlan *p) { delete p; }
+int ff_plan_variants() { return BF_NVARIANTS; }
+int ff_plan_default_variant() { return BF_DEFAULT_VARIANT; }
+void ff_plan_set_variant(FarFieldPlan *p, int v) { p->variant = (v >= 0 && v < BF_NVARIANTS) ? v : BF_DEFAULT_VARIANT; }
+int ff_plan_variant(const FarFieldPlan *p) { return p->variant; }
 
 #define FF_CHECK(x)                                                                                                  \
     do {                                                                                                             \
@@ -281,20 +623,28 @@ void ff_plan_destroy(FarFieldPlan *p) { delete p; }
         if (e_ != hipSuccess) return e_;                                                                             \
     } while (0)
 
-// (Re)build the direction-dependent factors and the GEMM descriptors when the
-// directions (or the integrand buffer) change.  Synchronises the stream.
+template <typename T>
+static hipError_t upload(FarFieldPlan *p, T **d, const std::vector<T> &h)
+{
+    FF_CHECK(p->alloc(d, h.size() * sizeof(T)));
+    return hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// (Re)build the direction-dependent factors, the work buffers and the GEMM
+// descriptors when the directions or the precision change.  Synchronises.
 hipError_t ff_plan_prepare(FarFieldPlan *p, const LevelGeom &g, double k0, double gamma, int M, const double *dirs,
-                           const cd *s_field, hipStream_t s)
+                           int prec, hipStream_t s)
 {
     const int d = g.dim;
     std::vector<double> key(dirs, dirs + (size_t)M * d);
-    if (p->M == M && p->dim == d && p->dirs == key && p->s_field == s_field) return hipSuccess;
+    if (p->M == M && p->dim == d && p->dirs == key && p->prec == prec) return hipSuccess;
     FF_CHECK(hipStreamSynchronize(s));
     p->release();
     p->dim = d;
     p->M = M;
     p->dirs = key;
-    p->s_field = s_field;
+    p->prec = prec;
+    p->ns = (prec == 2) ? 3 : (prec == 1) ? 2 : 0;
     // group directions by their last component (exact equality) in 3D
     p->perm.resize(M);
     for (int i = 0; i < M; ++i) p->perm[i] = i;
@@ -316,88 +666,199 @@ hipError_t ff_plan_prepare(FarFieldPlan *p, const LevelGeom &g, double k0, doubl
     for (int i = 0; i < M; ++i)
         for (int k = 0; k < d; ++k) al[(size_t)k * M + i] = dirs[(size_t)p->perm[i] * d + k];
     for (int gi = 0; gi < NG; ++gi) al[(size_t)3 * M + gi] = p->gval[gi];
-    FF_CHECK(hipMalloc(&p->d_alpha, al.size() * sizeof(double)));
-    FF_CHECK(hipMemcpy(p->d_alpha, al.data(), al.size() * sizeof(double), hipMemcpyHostToDevice));
-    FF_CHECK(hipMalloc(&p->d_perm, (size_t)M * sizeof(int)));
-    FF_CHECK(hipMemcpy(p->d_perm, p->perm.data(), (size_t)M * sizeof(int), hipMemcpyHostToDevice));
+    FF_CHECK(upload(p, &p->d_alpha, al));
+    FF_CHECK(upload(p, &p->d_perm, p->perm));
 
     const int mx = g.m[0], my = g.m[1], mz = g.m[2];
-    FF_CHECK(hipMalloc(&p->d_Plast, (size_t)M * mx * sizeof(cd)));
-    hipLaunchKernelGGL(k_plain_factor, dim3(std::min(65536, ceil_div((long)M * mx, 256))), dim3(256), 0, s,
-                       p->d_Plast, p->d_alpha, M, mx, g.lo[0], g.h[0], k0, gamma);
-    // packed Py per group (rows = the directions of the group)
-    const int ks_y = ceil_div(my, 4);
-    std::vector<size_t> off(NG);
-    size_t tot = 0;
-    for (int gi = 0; gi < NG; ++gi) {
-        int Mg = p->gstart[gi + 1] - p->gstart[gi];
-        off[gi] = tot;
-        tot += (size_t)ceil_div(2L * Mg, 16) * ks_y * 64;
-    }
-    FF_CHECK(hipMalloc(&p->d_A2, tot * sizeof(double)));
-    for (int gi = 0; gi < NG; ++gi) {
-        int Mg = p->gstart[gi + 1] - p->gstart[gi];
-        int rt = ceil_div(2L * Mg, 16);
-        size_t n = (size_t)rt * ks_y * 64;
-        hipLaunchKernelGGL(k_pack_factor, dim3((unsigned)std::min<size_t>(65536, (n + 255) / 256)), dim3(256), 0,
-                           s, p->d_A2 + off[gi], p->d_alpha + (size_t)1 * M + p->gstart[gi], Mg, my, rt, ks_y,
-                           g.lo[1], g.h[1], k0, gamma);
-    }
-    std::vector<GemmGroup> gr;
-    if (d == 3) {
-        const int ks_z = ceil_div(mz, 4);
-        int rt = ceil_div(2L * NG, 16);
-        size_t n = (size_t)rt * ks_z * 64;
-        FF_CHECK(hipMalloc(&p->d_A1, n * sizeof(double)));
-        hipLaunchKernelGGL(k_pack_factor, dim3((unsigned)std::min<size_t>(65536, (n + 255) / 256)), dim3(256), 0,
-                           s, p->d_A1, p->d_alpha + (size_t)3 * M, NG, mz, rt, ks_z, g.lo[2], g.h[2], k0, gamma);
-        FF_CHECK(hipMalloc(&p->d_T1, (size_t)NG * mx * my * sizeof(cd)));
-        // stage 1: T1[p][yx] = sum_z Pz[p][z] s[z][yx]
-        gr.push_back(GemmGroup{p->d_A1, (const double *)s_field, p->d_T1, NG, rt});
-    }
-    FF_CHECK(hipMalloc(&p->d_T2, (size_t)M * mx * sizeof(cd)));
-    FF_CHECK(hipMalloc(&p->d_F, (size_t)M * sizeof(cd)));
+    const long N = (long)g.N();
+    FF_CHECK(p->alloc(&p->d_Plast, (size_t)M * mx * sizeof(cd)));
+    hipLaunchKernelGGL(k_plain_factor, dim3(grid_for((long)M * mx)), dim3(256), 0, s, p->d_Plast, p->d_alpha, M, mx,
+                       g.lo[0], g.h[0], k0, gamma);
+    FF_CHECK(p->alloc(&p->d_T2, (size_t)M * mx * sizeof(cd)));
+    FF_CHECK(p->alloc(&p->d_F, (size_t)M * sizeof(cd)));
+    if (d == 3) FF_CHECK(p->alloc(&p->d_T1, (size_t)NG * mx * my * sizeof(cd)));
     int maxM = 0;
-    for (int gi = 0; gi < NG; ++gi) {
-        int Mg = p->gstart[gi + 1] - p->gstart[gi];
-        maxM = std::max(maxM, Mg);
-        const double *S = (d == 3) ? (const double *)(p->d_T1 + (size_t)gi * mx * my) : (const double *)s_field;
-        gr.push_back(GemmGroup{p->d_A2 + off[gi], S, p->d_T2 + (size_t)p->gstart[gi] * mx, Mg, ceil_div(2L * Mg, 16)});
-    }
-    FF_CHECK(hipMalloc(&p->d_groups, gr.size() * sizeof(GemmGroup)));
-    FF_CHECK(hipMemcpy(p->d_groups, gr.data(), gr.size() * sizeof(GemmGroup), hipMemcpyHostToDevice));
-    if (d == 3) {
-        p->L1 = GemmLaunch{p->d_groups, 1, mz, mx * my, NG, 2L * mx * my, (long)mx * my};
-        p->L2 = GemmLaunch{p->d_groups + 1, NG, my, mx, maxM, 2L * mx, (long)mx};
+    for (int gi = 0; gi < NG; ++gi) maxM = std::max(maxM, p->gstart[gi + 1] - p->gstart[gi]);
+
+    if (p->ns == 0) {
+        // ---- FP64 MFMA
+        FF_CHECK(p->alloc(&p->d_s, (size_t)N * sizeof(cd)));
+        const int ks_y = ceil_div(my, 4);
+        std::vector<size_t> off(NG);
+        size_t tot = 0;
+        for (int gi = 0; gi < NG; ++gi) {
+            off[gi] = tot;
+            tot += (size_t)ceil_div(2L * (p->gstart[gi + 1] - p->gstart[gi]), 16) * ks_y * 64;
+        }
+        double *A2 = nullptr;
+        FF_CHECK(p->alloc(&A2, tot * sizeof(double)));
+        for (int gi = 0; gi < NG; ++gi) {
+            int Mg = p->gstart[gi + 1] - p->gstart[gi];
+            int rt = ceil_div(2L * Mg, 16);
+            hipLaunchKernelGGL(k_pack_factor, dim3(grid_for((long)rt * ks_y * 64)), dim3(256), 0, s, A2 + off[gi],
+                               p->d_alpha + (size_t)1 * M + p->gstart[gi], Mg, my, rt, ks_y, g.lo[1], g.h[1], k0,
+                               gamma);
+        }
+        std::vector<GemmGroup> gr;
+        if (d == 3) {
+            const int ks_z = ceil_div(mz, 4);
+            int rt = ceil_div(2L * NG, 16);
+            double *A1 = nullptr;
+            FF_CHECK(p->alloc(&A1, (size_t)rt * ks_z * 64 * sizeof(double)));
+            hipLaunchKernelGGL(k_pack_factor, dim3(grid_for((long)rt * ks_z * 64)), dim3(256), 0, s, A1,
+                               p->d_alpha + (size_t)3 * M, NG, mz, rt, ks_z, g.lo[2], g.h[2], k0, gamma);
+            // stage 1: T1[p][yx] = sum_z Pz[p][z] s[z][yx]
+            gr.push_back(GemmGroup{A1, (const double *)p->d_s, p->d_T1, NG, rt});
+        }
+        for (int gi = 0; gi < NG; ++gi) {
+            int Mg = p->gstart[gi + 1] - p->gstart[gi];
+            const double *S = (d == 3) ? (const double *)(p->d_T1 + (size_t)gi * mx * my) : (const double *)p->d_s;
+            gr.push_back(GemmGroup{A2 + off[gi], S, p->d_T2 + (size_t)p->gstart[gi] * mx, Mg, ceil_div(2L * Mg, 16)});
+        }
+        GemmGroup *dg = nullptr;
+        FF_CHECK(upload(p, &dg, gr));
+        if (d == 3) {
+            p->L1 = GemmLaunch{dg, 1, mz, mx * my, NG, 2L * mx * my, (long)mx * my};
+            p->L2 = GemmLaunch{dg + 1, NG, my, mx, maxM, 2L * mx, (long)mx};
+        } else {
+            p->L2 = GemmLaunch{dg, 1, my, mx, maxM, 2L * mx, (long)mx};
+        }
     } else {
-        p->L2 = GemmLaunch{p->d_groups, 1, my, mx, maxM, 2L * mx, (long)mx};
+        // ---- split BF16 MFMA
+        const int ns = p->ns;
+        // integrand planes: contraction over the slowest axis
+        const int K1 = (d == 3) ? mz : my;
+        const long Nc1 = (d == 3) ? (long)mx * my : mx;
+        const int ks1 = ceil_div(K1, 32);
+        p->kb1 = 4 * ks1;
+        p->ldP1 = round_up(2 * Nc1, BF_COL_PAD);
+        p->ps1 = (long)p->kb1 * p->ldP1;
+        FF_CHECK(p->alloc(&p->d_S1b, (size_t)ns * p->ps1 * sizeof(us8)));
+        // last GEMM stage: contraction over y, per group
+        const int ks_y = ceil_div(my, 32);
+        std::vector<size_t> off(NG);
+        std::vector<int> rts(NG);
+        size_t tot = 0;
+        int maxrt = 0;
+        for (int gi = 0; gi < NG; ++gi) {
+            int Mg = p->gstart[gi + 1] - p->gstart[gi];
+            rts[gi] = (int)round_up(ceil_div(2L * Mg, 16), BF_RT_PAD);
+            maxrt = std::max(maxrt, rts[gi]);
+            off[gi] = tot;
+            tot += (size_t)rts[gi] * ks_y * 64;
+        }
+        us8 *A2 = nullptr;
+        FF_CHECK(p->alloc(&A2, (size_t)ns * tot * sizeof(us8)));
+        for (int gi = 0; gi < NG; ++gi) {
+            int Mg = p->gstart[gi + 1] - p->gstart[gi];
+            long n = (long)rts[gi] * ks_y * 64;
+            if (ns == 3)
+                hipLaunchKernelGGL(k_pack_factor_bf16<3>, dim3(grid_for(n)), dim3(256), 0, s, A2 + off[gi],
+                                   (long)tot, p->d_alpha + (size_t)1 * M + p->gstart[gi], Mg, my, rts[gi], ks_y,
+                                   g.lo[1], g.h[1], k0, gamma);
+            else
+                hipLaunchKernelGGL(k_pack_factor_bf16<2>, dim3(grid_for(n)), dim3(256), 0, s, A2 + off[gi],
+                                   (long)tot, p->d_alpha + (size_t)1 * M + p->gstart[gi], Mg, my, rts[gi], ks_y,
+                                   g.lo[1], g.h[1], k0, gamma);
+        }
+        std::vector<GemmGroupB> gr;
+        if (d == 3) {
+            const int rt1 = (int)round_up(ceil_div(2L * NG, 16), BF_RT_PAD);
+            us8 *A1 = nullptr;
+            long n1 = (long)rt1 * ks1 * 64;
+            FF_CHECK(p->alloc(&A1, (size_t)ns * n1 * sizeof(us8)));
+            if (ns == 3)
+                hipLaunchKernelGGL(k_pack_factor_bf16<3>, dim3(grid_for(n1)), dim3(256), 0, s, A1, n1,
+                                   p->d_alpha + (size_t)3 * M, NG, mz, rt1, ks1, g.lo[2], g.h[2], k0, gamma);
+            else
+                hipLaunchKernelGGL(k_pack_factor_bf16<2>, dim3(grid_for(n1)), dim3(256), 0, s, A1, n1,
+                                   p->d_alpha + (size_t)3 * M, NG, mz, rt1, ks1, g.lo[2], g.h[2], k0, gamma);
+            gr.push_back(GemmGroupB{(const bf8 *)A1, n1, (const bf8 *)p->d_S1b, p->ps1, p->d_T1, (long)mx * my, NG,
+                                    (int)Nc1, rt1});
+            // stage-1 result planes for stage 2 (one set per group)
+            p->kb2 = 4 * ks_y;
+            p->ldP2 = round_up(2L * mx, BF_COL_PAD);
+            p->ps2 = (long)p->kb2 * p->ldP2;
+            p->gs2 = (long)ns * p->ps2;
+            FF_CHECK(p->alloc(&p->d_S2b, (size_t)NG * p->gs2 * sizeof(us8)));
+        }
+        for (int gi = 0; gi < NG; ++gi) {
+            int Mg = p->gstart[gi + 1] - p->gstart[gi];
+            const us8 *S = (d == 3) ? p->d_S2b + (size_t)gi * p->gs2 : p->d_S1b;
+            long ps = (d == 3) ? p->ps2 : p->ps1;
+            gr.push_back(GemmGroupB{(const bf8 *)(A2 + off[gi]), (long)tot, (const bf8 *)S, ps,
+                                    p->d_T2 + (size_t)p->gstart[gi] * mx, (long)mx, Mg, mx, rts[gi]});
+        }
+        GemmGroupB *dg = nullptr;
+        FF_CHECK(upload(p, &dg, gr));
+        if (d == 3) {
+            p->B1 = GemmLaunchB{dg, 1, ks1, (int)round_up(ceil_div(2L * NG, 16), BF_RT_PAD), p->ldP1};
+            p->B2 = GemmLaunchB{dg + 1, NG, ks_y, maxrt, p->ldP2};
+        } else {
+            p->B2 = GemmLaunchB{dg, 1, ks_y, maxrt, p->ldP1};
+        }
     }
     FF_CHECK(hipGetLastError());
     return hipStreamSynchronize(s);
 }
 
-// Contract the integrand (the buffer given at prepare) into F (device, M
+// Integrand s = q (u_in + u) (u may be null: Born term), in FP64 or as BF16
+// planes.
+hipError_t ff_plan_integrand(FarFieldPlan *p, const LevelGeom &g, const cd *q, const cd *u, const cd *E,
+                             hipStream_t s)
+{
+    const int d = g.dim, mx = g.m[0], my = g.m[1], mz = (d == 3) ? g.m[2] : 1;
+    if (p->ns == 0) {
+        hipLaunchKernelGGL(k_ff_integrand, dim3(grid_for((long)g.N())), dim3(256), 0, s, q, u, E, p->d_s, mx, my,
+                           mz);
+    } else {
+        const long w1 = (long)p->kb1 * (p->ldP1 / 2);
+        if (p->ns == 3)
+            hipLaunchKernelGGL(k_ff_integrand_split<3>, dim3(grid_for(w1)), dim3(256), 0, s, q, u, E, p->d_S1b, mx,
+                               my, mz, d, p->kb1, p->ldP1, p->ps1);
+        else
+            hipLaunchKernelGGL(k_ff_integrand_split<2>, dim3(grid_for(w1)), dim3(256), 0, s, q, u, E, p->d_S1b, mx,
+                               my, mz, d, p->kb1, p->ldP1, p->ps1);
+    }
+    return hipGetLastError();
+}
+
+// The GEMM stages: T[m][x] (2D), or T1 then T2 (3D).
+hipError_t ff_plan_contract(FarFieldPlan *p, const LevelGeom &g, hipStream_t s)
+{
+    const int d = g.dim, mx = g.m[0], my = g.m[1];
+    if (p->ns == 0) {
+        if (d == 3) launch_gemm(p->L1, s);
+        launch_gemm(p->L2, s);
+    } else {
+        if (d == 3) {
+            launch_gemm_bf16(p->B1, p->ns, p->variant, s);
+            const int NG = (int)p->gval.size();
+            const long w2 = (long)p->kb2 * (p->ldP2 / 2);
+            dim3 grid(std::min<unsigned>(grid_for(w2), 4096u), (unsigned)NG);
+            if (p->ns == 3)
+                hipLaunchKernelGGL(k_split_field<3>, grid, dim3(256), 0, s, p->d_T1, (long)mx * my, my, (long)mx,
+                                   p->d_S2b, p->gs2, p->kb2, p->ldP2, p->ps2);
+            else
+                hipLaunchKernelGGL(k_split_field<2>, grid, dim3(256), 0, s, p->d_T1, (long)mx * my, my, (long)mx,
+                                   p->d_S2b, p->gs2, p->kb2, p->ldP2, p->ps2);
+        }
+        launch_gemm_bf16(p->B2, p->ns, p->variant, s);
+    }
+    return hipGetLastError();
+}
+
+// F_m = e^{i d gamma} prod h sum_x Px[m][x] T[m][x], into F_out (device, M
 // complex, the caller's direction order).
-hipError_t ff_plan_execute(FarFieldPlan *p, const LevelGeom &g, double gamma, cd *F_out, hipStream_t s)
+hipError_t ff_plan_finish(FarFieldPlan *p, const LevelGeom &g, double gamma, cd *F_out, hipStream_t s)
 {
     const int d = g.dim, M = p->M, mx = g.m[0];
-    if (d == 3) launch_gemm(p->L1, s);
-    launch_gemm(p->L2, s);
     double vol = 1.0;
     for (int k = 0; k < d; ++k) vol *= g.h[k];
     cd pre = {vol * cos(d * gamma), vol * sin(d * gamma)};
     hipLaunchKernelGGL(k_ff_final, dim3(ceil_div(M, 4)), dim3(256), 0, s, p->d_Plast, p->d_T2, M, mx, pre, p->d_F);
     hipLaunchKernelGGL(k_unpermute, dim3(ceil_div(M, 256)), dim3(256), 0, s, p->d_F, p->d_perm, M, F_out);
     return hipGetLastError();
-}
-
-void launch_ff_integrand(const LevelGeom &g, const cd *q, const cd *u, const cd *E, cd *s, hipStream_t st)
-{
-    size_t N = g.N();
-    size_t nb = (N + 255) / 256;
-    if (nb > 65536) nb = 65536;
-    hipLaunchKernelGGL(k_ff_integrand, dim3((unsigned)nb), dim3(256), 0, st, q, u, E, s, g.m[0], g.m[1],
-                       g.dim == 3 ? g.m[2] : 1);
 }
 
 void launch_axis_exp(cd *out, int m, double lo, double h, double cr, double ci, hipStream_t s)

@@ -50,7 +50,7 @@ struct ffmg_handle {
     ffmg::TailParams<double> tail64{};
     ffmg::TailParams<float> tail32{};
     ffmg::FarFieldPlan *ff = nullptr;
-    ffmg::cd *d_s = nullptr;         // far-field integrand
+    int ff_variant = -1;             // split-GEMM tile variant (-1: default; autotuned)
     ffmg::cd *d_E = nullptr;         // plane-wave axis factors
     ffmg::cd *d_F = nullptr;         // far-field staging
     int d_F_cap = 0;

@@ -25,7 +25,8 @@ enum ProfKernel {
     PROF_FF = 1,       // far-field contraction
     PROF_POST = 2,     // finest-level interpolation + post-smoothing (fused)
     PROF_REFINE = 3,   // FP64 update + residual of the refinement loop (fused)
-    PROF_N = 4
+    PROF_FFGEMM = 4,   // far-field GEMM stages alone
+    PROF_N = 5
 };
 
 // Device-resident state of one solve (residual-reduction stopping test of
@@ -153,9 +154,17 @@ void launch_tail2d(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top
 struct FarFieldPlan;
 FarFieldPlan *ff_plan_create();
 void ff_plan_destroy(FarFieldPlan *p);
+// prec: ffmg_ff_precision (0 FP64 MFMA, 1 split BF16 x3, 2 split BF16 x6).
 hipError_t ff_plan_prepare(FarFieldPlan *p, const LevelGeom &g, double k0, double gamma, int M, const double *dirs,
-                           const cd *s_field, hipStream_t s);
-hipError_t ff_plan_execute(FarFieldPlan *p, const LevelGeom &g, double gamma, cd *F_out, hipStream_t s);
-void launch_ff_integrand(const LevelGeom &g, const cd *q, const cd *u, const cd *E, cd *s, hipStream_t st);
+                           int prec, hipStream_t s);
+hipError_t ff_plan_integrand(FarFieldPlan *p, const LevelGeom &g, const cd *q, const cd *u, const cd *E,
+                             hipStream_t s);
+hipError_t ff_plan_contract(FarFieldPlan *p, const LevelGeom &g, hipStream_t s);
+hipError_t ff_plan_finish(FarFieldPlan *p, const LevelGeom &g, double gamma, cd *F_out, hipStream_t s);
+// split-GEMM tile variants (autotuning)
+int ff_plan_variants();
+int ff_plan_default_variant();
+void ff_plan_set_variant(FarFieldPlan *p, int v);
+int ff_plan_variant(const FarFieldPlan *p);
 void launch_axis_exp(cd *out, int m, double lo, double h, double cr, double ci, hipStream_t s);
 }  // namespace ffmg

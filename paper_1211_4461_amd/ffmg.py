@@ -60,7 +60,8 @@ _lib = None
 
 EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup", "mg_rhs_plane_wave",
            "mg_vcycle", "mg_solve", "farfield_map", "mg_apply", "mg_smooth", "mg_residual_norm",
-           "mg_num_levels", "mg_level_shape", "mg_destroy", "mg_profile_enable", "mg_profile_read"]
+           "mg_num_levels", "mg_level_shape", "mg_destroy", "mg_profile_enable", "mg_profile_read",
+           "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield"]
 
 
 def lib():
@@ -92,8 +93,13 @@ def lib():
     L.mg_destroy.restype = None
     L.mg_profile_enable.argtypes = [vp, ip]
     L.mg_profile_read.argtypes = [vp, ip, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
+    L.mg_tune_variants.argtypes = [vp, ip]
+    L.mg_tune_get.argtypes = [vp, ip, ctypes.POINTER(ip)]
+    L.mg_tune_set.argtypes = [vp, ip, ip]
+    L.mg_tune_farfield.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(dp), ip, ctypes.POINTER(ip)]
     for name in ("mg_setup", "mg_rhs_plane_wave", "mg_vcycle", "mg_solve", "farfield_map", "mg_apply",
-                 "mg_smooth", "mg_residual_norm", "mg_level_shape", "mg_profile_enable", "mg_profile_read"):
+                 "mg_smooth", "mg_residual_norm", "mg_level_shape", "mg_profile_enable", "mg_profile_read",
+                 "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield"):
         getattr(L, name).restype = ip
     _lib = L
     return L
@@ -229,6 +235,36 @@ def farfield_map(h: Handle, eta, u, dirs, out=None):
     return F
 
 
+TUNE_FF_GEMM = 0
+
+
+def mg_tune_variants(h: Handle, tunable=TUNE_FF_GEMM) -> int:
+    return int(lib().mg_tune_variants(h.ptr, int(tunable)))
+
+
+def mg_tune_get(h: Handle, tunable=TUNE_FF_GEMM) -> int:
+    v = ctypes.c_int()
+    h._check(lib().mg_tune_get(h.ptr, int(tunable), ctypes.byref(v)), "mg_tune_get")
+    return v.value
+
+
+def mg_tune_set(h: Handle, variant, tunable=TUNE_FF_GEMM):
+    h._check(lib().mg_tune_set(h.ptr, int(tunable), int(variant)), "mg_tune_set")
+
+
+def mg_tune_farfield(h: Handle, eta, u, dirs, reps=5):
+    """Time every variant of the far-field contraction on this handle's
+    shapes; selects the fastest.  Returns (best, [ms per variant])."""
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64))
+    nv = max(mg_tune_variants(h, TUNE_FF_GEMM), 1)
+    times = (ctypes.c_double * nv)()
+    best = ctypes.c_int()
+    up = None if u is None else _dev_ptr(u, "u")
+    h._check(lib().mg_tune_farfield(h.ptr, _eta3(eta), up, d.shape[0], ctypes.c_void_p(d.ctypes.data), int(reps),
+                                    times, nv, ctypes.byref(best)), "mg_tune_farfield")
+    return best.value, list(times)
+
+
 def mg_apply(h: Handle, u, Au):
     h._check(lib().mg_apply(h.ptr, _dev_ptr(u, "u"), _dev_ptr(Au, "Au")), "mg_apply")
     return Au
@@ -253,16 +289,16 @@ def mg_destroy(h: Handle):
 KERNEL_SWEEP, KERNEL_FARFIELD = 0, 1
 
 
-PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE = 0, 1, 2, 3
+PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE, PROF_FFGEMM = 0, 1, 2, 3, 4
 
 
-def mg_profile_enable(h: Handle, mask=0xF):
+def mg_profile_enable(h: Handle, mask=0x1F):
     """Time kernel k when bit k of mask is set (0 disables)."""
     h._check(lib().mg_profile_enable(h.ptr, int(mask)), "mg_profile_enable")
 
 
 def mg_profile_read(h: Handle, kernel):
-    """(total_ms, launches) of kernel 0 (finest sweep) or 1 (far field)."""
+    """(total_ms, launches) recorded for kernel PROF_* since the last read."""
     ms, n = ctypes.c_double(), ctypes.c_int64()
     h._check(lib().mg_profile_read(h.ptr, int(kernel), ctypes.byref(ms), ctypes.byref(n)), "mg_profile_read")
     return ms.value, n.value

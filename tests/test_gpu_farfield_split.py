@@ -1,0 +1,172 @@
+"""Split-BF16 MFMA far-field contraction against the FP64 oracle.
+
+Each FP64 operand is split into BF16 parts and the part products are summed
+with FP32 accumulation (flushed into FP64 after every 32-deep k-step), so the
+error of a direction is bounded by a multiple of the unit roundoff of the
+format times sum_j |term_j| (the oracle's `absum`):
+  * three parts, 6 products: ~2^-24 per term  -> bar 2e-6 * absum
+  * two parts,   3 products: ~3 * 2^-18       -> bar 1e-4 * absum
+Three-part results must also be clearly more accurate than two-part ones.
+The mixed map (FP32 V-cycles in FP64 refinement + three-part contraction)
+must match the oracle's converged map to 1e-6 relative (norm over angles).
+"""
+import numpy as np
+import pytest
+
+from paper_1211_4461_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+BARS = {1: 1e-4, 2: 2e-6}   # ff_precision -> error / absum bar
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_4461_amd import ffmg
+    ffmg.lib()
+    return ffmg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(np.asarray(b).ravel())
+
+
+def crand(seed, shape):
+    r = np.random.default_rng(seed)
+    return r.standard_normal(shape) + 1j * r.standard_normal(shape)
+
+
+def setup(ff, orc, w, **opt):
+    h, coef = ff.setup_workload(w, options=ff.default_options(**opt))
+    g = orc.Grid(w.dim, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    return h, coef, g, kappa, q, k0
+
+
+RANDOM_CASES = [
+    ("2d-63-M37", lambda: W.bumps_2d(n=64, seed=3, k0=1.7, M=37)),
+    ("2d-127-M40", lambda: W.bumps_2d(n=128, seed=5, k0=1.3, M=40)),
+    ("2d-255-M19", lambda: W.bumps_2d(n=256, seed=6, k0=0.9, M=19)),
+    ("3d-15", lambda: W.radial_3d(16, L=3.0, k0=1.2, n_az=7, n_pol=3)),
+    ("3d-31", lambda: W.radial_3d(32, L=6.0, k0=1.0, n_az=9, n_pol=5)),
+]
+
+
+@pytest.mark.parametrize("name,mk", RANDOM_CASES)
+def test_split_contraction_error_bound(ff, orc, name, mk):
+    """Random scattered wave, ragged grids and direction counts: per-direction
+    error within the bar of each split, and three parts beat two."""
+    w = mk()
+    u = crand(7, tuple(reversed([w.n - 1] * w.dim))) * 0.1
+    ratios = {}
+    for prec in (1, 2):
+        h, coef, g, kappa, q, k0 = setup(ff, orc, w, ff_precision=prec)
+        s = orc.ff_integrand(g, w.gamma, k0, q, w.eta, u)
+        Fo, ab = orc.ff_contract(g, w.gamma, k0, s, w.dirs, method="dense", want_absum=True)
+        Fg = ff.farfield_map(h, w.eta, dev(u), w.dirs)
+        r = np.abs(Fg - Fo) / ab
+        ratios[prec] = r.max()
+        assert np.all(r <= BARS[prec]), (prec, r.max())
+        assert np.all(np.isfinite(Fg))
+    assert ratios[2] < ratios[1] / 16, ratios
+
+
+def test_split_born_term(ff, orc):
+    """u = NULL (Born term) through the split path."""
+    w = W.radial_2d(128, L=10.0, k0=1.0, amp=0.5, width=1.0)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w, ff_precision=2)
+    s = orc.ff_integrand(g, w.gamma, k0, q, w.eta, None)
+    Fo, ab = orc.ff_contract(g, w.gamma, k0, s, w.dirs, method="dense", want_absum=True)
+    Fg = ff.farfield_map(h, w.eta, None, w.dirs)
+    assert np.all(np.abs(Fg - Fo) <= BARS[2] * ab)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mixed_map_matches_oracle(ff, orc, dim):
+    """The mixed form end to end: FP32 V-cycles in FP64 refinement and the
+    three-part split contraction, against the oracle's converged FP64 map."""
+    w = W.bumps_2d(n=256, seed=9, k0=1.0, M=90) if dim == 2 else W.radial_3d(32, L=6.0, n_az=8, n_pol=5)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w, precision=ff.FP32_IR, ff_precision=2)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    uo, st, k, _ = mg.solve(b, tol=1e-13)
+    assert st == 0
+    Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
+    bd = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    ud = torch.zeros_like(bd)
+    info = ff.mg_solve(h, bd, ud, tol=1e-10)
+    assert info.status == 0
+    Fg = ff.farfield_map(h, w.eta, ud, w.dirs)
+    assert rel(Fg, Fo) < 1e-6
+
+
+def test_repeated_maps_and_precision_switch(ff, orc):
+    """Plans are cached per direction set: maps with new directions, and the
+    same directions again, give the same numbers as a fresh handle."""
+    w = W.bumps_2d(n=128, seed=12, k0=1.0, M=33)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w, ff_precision=2)
+    u = dev(crand(3, g.shape) * 0.1)
+    F1 = ff.farfield_map(h, w.eta, u, w.dirs)
+    F2 = ff.farfield_map(h, w.eta, u, W.directions_2d(50))
+    F3 = ff.farfield_map(h, w.eta, u, w.dirs)
+    np.testing.assert_array_equal(F1, F3)
+    h2, _, _, _, _, _ = setup(ff, orc, w, ff_precision=2)
+    np.testing.assert_array_equal(ff.farfield_map(h2, w.eta, u, W.directions_2d(50)), F2)
+
+
+def test_split_range_error(ff, orc):
+    """Boxes whose contour exponentials leave the FP32 range are refused by the
+    split contraction and accepted by the FP64 one."""
+    w = W.radial_2d(64, L=10.0, k0=5.0, amp=0.5, width=1.0)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w, ff_precision=2)
+    with pytest.raises(ff.FfmgError) as e:
+        ff.farfield_map(h, w.eta, None, w.dirs)
+    assert e.value.status == ff.FFMG_ERANGE
+    h64, _, _, _, _, _ = setup(ff, orc, w)
+    assert np.all(np.isfinite(ff.farfield_map(h64, w.eta, None, w.dirs)))
+
+
+def test_gemm_variants_agree_and_tuner_selects(ff, orc, tmp_path):
+    """Every tile variant of the split GEMM sums in the same order, so maps
+    agree bit for bit; the library's sweep times all of them and the cached
+    choice is applied on a second handle."""
+    from paper_1211_4461_amd import autotune
+    w = W.bumps_2d(n=256, seed=4, k0=1.0, M=45)
+    h, coef, g, kappa, q, k0 = setup(ff, orc, w, ff_precision=2)
+    u = dev(crand(5, g.shape) * 0.1)
+    nv = ff.mg_tune_variants(h)
+    assert nv >= 2
+    ref = None
+    for v in range(nv):
+        ff.mg_tune_set(h, v)
+        assert ff.mg_tune_get(h) == v
+        F = ff.farfield_map(h, w.eta, u, w.dirs)
+        if ref is None:
+            ref = F
+        np.testing.assert_array_equal(F, ref)
+    best, times = ff.mg_tune_farfield(h, w.eta, u, w.dirs, reps=2)
+    assert 0 <= best < nv and all(t > 0 for t in times) and times[best] == min(times)
+    assert ff.mg_tune_get(h) == best
+    np.testing.assert_array_equal(ff.farfield_map(h, w.eta, u, w.dirs), ref)
+    cache = str(tmp_path / "tune.json")
+    v1 = autotune.tune_farfield(h, w.eta, u, w.dirs, 2, path=cache, reps=2)
+    h2, _, _, _, _, _ = setup(ff, orc, w, ff_precision=2)
+    assert autotune.tune_farfield(h2, w.eta, u, w.dirs, 2, path=cache) == v1
+    assert ff.mg_tune_get(h2) == v1
+    with pytest.raises(ff.FfmgError):
+        ff.mg_tune_set(h2, nv)
+    h64, _, _, _, _, _ = setup(ff, orc, w)
+    assert ff.mg_tune_variants(h64) == 1
