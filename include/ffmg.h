@@ -150,6 +150,35 @@ ffmg_status mg_solve(ffmg_handle *h, const void *b, void *u, double tol, ffmg_so
 ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs,
                          const double *dirs, void *F);
 
+/* Batched solve: count instances, instance i being the plane wave of
+ * direction etas[3i..3i+2] (the right-hand side of Sec. 2.1, built on the
+ * device) scattered by the operator of handle hs[i]; handles may repeat
+ * (several directions of one energy and grid) and may differ in grid size
+ * (e.g. the Schroedinger maps of Sec. 5 at several energies on 255^2 ..
+ * 1023^2 grids).  Every instance is solved from u = 0 to
+ * ||b - A u||_2 <= tol ||b||_2 with the FP32-in-FP64 refinement of mg_solve,
+ * and its result u[i] (DEVICE complex128[N_i], output) and info (infos[i],
+ * may be NULL) equal those of mg_solve on that handle bit for bit.  All
+ * instances advance together: one launch per kernel for the whole batch, the
+ * refinement step captured once in a HIP graph and replayed until every
+ * instance has met its stopping test on the device.  Requirements (EINVAL
+ * otherwise): 2D handles set up with precision FFMG_FP32_IR and tile_config
+ * 0, all with the same nu1 >= 1, nu2 >= 1 and inner cycles and the same
+ * coarse-level shapes (grids n = 2^k on one coarsest_n).  The workspace and
+ * graph are owned by hs[0] (freed by mg_destroy(hs[0])) and reused while the
+ * same list of handles is passed; the call is ordered after work on hs[0]'s
+ * stream and synchronises.  Returns ENOCONV if an instance did not converge
+ * (infos tells which), ENAN if a right-hand side is not finite. */
+ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *etas, void *const *u, double tol,
+                             ffmg_solve_info *infos);
+
+/* Far-field maps of count instances (hs[i], etas[3i..], u[i]; u may be NULL:
+ * Born terms) at the same n_dirs directions, into F (complex128
+ * [count][n_dirs], HOST or DEVICE) without synchronising between instances;
+ * each row equals farfield_map on that instance.  Synchronises. */
+ffmg_status farfield_map_batched(ffmg_handle *const *hs, int count, const double *etas, void *const *u, int n_dirs,
+                                 const double *dirs, void *F);
+
 /* Au = A u (the operator of eq. csg), DEVICE complex128[N] each. */
 ffmg_status mg_apply(ffmg_handle *h, const void *u, void *Au);
 

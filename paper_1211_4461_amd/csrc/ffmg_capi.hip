@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "ffmg_handle.hpp"
 
@@ -49,6 +50,18 @@ ffmg_status fail(ffmg_handle *h, ffmg_status s, const char *fmt, ...)
         h->err = buf;
     }
     return s;
+}
+
+// log of the largest magnitude of exp(+-i k0 e^{i gamma} a.x) over the box
+// for unit a: k0 sin(gamma) |x|_max.
+double exponent_budget(const ffmg_handle *h)
+{
+    double r2 = 0.0;
+    for (int k = 0; k < h->prob.dim; ++k) {
+        double m = std::max(fabs(h->prob.lo[k]), fabs(h->prob.hi[k]));
+        r2 += m * m;
+    }
+    return h->k0 * sin(h->prob.gamma) * sqrt(r2);
 }
 
 }  // namespace ffmg
@@ -240,18 +253,6 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
     if (o->tile_config < 0 || o->tile_config > 2) return fail(tmp, FFMG_EINVAL, "unknown tile_config");
     if (o->inner_cycles < 0 || o->inner_cycles > 16) return fail(tmp, FFMG_EINVAL, "inner_cycles must be in [0, 16]");
     return FFMG_OK;
-}
-
-// log of the largest magnitude of exp(+-i k0 e^{i gamma} a.x) over the box
-// for unit a: k0 sin(gamma) |x|_max.
-double exponent_budget(const ffmg_handle *h)
-{
-    double r2 = 0.0;
-    for (int k = 0; k < h->prob.dim; ++k) {
-        double m = std::max(fabs(h->prob.lo[k]), fabs(h->prob.hi[k]));
-        r2 += m * m;
-    }
-    return h->k0 * sin(h->prob.gamma) * sqrt(r2);
 }
 
 // Coarse levels handled by the one-workgroup LDS tail (2D): the longest
@@ -473,7 +474,9 @@ ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle *
 {
     if (!out) return FFMG_EINVAL;
     *out = nullptr;
+    static std::atomic<uint64_t> next_serial{1};
     ffmg_handle *h = new ffmg_handle();
+    h->serial = next_serial++;
     ffmg_status st = validate_problem(p, o, h);
     if (st == FFMG_OK) {
         h->prob = *p;
@@ -532,6 +535,7 @@ void mg_destroy(ffmg_handle *h)
         (void)hipEventDestroy(e.second);
     }
     if (h->ff) ff_plan_destroy(h->ff);
+    if (h->batch) batch_destroy(h->batch);
     for (void *p : h->allocs) (void)hipFree(p);
     if (h->h_scalar) (void)hipHostFree(h->h_scalar);
     if (h->h_ctl) (void)hipHostFree(h->h_ctl);
@@ -718,6 +722,28 @@ static ffmg_status ff_begin(ffmg_handle *h, const double eta[3], const void *u, 
     return FFMG_OK;
 }
 
+}  // extern "C"
+
+namespace ffmg {
+
+ffmg_status farfield_enqueue(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
+                             cd *Fd)
+{
+    int pi = -1;
+    TRY(ff_begin(h, eta, u, n_dirs, dirs, &pi));
+    const LevelGeom &g = h->L[0].g;
+    int pg = prof_begin(h, PROF_FFGEMM);
+    HIPCHK(h, ff_plan_contract(h->ff, g, h->stream));
+    prof_end(h, PROF_FFGEMM, pg);
+    HIPCHK(h, ff_plan_finish(h->ff, g, h->prob.gamma, Fd, h->stream));
+    prof_end(h, PROF_FF, pi);
+    return FFMG_OK;
+}
+
+}  // namespace ffmg
+
+extern "C" {
+
 ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
                          void *F)
 {
@@ -737,14 +763,7 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
         }
         Fd = h->d_F;
     }
-    int pi = -1;
-    TRY(ff_begin(h, eta, u, n_dirs, dirs, &pi));
-    const LevelGeom &g = h->L[0].g;
-    int pg = prof_begin(h, PROF_FFGEMM);
-    HIPCHK(h, ff_plan_contract(h->ff, g, h->stream));
-    prof_end(h, PROF_FFGEMM, pg);
-    HIPCHK(h, ff_plan_finish(h->ff, g, h->prob.gamma, Fd, h->stream));
-    prof_end(h, PROF_FF, pi);
+    TRY(farfield_enqueue(h, eta, u, n_dirs, dirs, Fd));
     if (!on_device)
         HIPCHK(h, hipMemcpyAsync(F, Fd, (size_t)n_dirs * sizeof(cd), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));

@@ -73,12 +73,29 @@ __device__ __forceinline__ cx<T> ld_masked(const cx<T> *__restrict__ p, size_t j
 // Block index -> tile index such that each XCD (blocks are dispatched
 // round-robin over the 8 XCDs) receives a contiguous run of tiles, so halo
 // rows shared by neighbouring tiles are served by the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb)
+__host__ __device__ __forceinline__ int xcd_tile(int b, int nb)
 {
     const int X = 8;
     int xcd = b % X, local = b / X;
     int q = nb / X, r = nb % X;
     return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
+// The block index that xcd_tile maps to tile t.
+__host__ __device__ __forceinline__ int xcd_tile_inv(int t, int nb)
+{
+    const int X = 8;
+    int q = nb / X, r = nb % X;
+    int xcd, local;
+    if (t < r * (q + 1)) {
+        xcd = t / (q + 1);
+        local = t - xcd * (q + 1);
+    } else {
+        int t2 = t - r * (q + 1);
+        xcd = r + t2 / q;
+        local = t2 - (xcd - r) * q;
+    }
+    return local * X + xcd;
 }
 
 }  // namespace ffmg

@@ -73,13 +73,11 @@ constexpr int smooth_th()
 //   2. (PROL) u += P e_c in LDS;
 //   3. (NS = 2) sweep 1 on the tile plus a one-point halo;
 //   4. the last sweep on the tile, written to out.
-template <typename T, int NS, bool ZERO, bool PROL, int TAG>
-__global__ __launch_bounds__(256) void k_smooth2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
-                                                  const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
-                                                  cx<T> *__restrict__ out, Stencil<T> P, int tiles_x,
-                                                  const int *__restrict__ stop)
+template <typename T, int NS, bool ZERO, bool PROL>
+__device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
+                                              const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                              cx<T> *__restrict__ out, const Stencil<T> &P, int tiles_x, int tile)
 {
-    if (stop && *stop) return;
     constexpr int TH = smooth_th<T>();
     constexpr int H = NS;                                  // halo depth of the staged u
     constexpr int UW = FTX + 2 * H, UH = TH + 2 * H;
@@ -94,7 +92,6 @@ __global__ __launch_bounds__(256) void k_smooth2d(const cx<T> *__restrict__ u, c
     __shared__ cx<T> EC[PROL ? ECH : 1][PROL ? ECW : 1];
     const int mx = P.mx, my = P.my;
     const int mxc = (mx - 1) / 2, myc = (my - 1) / 2;
-    int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int x0 = (tile % tiles_x) * FTX, y0 = (tile / tiles_x) * TH;
     const int ecx0 = x0 / 2 - 2, ecy0 = y0 / 2 - 2;
     const cx<T> zero = {T(0), T(0)};
@@ -227,21 +224,29 @@ __global__ __launch_bounds__(256) void k_smooth2d(const cx<T> *__restrict__ u, c
     }
 }
 
+template <typename T, int NS, bool ZERO, bool PROL, int TAG>
+__global__ __launch_bounds__(256) void k_smooth2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
+                                                  const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                                  cx<T> *__restrict__ out, Stencil<T> P, int tiles_x,
+                                                  const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    smooth2d_body<T, NS, ZERO, PROL>(u, ec, b, q, out, P, tiles_x, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // Residual + full weighting.  Coarse tile RCX x RCY; the fine residual is
 // needed at fine interior indices [2 I0, 2 (I0 + RCX)] x [2 J0, 2 (J0 + RCY)].
 template <typename T>
-__global__ __launch_bounds__(256) void k_resid_restrict2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
-                                                          const cx<T> *__restrict__ q, cx<T> *__restrict__ bc,
-                                                          Stencil<T> P, int ctiles_x, const int *__restrict__ stop)
+__device__ __forceinline__ void resid_restrict2d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                      const cx<T> *__restrict__ q, cx<T> *__restrict__ bc,
+                                                      const Stencil<T> &P, int ctiles_x, int tile)
 {
-    if (stop && *stop) return;
     constexpr int RW = 2 * RCX + 1, RH = 2 * RCY + 1;   // residual region
     constexpr int UW = RW + 2, UH = RH + 2;             // u region (one halo)
     __shared__ cx<T> U[UH][UW];
     __shared__ cx<T> R[RH][RW];
     const int mx = P.mx, my = P.my;
     const int mxc = (mx - 1) / 2, myc = (my - 1) / 2;
-    int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int I0 = (tile % ctiles_x) * RCX, J0 = (tile / ctiles_x) * RCY;
     const int fx0 = 2 * I0, fy0 = 2 * J0;               // first fine index of R
     const cx<T> zero = {T(0), T(0)};
@@ -298,21 +303,28 @@ __global__ __launch_bounds__(256) void k_resid_restrict2d(const cx<T> *__restric
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                          const cx<T> *__restrict__ q, cx<T> *__restrict__ bc,
+                                                          Stencil<T> P, int ctiles_x, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    resid_restrict2d_body<T>(u, b, q, bc, P, ctiles_x, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // Mixed-precision outer step: u' = u + s d with s = ctl->scale_cur;
 // r = b - A u' (FP64); r32 = r / ctl->scale_next; per-block sum |r|^2.
 // Out of place in u.
-__global__ __launch_bounds__(256) void k_refine2d(const cd *__restrict__ u, const cf *__restrict__ d,
-                                                  const cd *__restrict__ b, const cd *__restrict__ q,
-                                                  cd *__restrict__ u_out, cf *__restrict__ r32,
-                                                  const SolveCtl *__restrict__ ctl, Stencil<double> P, int tiles_x,
-                                                  double *__restrict__ partial, const int *__restrict__ stop)
+__device__ __forceinline__ void refine2d_body(const cd *__restrict__ u, const cf *__restrict__ d,
+                                              const cd *__restrict__ b, const cd *__restrict__ q,
+                                              cd *__restrict__ u_out, cf *__restrict__ r32,
+                                              const SolveCtl *__restrict__ ctl, const Stencil<double> &P,
+                                              int tiles_x, int tile, double *__restrict__ partial_slot)
 {
-    if (stop && *stop) return;
     const double s = ctl->scale_cur;
     const double inv_scale = 1.0 / ctl->scale_next;
     __shared__ cd U[FTY + 2][FTX + 2];
     const int mx = P.mx, my = P.my;
-    int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int x0 = (tile % tiles_x) * FTX, y0 = (tile / tiles_x) * FTY;
 #pragma unroll
     for (int k = 0; k < ((FTY + 2) * (FTX + 2) + 255) / 256; ++k) {
@@ -349,7 +361,17 @@ __global__ __launch_bounds__(256) void k_refine2d(const cd *__restrict__ u, cons
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) *partial_slot = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_refine2d(const cd *__restrict__ u, const cf *__restrict__ d,
+                                                  const cd *__restrict__ b, const cd *__restrict__ q,
+                                                  cd *__restrict__ u_out, cf *__restrict__ r32,
+                                                  const SolveCtl *__restrict__ ctl, Stencil<double> P, int tiles_x,
+                                                  double *__restrict__ partial, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    refine2d_body(u, d, b, q, u_out, r32, ctl, P, tiles_x, xcd_tile(blockIdx.x, gridDim.x), partial + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,12 +436,9 @@ __device__ void tail_smooth(const TailView<T> &v, const TailLevel<T> &L, int nu,
 }
 
 template <typename T>
-__global__ __launch_bounds__(1024) void k_tail2d(TailParams<T> tp, const cx<T> *__restrict__ b_top,
-                                                 cx<T> *__restrict__ u_top, const int *__restrict__ stop)
+__device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T> *__restrict__ b_top,
+                                            cx<T> *__restrict__ u_top, cx<T> *lds)
 {
-    if (stop && *stop) return;
-    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds[];
-    cx<T> *lds = reinterpret_cast<cx<T> *>(tail_lds);
     const int nt = tp.nt;
     {
         TailView<T> v0 = tail_view(lds, tp.lv[0]);
@@ -490,6 +509,15 @@ __global__ __launch_bounds__(1024) void k_tail2d(TailParams<T> tp, const cx<T> *
     }
     TailView<T> v0 = tail_view(lds, tp.lv[0]);
     for (int j = threadIdx.x; j < v0.N; j += blockDim.x) u_top[j] = v0.u[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail2d(TailParams<T> tp, const cx<T> *__restrict__ b_top,
+                                                 cx<T> *__restrict__ u_top, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds[];
+    tail2d_body<T>(tp, b_top, u_top, reinterpret_cast<cx<T> *>(tail_lds));
 }
 
 // ---------------------------------------------------------------------------
@@ -582,5 +610,121 @@ void launch_tail2d(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top
 }
 template void launch_tail2d<double>(const TailParams<double> &, size_t, const cd *, cd *, hipStream_t, const int *);
 template void launch_tail2d<float>(const TailParams<float> &, size_t, const cf *, cf *, hipStream_t, const int *);
+
+// ---------------------------------------------------------------------------
+// Batched launches.  The flat block index is mapped XCD-contiguously onto the
+// concatenated tiles of all jobs; within a job the tile and the slot of its
+// partial sum are those of the single-instance launch (block b of that launch
+// owns tile xcd_tile(b, n) and writes partial[b]), so the results, sums
+// included, are bit for bit those of one launch per instance.
+template <typename T, int NS, bool ZERO, bool PROL>
+__global__ __launch_bounds__(256) void k_smooth2d_batch(const SmoothJob<T> *__restrict__ jobs,
+                                                        const int *__restrict__ tile_job)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const SmoothJob<T> J = jobs[tile_job[t]];
+    if (J.stop && *J.stop) return;
+    smooth2d_body<T, NS, ZERO, PROL>(J.u, J.ec, J.b, J.q, J.out, J.P, J.tiles_x, t - J.tile0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict2d_batch(const RRJob<T> *__restrict__ jobs,
+                                                                const int *__restrict__ tile_job)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const RRJob<T> J = jobs[tile_job[t]];
+    if (J.stop && *J.stop) return;
+    resid_restrict2d_body<T>(J.u, J.b, J.q, J.bc, J.P, J.ctiles_x, t - J.tile0);
+}
+
+__global__ __launch_bounds__(256) void k_refine2d_batch(const RefineJob *__restrict__ jobs,
+                                                        const int *__restrict__ tile_job)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const RefineJob J = jobs[tile_job[t]];
+    if (J.stop && *J.stop) return;
+    const int tile = t - J.tile0;
+    refine2d_body(J.u, J.d, J.b, J.q, J.u_out, J.r32, J.ctl, J.P, J.tiles_x, tile,
+                  J.partial + xcd_tile_inv(tile, J.ntiles));
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail2d_batch(const TailJob<T> *__restrict__ jobs)
+{
+    const TailJob<T> &J = jobs[blockIdx.x];
+    if (J.stop && *J.stop) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds_b[];
+    tail2d_body<T>(J.tp, J.b_top, J.u_top, reinterpret_cast<cx<T> *>(tail_lds_b));
+}
+
+template <typename T>
+int smooth2d_tiles(const LevelGeom &g, int *tiles_x)
+{
+    *tiles_x = (g.m[0] + FTX - 1) / FTX;
+    return *tiles_x * ((g.m[1] + smooth_th<T>() - 1) / smooth_th<T>());
+}
+template int smooth2d_tiles<double>(const LevelGeom &, int *);
+template int smooth2d_tiles<float>(const LevelGeom &, int *);
+
+int resid_restrict2d_tiles(const LevelGeom &g, int *ctiles_x)
+{
+    int mxc = (g.m[0] - 1) / 2, myc = (g.m[1] - 1) / 2;
+    *ctiles_x = (mxc + RCX - 1) / RCX;
+    return *ctiles_x * ((myc + RCY - 1) / RCY);
+}
+
+int refine2d_tiles(const LevelGeom &g, int *tiles_x) { return tiles2d(g, *tiles_x); }
+
+template <typename T>
+void launch_smooth2d_batch(int nsweeps, bool zero, bool prol, const SmoothJob<T> *jobs, const int *tile_job,
+                           int ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return;
+    dim3 G(ntiles), B(256);
+#define SMB(NS, Z, PR) hipLaunchKernelGGL((k_smooth2d_batch<T, NS, Z, PR>), G, B, 0, s, jobs, tile_job)
+    if (nsweeps == 2) {
+        if (zero) SMB(2, true, false);
+        else if (prol) SMB(2, false, true);
+        else SMB(2, false, false);
+    } else {
+        if (zero) SMB(1, true, false);
+        else if (prol) SMB(1, false, true);
+        else SMB(1, false, false);
+    }
+#undef SMB
+}
+template void launch_smooth2d_batch<float>(int, bool, bool, const SmoothJob<float> *, const int *, int, hipStream_t);
+template void launch_smooth2d_batch<double>(int, bool, bool, const SmoothJob<double> *, const int *, int,
+                                            hipStream_t);
+
+template <typename T>
+void launch_resid_restrict2d_batch(const RRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL((k_resid_restrict2d_batch<T>), dim3(ntiles), dim3(256), 0, s, jobs, tile_job);
+}
+template void launch_resid_restrict2d_batch<float>(const RRJob<float> *, const int *, int, hipStream_t);
+template void launch_resid_restrict2d_batch<double>(const RRJob<double> *, const int *, int, hipStream_t);
+
+void launch_refine2d_batch(const RefineJob *jobs, const int *tile_job, int ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(k_refine2d_batch, dim3(ntiles), dim3(256), 0, s, jobs, tile_job);
+}
+
+template <typename T>
+void launch_tail2d_batch(const TailJob<T> *jobs, int njobs, size_t lds_bytes, hipStream_t s)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_tail2d_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr_set = true;
+    }
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL((k_tail2d_batch<T>), dim3(njobs), dim3(1024), lds_bytes, s, jobs);
+}
+template void launch_tail2d_batch<float>(const TailJob<float> *, int, size_t, hipStream_t);
+template void launch_tail2d_batch<double>(const TailJob<double> *, int, size_t, hipStream_t);
 
 }  // namespace ffmg

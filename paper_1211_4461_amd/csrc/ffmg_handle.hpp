@@ -26,9 +26,12 @@ struct Level {
 // tile_config values
 enum { TILE_FUSED = 0, TILE_REFERENCE = 1, TILE_FUSED_NO_TAIL = 2 };
 
+struct Batch;   // batched-solve workspace (ffmg_batch.hip)
+
 }  // namespace ffmg
 
 struct ffmg_handle {
+    uint64_t serial = 0;             // unique per handle of this process
     ffmg_problem prob{};
     ffmg_options opt{};
     double k0 = 0.0, k02 = 0.0;
@@ -54,6 +57,7 @@ struct ffmg_handle {
     ffmg::cd *d_E = nullptr;         // plane-wave axis factors
     ffmg::cd *d_F = nullptr;         // far-field staging
     int d_F_cap = 0;
+    ffmg::Batch *batch = nullptr;    // batched-solve workspace for a list of handles starting with this one
     std::vector<void *> allocs;
     std::string err;
     // optional event timing of selected kernels (benchmark instrumentation)
@@ -85,6 +89,12 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
 
 int prof_begin(ffmg_handle *h, int k);
 void prof_end(ffmg_handle *h, int k, int idx);
+// log of the largest magnitude of exp(+-i k0 e^{i gamma} a.x) over the box
+double exponent_budget(const ffmg_handle *h);
+// far-field map into device memory F on the handle's stream, no synchronisation
+ffmg_status farfield_enqueue(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
+                             cd *F);
+void batch_destroy(Batch *b);
 
 }  // namespace ffmg
 

@@ -43,6 +43,7 @@ struct SolveCtl {
     int k;             // completed cycles / refinement steps
     int grow;
     int max_cycles;
+    double b2;         // ||b||^2
 };
 
 // Geometry of one level (interior extents, spacings, origin).
@@ -149,6 +150,94 @@ size_t tail2d_lds_bytes(const int *mx, const int *my, int nt);
 template <typename T>
 void launch_tail2d(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top, cx<T> *u_top, hipStream_t s,
                    const int *stop);
+
+// Batched fused 2D kernels (one launch for many instances).  Each job is one
+// instance's level; a launch's tiles are the jobs' tiles back to back
+// (job j owns tiles [tile0, tile0 + its tile count)), tile_job maps a tile to
+// its job.  A job whose stop flag is set is skipped.
+template <typename T>
+struct SmoothJob {
+    const cx<T> *u, *ec, *b, *q;
+    cx<T> *out;
+    Stencil<T> P;
+    int tiles_x, tile0;
+    const int *stop;
+};
+template <typename T>
+struct RRJob {
+    const cx<T> *u, *b, *q;
+    cx<T> *bc;
+    Stencil<T> P;
+    int ctiles_x, tile0;
+    const int *stop;
+};
+struct RefineJob {
+    const cd *u;
+    const cf *d;
+    const cd *b, *q;
+    cd *u_out;
+    cf *r32;
+    const SolveCtl *ctl;
+    Stencil<double> P;
+    int tiles_x, tile0, ntiles;
+    double *partial;
+    const int *stop;
+};
+template <typename T>
+struct TailJob {
+    TailParams<T> tp;
+    const cx<T> *b_top;
+    cx<T> *u_top;
+    const int *stop;
+};
+// Tile counts (and tiles per row) of the fused kernels on a level.
+template <typename T>
+int smooth2d_tiles(const LevelGeom &g, int *tiles_x);
+int resid_restrict2d_tiles(const LevelGeom &g, int *ctiles_x);
+int refine2d_tiles(const LevelGeom &g, int *tiles_x);
+template <typename T>
+void launch_smooth2d_batch(int nsweeps, bool zero, bool prol, const SmoothJob<T> *jobs, const int *tile_job,
+                           int ntiles, hipStream_t s);
+template <typename T>
+void launch_resid_restrict2d_batch(const RRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s);
+void launch_refine2d_batch(const RefineJob *jobs, const int *tile_job, int ntiles, hipStream_t s);
+template <typename T>
+void launch_tail2d_batch(const TailJob<T> *jobs, int njobs, size_t lds_bytes, hipStream_t s);
+
+// Per-instance setup of a batched solve (ffmg_stencil.hip): plane-wave
+// right-hand side, zero guess, ||b||^2, control init and the initial scaled
+// FP32 residual, in the block structure of the single-instance kernels.
+struct InitJob {
+    const cd *q;
+    cd *b, *u;
+    cf *r32;
+    SolveCtl *ctl;
+    double *partial;
+    Stencil<double> P;
+    LevelGeom g;
+    double eta[3];
+    double ar_s, ai_s;     // i k0 e^{i gamma} = ar_s + i ai_s
+    double tol, inv_sqN;   // inv_sqN = 1 / sqrt(N), formed on the host as in the single solve
+    int max_cycles;
+    int nb_norm, nb_res, tiles_x;
+};
+struct CtlJob {
+    SolveCtl *ctl;
+    const double *parts;
+    int n;
+};
+struct FinishJob {
+    const cd *t;           // the other buffer of the FP64 iterate
+    cd *u;
+    const SolveCtl *ctl;
+    size_t N;
+};
+int norm2_blocks(size_t N);
+void stencil_grid2d(const LevelGeom &g, int *nb, int *tiles_x);   // blocks and tiles per row of k_stencil2d
+void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_nb_res, hipStream_t s);
+void launch_ctl_update_batch(const CtlJob *jobs, int n, hipStream_t s);
+void launch_count_done(const CtlJob *jobs, int n, int *ndone, hipStream_t s);
+void launch_finish_batch(const FinishJob *jobs, int n, hipStream_t s);
 
 // Far field (ffmg_farfield.hip).
 struct FarFieldPlan;

@@ -61,7 +61,8 @@ _lib = None
 EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup", "mg_rhs_plane_wave",
            "mg_vcycle", "mg_solve", "farfield_map", "mg_apply", "mg_smooth", "mg_residual_norm",
            "mg_num_levels", "mg_level_shape", "mg_destroy", "mg_profile_enable", "mg_profile_read",
-           "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield"]
+           "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_solve_batched",
+           "farfield_map_batched"]
 
 
 def lib():
@@ -97,9 +98,12 @@ def lib():
     L.mg_tune_get.argtypes = [vp, ip, ctypes.POINTER(ip)]
     L.mg_tune_set.argtypes = [vp, ip, ip]
     L.mg_tune_farfield.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(dp), ip, ctypes.POINTER(ip)]
+    L.mg_solve_batched.argtypes = [vp, ip, vp, vp, dp, vp]
+    L.farfield_map_batched.argtypes = [vp, ip, vp, vp, ip, vp, vp]
     for name in ("mg_setup", "mg_rhs_plane_wave", "mg_vcycle", "mg_solve", "farfield_map", "mg_apply",
                  "mg_smooth", "mg_residual_norm", "mg_level_shape", "mg_profile_enable", "mg_profile_read",
-                 "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield"):
+                 "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_solve_batched",
+                 "farfield_map_batched"):
         getattr(L, name).restype = ip
     _lib = L
     return L
@@ -236,6 +240,51 @@ def farfield_map(h: Handle, eta, u, dirs, out=None):
 
 
 TUNE_FF_GEMM = 0
+
+
+def _etas(etas):
+    E = np.zeros((len(etas), 3), dtype=np.float64)
+    for i, e_ in enumerate(etas):
+        v = np.asarray(e_, dtype=np.float64).ravel()[:3]
+        E[i, :len(v)] = v
+    return E
+
+
+def mg_solve_batched(hs, etas, us, tol=1e-10, raise_on_noconv=True):
+    """Solve the plane-wave problems (hs[i], etas[i]) together; us[i] are
+    device tensors of each handle's interior shape (written).  Returns the
+    list of SolveInfo."""
+    n = len(hs)
+    if n == 0 or len(us) != n or len(etas) != n:
+        raise ValueError("hs, etas and us must have the same nonzero length")
+    H = (ctypes.c_void_p * n)(*[h.ptr for h in hs])
+    U = (ctypes.c_void_p * n)(*[_dev_ptr(u, "u").value for u in us])
+    E = _etas(etas)
+    infos = (SolveInfo * n)()
+    st = lib().mg_solve_batched(H, n, ctypes.c_void_p(E.ctypes.data), U, float(tol), infos)
+    if st != FFMG_OK and not (st == FFMG_ENOCONV and not raise_on_noconv):
+        hs[0]._check(st, "mg_solve_batched")
+    return list(infos)
+
+
+def farfield_map_batched(hs, etas, us, dirs, out=None):
+    """Far-field maps of the instances (hs[i], etas[i], us[i]) at the same
+    directions: a (len(hs), len(dirs)) complex array (host numpy, or `out`)."""
+    n = len(hs)
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64))
+    M = d.shape[0]
+    H = (ctypes.c_void_p * n)(*[h.ptr for h in hs])
+    U = None if us is None else (ctypes.c_void_p * n)(*[_dev_ptr(u, "u").value for u in us])
+    E = _etas(etas)
+    if out is None:
+        F = np.empty((n, M), dtype=np.complex128)
+        fp = ctypes.c_void_p(F.ctypes.data)
+    else:
+        F = out
+        fp = _dev_ptr(out, "F")
+    hs[0]._check(lib().farfield_map_batched(H, n, ctypes.c_void_p(E.ctypes.data), U, M,
+                                            ctypes.c_void_p(d.ctypes.data), fp), "farfield_map_batched")
+    return F
 
 
 def mg_tune_variants(h: Handle, tunable=TUNE_FF_GEMM) -> int:

@@ -1,0 +1,134 @@
+"""Batched persistent solve (one launch per kernel for all instances, the
+refinement step replayed as a HIP graph) against the single-instance solve
+and the oracle.
+
+Every instance of a batch must reproduce mg_solve on its handle bit for bit
+(the batched kernels keep each instance's block structure and reduction
+order); the single-instance solve is itself pinned to the oracle in
+test_gpu_parity.py, and one instance per batch is checked against the oracle
+here as well.
+"""
+import numpy as np
+import pytest
+
+from paper_1211_4461_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_4461_amd import ffmg
+    ffmg.lib()
+    return ffmg
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(np.asarray(b).ravel())
+
+
+def operators(ff, insts, **opt):
+    """One handle per (energy, grid); returns (handles per instance, cache)."""
+    cache = {}
+    hs = []
+    for w in insts:
+        key = (w.energy, w.n)
+        if key not in cache:
+            o = ff.default_options(precision=ff.FP32_IR, **opt)
+            cache[key] = ff.setup_workload(w, options=o)[0]
+        hs.append(cache[key])
+    return hs, cache
+
+
+def single(ff, h, w, tol):
+    b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+    u = torch.zeros_like(b)
+    info = ff.mg_solve(h, b, u, tol=tol)
+    return u, info
+
+
+@pytest.mark.parametrize("sizes", [(128, 256), (256,), (128, 256, 512)])
+def test_batch_equals_single_solves(ff, orc, sizes):
+    insts = W.schrodinger_batch(seed=3, n_dirs=4, sizes=sizes, M=24)
+    hs, cache = operators(ff, insts)
+    us = [torch.full(w.shape, 7.0, dtype=torch.complex128, device="cuda") for w in insts]   # overwritten
+    infos = ff.mg_solve_batched(hs, [w.eta for w in insts], us, tol=1e-10)
+    for i, w in enumerate(insts):
+        u1, i1 = single(ff, hs[i], w, 1e-10)
+        torch.cuda.synchronize()
+        assert infos[i].status == 0 and infos[i].cycles == i1.cycles, (i, infos[i].cycles, i1.cycles)
+        assert infos[i].rel_residual == i1.rel_residual and infos[i].rel_residual <= 1e-10
+        assert torch.equal(us[i], u1), i
+    # one instance against the oracle's converged solution
+    w = insts[-1]
+    g = orc.Grid(2, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    uo, st, k, _ = orc.Multigrid(g, w.gamma, kappa).solve(b, tol=1e-13)
+    assert st == 0
+    assert rel(us[-1].cpu().numpy(), uo) < 1e-8
+
+
+def test_batch_reuse_and_far_fields(ff, orc):
+    """A second call with new directions reuses the graph; batched far fields
+    equal per-instance maps; a different handle list rebuilds the batch."""
+    insts = W.schrodinger_batch(seed=5, n_dirs=3, sizes=(128, 256), M=30)
+    hs, cache = operators(ff, insts, ff_precision=2)
+    us = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for w in insts]
+    etas = [w.eta for w in insts]
+    ff.mg_solve_batched(hs, etas, us)
+    etas2 = [-np.asarray(e) for e in etas]
+    infos = ff.mg_solve_batched(hs, etas2, us)
+    for i, w in enumerate(insts):
+        u1, i1 = single(ff, hs[i], W.Workload(w.name, 2, w.n, w.lo, w.hi, w.gamma, w.kind, w.k0, w.energy, w.coef,
+                                              etas2[i], w.dirs), 1e-10)
+        torch.cuda.synchronize()
+        assert infos[i].cycles == i1.cycles and torch.equal(us[i], u1)
+    dirs = insts[0].dirs
+    F = ff.farfield_map_batched(hs, etas2, us, dirs)
+    for i in range(len(insts)):
+        np.testing.assert_array_equal(F[i], ff.farfield_map(hs[i], etas2[i], us[i], dirs))
+    Fd = torch.empty((len(insts), len(dirs)), dtype=torch.complex128, device="cuda")
+    ff.farfield_map_batched(hs, etas2, us, dirs, out=Fd)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(Fd.cpu().numpy(), F)
+    # a sub-list of the handles: rebuilt workspace, same answers
+    sub = [0, 2, 4]
+    us2 = [torch.empty_like(us[i]) for i in sub]
+    ff.mg_solve_batched([hs[i] for i in sub], [etas2[i] for i in sub], us2)
+    torch.cuda.synchronize()
+    for j, i in enumerate(sub):
+        assert torch.equal(us2[j], us[i])
+
+
+def test_batch_reports_non_convergence(ff, orc):
+    """An instance whose handle allows too few cycles ends in ENOCONV with its
+    info filled; the others converge as alone."""
+    insts = W.schrodinger_batch(seed=3, n_dirs=2, sizes=(128,), M=8)
+    o_ok = ff.default_options(precision=ff.FP32_IR)
+    o_short = ff.default_options(precision=ff.FP32_IR, max_cycles=2)
+    h_ok = ff.setup_workload(insts[0], options=o_ok)[0]
+    h_short = ff.setup_workload(insts[0], options=o_short)[0]
+    hs = [h_ok, h_short]
+    us = [torch.empty(insts[0].shape, dtype=torch.complex128, device="cuda") for _ in hs]
+    infos = ff.mg_solve_batched(hs, [insts[0].eta, insts[1].eta], us, raise_on_noconv=False)
+    assert infos[0].status == 0 and infos[1].status == ff.FFMG_ENOCONV and infos[1].cycles == 2
+    with pytest.raises(ff.FfmgError) as e:
+        ff.mg_solve_batched(hs, [insts[0].eta, insts[1].eta], us)
+    assert e.value.status == ff.FFMG_ENOCONV
+
+
+def test_batch_rejects_unsupported_handles(ff, orc):
+    w = W.schrodinger_batch(seed=3, n_dirs=1, sizes=(128,), M=8)[0]
+    h64 = ff.setup_workload(w, options=ff.default_options())[0]
+    hir = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR))[0]
+    hnu = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, nu1=1, nu2=1))[0]
+    u = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for _ in range(2)]
+    for hs in ([h64, hir], [hir, hnu]):
+        with pytest.raises(ff.FfmgError) as e:
+            ff.mg_solve_batched(hs, [w.eta, w.eta], u)
+        assert e.value.status == ff.FFMG_EINVAL
