@@ -13,14 +13,18 @@ replacement, defined here (not in the paper):
 
   smoothing step      u <- u + s h^2 N(r / s, kappa h^2),  r = b - A u,
                       s = RMS of r over the grid, kappa = k0^2 + q
-  network N           x0 = (r~, kappa~)                 (2 complex channels)
-                      x1 = CReLU(W1 * x0)                (16 channels)
-                      x2 = CReLU(W2 * x1)                (16 channels)
+  network N           inputs r~ = r / s, kappa~ = kappa h^2
+                      a  = W1[:, :, 0] * r~,  m = W1[:, :, 1] * kappa~
+                      x1 = a (1 + m)                     (16 channels)
+                      x2 = W2 * x1                       (16 channels)
                       N  = W3 * x2                       (1 channel)
+                      N is complex-linear in r~ (a learned stencil of radius
+                      3 whose weights the gate 1 + m adapts to the local
+                      coefficient), so the smoothing step is a linear
+                      iteration and N(0, kappa~) = 0.
   3x3 convolution     (W * x)_o(p) = sum_t sum_i W[t, o, i] x_i(p + d_t),
                       tap t = 3 (dy + 1) + (dx + 1), d_t = (dy, dx), zero
                       outside the array (the Dirichlet boundary)
-  CReLU               max(Re z, 0) + i max(Im z, 0)
   loss (one patch)    mean over the masked points of |L5 (e~ - N)|^2,
                       e~ = e / (s h^2), L5 d = 4 d - (the 4 neighbours),
                       i.e. the high-frequency part of the error left after
@@ -97,26 +101,18 @@ def conv_backward(W, x, g):
     return dW, gx
 
 
-def crelu(a):
-    return np.maximum(a.real, 0.0) + 1j * np.maximum(a.imag, 0.0)
-
-
-def crelu_backward(a, g):
-    return g.real * (a.real > 0) + 1j * g.imag * (a.imag > 0)
-
-
-def forward(Ws, x0, quant=False):
-    """Activations (x0, a1, x1, a2, x2, y).  quant: weights and the layer
+def forward(Ws, rt, kt, quant=False):
+    """Activations (x0r, x0k, a, m, x1, x2, y).  quant: weights and the layer
     inputs rounded to BF16 (the GPU kernels' storage precision)."""
     W1, W2, W3 = (bf16(W) for W in Ws) if quant else Ws
     q = bf16 if quant else (lambda z: z)
-    x0 = q(x0)
-    a1 = conv(W1, x0)
-    x1 = q(crelu(a1))
-    a2 = conv(W2, x1)
-    x2 = q(crelu(a2))
+    x0r, x0k = q(rt)[None], q(kt)[None]
+    a = conv(W1[:, :, 0:1], x0r)
+    m = conv(W1[:, :, 1:2], x0k)
+    x1 = q(a * (1.0 + m))
+    x2 = q(conv(W2, x1))
     y = conv(W3, x2)[0]
-    return x0, a1, x1, a2, x2, y
+    return x0r, x0k, a, m, x1, x2, y
 
 
 def lap5(d):
@@ -134,13 +130,17 @@ def loss_and_grad_y(y, et, mask):
 
 def loss_and_grads(Ws, rt, kt, et, mask, quant=False):
     """Loss of one patch and dL/dW for W1, W2, W3 (analytic backward)."""
-    x0 = np.stack([rt, kt])
-    x0, a1, x1, a2, x2, y = forward(Ws, x0, quant)
+    x0r, x0k, a, m, x1, x2, y = forward(Ws, rt, kt, quant)
     W1, W2, W3 = (bf16(W) for W in Ws) if quant else Ws
     L, gy = loss_and_grad_y(y, et, mask)
     dW3, gx2 = conv_backward(W3, x2, gy[None])
-    dW2, gx1 = conv_backward(W2, x1, crelu_backward(a2, gx2))
-    dW1, _ = conv_backward(W1, x0, crelu_backward(a1, gx1))
+    dW2, gx1 = conv_backward(W2, x1, gx2)
+    # x1 = a c with c = 1 + m: g_a = conj(c) g_x1, g_m = conj(a) g_x1
+    ga = np.conj(1.0 + m) * gx1
+    gm = np.conj(a) * gx1
+    dW1a, _ = conv_backward(W1[:, :, 0:1], x0r, ga)
+    dW1m, _ = conv_backward(W1[:, :, 1:2], x0k, gm)
+    dW1 = np.concatenate([dW1a, dW1m], axis=2)
     return L, [dW1, dW2, dW3]
 
 
@@ -170,5 +170,4 @@ def smooth_step(Ws, r, kappa_h2, h2, quant=False):
     s = float(np.sqrt(np.mean(np.abs(r) ** 2)))
     if s == 0.0:
         return np.zeros_like(r)
-    x0 = np.stack([r / s, kappa_h2])
-    return s * h2 * forward(Ws, x0, quant)[-1]
+    return s * h2 * forward(Ws, r / s, kappa_h2, quant)[-1]

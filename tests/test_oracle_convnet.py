@@ -61,16 +61,26 @@ def test_tap_orientation_brute_force():
 
 
 def jacobi_weights(c):
-    """Weights with N(r~, kappa~) = c r~ exactly: layer 1 forms r~ and -r~,
-    CReLU keeps their positive parts, layer 2 passes them on, layer 3 takes
-    c (x_0 - x_1) = c r~."""
+    """Weights with N(r~, kappa~) = c r~ exactly: the centre taps pass r~
+    through channel 0 (gate 1 + 0) and layer 3 scales it by c."""
     W1 = np.zeros(cn.SHAPES[0], dtype=np.complex128)
     W2 = np.zeros(cn.SHAPES[1], dtype=np.complex128)
     W3 = np.zeros(cn.SHAPES[2], dtype=np.complex128)
-    W1[4, 0, 0], W1[4, 1, 0] = 1.0, -1.0
-    W2[4, 0, 0], W2[4, 1, 1] = 1.0, 1.0
-    W3[4, 0, 0], W3[4, 0, 1] = c, -c
+    W1[4, 0, 0] = 1.0
+    W2[4, 0, 0] = 1.0
+    W3[4, 0, 0] = c
     return [W1, W2, W3]
+
+
+def test_network_is_complex_linear_in_the_residual():
+    """N(alpha r~ + beta r2~, kappa~) = alpha N(r~) + beta N(r2~) for complex
+    alpha, beta, and N(0, kappa~) = 0."""
+    Ws = cn.init_weights(21)
+    r1, r2, k = rnd(1, (9, 10)), rnd(2, (9, 10)), rnd(3, (9, 10)) * 0.2
+    al, be = 0.3 - 1.7j, -2.1 + 0.4j
+    N = lambda r: cn.forward(Ws, r, k)[-1]
+    np.testing.assert_allclose(N(al * r1 + be * r2), al * N(r1) + be * N(r2), rtol=1e-12, atol=1e-12)
+    assert np.all(N(np.zeros_like(r1)) == 0)
 
 
 def test_linear_construction_is_weighted_jacobi():
