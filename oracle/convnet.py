@@ -25,10 +25,13 @@ replacement, defined here (not in the paper):
   3x3 convolution     (W * x)_o(p) = sum_t sum_i W[t, o, i] x_i(p + d_t),
                       tap t = 3 (dy + 1) + (dx + 1), d_t = (dy, dx), zero
                       outside the array (the Dirichlet boundary)
-  loss (one patch)    mean over the masked points of |L5 (e~ - N)|^2,
-                      e~ = e / (s h^2), L5 d = 4 d - (the 4 neighbours),
-                      i.e. the high-frequency part of the error left after
-                      the smoothing step (the part a smoother must remove).
+  loss (one patch)    mean over the masked points of
+                      |L5 (e~ - N)|^2 + ALPHA |e~ - N|^2,
+                      e~ = e / (s h^2), L5 d = 4 d - (the 4 neighbours):
+                      mainly the high-frequency part of the error left after
+                      the smoothing step (the part a smoother must remove);
+                      the unweighted term keeps the step from amplifying
+                      smooth error, which L5 does not see.
 
 Arrays are (channels, ny, nx), x fastest.  Complex gradients follow the
 convention g = dL/dRe + i dL/dIm; then for y = W x:
@@ -39,6 +42,7 @@ from __future__ import annotations
 import numpy as np
 
 C_IN, C_HID, C_OUT = 2, 16, 1
+ALPHA = 1.0
 SHAPES = ((9, C_HID, C_IN), (9, C_HID, C_HID), (9, C_OUT, C_HID))
 TAPS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
 
@@ -121,10 +125,11 @@ def lap5(d):
 
 
 def loss_and_grad_y(y, et, mask):
-    z = lap5(et - y) * mask
+    d = et - y
+    z = lap5(d) * mask
     cnt = float(mask.sum())
-    L = float(np.sum(np.abs(z) ** 2) / cnt)
-    gy = -lap5(2.0 * z / cnt)
+    L = float((np.sum(np.abs(z) ** 2) + ALPHA * np.sum(np.abs(d) ** 2 * mask)) / cnt)
+    gy = -(lap5(2.0 * z) + 2.0 * ALPHA * mask * d) / cnt
     return L, gy
 
 

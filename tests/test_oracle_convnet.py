@@ -106,7 +106,7 @@ def test_lap5_sine_eigenvalues():
     np.testing.assert_allclose(cn.lap5(d), lam * d, rtol=0, atol=1e-13)
     mask = cn.interior_mask(ny, nx, border=2)
     L, gy = cn.loss_and_grad_y(np.zeros_like(d), d, mask)
-    assert abs(L - lam ** 2 * np.sum(np.abs(d) ** 2 * mask) / mask.sum()) < 1e-12
+    assert abs(L - (lam ** 2 + cn.ALPHA) * np.sum(np.abs(d) ** 2 * mask) / mask.sum()) < 1e-12
 
 
 def test_adam_first_step_is_sign_descent():
