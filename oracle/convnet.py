@@ -25,13 +25,15 @@ replacement, defined here (not in the paper):
   3x3 convolution     (W * x)_o(p) = sum_t sum_i W[t, o, i] x_i(p + d_t),
                       tap t = 3 (dy + 1) + (dx + 1), d_t = (dy, dx), zero
                       outside the array (the Dirichlet boundary)
-  loss (one patch)    mean over the masked points of
-                      |L5 (e~ - N)|^2 + ALPHA |e~ - N|^2,
-                      e~ = e / (s h^2), L5 d = 4 d - (the 4 neighbours):
-                      mainly the high-frequency part of the error left after
-                      the smoothing step (the part a smoother must remove);
-                      the unweighted term keeps the step from amplifying
-                      smooth error, which L5 does not see.
+  loss (one patch)    mean over the masked points of |L5 (e~ - N)|^2
+                      + ALPHA max(0, ||e~ - N||^2 / ||e~||^2 - 1),
+                      e~ = e / (s h^2), L5 d = 4 d - (the 4 neighbours),
+                      norms over the masked points: the high-frequency part
+                      of the error left after the smoothing step (the part a
+                      smoother must remove), plus a penalty on any growth of
+                      the patch's error, which keeps the step from amplifying
+                      smooth error (L5 does not see it) without asking the
+                      network to remove it.
 
 Arrays are (channels, ny, nx), x fastest.  Complex gradients follow the
 convention g = dL/dRe + i dL/dIm; then for y = W x:
@@ -128,8 +130,13 @@ def loss_and_grad_y(y, et, mask):
     d = et - y
     z = lap5(d) * mask
     cnt = float(mask.sum())
-    L = float((np.sum(np.abs(z) ** 2) + ALPHA * np.sum(np.abs(d) ** 2 * mask)) / cnt)
-    gy = -(lap5(2.0 * z) + 2.0 * ALPHA * mask * d) / cnt
+    E = float(np.sum(np.abs(et) ** 2 * mask))
+    D = float(np.sum(np.abs(d) ** 2 * mask))
+    L = float(np.sum(np.abs(z) ** 2) / cnt)
+    gy = -lap5(2.0 * z) / cnt
+    if E > 0.0 and D > E:
+        L += ALPHA * (D / E - 1.0)
+        gy = gy - 2.0 * ALPHA * mask * d / E
     return L, gy
 
 

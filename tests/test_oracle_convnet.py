@@ -45,6 +45,31 @@ def test_gradients_match_central_differences():
     assert worst < 1e-6, worst
 
 
+def test_gradients_with_growth_penalty_match_central_differences():
+    """Large weights make the step amplify the patch error, so the growth
+    penalty is active."""
+    ny, nx = 10, 12
+    Ws = [W * 3.0 for W in cn.init_weights(4)]
+    rt, kt, et = rnd(1, (ny, nx)), rnd(2, (ny, nx)) * 0.3, rnd(4, (ny, nx)) * 0.01
+    mask = cn.interior_mask(ny, nx, border=2)
+    x = cn.forward(Ws, rt, kt)
+    d = et - x[-1]
+    assert np.sum(np.abs(d) ** 2 * mask) > np.sum(np.abs(et) ** 2 * mask)
+    L0, grads = cn.loss_and_grads(Ws, rt, kt, et, mask)
+    rng = np.random.default_rng(10)
+    eps = 1e-6
+    for li, W in enumerate(Ws):
+        gscale = np.max(np.abs(grads[li]))
+        for _ in range(6):
+            idx = tuple(rng.integers(0, s) for s in W.shape)
+            Wp = [w.copy() for w in Ws]
+            Wm = [w.copy() for w in Ws]
+            Wp[li][idx] += eps
+            Wm[li][idx] -= eps
+            fd = (cn.loss_and_grads(Wp, rt, kt, et, mask)[0] - cn.loss_and_grads(Wm, rt, kt, et, mask)[0]) / (2 * eps)
+            assert abs(fd - grads[li][idx].real) < 1e-5 * gscale
+
+
 def test_tap_orientation_brute_force():
     ny, nx = 5, 6
     x = rnd(5, (2, ny, nx))
@@ -106,7 +131,10 @@ def test_lap5_sine_eigenvalues():
     np.testing.assert_allclose(cn.lap5(d), lam * d, rtol=0, atol=1e-13)
     mask = cn.interior_mask(ny, nx, border=2)
     L, gy = cn.loss_and_grad_y(np.zeros_like(d), d, mask)
-    assert abs(L - (lam ** 2 + cn.ALPHA) * np.sum(np.abs(d) ** 2 * mask) / mask.sum()) < 1e-12
+    assert abs(L - lam ** 2 * np.sum(np.abs(d) ** 2 * mask) / mask.sum()) < 1e-12
+    # an output that doubles the error: the growth penalty adds ALPHA (4 - 1)
+    L2, _ = cn.loss_and_grad_y(-d, d, mask)
+    assert abs(L2 - (4 * lam ** 2 * np.sum(np.abs(d) ** 2 * mask) / mask.sum() + 3 * cn.ALPHA)) < 1e-10
 
 
 def test_adam_first_step_is_sign_descent():
