@@ -92,6 +92,12 @@ typedef struct ffmg_options {
                              without the LDS tail                              */
     int inner_cycles;     /* FP32_IR: V-cycles per FP64 refinement step
                              (0 = default 2)                                   */
+    int nu_coarse;        /* sweeps before and after the coarse correction on
+                             the levels below the finest (0 = nu1 / nu2)       */
+    int learned_levels;   /* FFMG_SMOOTH_LEARNED: bit l = level l smooths with
+                             the network (0 = the finest level only; levels of
+                             the LDS tail never do); the others use weighted
+                             Jacobi                                            */
     void *stream;         /* hipStream_t; NULL = the null stream               */
 } ffmg_options;
 
@@ -179,11 +185,56 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
 ffmg_status farfield_map_batched(ffmg_handle *const *hs, int count, const double *etas, void *const *u, int n_dirs,
                                  const double *dirs, void *F);
 
+/* ---- Learned smoother (a replacement of the weighted-Jacobi sweeps of
+ * the finest level; the paper smooths with weighted Jacobi, Sec. 4).  One
+ * smoothing step is u += s h^2 N(r / s, kappa h^2), r = b - A u, s = RMS(r),
+ * where N is a three-layer 3x3 complex convolutional network with 2 -> 16 ->
+ * 16 -> 1 complex channels, CReLU activations and no biases, stored in BF16
+ * and accumulated in FP32.  Weights: FFMG_NET_WEIGHTS complex values as
+ * interleaved (re, im) floats: W1 [9][16][2], W2 [9][16][16], W3 [9][1][16],
+ * indexed (tap, output channel, input channel), tap 3 (dy + 1) + (dx + 1)
+ * reading the point (y + dy, x + dx).
+ *
+ * Training patches: count patches of 32 x 32 points, DEVICE complex64
+ * [count][32][32] each: the scaled residual r / s, kappa h^2 and the scaled
+ * error e / (s h^2).  The loss of a patch is the mean over its points at
+ * least `border` from the patch edge of |L5 (e~ - N)|^2 (L5 the 5-point
+ * Laplacian stencil), the minibatch loss the mean over patches.
+ * ml_loss_grad returns the loss and its gradient (host, 2 * FFMG_NET_WEIGHTS
+ * floats, may be NULL) at the current weights; ml_train_step also applies
+ * one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) to the FP32 master
+ * weights and, if loss is not NULL, returns the minibatch loss (before the
+ * step; this synchronises).  The network object owns its device memory and
+ * works on the stream given at creation. */
+#define FFMG_NET_WEIGHTS 2736
+typedef struct ffmg_net ffmg_net;
+ffmg_status ml_net_create(const float *w, void *stream, ffmg_net **out);
+ffmg_status ml_net_set_weights(ffmg_net *net, const float *w);   /* also resets the Adam state */
+ffmg_status ml_net_get_weights(ffmg_net *net, float *w);
+ffmg_status ml_loss_grad(ffmg_net *net, const void *rt, const void *kt, const void *et, int count, int border,
+                         float *loss, float *grad);
+ffmg_status ml_train_step(ffmg_net *net, const void *rt, const void *kt, const void *et, int count, int border,
+                          float lr, float *loss);
+const char *ml_net_last_error(const ffmg_net *net);
+void ml_net_destroy(ffmg_net *net);
+
 /* Au = A u (the operator of eq. csg), DEVICE complex128[N] each. */
 ffmg_status mg_apply(ffmg_handle *h, const void *u, void *Au);
 
 /* One omega-Jacobi sweep u_out = u + omega D^{-1} (b - A u), out of place. */
 ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out);
+
+/* One learned smoothing step on the finest level, in place on u (DEVICE
+ * complex128[N]): u += s h^2 N(r / s, kappa h^2) with r = b - A u and
+ * s = RMS(r) (N is linear in r, so this is h^2 N(r, kappa h^2)).  The handle must use FFMG_SMOOTH_LEARNED on the finest level.
+ * With that smoother the levels selected by learned_levels take nu1 / nu2
+ * (nu_coarse) such steps instead of Jacobi sweeps, and mg_solve
+ * compares each batch of cycles with the convergence factor of the Jacobi
+ * V-cycle on the same operator (measured at setup, mg_jacobi_factor): a
+ * learned cycle that reduces the residual less makes the solve continue
+ * with Jacobi (info.fell_back = 1). */
+ffmg_status mg_learned_smooth(ffmg_handle *h, const void *b, void *u);
+double mg_jacobi_factor(const ffmg_handle *h);
 
 /* ||b - A u||_2 (FP64 accumulation) into *rnorm (host). */
 ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, double *rnorm);

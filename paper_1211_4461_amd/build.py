@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libffmg.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["ffmg_stencil.hip", "ffmg_fused2d.hip", "ffmg_farfield.hip", "ffmg_capi.hip", "ffmg_batch.hip"]
+SOURCES = ["ffmg_stencil.hip", "ffmg_fused2d.hip", "ffmg_farfield.hip", "ffmg_capi.hip", "ffmg_batch.hip", "ffmg_learned.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
@@ -46,7 +46,7 @@ def build(verbose: bool = False) -> str:
     """Compile every HIP source for gfx950 and link libffmg.so (always
     recompiles)."""
     os.makedirs(OBJDIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(5, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs

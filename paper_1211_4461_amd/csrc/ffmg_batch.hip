@@ -299,6 +299,7 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
                              "instance %d: batched solves need 2D operators set up with precision FP32_IR and the "
                              "fused kernels (tile_config 0)", i));
         if (o.nu1 != B.nu1 || o.nu2 != B.nu2 || o.nu1 < 1 || o.nu2 < 1 ||
+            (o.nu_coarse != 0 && (o.nu_coarse != o.nu1 || o.nu_coarse != o.nu2)) ||
             (o.inner_cycles > 0 ? o.inner_cycles : 2) != B.inner || o.smoother != FFMG_SMOOTH_JACOBI)
             return bail(fail(h0, FFMG_EINVAL, "instance %d: every operator needs the same nu1, nu2 >= 1 and inner "
                                               "cycles", i));

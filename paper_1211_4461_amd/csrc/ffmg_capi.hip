@@ -13,6 +13,7 @@
 #include <atomic>
 
 #include "ffmg_handle.hpp"
+#include "ffmg_learned.hpp"
 
 using namespace ffmg;
 
@@ -63,6 +64,11 @@ double exponent_budget(const ffmg_handle *h)
     }
     return h->k0 * sin(h->prob.gamma) * sqrt(r2);
 }
+
+// Smoothing sweeps on level l: nu1 / nu2 on the finest level, nu_coarse
+// (when set) on the coarser ones.
+int nu_pre(const ffmg_handle *h, int l) { return (l > 0 && h->opt.nu_coarse > 0) ? h->opt.nu_coarse : h->opt.nu1; }
+int nu_post(const ffmg_handle *h, int l) { return (l > 0 && h->opt.nu_coarse > 0) ? h->opt.nu_coarse : h->opt.nu2; }
 
 }  // namespace ffmg
 
@@ -194,9 +200,9 @@ void vcycle_fused2d(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_g
     using LP = LvlPtr<T>;
     Level &lv = h->L[l];
     Level &lc = h->L[l + 1];
-    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
     cx<T> *t = LP::t(lv), *scratch = LP::r(lv);
     cx<T> *cur = u;
+    const int nu1 = nu_pre(h, l), nu2 = nu_post(h, l);
     if (nu1 > 0) {
         smooth_chain2d<T>(h, lv, b, u, t, scratch, nu1, zero_guess, nullptr, PROF_PRE, stop);
         cur = t;
@@ -243,11 +249,23 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
     if (!p->coef) return fail(tmp, FFMG_EINVAL, "coef is null");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 + o->nu2 < 1 || o->nu1 > 64 || o->nu2 > 64)
         return fail(tmp, FFMG_EINVAL, "need 0 <= nu1, nu2 <= 64 and nu1 + nu2 >= 1");
+    if (o->nu_coarse < 0 || o->nu_coarse > 64) return fail(tmp, FFMG_EINVAL, "nu_coarse must lie in [0, 64]");
+    if (o->learned_levels < 0) return fail(tmp, FFMG_EINVAL, "learned_levels must be a bit mask >= 0");
     if (!(o->omega > 0.0 && o->omega <= 1.0)) return fail(tmp, FFMG_EINVAL, "omega must lie in (0, 1]");
     if (o->max_cycles < 1) return fail(tmp, FFMG_EINVAL, "max_cycles must be >= 1");
     if (o->precision != FFMG_FP64 && o->precision != FFMG_FP32_IR)
         return fail(tmp, FFMG_EINVAL, "unknown precision %d", o->precision);
-    if (o->smoother != FFMG_SMOOTH_JACOBI) return fail(tmp, FFMG_EINVAL, "unsupported smoother %d", o->smoother);
+    if (o->smoother == FFMG_SMOOTH_LEARNED) {
+        if (!o->smoother_weights) return fail(tmp, FFMG_EINVAL, "the learned smoother needs smoother_weights");
+        if (p->dim != 2 || o->precision != FFMG_FP64)
+            return fail(tmp, FFMG_EINVAL, "the learned smoother runs in 2D FP64 V-cycles");
+        double hx = (p->hi[0] - p->lo[0]) / (double)p->n[0], hy = (p->hi[1] - p->lo[1]) / (double)p->n[1];
+        if (fabs(hx - hy) > 1e-12 * hx) return fail(tmp, FFMG_EINVAL, "the learned smoother needs square cells");
+        for (int k = 0; k < 2 * FFMG_NET_WEIGHTS; ++k)
+            if (!isfinite(o->smoother_weights[k])) return fail(tmp, FFMG_ENAN, "smoother weight %d is not finite", k);
+    } else if (o->smoother != FFMG_SMOOTH_JACOBI) {
+        return fail(tmp, FFMG_EINVAL, "unknown smoother %d", o->smoother);
+    }
     if (o->ff_precision != FFMG_FF_FP64 && o->ff_precision != FFMG_FF_BF16X3 && o->ff_precision != FFMG_FF_BF16X6)
         return fail(tmp, FFMG_EINVAL, "unknown far-field precision %d", o->ff_precision);
     if (o->tile_config < 0 || o->tile_config > 2) return fail(tmp, FFMG_EINVAL, "unknown tile_config");
@@ -278,8 +296,8 @@ void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
     int nt = nl - top;
     if (nt < 2) return;   // the coarsest level alone is one matrix-vector product
     tp.nt = nt;
-    tp.nu1 = h->opt.nu1;
-    tp.nu2 = h->opt.nu2;
+    tp.nu1 = nu_pre(h, 1);     // tail levels are coarse levels
+    tp.nu2 = nu_post(h, 1);
     tp.aug = h->aug;
     tp.nc = h->nc;
     int off = 0;
@@ -294,6 +312,51 @@ void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
         off += 3 * t.mx * t.my;
     }
     lds = bytes;
+}
+
+// The learned smoother: weight fragments, kappa h^2 on the finest level, and
+// the convergence factor of the Jacobi V-cycle on this operator (measured on
+// a pseudo-random right-hand side), which the learned cycle has to beat.
+ffmg_status setup_learned(ffmg_handle *h)
+{
+    Level &l0 = h->L[0];
+    const size_t N = l0.g.N();
+    std::vector<unsigned short> frag(net_mfma_frag_count());
+    pack_net_mfma(h->opt.smoother_weights, frag.data());
+    TRY(dalloc(h, &h->d_wfrag, frag.size() * sizeof(unsigned short)));
+    HIPCHK(h, hipMemcpy(h->d_wfrag, frag.data(), frag.size() * sizeof(unsigned short), hipMemcpyHostToDevice));
+    h->d_kh2.assign(h->L.size(), nullptr);
+    for (size_t l = 0; l < h->L.size(); ++l) {
+        if (!learned_level(h, (int)l)) continue;
+        Level &lv = h->L[l];
+        TRY(dalloc(h, &h->d_kh2[l], lv.g.N() * sizeof(unsigned)));
+        launch_kappa_h2(lv.q, h->k02, lv.g.h[0] * lv.g.h[1], lv.g.N(), h->d_kh2[l], h->stream);
+    }
+    HIPCHK(h, hipGetLastError());
+    // reference: Jacobi V-cycles from u = 0 on a pseudo-random b
+    cd *b = nullptr, *u = nullptr;
+    HIPCHK(h, hipMalloc(&b, N * sizeof(cd)));
+    if (hipMalloc(&u, N * sizeof(cd)) != hipSuccess) {
+        (void)hipFree(b);
+        return fail(h, FFMG_ENOMEM, "hipMalloc failed");
+    }
+    launch_hash_fill(b, N, 0x5eed5eedull, h->stream);
+    launch_zero<double>(u, N, h->stream, nullptr);
+    // asymptotic factor: the mean reduction of cycles 7 .. 12
+    h->learned_on = false;
+    double r6 = 0.0, r12 = 0.0;
+    ffmg_status st = FFMG_OK;
+    for (int c = 1; c <= 12 && st == FFMG_OK; ++c) {
+        vcycle<double>(h, 0, b, u, c == 1, nullptr);
+        if (c == 6) st = resid_norm(h, b, u, &r6);
+        if (c == 12 && st == FFMG_OK) st = resid_norm(h, b, u, &r12);
+    }
+    (void)hipFree(b);
+    (void)hipFree(u);
+    TRY(st);
+    h->rho_jacobi = (r6 > 0.0) ? pow(r12 / r6, 1.0 / 6.0) : 0.0;
+    h->learned_on = true;
+    return FFMG_OK;
 }
 
 ffmg_status setup_impl(ffmg_handle *h)
@@ -374,6 +437,7 @@ ffmg_status setup_impl(ffmg_handle *h)
     if (info != 0) return fail(h, FFMG_EINVAL, "coarsest operator is singular (zero pivot in column %d)", info - 1);
     plan_tail<double>(h, h->tail64, h->tail_lds[0]);
     if (ir) plan_tail<float>(h, h->tail32, h->tail_lds[1]);
+    if (h->opt.smoother == FFMG_SMOOTH_LEARNED) TRY(setup_learned(h));
     return FFMG_OK;
 }
 
@@ -408,6 +472,50 @@ void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *st
 
 namespace ffmg {
 
+// Levels that smooth with the network: bit l of learned_levels (0: the
+// finest level only), never the levels of the LDS tail or the coarsest.
+bool learned_level(const ffmg_handle *h, int l)
+{
+    if (h->opt.smoother != FFMG_SMOOTH_LEARNED) return false;
+    const int nl = (int)h->L.size();
+    const int first_tail = (h->opt.tile_config == TILE_FUSED && h->tail64.nt > 0) ? nl - h->tail64.nt : nl - 1;
+    if (l >= first_tail) return false;
+    const int mask = h->opt.learned_levels ? h->opt.learned_levels : 1;
+    return l < 31 && ((mask >> l) & 1);
+}
+
+// One learned smoothing step on level l: r = b - A u (FP64), then
+// u += h^2 N(r, kappa h^2).
+void learned_step(ffmg_handle *h, int l, const cd *b, cd *u, const int *stop)
+{
+    Level &lv = h->L[l];
+    launch_stencil<double>(MODE_RESID, lv.g, lv.P64, u, b, lv.q, lv.r, (double *)nullptr, h->stream, false, stop);
+    launch_net_apply(lv.r, h->d_kh2[l], u, lv.g.m[0], lv.g.m[1], h->d_wfrag, lv.g.h[0] * lv.g.h[1], h->stream,
+                     stop);
+}
+
+// One level of a V-cycle with the learned smoother: nu learned steps,
+// residual + restriction, the coarse correction, interpolation, nu learned
+// steps.
+template <typename T>
+void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop);
+
+static void vcycle_learned(ffmg_handle *h, int l, const cd *b, cd *u, bool zero_guess, const int *stop)
+{
+    Level &lv = h->L[l];
+    Level &lc = h->L[l + 1];
+    if (zero_guess) launch_zero<double>(u, lv.g.N(), h->stream, stop);
+    for (int s = 0; s < nu_pre(h, l); ++s) learned_step(h, l, b, u, stop);
+    launch_resid_restrict2d<double>(lv.g, lv.P64, u, b, lv.q, lc.b, h->stream, stop);
+    const TailParams<double> &tp = h->tail64;
+    if (h->opt.tile_config == TILE_FUSED && tp.nt > 0 && l + 1 == (int)h->L.size() - tp.nt)
+        launch_tail2d<double>(tp, h->tail_lds[0], lc.b, lc.u, h->stream, stop);
+    else
+        vcycle<double>(h, l + 1, lc.b, lc.u, true, stop);
+    launch_prolong_add<double>(lv.g, lc.u, u, h->stream, stop);
+    for (int s = 0; s < nu_post(h, l); ++s) learned_step(h, l, b, u, stop);
+}
+
 template <typename T>
 void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop)
 {
@@ -418,11 +526,17 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
         launch_coarse_apply<T>(h->aug, h->nc, b, u, h->stream, stop);
         return;
     }
+    if constexpr (sizeof(T) == 8) {
+        if (h->learned_on && learned_level(h, l)) {
+            vcycle_learned(h, l, b, u, zero_guess, stop);
+            return;
+        }
+    }
     if (lv.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE) {
         vcycle_fused2d<T>(h, l, b, u, zero_guess, stop);
         return;
     }
-    const int nu1 = h->opt.nu1, nu2 = h->opt.nu2;
+    const int nu1 = nu_pre(h, l), nu2 = nu_post(h, l);
     if (nu1 > 0) smooth<T>(h, lv, b, u, nu1, zero_guess, stop);
     else if (zero_guess) launch_zero<T>(u, lv.g.N(), h->stream, stop);
     launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
@@ -581,6 +695,18 @@ ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out)
     return FFMG_OK;
 }
 
+ffmg_status mg_learned_smooth(ffmg_handle *h, const void *b, void *u)
+{
+    if (!h || !b || !u) return fail(h, FFMG_EINVAL, "null argument");
+    if (h->opt.smoother != FFMG_SMOOTH_LEARNED) return fail(h, FFMG_EINVAL, "the handle has no learned smoother");
+    if (!learned_level(h, 0)) return fail(h, FFMG_EINVAL, "the finest level does not use the learned smoother");
+    learned_step(h, 0, (const cd *)b, (cd *)u, nullptr);
+    HIPCHK(h, hipGetLastError());
+    return FFMG_OK;
+}
+
+double mg_jacobi_factor(const ffmg_handle *h) { return h ? h->rho_jacobi : 0.0; }
+
 ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, double *rnorm)
 {
     if (!h || !b || !u || !rnorm) return fail(h, FFMG_EINVAL, "null argument");
@@ -639,11 +765,22 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
         launch_resid_to_f32_ctl(l0.g, l0.P64, u, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, nullptr);
         launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
     }
-    // cycles in batches; the control block decides on the device
+    // cycles in batches; the control block decides on the device.  With the
+    // learned smoother the first cycle runs alone (its reduction from u = 0
+    // is a transient) and the mean reduction factor of every later batch of
+    // two cycles is compared with the asymptotic factor of the Jacobi V-cycle
+    // (measured at setup): two batches in a row more than 10% worse, or
+    // residual growth, switch the rest of the solve to Jacobi; a non-finite
+    // iterate or a residual ten times the initial one restarts it with Jacobi
+    // from u = 0.
+    h->learned_on = (h->opt.smoother == FFMG_SMOOTH_LEARNED);
     cd *ua = u, *ub = l0.t;
     int queued = 0;
     int batch = h->last_cycles > 0 ? h->last_cycles : 4;
+    if (h->learned_on) batch = 1;
     SolveCtl c{};
+    int k_prev = 0, bad = 0, k_before_restart = 0;
+    double r2_prev = -1.0;
     for (;;) {
         int nb = std::min(batch, maxc - queued);
         for (int i = 0; i < nb; ++i) {
@@ -656,6 +793,41 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
         HIPCHK(h, hipMemcpyAsync(h->h_ctl, h->d_ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
         c = *h->h_ctl;
+        if (h->learned_on && (c.done == 4 || !(c.rk2 <= 100.0 * c.r0_2))) {
+            // a non-finite iterate, or a residual up tenfold from the start:
+            // start again from u = 0 with Jacobi
+            h->learned_on = false;
+            inf.fell_back = 1;
+            k_before_restart = c.k;
+            launch_zero<double>(u, N, h->stream, nullptr);
+            launch_ctl_init(h->d_ctl, h->d_scalar, tol, N, maxc, h->stream);
+            launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
+            launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
+            queued = 0;
+            k_prev = 0;
+            r2_prev = -1.0;
+            batch = 2;
+            continue;
+        }
+        if (h->learned_on && c.done == 2) {
+            // the learned cycles made the residual grow: continue with Jacobi
+            // from the current iterate instead of failing
+            c.done = 0;
+            c.grow = 0;
+            *h->h_ctl = c;
+            HIPCHK(h, hipMemcpyAsync(h->d_ctl, h->h_ctl, sizeof(SolveCtl), hipMemcpyHostToDevice, h->stream));
+            h->learned_on = false;
+            inf.fell_back = 1;
+        } else if (h->learned_on && c.done == 0 && k_prev >= 1 && c.k > k_prev && r2_prev > 0.0) {
+            const double rho = pow(c.rk2 / r2_prev, 0.5 / (c.k - k_prev));
+            bad = (rho <= 1.10 * h->rho_jacobi) ? 0 : bad + 1;
+            if (bad >= 2) {
+                h->learned_on = false;
+                inf.fell_back = 1;
+            }
+        }
+        k_prev = c.k;
+        r2_prev = c.rk2;
         if (c.done || queued >= maxc) break;
         batch = 2;
     }
@@ -663,7 +835,8 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
     // number of completed steps the iterate is in l0.t
     const bool pingpong = (h->opt.precision == FFMG_FP32_IR && l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE);
     if (pingpong && (c.k % 2) == 1) HIPCHK(h, hipMemcpyAsync(u, l0.t, N * sizeof(cd), hipMemcpyDeviceToDevice, h->stream));
-    inf.cycles = std::max(c.k, 0);
+    h->learned_on = (h->opt.smoother == FFMG_SMOOTH_LEARNED);   // the fallback lasts for this solve only
+    inf.cycles = std::max(c.k, 0) + k_before_restart;
     inf.vcycles = inf.cycles * ((h->opt.precision == FFMG_FP32_IR)
                                     ? (h->opt.inner_cycles > 0 ? h->opt.inner_cycles : 2) : 1);
     const double bn = sqrt(bn2), rk = sqrt(c.rk2), r0 = sqrt(c.r0_2);

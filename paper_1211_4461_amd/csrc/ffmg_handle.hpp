@@ -57,6 +57,11 @@ struct ffmg_handle {
     ffmg::cd *d_E = nullptr;         // plane-wave axis factors
     ffmg::cd *d_F = nullptr;         // far-field staging
     int d_F_cap = 0;
+    // learned smoother on the finest level (smoother FFMG_SMOOTH_LEARNED)
+    unsigned short *d_wfrag = nullptr;   // MFMA weight fragments (BF16)
+    std::vector<unsigned *> d_kh2;       // kappa h^2 per level, BF16 complex (learned levels)
+    double rho_jacobi = 0.0;             // Jacobi V-cycle convergence factor (the reference)
+    bool learned_on = false;             // learned smoother in use
     ffmg::Batch *batch = nullptr;    // batched-solve workspace for a list of handles starting with this one
     std::vector<void *> allocs;
     std::string err;
@@ -95,6 +100,9 @@ double exponent_budget(const ffmg_handle *h);
 ffmg_status farfield_enqueue(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
                              cd *F);
 void batch_destroy(Batch *b);
+// one learned smoothing step on level l, in place on u
+void learned_step(ffmg_handle *h, int l, const cd *b, cd *u, const int *stop);
+bool learned_level(const ffmg_handle *h, int l);
 
 }  // namespace ffmg
 

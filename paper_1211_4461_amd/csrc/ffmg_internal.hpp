@@ -233,6 +233,7 @@ struct FinishJob {
     size_t N;
 };
 int norm2_blocks(size_t N);
+void launch_hash_fill(cd *out, size_t N, unsigned long long seed, hipStream_t s);
 void stencil_grid2d(const LevelGeom &g, int *nb, int *tiles_x);   // blocks and tiles per row of k_stencil2d
 void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_nb_res, hipStream_t s);
 void launch_ctl_update_batch(const CtlJob *jobs, int n, hipStream_t s);

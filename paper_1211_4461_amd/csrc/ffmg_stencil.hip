@@ -901,4 +901,28 @@ void launch_finish_batch(const FinishJob *jobs, int n, hipStream_t s)
     if (n > 0) hipLaunchKernelGGL(k_finish_batch, dim3(1024, n), dim3(256), 0, s, jobs);
 }
 
+// Pseudo-random complex values in [-1, 1)^2 from a counter-based hash of
+// (seed, index) (the splitmix64 finaliser), for calibration runs.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_hash_fill(cd *__restrict__ out, size_t N, unsigned long long seed)
+{
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
+        unsigned long long a = mix64(seed ^ (2 * j)), c = mix64(seed ^ (2 * j + 1));
+        out[j] = cd{(double)(a >> 11) * 0x1.0p-52 - 1.0, (double)(c >> 11) * 0x1.0p-52 - 1.0};
+    }
+}
+
+void launch_hash_fill(cd *out, size_t N, unsigned long long seed, hipStream_t s)
+{
+    size_t nb = std::min<size_t>((N + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_hash_fill, dim3((unsigned)nb), dim3(256), 0, s, out, N, seed);
+}
+
 }  // namespace ffmg

@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("smoother_weights", ctypes.c_void_p),
                 ("ff_precision", ctypes.c_int), ("tile_config", ctypes.c_int), ("inner_cycles", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("nu_coarse", ctypes.c_int), ("learned_levels", ctypes.c_int), ("stream", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -62,7 +62,8 @@ EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup
            "mg_vcycle", "mg_solve", "farfield_map", "mg_apply", "mg_smooth", "mg_residual_norm",
            "mg_num_levels", "mg_level_shape", "mg_destroy", "mg_profile_enable", "mg_profile_read",
            "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_solve_batched",
-           "farfield_map_batched"]
+           "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights", "ml_loss_grad",
+           "ml_train_step", "ml_net_last_error", "ml_net_destroy", "mg_learned_smooth", "mg_jacobi_factor"]
 
 
 def lib():
@@ -99,20 +100,45 @@ def lib():
     L.mg_tune_set.argtypes = [vp, ip, ip]
     L.mg_tune_farfield.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(dp), ip, ctypes.POINTER(ip)]
     L.mg_solve_batched.argtypes = [vp, ip, vp, vp, dp, vp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.ml_net_create.argtypes = [fp, vp, ctypes.POINTER(vp)]
+    L.ml_net_set_weights.argtypes = [vp, fp]
+    L.ml_net_get_weights.argtypes = [vp, fp]
+    L.ml_loss_grad.argtypes = [vp, vp, vp, vp, ip, ip, fp, fp]
+    L.ml_train_step.argtypes = [vp, vp, vp, vp, ip, ip, ctypes.c_float, fp]
+    L.ml_net_last_error.argtypes = [vp]
+    L.ml_net_last_error.restype = ctypes.c_char_p
+    L.ml_net_destroy.argtypes = [vp]
+    L.ml_net_destroy.restype = None
+    L.mg_learned_smooth.argtypes = [vp, vp, vp]
+    L.mg_learned_smooth.restype = ip
+    L.mg_jacobi_factor.argtypes = [vp]
+    L.mg_jacobi_factor.restype = ctypes.c_double
     L.farfield_map_batched.argtypes = [vp, ip, vp, vp, ip, vp, vp]
     for name in ("mg_setup", "mg_rhs_plane_wave", "mg_vcycle", "mg_solve", "farfield_map", "mg_apply",
                  "mg_smooth", "mg_residual_norm", "mg_level_shape", "mg_profile_enable", "mg_profile_read",
                  "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_solve_batched",
-                 "farfield_map_batched"):
+                 "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights",
+                 "ml_loss_grad", "ml_train_step"):
         getattr(L, name).restype = ip
     _lib = L
     return L
 
 
+SMOOTH_JACOBI, SMOOTH_LEARNED = 0, 1
+
+
 def default_options(**kw) -> Options:
+    """ffmg_default_options with overrides.  smoother_weights may be a list of
+    the three complex weight arrays or a flat float32 array; it is kept alive
+    with the options object."""
     o = Options()
     lib().ffmg_default_options(ctypes.byref(o))
     for k, v in kw.items():
+        if k == "smoother_weights" and v is not None and not isinstance(v, int):
+            w = net_flatten(v) if isinstance(v, (list, tuple)) else np.ascontiguousarray(v, dtype=np.float32)
+            o._weights = w
+            v = w.ctypes.data
         setattr(o, k, v)
     return o
 
@@ -319,6 +345,16 @@ def mg_apply(h: Handle, u, Au):
     return Au
 
 
+def mg_learned_smooth(h: Handle, b, u):
+    """One learned smoothing step on the finest level, in place on u."""
+    h._check(lib().mg_learned_smooth(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u")), "mg_learned_smooth")
+    return u
+
+
+def mg_jacobi_factor(h: Handle) -> float:
+    return float(lib().mg_jacobi_factor(h.ptr))
+
+
 def mg_smooth(h: Handle, b, u, u_out):
     h._check(lib().mg_smooth(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), _dev_ptr(u_out, "u_out")), "mg_smooth")
     return u_out
@@ -361,3 +397,101 @@ def setup_workload(w, device="cuda", options: Optional[Options] = None):
     h = mg_setup(w.dim, [w.n] * w.dim, lo, hi, w.gamma, coef, kind=w.kind, k0=w.k0, energy=w.energy,
                  options=options)
     return h, coef
+
+
+# ---------------------------------------------------------------------------
+# Learned smoother network
+NET_WEIGHTS = 2736
+NET_SHAPES = ((9, 16, 2), (9, 16, 16), (9, 1, 16))
+
+
+def net_flatten(Ws) -> np.ndarray:
+    """[W1, W2, W3] complex arrays (tap, out, in) -> interleaved float32."""
+    z = np.concatenate([np.asarray(W, dtype=np.complex128).ravel() for W in Ws])
+    if z.size != NET_WEIGHTS:
+        raise ValueError(f"expected {NET_WEIGHTS} complex weights, got {z.size}")
+    out = np.empty(2 * NET_WEIGHTS, dtype=np.float32)
+    out[0::2], out[1::2] = z.real, z.imag
+    return out
+
+
+def net_unflatten(w) -> list:
+    w = np.asarray(w, dtype=np.float32)
+    z = w[0::2].astype(np.float64) + 1j * w[1::2].astype(np.float64)
+    out, k = [], 0
+    for s in NET_SHAPES:
+        n = int(np.prod(s))
+        out.append(z[k:k + n].reshape(s))
+        k += n
+    return out
+
+
+class Net:
+    """The learned smoother's network: FP32 master weights, Adam state and
+    training buffers on the device (ml_net_*)."""
+
+    def __init__(self, Ws, stream=None):
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        w = net_flatten(Ws)
+        p = ctypes.c_void_p()
+        st = lib().ml_net_create(w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.c_void_p(stream),
+                                 ctypes.byref(p))
+        if st != FFMG_OK:
+            raise FfmgError(st, "ml_net_create failed")
+        self._p = p
+
+    def _check(self, st, what):
+        if st != FFMG_OK:
+            raise FfmgError(st, f"{what}: {lib().ml_net_last_error(self._p).decode()}")
+
+    @property
+    def ptr(self):
+        return self._p
+
+    def weights(self) -> list:
+        w = np.empty(2 * NET_WEIGHTS, dtype=np.float32)
+        self._check(lib().ml_net_get_weights(self._p, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    "ml_net_get_weights")
+        return net_unflatten(w)
+
+    def set_weights(self, Ws):
+        w = net_flatten(Ws)
+        self._check(lib().ml_net_set_weights(self._p, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+                    "ml_net_set_weights")
+
+    @staticmethod
+    def _patches(t, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.complex64 or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous complex64 device tensor")
+        if t.dim() != 3 or t.shape[1] != 32 or t.shape[2] != 32:
+            raise ValueError(f"{name} must have shape (count, 32, 32)")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def loss_grad(self, rt, kt, et, border=4):
+        loss = ctypes.c_float()
+        g = np.empty(2 * NET_WEIGHTS, dtype=np.float32)
+        self._check(lib().ml_loss_grad(self._p, self._patches(rt, "rt"), self._patches(kt, "kt"),
+                                       self._patches(et, "et"), rt.shape[0], int(border), ctypes.byref(loss),
+                                       g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))), "ml_loss_grad")
+        return loss.value, net_unflatten(g)
+
+    def train_step(self, rt, kt, et, lr, border=4, want_loss=False):
+        loss = ctypes.c_float()
+        self._check(lib().ml_train_step(self._p, self._patches(rt, "rt"), self._patches(kt, "kt"),
+                                        self._patches(et, "et"), rt.shape[0], int(border), ctypes.c_float(lr),
+                                        ctypes.byref(loss) if want_loss else None), "ml_train_step")
+        return loss.value if want_loss else None
+
+    def destroy(self):
+        if self._p:
+            lib().ml_net_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
