@@ -175,6 +175,84 @@ def run_batched(ff, torch, W, steps):
     return out
 
 
+def run_learned(ff, torch, W, reps=3, oracle_check=False):
+    """The learned-smoother workload: a network trained on the GPU (the
+    library's kernels) from weighted Jacobi on (error, residual) patches of
+    plain V-cycle iterates and white noise on 255^2 fields (k0 h in
+    [0.02, 0.6]); then on a 1023^2 random bump field (seed 4) the finest
+    level's smoother is the network or weighted Jacobi in V(2,2) cycles to
+    1e-8: cycles and wall time at the stress point k0 h = 0.5 and at 0.2, and
+    the far field at k0 = 1 (360 angles) against the plain FP64 map."""
+    import numpy as np
+    from paper_1211_4461_amd import learned as LS
+    t0 = time.perf_counter()
+    data = LS.make_patches(torch, n_fields=48, n=256, seed=1000)
+    net = ff.Net(LS.jacobi_init(7))
+    sub = [t[:1024].contiguous() for t in (data.rt, data.kt, data.et)]
+    L0, _ = net.loss_grad(*sub)
+    t1 = time.perf_counter()
+    LS.train(torch, net, data, steps=4000, batch=256, lr=1e-3, lr_final=1e-5, seed=1)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    L1, _ = net.loss_grad(*sub)
+    Ws = net.weights()
+    net.destroy()
+    out = {"workload": "random bump field seed 4 on 1023^2, box [-10,10]^2, gamma=30deg, V(2,2) to 1e-8; "
+                       "finest-level smoother: trained network vs omega=0.8 Jacobi",
+           "training": {"patches": int(data.count), "steps": 4000, "data_s": round(t1 - t0, 2),
+                        "train_s": round(t2 - t1, 2), "loss_jacobi_start": round(L0, 4), "loss_trained": round(L1, 4)}}
+
+    def solve(w, b, learned, tol=1e-8):
+        o = ff.default_options(smoother=ff.SMOOTH_LEARNED, smoother_weights=Ws) if learned else ff.default_options()
+        h = ff.setup_workload(w, options=o)[0]
+        u = torch.zeros_like(b)
+        info = ff.mg_solve(h, b, u, tol=tol)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            u.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = ff.mg_solve(h, b, u, tol=tol)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return h, u, info, 1e3 * min(ts)
+
+    for kh in (0.5, 0.2):
+        w = W.random_field(1024, 4, kh)
+        b = LS.phase_rhs(w, torch)
+        hj, uj, ij, tj = solve(w, b, False)
+        hl, ul, il, tl = solve(w, b, True)
+        out[f"k0h={kh}"] = {"jacobi": {"cycles": ij.cycles, "conv_factor": round(ij.conv_factor, 4), "ms": round(tj, 3)},
+                            "learned": {"cycles": il.cycles, "conv_factor": round(il.conv_factor, 4), "ms": round(tl, 3),
+                                        "fell_back": il.fell_back},
+                            "solution_rel_diff": float(torch.linalg.norm(ul - uj) / torch.linalg.norm(uj))}
+        hj.destroy()
+        hl.destroy()
+    # far field at k0 = 1 (the contour plane wave)
+    w = W.random_field(1024, 4, 20.0 / 1024)
+    maps = {}
+    for learned in (False, True):
+        o = ff.default_options(smoother=ff.SMOOTH_LEARNED, smoother_weights=Ws) if learned else ff.default_options()
+        h = ff.setup_workload(w, options=o)[0]
+        b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+        u = torch.zeros_like(b)
+        ff.mg_solve(h, b, u, tol=1e-8 if learned else 1e-10)
+        maps[learned] = ff.farfield_map(h, w.eta, u, w.dirs)
+        h.destroy()
+    out["k0=1"] = {"farfield_rel_err_vs_plain_fp64": float(np.linalg.norm(maps[True] - maps[False]) /
+                                                             np.linalg.norm(maps[False]))}
+    if oracle_check:
+        from oracle import oracle as orc
+        g = orc.Grid(2, w.n, w.lo, w.hi)
+        kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+        bo = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+        uo, st, k, _ = orc.Multigrid(g, w.gamma, kappa).solve(bo, tol=1e-10)
+        Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
+        out["k0=1"]["farfield_rel_err_vs_oracle"] = float(np.linalg.norm(maps[True] - Fo) / np.linalg.norm(Fo))
+    return out
+
+
 def gemm_report(prof, w, prec, tune=None):
     """MFMA rate of the far-field GEMM stage (2D: 8 M N flop per map as a
     complex GEMM; a split precision issues `products` times as many)."""
@@ -222,6 +300,7 @@ def main():
     ap.add_argument("--ff-precision", choices=("bf16x6", "bf16x3", "fp64"), default="bf16x6",
                     help="far-field contraction of the mixed path")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Schroedinger workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -317,6 +396,8 @@ def main():
         line["mixed_vs_plain_farfield_rel_err"] = ef
     if not args.no_batch:
         line["batched"] = run_batched(ffmg, torch, W, max(args.steps // 4, 2))
+    if not args.no_learned:
+        line["learned"] = run_learned(ffmg, torch, W, oracle_check=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         cb, Fo = cpu_baseline(w)
         line["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
