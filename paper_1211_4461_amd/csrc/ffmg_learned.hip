@@ -530,42 +530,222 @@ constexpr int R0 = IT + 6;                   // input region side
 constexpr int NR1 = (R1 * R1 + 15) / 16;     // row tiles of the layer-1 region
 constexpr int NR2 = (R2 * R2 + 15) / 16;
 
+// Activations: 32 BF16 channels per point, padded to 40 (80 bytes): the 8
+// lanes a 128-bit LDS read serves together then start 20 dwords apart and
+// cover all 32 banks once.
+constexpr int XS = 40;
 struct InferLds {
     unsigned short x0[R0 * R0][4];           // r~ re, r~ im, kappa~ re, kappa~ im
-    unsigned short x1[R1 * R1][32];
-    unsigned short x2[R2 * R2][32];
+    unsigned short x1[R1 * R1][XS];
+    unsigned short x2[R2 * R2][XS];
 };
 
 __device__ __forceinline__ bf8 as_bf8(us8 v) { return __builtin_bit_cast(bf8, v); }
 
-// N is complex-linear in its residual input, so s h^2 N(r / s) = h^2 N(r)
-// for any scale s; BF16 has the exponent range of FP32, so the residual is
-// fed unscaled and no global reduction precedes the step.
-__global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, const unsigned *__restrict__ kh2,
-                                                   cd *__restrict__ u, int mx, int my, int tiles_x,
-                                                   const us8 *__restrict__ wfrag, double h2,
-                                                   const int *__restrict__ stop)
+// Gate of layer 1 for one accumulator element: lane column j = 16 nt + li
+// is Re (li even) or Im (li odd) of channel j / 2, the partner lane li ^ 1
+// holds the other part.
+__device__ __forceinline__ float gate(float am, float mm, bool odd)
 {
-    if (stop && *stop) return;
-    __shared__ InferLds S;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int ox = (tile % tiles_x) * IT, oy = (tile / tiles_x) * IT;
+    const float ap = __shfl_xor(am, 1, 64), mp = __shfl_xor(mm, 1, 64);
+    const float are = odd ? ap : am, aim = odd ? am : ap;
+    const float mre = odd ? mp : mm, mim = odd ? mm : mp;
+    return odd ? (are * mim + aim * (1.f + mre)) : (are * (1.f + mre) - aim * mim);
+}
+
+// Hardware round-to-nearest-even FP32 -> BF16 (v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ unsigned short to_bf16(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
+
+// Point (y, x) of row-major region of width R for index p, advanced by one.
+struct RegionPos {
+    int y, x;
+};
+template <int R>
+__device__ __forceinline__ RegionPos region_pos(int p)
+{
+    return RegionPos{p / R, p - (p / R) * R};
+}
+template <int R>
+__device__ __forceinline__ void region_next(RegionPos &q)
+{
+    if (++q.x == R) {
+        q.x = 0;
+        ++q.y;
+    }
+}
+
+// One 16 x 16 output tile (origin oy, ox) with the weight fragments in
+// registers.  Each wave takes two row tiles at a time so that four
+// independent MFMA accumulation chains interleave.  LDS addresses of the 9
+// taps are one base per row tile plus compile-time offsets.
+__device__ __forceinline__ void net_tile(InferLds &S, const cd *__restrict__ r, const unsigned *__restrict__ kh2,
+                                         cd *__restrict__ u, int mx, int my, int oy, int ox, const bf8 (&w1)[2][2],
+                                         const bf8 (&w2)[9][2], const bf8 (&w3)[9], double h2)
+{
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
+    const bool odd = (li & 1) != 0;
     // inputs on the 22 x 22 region (origin oy - 3, ox - 3)
     for (int p = tid; p < R0 * R0; p += 256) {
-        const int gy = oy - 3 + p / R0, gx = ox - 3 + p % R0;
+        const RegionPos q = region_pos<R0>(p);
+        const int gy = oy - 3 + q.y, gx = ox - 3 + q.x;
         const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
         const size_t j = in ? (size_t)gy * mx + gx : 0;
         cd rv = r[j];
         unsigned kv = kh2[j];
         const float rr = in ? (float)rv.re : 0.f, ri = in ? (float)rv.im : 0.f;
-        S.x0[p][0] = (unsigned short)bf16_bits(rr);
-        S.x0[p][1] = (unsigned short)bf16_bits(ri);
-        S.x0[p][2] = in ? (unsigned short)(kv & 0xFFFFu) : 0;
-        S.x0[p][3] = in ? (unsigned short)(kv >> 16) : 0;
+        const unsigned rp = (unsigned)to_bf16(rr) | ((unsigned)to_bf16(ri) << 16);
+        uint2 v = make_uint2(rp, in ? kv : 0u);
+        *reinterpret_cast<uint2 *>(&S.x0[p][0]) = v;
     }
-    // weight fragments: layer 1 [a, m][nt 2], layer 2 [tap 9][nt 2], layer 3 [tap 9]
+    __syncthreads();
+    // layer 1 on the 20 x 20 region (origin -2)
+    for (int rt0 = wave; rt0 < NR1; rt0 += 8) {
+        f4 acc[2][2][2];   // [row tile][op][nt]
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int op = 0; op < 2; ++op)
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) acc[q][op][nt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            int p = (rt0 + 4 * q) * 16 + li;
+            if (p >= R1 * R1) p = 0;
+            const RegionPos P = region_pos<R1>(p);
+            const unsigned *base = reinterpret_cast<const unsigned *>(&S.x0[(P.y + 1) * R0 + P.x + 1][0]);
+#pragma unroll
+            for (int op = 0; op < 2; ++op) {
+                us8 av;
+#pragma unroll
+                for (int hh = 0; hh < 4; ++hh) {
+                    // tap t = 4 lg + hh (taps 9 .. 15 are zero padding)
+                    unsigned v = 0;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        if (lg == g && 4 * g + hh < 9) {
+                            const int t = 4 * g + hh;
+                            v = base[2 * (tap_dy(t) * R0 + tap_dx(t)) + op];
+                        }
+                    av[2 * hh] = (unsigned short)(v & 0xFFFFu);
+                    av[2 * hh + 1] = (unsigned short)(v >> 16);
+                }
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[q][op][nt] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(av), w1[op][nt], acc[q][op][nt], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int rt = rt0 + 4 * q;
+            int pp = rt * 16 + 4 * lg;
+            RegionPos P = region_pos<R1>(pp < R1 * R1 ? pp : 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float x0 = gate(acc[q][0][0][v], acc[q][1][0][v], odd);
+                const float x1 = gate(acc[q][0][1][v], acc[q][1][1][v], odd);
+                if (rt < NR1 && pp + v < R1 * R1) {
+                    const int gy = oy - 2 + P.y, gx = ox - 2 + P.x;
+                    const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
+                    S.x1[pp + v][li] = in ? to_bf16(x0) : 0;
+                    S.x1[pp + v][16 + li] = in ? to_bf16(x1) : 0;
+                }
+                region_next<R1>(P);
+            }
+        }
+    }
+    __syncthreads();
+    // layer 2 on the 18 x 18 region (origin -1)
+    for (int rt0 = wave; rt0 < NR2; rt0 += 8) {
+        f4 acc[2][2];
+        const us8 *base[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            int p = (rt0 + 4 * q) * 16 + li;
+            if (p >= R2 * R2) p = 0;
+            const RegionPos P = region_pos<R2>(p);
+            base[q] = reinterpret_cast<const us8 *>(&S.x1[(P.y + 1) * R1 + P.x + 1][8 * lg]);
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) acc[q][nt] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const us8 a = base[q][(tap_dy(t) * R1 + tap_dx(t)) * (XS / 8)];
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[q][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), w2[t][nt], acc[q][nt], 0, 0, 0);
+            }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int rt = rt0 + 4 * q;
+            int pp = rt * 16 + 4 * lg;
+            RegionPos P = region_pos<R2>(pp < R2 * R2 ? pp : 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                if (rt < NR2 && pp + v < R2 * R2) {
+                    const int gy = oy - 1 + P.y, gx = ox - 1 + P.x;
+                    const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
+                    S.x2[pp + v][li] = in ? to_bf16(acc[q][0][v]) : 0;
+                    S.x2[pp + v][16 + li] = in ? to_bf16(acc[q][1][v]) : 0;
+                }
+                region_next<R2>(P);
+            }
+        }
+    }
+    __syncthreads();
+    // layer 3 on the 16 x 16 tile: row tile rt = tile row rt
+    {
+        const int rt0 = wave;   // rows wave, wave + 4, wave + 8, wave + 12
+        f4 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+        const us8 *base = reinterpret_cast<const us8 *>(&S.x2[(rt0 + 1) * R2 + li + 1][8 * lg]);
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const us8 a = base[((4 * q + tap_dy(t)) * R2 + tap_dx(t)) * (XS / 8)];
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), w3[t], acc[q], 0, 0, 0);
+            }
+        // column 0 (Re) in lanes li = 0, column 1 (Im) in li = 1
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            f4 im;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) im[v] = __shfl_down(acc[q][v], 1, 64);
+            const int gy = oy + rt0 + 4 * q;
+            if (li == 0 && gy < my) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gx = ox + 4 * lg + v;
+                    if (gx < mx) {
+                        const size_t j = (size_t)gy * mx + gx;
+                        cd uv = u[j];
+                        u[j] = cd{uv.re + h2 * (double)acc[q][v], uv.im + h2 * (double)im[v]};
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();   // the LDS is reused by the next tile
+}
+
+// N is complex-linear in its residual input, so s h^2 N(r / s) = h^2 N(r)
+// for any scale s; BF16 has the exponent range of FP32, so the residual is
+// fed unscaled and no global reduction precedes the step.  Persistent
+// workgroups: each loads the weight fragments once and works through a
+// contiguous range of tiles (ranges of neighbouring workgroups sit on one XCD).
+__global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, const unsigned *__restrict__ kh2,
+                                                   cd *__restrict__ u, int mx, int my, int tiles_x, int ntiles,
+                                                   int per_block, const us8 *__restrict__ wfrag, double h2,
+                                                   const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    __shared__ InferLds S;
+    const int lane = threadIdx.x & 63;
     bf8 w1[2][2], w2[9][2], w3[9];
 #pragma unroll
     for (int op = 0; op < 2; ++op)
@@ -577,108 +757,10 @@ __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, con
         for (int nt = 0; nt < 2; ++nt) w2[t][nt] = as_bf8(wfrag[256 + (t * 2 + nt) * 64 + lane]);
 #pragma unroll
     for (int t = 0; t < 9; ++t) w3[t] = as_bf8(wfrag[256 + 1152 + t * 64 + lane]);
-    __syncthreads();
-    // layer 1 on the 20 x 20 region (origin -2)
-    for (int rt = wave; rt < NR1; rt += 4) {
-        int p = rt * 16 + li;
-        if (p >= R1 * R1) p = 0;
-        const int y1 = p / R1, x1 = p % R1;
-        f4 acc[2][2] = {{f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}},
-                        {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}}};
-#pragma unroll
-        for (int op = 0; op < 2; ++op) {            // 0: a from r~ (channels 0, 1); 1: m from kappa~ (2, 3)
-            us8 av;
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int t = 4 * lg + h;              // tap of elements 2h, 2h + 1
-                if (t < 9) {
-                    const int q = (y1 + 1 + tap_dy(t)) * R0 + (x1 + 1 + tap_dx(t));
-                    av[2 * h] = S.x0[q][2 * op];
-                    av[2 * h + 1] = S.x0[q][2 * op + 1];
-                } else {
-                    av[2 * h] = 0;
-                    av[2 * h + 1] = 0;
-                }
-            }
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
-                acc[op][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(av), w1[op][nt], acc[op][nt], 0, 0, 0);
-        }
-        // gate: lane column j = 16 nt + li is Re (li even) or Im (li odd) of
-        // channel j / 2; the partner lane li ^ 1 holds the other part
-        const bool odd = (li & 1) != 0;
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float am = acc[0][nt][v], mm = acc[1][nt][v];
-                const float ap = __shfl_xor(am, 1, 64), mp = __shfl_xor(mm, 1, 64);
-                const float are = odd ? ap : am, aim = odd ? am : ap;
-                const float mre = odd ? mp : mm, mim = odd ? mm : mp;
-                const float x = odd ? (are * mim + aim * (1.f + mre)) : (are * (1.f + mre) - aim * mim);
-                const int pp = rt * 16 + 4 * lg + v;
-                if (pp < R1 * R1) {
-                    const int gy = oy - 2 + pp / R1, gx = ox - 2 + pp % R1;
-                    const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
-                    S.x1[pp][16 * nt + li] = in ? (unsigned short)bf16_bits(x) : 0;
-                }
-            }
-    }
-    __syncthreads();
-    // layer 2 on the 18 x 18 region (origin -1)
-    for (int rt = wave; rt < NR2; rt += 4) {
-        int p = rt * 16 + li;
-        if (p >= R2 * R2) p = 0;
-        const int y2 = p / R2, x2 = p % R2;
-        f4 acc[2] = {f4{0.f, 0.f, 0.f, 0.f}, f4{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int q = (y2 + 1 + tap_dy(t)) * R1 + (x2 + 1 + tap_dx(t));
-            const us8 a = *reinterpret_cast<const us8 *>(&S.x1[q][8 * lg]);
-#pragma unroll
-            for (int nt = 0; nt < 2; ++nt)
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), w2[t][nt], acc[nt], 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int pp = rt * 16 + 4 * lg + v;
-            if (pp < R2 * R2) {
-                const int gy = oy - 1 + pp / R2, gx = ox - 1 + pp % R2;
-                const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-                    S.x2[pp][16 * nt + li] = in ? (unsigned short)bf16_bits(acc[nt][v]) : 0;
-            }
-        }
-    }
-    __syncthreads();
-    // layer 3 on the 16 x 16 tile: row tile rt = tile row rt
-    for (int rt = wave; rt < IT; rt += 4) {
-        f4 acc = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int q = (rt + 1 + tap_dy(t)) * R2 + (li + 1 + tap_dx(t));
-            const us8 a = *reinterpret_cast<const us8 *>(&S.x2[q][8 * lg]);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), w3[t], acc, 0, 0, 0);
-        }
-        // column 0 (Re) in lanes li = 0, column 1 (Im) in li = 1
-        f4 im;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) im[v] = __shfl_down(acc[v], 1, 64);
-        const int gy = oy + rt;
-        if (li == 0 && gy < my) {
-            const double sc = h2;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int gx = ox + 4 * lg + v;
-                if (gx < mx) {
-                    const size_t j = (size_t)gy * mx + gx;
-                    cd uv = u[j];
-                    u[j] = cd{uv.re + sc * (double)acc[v], uv.im + sc * (double)im[v]};
-                }
-            }
-        }
-    }
+    const int first = xcd_tile(blockIdx.x, gridDim.x) * per_block;
+    const int last = min(first + per_block, ntiles);
+    for (int tile = first; tile < last; ++tile)
+        net_tile(S, r, kh2, u, mx, my, (tile / tiles_x) * IT, (tile % tiles_x) * IT, w1, w2, w3, h2);
 }
 
 // MFMA B-operand fragments of the three layers from the complex weights
@@ -752,8 +834,11 @@ void launch_kappa_h2(const cd *q, double k02, double h2, size_t N, unsigned *out
 void launch_net_apply(const cd *r, const unsigned *kh2, cd *u, int mx, int my, const unsigned short *wfrag,
                       double h2, hipStream_t st, const int *stop)
 {
-    const int tx = (mx + IT - 1) / IT, ty = (my + IT - 1) / IT;
-    hipLaunchKernelGGL(k_net_apply, dim3(tx * ty), dim3(256), 0, st, r, kh2, u, mx, my, tx,
+    const int tx = (mx + IT - 1) / IT, ty = (my + IT - 1) / IT, nt = tx * ty;
+    const int blocks = std::min(nt, 256 * 2);   // two resident workgroups per CU
+    const int per = (nt + blocks - 1) / blocks;
+    const int nb = (nt + per - 1) / per;
+    hipLaunchKernelGGL(k_net_apply, dim3(nb), dim3(256), 0, st, r, kh2, u, mx, my, tx, nt, per,
                        reinterpret_cast<const us8 *>(wfrag), h2, stop);
 }
 
