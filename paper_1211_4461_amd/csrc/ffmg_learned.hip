@@ -529,34 +529,49 @@ constexpr int R1 = IT + 4, R2 = IT + 2;      // layer-1 / layer-2 region sides
 constexpr int R0 = IT + 6;                   // input region side
 constexpr int NR1 = (R1 * R1 + 15) / 16;     // row tiles of the layer-1 region
 constexpr int NR2 = (R2 * R2 + 15) / 16;
+constexpr int IN_PER_THREAD = (R0 * R0 + 255) / 256;
 
-// Activations: 32 BF16 channels per point, padded to 40 (80 bytes): the 8
-// lanes a 128-bit LDS read serves together then start 20 dwords apart and
-// cover all 32 banks once.
+// Activations: 32 BF16 channel slots per point, padded to 40 (80 bytes): the
+// 8 lanes a 128-bit LDS read serves together then start 20 dwords apart and
+// cover all 32 banks once.  Slot s holds accumulator column
+// 16 (s & 1) + (s >> 1) of the producing layer, so that the lane owning
+// column li of both column tiles writes slots 2 li and 2 li + 1 as one dword;
+// column j is Re (j even) or Im (j odd) of channel j / 2.
 constexpr int XS = 40;
 struct InferLds {
     unsigned short x0[R0 * R0][4];           // r~ re, r~ im, kappa~ re, kappa~ im
-    unsigned short x1[R1 * R1][XS];
-    unsigned short x2[R2 * R2][XS];
+    unsigned short x1[NR1 * 16][XS];
+    unsigned short x2[NR2 * 16][XS];         // rows past R2 * R2 take unused writes
+    float2 y[IT * IT];                       // network output of the tile
 };
 
 __device__ __forceinline__ bf8 as_bf8(us8 v) { return __builtin_bit_cast(bf8, v); }
 
+// Value of the neighbouring lane (lane ^ 1) through a DPP quad permutation.
+__device__ __forceinline__ float swap_pair(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+
 // Gate of layer 1 for one accumulator element: lane column j = 16 nt + li
 // is Re (li even) or Im (li odd) of channel j / 2, the partner lane li ^ 1
-// holds the other part.
+// holds the other part.  Re: a_re (1 + m_re) - a_im m_im;
+// Im: a_re m_im + a_im (1 + m_re).
 __device__ __forceinline__ float gate(float am, float mm, bool odd)
 {
-    const float ap = __shfl_xor(am, 1, 64), mp = __shfl_xor(mm, 1, 64);
-    const float are = odd ? ap : am, aim = odd ? am : ap;
-    const float mre = odd ? mp : mm, mim = odd ? mm : mp;
-    return odd ? (are * mim + aim * (1.f + mre)) : (are * (1.f + mre) - aim * mim);
+    const float ap = swap_pair(am), mp = swap_pair(mm);
+    const float s1 = odd ? mp : mm, s2 = odd ? mm : -mp;
+    return am * (1.f + s1) + ap * s2;
 }
 
 // Hardware round-to-nearest-even FP32 -> BF16 (v_cvt_pk_bf16_f32 on gfx950).
 __device__ __forceinline__ unsigned short to_bf16(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
+__device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
+{
+    return (unsigned)to_bf16(lo) | ((unsigned)to_bf16(hi) << 16);
+}
 
-// Point (y, x) of row-major region of width R for index p, advanced by one.
+// Point (y, x) of row-major region of width R for index p.
 struct RegionPos {
     int y, x;
 };
@@ -568,46 +583,77 @@ __device__ __forceinline__ RegionPos region_pos(int p)
 template <int R>
 __device__ __forceinline__ void region_next(RegionPos &q)
 {
-    if (++q.x == R) {
-        q.x = 0;
-        ++q.y;
+    const bool wrap = q.x == R - 1;
+    q.x = wrap ? 0 : q.x + 1;
+    q.y += wrap ? 1 : 0;
+}
+
+// Inputs of one tile's 22 x 22 region (origin oy - 3, ox - 3), held in
+// registers between their global load and their LDS store so that the next
+// tile's loads overlap the current tile's layers.
+struct TileInput {
+    cd r[IN_PER_THREAD];
+    unsigned k[IN_PER_THREAD];
+};
+
+__device__ __forceinline__ bool input_in_grid(int p, int mx, int my, int oy, int ox)
+{
+    const RegionPos q = region_pos<R0>(p < R0 * R0 ? p : 0);
+    const int gy = oy - 3 + q.y, gx = ox - 3 + q.x;
+    return p < R0 * R0 && gy >= 0 && gy < my && gx >= 0 && gx < mx;
+}
+
+// Issues the loads only (points outside the grid read element 0 and are
+// zeroed when stored), so that nothing waits for them before the store.
+__device__ __forceinline__ void load_tile_input(TileInput &in, const cd *__restrict__ r,
+                                                const unsigned *__restrict__ kh2, int mx, int my, int oy, int ox)
+{
+#pragma unroll
+    for (int i = 0; i < IN_PER_THREAD; ++i) {
+        const int p = threadIdx.x + 256 * i;
+        const RegionPos q = region_pos<R0>(p < R0 * R0 ? p : 0);
+        const size_t j = input_in_grid(p, mx, my, oy, ox) ? (size_t)(oy - 3 + q.y) * mx + (ox - 3 + q.x) : 0;
+        in.r[i] = r[j];
+        in.k[i] = kh2[j];
     }
 }
 
-// One 16 x 16 output tile (origin oy, ox) with the weight fragments in
-// registers.  Each wave takes two row tiles at a time so that four
-// independent MFMA accumulation chains interleave.  LDS addresses of the 9
-// taps are one base per row tile plus compile-time offsets.
-__device__ __forceinline__ void net_tile(InferLds &S, const cd *__restrict__ r, const unsigned *__restrict__ kh2,
-                                         cd *__restrict__ u, int mx, int my, int oy, int ox, const bf8 (&w1)[2][2],
-                                         const bf8 (&w2)[9][2], const bf8 (&w3)[9], double h2)
+__device__ __forceinline__ void store_tile_input(InferLds &S, const TileInput &in, int mx, int my, int oy, int ox)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int i = 0; i < IN_PER_THREAD; ++i) {
+        const int p = threadIdx.x + 256 * i;
+        const bool ok = input_in_grid(p, mx, my, oy, ox);
+        if (p < R0 * R0)
+            *reinterpret_cast<uint2 *>(&S.x0[p][0]) =
+                ok ? make_uint2(pack_bf16((float)in.r[i].re, (float)in.r[i].im), in.k[i]) : make_uint2(0u, 0u);
+    }
+}
+
+// Layers of one 16 x 16 output tile (origin oy, ox) whose inputs are in
+// S.x0; leaves h^2 N in S.y.  The weight fragments stay in registers.  Each
+// wave takes two row tiles at a time so that four independent MFMA
+// accumulation chains interleave.
+__device__ __forceinline__ void net_layers(InferLds &S, int mx, int my, int oy, int ox, const bf8 (&w1)[2][2],
+                                           const bf8 (&w2)[9][2], const bf8 (&w3)[9], int wave)
+{
+    const int lane = threadIdx.x & 63;
     const int li = lane & 15, lg = lane >> 4;
     const bool odd = (li & 1) != 0;
-    // inputs on the 22 x 22 region (origin oy - 3, ox - 3)
-    for (int p = tid; p < R0 * R0; p += 256) {
-        const RegionPos q = region_pos<R0>(p);
-        const int gy = oy - 3 + q.y, gx = ox - 3 + q.x;
-        const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
-        const size_t j = in ? (size_t)gy * mx + gx : 0;
-        cd rv = r[j];
-        unsigned kv = kh2[j];
-        const float rr = in ? (float)rv.re : 0.f, ri = in ? (float)rv.im : 0.f;
-        const unsigned rp = (unsigned)to_bf16(rr) | ((unsigned)to_bf16(ri) << 16);
-        uint2 v = make_uint2(rp, in ? kv : 0u);
-        *reinterpret_cast<uint2 *>(&S.x0[p][0]) = v;
+    // layer-1 operand: lane group lg holds taps 4 lg .. 4 lg + 3 (taps 9 ..
+    // 15 are zero padding, read from any valid slot and masked)
+    int off1[4];
+    unsigned msk1[4];
+#pragma unroll
+    for (int hh = 0; hh < 4; ++hh) {
+        const int t = 4 * lg + hh;
+        const bool ok = t < 9;
+        off1[hh] = ok ? 2 * ((t / 3 - 1) * R0 + (t % 3 - 1)) : 0;
+        msk1[hh] = ok ? 0xFFFFFFFFu : 0u;
     }
-    __syncthreads();
     // layer 1 on the 20 x 20 region (origin -2)
     for (int rt0 = wave; rt0 < NR1; rt0 += 8) {
         f4 acc[2][2][2];   // [row tile][op][nt]
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int op = 0; op < 2; ++op)
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt) acc[q][op][nt] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             int p = (rt0 + 4 * q) * 16 + li;
@@ -619,38 +665,29 @@ __device__ __forceinline__ void net_tile(InferLds &S, const cd *__restrict__ r, 
                 us8 av;
 #pragma unroll
                 for (int hh = 0; hh < 4; ++hh) {
-                    // tap t = 4 lg + hh (taps 9 .. 15 are zero padding)
-                    unsigned v = 0;
-#pragma unroll
-                    for (int g = 0; g < 4; ++g)
-                        if (lg == g && 4 * g + hh < 9) {
-                            const int t = 4 * g + hh;
-                            v = base[2 * (tap_dy(t) * R0 + tap_dx(t)) + op];
-                        }
+                    const unsigned v = base[off1[hh] + op] & msk1[hh];
                     av[2 * hh] = (unsigned short)(v & 0xFFFFu);
                     av[2 * hh + 1] = (unsigned short)(v >> 16);
                 }
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt)
-                    acc[q][op][nt] =
-                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(av), w1[op][nt], acc[q][op][nt], 0, 0, 0);
+                    acc[q][op][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(av), w1[op][nt],
+                                                                             f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
             }
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int rt = rt0 + 4 * q;
-            int pp = rt * 16 + 4 * lg;
-            RegionPos P = region_pos<R1>(pp < R1 * R1 ? pp : 0);
+            if (rt >= NR1) break;
+            const int pp = rt * 16 + 4 * lg;
+            RegionPos P = region_pos<R1>(pp);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const float x0 = gate(acc[q][0][0][v], acc[q][1][0][v], odd);
                 const float x1 = gate(acc[q][0][1][v], acc[q][1][1][v], odd);
-                if (rt < NR1 && pp + v < R1 * R1) {
-                    const int gy = oy - 2 + P.y, gx = ox - 2 + P.x;
-                    const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
-                    S.x1[pp + v][li] = in ? to_bf16(x0) : 0;
-                    S.x1[pp + v][16 + li] = in ? to_bf16(x1) : 0;
-                }
+                const int gy = oy - 2 + P.y, gx = ox - 2 + P.x;
+                const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
+                *reinterpret_cast<unsigned *>(&S.x1[pp + v][2 * li]) = in ? pack_bf16(x0, x1) : 0u;
                 region_next<R1>(P);
             }
         }
@@ -669,75 +706,84 @@ __device__ __forceinline__ void net_tile(InferLds &S, const cd *__restrict__ r, 
 #pragma unroll
             for (int nt = 0; nt < 2; ++nt) acc[q][nt] = f4{0.f, 0.f, 0.f, 0.f};
         }
+        us8 a[2];
 #pragma unroll
-        for (int t = 0; t < 9; ++t)
+        for (int q = 0; q < 2; ++q) a[q] = base[q][(tap_dy(0) * R1 + tap_dx(0)) * (XS / 8)];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const us8 a = base[q][(tap_dy(t) * R1 + tap_dx(t)) * (XS / 8)];
+        for (int t = 0; t < 9; ++t) {
+            us8 an[2];
+            if (t + 1 < 9) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) an[q] = base[q][(tap_dy(t + 1) * R1 + tap_dx(t + 1)) * (XS / 8)];
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int nt = 0; nt < 2; ++nt)
-                    acc[q][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), w2[t][nt], acc[q][nt], 0, 0, 0);
+                    acc[q][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[q]), w2[t][nt], acc[q][nt], 0, 0, 0);
+            if (t + 1 < 9) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) a[q] = an[q];
             }
+        }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int rt = rt0 + 4 * q;
-            int pp = rt * 16 + 4 * lg;
-            RegionPos P = region_pos<R2>(pp < R2 * R2 ? pp : 0);
+            if (rt >= NR2) break;
+            const int pp = rt * 16 + 4 * lg;
+            RegionPos P = region_pos<R2>(pp);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                if (rt < NR2 && pp + v < R2 * R2) {
-                    const int gy = oy - 1 + P.y, gx = ox - 1 + P.x;
-                    const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
-                    S.x2[pp + v][li] = in ? to_bf16(acc[q][0][v]) : 0;
-                    S.x2[pp + v][16 + li] = in ? to_bf16(acc[q][1][v]) : 0;
-                }
+                const int gy = oy - 1 + P.y, gx = ox - 1 + P.x;
+                const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
+                *reinterpret_cast<unsigned *>(&S.x2[pp + v][2 * li]) = in ? pack_bf16(acc[q][0][v], acc[q][1][v]) : 0u;
                 region_next<R2>(P);
             }
         }
     }
     __syncthreads();
-    // layer 3 on the 16 x 16 tile: row tile rt = tile row rt
+    // layer 3 on the 16 x 16 tile: row tiles wave, wave + 4, wave + 8, wave + 12
     {
-        const int rt0 = wave;   // rows wave, wave + 4, wave + 8, wave + 12
         f4 acc[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-        const us8 *base = reinterpret_cast<const us8 *>(&S.x2[(rt0 + 1) * R2 + li + 1][8 * lg]);
+        const us8 *base = reinterpret_cast<const us8 *>(&S.x2[(wave + 1) * R2 + li + 1][8 * lg]);
+        us8 a[4];
 #pragma unroll
-        for (int t = 0; t < 9; ++t)
+        for (int q = 0; q < 4; ++q) a[q] = base[((4 * q + tap_dy(0)) * R2 + tap_dx(0)) * (XS / 8)];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const us8 a = base[((4 * q + tap_dy(t)) * R2 + tap_dx(t)) * (XS / 8)];
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), w3[t], acc[q], 0, 0, 0);
+        for (int t = 0; t < 9; ++t) {
+            us8 an[4];
+            if (t + 1 < 9) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) an[q] = base[((4 * q + tap_dy(t + 1)) * R2 + tap_dx(t + 1)) * (XS / 8)];
             }
-        // column 0 (Re) in lanes li = 0, column 1 (Im) in li = 1
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            f4 im;
+            for (int q = 0; q < 4; ++q)
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[q]), w3[t], acc[q], 0, 0, 0);
+            if (t + 1 < 9) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) im[v] = __shfl_down(acc[q][v], 1, 64);
-            const int gy = oy + rt0 + 4 * q;
-            if (li == 0 && gy < my) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int gx = ox + 4 * lg + v;
-                    if (gx < mx) {
-                        const size_t j = (size_t)gy * mx + gx;
-                        cd uv = u[j];
-                        u[j] = cd{uv.re + h2 * (double)acc[q][v], uv.im + h2 * (double)im[v]};
-                    }
-                }
+                for (int q = 0; q < 4; ++q) a[q] = an[q];
             }
         }
+        // column 0 (Re) in lanes li = 0, column 1 (Im) in li = 1
+        if (li < 2) {
+            float *y = reinterpret_cast<float *>(S.y);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) y[2 * ((wave + 4 * q) * IT + 4 * lg + v) + li] = acc[q][v];
+        }
     }
-    __syncthreads();   // the LDS is reused by the next tile
 }
 
 // N is complex-linear in its residual input, so s h^2 N(r / s) = h^2 N(r)
 // for any scale s; BF16 has the exponent range of FP32, so the residual is
 // fed unscaled and no global reduction precedes the step.  Persistent
 // workgroups: each loads the weight fragments once and works through a
-// contiguous range of tiles (ranges of neighbouring workgroups sit on one XCD).
+// contiguous range of tiles (ranges of neighbouring workgroups sit on one
+// XCD); the inputs of the next tile are loaded while the current one is
+// computed, and u is updated by all threads, one point each.
 __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, const unsigned *__restrict__ kh2,
                                                    cd *__restrict__ u, int mx, int my, int tiles_x, int ntiles,
                                                    int per_block, const us8 *__restrict__ wfrag, double h2,
@@ -745,7 +791,8 @@ __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, con
 {
     if (stop && *stop) return;
     __shared__ InferLds S;
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     bf8 w1[2][2], w2[9][2], w3[9];
 #pragma unroll
     for (int op = 0; op < 2; ++op)
@@ -759,9 +806,35 @@ __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, con
     for (int t = 0; t < 9; ++t) w3[t] = as_bf8(wfrag[256 + 1152 + t * 64 + lane]);
     const int first = xcd_tile(blockIdx.x, gridDim.x) * per_block;
     const int last = min(first + per_block, ntiles);
-    for (int tile = first; tile < last; ++tile)
-        net_tile(S, r, kh2, u, mx, my, (tile / tiles_x) * IT, (tile % tiles_x) * IT, w1, w2, w3, h2);
+    if (first >= last) return;
+    TileInput in;
+    load_tile_input(in, r, kh2, mx, my, (first / tiles_x) * IT, (first % tiles_x) * IT);
+    // this thread's output point of the tile
+    const int py = tid >> 4, px = tid & 15;
+    for (int tile = first; tile < last; ++tile) {
+        const int oy = (tile / tiles_x) * IT, ox = (tile % tiles_x) * IT;
+        store_tile_input(S, in, mx, my, oy, ox);
+        __syncthreads();
+        if (tile + 1 < last)
+            load_tile_input(in, r, kh2, mx, my, ((tile + 1) / tiles_x) * IT, ((tile + 1) % tiles_x) * IT);
+        const int gy = oy + py, gx = ox + px;
+        const bool mine = gy < my && gx < mx;
+        const size_t j = mine ? (size_t)gy * mx + gx : 0;
+        const cd uv = u[j];
+        net_layers(S, mx, my, oy, ox, w1, w2, w3, wave);
+        __syncthreads();
+        if (mine) {
+            const float2 yv = S.y[tid];
+            u[j] = cd{uv.re + h2 * (double)yv.x, uv.im + h2 * (double)yv.y};
+        }
+        // the next tile's layers start after its input barrier, so S.y and
+        // the activations are not overwritten before they are read here
+    }
 }
+
+// Channel and Re / Im part held in activation slot s (see InferLds).
+static int slot_channel(int s) { return (16 * (s & 1) + (s >> 1)) / 2; }
+static int slot_part(int s) { return (s >> 1) & 1; }
 
 // MFMA B-operand fragments of the three layers from the complex weights
 // (rounded to BF16): 64 lanes x 8 values per fragment, in the order read by
@@ -794,18 +867,18 @@ void pack_net_mfma(const float *w, unsigned short *out)
         for (int nt = 0; nt < 2; ++nt)
             for (int lane = 0; lane < 64; ++lane)
                 for (int e = 0; e < 8; ++e) {
-                    const int ch = 8 * (lane / 16) + e, j = 16 * nt + lane % 16;
-                    const int i = ch / 2, pi = ch % 2, oc = j / 2, po = j % 2;
+                    const int slot = 8 * (lane / 16) + e, j = 16 * nt + lane % 16;
+                    const int i = slot_channel(slot), pi = slot_part(slot), oc = j / 2, po = j % 2;
                     const int idx = (t * 16 + oc) * 16 + i;
                     out[o++] = bf(real_block(W(NET_W2, idx, 0), W(NET_W2, idx, 1), po, pi));
                 }
     for (int t = 0; t < 9; ++t)
         for (int lane = 0; lane < 64; ++lane)
             for (int e = 0; e < 8; ++e) {
-                const int ch = 8 * (lane / 16) + e, j = lane % 16;
+                const int slot = 8 * (lane / 16) + e, j = lane % 16;
                 float v = 0.f;
                 if (j < 2) {
-                    const int i = ch / 2, pi = ch % 2;
+                    const int i = slot_channel(slot), pi = slot_part(slot);
                     const int idx = t * 16 + i;
                     v = real_block(W(NET_W3, idx, 0), W(NET_W3, idx, 1), j, pi);
                 }
