@@ -512,9 +512,12 @@ void launch_round_weights(const float2 *Wm, float2 *Wq, hipStream_t s)
 // channels (Re / Im of each complex channel), K the (tap, real input
 // channel) pairs.  A complex weight w acts on (Re x, Im x) as the real 2 x 2
 // block [[Re w, -Im w], [Im w, Re w]].
-//   layer 1: a from r~ and m from kappa~, each K = 9 taps x 2, padded to 32
-//            (one k-step each); the gate x1 = a (1 + m) pairs the Re / Im
-//            columns of neighbouring lanes
+//   layer 1: K = 9 taps x 2 (Re / Im), padded to 32, one k-step.  For the
+//            column of part p of channel c, four products give
+//            A = p of a, A' = (-Im a, Re a)[p], M = 1 + Re m (accumulator
+//            started at 1), M' = Im m, and the gate is x1 = A M + A' M'
+//            (Re: a_re (1 + m_re) - a_im m_im; Im: a_im (1 + m_re) +
+//            a_re m_im) without any exchange between lanes
 //   layer 2: K = 32 channels per tap, one k-step per tap; N = 32
 //   layer 3: K as layer 2; N = 2 (padded to 16)
 // A 16 x 16 output tile needs layer-2 values on 18 x 18 points, layer-1
@@ -538,7 +541,7 @@ constexpr int IN_PER_THREAD = (R0 * R0 + 255) / 256;
 // column li of both column tiles writes slots 2 li and 2 li + 1 as one dword;
 // column j is Re (j even) or Im (j odd) of channel j / 2.
 constexpr int XS = 40;
-struct InferLds {
+struct alignas(16) InferLds {
     unsigned short x0[R0 * R0][4];           // r~ re, r~ im, kappa~ re, kappa~ im
     unsigned short x1[NR1 * 16][XS];
     unsigned short x2[NR2 * 16][XS];         // rows past R2 * R2 take unused writes
@@ -547,28 +550,13 @@ struct InferLds {
 
 __device__ __forceinline__ bf8 as_bf8(us8 v) { return __builtin_bit_cast(bf8, v); }
 
-// Value of the neighbouring lane (lane ^ 1) through a DPP quad permutation.
-__device__ __forceinline__ float swap_pair(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
-}
-
-// Gate of layer 1 for one accumulator element: lane column j = 16 nt + li
-// is Re (li even) or Im (li odd) of channel j / 2, the partner lane li ^ 1
-// holds the other part.  Re: a_re (1 + m_re) - a_im m_im;
-// Im: a_re m_im + a_im (1 + m_re).
-__device__ __forceinline__ float gate(float am, float mm, bool odd)
-{
-    const float ap = swap_pair(am), mp = swap_pair(mm);
-    const float s1 = odd ? mp : mm, s2 = odd ? mm : -mp;
-    return am * (1.f + s1) + ap * s2;
-}
-
 // Hardware round-to-nearest-even FP32 -> BF16 (v_cvt_pk_bf16_f32 on gfx950).
 __device__ __forceinline__ unsigned short to_bf16(float f) { return __builtin_bit_cast(unsigned short, (__bf16)f); }
+typedef float fv2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bv2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned pack_bf16(float lo, float hi)
 {
-    return (unsigned)to_bf16(lo) | ((unsigned)to_bf16(hi) << 16);
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(fv2{lo, hi}, bv2));
 }
 
 // Point (y, x) of row-major region of width R for index p.
@@ -633,63 +621,61 @@ __device__ __forceinline__ void store_tile_input(InferLds &S, const TileInput &i
 // Layers of one 16 x 16 output tile (origin oy, ox) whose inputs are in
 // S.x0; leaves h^2 N in S.y.  The weight fragments stay in registers.  Each
 // wave takes two row tiles at a time so that four independent MFMA
-// accumulation chains interleave.
-__device__ __forceinline__ void net_layers(InferLds &S, int mx, int my, int oy, int ox, const bf8 (&w1)[2][2],
+// accumulation chains interleave.  EDGE: the tile's layer-1 region reaches
+// outside the grid, so activations there are set to zero (interior tiles
+// skip the test).
+template <bool EDGE>
+__device__ __forceinline__ void net_layers(InferLds &S, int mx, int my, int oy, int ox, const bf8 (&w1)[4][2],
                                            const bf8 (&w2)[9][2], const bf8 (&w3)[9], int wave)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lg = lane >> 4;
-    const bool odd = (li & 1) != 0;
-    // layer-1 operand: lane group lg holds taps 4 lg .. 4 lg + 3 (taps 9 ..
-    // 15 are zero padding, read from any valid slot and masked)
+    // layer-1 operand: lane group lg holds taps 4 lg .. 4 lg + 3; taps 9 ..
+    // 15 are zero padding whose weights are zero, so they may read any
+    // (finite) slot: the point itself
     int off1[4];
-    unsigned msk1[4];
 #pragma unroll
     for (int hh = 0; hh < 4; ++hh) {
         const int t = 4 * lg + hh;
-        const bool ok = t < 9;
-        off1[hh] = ok ? 2 * ((t / 3 - 1) * R0 + (t % 3 - 1)) : 0;
-        msk1[hh] = ok ? 0xFFFFFFFFu : 0u;
+        off1[hh] = t < 9 ? 2 * ((t / 3 - 1) * R0 + (t % 3 - 1)) : 0;
     }
-    // layer 1 on the 20 x 20 region (origin -2)
-    for (int rt0 = wave; rt0 < NR1; rt0 += 8) {
-        f4 acc[2][2][2];   // [row tile][op][nt]
+    // layer 1 on the 20 x 20 region (origin -2), one row tile at a time
+    for (int rt = wave; rt < NR1; rt += 4) {
+        const int p = rt * 16 + li;
+        const RegionPos P = region_pos<R1>(p);
+        const uint2 *base = reinterpret_cast<const uint2 *>(&S.x0[(P.y + 1) * R0 + P.x + 1][0]);
+        us8 ar, ak;   // the r~ and kappa~ operands
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            int p = (rt0 + 4 * q) * 16 + li;
-            if (p >= R1 * R1) p = 0;
-            const RegionPos P = region_pos<R1>(p);
-            const unsigned *base = reinterpret_cast<const unsigned *>(&S.x0[(P.y + 1) * R0 + P.x + 1][0]);
-#pragma unroll
-            for (int op = 0; op < 2; ++op) {
-                us8 av;
-#pragma unroll
-                for (int hh = 0; hh < 4; ++hh) {
-                    const unsigned v = base[off1[hh] + op] & msk1[hh];
-                    av[2 * hh] = (unsigned short)(v & 0xFFFFu);
-                    av[2 * hh + 1] = (unsigned short)(v >> 16);
-                }
-#pragma unroll
-                for (int nt = 0; nt < 2; ++nt)
-                    acc[q][op][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(av), w1[op][nt],
-                                                                             f4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-            }
+        for (int hh = 0; hh < 4; ++hh) {
+            const uint2 v = base[off1[hh] / 2];
+            ar[2 * hh] = (unsigned short)(v.x & 0xFFFFu);
+            ar[2 * hh + 1] = (unsigned short)(v.x >> 16);
+            ak[2 * hh] = (unsigned short)(v.y & 0xFFFFu);
+            ak[2 * hh + 1] = (unsigned short)(v.y >> 16);
         }
+        float x[2][4];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int rt = rt0 + 4 * q;
-            if (rt >= NR1) break;
-            const int pp = rt * 16 + 4 * lg;
-            RegionPos P = region_pos<R1>(pp);
+        for (int nt = 0; nt < 2; ++nt) {
+            const f4 z = f4{0.f, 0.f, 0.f, 0.f}, one = f4{1.f, 1.f, 1.f, 1.f};
+            const f4 A = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ar), w1[0][nt], z, 0, 0, 0);
+            const f4 Ap = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ar), w1[1][nt], z, 0, 0, 0);
+            const f4 M = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ak), w1[2][nt], one, 0, 0, 0);
+            const f4 Mp = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(ak), w1[3][nt], z, 0, 0, 0);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float x0 = gate(acc[q][0][0][v], acc[q][1][0][v], odd);
-                const float x1 = gate(acc[q][0][1][v], acc[q][1][1][v], odd);
-                const int gy = oy - 2 + P.y, gx = ox - 2 + P.x;
+            for (int v = 0; v < 4; ++v) x[nt][v] = fmaf(A[v], M[v], Ap[v] * Mp[v]);
+        }
+        const int pp = rt * 16 + 4 * lg;
+        RegionPos Q = region_pos<R1>(pp);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            unsigned val = pack_bf16(x[0][v], x[1][v]);
+            if (EDGE) {
+                const int gy = oy - 2 + Q.y, gx = ox - 2 + Q.x;
                 const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
-                *reinterpret_cast<unsigned *>(&S.x1[pp + v][2 * li]) = in ? pack_bf16(x0, x1) : 0u;
-                region_next<R1>(P);
+                val = in ? val : 0u;
+                region_next<R1>(Q);
             }
+            *reinterpret_cast<unsigned *>(&S.x1[pp + v][2 * li]) = val;
         }
     }
     __syncthreads();
@@ -734,10 +720,14 @@ __device__ __forceinline__ void net_layers(InferLds &S, int mx, int my, int oy, 
             RegionPos P = region_pos<R2>(pp);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int gy = oy - 1 + P.y, gx = ox - 1 + P.x;
-                const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
-                *reinterpret_cast<unsigned *>(&S.x2[pp + v][2 * li]) = in ? pack_bf16(acc[q][0][v], acc[q][1][v]) : 0u;
-                region_next<R2>(P);
+                unsigned val = pack_bf16(acc[q][0][v], acc[q][1][v]);
+                if (EDGE) {
+                    const int gy = oy - 1 + P.y, gx = ox - 1 + P.x;
+                    const bool in = gy >= 0 && gy < my && gx >= 0 && gx < mx;
+                    val = in ? val : 0u;
+                    region_next<R2>(P);
+                }
+                *reinterpret_cast<unsigned *>(&S.x2[pp + v][2 * li]) = val;
             }
         }
     }
@@ -793,17 +783,17 @@ __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, con
     __shared__ InferLds S;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    bf8 w1[2][2], w2[9][2], w3[9];
+    bf8 w1[4][2], w2[9][2], w3[9];
 #pragma unroll
-    for (int op = 0; op < 2; ++op)
+    for (int ty = 0; ty < 4; ++ty)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) w1[op][nt] = as_bf8(wfrag[(op * 2 + nt) * 64 + lane]);
+        for (int nt = 0; nt < 2; ++nt) w1[ty][nt] = as_bf8(wfrag[(ty * 2 + nt) * 64 + lane]);
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) w2[t][nt] = as_bf8(wfrag[256 + (t * 2 + nt) * 64 + lane]);
+        for (int nt = 0; nt < 2; ++nt) w2[t][nt] = as_bf8(wfrag[512 + (t * 2 + nt) * 64 + lane]);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) w3[t] = as_bf8(wfrag[256 + 1152 + t * 64 + lane]);
+    for (int t = 0; t < 9; ++t) w3[t] = as_bf8(wfrag[512 + 1152 + t * 64 + lane]);
     const int first = xcd_tile(blockIdx.x, gridDim.x) * per_block;
     const int last = min(first + per_block, ntiles);
     if (first >= last) return;
@@ -821,7 +811,12 @@ __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, con
         const bool mine = gy < my && gx < mx;
         const size_t j = mine ? (size_t)gy * mx + gx : 0;
         const cd uv = u[j];
-        net_layers(S, mx, my, oy, ox, w1, w2, w3, wave);
+        // the layer-1 region (origin -2, side 20) lies inside the grid
+        const bool interior = oy >= 2 && ox >= 2 && oy + IT + 2 <= my && ox + IT + 2 <= mx;
+        if (interior)
+            net_layers<false>(S, mx, my, oy, ox, w1, w2, w3, wave);
+        else
+            net_layers<true>(S, mx, my, oy, ox, w1, w2, w3, wave);
         __syncthreads();
         if (mine) {
             const float2 yv = S.y[tid];
@@ -848,9 +843,11 @@ void pack_net_mfma(const float *w, unsigned short *out)
     };
     auto bf = [](float f) { return (unsigned short)bf16_bits(f); };
     size_t o = 0;
-    // layer 1: operand op (0: the r~ weights, 1: the kappa~ weights),
-    // k = 2 tap + part (k < 18)
-    for (int op = 0; op < 2; ++op)
+    // layer 1, k = 2 tap + part (k < 18); four products per column j (part
+    // po of channel j / 2): type 0 A = part po of a, type 1
+    // A' = (-Im a, Re a)[po] (both from the r~ weights), type 2 Re m, type 3
+    // Im m (both from the kappa~ weights)
+    for (int ty = 0; ty < 4; ++ty)
         for (int nt = 0; nt < 2; ++nt)
             for (int lane = 0; lane < 64; ++lane)
                 for (int e = 0; e < 8; ++e) {
@@ -858,8 +855,14 @@ void pack_net_mfma(const float *w, unsigned short *out)
                     float v = 0.f;
                     if (k < 18) {
                         const int t = k / 2, pi = k % 2, oc = j / 2, po = j % 2;
-                        const int idx = (t * 16 + oc) * 2 + op;
-                        v = real_block(W(NET_W1, idx, 0), W(NET_W1, idx, 1), po, pi);
+                        const int idx = (t * 16 + oc) * 2 + (ty < 2 ? 0 : 1);
+                        const float re = W(NET_W1, idx, 0), im = W(NET_W1, idx, 1);
+                        switch (ty) {
+                        case 0: v = real_block(re, im, po, pi); break;
+                        case 1: v = po == 0 ? -real_block(re, im, 1, pi) : real_block(re, im, 0, pi); break;
+                        case 2: v = real_block(re, im, 0, pi); break;
+                        default: v = real_block(re, im, 1, pi); break;
+                        }
                     }
                     out[o++] = bf(v);
                 }
@@ -886,7 +889,7 @@ void pack_net_mfma(const float *w, unsigned short *out)
             }
 }
 
-size_t net_mfma_frag_count() { return (size_t)(4 + 18 + 9) * 64 * 8; }
+size_t net_mfma_frag_count() { return (size_t)(8 + 18 + 9) * 64 * 8; }
 
 // kappa h^2 as packed BF16 complex
 __global__ __launch_bounds__(256) void k_kappa_h2(const cd *__restrict__ q, double k02, double h2, size_t N,
