@@ -5,7 +5,8 @@ variant of a family computes the same bits with a different tile shape, and
 which one is fastest depends on the device and on the problem's shapes.  This
 module keys a choice by (device architecture, tunable, dimension, interior
 extents, number of directions, precision), runs the library's own timing
-sweep (``mg_tune_farfield``) on a cache miss, and stores the winner.
+sweep (``mg_tune_farfield``, ``mg_tune_solve``) on a cache miss, and stores
+the winner.
 
 The cache is a flat JSON object ``{key: {"variant": v, "ms": [...]}}``; a
 missing or unreadable file is an empty cache.
@@ -70,5 +71,26 @@ def tune_farfield(h: "ffmg.Handle", eta, u, dirs, ff_precision: int, path: Optio
         return hit["variant"]
     best, times = ffmg.mg_tune_farfield(h, eta, u, dirs, reps=reps)
     cache[k] = {"variant": best, "ms": [round(t, 5) for t in times]}
+    save(cache, path)
+    return best
+
+
+def tune_solve(h: "ffmg.Handle", b, u, precision: int, tol: float = 1e-10, path: Optional[str] = None,
+               reps: int = 3, force: bool = False) -> int:
+    """Select the LDS-tail variant of the fused 2D cycle for this handle: from
+    the cache, or by timing whole solves per variant (then cached; u is
+    overwritten).  Returns the variant."""
+    nv = ffmg.mg_tune_variants(h, ffmg.TUNE_TAIL)
+    if nv <= 1:
+        return 0
+    shape = [m for m in h.level_shape(0) if m > 1]
+    k = key(device_arch(), ffmg.TUNE_TAIL, len(shape), shape, 0, precision)
+    cache = load(path)
+    hit = cache.get(k)
+    if not force and isinstance(hit, dict) and isinstance(hit.get("variant"), int) and 0 <= hit["variant"] < nv:
+        ffmg.mg_tune_set(h, hit["variant"], ffmg.TUNE_TAIL)
+        return hit["variant"]
+    best, times = ffmg.mg_tune_solve(h, b, u, tol=tol, reps=reps)
+    cache[k] = {"variant": best, "ms": [round(t, 4) for t in times]}
     save(cache, path)
     return best

@@ -273,12 +273,24 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
     return FFMG_OK;
 }
 
+// Unique per handle configuration of this process (keys batched workspaces).
+uint64_t next_handle_serial()
+{
+    static std::atomic<uint64_t> next{1};
+    return next++;
+}
+
+// Largest level of the LDS tail per FFMG_TUNE_TAIL variant (interior points).
+constexpr int TAIL_POINTS[] = {4096, 1024, 256};
+constexpr int TAIL_VARIANTS = (int)(sizeof(TAIL_POINTS) / sizeof(TAIL_POINTS[0]));
+
 // Coarse levels handled by the one-workgroup LDS tail (2D): the longest
 // run of levels l >= 1 ending at the coarsest level whose b, u, t fit in LDS
-// and that hold at most 4096 points each.
+// and that hold at most TAIL_POINTS[tail_variant] points each.
 template <typename T>
 void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
 {
+    const size_t max_points = (size_t)TAIL_POINTS[h->tail_variant];
     tp = TailParams<T>{};
     lds = 0;
     const int nl = (int)h->L.size();
@@ -289,7 +301,7 @@ void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
     for (int l = nl - 1; l >= 1; --l) {
         const Level &lv = h->L[l];
         size_t add = 3 * lv.g.N() * sizeof(cx<T>);
-        if (lv.g.N() > 4096 || bytes + add > budget || nl - l > TAIL_MAX_LEVELS) break;
+        if (lv.g.N() > max_points || bytes + add > budget || nl - l > TAIL_MAX_LEVELS) break;
         bytes += add;
         top = l;
     }
@@ -588,9 +600,8 @@ ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle *
 {
     if (!out) return FFMG_EINVAL;
     *out = nullptr;
-    static std::atomic<uint64_t> next_serial{1};
     ffmg_handle *h = new ffmg_handle();
-    h->serial = next_serial++;
+    h->serial = next_handle_serial();
     ffmg_status st = validate_problem(p, o, h);
     if (st == FFMG_OK) {
         h->prob = *p;
@@ -943,11 +954,33 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
     return FFMG_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// Re-plans both tails for variant v; batched workspaces built for the old
+// tail are rebuilt (they are keyed by the handle serial).
+void set_tail_variant(ffmg_handle *h, int v)
+{
+    if (v == h->tail_variant) return;
+    h->tail_variant = v;
+    plan_tail<double>(h, h->tail64, h->tail_lds[0]);
+    if (h->opt.precision == FFMG_FP32_IR) plan_tail<float>(h, h->tail32, h->tail_lds[1]);
+    h->serial = next_handle_serial();
+}
+}  // namespace
+
+extern "C" {
+
 int mg_tune_variants(const ffmg_handle *h, int tunable)
 {
     if (!h) return 0;
     switch (tunable) {
     case FFMG_TUNE_FF_GEMM: return (h->opt.ff_precision == FFMG_FF_FP64) ? 1 : ff_plan_variants();
+    case FFMG_TUNE_TAIL:
+        return (h->prob.dim == 2 && h->opt.tile_config == TILE_FUSED && h->opt.smoother != FFMG_SMOOTH_LEARNED &&
+                h->tail64.nt > 0)
+                   ? TAIL_VARIANTS
+                   : 1;
     default: return 0;
     }
 }
@@ -961,6 +994,7 @@ ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant)
                    : (h->ff_variant < 0)                 ? ff_plan_default_variant()
                                                          : h->ff_variant;
         return FFMG_OK;
+    case FFMG_TUNE_TAIL: *variant = h->tail_variant; return FFMG_OK;
     default: return FFMG_EINVAL;
     }
 }
@@ -976,6 +1010,7 @@ ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant)
         h->ff_variant = variant;
         if (h->ff) ff_plan_set_variant(h->ff, variant);
         return FFMG_OK;
+    case FFMG_TUNE_TAIL: set_tail_variant(h, variant); return FFMG_OK;
     default: return fail(h, FFMG_EINVAL, "unknown tunable %d", tunable);
     }
 }
@@ -1025,6 +1060,36 @@ ffmg_status mg_tune_farfield(ffmg_handle *h, const double eta[3], const void *u,
         h->ff_variant = arg;
         ff_plan_set_variant(h->ff, arg);
     }
+    if (best) *best = arg;
+    return FFMG_OK;
+}
+
+ffmg_status mg_tune_solve(ffmg_handle *h, const void *b, void *u, double tol, int reps, double *times_ms, int n_times,
+                          int *best)
+{
+    if (!h || !b || !u || reps < 1) return fail(h, FFMG_EINVAL, "null argument or reps < 1");
+    const int nv = mg_tune_variants(h, FFMG_TUNE_TAIL);
+    const size_t bytes = h->L[0].g.N() * sizeof(cd);
+    int arg = h->tail_variant;
+    double tbest = 0.0;
+    for (int v = 0; v < nv; ++v) {
+        set_tail_variant(h, v);
+        double t = 0.0;
+        for (int r = 0; r <= reps; ++r) {
+            HIPCHK(h, hipMemsetAsync(u, 0, bytes, h->stream));
+            ffmg_solve_info inf{};
+            ffmg_status st = mg_solve(h, b, u, tol, &inf);
+            if (st != FFMG_OK) return st;
+            if (r > 0) t += inf.t_solve_ms;
+        }
+        t /= reps;
+        if (times_ms && v < n_times) times_ms[v] = t;
+        if (v == 0 || t < tbest) {
+            tbest = t;
+            arg = v;
+        }
+    }
+    set_tail_variant(h, arg);
     if (best) *best = arg;
     return FFMG_OK;
 }

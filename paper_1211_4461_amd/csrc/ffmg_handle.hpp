@@ -50,6 +50,7 @@ struct ffmg_handle {
     // coarse end of the 2D cycle run by one workgroup in LDS (levels >= tail_l)
     int tail_l = -1;
     size_t tail_lds[2] = {0, 0};     // [FP64, FP32]
+    int tail_variant = 0;            // index into TAIL_POINTS (autotuned)
     ffmg::TailParams<double> tail64{};
     ffmg::TailParams<float> tail32{};
     ffmg::FarFieldPlan *ff = nullptr;

@@ -61,7 +61,7 @@ _lib = None
 EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup", "mg_rhs_plane_wave",
            "mg_vcycle", "mg_solve", "farfield_map", "mg_apply", "mg_smooth", "mg_residual_norm",
            "mg_num_levels", "mg_level_shape", "mg_destroy", "mg_profile_enable", "mg_profile_read",
-           "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_solve_batched",
+           "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_tune_solve", "mg_solve_batched",
            "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights", "ml_loss_grad",
            "ml_train_step", "ml_net_last_error", "ml_net_destroy", "mg_learned_smooth", "mg_jacobi_factor"]
 
@@ -99,6 +99,7 @@ def lib():
     L.mg_tune_get.argtypes = [vp, ip, ctypes.POINTER(ip)]
     L.mg_tune_set.argtypes = [vp, ip, ip]
     L.mg_tune_farfield.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(dp), ip, ctypes.POINTER(ip)]
+    L.mg_tune_solve.argtypes = [vp, vp, vp, dp, ip, ctypes.POINTER(dp), ip, ctypes.POINTER(ip)]
     L.mg_solve_batched.argtypes = [vp, ip, vp, vp, dp, vp]
     fp = ctypes.POINTER(ctypes.c_float)
     L.ml_net_create.argtypes = [fp, vp, ctypes.POINTER(vp)]
@@ -117,8 +118,8 @@ def lib():
     L.farfield_map_batched.argtypes = [vp, ip, vp, vp, ip, vp, vp]
     for name in ("mg_setup", "mg_rhs_plane_wave", "mg_vcycle", "mg_solve", "farfield_map", "mg_apply",
                  "mg_smooth", "mg_residual_norm", "mg_level_shape", "mg_profile_enable", "mg_profile_read",
-                 "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_solve_batched",
-                 "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights",
+                 "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_tune_solve",
+                 "mg_solve_batched", "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights",
                  "ml_loss_grad", "ml_train_step"):
         getattr(L, name).restype = ip
     _lib = L
@@ -266,6 +267,7 @@ def farfield_map(h: Handle, eta, u, dirs, out=None):
 
 
 TUNE_FF_GEMM = 0
+TUNE_TAIL = 1
 
 
 def _etas(etas):
@@ -337,6 +339,17 @@ def mg_tune_farfield(h: Handle, eta, u, dirs, reps=5):
     up = None if u is None else _dev_ptr(u, "u")
     h._check(lib().mg_tune_farfield(h.ptr, _eta3(eta), up, d.shape[0], ctypes.c_void_p(d.ctypes.data), int(reps),
                                     times, nv, ctypes.byref(best)), "mg_tune_farfield")
+    return best.value, list(times)
+
+
+def mg_tune_solve(h: Handle, b, u, tol=1e-10, reps=3):
+    """Time `reps` solves per LDS-tail variant (u is overwritten); selects the
+    fastest.  Returns (best, [ms per variant])."""
+    nv = max(mg_tune_variants(h, TUNE_TAIL), 1)
+    times = (ctypes.c_double * nv)()
+    best = ctypes.c_int()
+    h._check(lib().mg_tune_solve(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol), int(reps), times, nv,
+                                 ctypes.byref(best)), "mg_tune_solve")
     return best.value, list(times)
 
 

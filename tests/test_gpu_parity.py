@@ -308,6 +308,61 @@ def test_fused_2d_path_is_bitwise_identical(ff, orc, n):
             assert torch.equal(uf, ur2)
 
 
+@pytest.mark.parametrize("n", [256, 512])
+def test_tail_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path):
+    """The LDS tail runs the per-point arithmetic of the grid-wide kernels, so
+    every tail size gives the same iterates bit for bit (FP64 V-cycles and
+    FP32-in-FP64 solves); the solve-timing sweep selects one of them and the
+    cached choice is applied to a second handle; a batch built before a tail
+    change is rebuilt and still equals the single solve."""
+    from paper_1211_4461_amd import autotune
+    w = W.bumps_2d(n=n, seed=n + 1, k0=1.2, M=8)
+    h64, _, g, _, _, _ = setup(ff, orc, w)
+    nv = ff.mg_tune_variants(h64, ff.TUNE_TAIL)
+    assert nv == 3
+    b = ff.mg_rhs_plane_wave(h64, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+    ref = None
+    for v in range(nv):
+        ff.mg_tune_set(h64, v, ff.TUNE_TAIL)
+        assert ff.mg_tune_get(h64, ff.TUNE_TAIL) == v
+        u = torch.zeros_like(b)
+        for _ in range(3):
+            ff.mg_vcycle(h64, b, u)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = u.clone()
+        assert torch.equal(u, ref), v
+    h32, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR)
+    sols = []
+    for v in range(nv):
+        ff.mg_tune_set(h32, v, ff.TUNE_TAIL)
+        u = torch.zeros_like(b)
+        info = ff.mg_solve(h32, b, u)
+        sols.append((info.cycles, info.rel_residual, u))
+    for c, r, u in sols[1:]:
+        assert c == sols[0][0] and r == sols[0][1] and torch.equal(u, sols[0][2])
+    ub = [torch.zeros_like(b)]
+    ff.mg_solve_batched([h32], [w.eta], ub)
+    assert torch.equal(ub[0], sols[0][2])
+    ws = torch.zeros_like(b)
+    best, times = ff.mg_tune_solve(h32, b, ws, tol=1e-10, reps=1)
+    assert 0 <= best < nv and len(times) == nv and times[best] == min(times)
+    assert ff.mg_tune_get(h32, ff.TUNE_TAIL) == best
+    assert torch.equal(ws, sols[0][2])
+    ub = [torch.zeros_like(b)]
+    ff.mg_solve_batched([h32], [w.eta], ub)
+    assert torch.equal(ub[0], sols[0][2])
+    cache = str(tmp_path / "tune.json")
+    v1 = autotune.tune_solve(h32, b, ws, ff.FP32_IR, path=cache, reps=1)
+    h2, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR)
+    assert autotune.tune_solve(h2, b, ws, ff.FP32_IR, path=cache) == v1
+    assert ff.mg_tune_get(h2, ff.TUNE_TAIL) == v1
+    with pytest.raises(ff.FfmgError):
+        ff.mg_tune_set(h2, nv, ff.TUNE_TAIL)
+    h3, _, _, _, _, _ = setup(ff, orc, w, tile_config=1)
+    assert ff.mg_tune_variants(h3, ff.TUNE_TAIL) == 1
+
+
 def test_repeated_solves_and_batches(ff, orc):
     """The device-side stopping test with batched enqueueing: repeated solves
     (whose batch size follows the previous cycle count) and a solve from a
