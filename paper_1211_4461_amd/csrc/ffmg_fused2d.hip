@@ -85,11 +85,16 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
     constexpr int BW = FTX + 2 * BO, BH = TH + 2 * BO;
     constexpr int S1W = BW, S1H = BH;                      // sweep-1 values
     constexpr int ECW = FTX / 2 + 4, ECH = TH / 2 + 4;     // coarse tile covering the u region
+    constexpr int U1H = NS == 2 ? S1H : 1, U1W = NS == 2 ? S1W : 1;
+    constexpr int ECH_ = PROL ? ECH : 1, ECW_ = PROL ? ECW : 1;
     __shared__ cx<T> U0[ZERO ? 1 : UH][ZERO ? 1 : UW];
-    __shared__ cx<T> U1[NS == 2 ? S1H : 1][NS == 2 ? S1W : 1];
     __shared__ cx<T> Bs[BH][BW];
     __shared__ cx<T> Qs[BH][BW];
-    __shared__ cx<T> EC[PROL ? ECH : 1][PROL ? ECW : 1];
+    // the coarse tile is dead once phase 2 has ended (barrier), before sweep 1
+    // writes U1: the two share storage, so that four blocks fit in a CU's LDS
+    __shared__ cx<T> U1EC[U1H * U1W > ECH_ * ECW_ ? U1H * U1W : ECH_ * ECW_];
+    cx<T>(&U1)[U1H][U1W] = *reinterpret_cast<cx<T>(*)[U1H][U1W]>(&U1EC[0]);
+    cx<T>(&EC)[ECH_][ECW_] = *reinterpret_cast<cx<T>(*)[ECH_][ECW_]>(&U1EC[0]);
     const int mx = P.mx, my = P.my;
     const int mxc = (mx - 1) / 2, myc = (my - 1) / 2;
     const int x0 = (tile % tiles_x) * FTX, y0 = (tile / tiles_x) * TH;
@@ -225,7 +230,7 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
 }
 
 template <typename T, int NS, bool ZERO, bool PROL, int TAG>
-__global__ __launch_bounds__(256) void k_smooth2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_smooth2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                   const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                   cx<T> *__restrict__ out, Stencil<T> P, int tiles_x,
                                                   const int *__restrict__ stop)
@@ -618,7 +623,7 @@ template void launch_tail2d<float>(const TailParams<float> &, size_t, const cf *
 // owns tile xcd_tile(b, n) and writes partial[b]), so the results, sums
 // included, are bit for bit those of one launch per instance.
 template <typename T, int NS, bool ZERO, bool PROL>
-__global__ __launch_bounds__(256) void k_smooth2d_batch(const SmoothJob<T> *__restrict__ jobs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_smooth2d_batch(const SmoothJob<T> *__restrict__ jobs,
                                                         const int *__restrict__ tile_job)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
