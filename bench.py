@@ -51,6 +51,10 @@ def measured_traffic(kernel):
 
 
 KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3), ("ffgemm", 4))
+# Useful flops of one learned-smoother application per point: 2736 complex
+# multiply-adds (one per complex weight: 3x3 taps, 1 + 1 -> 16 -> 16 -> 1
+# channels), 8 real flops each.
+NET_FLOP_PER_POINT = 8 * 2736
 
 
 def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point):
@@ -222,16 +226,29 @@ def run_learned(ff, torch, W, reps=3, oracle_check=False):
             info = ff.mg_solve(h, b, u, tol=tol)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t)
-        return h, u, info, 1e3 * min(ts)
+        net = None
+        if learned:   # the network kernel alone, bracketed by HIP events in one more solve
+            ff.mg_profile_enable(h, 1 << ff.PROF_NET)
+            ff.mg_profile_read(h, ff.PROF_NET)
+            u.zero_()
+            ff.mg_solve(h, b, u, tol=tol)
+            ms, cnt = ff.mg_profile_read(h, ff.PROF_NET)
+            ff.mg_profile_enable(h, 0)
+            us = 1e3 * ms / max(cnt, 1)
+            useful = NET_FLOP_PER_POINT * w.N
+            net = {"applications": cnt, "avg_us": round(us, 2), "useful_flop": useful,
+                   "useful_TFLOPs": round(useful / (us * 1e-6) / 1e12, 1),
+                   "mfma_frac_useful": round(useful / (us * 1e-6) / 1e12 / 2500.0, 4)}
+        return h, u, info, 1e3 * min(ts), net
 
     for kh in (0.5, 0.2):
         w = W.random_field(1024, 4, kh)
         b = LS.phase_rhs(w, torch)
-        hj, uj, ij, tj = solve(w, b, False)
-        hl, ul, il, tl = solve(w, b, True)
+        hj, uj, ij, tj, _ = solve(w, b, False)
+        hl, ul, il, tl, net = solve(w, b, True)
         out[f"k0h={kh}"] = {"jacobi": {"cycles": ij.cycles, "conv_factor": round(ij.conv_factor, 4), "ms": round(tj, 3)},
                             "learned": {"cycles": il.cycles, "conv_factor": round(il.conv_factor, 4), "ms": round(tl, 3),
-                                        "fell_back": il.fell_back},
+                                        "fell_back": il.fell_back, "network_kernel": net},
                             "solution_rel_diff": float(torch.linalg.norm(ul - uj) / torch.linalg.norm(uj))}
         hj.destroy()
         hl.destroy()

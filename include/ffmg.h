@@ -244,7 +244,8 @@ ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, doubl
  * 0 finest-level pre-smoothing (the fused two-sweep kernel, or each sweep),
  * 1 far-field map (integrand, contraction, final sum), 2 finest-level
  * interpolation + post-smoothing, 3 FP64 update + residual of the
- * mixed-precision refinement, 4 the far-field GEMM stages alone.  mask = 0
+ * mixed-precision refinement, 4 the far-field GEMM stages alone, 5 the
+ * learned smoother's network on the finest level.  mask = 0
  * disables.  mg_profile_read synchronises, returns the summed duration (ms)
  * and launch count of one kernel, and clears its record. */
 ffmg_status mg_profile_enable(ffmg_handle *h, int mask);

@@ -502,8 +502,10 @@ void learned_step(ffmg_handle *h, int l, const cd *b, cd *u, const int *stop)
 {
     Level &lv = h->L[l];
     launch_stencil<double>(MODE_RESID, lv.g, lv.P64, u, b, lv.q, lv.r, (double *)nullptr, h->stream, false, stop);
+    const int pi = (l == 0) ? prof_begin(h, PROF_NET) : -1;
     launch_net_apply(lv.r, h->d_kh2[l], u, lv.g.m[0], lv.g.m[1], h->d_wfrag, lv.g.h[0] * lv.g.h[1], h->stream,
                      stop);
+    prof_end(h, PROF_NET, pi);
 }
 
 // One level of a V-cycle with the learned smoother: nu learned steps,

@@ -26,7 +26,8 @@ enum ProfKernel {
     PROF_POST = 2,     // finest-level interpolation + post-smoothing (fused)
     PROF_REFINE = 3,   // FP64 update + residual of the refinement loop (fused)
     PROF_FFGEMM = 4,   // far-field GEMM stages alone
-    PROF_N = 5
+    PROF_NET = 5,      // learned-smoother network application (finest level)
+    PROF_N = 6
 };
 
 // Device-resident state of one solve (residual-reduction stopping test of

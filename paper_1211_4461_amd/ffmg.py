@@ -387,10 +387,10 @@ def mg_destroy(h: Handle):
 KERNEL_SWEEP, KERNEL_FARFIELD = 0, 1
 
 
-PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE, PROF_FFGEMM = 0, 1, 2, 3, 4
+PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE, PROF_FFGEMM, PROF_NET = 0, 1, 2, 3, 4, 5
 
 
-def mg_profile_enable(h: Handle, mask=0x1F):
+def mg_profile_enable(h: Handle, mask=0x3F):
     """Time kernel k when bit k of mask is set (0 disables)."""
     h._check(lib().mg_profile_enable(h.ptr, int(mask)), "mg_profile_enable")
 
