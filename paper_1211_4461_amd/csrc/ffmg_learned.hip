@@ -519,7 +519,9 @@ void launch_round_weights(const float2 *Wm, float2 *Wq, hipStream_t s)
 //            (Re: a_re (1 + m_re) - a_im m_im; Im: a_im (1 + m_re) +
 //            a_re m_im) without any exchange between lanes
 //   layer 2: K = 32 channels per tap, one k-step per tap; N = 32
-//   layer 3: K as layer 2; N = 2 (padded to 16)
+//   layer 3: one output channel, so the 9 taps go to the columns instead:
+//            Z_t = W3[t] x2 per point (K = 32, columns 2 t + part, 18 of 32
+//            used), then N(p) = sum_t Z_t(p + d_t) by a gather from LDS
 // A 16 x 16 output tile needs layer-2 values on 18 x 18 points, layer-1
 // values on 20 x 20 and the inputs on 22 x 22 (zero outside the grid); the
 // activations live in LDS as BF16 [point][channel].  The weight fragments
@@ -541,11 +543,15 @@ constexpr int IN_PER_THREAD = (R0 * R0 + 255) / 256;
 // column li of both column tiles writes slots 2 li and 2 li + 1 as one dword;
 // column j is Re (j even) or Im (j odd) of channel j / 2.
 constexpr int XS = 40;
+// Per-tap layer-3 products: 18 floats per point, rows of 20 (80 bytes).
+constexpr int ZS = 20;
 struct alignas(16) InferLds {
     unsigned short x0[R0 * R0][4];           // r~ re, r~ im, kappa~ re, kappa~ im
-    unsigned short x1[NR1 * 16][XS];
+    union {
+        unsigned short x1[NR1 * 16][XS];
+        float z[NR2 * 16][ZS];               // layer-3 per-tap products (after layer 2)
+    };
     unsigned short x2[NR2 * 16][XS];         // rows past R2 * R2 take unused writes
-    float2 y[IT * IT];                       // network output of the tile
 };
 
 __device__ __forceinline__ bf8 as_bf8(us8 v) { return __builtin_bit_cast(bf8, v); }
@@ -619,14 +625,14 @@ __device__ __forceinline__ void store_tile_input(InferLds &S, const TileInput &i
 }
 
 // Layers of one 16 x 16 output tile (origin oy, ox) whose inputs are in
-// S.x0; leaves h^2 N in S.y.  The weight fragments stay in registers.  Each
-// wave takes two row tiles at a time so that four independent MFMA
-// accumulation chains interleave.  EDGE: the tile's layer-1 region reaches
+// S.x0; leaves layer 3's per-tap products in S.z.  The weight fragments stay
+// in registers.  In layer 2 each wave takes two row tiles at a time so that
+// four independent MFMA accumulation chains interleave.  EDGE: the tile's layer-1 region reaches
 // outside the grid, so activations there are set to zero (interior tiles
 // skip the test).
 template <bool EDGE>
 __device__ __forceinline__ void net_layers(InferLds &S, int mx, int my, int oy, int ox, const bf8 (&w1)[4][2],
-                                           const bf8 (&w2)[9][2], const bf8 (&w3)[9], int wave)
+                                           const bf8 (&w2)[9][2], const bf8 (&w3)[2], int wave)
 {
     const int lane = threadIdx.x & 63;
     const int li = lane & 15, lg = lane >> 4;
@@ -639,7 +645,9 @@ __device__ __forceinline__ void net_layers(InferLds &S, int mx, int my, int oy, 
         const int t = 4 * lg + hh;
         off1[hh] = t < 9 ? 2 * ((t / 3 - 1) * R0 + (t % 3 - 1)) : 0;
     }
-    // layer 1 on the 20 x 20 region (origin -2), one row tile at a time
+    // layer 1 on the 20 x 20 region (origin -2), one row tile per iteration,
+    // two iterations interleaved
+#pragma unroll 2
     for (int rt = wave; rt < NR1; rt += 4) {
         const int p = rt * 16 + li;
         const RegionPos P = region_pos<R1>(p);
@@ -732,39 +740,42 @@ __device__ __forceinline__ void net_layers(InferLds &S, int mx, int my, int oy, 
         }
     }
     __syncthreads();
-    // layer 3 on the 16 x 16 tile: row tiles wave, wave + 4, wave + 8, wave + 12
-    {
-        f4 acc[4];
+    // layer 3, first part: per-tap products Z_t(q) = W3[t] x2(q) at every
+    // point q of the 18 x 18 region (one k-step, columns 2 t + part; taps
+    // 0..7 in column tile 0, tap 8 in column tile 1), written to S.z, which
+    // reuses the layer-1 storage (dead once layer 2 has been read).  The
+    // second part, the 9-point gather N(p) = sum_t Z_t(p + d_t), follows the
+    // next barrier (layer3_gather).
+#pragma unroll 2
+    for (int rt = wave; rt < NR2; rt += 4) {
+        int p = rt * 16 + li;
+        if (p >= R2 * R2) p = 0;
+        const us8 a = *reinterpret_cast<const us8 *>(&S.x2[p][8 * lg]);
+        const f4 z = f4{0.f, 0.f, 0.f, 0.f};
+        const f4 Z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), w3[0], z, 0, 0, 0);
+        const f4 Z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), w3[1], z, 0, 0, 0);
+        const int pp = rt * 16 + 4 * lg;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-        const us8 *base = reinterpret_cast<const us8 *>(&S.x2[(wave + 1) * R2 + li + 1][8 * lg]);
-        us8 a[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = base[((4 * q + tap_dy(0)) * R2 + tap_dx(0)) * (XS / 8)];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            us8 an[4];
-            if (t + 1 < 9) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) an[q] = base[((4 * q + tap_dy(t + 1)) * R2 + tap_dx(t + 1)) * (XS / 8)];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a[q]), w3[t], acc[q], 0, 0, 0);
-            if (t + 1 < 9) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) a[q] = an[q];
-            }
-        }
-        // column 0 (Re) in lanes li = 0, column 1 (Im) in li = 1
-        if (li < 2) {
-            float *y = reinterpret_cast<float *>(S.y);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) y[2 * ((wave + 4 * q) * IT + 4 * lg + v) + li] = acc[q][v];
+        for (int v = 0; v < 4; ++v) {
+            S.z[pp + v][li] = Z0[v];
+            if (li < 2) S.z[pp + v][16 + li] = Z1[v];
         }
     }
+}
+
+// Layer 3, second part, for this thread's output point (py, px) of the tile:
+// N = sum over the 9 taps of Z_t at the neighbour p + d_t (region origin -1).
+__device__ __forceinline__ float2 layer3_gather(const InferLds &S, int py, int px)
+{
+    float2 y = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int q = (py + 1 + tap_dy(t)) * R2 + (px + 1 + tap_dx(t));
+        const float2 zt = *reinterpret_cast<const float2 *>(&S.z[q][2 * t]);
+        y.x += zt.x;
+        y.y += zt.y;
+    }
+    return y;
 }
 
 // N is complex-linear in its residual input, so s h^2 N(r / s) = h^2 N(r)
@@ -783,7 +794,7 @@ __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, con
     __shared__ InferLds S;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    bf8 w1[4][2], w2[9][2], w3[9];
+    bf8 w1[4][2], w2[9][2], w3[2];
 #pragma unroll
     for (int ty = 0; ty < 4; ++ty)
 #pragma unroll
@@ -793,7 +804,7 @@ __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, con
 #pragma unroll
         for (int nt = 0; nt < 2; ++nt) w2[t][nt] = as_bf8(wfrag[512 + (t * 2 + nt) * 64 + lane]);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) w3[t] = as_bf8(wfrag[512 + 1152 + t * 64 + lane]);
+    for (int nt = 0; nt < 2; ++nt) w3[nt] = as_bf8(wfrag[512 + 1152 + nt * 64 + lane]);
     const int first = xcd_tile(blockIdx.x, gridDim.x) * per_block;
     const int last = min(first + per_block, ntiles);
     if (first >= last) return;
@@ -819,11 +830,11 @@ __global__ __launch_bounds__(256) void k_net_apply(const cd *__restrict__ r, con
             net_layers<true>(S, mx, my, oy, ox, w1, w2, w3, wave);
         __syncthreads();
         if (mine) {
-            const float2 yv = S.y[tid];
+            const float2 yv = layer3_gather(S, py, px);
             u[j] = cd{uv.re + h2 * (double)yv.x, uv.im + h2 * (double)yv.y};
         }
-        // the next tile's layers start after its input barrier, so S.y and
-        // the activations are not overwritten before they are read here
+        // the next tile's layers start after its input barrier, so S.z (the
+        // layer-1 storage) is not overwritten before it is read here
     }
 }
 
@@ -875,21 +886,23 @@ void pack_net_mfma(const float *w, unsigned short *out)
                     const int idx = (t * 16 + oc) * 16 + i;
                     out[o++] = bf(real_block(W(NET_W2, idx, 0), W(NET_W2, idx, 1), po, pi));
                 }
-    for (int t = 0; t < 9; ++t)
+    // layer 3: column c = 16 nt + lane % 16 is part c % 2 of tap c / 2 (< 9)
+    for (int nt = 0; nt < 2; ++nt)
         for (int lane = 0; lane < 64; ++lane)
             for (int e = 0; e < 8; ++e) {
-                const int slot = 8 * (lane / 16) + e, j = lane % 16;
+                const int slot = 8 * (lane / 16) + e, c = 16 * nt + lane % 16;
+                const int t = c / 2, po = c % 2;
                 float v = 0.f;
-                if (j < 2) {
+                if (t < 9) {
                     const int i = slot_channel(slot), pi = slot_part(slot);
                     const int idx = t * 16 + i;
-                    v = real_block(W(NET_W3, idx, 0), W(NET_W3, idx, 1), j, pi);
+                    v = real_block(W(NET_W3, idx, 0), W(NET_W3, idx, 1), po, pi);
                 }
                 out[o++] = bf(v);
             }
 }
 
-size_t net_mfma_frag_count() { return (size_t)(8 + 18 + 9) * 64 * 8; }
+size_t net_mfma_frag_count() { return (size_t)(8 + 18 + 2) * 64 * 8; }
 
 // kappa h^2 as packed BF16 complex
 __global__ __launch_bounds__(256) void k_kappa_h2(const cd *__restrict__ q, double k02, double h2, size_t N,
