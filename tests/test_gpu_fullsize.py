@@ -1,0 +1,174 @@
+"""Parity at the workloads' full sizes, in the configuration the benchmark
+times, on outputs the FP64 oracle can afford there:
+
+* 2048^2 bumps, FP32 V-cycles in FP64 refinement + split-BF16 far field: the
+  right-hand side element by element, the residual of the GPU solution under
+  the oracle's operator, and the map against the oracle's map of the GPU
+  solution and of its own converged solution (1e-6, the mixed forms' bar);
+* 512^3 Gaussian (3D, 7-point stencil), same form: right-hand side, residual
+  under the oracle's operator, and 16 sampled directions of the 128 x 64 map
+  against the oracle's quadrature of the GPU solution;
+* the 96-instance batched Schroedinger workload: sampled instances of every
+  grid size bit for bit equal to their single solves, residual under the
+  oracle's operator and far field against the oracle;
+* 1023^2 learned smoothing step: sampled output points against the oracle
+  network evaluated on the window each point depends on.
+"""
+import numpy as np
+import pytest
+
+from paper_1211_4461_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_4461_amd import ffmg
+    ffmg.lib()
+    return ffmg
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def check_solution(orc, w, b_gpu, u_gpu, info, tol):
+    """RHS against the oracle element by element; the GPU solution's residual
+    under the oracle's FP64 operator meets the tolerance and agrees with the
+    residual the library reported."""
+    g = orc.Grid(w.dim, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    bo = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    bg = b_gpu.cpu().numpy().reshape(g.shape)
+    assert np.max(np.abs(bg - bo)) <= 1e-12 * np.max(np.abs(bo))
+    u = u_gpu.cpu().numpy().reshape(g.shape)
+    r = orc.residual(g, w.gamma, kappa, bo, u)
+    rel = float(np.linalg.norm(r) / np.linalg.norm(bo))
+    assert rel <= 1.01 * tol, rel
+    assert abs(rel - info.rel_residual) <= 1e-2 * rel, (rel, info.rel_residual)
+    return g, kappa, q, k0, bo, u
+
+
+def test_bumps_2048_mixed_map(ff, orc):
+    w = W.bumps_2d()
+    o = ff.default_options(precision=ff.FP32_IR, ff_precision=ff.FF_BF16X6)
+    h = ff.setup_workload(w, options=o)[0]
+    b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+    u = torch.zeros_like(b)
+    info = ff.mg_solve(h, b, u, tol=w.tol)
+    assert info.status == 0
+    F = ff.farfield_map(h, w.eta, u, w.dirs)
+    g, kappa, q, k0, bo, ug = check_solution(orc, w, b, u, info, w.tol)
+    Fu = orc.farfield(g, w.gamma, k0, q, w.eta, ug, w.dirs)
+    assert relerr(F, Fu) < 1e-6
+    uo, st, k, _ = orc.Multigrid(g, w.gamma, kappa).solve(bo, tol=1e-11)
+    assert st == 0
+    Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
+    print(f"2048^2: {info.cycles} refinement steps, residual {info.rel_residual:.2e}; map vs oracle "
+          f"{relerr(F, Fo):.2e} (oracle {k} cycles)")
+    assert relerr(F, Fo) < 1e-6
+    h.destroy()
+
+
+def test_gauss3d_512_mixed(ff, orc):
+    w = W.gauss_3d()
+    o = ff.default_options(precision=ff.FP32_IR, ff_precision=ff.FF_BF16X6)
+    h = ff.setup_workload(w, options=o)[0]
+    b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+    u = torch.zeros_like(b)
+    info = ff.mg_solve(h, b, u, tol=w.tol)
+    assert info.status == 0
+    F = ff.farfield_map(h, w.eta, u, w.dirs)
+    h.destroy()
+    g, kappa, q, k0, bo, ug = check_solution(orc, w, b, u, info, w.tol)
+    del b, u, kappa, bo
+    # 16 sampled directions on two polar angles (the oracle contracts each
+    # direction over the whole grid)
+    rng = np.random.default_rng(7)
+    n_az = 128
+    idx = np.concatenate([p * n_az + rng.choice(n_az, 8, replace=False) for p in (5, 40)])
+    Fs = orc.farfield(g, w.gamma, k0, q, w.eta, ug, w.dirs[idx])
+    print(f"512^3: {info.cycles} refinement steps, residual {info.rel_residual:.2e}; sampled map vs oracle "
+          f"{relerr(F[idx], Fs):.2e}")
+    assert relerr(F[idx], Fs) < 1e-6
+
+
+def test_schrodinger_batch_full(ff, orc):
+    insts = W.schrodinger_batch(seed=3)
+    hs, cache = [], {}
+    for w in insts:
+        key = (w.energy, w.n)
+        if key not in cache:
+            o = ff.default_options(precision=ff.FP32_IR, ff_precision=ff.FF_BF16X6)
+            cache[key] = ff.setup_workload(w, options=o)[0]
+        hs.append(cache[key])
+    us = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for w in insts]
+    infos = ff.mg_solve_batched(hs, [w.eta for w in insts], us)
+    dirs = insts[0].dirs
+    Fb = ff.farfield_map_batched(hs, [w.eta for w in insts], us, dirs)
+    assert all(i.status == 0 and i.rel_residual <= 1e-10 for i in infos)
+    # two sampled instances of every grid size
+    rng = np.random.default_rng(11)
+    picks = []
+    for n in (256, 512, 1024):
+        ids = [i for i, w in enumerate(insts) if w.n == n]
+        picks += list(rng.choice(ids, min(2, len(ids)), replace=False))
+    for i in picks:
+        w = insts[i]
+        b = ff.mg_rhs_plane_wave(hs[i], w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+        u = torch.zeros_like(b)
+        info = ff.mg_solve(hs[i], b, u, tol=w.tol)
+        assert torch.equal(u, us[i]), i
+        assert info.cycles == infos[i].cycles and info.rel_residual == infos[i].rel_residual
+        F1 = ff.farfield_map(hs[i], w.eta, u, dirs)
+        np.testing.assert_array_equal(Fb[i], F1)
+        g, kappa, q, k0, bo, ug = check_solution(orc, w, b, u, info, w.tol)
+        Fo = orc.farfield(g, w.gamma, k0, q, w.eta, ug, dirs)
+        assert relerr(F1, Fo) < 1e-6, (i, relerr(F1, Fo))
+    for h in cache.values():
+        h.destroy()
+
+
+def test_learned_step_1023_sampled_points(ff, orc):
+    """One learned smoothing step on the 1023^2 grid of the learned workload:
+    the update at sampled points (corners, edges, interior) against the oracle
+    network on the window of radius 6 around each point (the output depends on
+    the residual within radius 3, the window keeps the grid's zero padding
+    where it reaches the boundary)."""
+    from oracle import convnet as cn
+    from paper_1211_4461_amd import learned as LS
+    w = W.random_field(1024, 4, 0.5)
+    Ws = [Wl.astype(np.complex64).astype(np.complex128) for Wl in LS.jacobi_init(3, noise=0.5)]
+    h = ff.setup_workload(w, options=ff.default_options(smoother=ff.SMOOTH_LEARNED, smoother_weights=Ws))[0]
+    g = orc.Grid(2, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    b = LS.phase_rhs(w, torch)
+    rng = np.random.default_rng(12)
+    u0 = (rng.standard_normal(g.shape) + 1j * rng.standard_normal(g.shape)) * 0.1
+    ud = torch.from_numpy(u0).cuda()
+    ff.mg_learned_smooth(h, b, ud)
+    upd = ud.cpu().numpy() - u0
+    r = orc.residual(g, w.gamma, kappa, b.cpu().numpy(), u0)
+    hh = (w.hi - w.lo) / w.n
+    kh2 = kappa * hh * hh
+    m = g.shape[0]
+    pts = [(0, 0), (0, m - 1), (m - 1, 0), (m - 1, m - 1), (0, 500), (m - 1, 17), (3, 3), (511, 511)]
+    pts += [tuple(int(v) for v in rng.integers(0, m, 2)) for _ in range(24)]
+    R = 6
+    errs = []
+    for (y, x) in pts:
+        y0, y1, x0, x1 = max(y - R, 0), min(y + R + 1, m), max(x - R, 0), min(x + R + 1, m)
+        # the window is cut only at the grid boundary, so the oracle's zero
+        # padding at its edges is the grid's Dirichlet boundary there and at
+        # distance >= R > 3 elsewhere
+        ref = cn.smooth_step(Ws, r[y0:y1, x0:x1], kh2[y0:y1, x0:x1], hh * hh, quant=True)
+        # smooth_step scales by the window's RMS; N is linear in r, so the
+        # scale cancels
+        errs.append(abs(upd[y, x] - ref[y - y0, x - x0]) / (np.max(np.abs(ref)) + 1e-300))
+    h.destroy()
+    assert max(errs) < 1e-2, max(errs)
