@@ -276,6 +276,62 @@ def run_learned(ff, torch, W, reps=3, oracle_check=False):
     return out
 
 
+def run_3d(ff, torch, W, steps=2):
+    """The 3D workload (512^3 intervals, chi = 0.5 exp(-z.z/2), 128 x 64
+    directions): maps with FP32 V-cycles in FP64 refinement + split-BF16 far
+    field and plain FP64 maps, each solved to 1e-10; the finest-level Jacobi
+    sweep's rate (one 7-point sweep per launch, 4 e bytes per point) from the
+    library's events."""
+    import numpy as np
+    from paper_1211_4461_amd import autotune
+    w = W.gauss_3d()
+    out = {"workload": f"gauss_3d n={w.n} box=[-6,6]^3 k0=1 gamma=30deg eta=+x, "
+                       f"{len(w.dirs)} directions (128 azimuth x 64 polar)", "unknowns": w.N}
+    maps = {}
+    for name, prec, ffp, e in (("mixed", ff.FP32_IR, ff.FF_BF16X6, 8), ("plain_fp64", ff.FP64, ff.FF_FP64, 16)):
+        h = ff.setup_workload(w, options=ff.default_options(precision=prec, ff_precision=ffp))[0]
+        if ff.mg_tune_variants(h, ff.TUNE_FF_GEMM) > 1:
+            autotune.tune_farfield(h, w.eta, None, w.dirs, ffp)
+        b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
+        u = torch.empty_like(b)
+        info = None
+
+        def step():
+            nonlocal info
+            ff.mg_rhs_plane_wave(h, w.eta, b)
+            u.zero_()
+            info = ff.mg_solve(h, b, u, tol=w.tol)
+            return ff.farfield_map(h, w.eta, u, w.dirs)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            F = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ff.mg_profile_enable(h, (1 << ff.PROF_PRE) | (1 << ff.PROF_FF) | (1 << ff.PROF_FFGEMM))
+        step()
+        pre, ffm, gem = (ff.mg_profile_read(h, k) for k in (ff.PROF_PRE, ff.PROF_FF, ff.PROF_FFGEMM))
+        ff.mg_profile_enable(h, 0)
+        sweep_us = 1e3 * pre[0] / max(pre[1], 1)
+        gbs = 4 * e * w.N / (sweep_us * 1e-6) / 1e9
+        out[name] = {"maps_per_s": round(1.0 / dt, 3), "ms_per_map": round(1e3 * dt, 2), "cycles": info.cycles,
+                     "vcycles": info.vcycles, "rel_residual": info.rel_residual,
+                     "finest_sweep": {"avg_us": round(sweep_us, 1), "GB_s": round(gbs, 1),
+                                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": 4 * e},
+                     "ff_ms_per_map": round(ffm[0] / max(ffm[1], 1), 3),
+                     "ff_gemm_ms": round(gem[0] / max(gem[1], 1), 3)}
+        maps[name] = F
+        h.destroy()
+        del b, u
+        torch.cuda.empty_cache()
+    out["speedup_vs_plain"] = round(out["mixed"]["maps_per_s"] / out["plain_fp64"]["maps_per_s"], 3)
+    out["mixed_vs_plain_farfield_rel_err"] = float(np.linalg.norm(maps["mixed"] - maps["plain_fp64"]) /
+                                                   np.linalg.norm(maps["plain_fp64"]))
+    return out
+
+
 def gemm_report(prof, w, prec, tune=None):
     """MFMA rate of the far-field GEMM stage (2D: 8 M N flop per map as a
     complex GEMM; a split precision issues `products` times as many)."""
@@ -323,6 +379,7 @@ def main():
     ap.add_argument("--ff-precision", choices=("bf16x6", "bf16x3", "fp64"), default="bf16x6",
                     help="far-field contraction of the mixed path")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Schroedinger workload")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 512^3 workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -418,6 +475,8 @@ def main():
                               "farfield_gemm": gemm_report(pp, w, "fp64")}
         line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
         line["mixed_vs_plain_farfield_rel_err"] = ef
+    if not args.no_3d:
+        line["gauss_3d"] = run_3d(ffmg, torch, W)
     if not args.no_batch:
         line["batched"] = run_batched(ffmg, torch, W, max(args.steps // 4, 2))
     if not args.no_learned:
