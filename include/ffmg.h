@@ -87,9 +87,13 @@ typedef struct ffmg_options {
     int smoother;         /* ffmg_smoother                                     */
     const float *smoother_weights; /* HOST, learned smoother parameters, or NULL */
     int ff_precision;     /* ffmg_ff_precision                                 */
-    int tile_config;      /* 0 = fused 2D kernels + LDS tail (default), 1 = one
-                             operation per launch (reference), 2 = fused
-                             without the LDS tail                              */
+    int tile_config;      /* 0 = fused kernels (default; 2D: two sweeps per
+                             pass, residual + restriction, interpolation +
+                             sweeps, LDS tail; 3D: the two sweeps from a zero
+                             guess in one pass, interpolation fused into the
+                             first post-smoothing sweep), 1 = one operation
+                             per launch (reference), 2 = fused without the
+                             LDS tail                                          */
     int inner_cycles;     /* FP32_IR: V-cycles per FP64 refinement step
                              (0 = default 2)                                   */
     int nu_coarse;        /* sweeps before and after the coarse correction on

@@ -165,6 +165,40 @@ void smooth(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, int nu, bool ze
     if (src != u) launch_copy<T>(src, u, lv.g.N(), h->stream, stop);
 }
 
+// 3D smoothing with fused inputs: from a zero guess the first two sweeps run
+// as one pass (written straight to u, which they do not read); with ec the
+// coarse-grid correction u + P ec is formed inside the first sweep (u itself
+// is not updated: the sweep writes t).  Remaining sweeps as in smooth().
+template <typename T>
+void smooth3d_fused(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, int nu, bool zero_guess, const cx<T> *ec,
+                    const int *stop)
+{
+    using LP = LvlPtr<T>;
+    cx<T> *t = LP::t(lv);
+    const cx<T> *q = LP::q(lv);
+    const Stencil<T> &P = LP::P(lv);
+    const bool finest = (&lv == &h->L[0]);
+    cx<T> *src = u, *dst = t;
+    int s = 0;
+    if (zero_guess && nu >= 2) {
+        launch_sweep3d_fused<T>(true, lv.g, P, nullptr, nullptr, b, q, u, h->stream, finest, stop);
+        s = 2;
+        zero_guess = false;
+    } else if (ec) {
+        launch_sweep3d_fused<T>(false, lv.g, P, src, ec, b, q, dst, h->stream, finest, stop);
+        std::swap(src, dst);
+        s = 1;
+    }
+    for (; s < nu; ++s) {
+        int mode = (s == 0 && zero_guess) ? MODE_JACOBI0 : MODE_JACOBI;
+        int pi = (finest && mode == MODE_JACOBI) ? prof_begin(h, PROF_PRE) : -1;
+        launch_stencil<T>(mode, lv.g, P, src, b, q, dst, nullptr, h->stream, finest, stop);
+        prof_end(h, PROF_PRE, pi);
+        std::swap(src, dst);
+    }
+    if (src != u) launch_copy<T>(src, u, lv.g.N(), h->stream, stop);
+}
+
 // Fused 2D smoothing chain: nu sweeps from src (0 when zero; src + P ec when
 // ec is given) into dst, two sweeps per launch; tmp is a third buffer for
 // chains of more than one launch.
@@ -551,14 +585,25 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
         return;
     }
     const int nu1 = nu_pre(h, l), nu2 = nu_post(h, l);
-    if (nu1 > 0) smooth<T>(h, lv, b, u, nu1, zero_guess, stop);
-    else if (zero_guess) launch_zero<T>(u, lv.g.N(), h->stream, stop);
+    const bool fuse3 = lv.g.dim == 3 && h->opt.tile_config != TILE_REFERENCE;
+    if (nu1 > 0) {
+        if (fuse3)
+            smooth3d_fused<T>(h, lv, b, u, nu1, zero_guess, nullptr, stop);
+        else
+            smooth<T>(h, lv, b, u, nu1, zero_guess, stop);
+    } else if (zero_guess) {
+        launch_zero<T>(u, lv.g.N(), h->stream, stop);
+    }
     launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
     Level &lc = h->L[l + 1];
     launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream, stop);
     vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
-    launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
-    if (nu2 > 0) smooth<T>(h, lv, b, u, nu2, false, stop);
+    if (fuse3 && nu2 > 0) {
+        smooth3d_fused<T>(h, lv, b, u, nu2, false, LP::u(lc), stop);
+    } else {
+        launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
+        if (nu2 > 0) smooth<T>(h, lv, b, u, nu2, false, stop);
+    }
 }
 template void vcycle<double>(ffmg_handle *, int, const cd *, cd *, bool, const int *);
 template void vcycle<float>(ffmg_handle *, int, const cf *, cf *, bool, const int *);

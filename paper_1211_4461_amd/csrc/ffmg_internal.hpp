@@ -70,6 +70,13 @@ void launch_stencil(int mode, const LevelGeom &g, const Stencil<T> &P, const cx<
                     const cx<T> *q, cx<T> *out, double *partial, hipStream_t s, bool finest = false,
                     const int *stop = nullptr);
 
+// 3D Jacobi sweep with its input formed on the fly: zero2 = the two sweeps
+// from a zero guess in one pass (u unused), else u + P ec (the coarse-grid
+// correction fused into the sweep).  u and ec are not written.
+template <typename T>
+void launch_sweep3d_fused(bool zero2, const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec,
+                          const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
+                          const int *stop = nullptr);
 template <typename T>
 void launch_restrict(const LevelGeom &fine, const cx<T> *rf, cx<T> *bc, hipStream_t s, const int *stop = nullptr);
 

@@ -139,21 +139,67 @@ __global__ __launch_bounds__(256) void k_stencil2d(const cx<T> *__restrict__ u, 
                                 partial ? partial + blockIdx.x : nullptr);
 }
 
+// Linear interpolation: fine node f (1-based) takes coarse nodes floor(f/2)
+// and ceil(f/2) with weights 1 (f even) or 1/2 (f odd), tensorised; coarse
+// boundary values are zero.  One thread per fine point, summed z-outer.
+template <typename T>
+__device__ __forceinline__ T iw(int f, int C)
+{
+    int d = f - 2 * C;
+    return d == 0 ? T(1) : ((d == 1 || d == -1) ? T(0.5) : T(0));
+}
+
+// (P e_c) at fine interior point (ix, iy, iz) (0-based).
+template <typename T, int DIM>
+__device__ __forceinline__ cx<T> prolong_at(const cx<T> *__restrict__ ec, int ix, int iy, int iz, int mxc, int myc,
+                                            int mzc)
+{
+    int fx = ix + 1, fy = iy + 1, fz = iz + 1;
+    cx<T> acc = {T(0), T(0)};
+    int zlo = (DIM == 3) ? fz / 2 : 1, zhi = (DIM == 3) ? (fz + 1) / 2 : 1;
+    for (int Cz = zlo; Cz <= zhi; ++Cz)
+        for (int Cy = fy / 2; Cy <= (fy + 1) / 2; ++Cy)
+            for (int Cx = fx / 2; Cx <= (fx + 1) / 2; ++Cx) {
+                T wgt = iw<T>(fx, Cx) * iw<T>(fy, Cy) * ((DIM == 3) ? iw<T>(fz, Cz) : T(1));
+                if (wgt == T(0)) continue;
+                int ax = Cx - 1, ay = Cy - 1, az = (DIM == 3) ? Cz - 1 : 0;
+                if (ax < 0 || ay < 0 || az < 0 || ax >= mxc || ay >= myc || az >= mzc) continue;
+                acc = acc + wgt * ec[((size_t)az * myc + ay) * mxc + ax];
+            }
+    return acc;
+}
+
 // 3D: 256 threads as 64 (x) x 4 (y); each block owns a 64 x TY3 column of
 // TZ3 planes and marches up in z.  The centre plane (with its x/y halo) is
 // staged in a double-buffered LDS plane; u at z-1 and z+1 stays in registers.
-template <typename T, typename TO, int MODE, int TAG>
-__global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
-                                                   const cx<T> *__restrict__ q, cx<TO> *__restrict__ out,
-                                                   Stencil<T> P, T rscale, int tiles_x, int tiles_y,
-                                                   double *__restrict__ partial, const SolveCtl *__restrict__ ctl,
-                                                   const int *__restrict__ stop)
+// SRC says where the u values of the stencil come from:
+//   SRC_MEM   u in memory;
+//   SRC_ZERO2 the first of two sweeps from a zero guess, omega b / D, formed
+//             for every value the second sweep reads (two sweeps in one pass);
+//   SRC_PROL  u + P e_c, the coarse-grid correction formed on the fly (the
+//             interpolation fused into the first post-smoothing sweep); the
+//             coarse planes the tile needs are staged in an LDS ring as the
+//             block marches up, and the interpolation is branch free: the
+//             terms are summed in the order of k_prolong_add, whose skipped
+//             terms (zero weight, or coarse nodes outside the grid, zero in
+//             LDS) add exact zeros here.
+// The per-point arithmetic is that of the separate kernels, so the fused
+// passes reproduce them bit for bit.
+enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2 };
+
+template <typename T, typename TO, int MODE, int SRC>
+__device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
+                                               const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                               cx<TO> *__restrict__ out, const Stencil<T> &P, T rscale, int tiles_x,
+                                               int tiles_y, double *__restrict__ partial)
 {
-    if (stop && *stop) return;
-    if (ctl) rscale = T(1.0 / ctl->scale_next);
     constexpr int PY = TY3 / 4;
+    // coarse tile of the fine tile plus its one-point halo: 34 x (TY3/2 + 2)
+    constexpr int CW = 34, CH = TY3 / 2 + 2, NCS = SRC == SRC_PROL ? 4 : 1;
     __shared__ cx<T> s[2][TY3 + 2][66];
+    __shared__ cx<T> cs[NCS][SRC == SRC_PROL ? CH : 1][SRC == SRC_PROL ? CW : 1];
     const int mx = P.mx, my = P.my, mz = P.mz;
+    const int mxc = (mx - 1) / 2, myc = (my - 1) / 2, mzc = (mz - 1) / 2;
     int tile = xcd_tile(blockIdx.x, gridDim.x);
     int txi = tile % tiles_x;
     int rest = tile / tiles_x;
@@ -164,11 +210,53 @@ __global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, 
     const int gx = x0 + lx;
     const size_t plane = (size_t)mx * my;
     const bool zero_u = (MODE == MODE_JACOBI0);
+    const cx<T> zero = {T(0), T(0)};
+    const int cx0 = (x0 >> 1) - 1, cy0 = (y0 >> 1) - 1;   // coarse origin of cs
 
-    auto ld = [=](int x, int y, int z) -> cx<T> {
-        bool in = !zero_u && x >= 0 && x < mx && y >= 0 && y < my && z >= 0 && z < mz;
-        return ld_masked(u, (size_t)z * plane + (size_t)y * mx + x, in);
+    // coarse plane a (0-based) into ring slot a & 3, zero outside the grid
+    auto load_coarse = [&](int a) {
+        for (int t = threadIdx.x; t < CH * CW; t += 256) {
+            const int yy = t / CW, xx = t - yy * CW;
+            const int ax = cx0 + xx, ay = cy0 + yy;
+            const bool in = a >= 0 && a < mzc && ax >= 0 && ax < mxc && ay >= 0 && ay < myc;
+            cs[a & (NCS - 1)][yy][xx] = ld_masked(ec, ((size_t)a * myc + ay) * mxc + ax, in);
+        }
     };
+    // (P e_c) at fine point (x, y, z) from the staged coarse planes
+    auto interp = [&](int x, int y, int z) -> cx<T> {
+        const int fx = x + 1, fy = y + 1, fz = z + 1;
+        const int ex = (fx >> 1) - 1 - cx0, ey = (fy >> 1) - 1 - cy0, az = (fz >> 1) - 1;
+        const T wx[2] = {(fx & 1) ? T(0.5) : T(1), (fx & 1) ? T(0.5) : T(0)};
+        const T wy[2] = {(fy & 1) ? T(0.5) : T(1), (fy & 1) ? T(0.5) : T(0)};
+        const T wz[2] = {(fz & 1) ? T(0.5) : T(1), (fz & 1) ? T(0.5) : T(0)};
+        cx<T> acc = {T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int jy = 0; jy < 2; ++jy)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix)
+                    acc = acc + ((wx[ix] * wy[jy]) * wz[k]) * cs[(az + k) & (NCS - 1)][ey + jy][ex + ix];
+        return acc;
+    };
+    auto ld = [&](int x, int y, int z) -> cx<T> {
+        bool in = !zero_u && x >= 0 && x < mx && y >= 0 && y < my && z >= 0 && z < mz;
+        const size_t j = (size_t)z * plane + (size_t)y * mx + x;
+        if (SRC == SRC_ZERO2) {
+            if (!in) return zero;
+            return jacobi0_from(P, b[j], q[j]);
+        }
+        cx<T> v = ld_masked(u, j, in);
+        if (SRC == SRC_PROL && in) v = v + interp(x, y, z);
+        return v;
+    };
+    // coarse planes a = ((iz + 1) >> 1) - 1 .. (iz + 1) >> 1 serve fine plane iz
+    int a_hi = 0;
+    if (SRC == SRC_PROL) {
+        for (int a = (z0 >> 1) - 1; a <= ((z0 + 1) >> 1); ++a) load_coarse(a);
+        a_hi = (z0 + 1) >> 1;
+        __syncthreads();
+    }
 
     cx<T> prev[PY], cur[PY], nxt[PY];
 #pragma unroll
@@ -180,6 +268,12 @@ __global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, 
     int it = 0;
     for (int z = z0; z < z1; ++z, ++it) {
         const int buf = it & 1;
+        if (SRC == SRC_PROL && ((z + 2) >> 1) > a_hi) {
+            // the slot it takes held plane a_hi - 3, which no fine plane >= z
+            // reads; every thread has passed the barrier after its last use
+            load_coarse(++a_hi);
+            __syncthreads();
+        }
         if (!zero_u) {
 #pragma unroll
             for (int i = 0; i < PY; ++i) s[buf][ly0 + 4 * i + 1][lx + 1] = cur[i];
@@ -225,6 +319,29 @@ __global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, 
     }
     if (MODE == MODE_RESID || MODE == MODE_RNORM)
         if (partial) block_sum_256(acc, partial + blockIdx.x);
+}
+
+template <typename T, typename TO, int MODE, int TAG>
+__global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                   const cx<T> *__restrict__ q, cx<TO> *__restrict__ out,
+                                                   Stencil<T> P, T rscale, int tiles_x, int tiles_y,
+                                                   double *__restrict__ partial, const SolveCtl *__restrict__ ctl,
+                                                   const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    if (ctl) rscale = T(1.0 / ctl->scale_next);
+    stencil3d_body<T, TO, MODE, SRC_MEM>(u, nullptr, b, q, out, P, rscale, tiles_x, tiles_y, partial);
+}
+
+// One Jacobi sweep whose input is formed on the fly (SRC_ZERO2, SRC_PROL).
+template <typename T, int SRC, int TAG>
+__global__ __launch_bounds__(256) void k_sweep3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
+                                                 const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                                 cx<T> *__restrict__ out, Stencil<T> P, int tiles_x, int tiles_y,
+                                                 const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    stencil3d_body<T, T, MODE_JACOBI, SRC>(u, ec, b, q, out, P, T(1), tiles_x, tiles_y, nullptr);
 }
 
 static void grid_of(const LevelGeom &g, int &nb, int &tx, int &ty)
@@ -289,6 +406,33 @@ template void launch_stencil<double>(int, const LevelGeom &, const Stencil<doubl
                                      const cd *, cd *, double *, hipStream_t, bool, const int *);
 template void launch_stencil<float>(int, const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
                                     const cf *, cf *, double *, hipStream_t, bool, const int *);
+
+template <typename T>
+void launch_sweep3d_fused(bool zero2, const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec,
+                          const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop)
+{
+    int nb, tx, ty;
+    grid_of(g, nb, tx, ty);
+    if (zero2) {
+        if (finest)
+            hipLaunchKernelGGL((k_sweep3d<T, SRC_ZERO2, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx, ty,
+                               stop);
+        else
+            hipLaunchKernelGGL((k_sweep3d<T, SRC_ZERO2, 0>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx, ty,
+                               stop);
+    } else {
+        if (finest)
+            hipLaunchKernelGGL((k_sweep3d<T, SRC_PROL, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx, ty,
+                               stop);
+        else
+            hipLaunchKernelGGL((k_sweep3d<T, SRC_PROL, 0>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx, ty,
+                               stop);
+    }
+}
+template void launch_sweep3d_fused<double>(bool, const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
+                                           const cd *, const cd *, cd *, hipStream_t, bool, const int *);
+template void launch_sweep3d_fused<float>(bool, const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
+                                          const cf *, const cf *, cf *, hipStream_t, bool, const int *);
 
 // Copy / zero with the loop's stop flag.
 template <typename T>
@@ -366,16 +510,6 @@ void launch_restrict(const LevelGeom &f, const cx<T> *rf, cx<T> *bc, hipStream_t
 template void launch_restrict<double>(const LevelGeom &, const cd *, cd *, hipStream_t, const int *);
 template void launch_restrict<float>(const LevelGeom &, const cf *, cf *, hipStream_t, const int *);
 
-// Linear interpolation: fine node f (1-based) takes coarse nodes floor(f/2)
-// and ceil(f/2) with weights 1 (f even) or 1/2 (f odd), tensorised; coarse
-// boundary values are zero.  One thread per fine point, summed z-outer.
-template <typename T>
-__device__ __forceinline__ T iw(int f, int C)
-{
-    int d = f - 2 * C;
-    return d == 0 ? T(1) : ((d == 1 || d == -1) ? T(0.5) : T(0));
-}
-
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_prolong_add(const cx<T> *__restrict__ ec, cx<T> *__restrict__ uf,
                                                      int mxf, int myf, int mzf, int mxc, int myc, int mzc,
@@ -389,19 +523,7 @@ __global__ __launch_bounds__(256) void k_prolong_add(const cx<T> *__restrict__ e
     size_t rest = idx / mxf;
     int iy = (int)(rest % myf);
     int iz = (int)(rest / myf);
-    int fx = ix + 1, fy = iy + 1, fz = iz + 1;
-    cx<T> acc = {T(0), T(0)};
-    int zlo = (DIM == 3) ? fz / 2 : 1, zhi = (DIM == 3) ? (fz + 1) / 2 : 1;
-    for (int Cz = zlo; Cz <= zhi; ++Cz)
-        for (int Cy = fy / 2; Cy <= (fy + 1) / 2; ++Cy)
-            for (int Cx = fx / 2; Cx <= (fx + 1) / 2; ++Cx) {
-                T wgt = iw<T>(fx, Cx) * iw<T>(fy, Cy) * ((DIM == 3) ? iw<T>(fz, Cz) : T(1));
-                if (wgt == T(0)) continue;
-                int ax = Cx - 1, ay = Cy - 1, az = (DIM == 3) ? Cz - 1 : 0;
-                if (ax < 0 || ay < 0 || az < 0 || ax >= mxc || ay >= myc || az >= mzc) continue;
-                acc = acc + wgt * ec[((size_t)az * myc + ay) * mxc + ax];
-            }
-    uf[idx] = uf[idx] + acc;
+    uf[idx] = uf[idx] + prolong_at<T, DIM>(ec, ix, iy, iz, mxc, myc, mzc);
 }
 
 template <typename T>
