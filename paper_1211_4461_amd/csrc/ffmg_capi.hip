@@ -594,9 +594,13 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
     } else if (zero_guess) {
         launch_zero<T>(u, lv.g.N(), h->stream, stop);
     }
-    launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
     Level &lc = h->L[l + 1];
-    launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream, stop);
+    if (fuse3) {
+        launch_resid_restrict3d<T>(lv.g, LP::P(lv), u, b, LP::q(lv), LP::b(lc), h->stream, stop);
+    } else {
+        launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
+        launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream, stop);
+    }
     vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
     if (fuse3 && nu2 > 0) {
         smooth3d_fused<T>(h, lv, b, u, nu2, false, LP::u(lc), stop);

@@ -70,6 +70,11 @@ void launch_stencil(int mode, const LevelGeom &g, const Stencil<T> &P, const cx<
                     const cx<T> *q, cx<T> *out, double *partial, hipStream_t s, bool finest = false,
                     const int *stop = nullptr);
 
+// 3D residual + full weighting in one pass: bc = FW(b - A u) on the coarse
+// level (bit for bit the MODE_RESID launch followed by launch_restrict).
+template <typename T>
+void launch_resid_restrict3d(const LevelGeom &fine, const Stencil<T> &P, const cx<T> *u, const cx<T> *b,
+                             const cx<T> *q, cx<T> *bc, hipStream_t s, const int *stop = nullptr);
 // 3D Jacobi sweep with its input formed on the fly: zero2 = the two sweeps
 // from a zero guess in one pass (u unused), else u + P ec (the coarse-grid
 // correction fused into the sweep).  u and ec are not written.

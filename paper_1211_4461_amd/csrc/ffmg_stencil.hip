@@ -510,6 +510,150 @@ void launch_restrict(const LevelGeom &f, const cx<T> *rf, cx<T> *bc, hipStream_t
 template void launch_restrict<double>(const LevelGeom &, const cd *, cd *, hipStream_t, const int *);
 template void launch_restrict<float>(const LevelGeom &, const cf *, cf *, hipStream_t, const int *);
 
+// Residual + full weighting in 3D, one pass: a block owns a coarse tile of
+// RX3 x RY3 points and RZ3 planes and marches up through the fine planes it
+// needs (fine 2K .. 2K + 2 for coarse plane K).  u planes (with a one-point
+// halo) rotate through a ring of three LDS planes, the fine residual planes
+// through a second ring of three; a coarse plane is emitted once its third
+// fine plane is done.  The residual and the weighted sum are those of
+// k_stencil3d (MODE_RESID) and k_restrict, in the same order, so the result
+// is bit for bit that of the two passes.
+constexpr int RX3 = 32, RY3 = 4, RZ3 = 16;
+constexpr int RFW = 2 * RX3 + 1, RFH = 2 * RY3 + 1;   // fine residual region of a plane
+constexpr int RUW = RFW + 2, RUH = RFH + 2;           // u region (one halo)
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                          const cx<T> *__restrict__ q, cx<T> *__restrict__ bc,
+                                                          Stencil<T> P, int tiles_x, int tiles_y,
+                                                          const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    __shared__ cx<T> us[3][RUH][RUW];
+    __shared__ cx<T> rs[3][RFH][RFW];
+    const int mx = P.mx, my = P.my, mz = P.mz;
+    const int mxc = (mx - 1) / 2, myc = (my - 1) / 2, mzc = (mz - 1) / 2;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int txi = tile % tiles_x, rest = tile / tiles_x;
+    const int tyi = rest % tiles_y, tzi = rest / tiles_y;
+    const int I0 = txi * RX3, J0 = tyi * RY3, K0 = tzi * RZ3;
+    const int K1 = min(K0 + RZ3, mzc);
+    const int fx0 = 2 * I0, fy0 = 2 * J0;                 // fine origin of the residual region
+    const size_t plane = (size_t)mx * my;
+    const T w[3] = {T(0.25), T(0.5), T(0.25)};
+
+    // Loads run one plane ahead through registers: while residual plane fz is
+    // formed, u of plane fz + 2 and b, q of plane fz + 1 are in flight.
+    constexpr int NUL = (RUH * RUW + 255) / 256, NRL = (RFH * RFW + 255) / 256;
+    cx<T> un[NUL], bn[NRL], qn[NRL];
+    auto issue_u = [&](int fz) {
+#pragma unroll
+        for (int k = 0; k < NUL; ++k) {
+            const int t = threadIdx.x + 256 * k;
+            const int yy = t / RUW, xx = t - yy * RUW;
+            const int gx = fx0 - 1 + xx, gy = fy0 - 1 + yy;
+            const bool in = t < RUH * RUW && gx >= 0 && gx < mx && gy >= 0 && gy < my && fz >= 0 && fz < mz;
+            un[k] = ld_masked(u, (size_t)fz * plane + (size_t)gy * mx + gx, in);
+        }
+    };
+    auto store_u = [&](int fz) {
+        cx<T> *dst = &us[(fz + 3) % 3][0][0];
+#pragma unroll
+        for (int k = 0; k < NUL; ++k) {
+            const int t = threadIdx.x + 256 * k;
+            if (t < RUH * RUW) dst[t] = un[k];
+        }
+    };
+    auto issue_bq = [&](int fz) {
+#pragma unroll
+        for (int k = 0; k < NRL; ++k) {
+            const int t = threadIdx.x + 256 * k;
+            const int yy = t / RFW, xx = t - yy * RFW;
+            const int gx = fx0 + xx, gy = fy0 + yy;
+            const bool in = t < RFH * RFW && gx < mx && gy < my && fz < mz;
+            const size_t j = (size_t)fz * plane + (size_t)gy * mx + gx;
+            bn[k] = ld_masked(b, j, in);
+            qn[k] = ld_masked(q, j, in);
+        }
+    };
+    const int fz_first = 2 * K0, fz_last = 2 * K1;        // fine residual planes of the block
+    issue_u(fz_first - 1);
+    store_u(fz_first - 1);
+    issue_u(fz_first);
+    store_u(fz_first);
+    issue_u(fz_first + 1);
+    issue_bq(fz_first);
+    for (int fz = fz_first; fz <= fz_last; ++fz) {
+        store_u(fz + 1);
+        cx<T> bc_[NRL], qc_[NRL];
+#pragma unroll
+        for (int k = 0; k < NRL; ++k) {
+            bc_[k] = bn[k];
+            qc_[k] = qn[k];
+        }
+        __syncthreads();
+        if (fz < fz_last) {
+            issue_u(fz + 2);
+            issue_bq(fz + 1);
+        }
+        // fine residual plane fz on the RFW x RFH region (0 outside the grid)
+        const cx<T>(&um)[RUH][RUW] = us[(fz + 2) % 3];
+        const cx<T>(&uc_)[RUH][RUW] = us[fz % 3];
+        const cx<T>(&up)[RUH][RUW] = us[(fz + 1) % 3];
+        cx<T> *rd = &rs[fz % 3][0][0];
+#pragma unroll
+        for (int k = 0; k < NRL; ++k) {
+            const int t = threadIdx.x + 256 * k;
+            if (t < RFH * RFW) {
+                const int yy = t / RFW, xx = t - yy * RFW;
+                const int gx = fx0 + xx, gy = fy0 + yy;
+                cx<T> r = {T(0), T(0)};
+                if (gx < mx && gy < my && fz < mz) {
+                    const cx<T> uc = uc_[yy + 1][xx + 1];
+                    cx<T> lap = lap_xy(P, uc, uc_[yy + 1][xx], uc_[yy + 1][xx + 2], uc_[yy][xx + 1],
+                                       uc_[yy + 2][xx + 1]);
+                    lap = lap_add_z(P, lap, uc, um[yy + 1][xx + 1], up[yy + 1][xx + 1]);
+                    r = resid_from(P, lap, uc, bc_[k], qc_[k]);
+                }
+                rd[t] = r;
+            }
+        }
+        __syncthreads();
+        // coarse plane K = (fz - 2) / 2 once fine planes 2K .. 2K + 2 are done
+        if (fz >= fz_first + 2 && ((fz - fz_first) & 1) == 0) {
+            const int K = (fz - 2) / 2;
+            for (int t = threadIdx.x; t < RX3 * RY3; t += 256) {
+                const int cy = t / RX3, cxx = t - cy * RX3;
+                const int I = I0 + cxx, J = J0 + cy;
+                if (I < mxc && J < myc) {
+                    cx<T> acc = {T(0), T(0)};
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const cx<T>(&rz)[RFH][RFW] = rs[(2 * K + 1 + dz) % 3];
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dx = -1; dx <= 1; ++dx)
+                                acc = acc + ((w[dx + 1] * w[dy + 1]) * w[dz + 1]) *
+                                                rz[2 * cy + 1 + dy][2 * cxx + 1 + dx];
+                    }
+                    bc[((size_t)K * myc + J) * mxc + I] = acc;
+                }
+            }
+        }
+    }
+}
+
+template <typename T>
+void launch_resid_restrict3d(const LevelGeom &f, const Stencil<T> &P, const cx<T> *u, const cx<T> *b, const cx<T> *q,
+                             cx<T> *bc, hipStream_t s, const int *stop)
+{
+    const int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.m[2] - 1) / 2;
+    const int tx = (mxc + RX3 - 1) / RX3, ty = (myc + RY3 - 1) / RY3, tz = (mzc + RZ3 - 1) / RZ3;
+    hipLaunchKernelGGL(k_resid_restrict3d<T>, dim3(tx * ty * tz), dim3(256), 0, s, u, b, q, bc, P, tx, ty, stop);
+}
+template void launch_resid_restrict3d<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
+                                              const cd *, cd *, hipStream_t, const int *);
+template void launch_resid_restrict3d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
+                                             const cf *, cf *, hipStream_t, const int *);
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_prolong_add(const cx<T> *__restrict__ ec, cx<T> *__restrict__ uf,
                                                      int mxf, int myf, int mzf, int mxc, int myc, int mzc,
