@@ -319,7 +319,7 @@ constexpr int TAIL_POINTS[] = {4096, 1024, 256};
 constexpr int TAIL_VARIANTS = (int)(sizeof(TAIL_POINTS) / sizeof(TAIL_POINTS[0]));
 
 // Coarse levels handled by the one-workgroup LDS tail (2D): the longest
-// run of levels l >= 1 ending at the coarsest level whose b, u, t fit in LDS
+// run of levels l >= 1 ending at the coarsest level whose b, u, t, q fit in LDS
 // and that hold at most TAIL_POINTS[tail_variant] points each.
 template <typename T>
 void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
@@ -334,7 +334,7 @@ void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
     int top = nl;   // first tail level
     for (int l = nl - 1; l >= 1; --l) {
         const Level &lv = h->L[l];
-        size_t add = 3 * lv.g.N() * sizeof(cx<T>);
+        size_t add = 4 * lv.g.N() * sizeof(cx<T>);   // b, u, t and a copy of q
         if (lv.g.N() > max_points || bytes + add > budget || nl - l > TAIL_MAX_LEVELS) break;
         bytes += add;
         top = l;

@@ -381,18 +381,32 @@ __global__ __launch_bounds__(256) void k_refine2d(const cd *__restrict__ u, cons
 
 // ---------------------------------------------------------------------------
 // The coarse end of the V-cycle in one workgroup.  Fields b, u, t of every
-// tail level live in LDS; q is read from global memory.  Level 0 of the tail
-// starts from a zero guess with b read from b_top; its correction is written
-// to u_top.  Steps are separated by workgroup barriers.
+// tail level live in LDS (at the level's offset), and so does q (copied in at
+// the start, after the b, u, t arrays of all levels: every pass would
+// otherwise wait for a global load).  Level 0 of the tail starts from a zero
+// guess with b read from b_top; its correction is written to u_top.  Steps
+// are separated by workgroup barriers.
 template <typename T>
 struct TailView {
     cx<T> *b, *u, *t;
+    const cx<T> *q;
     int mx, my, N;
 };
 
+// Offset (in complex values) of level i's q in LDS.
 template <typename T>
-__device__ __forceinline__ TailView<T> tail_view(cx<T> *lds, const TailLevel<T> &L)
+__device__ __forceinline__ int tail_q_off(const TailParams<T> &tp, int i)
 {
+    const TailLevel<T> &last = tp.lv[tp.nt - 1];
+    int off = last.off + 3 * last.mx * last.my;
+    for (int k = 0; k < i; ++k) off += tp.lv[k].mx * tp.lv[k].my;
+    return off;
+}
+
+template <typename T>
+__device__ __forceinline__ TailView<T> tail_view(cx<T> *lds, const TailParams<T> &tp, int i)
+{
+    const TailLevel<T> &L = tp.lv[i];
     TailView<T> v;
     v.mx = L.mx;
     v.my = L.my;
@@ -400,6 +414,7 @@ __device__ __forceinline__ TailView<T> tail_view(cx<T> *lds, const TailLevel<T> 
     v.b = lds + L.off;
     v.u = v.b + v.N;
     v.t = v.u + v.N;
+    v.q = lds + tail_q_off(tp, i);
     return v;
 }
 
@@ -417,7 +432,7 @@ __device__ void tail_smooth(const TailView<T> &v, const TailLevel<T> &L, int nu,
     for (int s = 0; s < nu; ++s) {
         for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
             int x = j % v.mx, y = j / v.mx;
-            cx<T> bj = v.b[j], qj = L.q[j];
+            cx<T> bj = v.b[j], qj = v.q[j];
             if (s == 0 && zero) {
                 dst[j] = jacobi0_point<T>(L.P, bj, qj);
             } else {
@@ -446,22 +461,28 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
 {
     const int nt = tp.nt;
     {
-        TailView<T> v0 = tail_view(lds, tp.lv[0]);
+        TailView<T> v0 = tail_view(lds, tp, 0);
         for (int j = threadIdx.x; j < v0.N; j += blockDim.x) v0.b[j] = b_top[j];
+        for (int i = 0; i < nt; ++i) {
+            cx<T> *qd = lds + tail_q_off(tp, i);
+            const cx<T> *qs = tp.lv[i].q;
+            const int N = tp.lv[i].mx * tp.lv[i].my;
+            for (int j = threadIdx.x; j < N; j += blockDim.x) qd[j] = qs[j];
+        }
         __syncthreads();
     }
     // down: smoothing from zero, residual, restriction
     for (int i = 0; i + 1 < nt; ++i) {
         const TailLevel<T> &L = tp.lv[i];
-        TailView<T> v = tail_view(lds, L);
+        TailView<T> v = tail_view(lds, tp, i);
         tail_smooth<T>(v, L, tp.nu1, true);
         for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
             int x = j % v.mx, y = j / v.mx;
             v.t[j] = resid_point<T>(L.P, v.u[j], at2(v.u, v.mx, v.my, x - 1, y), at2(v.u, v.mx, v.my, x + 1, y),
-                                    at2(v.u, v.mx, v.my, x, y - 1), at2(v.u, v.mx, v.my, x, y + 1), v.b[j], L.q[j]);
+                                    at2(v.u, v.mx, v.my, x, y - 1), at2(v.u, v.mx, v.my, x, y + 1), v.b[j], v.q[j]);
         }
         __syncthreads();
-        TailView<T> c = tail_view(lds, tp.lv[i + 1]);
+        TailView<T> c = tail_view(lds, tp, i + 1);
         const T w[3] = {T(0.25), T(0.5), T(0.25)};
         for (int J = threadIdx.x; J < c.N; J += blockDim.x) {
             int I = J % c.mx, K = J / c.mx;
@@ -479,7 +500,7 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
     // coarsest: u = A^{-1} b in FP64, one wave per row, lane-strided sums then
     // a shuffle tree (the order of the one-operation kernel)
     {
-        TailView<T> c = tail_view(lds, tp.lv[nt - 1]);
+        TailView<T> c = tail_view(lds, tp, nt - 1);
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
         const int n = tp.nc;
         for (int row = wave; row < n; row += nw) {
@@ -503,8 +524,8 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
     // up: interpolation of the correction, smoothing
     for (int i = nt - 2; i >= 0; --i) {
         const TailLevel<T> &L = tp.lv[i];
-        TailView<T> v = tail_view(lds, L);
-        TailView<T> c = tail_view(lds, tp.lv[i + 1]);
+        TailView<T> v = tail_view(lds, tp, i);
+        TailView<T> c = tail_view(lds, tp, i + 1);
         for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
             int x = j % v.mx, y = j / v.mx;
             v.u[j] = v.u[j] + interp2d<T>(c.u, c.mx, 0, 0, c.mx, c.my, x, y);
@@ -512,7 +533,7 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
         __syncthreads();
         tail_smooth<T>(v, L, tp.nu2, false);
     }
-    TailView<T> v0 = tail_view(lds, tp.lv[0]);
+    TailView<T> v0 = tail_view(lds, tp, 0);
     for (int j = threadIdx.x; j < v0.N; j += blockDim.x) u_top[j] = v0.u[j];
 }
 
