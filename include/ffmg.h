@@ -95,7 +95,7 @@ typedef struct ffmg_options {
                              per launch (reference), 2 = fused without the
                              LDS tail                                          */
     int inner_cycles;     /* FP32_IR: V-cycles per FP64 refinement step
-                             (0 = default 2)                                   */
+                             (0 = default 3)                                   */
     int nu_coarse;        /* sweeps before and after the coarse correction on
                              the levels below the finest (0 = nu1 / nu2)       */
     int learned_levels;   /* FFMG_SMOOTH_LEARNED: bit l = level l smooths with

@@ -288,7 +288,7 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
     const ffmg_options &o0 = h0->opt;
     B.nu1 = o0.nu1;
     B.nu2 = o0.nu2;
-    B.inner = o0.inner_cycles > 0 ? o0.inner_cycles : 2;
+    B.inner = o0.inner_cycles > 0 ? o0.inner_cycles : DEFAULT_INNER_CYCLES;
     for (int i = 0; i < count; ++i) {
         ffmg_handle *h = hs[i];
         if (!h) return bail(fail(h0, FFMG_EINVAL, "hs[%d] is null", i));
@@ -300,7 +300,7 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
                              "fused kernels (tile_config 0)", i));
         if (o.nu1 != B.nu1 || o.nu2 != B.nu2 || o.nu1 < 1 || o.nu2 < 1 ||
             (o.nu_coarse != 0 && (o.nu_coarse != o.nu1 || o.nu_coarse != o.nu2)) ||
-            (o.inner_cycles > 0 ? o.inner_cycles : 2) != B.inner || o.smoother != FFMG_SMOOTH_JACOBI)
+            (o.inner_cycles > 0 ? o.inner_cycles : DEFAULT_INNER_CYCLES) != B.inner || o.smoother != FFMG_SMOOTH_JACOBI)
             return bail(fail(h0, FFMG_EINVAL, "instance %d: every operator needs the same nu1, nu2 >= 1 and inner "
                                               "cycles", i));
         const TailParams<float> &tp = h->tail32, &t0 = h0->tail32;

@@ -500,7 +500,7 @@ void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *st
         launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
         return;
     }
-    const int inner = h->opt.inner_cycles > 0 ? h->opt.inner_cycles : 2;
+    const int inner = h->opt.inner_cycles > 0 ? h->opt.inner_cycles : DEFAULT_INNER_CYCLES;
     for (int c = 0; c < inner; ++c) vcycle<float>(h, 0, l0.b32, l0.u32, c == 0, stop);
     if (l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE) {
         int pi = prof_begin(h, PROF_REFINE);
@@ -900,7 +900,7 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
     h->learned_on = (h->opt.smoother == FFMG_SMOOTH_LEARNED);   // the fallback lasts for this solve only
     inf.cycles = std::max(c.k, 0) + k_before_restart;
     inf.vcycles = inf.cycles * ((h->opt.precision == FFMG_FP32_IR)
-                                    ? (h->opt.inner_cycles > 0 ? h->opt.inner_cycles : 2) : 1);
+                                    ? (h->opt.inner_cycles > 0 ? h->opt.inner_cycles : DEFAULT_INNER_CYCLES) : 1);
     const double bn = sqrt(bn2), rk = sqrt(c.rk2), r0 = sqrt(c.r0_2);
     inf.rel_residual = rk / bn;
     inf.conv_factor = (inf.cycles > 0 && r0 > 0) ? pow(rk / r0, 1.0 / inf.cycles) : 0.0;
