@@ -334,7 +334,8 @@ void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
     int top = nl;   // first tail level
     for (int l = nl - 1; l >= 1; --l) {
         const Level &lv = h->L[l];
-        size_t add = 4 * lv.g.N() * sizeof(cx<T>);   // b, u, t and a copy of q
+        // b, u, t and a copy of q, each with a one-point zero border
+        size_t add = 4 * (size_t)(lv.g.m[0] + 2) * (lv.g.m[1] + 2) * sizeof(cx<T>);
         if (lv.g.N() > max_points || bytes + add > budget || nl - l > TAIL_MAX_LEVELS) break;
         bytes += add;
         top = l;
@@ -355,7 +356,7 @@ void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
         t.off = off;
         t.P = LvlPtr<T>::P(lv);
         t.q = LvlPtr<T>::q(lv);
-        off += 3 * t.mx * t.my;
+        off += 4 * (t.mx + 2) * (t.my + 2);
     }
     lds = bytes;
 }

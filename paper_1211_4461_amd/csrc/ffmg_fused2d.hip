@@ -380,48 +380,43 @@ __global__ __launch_bounds__(256) void k_refine2d(const cd *__restrict__ u, cons
 }
 
 // ---------------------------------------------------------------------------
-// The coarse end of the V-cycle in one workgroup.  Fields b, u, t of every
-// tail level live in LDS (at the level's offset), and so does q (copied in at
-// the start, after the b, u, t arrays of all levels: every pass would
-// otherwise wait for a global load).  Level 0 of the tail starts from a zero
-// guess with b read from b_top; its correction is written to u_top.  Steps
-// are separated by workgroup barriers.
+// The coarse end of the V-cycle in one workgroup.  Every tail level keeps
+// b, u, t and a copy of q in LDS, each as a (mx + 2) x (my + 2) array whose
+// one-point border stays zero (the Dirichlet values), so stencil reads need
+// no bounds tests.  Level 0 of the tail starts from a zero guess with b read
+// from b_top; its correction is written to u_top.  Steps are separated by
+// workgroup barriers.
 template <typename T>
 struct TailView {
-    cx<T> *b, *u, *t;
-    const cx<T> *q;
-    int mx, my, N;
+    cx<T> *b, *u, *t, *q;
+    int mx, my, W, N;
+    float inv_mx;
+    // padded index of interior point (x, y)
+    __device__ __forceinline__ int at(int x, int y) const { return (y + 1) * W + x + 1; }
+    // (x, y) of the j-th interior point, j < 2^16 (the float quotient is
+    // exact there: its distance to the next integer is >= 0.5 / mx)
+    __device__ __forceinline__ void xy(int j, int &x, int &y) const
+    {
+        y = (int)(((float)j + 0.5f) * inv_mx);
+        x = j - y * mx;
+    }
 };
 
-// Offset (in complex values) of level i's q in LDS.
 template <typename T>
-__device__ __forceinline__ int tail_q_off(const TailParams<T> &tp, int i)
+__device__ __forceinline__ TailView<T> tail_view(cx<T> *lds, const TailLevel<T> &L)
 {
-    const TailLevel<T> &last = tp.lv[tp.nt - 1];
-    int off = last.off + 3 * last.mx * last.my;
-    for (int k = 0; k < i; ++k) off += tp.lv[k].mx * tp.lv[k].my;
-    return off;
-}
-
-template <typename T>
-__device__ __forceinline__ TailView<T> tail_view(cx<T> *lds, const TailParams<T> &tp, int i)
-{
-    const TailLevel<T> &L = tp.lv[i];
     TailView<T> v;
     v.mx = L.mx;
     v.my = L.my;
+    v.W = L.mx + 2;
     v.N = L.mx * L.my;
+    v.inv_mx = 1.f / (float)L.mx;
+    const int np = (L.mx + 2) * (L.my + 2);
     v.b = lds + L.off;
-    v.u = v.b + v.N;
-    v.t = v.u + v.N;
-    v.q = lds + tail_q_off(tp, i);
+    v.u = v.b + np;
+    v.t = v.u + np;
+    v.q = v.t + np;
     return v;
-}
-
-template <typename T>
-__device__ __forceinline__ cx<T> at2(const cx<T> *a, int mx, int my, int x, int y)
-{
-    return (x >= 0 && x < mx && y >= 0 && y < my) ? a[y * mx + x] : cx<T>{T(0), T(0)};
 }
 
 // nu sweeps on one tail level into v.u; zero: the incoming u is 0.
@@ -431,13 +426,14 @@ __device__ void tail_smooth(const TailView<T> &v, const TailLevel<T> &L, int nu,
     cx<T> *src = v.u, *dst = v.t;
     for (int s = 0; s < nu; ++s) {
         for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
-            int x = j % v.mx, y = j / v.mx;
-            cx<T> bj = v.b[j], qj = v.q[j];
+            int x, y;
+            v.xy(j, x, y);
+            const int k = v.at(x, y);
+            cx<T> bj = v.b[k], qj = v.q[k];
             if (s == 0 && zero) {
-                dst[j] = jacobi0_point<T>(L.P, bj, qj);
+                dst[k] = jacobi0_point<T>(L.P, bj, qj);
             } else {
-                dst[j] = jacobi_point<T>(L.P, src[j], at2(src, v.mx, v.my, x - 1, y), at2(src, v.mx, v.my, x + 1, y),
-                                         at2(src, v.mx, v.my, x, y - 1), at2(src, v.mx, v.my, x, y + 1), bj, qj);
+                dst[k] = jacobi_point<T>(L.P, src[k], src[k - 1], src[k + 1], src[k - v.W], src[k + v.W], bj, qj);
             }
         }
         __syncthreads();
@@ -446,11 +442,19 @@ __device__ void tail_smooth(const TailView<T> &v, const TailLevel<T> &L, int nu,
         dst = tmp;
     }
     if (src != v.u) {
-        for (int j = threadIdx.x; j < v.N; j += blockDim.x) v.u[j] = src[j];
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
+            int x, y;
+            v.xy(j, x, y);
+            v.u[v.at(x, y)] = src[v.at(x, y)];
+        }
         __syncthreads();
     }
     if (nu == 0 && zero) {
-        for (int j = threadIdx.x; j < v.N; j += blockDim.x) v.u[j] = cx<T>{T(0), T(0)};
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
+            int x, y;
+            v.xy(j, x, y);
+            v.u[v.at(x, y)] = cx<T>{T(0), T(0)};
+        }
         __syncthreads();
     }
 }
@@ -461,46 +465,60 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
 {
     const int nt = tp.nt;
     {
-        TailView<T> v0 = tail_view(lds, tp, 0);
-        for (int j = threadIdx.x; j < v0.N; j += blockDim.x) v0.b[j] = b_top[j];
+        // zero every array (borders included), then b of level 0 and q of all
+        const TailLevel<T> &last = tp.lv[nt - 1];
+        const int total = last.off + 4 * (last.mx + 2) * (last.my + 2);
+        for (int j = threadIdx.x; j < total; j += blockDim.x) lds[j] = cx<T>{T(0), T(0)};
+        __syncthreads();
+        TailView<T> v0 = tail_view(lds, tp.lv[0]);
+        for (int j = threadIdx.x; j < v0.N; j += blockDim.x) {
+            int x, y;
+            v0.xy(j, x, y);
+            v0.b[v0.at(x, y)] = b_top[j];
+        }
         for (int i = 0; i < nt; ++i) {
-            cx<T> *qd = lds + tail_q_off(tp, i);
+            TailView<T> v = tail_view(lds, tp.lv[i]);
             const cx<T> *qs = tp.lv[i].q;
-            const int N = tp.lv[i].mx * tp.lv[i].my;
-            for (int j = threadIdx.x; j < N; j += blockDim.x) qd[j] = qs[j];
+            for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
+                int x, y;
+                v.xy(j, x, y);
+                v.q[v.at(x, y)] = qs[j];
+            }
         }
         __syncthreads();
     }
     // down: smoothing from zero, residual, restriction
     for (int i = 0; i + 1 < nt; ++i) {
         const TailLevel<T> &L = tp.lv[i];
-        TailView<T> v = tail_view(lds, tp, i);
+        TailView<T> v = tail_view(lds, L);
         tail_smooth<T>(v, L, tp.nu1, true);
         for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
-            int x = j % v.mx, y = j / v.mx;
-            v.t[j] = resid_point<T>(L.P, v.u[j], at2(v.u, v.mx, v.my, x - 1, y), at2(v.u, v.mx, v.my, x + 1, y),
-                                    at2(v.u, v.mx, v.my, x, y - 1), at2(v.u, v.mx, v.my, x, y + 1), v.b[j], v.q[j]);
+            int x, y;
+            v.xy(j, x, y);
+            const int k = v.at(x, y);
+            v.t[k] = resid_point<T>(L.P, v.u[k], v.u[k - 1], v.u[k + 1], v.u[k - v.W], v.u[k + v.W], v.b[k], v.q[k]);
         }
         __syncthreads();
-        TailView<T> c = tail_view(lds, tp, i + 1);
+        TailView<T> c = tail_view(lds, tp.lv[i + 1]);
         const T w[3] = {T(0.25), T(0.5), T(0.25)};
         for (int J = threadIdx.x; J < c.N; J += blockDim.x) {
-            int I = J % c.mx, K = J / c.mx;
-            int fx = 2 * I + 1, fy = 2 * K + 1;
+            int I, K;
+            c.xy(J, I, K);
+            const int fk = v.at(2 * I + 1, 2 * K + 1);
             cx<T> acc = {T(0), T(0)};
             for (int dy = -1; dy <= 1; ++dy)
                 for (int dx = -1; dx <= 1; ++dx) {
                     T wgt = (w[dx + 1] * w[dy + 1]) * T(1);
-                    acc = acc + wgt * v.t[(fy + dy) * v.mx + (fx + dx)];
+                    acc = acc + wgt * v.t[fk + dy * v.W + dx];
                 }
-            c.b[J] = acc;
+            c.b[c.at(I, K)] = acc;
         }
         __syncthreads();
     }
     // coarsest: u = A^{-1} b in FP64, one wave per row, lane-strided sums then
     // a shuffle tree (the order of the one-operation kernel)
     {
-        TailView<T> c = tail_view(lds, tp, nt - 1);
+        TailView<T> c = tail_view(lds, tp.lv[nt - 1]);
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
         const int n = tp.nc;
         for (int row = wave; row < n; row += nw) {
@@ -508,7 +526,9 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
             double re = 0.0, im = 0.0;
             for (int k = lane; k < n; k += 64) {
                 cd a = ar[k];
-                cx<T> bk = c.b[k];
+                int x, y;
+                c.xy(k, x, y);
+                cx<T> bk = c.b[c.at(x, y)];
                 double br = (double)bk.re, bi = (double)bk.im;
                 re += a.re * br - a.im * bi;
                 im += a.re * bi + a.im * br;
@@ -517,24 +537,35 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
                 re += __shfl_down(re, off, 64);
                 im += __shfl_down(im, off, 64);
             }
-            if (lane == 0) c.u[row] = cx<T>{T(re), T(im)};
+            if (lane == 0) {
+                int x, y;
+                c.xy(row, x, y);
+                c.u[c.at(x, y)] = cx<T>{T(re), T(im)};
+            }
         }
         __syncthreads();
     }
     // up: interpolation of the correction, smoothing
     for (int i = nt - 2; i >= 0; --i) {
         const TailLevel<T> &L = tp.lv[i];
-        TailView<T> v = tail_view(lds, tp, i);
-        TailView<T> c = tail_view(lds, tp, i + 1);
+        TailView<T> v = tail_view(lds, L);
+        TailView<T> c = tail_view(lds, tp.lv[i + 1]);
+        const cx<T> *cu = c.u + c.W + 1;   // interior (0, 0) of the coarse correction, row stride c.W
         for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
-            int x = j % v.mx, y = j / v.mx;
-            v.u[j] = v.u[j] + interp2d<T>(c.u, c.mx, 0, 0, c.mx, c.my, x, y);
+            int x, y;
+            v.xy(j, x, y);
+            const int k = v.at(x, y);
+            v.u[k] = v.u[k] + interp2d<T>(cu, c.W, 0, 0, c.mx, c.my, x, y);
         }
         __syncthreads();
         tail_smooth<T>(v, L, tp.nu2, false);
     }
-    TailView<T> v0 = tail_view(lds, tp, 0);
-    for (int j = threadIdx.x; j < v0.N; j += blockDim.x) u_top[j] = v0.u[j];
+    TailView<T> v0 = tail_view(lds, tp.lv[0]);
+    for (int j = threadIdx.x; j < v0.N; j += blockDim.x) {
+        int x, y;
+        v0.xy(j, x, y);
+        u_top[j] = v0.u[v0.at(x, y)];
+    }
 }
 
 template <typename T>
