@@ -64,13 +64,19 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
     opts = ff.default_options(precision=precision, ff_precision=ff_precision)
     h, coef = ff.setup_workload(w, options=opts)
     from paper_1211_4461_amd import autotune
-    tune = {"ff_gemm": None, "tail": None}
+    tune = {"ff_gemm": None, "smooth": None, "tail": None}
     if ff.mg_tune_variants(h, ff.TUNE_FF_GEMM) > 1:   # tile shape of the split GEMM, off the timed path
         v = autotune.tune_farfield(h, w.eta, None, w.dirs, ff_precision)
         tune["ff_gemm"] = {"variant": v, "cache": autotune.load().get(autotune.key(
             autotune.device_arch(), ff.TUNE_FF_GEMM, w.dim, [w.n - 1] * w.dim, len(w.dirs), ff_precision))}
     b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
     u = torch.empty_like(b)
+    if ff.mg_tune_variants(h, ff.TUNE_SMOOTH) > 1:    # tile height of the fused smoothing kernel
+        ff.mg_rhs_plane_wave(h, w.eta, b)
+        v = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=ff.TUNE_SMOOTH)
+        tune["smooth"] = {"variant": v, "tile_rows": (8, 16, 4)[v],
+                          "cache": autotune.load().get(autotune.key(
+                              autotune.device_arch(), ff.TUNE_SMOOTH, w.dim, [w.n - 1] * w.dim, 0, precision))}
     if ff.mg_tune_variants(h, ff.TUNE_TAIL) > 1:      # size of the one-workgroup LDS tail, off the timed path
         ff.mg_rhs_plane_wave(h, w.eta, b)
         v = autotune.tune_solve(h, b, u, precision, tol=w.tol)
@@ -460,7 +466,7 @@ def main():
                   "conv_factor": round(mixed["conv_factor"], 4),
                   "ff_ms_per_map": round(pr["ff"][0] / max(pr["ff"][1], 1), 3),
                   "farfield_gemm": gemm_report(pr, w, args.ff_precision, mixed["tune"]["ff_gemm"]),
-                  "lds_tail": mixed["tune"]["tail"]},
+                  "smooth_tile": mixed["tune"]["smooth"], "lds_tail": mixed["tune"]["tail"]},
         "roofline": roof,
     }
     if plain is not None:
@@ -470,7 +476,8 @@ def main():
                  for k, b_ in bpp_plain.items() if pp[k][1] > 0}
         line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
                               "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
-                              "finest_kernels_GBs": p_gbs, "lds_tail": plain["tune"]["tail"],
+                              "finest_kernels_GBs": p_gbs, "smooth_tile": plain["tune"]["smooth"],
+                              "lds_tail": plain["tune"]["tail"],
                               "ff_ms_per_map": round(pp["ff"][0] / max(pp["ff"][1], 1), 3),
                               "farfield_gemm": gemm_report(pp, w, "fp64")}
         line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)

@@ -264,7 +264,9 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
  * points for variants 0, 1, 2) run inside the one-workgroup LDS tail of the
  * fused 2D cycle; the levels above it run as grid-wide launches.  It has one
  * variant for handles without the LDS tail (3D, tile_config != 0) and for the
- * learned smoother.
+ * learned smoother.  FFMG_TUNE_SMOOTH: the tile height of the fused 2D
+ * smoothing kernel (8, 16 or 4 rows of 64 points for variants 0, 1, 2; the
+ * batched path keeps 8); one variant for 3D and tile_config 1.
  * mg_tune_variants returns the number of variants (0 for an unknown
  * tunable); mg_tune_get / mg_tune_set read and select one (a cached choice).
  * mg_tune_farfield builds the integrand of (eta, u) for the n_dirs
@@ -272,18 +274,18 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
  * events on the handle's stream, selects the fastest and returns its index in
  * *best and the mean time of variant v in times_ms[v] (v < n_times; times_ms
  * may be NULL).  Synchronises.
- * mg_tune_solve times `reps` solves of b from u = 0 to tol per FFMG_TUNE_TAIL
- * variant (after one untimed solve), selects the fastest and reports like
- * mg_tune_farfield; u is the caller's workspace and holds the last solution
- * on return.  Synchronises. */
-typedef enum { FFMG_TUNE_FF_GEMM = 0, FFMG_TUNE_TAIL = 1 } ffmg_tunable;
+ * mg_tune_solve times `reps` solves of b from u = 0 to tol per variant of
+ * `tunable` (FFMG_TUNE_TAIL or FFMG_TUNE_SMOOTH; after one untimed solve),
+ * selects the fastest and reports like mg_tune_farfield; u is the caller's
+ * workspace and holds the last solution on return.  Synchronises. */
+typedef enum { FFMG_TUNE_FF_GEMM = 0, FFMG_TUNE_TAIL = 1, FFMG_TUNE_SMOOTH = 2 } ffmg_tunable;
 int mg_tune_variants(const ffmg_handle *h, int tunable);
 ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant);
 ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant);
 ffmg_status mg_tune_farfield(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
                              int reps, double *times_ms, int n_times, int *best);
-ffmg_status mg_tune_solve(ffmg_handle *h, const void *b, void *u, double tol, int reps, double *times_ms, int n_times,
-                          int *best);
+ffmg_status mg_tune_solve(ffmg_handle *h, int tunable, const void *b, void *u, double tol, int reps, double *times_ms,
+                          int n_times, int *best);
 
 /* Number of levels and the interior sizes of level l (n[k] - 1 per axis). */
 int mg_num_levels(const ffmg_handle *h);

@@ -76,21 +76,23 @@ def tune_farfield(h: "ffmg.Handle", eta, u, dirs, ff_precision: int, path: Optio
 
 
 def tune_solve(h: "ffmg.Handle", b, u, precision: int, tol: float = 1e-10, path: Optional[str] = None,
-               reps: int = 3, force: bool = False) -> int:
-    """Select the LDS-tail variant of the fused 2D cycle for this handle: from
-    the cache, or by timing whole solves per variant (then cached; u is
+               reps: int = 3, force: bool = False, tunable: int = None) -> int:
+    """Select a variant of a solve-level tunable of the fused 2D cycle for
+    this handle (the LDS-tail size by default, or the smoothing tile height):
+    from the cache, or by timing whole solves per variant (then cached; u is
     overwritten).  Returns the variant."""
-    nv = ffmg.mg_tune_variants(h, ffmg.TUNE_TAIL)
+    tunable = ffmg.TUNE_TAIL if tunable is None else tunable
+    nv = ffmg.mg_tune_variants(h, tunable)
     if nv <= 1:
         return 0
     shape = [m for m in h.level_shape(0) if m > 1]
-    k = key(device_arch(), ffmg.TUNE_TAIL, len(shape), shape, 0, precision)
+    k = key(device_arch(), tunable, len(shape), shape, 0, precision)
     cache = load(path)
     hit = cache.get(k)
     if not force and isinstance(hit, dict) and isinstance(hit.get("variant"), int) and 0 <= hit["variant"] < nv:
-        ffmg.mg_tune_set(h, hit["variant"], ffmg.TUNE_TAIL)
+        ffmg.mg_tune_set(h, hit["variant"], tunable)
         return hit["variant"]
-    best, times = ffmg.mg_tune_solve(h, b, u, tol=tol, reps=reps)
+    best, times = ffmg.mg_tune_solve(h, b, u, tol=tol, reps=reps, tunable=tunable)
     cache[k] = {"variant": best, "ms": [round(t, 4) for t in times]}
     save(cache, path)
     return best

@@ -165,6 +165,11 @@ void smooth(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, int nu, bool ze
     if (src != u) launch_copy<T>(src, u, lv.g.N(), h->stream, stop);
 }
 
+// Tile height (rows of 64 points) of the fused 2D smoothing kernel per
+// FFMG_TUNE_SMOOTH variant.
+constexpr int SMOOTH_TH[] = {8, 16, 4};
+constexpr int SMOOTH_VARIANTS = (int)(sizeof(SMOOTH_TH) / sizeof(SMOOTH_TH[0]));
+
 // 3D smoothing with fused inputs: from a zero guess the first two sweeps run
 // as one pass (written straight to u, which they do not read); with ec the
 // coarse-grid correction u + P ec is formed inside the first sweep (u itself
@@ -216,7 +221,8 @@ void smooth_chain2d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
         left -= ns;
         cx<T> *o = ((nk - 1 - kk) % 2 == 0) ? dst : tmp;   // the last launch lands in dst
         int pi = finest ? prof_begin(h, prof_id) : -1;
-        launch_smooth2d<T>(lv.g, LP::P(lv), ns, zero, cur, ec, b, LP::q(lv), o, h->stream, finest && ns == 2, stop);
+        launch_smooth2d<T>(lv.g, LP::P(lv), ns, zero, cur, ec, b, LP::q(lv), o, h->stream, finest && ns == 2, stop,
+                           SMOOTH_TH[h->smooth_variant]);
         prof_end(h, prof_id, pi);
         cur = o;
         zero = false;
@@ -1033,6 +1039,8 @@ int mg_tune_variants(const ffmg_handle *h, int tunable)
                 h->tail64.nt > 0)
                    ? TAIL_VARIANTS
                    : 1;
+    case FFMG_TUNE_SMOOTH:
+        return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
     default: return 0;
     }
 }
@@ -1047,6 +1055,7 @@ ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant)
                                                          : h->ff_variant;
         return FFMG_OK;
     case FFMG_TUNE_TAIL: *variant = h->tail_variant; return FFMG_OK;
+    case FFMG_TUNE_SMOOTH: *variant = h->smooth_variant; return FFMG_OK;
     default: return FFMG_EINVAL;
     }
 }
@@ -1063,6 +1072,7 @@ ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant)
         if (h->ff) ff_plan_set_variant(h->ff, variant);
         return FFMG_OK;
     case FFMG_TUNE_TAIL: set_tail_variant(h, variant); return FFMG_OK;
+    case FFMG_TUNE_SMOOTH: h->smooth_variant = variant; return FFMG_OK;
     default: return fail(h, FFMG_EINVAL, "unknown tunable %d", tunable);
     }
 }
@@ -1116,16 +1126,19 @@ ffmg_status mg_tune_farfield(ffmg_handle *h, const double eta[3], const void *u,
     return FFMG_OK;
 }
 
-ffmg_status mg_tune_solve(ffmg_handle *h, const void *b, void *u, double tol, int reps, double *times_ms, int n_times,
-                          int *best)
+ffmg_status mg_tune_solve(ffmg_handle *h, int tunable, const void *b, void *u, double tol, int reps, double *times_ms,
+                          int n_times, int *best)
 {
     if (!h || !b || !u || reps < 1) return fail(h, FFMG_EINVAL, "null argument or reps < 1");
-    const int nv = mg_tune_variants(h, FFMG_TUNE_TAIL);
+    if (tunable != FFMG_TUNE_TAIL && tunable != FFMG_TUNE_SMOOTH)
+        return fail(h, FFMG_EINVAL, "mg_tune_solve tunes FFMG_TUNE_TAIL or FFMG_TUNE_SMOOTH (got %d)", tunable);
+    const int nv = mg_tune_variants(h, tunable);
     const size_t bytes = h->L[0].g.N() * sizeof(cd);
-    int arg = h->tail_variant;
+    int arg = 0;
+    TRY(mg_tune_get(h, tunable, &arg));
     double tbest = 0.0;
     for (int v = 0; v < nv; ++v) {
-        set_tail_variant(h, v);
+        TRY(mg_tune_set(h, tunable, v));
         double t = 0.0;
         for (int r = 0; r <= reps; ++r) {
             HIPCHK(h, hipMemsetAsync(u, 0, bytes, h->stream));
@@ -1141,7 +1154,7 @@ ffmg_status mg_tune_solve(ffmg_handle *h, const void *b, void *u, double tol, in
             arg = v;
         }
     }
-    set_tail_variant(h, arg);
+    TRY(mg_tune_set(h, tunable, arg));
     if (best) *best = arg;
     return FFMG_OK;
 }

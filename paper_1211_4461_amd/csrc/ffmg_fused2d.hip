@@ -58,13 +58,10 @@ __device__ __forceinline__ cx<T> interp2d(const cx<T> *ec, int ld, int ox, int o
     return acc;
 }
 
-// Tile height of the smoothing kernel: 16 rows in FP32, 8 in FP64 (LDS
-// stays near 50 KB per block, three blocks per CU).
-template <typename T>
-constexpr int smooth_th()
-{
-    return sizeof(T) == 8 ? 8 : 16;
-}
+// Tile heights of the smoothing kernel (rows of 64 points): a tunable of the
+// handle (FFMG_TUNE_SMOOTH); the batched path uses SMOOTH_TH_BATCH.  Every
+// height computes the same bits.
+constexpr int SMOOTH_TH_BATCH = 8;
 
 // k_smooth2d runs in four phases separated by barriers:
 //   1. every global load of the block is issued together (fully unrolled
@@ -73,12 +70,12 @@ constexpr int smooth_th()
 //   2. (PROL) u += P e_c in LDS;
 //   3. (NS = 2) sweep 1 on the tile plus a one-point halo;
 //   4. the last sweep on the tile, written to out.
-template <typename T, int NS, bool ZERO, bool PROL>
+template <typename T, int NS, bool ZERO, bool PROL, int TH>
 __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                               const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                               cx<T> *__restrict__ out, const Stencil<T> &P, int tiles_x, int tile)
 {
-    constexpr int TH = smooth_th<T>();
+    static_assert(TH % 4 == 0 && TH >= 4, "tile height: a multiple of the 4 rows of a 256-thread block");
     constexpr int H = NS;                                  // halo depth of the staged u
     constexpr int UW = FTX + 2 * H, UH = TH + 2 * H;
     constexpr int BO = NS - 1;                             // b, q region: tile + (NS-1) halo
@@ -229,14 +226,14 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
     }
 }
 
-template <typename T, int NS, bool ZERO, bool PROL, int TAG>
+template <typename T, int NS, bool ZERO, bool PROL, int TAG, int TH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_smooth2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                   const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                   cx<T> *__restrict__ out, Stencil<T> P, int tiles_x,
                                                   const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    smooth2d_body<T, NS, ZERO, PROL>(u, ec, b, q, out, P, tiles_x, xcd_tile(blockIdx.x, gridDim.x));
+    smooth2d_body<T, NS, ZERO, PROL, TH>(u, ec, b, q, out, P, tiles_x, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Residual + full weighting.  Coarse tile RCX x RCY; the fine residual is
@@ -590,16 +587,16 @@ int fused2d_blocks(const LevelGeom &g)
     return tiles2d(g, tx);
 }
 
-template <typename T>
-void launch_smooth2d(const LevelGeom &g, const Stencil<T> &P, int nsweeps, bool zero, const cx<T> *u,
-                     const cx<T> *ec, const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
-                     const int *stop)
+template <typename T, int TH>
+static void launch_smooth2d_th(const LevelGeom &g, const Stencil<T> &P, int nsweeps, bool zero, const cx<T> *u,
+                               const cx<T> *ec, const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s,
+                               bool finest, const int *stop)
 {
     const int tx = (g.m[0] + FTX - 1) / FTX;
-    const int nb = tx * ((g.m[1] + smooth_th<T>() - 1) / smooth_th<T>());
+    const int nb = tx * ((g.m[1] + TH - 1) / TH);
     dim3 G(nb), B(256);
 #define SM(NS, Z, PR, TAG) \
-    hipLaunchKernelGGL((k_smooth2d<T, NS, Z, PR, TAG>), G, B, 0, s, u, ec, b, q, out, P, tx, stop)
+    hipLaunchKernelGGL((k_smooth2d<T, NS, Z, PR, TAG, TH>), G, B, 0, s, u, ec, b, q, out, P, tx, stop)
     const bool prol = (ec != nullptr);
     if (nsweeps == 2) {
         if (zero) {
@@ -616,10 +613,22 @@ void launch_smooth2d(const LevelGeom &g, const Stencil<T> &P, int nsweeps, bool 
     }
 #undef SM
 }
+
+template <typename T>
+void launch_smooth2d(const LevelGeom &g, const Stencil<T> &P, int nsweeps, bool zero, const cx<T> *u,
+                     const cx<T> *ec, const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
+                     const int *stop, int th)
+{
+    switch (th) {
+    case 4: launch_smooth2d_th<T, 4>(g, P, nsweeps, zero, u, ec, b, q, out, s, finest, stop); break;
+    case 16: launch_smooth2d_th<T, 16>(g, P, nsweeps, zero, u, ec, b, q, out, s, finest, stop); break;
+    default: launch_smooth2d_th<T, 8>(g, P, nsweeps, zero, u, ec, b, q, out, s, finest, stop); break;
+    }
+}
 template void launch_smooth2d<double>(const LevelGeom &, const Stencil<double> &, int, bool, const cd *, const cd *,
-                                      const cd *, const cd *, cd *, hipStream_t, bool, const int *);
+                                      const cd *, const cd *, cd *, hipStream_t, bool, const int *, int);
 template void launch_smooth2d<float>(const LevelGeom &, const Stencil<float> &, int, bool, const cf *, const cf *,
-                                     const cf *, const cf *, cf *, hipStream_t, bool, const int *);
+                                     const cf *, const cf *, cf *, hipStream_t, bool, const int *, int);
 
 template <typename T>
 void launch_resid_restrict2d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b,
@@ -681,7 +690,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const SmoothJob<T> J = jobs[tile_job[t]];
     if (J.stop && *J.stop) return;
-    smooth2d_body<T, NS, ZERO, PROL>(J.u, J.ec, J.b, J.q, J.out, J.P, J.tiles_x, t - J.tile0);
+    smooth2d_body<T, NS, ZERO, PROL, SMOOTH_TH_BATCH>(J.u, J.ec, J.b, J.q, J.out, J.P, J.tiles_x, t - J.tile0);
 }
 
 template <typename T>
@@ -718,7 +727,7 @@ template <typename T>
 int smooth2d_tiles(const LevelGeom &g, int *tiles_x)
 {
     *tiles_x = (g.m[0] + FTX - 1) / FTX;
-    return *tiles_x * ((g.m[1] + smooth_th<T>() - 1) / smooth_th<T>());
+    return *tiles_x * ((g.m[1] + SMOOTH_TH_BATCH - 1) / SMOOTH_TH_BATCH);
 }
 template int smooth2d_tiles<double>(const LevelGeom &, int *);
 template int smooth2d_tiles<float>(const LevelGeom &, int *);

@@ -57,6 +57,7 @@ struct ffmg_handle {
     int tail_l = -1;
     size_t tail_lds[2] = {0, 0};     // [FP64, FP32]
     int tail_variant = 0;            // index into TAIL_POINTS (autotuned)
+    int smooth_variant = 0;          // index into SMOOTH_TH (autotuned)
     ffmg::TailParams<double> tail64{};
     ffmg::TailParams<float> tail32{};
     ffmg::FarFieldPlan *ff = nullptr;

@@ -125,12 +125,12 @@ void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const
 
 // Fused 2D level kernels (ffmg_fused2d.hip).  launch_smooth2d runs 1 or 2
 // sweeps from u (or from 0 when zero) into out; with ec != null the coarse
-// correction P ec is added to u first.
+// correction P ec is added to u first; th: tile height (4, 8 or 16 rows).
 int fused2d_blocks(const LevelGeom &g);
 template <typename T>
 void launch_smooth2d(const LevelGeom &g, const Stencil<T> &P, int nsweeps, bool zero, const cx<T> *u,
                      const cx<T> *ec, const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
-                     const int *stop);
+                     const int *stop, int th);
 template <typename T>
 void launch_resid_restrict2d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b,
                              const cx<T> *q, cx<T> *bc, hipStream_t s, const int *stop);

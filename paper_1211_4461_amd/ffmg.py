@@ -99,7 +99,7 @@ def lib():
     L.mg_tune_get.argtypes = [vp, ip, ctypes.POINTER(ip)]
     L.mg_tune_set.argtypes = [vp, ip, ip]
     L.mg_tune_farfield.argtypes = [vp, vp, vp, ip, vp, ip, ctypes.POINTER(dp), ip, ctypes.POINTER(ip)]
-    L.mg_tune_solve.argtypes = [vp, vp, vp, dp, ip, ctypes.POINTER(dp), ip, ctypes.POINTER(ip)]
+    L.mg_tune_solve.argtypes = [vp, ip, vp, vp, dp, ip, ctypes.POINTER(dp), ip, ctypes.POINTER(ip)]
     L.mg_solve_batched.argtypes = [vp, ip, vp, vp, dp, vp]
     fp = ctypes.POINTER(ctypes.c_float)
     L.ml_net_create.argtypes = [fp, vp, ctypes.POINTER(vp)]
@@ -268,6 +268,7 @@ def farfield_map(h: Handle, eta, u, dirs, out=None):
 
 TUNE_FF_GEMM = 0
 TUNE_TAIL = 1
+TUNE_SMOOTH = 2
 
 
 def _etas(etas):
@@ -342,14 +343,14 @@ def mg_tune_farfield(h: Handle, eta, u, dirs, reps=5):
     return best.value, list(times)
 
 
-def mg_tune_solve(h: Handle, b, u, tol=1e-10, reps=3):
-    """Time `reps` solves per LDS-tail variant (u is overwritten); selects the
-    fastest.  Returns (best, [ms per variant])."""
-    nv = max(mg_tune_variants(h, TUNE_TAIL), 1)
+def mg_tune_solve(h: Handle, b, u, tol=1e-10, reps=3, tunable=TUNE_TAIL):
+    """Time `reps` solves per variant of `tunable` (TUNE_TAIL or TUNE_SMOOTH;
+    u is overwritten); selects the fastest.  Returns (best, [ms per variant])."""
+    nv = max(mg_tune_variants(h, tunable), 1)
     times = (ctypes.c_double * nv)()
     best = ctypes.c_int()
-    h._check(lib().mg_tune_solve(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol), int(reps), times, nv,
-                                 ctypes.byref(best)), "mg_tune_solve")
+    h._check(lib().mg_tune_solve(h.ptr, int(tunable), _dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol), int(reps),
+                                 times, nv, ctypes.byref(best)), "mg_tune_solve")
     return best.value, list(times)
 
 

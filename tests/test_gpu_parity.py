@@ -388,6 +388,47 @@ def test_tail_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path):
         ff.mg_tune_set(h2, nv, ff.TUNE_TAIL)
     h3, _, _, _, _, _ = setup(ff, orc, w, tile_config=1)
     assert ff.mg_tune_variants(h3, ff.TUNE_TAIL) == 1
+    assert ff.mg_tune_variants(h3, ff.TUNE_SMOOTH) == 1
+
+
+@pytest.mark.parametrize("n", [128, 512])
+def test_smoothing_tile_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path):
+    """Every tile height of the fused smoothing kernel (8, 16, 4 rows) does the
+    same per-point arithmetic: FP64 V-cycles and FP32-in-FP64 solves agree bit
+    for bit (ragged last tiles included); the solve-timing sweep selects one
+    and the cache applies it to a second handle."""
+    from paper_1211_4461_amd import autotune
+    w = W.bumps_2d(n=n, seed=n + 3, k0=1.1, M=8)
+    for prec in (ff.FP64, ff.FP32_IR):
+        h, _, g, _, _, _ = setup(ff, orc, w, precision=prec)
+        nv = ff.mg_tune_variants(h, ff.TUNE_SMOOTH)
+        assert nv == 3
+        b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+        ref = None
+        for v in range(nv):
+            ff.mg_tune_set(h, v, ff.TUNE_SMOOTH)
+            assert ff.mg_tune_get(h, ff.TUNE_SMOOTH) == v
+            u = torch.zeros_like(b)
+            if prec == ff.FP64:
+                for _ in range(3):
+                    ff.mg_vcycle(h, b, u)
+                key = None
+            else:
+                info = ff.mg_solve(h, b, u)
+                key = (info.cycles, info.rel_residual)
+            torch.cuda.synchronize()
+            if ref is None:
+                ref = (key, u.clone())
+            assert key == ref[0] and torch.equal(u, ref[1]), (prec, v)
+    ws = torch.zeros_like(b)
+    best, times = ff.mg_tune_solve(h, b, ws, reps=1, tunable=ff.TUNE_SMOOTH)
+    assert 0 <= best < 3 and times[best] == min(times) and ff.mg_tune_get(h, ff.TUNE_SMOOTH) == best
+    assert torch.equal(ws, ref[1])
+    cache = str(tmp_path / "tune.json")
+    v1 = autotune.tune_solve(h, b, ws, ff.FP32_IR, path=cache, reps=1, tunable=ff.TUNE_SMOOTH)
+    h2, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR)
+    assert autotune.tune_solve(h2, b, ws, ff.FP32_IR, path=cache, tunable=ff.TUNE_SMOOTH) == v1
+    assert ff.mg_tune_get(h2, ff.TUNE_SMOOTH) == v1
 
 
 def test_repeated_solves_and_batches(ff, orc):
