@@ -429,8 +429,9 @@ def main():
     mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed)
     plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2),
                                                  args.warmup, bpp_plain)
-    names = {"pre": "finest-level pre-smoothing: 2 fused FP32 Jacobi sweeps from zero (k_smooth2d<float,2,true,false,1>)",
-             "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1>)",
+    names = {"pre": "finest-level pre-smoothing: 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,*,false,1,TH>)",
+             "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1,TH>, "
+                     "TH = the tuned tile height)",
              "refine": "FP64 update + residual of the refinement loop (k_refine2d)"}
     pr = mixed["prof"]
     dom = mixed["dominant"]
