@@ -170,38 +170,39 @@ void smooth(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, int nu, bool ze
 constexpr int SMOOTH_TH[] = {8, 16, 4};
 constexpr int SMOOTH_VARIANTS = (int)(sizeof(SMOOTH_TH) / sizeof(SMOOTH_TH[0]));
 
-// 3D smoothing with fused inputs: from a zero guess the first two sweeps run
-// as one pass (written straight to u, which they do not read); with ec the
-// coarse-grid correction u + P ec is formed inside the first sweep (u itself
-// is not updated: the sweep writes t).  Remaining sweeps as in smooth().
+// Fused 3D smoothing chain: nu sweeps from src (0 when zero; src + P ec when
+// ec is given) into dst: from a zero guess the first two sweeps are one pass
+// reading b and q only; with ec the interpolation is formed inside the first
+// sweep; the other sweeps are single z-marching passes (a pass doing two
+// sweeps through LDS planes was slower than two single passes).  tmp is a
+// third buffer, so that the last launch lands in dst without a copy.
 template <typename T>
-void smooth3d_fused(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, int nu, bool zero_guess, const cx<T> *ec,
-                    const int *stop)
+void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src, cx<T> *dst, cx<T> *tmp, int nu,
+                    bool zero, const cx<T> *ec, int prof_id, const int *stop)
 {
     using LP = LvlPtr<T>;
-    cx<T> *t = LP::t(lv);
-    const cx<T> *q = LP::q(lv);
-    const Stencil<T> &P = LP::P(lv);
     const bool finest = (&lv == &h->L[0]);
-    cx<T> *src = u, *dst = t;
-    int s = 0;
-    if (zero_guess && nu >= 2) {
-        launch_sweep3d_fused<T>(true, lv.g, P, nullptr, nullptr, b, q, u, h->stream, finest, stop);
-        s = 2;
-        zero_guess = false;
-    } else if (ec) {
-        launch_sweep3d_fused<T>(false, lv.g, P, src, ec, b, q, dst, h->stream, finest, stop);
-        std::swap(src, dst);
-        s = 1;
+    const Stencil<T> &P = LP::P(lv);
+    const cx<T> *q = LP::q(lv);
+    const bool zero2 = zero && nu >= 2;
+    const int nk = zero2 ? nu - 1 : nu;   // launches
+    const bool alias = (src == dst);      // then launches alternate tmp, dst, ... (a copy ends an odd count)
+    const cx<T> *cur = src;
+    for (int kk = 0; kk < nk; ++kk) {
+        cx<T> *o = alias ? ((kk % 2 == 0) ? tmp : dst) : (((nk - 1 - kk) % 2 == 0) ? dst : tmp);
+        const int pi = finest ? prof_begin(h, prof_id) : -1;
+        if (kk == 0 && zero2)
+            launch_sweep3d_fused<T>(true, lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop);
+        else if (kk == 0 && zero)
+            launch_stencil<T>(MODE_JACOBI0, lv.g, P, cur, b, q, o, nullptr, h->stream, finest, stop);
+        else if (kk == 0 && ec)
+            launch_sweep3d_fused<T>(false, lv.g, P, cur, ec, b, q, o, h->stream, finest, stop);
+        else
+            launch_stencil<T>(MODE_JACOBI, lv.g, P, cur, b, q, o, nullptr, h->stream, finest, stop);
+        prof_end(h, prof_id, pi);
+        cur = o;
     }
-    for (; s < nu; ++s) {
-        int mode = (s == 0 && zero_guess) ? MODE_JACOBI0 : MODE_JACOBI;
-        int pi = (finest && mode == MODE_JACOBI) ? prof_begin(h, PROF_PRE) : -1;
-        launch_stencil<T>(mode, lv.g, P, src, b, q, dst, nullptr, h->stream, finest, stop);
-        prof_end(h, PROF_PRE, pi);
-        std::swap(src, dst);
-    }
-    if (src != u) launch_copy<T>(src, u, lv.g.N(), h->stream, stop);
+    if (cur != dst) launch_copy<T>(cur, dst, lv.g.N(), h->stream, stop);
 }
 
 // Fused 2D smoothing chain: nu sweeps from src (0 when zero; src + P ec when
@@ -216,10 +217,11 @@ void smooth_chain2d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
     const cx<T> *cur = src;
     int left = nu, kk = 0;
     int nk = (nu + 1) / 2;
+    const bool alias = (src == dst);   // then launches alternate tmp, dst, ... (a copy ends an odd count)
     while (left > 0) {
         int ns = left >= 2 ? 2 : 1;
         left -= ns;
-        cx<T> *o = ((nk - 1 - kk) % 2 == 0) ? dst : tmp;   // the last launch lands in dst
+        cx<T> *o = alias ? ((kk % 2 == 0) ? tmp : dst) : (((nk - 1 - kk) % 2 == 0) ? dst : tmp);
         int pi = finest ? prof_begin(h, prof_id) : -1;
         launch_smooth2d<T>(lv.g, LP::P(lv), ns, zero, cur, ec, b, LP::q(lv), o, h->stream, finest && ns == 2, stop,
                            SMOOTH_TH[h->smooth_variant]);
@@ -229,6 +231,7 @@ void smooth_chain2d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
         ec = nullptr;
         ++kk;
     }
+    if (cur != dst) launch_copy<T>(cur, dst, lv.g.N(), h->stream, stop);
 }
 
 // One V(nu1, nu2) cycle with the fused 2D kernels: pre-smoothing u -> t,
@@ -592,29 +595,35 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
         return;
     }
     const int nu1 = nu_pre(h, l), nu2 = nu_post(h, l);
-    const bool fuse3 = lv.g.dim == 3 && h->opt.tile_config != TILE_REFERENCE;
-    if (nu1 > 0) {
-        if (fuse3)
-            smooth3d_fused<T>(h, lv, b, u, nu1, zero_guess, nullptr, stop);
-        else
-            smooth<T>(h, lv, b, u, nu1, zero_guess, stop);
-    } else if (zero_guess) {
-        launch_zero<T>(u, lv.g.N(), h->stream, stop);
-    }
     Level &lc = h->L[l + 1];
-    if (fuse3) {
-        launch_resid_restrict3d<T>(lv.g, LP::P(lv), u, b, LP::q(lv), LP::b(lc), h->stream, stop);
-    } else {
-        launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
-        launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream, stop);
+    if (lv.g.dim == 3 && h->opt.tile_config != TILE_REFERENCE) {
+        // fused 3D level: pre-smoothing u -> t, residual + restriction from
+        // t, coarse correction, interpolation fused into post-smoothing t -> u
+        cx<T> *t = LP::t(lv), *scratch = LP::r(lv);
+        cx<T> *cur = u;
+        if (nu1 > 0) {
+            smooth_chain3d<T>(h, lv, b, u, t, scratch, nu1, zero_guess, nullptr, PROF_PRE, stop);
+            cur = t;
+        } else if (zero_guess) {
+            launch_zero<T>(u, lv.g.N(), h->stream, stop);
+        }
+        launch_resid_restrict3d<T>(lv.g, LP::P(lv), cur, b, LP::q(lv), LP::b(lc), h->stream, stop);
+        vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
+        if (nu2 > 0) {
+            smooth_chain3d<T>(h, lv, b, cur, u, scratch, nu2, false, LP::u(lc), PROF_POST, stop);
+        } else {
+            if (cur != u) launch_copy<T>(cur, u, lv.g.N(), h->stream, stop);
+            launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
+        }
+        return;
     }
+    if (nu1 > 0) smooth<T>(h, lv, b, u, nu1, zero_guess, stop);
+    else if (zero_guess) launch_zero<T>(u, lv.g.N(), h->stream, stop);
+    launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
+    launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream, stop);
     vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
-    if (fuse3 && nu2 > 0) {
-        smooth3d_fused<T>(h, lv, b, u, nu2, false, LP::u(lc), stop);
-    } else {
-        launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
-        if (nu2 > 0) smooth<T>(h, lv, b, u, nu2, false, stop);
-    }
+    launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
+    if (nu2 > 0) smooth<T>(h, lv, b, u, nu2, false, stop);
 }
 template void vcycle<double>(ffmg_handle *, int, const cd *, cd *, bool, const int *);
 template void vcycle<float>(ffmg_handle *, int, const cf *, cf *, bool, const int *);

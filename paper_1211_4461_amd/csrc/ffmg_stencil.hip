@@ -434,6 +434,7 @@ template void launch_sweep3d_fused<double>(bool, const LevelGeom &, const Stenci
 template void launch_sweep3d_fused<float>(bool, const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
                                           const cf *, const cf *, cf *, hipStream_t, bool, const int *);
 
+
 // Copy / zero with the loop's stop flag.
 template <typename T>
 __global__ __launch_bounds__(256) void k_copy(const cx<T> *__restrict__ src, cx<T> *__restrict__ dst, size_t N,

@@ -277,7 +277,7 @@ def test_fused_2d_path_is_bitwise_identical(ff, orc, n):
         ff.mg_vcycle(hr, b, ur)
     torch.cuda.synchronize()
     assert torch.equal(uf, ur)
-    for nu1, nu2 in [(1, 1), (3, 0), (0, 3)]:
+    for nu1, nu2 in [(1, 1), (3, 0), (0, 3), (0, 2), (0, 1), (2, 0)]:
         hf2, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2)
         hr2, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2, tile_config=1)
         uf, ur = torch.zeros_like(b), torch.zeros_like(b)
@@ -316,7 +316,7 @@ def test_fused_3d_path_is_bitwise_identical(ff, orc, n):
     bit with the reference path, for FP64 V-cycles with several (nu1, nu2)
     and for FP32-in-FP64 solves."""
     w = W.radial_3d(n, L=5.0, k0=1.3, n_az=4, n_pol=3)
-    for nu1, nu2 in [(2, 2), (1, 1), (3, 1), (0, 2), (2, 0)]:
+    for nu1, nu2 in [(2, 2), (1, 1), (3, 1), (0, 2), (0, 1), (0, 3), (2, 0), (4, 3)]:
         hf, _, g, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2)
         hr, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2, tile_config=1)
         b = ff.mg_rhs_plane_wave(hf, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
