@@ -424,6 +424,43 @@ void or_mg_vcycle(void *p, const cplx *b, cplx *u)
     vcycle((or_mg *)p, 0, b, u);
 }
 
+/* Full multigrid start (Sec. 4 with Tables 3 and 4, the nested iteration of
+ * V-cycles; Sec. 5.7, the F(5) cycle): the right-hand side of every coarser
+ * level is the fine one sampled at the coarse nodes (injection: the same
+ * problem discretized on the coarse grid, as the coefficients are), the
+ * coarsest level is solved exactly, and on every level between it and the
+ * finest the interpolated coarser solution is improved by k V-cycles.  u
+ * receives the interpolated level-1 solution: the initial guess of the
+ * finest-level solve. */
+void or_mg_fmg(void *p, const cplx *b, cplx *u, int k)
+{
+    or_mg *g = p;
+    int dim = g->dim, L = g->nlev - 1;
+    long N0 = npts(dim, g->m[0]);
+    if (L == 0) {                                  /* one level: exact solve */
+        memcpy(u, b, (size_t)N0 * sizeof(cplx));
+        or_lu_solve(N0, g->LU, g->piv, u);
+        return;
+    }
+    cplx *fb[OR_MAXLEV], *fu[OR_MAXLEV];
+    fb[0] = (cplx *)b;
+    for (int l = 1; l <= L; ++l) {
+        long N = npts(dim, g->m[l]);
+        fb[l] = malloc((size_t)N * sizeof(cplx));
+        fu[l] = calloc((size_t)N, sizeof(cplx));
+        or_inject(dim, g->m[l - 1], fb[l - 1], fb[l]);            /* b_l = b_{l-1} at coarse nodes */
+    }
+    memcpy(fu[L], fb[L], (size_t)npts(dim, g->m[L]) * sizeof(cplx));
+    or_lu_solve(npts(dim, g->m[L]), g->LU, g->piv, fu[L]);          /* exact on the coarsest */
+    for (int l = L - 1; l >= 1; --l) {
+        or_prolong_add(dim, g->m[l + 1], fu[l + 1], fu[l]);          /* u_l = P u_{l+1} (fu[l] = 0) */
+        for (int c = 0; c < k; ++c) vcycle(g, l, fb[l], fu[l]);      /* k V-cycles on level l */
+    }
+    memset(u, 0, (size_t)N0 * sizeof(cplx));
+    or_prolong_add(dim, g->m[1], fu[1], u);                          /* finest initial guess */
+    for (int l = 1; l <= L; ++l) { free(fb[l]); free(fu[l]); }
+}
+
 static double norm2(long N, const cplx *v)
 {
     double s = 0.0;

@@ -55,6 +55,7 @@ def lib():
         L.or_mg_coarse_n.restype = lp
         L.or_mg_kappa.argtypes = [vp, ip, vp]
         L.or_mg_vcycle.argtypes = [vp, vp, vp]
+        L.or_mg_fmg.argtypes = [vp, vp, vp, ip]
         L.or_mg_solve.argtypes = [vp, vp, vp, dp, ip, vp, vp]
         L.or_mg_solve.restype = ip
         L.or_apply.argtypes = [ip, vp, vp, dp, vp, vp, vp]
@@ -230,6 +231,16 @@ class Multigrid:
         uu = np.array(u, dtype=np.complex128, copy=True).ravel()
         lib().or_mg_vcycle(self._h, bp, uu.ctypes.data)
         return uu.reshape(np.shape(u))
+
+    def fmg(self, b, k):
+        """Full multigrid initial guess (Sec. 4, Tables 3-4: nested
+        iteration; Sec. 5.7: the F(k) cycle): coarse right-hand sides by
+        injection, exact coarsest solve, k V-cycles on each level between,
+        interpolated to the finest."""
+        bb, bp = _c(b.ravel(), np.complex128)
+        u = np.empty_like(bb)
+        lib().or_mg_fmg(self._h, bp, u.ctypes.data, int(k))
+        return u.reshape(np.shape(b))
 
     def solve(self, b, u0=None, tol=1e-10, max_cycles=200):
         """Returns (u, status, cycles, residual history)."""

@@ -104,6 +104,38 @@ def dense_vcycle(m, h, gamma, kappa, b, u, nu1, nu2, omega, coarsest_n=8):
     return u
 
 
+def prolong_sparse(mf):
+    """prolong(mf) as a sparse matrix (large fine grids)."""
+    out = None
+    for m in mf:                 # x first; kron puts later factors slower
+        M = sp.csr_matrix(2.0 * fw_1d(m).T)
+        out = M if out is None else sp.kron(M, out, format="csr")
+    return out
+
+
+def dense_fmg(m, h, gamma, kappa, b, k, nu1, nu2, omega, coarsest_n=8):
+    """Full-multigrid initial guess for the grid with interior counts m,
+    written with the matrices above: the right-hand side and kappa of each
+    coarser grid are the finer ones at the coarse nodes, the coarsest system
+    is solved exactly, each level in between runs k dense V-cycles from the
+    interpolated coarser solution, and the guess is the interpolated
+    solution of the first coarse level."""
+    m = list(m)
+    if min(mk + 1 for mk in m) <= coarsest_n:
+        return np.linalg.solve(kron_operator(m, h, gamma, kappa).toarray(), b)
+    idx = inject_index(m)
+    mc = [(mk - 1) // 2 for mk in m]
+    hc = [2 * hk for hk in h]
+    kc, bc = np.asarray(kappa).ravel()[idx], np.asarray(b).ravel()[idx]
+    if min(mk + 1 for mk in mc) <= coarsest_n:
+        uc = np.linalg.solve(kron_operator(mc, hc, gamma, kc).toarray(), bc)
+    else:
+        uc = dense_fmg(mc, hc, gamma, kc, bc, k, nu1, nu2, omega, coarsest_n)
+        for _ in range(k):
+            uc = dense_vcycle(mc, hc, gamma, kc, bc, uc, nu1, nu2, omega, coarsest_n)
+    return prolong_sparse(m) @ uc
+
+
 # ------------------------------------------------------------------ physics
 
 def born_2d(k0, amp, sigma, alpha_dirs, eta):

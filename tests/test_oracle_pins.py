@@ -139,6 +139,74 @@ def test_vcycle_matches_dense_matrix_cycle(orc, dim, n, nu):
     assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("dim,n,k,nu", [(2, (64, 64), 1, (2, 2)), (2, (128, 64), 2, (1, 1)),
+                                         (2, (16, 32), 3, (2, 2)), (3, (32, 32, 32), 2, (2, 2))])
+def test_fmg_matches_dense_nested_iteration(orc, dim, n, k, nu):
+    """Full multigrid start (Sec. 4 with Tables 3 and 4; Sec. 5.7, the F(5)
+    cycle) written with dense Kronecker matrices: right-hand side and kappa
+    injected level by level, exact coarsest solve, k dense V-cycles on every
+    level in between, interpolation to the finest grid.  (16, 32) has two
+    levels: the guess is the interpolated exact coarse solution."""
+    L = [4.0] * dim
+    g = orc.Grid(dim, n, [-l for l in L], L)
+    r = rng(4)
+    kappa = 4.0 * (1.0 + 0.5 * r.random(g.shape)) + 0.3j * r.random(g.shape)
+    b = crand(r, g.shape)
+    mg = orc.Multigrid(g, G30, kappa, nu1=nu[0], nu2=nu[1], omega=0.8)
+    got = mg.fmg(b, k)
+    ref = refs.dense_fmg(list(g.m), list(g.h), G30, kappa.ravel(), b.ravel(), k, nu[0], nu[1],
+                         0.8).reshape(g.shape)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _coarse_direct(orc, g, gamma, kappa, b):
+    """Exact solution of the problem rediscretized on the first coarse grid
+    (right-hand side and kappa at the coarse nodes, spacing 2h)."""
+    m = list(g.m)
+    idx = refs.inject_index(m)
+    A1 = refs.kron_operator([(x - 1) // 2 for x in m], [2 * x for x in g.h], gamma, kappa.ravel()[idx])
+    return spla.spsolve(A1.tocsc(), b.ravel()[idx]), idx
+
+
+def test_fmg_limit_is_interpolated_coarse_solution(orc):
+    """With many V-cycles per level every coarse level is solved exactly, so
+    the guess tends to P A_1^{-1} b_1 (sparse direct solve of the coarse
+    system); the distance falls monotonically with the cycles per level."""
+    w = W.small_2d(n=128)
+    g = orc.Grid(2, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    u1, _ = _coarse_direct(orc, g, w.gamma, kappa, b)
+    lim = (refs.prolong_sparse(list(g.m)) @ u1).reshape(g.shape)
+    errs = [np.linalg.norm(mg.fmg(b, k) - lim) / np.linalg.norm(lim) for k in (1, 2, 3, 5, 10, 30)]
+    assert all(e1 < e0 for e0, e1 in zip(errs, errs[1:])), errs
+    assert errs[-1] < 1e-12, errs
+
+
+def test_fmg_reaches_discretization_accuracy(orc):
+    """The textbook property of the full multigrid cycle: from its start one
+    V-cycle on the finest grid leaves an algebraic error well below the
+    discretization error (estimated by the gap between the exact fine and
+    coarse discrete solutions at the coarse nodes), and the finest-level
+    solve needs fewer cycles than from u = 0 (Sec. 4, Table 3)."""
+    w = W.small_2d(n=128)
+    g = orc.Grid(2, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    A = refs.kron_operator(list(g.m), list(g.h), w.gamma, kappa)
+    us = spla.spsolve(A.tocsc(), b.ravel()).reshape(g.shape)
+    u1, idx = _coarse_direct(orc, g, w.gamma, kappa, b)
+    e_disc = np.linalg.norm(us.ravel()[idx] - u1) / np.linalg.norm(u1)
+    u0 = mg.fmg(b, 2)
+    e_alg = np.linalg.norm(mg.vcycle(b, u0) - us) / np.linalg.norm(us)
+    assert e_alg < 0.25 * e_disc, (e_alg, e_disc)
+    _, st0, k_zero, _ = mg.solve(b, tol=1e-10)
+    _, st1, k_fmg, _ = mg.solve(b, u0=u0, tol=1e-10)
+    assert st0 == 0 and st1 == 0 and k_fmg < k_zero, (k_fmg, k_zero)
+
+
 def test_coarse_kappa_is_injected(orc):
     g = orc.Grid(2, 32, -4, 4)
     r = rng(5)
