@@ -57,11 +57,13 @@ KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3), ("ffgemm", 4))
 NET_FLOP_PER_POINT = 8 * 2736
 
 
-def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point):
+def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0):
     """Time `steps` maps.  The warm-up maps record every timed kernel; the one
     with the largest total time is the dominant kernel, and inside the timed
-    region HIP events bracket only that kernel's launches."""
-    opts = ff.default_options(precision=precision, ff_precision=ff_precision)
+    region HIP events bracket only that kernel's launches.  fmg_cycles > 0:
+    every solve starts from the full multigrid guess (k V-cycles per coarse
+    level) instead of u = 0."""
+    opts = ff.default_options(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles)
     h, coef = ff.setup_workload(w, options=opts)
     from paper_1211_4461_amd import autotune
     tune = {"ff_gemm": None, "smooth": None, "tail": None}
@@ -388,6 +390,7 @@ def main():
                     help="far-field contraction of the mixed path")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Schroedinger workload")
     ap.add_argument("--no-3d", action="store_true", help="skip the 512^3 workload")
+    ap.add_argument("--no-fmg", action="store_true", help="skip the full-multigrid-start forms")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -485,6 +488,24 @@ def main():
                               "farfield_gemm": gemm_report(pp, w, "fp64")}
         line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
         line["mixed_vs_plain_farfield_rel_err"] = ef
+    if not args.no_fmg:
+        # full multigrid start (nested iteration, F(k) cycle): the same map to
+        # the same tolerance with fewer finest-level cycles
+        fm = {}
+        for prec, ffp_k, ks, tag, bpp in ((ffmg.FP32_IR, ffp, (1, 2, 3), "mixed", bpp_mixed),
+                                           (ffmg.FP64, ffmg.FF_FP64, (1, 2), "plain_fp64", bpp_plain)):
+            if tag == "plain_fp64" and plain is None:
+                continue
+            ref = mixed if tag == "mixed" else plain
+            for k in ks:
+                r = run_path(ffmg, torch, w, prec, ffp_k, max(args.steps // 2, 2), args.warmup, bpp, fmg_cycles=k)
+                fm[f"{tag}_k{k}"] = {
+                    "maps_per_s": round(r["maps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
+                    "cycles": r["cycles"], "vcycles_finest": r["vcycles"], "rel_residual": r["rel_residual"],
+                    "speedup_vs_zero_start": round(r["maps_per_s"] / ref["maps_per_s"], 3),
+                    "farfield_rel_diff_vs_zero_start": float(np.linalg.norm(r["F"] - ref["F"])
+                                                             / np.linalg.norm(ref["F"]))}
+        line["fmg_start"] = fm
     if not args.no_3d:
         line["gauss_3d"] = run_3d(ffmg, torch, W)
     if not args.no_batch:

@@ -102,6 +102,9 @@ typedef struct ffmg_options {
                              the network (0 = the finest level only; levels of
                              the LDS tail never do); the others use weighted
                              Jacobi                                            */
+    int fmg_cycles;       /* mg_solve starts from the full multigrid guess of
+                             mg_fmg with this many V-cycles per coarse level
+                             (0 = off: start from the caller's u)            */
     void *stream;         /* hipStream_t; NULL = the null stream               */
 } ffmg_options;
 
@@ -110,7 +113,7 @@ typedef struct ffmg_solve_info {
     int vcycles;          /* V-cycles in total (FP32_IR: steps x inner_cycles) */
     int status;           /* ffmg_status of the solve                          */
     double rel_residual;  /* ||b - A u||_2 / ||b||_2 in FP64 at return         */
-    double conv_factor;   /* (||r_k|| / ||r_0||)^(1/k)  (Sec. 5.4 definition)  */
+    double conv_factor;   /* (||r_k|| / ||r_0||)^(1/k)  (Sec. 5.5/5.7 rate)   */
     int fell_back;        /* learned smoother replaced by Jacobi (1) or not    */
     double t_solve_ms;    /* wall time of the solve on the stream              */
 } ffmg_solve_info;
@@ -122,7 +125,7 @@ void ffmg_default_options(ffmg_options *o);
 /* Build the multigrid hierarchy for one problem (Sec. 4; coarse grids
  * n/2^l down to coarsest_n, coefficients injected, coarse operators
  * rediscretised at 2^l h; the coarsest system is inverted exactly, as the
- * 7^3 grid of the F(5) cycle in Sec. 5.5).  Copies coef; allocates all device
+ * 7^3 grid of the F(5) cycle in Sec. 5.7).  Copies coef; allocates all device
  * workspace.  EINVAL on bad sizes or angles; ENAN if coef holds NaN/Inf;
  * ENOMEM / EDEVICE on HIP failures.  *out is NULL on failure. */
 ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle **out);
@@ -139,11 +142,26 @@ ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b);
  * complex128[N], read; u: DEVICE complex128[N], updated.  Always FP64. */
 ffmg_status mg_vcycle(ffmg_handle *h, const void *b, void *u);
 
+/* Full multigrid start (Sec. 4 with Tables 3 and 4: the nested iteration of
+ * V-cycles; Sec. 5.7: the F(k) cycle).  u <- the initial guess for A u = b on
+ * the finest grid: b sampled at the nodes of every coarser level
+ * (injection: the same problem discretised on the coarse grid, like the
+ * coefficients), exact solve on the coarsest level, then on each level
+ * between, from the interpolated coarser solution, k V-cycles; u is the
+ * interpolated solution of the first coarse level (no cycle runs on the
+ * finest level).  Computed in FP64, or, when the handle's precision is
+ * FFMG_FP32_IR, in FP32 on b scaled to unit RMS (scaled back in FP64).
+ * b: DEVICE complex128[N], read; u: DEVICE complex128[N], overwritten (not
+ * read).  0 <= k <= 64 (EINVAL otherwise).  A one-level hierarchy gives the
+ * exact solve.  Synchronises. */
+ffmg_status mg_fmg(ffmg_handle *h, const void *b, void *u, int k);
+
 /* Solve A u = b by V-cycles (FP64) or by FP32 V-cycles inside FP64
  * iterative refinement (FP32_IR: FP64 outer residual, FP64 update, FP64
- * coarsest solve), from the guess in u, until ||b - A u||_2 <= tol ||b||_2
- * (residual-reduction tolerance, Sec. 4).  u: DEVICE complex128[N], in:
- * guess, out: solution.  ENOCONV after max_cycles or when the residual grows
+ * coarsest solve), from the guess in u (or, with options.fmg_cycles > 0,
+ * from the mg_fmg guess, which overwrites u first), until
+ * ||b - A u||_2 <= tol ||b||_2 (residual-reduction tolerance, Sec. 4).
+ * u: DEVICE complex128[N], in: guess, out: solution.  ENOCONV after max_cycles or when the residual grows
  * on 3 consecutive cycles; u then holds the last iterate and info is filled.
  * b = 0 returns u = 0 after 0 cycles.  info may be NULL.  Synchronises. */
 ffmg_status mg_solve(ffmg_handle *h, const void *b, void *u, double tol, ffmg_solve_info *info);
@@ -178,7 +196,9 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
  * graph are owned by hs[0] (freed by mg_destroy(hs[0])) and reused while the
  * same list of handles is passed; the call is ordered after work on hs[0]'s
  * stream and synchronises.  Returns ENOCONV if an instance did not converge
- * (infos tells which), ENAN if a right-hand side is not finite. */
+ * (infos tells which), ENAN if a right-hand side is not finite.  Handles
+ * with options.fmg_cycles > 0 are refused (EINVAL): the batch starts from
+ * u = 0. */
 ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *etas, void *const *u, double tol,
                              ffmg_solve_info *infos);
 

@@ -31,7 +31,7 @@
  *     restriction, bilinear/trilinear prolongation, rediscretised coarse
  *     operators with injected kappa, exact (LU) solve on the coarsest grid
  *     (Sec. 4: V-cycles, bilinear interpolation and full weighting; F(5)
- *     cycle of Sec. 5.5: coarsest 7^3 grid solved exactly).
+ *     cycle of Sec. 5.7: coarsest 7^3 grid solved exactly).
  */
 #include <complex.h>
 #include <math.h>

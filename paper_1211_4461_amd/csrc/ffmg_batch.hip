@@ -298,6 +298,9 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
             return bail(fail(h0, FFMG_EINVAL,
                              "instance %d: batched solves need 2D operators set up with precision FP32_IR and the "
                              "fused kernels (tile_config 0)", i));
+        if (o.fmg_cycles != 0)
+            return bail(fail(h0, FFMG_EINVAL, "instance %d: batched solves start from u = 0 (fmg_cycles must be 0)",
+                             i));
         if (o.nu1 != B.nu1 || o.nu2 != B.nu2 || o.nu1 < 1 || o.nu2 < 1 ||
             (o.nu_coarse != 0 && (o.nu_coarse != o.nu1 || o.nu_coarse != o.nu2)) ||
             (o.inner_cycles > 0 ? o.inner_cycles : DEFAULT_INNER_CYCLES) != B.inner || o.smoother != FFMG_SMOOTH_JACOBI)

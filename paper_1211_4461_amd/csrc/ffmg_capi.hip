@@ -313,6 +313,7 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
         return fail(tmp, FFMG_EINVAL, "unknown far-field precision %d", o->ff_precision);
     if (o->tile_config < 0 || o->tile_config > 2) return fail(tmp, FFMG_EINVAL, "unknown tile_config");
     if (o->inner_cycles < 0 || o->inner_cycles > 16) return fail(tmp, FFMG_EINVAL, "inner_cycles must be in [0, 16]");
+    if (o->fmg_cycles < 0 || o->fmg_cycles > 64) return fail(tmp, FFMG_EINVAL, "fmg_cycles must be in [0, 64]");
     return FFMG_OK;
 }
 
@@ -628,6 +629,42 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
 template void vcycle<double>(ffmg_handle *, int, const cd *, cd *, bool, const int *);
 template void vcycle<float>(ffmg_handle *, int, const cf *, cf *, bool, const int *);
 
+// Full multigrid start on the stream: the finest right-hand side injected
+// level by level into the coarse right-hand-side buffers, exact solve on the
+// coarsest level, then, finest-ward, each level's solution buffer set to the
+// interpolated coarser solution and improved by k V-cycles; u = P u_1.  A
+// V-cycle on level l uses only the buffers of levels >= l + 1 besides its
+// own temporaries, so the hierarchy's coarse buffers hold the start too.
+// T = float works on b / s, s = sqrt(*bnorm2 / N) (unit RMS).
+template <typename T>
+void fmg_start(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2)
+{
+    using LP = LvlPtr<T>;
+    const int last = (int)h->L.size() - 1;
+    Level &l0 = h->L[0];
+    if (last == 0) {
+        launch_coarse_apply<double>(h->aug, h->nc, b, u, h->stream, nullptr);
+        return;
+    }
+    launch_inject_rhs<T>(l0.g, b, LP::b(h->L[1]), bnorm2, h->stream);
+    for (int l = 1; l < last; ++l) launch_inject<T>(h->L[l].g, LP::b(h->L[l]), LP::b(h->L[l + 1]), h->stream);
+    launch_coarse_apply<T>(h->aug, h->nc, LP::b(h->L[last]), LP::u(h->L[last]), h->stream, nullptr);
+    for (int l = last - 1; l >= 1; --l) {
+        Level &lv = h->L[l];
+        launch_prolong_set<T, T>(lv.g, LP::u(h->L[l + 1]), LP::u(lv), nullptr, 1.0, h->stream);
+        for (int c = 0; c < k; ++c) vcycle<T>(h, l, LP::b(lv), LP::u(lv), false, nullptr);
+    }
+    launch_prolong_set<T, double>(l0.g, LP::u(h->L[1]), u, bnorm2, 1.0 / sqrt((double)l0.g.N()), h->stream);
+}
+
+// The FMG start in the handle's precision; bnorm2: ||b||^2 on the device
+// (read by the FP32 form only).
+void fmg_enqueue(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2)
+{
+    if (h->opt.precision == FFMG_FP32_IR) fmg_start<float>(h, b, u, k, bnorm2);
+    else fmg_start<double>(h, b, u, k, nullptr);
+}
+
 }  // namespace ffmg
 
 // =========================================================================
@@ -645,6 +682,7 @@ void ffmg_default_options(ffmg_options *o)
     o->precision = FFMG_FP64;
     o->smoother = FFMG_SMOOTH_JACOBI;
     o->ff_precision = FFMG_FF_FP64;
+    o->fmg_cycles = 0;
 }
 
 const char *ffmg_strerror(ffmg_status s)
@@ -799,6 +837,24 @@ ffmg_status mg_vcycle(ffmg_handle *h, const void *b, void *u)
     return FFMG_OK;
 }
 
+ffmg_status mg_fmg(ffmg_handle *h, const void *bv, void *uv, int k)
+{
+    if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
+    if (k < 0 || k > 64) return fail(h, FFMG_EINVAL, "k must be in [0, 64]");
+    const cd *b = (const cd *)bv;
+    cd *u = (cd *)uv;
+    h->learned_on = (h->opt.smoother == FFMG_SMOOTH_LEARNED);
+    double bn2 = 0.0;
+    if (h->opt.precision == FFMG_FP32_IR) {
+        TRY(norm2_of(h, b, h->L[0].g.N(), &bn2));   // leaves ||b||^2 in h->d_scalar
+        if (!isfinite(bn2)) return fail(h, FFMG_ENAN, "right-hand side holds non-finite values");
+    }
+    fmg_enqueue(h, b, u, k, h->d_scalar);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return FFMG_OK;
+}
+
 ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_solve_info *info)
 {
     if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
@@ -835,6 +891,8 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
     const int maxc = h->opt.max_cycles;
     launch_ctl_init(h->d_ctl, h->d_scalar, tol, N, maxc, h->stream);
     const int *stop = &h->d_ctl->done;
+    h->learned_on = (h->opt.smoother == FFMG_SMOOTH_LEARNED);
+    if (h->opt.fmg_cycles > 0) fmg_enqueue(h, b, u, h->opt.fmg_cycles, h->d_scalar);
     // initial residual (cycle 0)
     if (h->opt.precision == FFMG_FP64) {
         launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
@@ -851,7 +909,6 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
     // residual growth, switch the rest of the solve to Jacobi; a non-finite
     // iterate or a residual ten times the initial one restarts it with Jacobi
     // from u = 0.
-    h->learned_on = (h->opt.smoother == FFMG_SMOOTH_LEARNED);
     cd *ua = u, *ub = l0.t;
     int queued = 0;
     int batch = h->last_cycles > 0 ? h->last_cycles : 4;

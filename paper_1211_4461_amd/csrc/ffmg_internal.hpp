@@ -108,6 +108,15 @@ template <typename T>
 void launch_inject(const LevelGeom &fine, const cx<T> *qf, cx<T> *qc, hipStream_t s);
 template <typename To, typename Ti>
 void launch_convert(const cx<Ti> *in, cx<To> *out, size_t N, hipStream_t s);
+// Full multigrid transfers: the finest right-hand side at the first coarse
+// level's nodes, divided by s = sqrt(*bnorm2 / N) (s = 1 when bnorm2 is
+// null), and uf = s P ec overwriting uf (inv_sqN = 1 / sqrt(N) of the finest
+// level; s = 1 when bnorm2 is null).
+template <typename TO>
+void launch_inject_rhs(const LevelGeom &fine, const cd *bf, cx<TO> *bc, const double *bnorm2, hipStream_t s);
+template <typename TC, typename TF>
+void launch_prolong_set(const LevelGeom &fine, const cx<TC> *ec, cx<TF> *uf, const double *bnorm2, double inv_sqN,
+                        hipStream_t s);
 void launch_build_coarse(const LevelGeom &g, const Stencil<double> &P, const cd *q, cd *aug, hipStream_t s);
 void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s);
 template <typename T>

@@ -3,7 +3,7 @@
 // omega-Jacobi), full-weighting restriction and bilinear / trilinear
 // interpolation (Sec. 4), residual norms, and the setup kernels (contrast,
 // injected coarse coefficients, exact inverse of the coarsest operator as in
-// the F(5) cycle of Sec. 5.5, plane-wave right-hand side of Sec. 2.1).
+// the F(5) cycle of Sec. 5.7, plane-wave right-hand side of Sec. 2.1).
 //
 // All of these are HBM-bandwidth bound (about one flop per byte).  The sweeps
 // stage a u tile with its halo in LDS (2D: one 64 x TY tile; 3D: the centre
@@ -824,6 +824,90 @@ void launch_inject(const LevelGeom &f, const cx<T> *qf, cx<T> *qc, hipStream_t s
 }
 template void launch_inject<double>(const LevelGeom &, const cd *, cd *, hipStream_t);
 template void launch_inject<float>(const LevelGeom &, const cf *, cf *, hipStream_t);
+
+// Full multigrid transfers.  The scale s = sqrt(bnorm2) / sqrt(N) (the RMS
+// of the finest right-hand side; 1 without bnorm2) keeps an FP32 hierarchy
+// at unit size: the start is computed for b / s and multiplied back by s.
+__device__ __forceinline__ double fmg_scale(const double *bnorm2, double inv_sqN)
+{
+    if (!bnorm2) return 1.0;
+    double s = sqrt(bnorm2[0]) * inv_sqN;
+    return (s > 0.0 && isfinite(s)) ? s : 1.0;
+}
+
+// b_1 = b_0 / s at the coarse nodes (injection of the finest right-hand side).
+template <typename TO>
+__global__ __launch_bounds__(256) void k_inject_rhs(const cd *__restrict__ bf, cx<TO> *__restrict__ bc, int mxf,
+                                                    int myf, int mxc, int myc, int mzc, int dim,
+                                                    const double *__restrict__ bnorm2, double inv_sqN)
+{
+    size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t Nc = (size_t)mxc * myc * mzc;
+    if (idx >= Nc) return;
+    const double inv = 1.0 / fmg_scale(bnorm2, inv_sqN);
+    int I = (int)(idx % mxc);
+    size_t rest = idx / mxc;
+    int J = (int)(rest % myc);
+    int K = (int)(rest / myc);
+    int z = (dim == 3) ? 2 * K + 1 : 0;
+    cd v = bf[((size_t)z * myf + (2 * J + 1)) * mxf + (2 * I + 1)];
+    bc[idx] = cvt<TO>(cd{v.re * inv, v.im * inv});
+}
+
+template <typename TO>
+void launch_inject_rhs(const LevelGeom &f, const cd *bf, cx<TO> *bc, const double *bnorm2, hipStream_t s)
+{
+    int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.dim == 3) ? (f.m[2] - 1) / 2 : 1;
+    size_t Nc = (size_t)mxc * myc * mzc;
+    hipLaunchKernelGGL((k_inject_rhs<TO>), dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, s, bf, bc, f.m[0],
+                       f.m[1], mxc, myc, mzc, f.dim, bnorm2, 1.0 / sqrt((double)f.N()));
+}
+template void launch_inject_rhs<double>(const LevelGeom &, const cd *, cd *, const double *, hipStream_t);
+template void launch_inject_rhs<float>(const LevelGeom &, const cd *, cf *, const double *, hipStream_t);
+
+// uf = s P ec: the interpolated coarse solution overwrites uf (the initial
+// guess of the next finer level).
+template <typename TC, typename TF, int DIM>
+__global__ __launch_bounds__(256) void k_prolong_set(const cx<TC> *__restrict__ ec, cx<TF> *__restrict__ uf, int mxf,
+                                                     int myf, int mzf, int mxc, int myc, int mzc,
+                                                     const double *__restrict__ bnorm2, double inv_sqN)
+{
+    size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t Nf = (size_t)mxf * myf * mzf;
+    if (idx >= Nf) return;
+    int ix = (int)(idx % mxf);
+    size_t rest = idx / mxf;
+    int iy = (int)(rest % myf);
+    int iz = (int)(rest / myf);
+    cx<TC> v = prolong_at<TC, DIM>(ec, ix, iy, iz, mxc, myc, mzc);
+    if (bnorm2) {
+        const double sc = fmg_scale(bnorm2, inv_sqN);
+        uf[idx] = cvt<TF>(cd{(double)v.re * sc, (double)v.im * sc});
+    } else {
+        uf[idx] = cvt<TF>(v);
+    }
+}
+
+template <typename TC, typename TF>
+void launch_prolong_set(const LevelGeom &f, const cx<TC> *ec, cx<TF> *uf, const double *bnorm2, double inv_sqN,
+                        hipStream_t s)
+{
+    int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.dim == 3) ? (f.m[2] - 1) / 2 : 1;
+    size_t Nf = f.N();
+    unsigned nb = (unsigned)((Nf + 255) / 256);
+    if (f.dim == 2)
+        hipLaunchKernelGGL((k_prolong_set<TC, TF, 2>), dim3(nb), dim3(256), 0, s, ec, uf, f.m[0], f.m[1], 1, mxc, myc,
+                           1, bnorm2, inv_sqN);
+    else
+        hipLaunchKernelGGL((k_prolong_set<TC, TF, 3>), dim3(nb), dim3(256), 0, s, ec, uf, f.m[0], f.m[1], f.m[2],
+                           mxc, myc, mzc, bnorm2, inv_sqN);
+}
+template void launch_prolong_set<double, double>(const LevelGeom &, const cd *, cd *, const double *, double,
+                                                 hipStream_t);
+template void launch_prolong_set<float, float>(const LevelGeom &, const cf *, cf *, const double *, double,
+                                               hipStream_t);
+template void launch_prolong_set<float, double>(const LevelGeom &, const cf *, cd *, const double *, double,
+                                                hipStream_t);
 
 template <typename To, typename Ti>
 __global__ __launch_bounds__(256) void k_convert(const cx<Ti> *__restrict__ in, cx<To> *__restrict__ out, size_t N)

@@ -6,7 +6,7 @@ fallback -- importing works without a GPU, but any call needs the built
 library and a gfx950 device, and fails loudly otherwise.
 
 Names follow the C entry points: ``mg_setup``, ``mg_rhs_plane_wave``,
-``mg_vcycle``, ``mg_solve``, ``farfield_map``, ``mg_apply``, ``mg_smooth``,
+``mg_vcycle``, ``mg_fmg``, ``mg_solve``, ``farfield_map``, ``mg_apply``, ``mg_smooth``,
 ``mg_residual_norm``, ``mg_destroy``.
 """
 from __future__ import annotations
@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("smoother_weights", ctypes.c_void_p),
                 ("ff_precision", ctypes.c_int), ("tile_config", ctypes.c_int), ("inner_cycles", ctypes.c_int),
-                ("nu_coarse", ctypes.c_int), ("learned_levels", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("nu_coarse", ctypes.c_int), ("learned_levels", ctypes.c_int), ("fmg_cycles", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -59,7 +60,7 @@ class FfmgError(RuntimeError):
 _lib = None
 
 EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup", "mg_rhs_plane_wave",
-           "mg_vcycle", "mg_solve", "farfield_map", "mg_apply", "mg_smooth", "mg_residual_norm",
+           "mg_vcycle", "mg_fmg", "mg_solve", "farfield_map", "mg_apply", "mg_smooth", "mg_residual_norm",
            "mg_num_levels", "mg_level_shape", "mg_destroy", "mg_profile_enable", "mg_profile_read",
            "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_tune_solve", "mg_solve_batched",
            "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights", "ml_loss_grad",
@@ -83,6 +84,7 @@ def lib():
     L.mg_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(vp)]
     L.mg_rhs_plane_wave.argtypes = [vp, vp, vp]
     L.mg_vcycle.argtypes = [vp, vp, vp]
+    L.mg_fmg.argtypes = [vp, vp, vp, ip]
     L.mg_solve.argtypes = [vp, vp, vp, dp, ctypes.POINTER(SolveInfo)]
     L.farfield_map.argtypes = [vp, vp, vp, ip, vp, vp]
     L.mg_apply.argtypes = [vp, vp, vp]
@@ -116,7 +118,7 @@ def lib():
     L.mg_jacobi_factor.argtypes = [vp]
     L.mg_jacobi_factor.restype = ctypes.c_double
     L.farfield_map_batched.argtypes = [vp, ip, vp, vp, ip, vp, vp]
-    for name in ("mg_setup", "mg_rhs_plane_wave", "mg_vcycle", "mg_solve", "farfield_map", "mg_apply",
+    for name in ("mg_setup", "mg_rhs_plane_wave", "mg_vcycle", "mg_fmg", "mg_solve", "farfield_map", "mg_apply",
                  "mg_smooth", "mg_residual_norm", "mg_level_shape", "mg_profile_enable", "mg_profile_read",
                  "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_tune_solve",
                  "mg_solve_batched", "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights",
@@ -239,6 +241,12 @@ def mg_rhs_plane_wave(h: Handle, eta, b):
 
 def mg_vcycle(h: Handle, b, u):
     h._check(lib().mg_vcycle(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u")), "mg_vcycle")
+    return u
+
+
+def mg_fmg(h: Handle, b, u, k):
+    """u <- the full multigrid start with k V-cycles per coarse level."""
+    h._check(lib().mg_fmg(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), int(k)), "mg_fmg")
     return u
 
 

@@ -1,0 +1,180 @@
+"""GPU parity of the full multigrid start (mg_fmg, and mg_solve with
+options.fmg_cycles) against the FP64 oracle's nested iteration (Sec. 4 with
+Tables 3 and 4; Sec. 5.7, the F(k) cycle).
+
+Bars: the FP64 start to 1e-12 (the same operations as the oracle's, in
+another summation order), in every kernel configuration; the FP32 start
+(hierarchy in FP32 on the right-hand side scaled to unit RMS) to 2e-5;
+solves from the start as the solves from u = 0 (same cycle count and 1e-12 in
+FP64, the FP64 tolerance and the mixed-precision far-field bar in FP32_IR).
+"""
+import numpy as np
+import pytest
+
+from paper_1211_4461_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_4461_amd import ffmg
+    ffmg.lib()
+    return ffmg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300)
+
+
+def nan_like(shape):
+    """An output buffer whose every input value is NaN: the start must not
+    read it."""
+    return torch.full(shape, complex(float("nan"), float("nan")), dtype=torch.complex128, device="cuda")
+
+
+CASES = [
+    ("2d-63", lambda: W.small_2d(n=64)),
+    ("2d-127-ragged", lambda: W.bumps_2d(n=128, seed=5, k0=1.3, M=40)),
+    ("2d-255", lambda: W.bumps_2d(n=256, seed=2, M=24)),
+    ("3d-15", lambda: W.radial_3d(16, L=4.0, n_az=6, n_pol=4)),
+    ("3d-31", lambda: W.radial_3d(32, L=6.0, n_az=8, n_pol=5)),
+]
+
+
+def problem(ff, orc, w, **opt):
+    h, _ = ff.setup_workload(w, options=ff.default_options(**opt))
+    g = orc.Grid(w.dim, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    return h, g, kappa, q, k0, b
+
+
+@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("name,mk", CASES)
+def test_fmg_start_matches_oracle(ff, orc, name, mk, k, tile):
+    w = mk()
+    h, g, kappa, q, k0, b = problem(ff, orc, w, tile_config=tile)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    assert h.num_levels() == mg.nlev
+    ud = nan_like(g.shape)
+    ff.mg_fmg(h, dev(b), ud, k)
+    uo = mg.fmg(b, k)
+    assert rel(host(ud), uo) < 1e-12
+    h.destroy()
+
+
+def test_fmg_one_level_is_the_exact_solve(ff, orc):
+    """n = coarsest_n: the hierarchy is the coarsest level alone and the start
+    is its exact solution."""
+    w = W.small_2d(n=8)
+    h, g, kappa, q, k0, b = problem(ff, orc, w)
+    assert h.num_levels() == 1
+    ud = nan_like(g.shape)
+    ff.mg_fmg(h, dev(b), ud, 3)
+    uo = orc.Multigrid(g, w.gamma, kappa).fmg(b, 3)
+    assert rel(host(ud), uo) < 1e-12
+    r = orc.residual(g, w.gamma, kappa, b, host(ud))
+    assert np.linalg.norm(r) < 1e-12 * np.linalg.norm(b)
+    h.destroy()
+
+
+@pytest.mark.parametrize("k", [1, 3])
+@pytest.mark.parametrize("name,mk", [CASES[1], CASES[2], CASES[4]])
+def test_fmg_start_fp32(ff, orc, name, mk, k):
+    """FP32_IR handles build the start in FP32 on b / RMS(b): the oracle's FP64
+    start to FP32 accuracy, for any scale of b."""
+    w = mk()
+    h, g, kappa, q, k0, b = problem(ff, orc, w, precision=ff.FP32_IR)
+    uo = orc.Multigrid(g, w.gamma, kappa).fmg(b, k)
+    for scale in (1.0, 1e-30, 1e30):
+        ud = nan_like(g.shape)
+        ff.mg_fmg(h, dev(scale * b), ud, k)
+        assert rel(host(ud) / scale, uo) < 2e-5, scale
+    h.destroy()
+
+
+@pytest.mark.parametrize("name,mk", CASES)
+def test_fmg_solve_matches_oracle(ff, orc, name, mk):
+    """FP64 solve with fmg_cycles = 2: the oracle's solve from its own start
+    takes as many cycles and gives the same iterate; the start ignores what u
+    held."""
+    w = mk()
+    h, g, kappa, q, k0, b = problem(ff, orc, w, fmg_cycles=2)
+    mg = orc.Multigrid(g, w.gamma, kappa)
+    uo, st, k, _ = mg.solve(b, u0=mg.fmg(b, 2), tol=1e-10)
+    _, _, k_zero, _ = mg.solve(b, tol=1e-10)
+    assert st == 0
+    ud = nan_like(g.shape)
+    info = ff.mg_solve(h, dev(b), ud, tol=1e-10)
+    assert info.status == 0 and info.cycles == k and info.rel_residual <= 1e-10
+    assert k <= k_zero
+    assert rel(host(ud), uo) < 1e-12
+    Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
+    assert rel(ff.farfield_map(h, w.eta, ud, w.dirs), Fo) < 1e-10
+    h.destroy()
+
+
+@pytest.mark.parametrize("name,mk", [CASES[1], CASES[2], CASES[4]])
+def test_fmg_mixed_precision_solve(ff, orc, name, mk):
+    """FP32_IR with fmg_cycles = 2 reaches the FP64 tolerance in no more
+    refinement steps than from u = 0; far field to the mixed bar."""
+    w = mk()
+    h0, g, kappa, q, k0, b = problem(ff, orc, w, precision=ff.FP32_IR)
+    h, *_ = problem(ff, orc, w, precision=ff.FP32_IR, fmg_cycles=2)
+    bd = dev(b)
+    u0 = torch.zeros(g.shape, dtype=torch.complex128, device="cuda")
+    i0 = ff.mg_solve(h0, bd, u0, tol=1e-10)
+    ud = nan_like(g.shape)
+    info = ff.mg_solve(h, bd, ud, tol=1e-10)
+    assert info.status == 0 and info.rel_residual <= 1e-10
+    assert info.cycles <= i0.cycles, (info.cycles, i0.cycles)
+    uo, st, _, _ = orc.Multigrid(g, w.gamma, kappa).solve(b, tol=1e-13)
+    assert rel(host(ud), uo) < 1e-8
+    Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
+    assert rel(ff.farfield_map(h, w.eta, ud, w.dirs), Fo) < 1e-8
+    h.destroy()
+    h0.destroy()
+
+
+def test_fmg_edge_cases(ff, orc):
+    """b = 0 gives u = 0 in both precisions; k outside [0, 64], fmg_cycles
+    outside [0, 64] and FMG handles in a batched solve are refused; k = 0 is
+    the interpolated hierarchy without cycles (as the oracle's)."""
+    w = W.small_2d(n=64)
+    for prec in (0, 1):
+        h, g, kappa, q, k0, b = problem(ff, orc, w, precision=prec)
+        ud = nan_like(g.shape)
+        ff.mg_fmg(h, torch.zeros(g.shape, dtype=torch.complex128, device="cuda"), ud, 2)
+        assert torch.count_nonzero(ud).item() == 0
+        for bad in (-1, 65):
+            with pytest.raises(ff.FfmgError) as e:
+                ff.mg_fmg(h, dev(b), ud, bad)
+            assert e.value.status == ff.FFMG_EINVAL
+        ff.mg_fmg(h, dev(b), ud, 0)
+        tol = 1e-12 if prec == 0 else 2e-5
+        assert rel(host(ud), orc.Multigrid(g, w.gamma, kappa).fmg(b, 0)) < tol
+        h.destroy()
+    with pytest.raises(ff.FfmgError) as e:
+        ff.setup_workload(w, options=ff.default_options(fmg_cycles=65))
+    assert e.value.status == ff.FFMG_EINVAL
+    h, _ = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, fmg_cycles=1))
+    u = torch.empty((63, 63), dtype=torch.complex128, device="cuda")
+    with pytest.raises(ff.FfmgError) as e:
+        ff.mg_solve_batched([h], [w.eta], [u])
+    assert e.value.status == ff.FFMG_EINVAL
+    h.destroy()
