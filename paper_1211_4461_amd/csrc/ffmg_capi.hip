@@ -635,6 +635,8 @@ template void vcycle<float>(ffmg_handle *, int, const cf *, cf *, bool, const in
 // interpolated coarser solution and improved by k V-cycles; u = P u_1.  A
 // V-cycle on level l uses only the buffers of levels >= l + 1 besides its
 // own temporaries, so the hierarchy's coarse buffers hold the start too.
+// With the LDS tail (2D fused kernels) the levels it covers (from level 1 at
+// the finest) run their whole part of the nested iteration in one launch.
 // T = float works on b / s, s = sqrt(*bnorm2 / N) (unit RMS).
 template <typename T>
 void fmg_start(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2)
@@ -646,10 +648,24 @@ void fmg_start(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2)
         launch_coarse_apply<double>(h->aug, h->nc, b, u, h->stream, nullptr);
         return;
     }
+    const TailParams<T> &tp = LP::tail(h);
+    const bool tail = (l0.g.dim == 2 && h->opt.tile_config == TILE_FUSED && tp.nt >= 2);
+    const int t0 = tail ? last + 1 - tp.nt : last + 1;   // first tail level
+    const int s0 = (t0 == 0) ? 1 : 0;                      // its first level the start runs on
+    const int top = tail ? t0 + s0 : last;                 // right-hand sides injected down to here
+    const bool tail_fmg = tail && top < last;
     launch_inject_rhs<T>(l0.g, b, LP::b(h->L[1]), bnorm2, h->stream);
-    for (int l = 1; l < last; ++l) launch_inject<T>(h->L[l].g, LP::b(h->L[l]), LP::b(h->L[l + 1]), h->stream);
-    launch_coarse_apply<T>(h->aug, h->nc, LP::b(h->L[last]), LP::u(h->L[last]), h->stream, nullptr);
-    for (int l = last - 1; l >= 1; --l) {
+    for (int l = 1; l < top; ++l) launch_inject<T>(h->L[l].g, LP::b(h->L[l]), LP::b(h->L[l + 1]), h->stream);
+    int from;
+    if (tail_fmg) {
+        launch_tail2d_fmg<T>(tp, LP::tail_lds(h), LP::b(h->L[top]), LP::u(h->L[top]), s0, k, h->stream);
+        from = top - 1;
+    } else {
+        for (int l = top; l < last; ++l) launch_inject<T>(h->L[l].g, LP::b(h->L[l]), LP::b(h->L[l + 1]), h->stream);
+        launch_coarse_apply<T>(h->aug, h->nc, LP::b(h->L[last]), LP::u(h->L[last]), h->stream, nullptr);
+        from = last - 1;
+    }
+    for (int l = from; l >= 1; --l) {
         Level &lv = h->L[l];
         launch_prolong_set<T, T>(lv.g, LP::u(h->L[l + 1]), LP::u(lv), nullptr, 1.0, h->stream);
         for (int c = 0; c < k; ++c) vcycle<T>(h, l, LP::b(lv), LP::u(lv), false, nullptr);

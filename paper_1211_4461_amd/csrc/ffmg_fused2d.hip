@@ -456,39 +456,80 @@ __device__ void tail_smooth(const TailView<T> &v, const TailLevel<T> &L, int nu,
     }
 }
 
+// Zero every array (borders included), then b of tail level s0 from b_top
+// and q of all levels.
 template <typename T>
-__device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T> *__restrict__ b_top,
-                                            cx<T> *__restrict__ u_top, cx<T> *lds)
+__device__ __forceinline__ void tail_load(const TailParams<T> &tp, const cx<T> *__restrict__ b_top, cx<T> *lds,
+                                          int s0)
 {
     const int nt = tp.nt;
-    {
-        // zero every array (borders included), then b of level 0 and q of all
-        const TailLevel<T> &last = tp.lv[nt - 1];
-        const int total = last.off + 4 * (last.mx + 2) * (last.my + 2);
-        for (int j = threadIdx.x; j < total; j += blockDim.x) lds[j] = cx<T>{T(0), T(0)};
-        __syncthreads();
-        TailView<T> v0 = tail_view(lds, tp.lv[0]);
-        for (int j = threadIdx.x; j < v0.N; j += blockDim.x) {
-            int x, y;
-            v0.xy(j, x, y);
-            v0.b[v0.at(x, y)] = b_top[j];
-        }
-        for (int i = 0; i < nt; ++i) {
-            TailView<T> v = tail_view(lds, tp.lv[i]);
-            const cx<T> *qs = tp.lv[i].q;
-            for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
-                int x, y;
-                v.xy(j, x, y);
-                v.q[v.at(x, y)] = qs[j];
-            }
-        }
-        __syncthreads();
+    const TailLevel<T> &last = tp.lv[nt - 1];
+    const int total = last.off + 4 * (last.mx + 2) * (last.my + 2);
+    for (int j = threadIdx.x; j < total; j += blockDim.x) lds[j] = cx<T>{T(0), T(0)};
+    __syncthreads();
+    TailView<T> v0 = tail_view(lds, tp.lv[s0]);
+    for (int j = threadIdx.x; j < v0.N; j += blockDim.x) {
+        int x, y;
+        v0.xy(j, x, y);
+        v0.b[v0.at(x, y)] = b_top[j];
     }
-    // down: smoothing from zero, residual, restriction
-    for (int i = 0; i + 1 < nt; ++i) {
+    for (int i = 0; i < nt; ++i) {
+        TailView<T> v = tail_view(lds, tp.lv[i]);
+        const cx<T> *qs = tp.lv[i].q;
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
+            int x, y;
+            v.xy(j, x, y);
+            v.q[v.at(x, y)] = qs[j];
+        }
+    }
+    __syncthreads();
+}
+
+// Coarsest tail level: u = A^{-1} b in FP64, one wave per row, lane-strided
+// sums then a shuffle tree (the order of the one-operation kernel).
+template <typename T>
+__device__ __forceinline__ void tail_coarsest(const TailParams<T> &tp, cx<T> *lds)
+{
+    TailView<T> c = tail_view(lds, tp.lv[tp.nt - 1]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int n = tp.nc;
+    for (int row = wave; row < n; row += nw) {
+        const cd *ar = tp.aug + (size_t)row * 2 * n + n;
+        double re = 0.0, im = 0.0;
+        for (int k = lane; k < n; k += 64) {
+            cd a = ar[k];
+            int x, y;
+            c.xy(k, x, y);
+            cx<T> bk = c.b[c.at(x, y)];
+            double br = (double)bk.re, bi = (double)bk.im;
+            re += a.re * br - a.im * bi;
+            im += a.re * bi + a.im * br;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            re += __shfl_down(re, off, 64);
+            im += __shfl_down(im, off, 64);
+        }
+        if (lane == 0) {
+            int x, y;
+            c.xy(row, x, y);
+            c.u[c.at(x, y)] = cx<T>{T(re), T(im)};
+        }
+    }
+    __syncthreads();
+}
+
+// One V-cycle from tail level i0 (its b and u in LDS; zero_top: its u is
+// taken as 0): pre-smoothing, residual and restriction down to the coarsest
+// level (every coarser level from a zero guess), exact solve, then
+// interpolation of the correction and post-smoothing back up to i0.
+template <typename T>
+__device__ __forceinline__ void tail_vcycle(const TailParams<T> &tp, cx<T> *lds, int i0, bool zero_top)
+{
+    const int nt = tp.nt;
+    for (int i = i0; i + 1 < nt; ++i) {
         const TailLevel<T> &L = tp.lv[i];
         TailView<T> v = tail_view(lds, L);
-        tail_smooth<T>(v, L, tp.nu1, true);
+        tail_smooth<T>(v, L, tp.nu1, zero_top || i > i0);
         for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
             int x, y;
             v.xy(j, x, y);
@@ -512,38 +553,8 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
         }
         __syncthreads();
     }
-    // coarsest: u = A^{-1} b in FP64, one wave per row, lane-strided sums then
-    // a shuffle tree (the order of the one-operation kernel)
-    {
-        TailView<T> c = tail_view(lds, tp.lv[nt - 1]);
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-        const int n = tp.nc;
-        for (int row = wave; row < n; row += nw) {
-            const cd *ar = tp.aug + (size_t)row * 2 * n + n;
-            double re = 0.0, im = 0.0;
-            for (int k = lane; k < n; k += 64) {
-                cd a = ar[k];
-                int x, y;
-                c.xy(k, x, y);
-                cx<T> bk = c.b[c.at(x, y)];
-                double br = (double)bk.re, bi = (double)bk.im;
-                re += a.re * br - a.im * bi;
-                im += a.re * bi + a.im * br;
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                re += __shfl_down(re, off, 64);
-                im += __shfl_down(im, off, 64);
-            }
-            if (lane == 0) {
-                int x, y;
-                c.xy(row, x, y);
-                c.u[c.at(x, y)] = cx<T>{T(re), T(im)};
-            }
-        }
-        __syncthreads();
-    }
-    // up: interpolation of the correction, smoothing
-    for (int i = nt - 2; i >= 0; --i) {
+    tail_coarsest<T>(tp, lds);
+    for (int i = nt - 2; i >= i0; --i) {
         const TailLevel<T> &L = tp.lv[i];
         TailView<T> v = tail_view(lds, L);
         TailView<T> c = tail_view(lds, tp.lv[i + 1]);
@@ -557,12 +568,64 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
         __syncthreads();
         tail_smooth<T>(v, L, tp.nu2, false);
     }
-    TailView<T> v0 = tail_view(lds, tp.lv[0]);
+}
+
+template <typename T>
+__device__ __forceinline__ void tail_store(const TailParams<T> &tp, cx<T> *lds, int s0, cx<T> *__restrict__ u_top)
+{
+    TailView<T> v0 = tail_view(lds, tp.lv[s0]);
     for (int j = threadIdx.x; j < v0.N; j += blockDim.x) {
         int x, y;
         v0.xy(j, x, y);
         u_top[j] = v0.u[v0.at(x, y)];
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T> *__restrict__ b_top,
+                                            cx<T> *__restrict__ u_top, cx<T> *lds)
+{
+    tail_load<T>(tp, b_top, lds, 0);
+    tail_vcycle<T>(tp, lds, 0, true);
+    tail_store<T>(tp, lds, 0, u_top);
+}
+
+// Full multigrid start on the tail levels s0 .. nt - 1 in one workgroup: b of
+// level s0 from b_top, injected level by level down to the coarsest, exact
+// solve there, then on each level up to s0 the interpolated coarser solution
+// as the guess and k V-cycles; u_top receives level s0's solution.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail2d_fmg(TailParams<T> tp, const cx<T> *__restrict__ b_top,
+                                                     cx<T> *__restrict__ u_top, int s0, int k)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds_f[];
+    cx<T> *lds = reinterpret_cast<cx<T> *>(tail_lds_f);
+    const int nt = tp.nt;
+    tail_load<T>(tp, b_top, lds, s0);
+    for (int i = s0; i + 1 < nt; ++i) {
+        TailView<T> v = tail_view(lds, tp.lv[i]);
+        TailView<T> c = tail_view(lds, tp.lv[i + 1]);
+        for (int J = threadIdx.x; J < c.N; J += blockDim.x) {
+            int I, K;
+            c.xy(J, I, K);
+            c.b[c.at(I, K)] = v.b[v.at(2 * I + 1, 2 * K + 1)];
+        }
+        __syncthreads();
+    }
+    tail_coarsest<T>(tp, lds);
+    for (int i = nt - 2; i >= s0; --i) {
+        TailView<T> v = tail_view(lds, tp.lv[i]);
+        TailView<T> c = tail_view(lds, tp.lv[i + 1]);
+        const cx<T> *cu = c.u + c.W + 1;
+        for (int j = threadIdx.x; j < v.N; j += blockDim.x) {
+            int x, y;
+            v.xy(j, x, y);
+            v.u[v.at(x, y)] = interp2d<T>(cu, c.W, 0, 0, c.mx, c.my, x, y);
+        }
+        __syncthreads();
+        for (int c2 = 0; c2 < k; ++c2) tail_vcycle<T>(tp, lds, i, false);
+    }
+    tail_store<T>(tp, lds, s0, u_top);
 }
 
 template <typename T>
@@ -674,6 +737,20 @@ void launch_tail2d(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top
     }
     hipLaunchKernelGGL((k_tail2d<T>), dim3(1), dim3(1024), lds_bytes, s, tp, b_top, u_top, stop);
 }
+template <typename T>
+void launch_tail2d_fmg(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top, cx<T> *u_top, int s0, int k,
+                       hipStream_t s)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)k_tail2d_fmg<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_tail2d_fmg<T>), dim3(1), dim3(1024), lds_bytes, s, tp, b_top, u_top, s0, k);
+}
+template void launch_tail2d_fmg<double>(const TailParams<double> &, size_t, const cd *, cd *, int, int, hipStream_t);
+template void launch_tail2d_fmg<float>(const TailParams<float> &, size_t, const cf *, cf *, int, int, hipStream_t);
 template void launch_tail2d<double>(const TailParams<double> &, size_t, const cd *, cd *, hipStream_t, const int *);
 template void launch_tail2d<float>(const TailParams<float> &, size_t, const cf *, cf *, hipStream_t, const int *);
 

@@ -172,6 +172,11 @@ size_t tail2d_lds_bytes(const int *mx, const int *my, int nt);
 template <typename T>
 void launch_tail2d(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top, cx<T> *u_top, hipStream_t s,
                    const int *stop);
+// Full multigrid start on tail levels s0 .. nt - 1 (b_top: level s0's
+// right-hand side; u_top: its solution after k V-cycles there).
+template <typename T>
+void launch_tail2d_fmg(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top, cx<T> *u_top, int s0, int k,
+                       hipStream_t s);
 
 // Batched fused 2D kernels (one launch for many instances).  Each job is one
 // instance's level; a launch's tiles are the jobs' tiles back to back

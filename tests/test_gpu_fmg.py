@@ -178,3 +178,28 @@ def test_fmg_edge_cases(ff, orc):
         ff.mg_solve_batched([h], [w.eta], [u])
     assert e.value.status == ff.FFMG_EINVAL
     h.destroy()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n", [256, 1024])
+def test_fmg_tail_is_bitwise_the_per_level_start(ff, orc, n, prec):
+    """The one-workgroup tail runs the tail levels' part of the nested
+    iteration with the per-point arithmetic of the grid-wide kernels: every
+    tail size and the start without the tail (one launch per operation on
+    those levels) agree bit for bit."""
+    w = W.bumps_2d(n=n, seed=n + 3, k0=1.1, M=8)
+    h, g, kappa, q, k0, b = problem(ff, orc, w, precision=prec)
+    h2, *_ = problem(ff, orc, w, precision=prec, tile_config=2)
+    bd = dev(b)
+    ref = nan_like(g.shape)
+    ff.mg_fmg(h2, bd, ref, 2)
+    for v in range(ff.mg_tune_variants(h, ff.TUNE_TAIL)):
+        ff.mg_tune_set(h, v, ff.TUNE_TAIL)
+        ud = nan_like(g.shape)
+        ff.mg_fmg(h, bd, ud, 2)
+        torch.cuda.synchronize()
+        assert torch.equal(ud, ref), v
+    uo = orc.Multigrid(g, w.gamma, kappa).fmg(b, 2)
+    assert rel(host(ref), uo) < (1e-12 if prec == 0 else 2e-5)
+    h.destroy()
+    h2.destroy()
