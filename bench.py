@@ -73,19 +73,32 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
     opts = ff.default_options(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles)
     h, coef = ff.setup_workload(w, options=opts)
     from paper_1211_4461_amd import autotune
-    tune = {"ff_gemm": None, "smooth": None, "tail": None}
+    tune = {"ff_gemm": None, "smooth": None, "smooth_coarse": None, "pre": None, "tail": None}
     if ff.mg_tune_variants(h, ff.TUNE_FF_GEMM) > 1:   # tile shape of the split GEMM, off the timed path
         v = autotune.tune_farfield(h, w.eta, None, w.dirs, ff_precision)
         tune["ff_gemm"] = {"variant": v, "cache": autotune.load().get(autotune.key(
             autotune.device_arch(), ff.TUNE_FF_GEMM, w.dim, [w.n - 1] * w.dim, len(w.dirs), ff_precision))}
     b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
     u = torch.empty_like(b)
-    if ff.mg_tune_variants(h, ff.TUNE_SMOOTH) > 1:    # tile height of the fused smoothing kernel
+    if ff.mg_tune_variants(h, ff.TUNE_SMOOTH_COARSE) > 1:   # tile height of the smoothing kernel, coarse levels
+        ff.mg_rhs_plane_wave(h, w.eta, b)
+        v = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=ff.TUNE_SMOOTH_COARSE)
+        tune["smooth_coarse"] = {"variant": v, "tile_rows": (8, 16, 4)[v],
+                                 "cache": autotune.load().get(autotune.key(
+                                     autotune.device_arch(), ff.TUNE_SMOOTH_COARSE, w.dim, [w.n - 1] * w.dim, 0,
+                                     precision))}
+    if ff.mg_tune_variants(h, ff.TUNE_SMOOTH) > 1:    # tile height of the fused smoothing kernel, finest level
         ff.mg_rhs_plane_wave(h, w.eta, b)
         v = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=ff.TUNE_SMOOTH)
         tune["smooth"] = {"variant": v, "tile_rows": (8, 16, 4)[v],
                           "cache": autotune.load().get(autotune.key(
                               autotune.device_arch(), ff.TUNE_SMOOTH, w.dim, [w.n - 1] * w.dim, 0, precision))}
+    if ff.mg_tune_variants(h, ff.TUNE_PRE) > 1:       # pre-smoothing + residual + restriction in one pass or two
+        ff.mg_rhs_plane_wave(h, w.eta, b)
+        v = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=ff.TUNE_PRE)
+        tune["pre"] = {"variant": v, "form": ("one pass", "two launches")[v],
+                       "cache": autotune.load().get(autotune.key(
+                           autotune.device_arch(), ff.TUNE_PRE, w.dim, [w.n - 1] * w.dim, 0, precision))}
     if ff.mg_tune_variants(h, ff.TUNE_TAIL) > 1:      # size of the one-workgroup LDS tail, off the timed path
         ff.mg_rhs_plane_wave(h, w.eta, b)
         v = autotune.tune_solve(h, b, u, precision, tol=w.tol)
@@ -431,12 +444,13 @@ def main():
         del x, y
 
     # Algorithmic bytes per point of the timed kernels (FP32 complex 8 B, FP64 16 B):
-    #   pre    2 fused sweeps from a zero guess (FP32 inner cycle): read b, q; write u      = 24
-    #          (FP64 cycle, nonzero guess: read u, b, q; write u                          = 64)
+    #   pre    2 sweeps + residual + full weighting in one pass, from a zero guess (FP32
+    #          inner cycle): read b, q; write u, b_c (N/4)                                 = 26
+    #          (nonzero guess: also read u: 34 FP32, 68 FP64)
     #   post   interpolation + 2 fused sweeps: read u, b, q, e_c (N/4); write u          = 34 / 68
     #   refine FP64 update + residual: read u, b, q (16 each), d (8); write u (16), r (8) = 80
-    # "pre" brackets two kernel symbols (the first sweep pair from zero, 24 B,
-    # and the pair from a nonzero guess, 32 B) and is reported, not ranked.
+    # "pre" brackets two kernel symbols (the pass from zero, 26 B, and the
+    # pass from a nonzero guess, 34 B) and is reported, not ranked.
     bpp_mixed = {"post": 34.0, "refine": 80.0}
     bpp_plain = {"post": 68.0}
     ffp = {"bf16x6": ffmg.FF_BF16X6, "bf16x3": ffmg.FF_BF16X3, "fp64": ffmg.FF_FP64}[args.ff_precision]
@@ -446,7 +460,8 @@ def main():
     mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed, fmg_cycles=fk)
     plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2),
                                                  args.warmup, bpp_plain, fmg_cycles=fk)
-    names = {"pre": "finest-level pre-smoothing: 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,*,false,1,TH>)",
+    names = {"pre": "finest-level pre-smoothing: 2 FP32 Jacobi sweeps, residual and full weighting in one pass "
+                    "(k_smooth_rr2d<float,*,1,16>)",
              "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1,TH>, "
                      "TH = the tuned tile height)",
              "refine": "FP64 update + residual of the refinement loop (k_refine2d)"}
@@ -486,7 +501,9 @@ def main():
                   "conv_factor": round(mixed["conv_factor"], 4),
                   "ff_ms_per_map": round(pr["ff"][0] / max(pr["ff"][1], 1), 3),
                   "farfield_gemm": gemm_report(pr, w, args.ff_precision, mixed["tune"]["ff_gemm"]),
-                  "smooth_tile": mixed["tune"]["smooth"], "lds_tail": mixed["tune"]["tail"]},
+                  "smooth_tile": mixed["tune"]["smooth"], "smooth_tile_coarse": mixed["tune"]["smooth_coarse"],
+                  "pre_pass": mixed["tune"]["pre"],
+                  "lds_tail": mixed["tune"]["tail"]},
         "roofline": roof,
     }
     if plain is not None:
@@ -497,6 +514,8 @@ def main():
         line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
                               "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
                               "finest_kernels_GBs": p_gbs, "smooth_tile": plain["tune"]["smooth"],
+                              "smooth_tile_coarse": plain["tune"]["smooth_coarse"],
+                              "pre_pass": plain["tune"]["pre"],
                               "lds_tail": plain["tune"]["tail"],
                               "ff_ms_per_map": round(pp["ff"][0] / max(pp["ff"][1], 1), 3),
                               "farfield_gemm": gemm_report(pp, w, "fp64")}

@@ -285,8 +285,13 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
  * fused 2D cycle; the levels above it run as grid-wide launches.  It has one
  * variant for handles without the LDS tail (3D, tile_config != 0) and for the
  * learned smoother.  FFMG_TUNE_SMOOTH: the tile height of the fused 2D
- * smoothing kernel (8, 16 or 4 rows of 64 points for variants 0, 1, 2; the
- * batched path keeps 8); one variant for 3D and tile_config 1.
+ * smoothing kernel on the finest level (8, 16 or 4 rows of 64 points for
+ * variants 0, 1, 2; the batched path keeps 8); FFMG_TUNE_SMOOTH_COARSE: the
+ * same on the coarser levels; one variant each for 3D and tile_config 1.
+ * FFMG_TUNE_PRE: the pre-smoothing of a fused 2D level with nu1 = 2 as one
+ * pass of two sweeps, residual and full weighting (variant 0) or as the
+ * two-sweep launch followed by the residual + restriction launch (1); one
+ * variant for 3D and tile_config 1.
  * mg_tune_variants returns the number of variants (0 for an unknown
  * tunable); mg_tune_get / mg_tune_set read and select one (a cached choice).
  * mg_tune_farfield builds the integrand of (eta, u) for the n_dirs
@@ -295,10 +300,17 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
  * *best and the mean time of variant v in times_ms[v] (v < n_times; times_ms
  * may be NULL).  Synchronises.
  * mg_tune_solve times `reps` solves of b from u = 0 to tol per variant of
- * `tunable` (FFMG_TUNE_TAIL or FFMG_TUNE_SMOOTH; after one untimed solve),
+ * `tunable` (FFMG_TUNE_TAIL, FFMG_TUNE_SMOOTH, FFMG_TUNE_PRE or
+ * FFMG_TUNE_SMOOTH_COARSE; after one untimed solve),
  * selects the fastest and reports like mg_tune_farfield; u is the caller's
  * workspace and holds the last solution on return.  Synchronises. */
-typedef enum { FFMG_TUNE_FF_GEMM = 0, FFMG_TUNE_TAIL = 1, FFMG_TUNE_SMOOTH = 2 } ffmg_tunable;
+typedef enum {
+    FFMG_TUNE_FF_GEMM = 0,
+    FFMG_TUNE_TAIL = 1,
+    FFMG_TUNE_SMOOTH = 2,
+    FFMG_TUNE_PRE = 3,
+    FFMG_TUNE_SMOOTH_COARSE = 4
+} ffmg_tunable;
 int mg_tune_variants(const ffmg_handle *h, int tunable);
 ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant);
 ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant);

@@ -224,7 +224,7 @@ void smooth_chain2d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
         cx<T> *o = alias ? ((kk % 2 == 0) ? tmp : dst) : (((nk - 1 - kk) % 2 == 0) ? dst : tmp);
         int pi = finest ? prof_begin(h, prof_id) : -1;
         launch_smooth2d<T>(lv.g, LP::P(lv), ns, zero, cur, ec, b, LP::q(lv), o, h->stream, finest && ns == 2, stop,
-                           SMOOTH_TH[h->smooth_variant]);
+                           SMOOTH_TH[finest ? h->smooth_variant : h->smooth_coarse_variant]);
         prof_end(h, prof_id, pi);
         cur = o;
         zero = false;
@@ -246,13 +246,22 @@ void vcycle_fused2d(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_g
     cx<T> *t = LP::t(lv), *scratch = LP::r(lv);
     cx<T> *cur = u;
     const int nu1 = nu_pre(h, l), nu2 = nu_post(h, l);
-    if (nu1 > 0) {
-        smooth_chain2d<T>(h, lv, b, u, t, scratch, nu1, zero_guess, nullptr, PROF_PRE, stop);
+    if (nu1 == 2 && h->pre_variant == 0) {
+        // two sweeps, residual and full weighting in one pass
+        const bool finest = (l == 0);
+        int pi = finest ? prof_begin(h, PROF_PRE) : -1;
+        launch_smooth_rr2d<T>(lv.g, LP::P(lv), zero_guess, u, b, LP::q(lv), t, LP::b(lc), h->stream, finest, stop);
+        prof_end(h, PROF_PRE, pi);
         cur = t;
-    } else if (zero_guess) {
-        launch_zero<T>(u, lv.g.N(), h->stream, stop);
+    } else {
+        if (nu1 > 0) {
+            smooth_chain2d<T>(h, lv, b, u, t, scratch, nu1, zero_guess, nullptr, PROF_PRE, stop);
+            cur = t;
+        } else if (zero_guess) {
+            launch_zero<T>(u, lv.g.N(), h->stream, stop);
+        }
+        launch_resid_restrict2d<T>(lv.g, LP::P(lv), cur, b, LP::q(lv), LP::b(lc), h->stream, stop);
     }
-    launch_resid_restrict2d<T>(lv.g, LP::P(lv), cur, b, LP::q(lv), LP::b(lc), h->stream, stop);
     const TailParams<T> &tp = LP::tail(h);
     if (h->opt.tile_config == TILE_FUSED && tp.nt > 0 && l + 1 == (int)h->L.size() - tp.nt)
         launch_tail2d<T>(tp, LP::tail_lds(h), LP::b(lc), LP::u(lc), h->stream, stop);
@@ -1123,6 +1132,9 @@ int mg_tune_variants(const ffmg_handle *h, int tunable)
                    : 1;
     case FFMG_TUNE_SMOOTH:
         return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
+    case FFMG_TUNE_PRE: return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? 2 : 1;
+    case FFMG_TUNE_SMOOTH_COARSE:
+        return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
     default: return 0;
     }
 }
@@ -1138,6 +1150,8 @@ ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant)
         return FFMG_OK;
     case FFMG_TUNE_TAIL: *variant = h->tail_variant; return FFMG_OK;
     case FFMG_TUNE_SMOOTH: *variant = h->smooth_variant; return FFMG_OK;
+    case FFMG_TUNE_PRE: *variant = h->pre_variant; return FFMG_OK;
+    case FFMG_TUNE_SMOOTH_COARSE: *variant = h->smooth_coarse_variant; return FFMG_OK;
     default: return FFMG_EINVAL;
     }
 }
@@ -1155,6 +1169,8 @@ ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant)
         return FFMG_OK;
     case FFMG_TUNE_TAIL: set_tail_variant(h, variant); return FFMG_OK;
     case FFMG_TUNE_SMOOTH: h->smooth_variant = variant; return FFMG_OK;
+    case FFMG_TUNE_PRE: h->pre_variant = variant; return FFMG_OK;
+    case FFMG_TUNE_SMOOTH_COARSE: h->smooth_coarse_variant = variant; return FFMG_OK;
     default: return fail(h, FFMG_EINVAL, "unknown tunable %d", tunable);
     }
 }
@@ -1212,8 +1228,9 @@ ffmg_status mg_tune_solve(ffmg_handle *h, int tunable, const void *b, void *u, d
                           int n_times, int *best)
 {
     if (!h || !b || !u || reps < 1) return fail(h, FFMG_EINVAL, "null argument or reps < 1");
-    if (tunable != FFMG_TUNE_TAIL && tunable != FFMG_TUNE_SMOOTH)
-        return fail(h, FFMG_EINVAL, "mg_tune_solve tunes FFMG_TUNE_TAIL or FFMG_TUNE_SMOOTH (got %d)", tunable);
+    if (tunable != FFMG_TUNE_TAIL && tunable != FFMG_TUNE_SMOOTH && tunable != FFMG_TUNE_PRE &&
+        tunable != FFMG_TUNE_SMOOTH_COARSE)
+        return fail(h, FFMG_EINVAL, "mg_tune_solve tunes the solve's tunables (got %d)", tunable);
     const int nv = mg_tune_variants(h, tunable);
     const size_t bytes = h->L[0].g.N() * sizeof(cd);
     int arg = 0;

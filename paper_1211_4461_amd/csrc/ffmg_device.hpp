@@ -56,6 +56,7 @@ struct Stencil {
     cx<T> csum2;        // 2 sum_k c_k
     T k02;              // k0^2
     T omega;            // Jacobi damping
+    T omc;              // 1 - omega
 };
 
 // p[j] where `in` holds, 0 elsewhere.  The load always goes to a valid

@@ -65,11 +65,14 @@ constexpr int SMOOTH_TH_BATCH = 8;
 
 // k_smooth2d runs in four phases separated by barriers:
 //   1. every global load of the block is issued together (fully unrolled
-//      loops into LDS): the u tile with its NS-deep halo, b and q on the
-//      region the sweeps touch, and the coarse-correction tile (PROL);
+//      loops): the u tile with its NS-deep halo and the coarse-correction tile
+//      (PROL) into LDS, b and q of the thread's own points into registers;
 //   2. (PROL) u += P e_c in LDS;
 //   3. (NS = 2) sweep 1 on the tile plus a one-point halo;
 //   4. the last sweep on the tile, written to out.
+// Each thread keeps the same points of the sweep-1 region (the tile plus an
+// (NS-1) halo) in phases 3 and 4, so b and omega / D of its points stay in
+// registers; only u values that neighbours read pass through LDS.
 template <typename T, int NS, bool ZERO, bool PROL, int TH>
 __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                               const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
@@ -78,17 +81,14 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
     static_assert(TH % 4 == 0 && TH >= 4, "tile height: a multiple of the 4 rows of a 256-thread block");
     constexpr int H = NS;                                  // halo depth of the staged u
     constexpr int UW = FTX + 2 * H, UH = TH + 2 * H;
-    constexpr int BO = NS - 1;                             // b, q region: tile + (NS-1) halo
+    constexpr int BO = NS - 1;                             // sweep-1 region: tile + (NS-1) halo
     constexpr int BW = FTX + 2 * BO, BH = TH + 2 * BO;
-    constexpr int S1W = BW, S1H = BH;                      // sweep-1 values
     constexpr int ECW = FTX / 2 + 4, ECH = TH / 2 + 4;     // coarse tile covering the u region
-    constexpr int U1H = NS == 2 ? S1H : 1, U1W = NS == 2 ? S1W : 1;
+    constexpr int U1H = NS == 2 ? BH : 1, U1W = NS == 2 ? BW : 1;
     constexpr int ECH_ = PROL ? ECH : 1, ECW_ = PROL ? ECW : 1;
     __shared__ cx<T> U0[ZERO ? 1 : UH][ZERO ? 1 : UW];
-    __shared__ cx<T> Bs[BH][BW];
-    __shared__ cx<T> Qs[BH][BW];
     // the coarse tile is dead once phase 2 has ended (barrier), before sweep 1
-    // writes U1: the two share storage, so that four blocks fit in a CU's LDS
+    // writes U1: the two share storage
     __shared__ cx<T> U1EC[U1H * U1W > ECH_ * ECW_ ? U1H * U1W : ECH_ * ECW_];
     cx<T>(&U1)[U1H][U1W] = *reinterpret_cast<cx<T>(*)[U1H][U1W]>(&U1EC[0]);
     cx<T>(&EC)[ECH_][ECW_] = *reinterpret_cast<cx<T>(*)[ECH_][ECW_]>(&U1EC[0]);
@@ -99,11 +99,13 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
     const cx<T> zero = {T(0), T(0)};
 
     // phase 1: loads, issued into registers first so that all of them are in
-    // flight together, then stored to LDS
+    // flight together, then the shared ones stored to LDS
     constexpr int NU = ZERO ? 1 : (UH * UW + 255) / 256;
-    constexpr int NB = (BH * BW + 255) / 256;
+    constexpr int NP = (BH * BW + 255) / 256;             // the thread's points: slot k is point tid + 256 k
     constexpr int NE = PROL ? (ECH * ECW + 255) / 256 : 1;
-    cx<T> ru[NU], rb[NB], rq[NB], re[NE];
+    cx<T> ru[NU], rb[NP], rw[NP], re[NE];
+    int px[NP], py[NP];
+    bool act[NP], ing[NP];
     if (!ZERO) {
 #pragma unroll
         for (int k = 0; k < NU; ++k) {
@@ -115,14 +117,16 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
         }
     }
 #pragma unroll
-    for (int k = 0; k < NB; ++k) {
+    for (int k = 0; k < NP; ++k) {
         int i = threadIdx.x + 256 * k;
-        int ly = i / BW, lx = i - ly * BW;
-        int gx = x0 + lx - BO, gy = y0 + ly - BO;
-        bool in = i < BH * BW && gx >= 0 && gx < mx && gy >= 0 && gy < my;
+        py[k] = i / BW;
+        px[k] = i - py[k] * BW;
+        act[k] = i < BH * BW;
+        int gx = x0 + px[k] - BO, gy = y0 + py[k] - BO;
+        ing[k] = act[k] && gx >= 0 && gx < mx && gy >= 0 && gy < my;
         size_t j = (size_t)gy * mx + gx;
-        rb[k] = ld_masked(b, j, in);
-        rq[k] = ld_masked(q, j, in);
+        rb[k] = ld_masked(b, j, ing[k]);
+        rw[k] = ld_masked(q, j, ing[k]);
     }
     if (PROL) {
 #pragma unroll
@@ -141,14 +145,6 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
             if (i < UH * UW) (&U0[0][0])[i] = ru[k];
         }
     }
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-        int i = threadIdx.x + 256 * k;
-        if (i < BH * BW) {
-            (&Bs[0][0])[i] = rb[k];
-            (&Qs[0][0])[i] = rq[k];
-        }
-    }
     if (PROL) {
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
@@ -156,6 +152,8 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
             if (i < ECH * ECW) (&EC[0][0])[i] = re[k];
         }
     }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) rw[k] = jweight(P, rw[k]);   // q -> omega / D
     __syncthreads();
     // phase 2: coarse-grid correction u += P e_c on the staged u.  Branch
     // free: fine node f = g + 1 takes coarse interior nodes f/2 - 1 (weight 1
@@ -183,46 +181,42 @@ __device__ __forceinline__ void smooth2d_body(const cx<T> *__restrict__ u, const
     }
     // phase 3: sweep 1 on the tile plus a one-point halo (zero outside the domain)
     if (NS == 2) {
-        for (int i = threadIdx.x; i < S1H * S1W; i += 256) {
-            int sy = i / S1W, sx = i - sy * S1W;             // position in the b, q region
-            int gx = x0 + sx - BO, gy = y0 + sy - BO;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            if (!act[k]) continue;
+            const int sx = px[k], sy = py[k];
             cx<T> v = zero;
-            if (gx >= 0 && gx < mx && gy >= 0 && gy < my) {
+            if (ing[k]) {
                 if (ZERO) {
-                    v = jacobi0_point<T>(P, Bs[sy][sx], Qs[sy][sx]);
+                    v = jacobi0_w(rb[k], rw[k]);
                 } else {
                     int ux = sx + 1, uy = sy + 1;            // same point in U0 (halo 2)
                     v = jacobi_point<T>(P, U0[uy][ux], U0[uy][ux - 1], U0[uy][ux + 1], U0[uy - 1][ux],
-                                        U0[uy + 1][ux], Bs[sy][sx], Qs[sy][sx]);
+                                        U0[uy + 1][ux], rb[k], rw[k]);
                 }
             }
             U1[sy][sx] = v;
         }
         __syncthreads();
     }
-    // phase 4: last sweep on the tile
-    const int lx = threadIdx.x & 63;
-    const int gx = x0 + lx;
+    // phase 4: last sweep on the tile (the thread's points inside it)
 #pragma unroll
-    for (int k = 0; k < TH / 4; ++k) {
-        int ly = (threadIdx.x >> 6) + 4 * k;
-        int gy = y0 + ly;
-        if (gx < mx && gy < my) {
-            size_t j = (size_t)gy * mx + gx;
-            const int bx = lx + BO, by = ly + BO;
-            cx<T> v;
-            if (NS == 2) {
-                v = jacobi_point<T>(P, U1[by][bx], U1[by][bx - 1], U1[by][bx + 1], U1[by - 1][bx], U1[by + 1][bx],
-                                    Bs[by][bx], Qs[by][bx]);
-            } else if (ZERO) {
-                v = jacobi0_point<T>(P, Bs[by][bx], Qs[by][bx]);
-            } else {
-                int ax = lx + H, ay = ly + H;
-                v = jacobi_point<T>(P, U0[ay][ax], U0[ay][ax - 1], U0[ay][ax + 1], U0[ay - 1][ax], U0[ay + 1][ax],
-                                    Bs[by][bx], Qs[by][bx]);
-            }
-            out[j] = v;
+    for (int k = 0; k < NP; ++k) {
+        const int sx = px[k], sy = py[k];
+        if (!ing[k] || sx < BO || sx >= BO + FTX || sy < BO || sy >= BO + TH) continue;
+        const size_t j = (size_t)(y0 + sy - BO) * mx + (x0 + sx - BO);
+        cx<T> v;
+        if (NS == 2) {
+            v = jacobi_point<T>(P, U1[sy][sx], U1[sy][sx - 1], U1[sy][sx + 1], U1[sy - 1][sx], U1[sy + 1][sx], rb[k],
+                                rw[k]);
+        } else if (ZERO) {
+            v = jacobi0_w(rb[k], rw[k]);
+        } else {
+            int ax = sx + H, ay = sy + H;
+            v = jacobi_point<T>(P, U0[ay][ax], U0[ay][ax - 1], U0[ay][ax + 1], U0[ay - 1][ax], U0[ay + 1][ax], rb[k],
+                                rw[k]);
         }
+        out[j] = v;
     }
 }
 
@@ -312,6 +306,162 @@ __global__ __launch_bounds__(256) void k_resid_restrict2d(const cx<T> *__restric
 {
     if (stop && *stop) return;
     resid_restrict2d_body<T>(u, b, q, bc, P, ctiles_x, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Pre-smoothing (two sweeps), residual and full weighting in one pass.  The
+// block owns the fine points [x0, x0 + 64) x [y0, y0 + FH) (written to out:
+// the smoothed u) and the coarse points whose centre lies there, I in
+// [x0/2, x0/2 + 32), J in [y0/2, y0/2 + FH/2) (written to bc).  Their full
+// weighting needs the residual on [x0, x0 + 64] x [y0, y0 + FH] (one column
+// and one row past the owned points); the residual needs the smoothed u one
+// point further out, sweep 2 needs sweep 1 one point further, sweep 1 needs u
+// one point further:
+//   R   [x0, x0 + 64]      x [y0, y0 + FH]          residual
+//   S2  [x0 - 1, x0 + 65]  x [y0 - 1, y0 + FH + 1]  sweep 2 (the smoothed u)
+//   S1  [x0 - 2, x0 + 66]  x [y0 - 2, y0 + FH + 2]  sweep 1
+//   U0  [x0 - 3, x0 + 67]  x [y0 - 3, y0 + FH + 3]  incoming u (not ZERO)
+// Each thread keeps the same points of S1 through sweep 1, sweep 2 and the
+// residual (S2 and R lie inside S1), so b, q and omega / D of its points stay
+// in registers and only the u values that neighbours read pass through LDS.
+// Values outside the grid are 0 (the Dirichlet border).  Every value is
+// formed by the same point functions as in k_smooth2d and
+// k_resid_restrict2d, so the pass equals the two launches bit for bit; it
+// skips their re-read of the smoothed u, b and q and one launch.
+template <typename T, bool ZERO, int FH>
+__device__ __forceinline__ void smooth_rr2d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                 const cx<T> *__restrict__ q, cx<T> *__restrict__ out,
+                                                 cx<T> *__restrict__ bc, const Stencil<T> &P, int tiles_x, int tile)
+{
+    static_assert(FH % 8 == 0, "fine tile height: a multiple of 8 rows");
+    constexpr int RW = FTX + 1, RH = FH + 1;
+    constexpr int S2W = FTX + 3, S2H = FH + 3;
+    constexpr int S1W = FTX + 5, S1H = FH + 5;
+    constexpr int UW = FTX + 7, UH = FH + 7;
+    constexpr int A0 = (ZERO ? S2H * S2W : (UH * UW > S2H * S2W ? UH * UW : S2H * S2W));
+    constexpr int A1 = S1H * S1W > RH * RW ? S1H * S1W : RH * RW;
+    // U0 is dead once sweep 1 is done, S1 once sweep 2 is done (barriers)
+    __shared__ cx<T> L0[A0];
+    __shared__ cx<T> L1[A1];
+    cx<T>(&U0)[UH][UW] = *reinterpret_cast<cx<T>(*)[UH][UW]>(&L0[0]);
+    cx<T>(&S2)[S2H][S2W] = *reinterpret_cast<cx<T>(*)[S2H][S2W]>(&L0[0]);
+    cx<T>(&S1)[S1H][S1W] = *reinterpret_cast<cx<T>(*)[S1H][S1W]>(&L1[0]);
+    cx<T>(&R)[RH][RW] = *reinterpret_cast<cx<T>(*)[RH][RW]>(&L1[0]);
+    const int mx = P.mx, my = P.my;
+    const int mxc = (mx - 1) / 2, myc = (my - 1) / 2;
+    const int x0 = (tile % tiles_x) * FTX, y0 = (tile / tiles_x) * FH;
+    const cx<T> zero = {T(0), T(0)};
+
+    // the thread's points of S1: slot k is point threadIdx.x + 256 k
+    constexpr int NP = (S1H * S1W + 255) / 256;
+    int px[NP], py[NP];
+    bool act[NP], ing[NP];
+    cx<T> rb[NP], rq[NP], rw[NP];
+    constexpr int NU = ZERO ? 1 : (UH * UW + 255) / 256;
+    cx<T> ru[NU];
+    if (!ZERO) {
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            int i = threadIdx.x + 256 * k;
+            int ly = i / UW, lx = i - ly * UW;
+            int gx = x0 + lx - 3, gy = y0 + ly - 3;
+            bool in = i < UH * UW && gx >= 0 && gx < mx && gy >= 0 && gy < my;
+            ru[k] = ld_masked(u, (size_t)gy * mx + gx, in);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        int i = threadIdx.x + 256 * k;
+        py[k] = i / S1W;
+        px[k] = i - py[k] * S1W;
+        act[k] = i < S1H * S1W;
+        int gx = x0 + px[k] - 2, gy = y0 + py[k] - 2;
+        ing[k] = act[k] && gx >= 0 && gx < mx && gy >= 0 && gy < my;
+        size_t j = (size_t)gy * mx + gx;
+        rb[k] = ld_masked(b, j, ing[k]);
+        rq[k] = ld_masked(q, j, ing[k]);
+    }
+    if (!ZERO) {
+#pragma unroll
+        for (int k = 0; k < NU; ++k) {
+            int i = threadIdx.x + 256 * k;
+            if (i < UH * UW) (&U0[0][0])[i] = ru[k];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) rw[k] = jweight(P, rq[k]);
+    __syncthreads();
+    // sweep 1 on S1
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        if (!act[k]) continue;
+        const int sx = px[k], sy = py[k];
+        cx<T> v = zero;
+        if (ing[k]) {
+            if (ZERO) {
+                v = jacobi0_w(rb[k], rw[k]);
+            } else {
+                int ux = sx + 1, uy = sy + 1;
+                v = jacobi_point<T>(P, U0[uy][ux], U0[uy][ux - 1], U0[uy][ux + 1], U0[uy - 1][ux], U0[uy + 1][ux],
+                                    rb[k], rw[k]);
+            }
+        }
+        S1[sy][sx] = v;
+    }
+    __syncthreads();
+    // sweep 2 on S2 (over U0's storage); the owned points go to out
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int sx = px[k], sy = py[k];                     // S1 coordinates; S2 is S1 less its rim
+        if (!act[k] || sx < 1 || sx > S2W || sy < 1 || sy > S2H) continue;
+        cx<T> v = zero;
+        if (ing[k]) {
+            v = jacobi_point<T>(P, S1[sy][sx], S1[sy][sx - 1], S1[sy][sx + 1], S1[sy - 1][sx], S1[sy + 1][sx], rb[k],
+                                rw[k]);
+            if (sx >= 2 && sx <= FTX + 1 && sy >= 2 && sy <= FH + 1)
+                out[(size_t)(y0 + sy - 2) * mx + (x0 + sx - 2)] = v;
+        }
+        S2[sy - 1][sx - 1] = v;
+    }
+    __syncthreads();
+    // residual on R (over S1's storage)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int sx = px[k], sy = py[k];                     // R is S1 less two rims, low sides
+        if (!act[k] || sx < 2 || sx > RW + 1 || sy < 2 || sy > RH + 1) continue;
+        const int tx = sx - 1, ty = sy - 1;                   // same point in S2
+        cx<T> r = zero;
+        if (ing[k])
+            r = resid_point<T>(P, S2[ty][tx], S2[ty][tx - 1], S2[ty][tx + 1], S2[ty - 1][tx], S2[ty + 1][tx], rb[k],
+                               rq[k]);
+        R[sy - 2][sx - 2] = r;
+    }
+    __syncthreads();
+    // full weighting at the owned coarse points
+    const int I0 = x0 / 2, J0 = y0 / 2;
+    for (int i = threadIdx.x; i < (FTX / 2) * (FH / 2); i += 256) {
+        const int cj = i / (FTX / 2), ci = i - cj * (FTX / 2);
+        const int I = I0 + ci, J = J0 + cj;
+        if (I < mxc && J < myc) {
+            const T w[3] = {T(0.25), T(0.5), T(0.25)};
+            cx<T> acc = {T(0), T(0)};
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    T wgt = (w[dx + 1] * w[dy + 1]) * T(1);
+                    acc = acc + wgt * R[2 * cj + 1 + dy][2 * ci + 1 + dx];
+                }
+            bc[(size_t)J * mxc + I] = acc;
+        }
+    }
+}
+
+template <typename T, bool ZERO, int TAG, int FH>
+__global__ __launch_bounds__(256) void k_smooth_rr2d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                     const cx<T> *__restrict__ q, cx<T> *__restrict__ out,
+                                                     cx<T> *__restrict__ bc, Stencil<T> P, int tiles_x,
+                                                     const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    smooth_rr2d_body<T, ZERO, FH>(u, b, q, out, bc, P, tiles_x, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Mixed-precision outer step: u' = u + s d with s = ctl->scale_cur;
@@ -428,9 +578,10 @@ __device__ void tail_smooth(const TailView<T> &v, const TailLevel<T> &L, int nu,
             const int k = v.at(x, y);
             cx<T> bj = v.b[k], qj = v.q[k];
             if (s == 0 && zero) {
-                dst[k] = jacobi0_point<T>(L.P, bj, qj);
+                dst[k] = jacobi0_w(bj, jweight(L.P, qj));
             } else {
-                dst[k] = jacobi_point<T>(L.P, src[k], src[k - 1], src[k + 1], src[k - v.W], src[k + v.W], bj, qj);
+                dst[k] = jacobi_point<T>(L.P, src[k], src[k - 1], src[k + 1], src[k - v.W], src[k + v.W], bj,
+                                         jweight(L.P, qj));
             }
         }
         __syncthreads();
@@ -705,6 +856,36 @@ template void launch_resid_restrict2d<double>(const LevelGeom &, const Stencil<d
                                               const cd *, cd *, hipStream_t, const int *);
 template void launch_resid_restrict2d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
                                              const cf *, cf *, hipStream_t, const int *);
+
+// Fine tile height of the fused pre-smoothing + residual + restriction pass:
+// FP32 16 rows (48 KB of LDS, three blocks per CU), FP64 8 rows (60 KB, two).
+template <typename T>
+struct SmoothRR {
+    static constexpr int FH = sizeof(T) == 4 ? 16 : 8;
+};
+
+template <typename T>
+void launch_smooth_rr2d(const LevelGeom &g, const Stencil<T> &P, bool zero, const cx<T> *u, const cx<T> *b,
+                        const cx<T> *q, cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop)
+{
+    constexpr int FH = SmoothRR<T>::FH;
+    const int tx = (g.m[0] + FTX - 1) / FTX;
+    const int nb = tx * ((g.m[1] + FH - 1) / FH);
+#define FFMG_SRR(Z, TG) \
+    hipLaunchKernelGGL((k_smooth_rr2d<T, Z, TG, FH>), dim3(nb), dim3(256), 0, s, u, b, q, out, bc, P, tx, stop)
+    if (zero) {
+        if (finest) FFMG_SRR(true, 1);
+        else FFMG_SRR(true, 0);
+    } else {
+        if (finest) FFMG_SRR(false, 1);
+        else FFMG_SRR(false, 0);
+    }
+#undef FFMG_SRR
+}
+template void launch_smooth_rr2d<double>(const LevelGeom &, const Stencil<double> &, bool, const cd *, const cd *,
+                                         const cd *, cd *, cd *, hipStream_t, bool, const int *);
+template void launch_smooth_rr2d<float>(const LevelGeom &, const Stencil<float> &, bool, const cf *, const cf *,
+                                        const cf *, cf *, cf *, hipStream_t, bool, const int *);
 
 void launch_refine2d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *u_out, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t st,

@@ -57,7 +57,9 @@ struct ffmg_handle {
     int tail_l = -1;
     size_t tail_lds[2] = {0, 0};     // [FP64, FP32]
     int tail_variant = 0;            // index into TAIL_POINTS (autotuned)
-    int smooth_variant = 0;          // index into SMOOTH_TH (autotuned)
+    int smooth_variant = 0;          // index into SMOOTH_TH, finest level (autotuned)
+    int smooth_coarse_variant = 0;   // index into SMOOTH_TH, coarser levels (autotuned)
+    int pre_variant = 0;             // FFMG_TUNE_PRE: 0 fused pre-smoothing + residual + restriction (autotuned)
     ffmg::TailParams<double> tail64{};
     ffmg::TailParams<float> tail32{};
     ffmg::FarFieldPlan *ff = nullptr;

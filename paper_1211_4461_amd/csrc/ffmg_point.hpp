@@ -5,6 +5,7 @@
 //   (A u)_j = e^{-2 i gamma} sum_k (2 u_j - u_{j-e_k} - u_{j+e_k}) / h_k^2
 //             - (k0^2 + q_j) u_j                                 (Sec. 3.2, eq. csg)
 //   D_j     = e^{-2 i gamma} sum_k 2 / h_k^2 - (k0^2 + q_j)        (Jacobi diagonal)
+//   (A u)_j = D_j u_j - e^{-2 i gamma} N_j,  N_j = sum_k (u_{j-e_k} + u_{j+e_k}) / h_k^2
 //
 // The rotation e^{-2 i gamma} is common to every axis, so the real weighted
 // second differences are summed first and multiplied by it once.  Products
@@ -71,37 +72,59 @@ __device__ __forceinline__ cx<T> resid_from(const Stencil<T> &P, cx<T> L, cx<T> 
     return {bj.re - Au.re, bj.im - Au.im};
 }
 
-// u + omega r / D
+// The Jacobi weight omega / D_j of a point (a function of q_j only: kernels
+// that sweep a point several times form it once).
 template <typename T>
-__device__ __forceinline__ cx<T> jacobi_from(const Stencil<T> &P, cx<T> L, cx<T> uc, cx<T> bj, cx<T> qj)
-{
-    cx<T> r = resid_from(P, L, uc, bj, qj);
-    cx<T> D = {P.csum2.re - (P.k02 + qj.re), P.csum2.im - qj.im};
-    cx<T> t = cmul(r, crecip(D));
-    return {fma_(P.omega, t.re, uc.re), fma_(P.omega, t.im, uc.im)};
-}
-
-// first sweep from a zero guess: omega b / D
-template <typename T>
-__device__ __forceinline__ cx<T> jacobi0_from(const Stencil<T> &P, cx<T> bj, cx<T> qj)
+__device__ __forceinline__ cx<T> jweight(const Stencil<T> &P, cx<T> qj)
 {
     cx<T> D = {P.csum2.re - (P.k02 + qj.re), P.csum2.im - qj.im};
-    cx<T> t = cmul(bj, crecip(D));
-    return {P.omega * t.re, P.omega * t.im};
+    cx<T> r = crecip(D);
+    return {P.omega * r.re, P.omega * r.im};
 }
 
-// 2D conveniences from the five stencil values
+// N = sum_k (u_- + u_+) / h_k^2 for the x and y axes (real weights), and the
+// z-axis term added to it.
+template <typename T>
+__device__ __forceinline__ cx<T> nsum_xy(const Stencil<T> &P, cx<T> w, cx<T> e, cx<T> s, cx<T> n)
+{
+    return {fma_(s.re + n.re, P.ih2[1], (w.re + e.re) * P.ih2[0]),
+            fma_(s.im + n.im, P.ih2[1], (w.im + e.im) * P.ih2[0])};
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> nsum_add_z(const Stencil<T> &P, cx<T> N, cx<T> d, cx<T> u_)
+{
+    return {fma_(d.re + u_.re, P.ih2[2], N.re), fma_(d.im + u_.im, P.ih2[2], N.im)};
+}
+
+// One omega-Jacobi update u + omega (b - A u) / D.  Since A u = D u - rot N
+// (N the weighted neighbour sum), it equals (1 - omega) u + (omega / D)
+// (b + rot N), which needs neither the residual nor a division per sweep.
+// The rounding of the new iterate is of the order of eps |u| either way; the
+// residual itself (restriction, norms, refinement) keeps the
+// second-difference form, whose rounding does not grow with 1 / h^2.
+template <typename T>
+__device__ __forceinline__ cx<T> jacobi_n(const Stencil<T> &P, cx<T> N, cx<T> uc, cx<T> bj, cx<T> wj)
+{
+    cx<T> rn = cmul(P.rot, N);
+    cx<T> t = {bj.re + rn.re, bj.im + rn.im};
+    cx<T> v = cmul(wj, t);
+    return {fma_(P.omc, uc.re, v.re), fma_(P.omc, uc.im, v.im)};
+}
+
+// first sweep from a zero guess: (omega / D) b
+template <typename T>
+__device__ __forceinline__ cx<T> jacobi0_w(cx<T> bj, cx<T> wj)
+{
+    return cmul(wj, bj);
+}
+
+// 2D sweep from the five stencil values and the point's weight
 template <typename T>
 __device__ __forceinline__ cx<T> jacobi_point(const Stencil<T> &P, cx<T> uc, cx<T> w, cx<T> e, cx<T> s, cx<T> n,
-                                              cx<T> bj, cx<T> qj)
+                                              cx<T> bj, cx<T> wj)
 {
-    return jacobi_from(P, lap_xy(P, uc, w, e, s, n), uc, bj, qj);
-}
-
-template <typename T>
-__device__ __forceinline__ cx<T> jacobi0_point(const Stencil<T> &P, cx<T> bj, cx<T> qj)
-{
-    return jacobi0_from(P, bj, qj);
+    return jacobi_n(P, nsum_xy(P, w, e, s, n), uc, bj, wj);
 }
 
 template <typename T>

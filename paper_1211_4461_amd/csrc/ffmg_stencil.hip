@@ -46,6 +46,7 @@ Stencil<T> make_stencil(const LevelGeom &g, double gamma, double k02, double ome
     P.csum2 = cx<T>{T(cr * s2), T(ci * s2)};
     P.k02 = T(k02);
     P.omega = T(omega);
+    P.omc = T(1.0 - omega);
     return P;
 }
 template Stencil<double> make_stencil<double>(const LevelGeom &, double, double, double);
@@ -55,7 +56,8 @@ template Stencil<float> make_stencil<float>(const LevelGeom &, double, double, d
 // The point update shared by all stencil kernels.
 // MODE_RESID writes rscale * r converted to TO (the FP64 residual of the
 // refinement loop is written as a scaled FP32 right-hand side this way).
-// L = sum_k (2u - u_- - u_+)/h_k^2, the weighted second differences.
+// L = sum_k (2u - u_- - u_+)/h_k^2, the weighted second differences, except
+// for MODE_JACOBI, where it is the neighbour sum N = sum_k (u_- + u_+)/h_k^2.
 template <typename T, typename TO, int MODE>
 __device__ __forceinline__ void point_update(const Stencil<T> &P, T rscale, cx<T> uc, cx<T> L, size_t j,
                                              const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
@@ -65,9 +67,9 @@ __device__ __forceinline__ void point_update(const Stencil<T> &P, T rscale, cx<T
     if (MODE == MODE_APPLY) {
         out[j] = cvt<TO>(apply_point(P, L, uc, qj));
     } else if (MODE == MODE_JACOBI0) {
-        out[j] = cvt<TO>(jacobi0_from(P, b[j], qj));
+        out[j] = cvt<TO>(jacobi0_w(b[j], jweight(P, qj)));
     } else if (MODE == MODE_JACOBI) {
-        out[j] = cvt<TO>(jacobi_from(P, L, uc, b[j], qj));
+        out[j] = cvt<TO>(jacobi_n(P, L, uc, b[j], jweight(P, qj)));
     } else {
         cx<T> r = resid_from(P, L, uc, b[j], qj);
         if (MODE == MODE_RESID) out[j] = cvt<TO>(rscale * r);
@@ -118,7 +120,10 @@ __device__ __forceinline__ void stencil2d_body(const cx<T> *__restrict__ u, cons
             cx<T> uc = {T(0), T(0)}, lap = {T(0), T(0)};
             if (!zero_u) {
                 uc = s[ly + 1][lx + 1];
-                lap = lap_xy(P, uc, s[ly + 1][lx], s[ly + 1][lx + 2], s[ly][lx + 1], s[ly + 2][lx + 1]);
+                if (MODE == MODE_JACOBI)
+                    lap = nsum_xy(P, s[ly + 1][lx], s[ly + 1][lx + 2], s[ly][lx + 1], s[ly + 2][lx + 1]);
+                else
+                    lap = lap_xy(P, uc, s[ly + 1][lx], s[ly + 1][lx + 2], s[ly][lx + 1], s[ly + 2][lx + 1]);
             }
             point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
         }
@@ -244,7 +249,7 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
         const size_t j = (size_t)z * plane + (size_t)y * mx + x;
         if (SRC == SRC_ZERO2) {
             if (!in) return zero;
-            return jacobi0_from(P, b[j], q[j]);
+            return jacobi0_w(b[j], jweight(P, q[j]));
         }
         cx<T> v = ld_masked(u, j, in);
         if (SRC == SRC_PROL && in) v = v + interp(x, y, z);
@@ -302,9 +307,15 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                 cx<T> uc = {T(0), T(0)}, lap = {T(0), T(0)};
                 if (!zero_u) {
                     uc = cur[i];
-                    lap = lap_xy(P, uc, s[buf][ly + 1][lx], s[buf][ly + 1][lx + 2], s[buf][ly][lx + 1],
-                                 s[buf][ly + 2][lx + 1]);
-                    lap = lap_add_z(P, lap, uc, prev[i], nxt[i]);
+                    if (MODE == MODE_JACOBI) {
+                        lap = nsum_xy(P, s[buf][ly + 1][lx], s[buf][ly + 1][lx + 2], s[buf][ly][lx + 1],
+                                      s[buf][ly + 2][lx + 1]);
+                        lap = nsum_add_z(P, lap, prev[i], nxt[i]);
+                    } else {
+                        lap = lap_xy(P, uc, s[buf][ly + 1][lx], s[buf][ly + 1][lx + 2], s[buf][ly][lx + 1],
+                                     s[buf][ly + 2][lx + 1]);
+                        lap = lap_add_z(P, lap, uc, prev[i], nxt[i]);
+                    }
                 }
                 point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
             }

@@ -277,6 +277,8 @@ def farfield_map(h: Handle, eta, u, dirs, out=None):
 TUNE_FF_GEMM = 0
 TUNE_TAIL = 1
 TUNE_SMOOTH = 2
+TUNE_PRE = 3
+TUNE_SMOOTH_COARSE = 4
 
 
 def _etas(etas):
@@ -352,7 +354,7 @@ def mg_tune_farfield(h: Handle, eta, u, dirs, reps=5):
 
 
 def mg_tune_solve(h: Handle, b, u, tol=1e-10, reps=3, tunable=TUNE_TAIL):
-    """Time `reps` solves per variant of `tunable` (TUNE_TAIL or TUNE_SMOOTH;
+    """Time `reps` solves per variant of `tunable` (TUNE_TAIL, TUNE_SMOOTH, TUNE_PRE, TUNE_SMOOTH_COARSE;
     u is overwritten); selects the fastest.  Returns (best, [ms per variant])."""
     nv = max(mg_tune_variants(h, tunable), 1)
     times = (ctypes.c_double * nv)()

@@ -393,21 +393,23 @@ def test_tail_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path):
 
 @pytest.mark.parametrize("n", [128, 512])
 def test_smoothing_tile_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path):
-    """Every tile height of the fused smoothing kernel (8, 16, 4 rows) does the
-    same per-point arithmetic: FP64 V-cycles and FP32-in-FP64 solves agree bit
-    for bit (ragged last tiles included); the solve-timing sweep selects one
-    and the cache applies it to a second handle."""
+    """Every tile height of the fused smoothing kernel (8, 16, 4 rows), on the
+    finest level and on the coarser ones (two tunables), does the same
+    per-point arithmetic: FP64 V-cycles and FP32-in-FP64 solves agree bit for
+    bit (ragged last tiles included); the solve-timing sweep selects one and
+    the cache applies it to a second handle."""
     from paper_1211_4461_amd import autotune
     w = W.bumps_2d(n=n, seed=n + 3, k0=1.1, M=8)
     for prec in (ff.FP64, ff.FP32_IR):
         h, _, g, _, _, _ = setup(ff, orc, w, precision=prec)
         nv = ff.mg_tune_variants(h, ff.TUNE_SMOOTH)
-        assert nv == 3
+        assert nv == 3 and ff.mg_tune_variants(h, ff.TUNE_SMOOTH_COARSE) == 3
         b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
         ref = None
-        for v in range(nv):
+        for v, vc in ((0, 0), (1, 1), (2, 2), (0, 2), (2, 1)):
             ff.mg_tune_set(h, v, ff.TUNE_SMOOTH)
-            assert ff.mg_tune_get(h, ff.TUNE_SMOOTH) == v
+            ff.mg_tune_set(h, vc, ff.TUNE_SMOOTH_COARSE)
+            assert ff.mg_tune_get(h, ff.TUNE_SMOOTH) == v and ff.mg_tune_get(h, ff.TUNE_SMOOTH_COARSE) == vc
             u = torch.zeros_like(b)
             if prec == ff.FP64:
                 for _ in range(3):
@@ -419,8 +421,11 @@ def test_smoothing_tile_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp
             torch.cuda.synchronize()
             if ref is None:
                 ref = (key, u.clone())
-            assert key == ref[0] and torch.equal(u, ref[1]), (prec, v)
+            assert key == ref[0] and torch.equal(u, ref[1]), (prec, v, vc)
     ws = torch.zeros_like(b)
+    best, times = ff.mg_tune_solve(h, b, ws, reps=1, tunable=ff.TUNE_SMOOTH_COARSE)
+    assert 0 <= best < 3 and times[best] == min(times) and ff.mg_tune_get(h, ff.TUNE_SMOOTH_COARSE) == best
+    assert torch.equal(ws, ref[1])
     best, times = ff.mg_tune_solve(h, b, ws, reps=1, tunable=ff.TUNE_SMOOTH)
     assert 0 <= best < 3 and times[best] == min(times) and ff.mg_tune_get(h, ff.TUNE_SMOOTH) == best
     assert torch.equal(ws, ref[1])
@@ -429,6 +434,54 @@ def test_smoothing_tile_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp
     h2, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR)
     assert autotune.tune_solve(h2, b, ws, ff.FP32_IR, path=cache, tunable=ff.TUNE_SMOOTH) == v1
     assert ff.mg_tune_get(h2, ff.TUNE_SMOOTH) == v1
+
+
+@pytest.mark.parametrize("n", [64, 128, 512])
+def test_pre_pass_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path):
+    """The one-pass pre-smoothing (two sweeps, residual, full weighting) and
+    the two launches it replaces agree bit for bit: FP64 V-cycles from zero and
+    from a nonzero guess, FP32-in-FP64 solves and the full multigrid start
+    (ragged last tiles and the grid border included); the solve-timing sweep
+    selects one and the cache applies it to a second handle."""
+    from paper_1211_4461_amd import autotune
+    w = W.bumps_2d(n=n, seed=n + 7, k0=1.2, M=8)
+    for prec in (ff.FP64, ff.FP32_IR):
+        h, _, g, _, _, _ = setup(ff, orc, w, precision=prec)
+        assert ff.mg_tune_variants(h, ff.TUNE_PRE) == 2
+        assert ff.mg_tune_get(h, ff.TUNE_PRE) == 0
+        b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+        u0 = dev(0.3 * crand(n, g.shape))
+        outs = []
+        for v in (0, 1):
+            ff.mg_tune_set(h, v, ff.TUNE_PRE)
+            if prec == ff.FP64:
+                u = torch.zeros_like(b)
+                for _ in range(2):
+                    ff.mg_vcycle(h, b, u)
+                u2 = u0.clone()
+                ff.mg_vcycle(h, b, u2)
+                key = None
+            else:
+                u = torch.zeros_like(b)
+                info = ff.mg_solve(h, b, u)
+                key = (info.cycles, info.rel_residual)
+                u2 = torch.empty_like(b)
+                ff.mg_fmg(h, b, u2, 2)
+            torch.cuda.synchronize()
+            outs.append((key, u.clone(), u2.clone()))
+        assert outs[0][0] == outs[1][0]
+        assert torch.equal(outs[0][1], outs[1][1]) and torch.equal(outs[0][2], outs[1][2]), prec
+    ws = torch.zeros_like(b)
+    best, times = ff.mg_tune_solve(h, b, ws, reps=1, tunable=ff.TUNE_PRE)
+    assert best in (0, 1) and times[best] == min(times) and ff.mg_tune_get(h, ff.TUNE_PRE) == best
+    assert torch.equal(ws, outs[0][1])
+    cache = str(tmp_path / "tune.json")
+    v1 = autotune.tune_solve(h, b, ws, ff.FP32_IR, path=cache, reps=1, tunable=ff.TUNE_PRE)
+    h2, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR)
+    assert autotune.tune_solve(h2, b, ws, ff.FP32_IR, path=cache, tunable=ff.TUNE_PRE) == v1
+    assert ff.mg_tune_get(h2, ff.TUNE_PRE) == v1
+    h3, _, _, _, _, _ = setup(ff, orc, w, tile_config=1)
+    assert ff.mg_tune_variants(h3, ff.TUNE_PRE) == 1
 
 
 def test_repeated_solves_and_batches(ff, orc):
