@@ -44,9 +44,10 @@ def src_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from committed rocprofv3 --pmc
-    counters, or None if absent or taken on a different kernel source."""
+def measured_traffic(kernel, tile_rows):
+    """HBM bytes per launch of `kernel` (the variant with `tile_rows` rows)
+    from committed rocprofv3 --pmc counters, or None if absent or taken on a
+    different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -54,7 +55,8 @@ def measured_traffic(kernel):
         return None
     if t.get("src_sha") != src_hash() or t.get("kernel") != kernel:
         return None
-    return t.get("bytes_per_launch")
+    v = t.get("per_tile_rows", {}).get(str(tile_rows))
+    return None if v is None else v.get("bytes_per_launch")
 
 
 KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3), ("ffgemm", 4))
@@ -462,8 +464,8 @@ def main():
                                                  args.warmup, bpp_plain, fmg_cycles=fk)
     names = {"pre": "finest-level pre-smoothing: 2 FP32 Jacobi sweeps, residual and full weighting in one pass "
                     "(k_smooth_rr2d<float,*,1,16>)",
-             "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1,TH>, "
-                     "TH = the tuned tile height)",
+             "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1,%d>, "
+                     "the tuned tile height)" % (mixed["tune"]["smooth"] or {}).get("tile_rows", 8),
              "refine": "FP64 update + residual of the refinement loop (k_refine2d)"}
     pr = mixed["prof"]
     dom = mixed["dominant"]
@@ -471,7 +473,8 @@ def main():
     bytes_alg = bpp_mixed[dom] * N
     achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
     roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, (mixed["tune"]["smooth"] or {}).get("tile_rows", 8)),
             "bytes_per_launch": bytes_alg, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": mixed["live"][1],
             "warmup_GBs": {k: round(bpp_mixed[k] * N / (pr[k][0] / max(pr[k][1], 1) * 1e-3) / 1e9, 1)
                            for k in bpp_mixed if pr[k][1] > 0}}
