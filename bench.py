@@ -306,21 +306,26 @@ def run_learned(ff, torch, W, reps=3, oracle_check=False):
     return out
 
 
-def run_3d(ff, torch, W, steps=2):
+def run_3d(ff, torch, W, steps=2, fmg_cycles=FMG_K):
     """The 3D workload (512^3 intervals, chi = 0.5 exp(-z.z/2), 128 x 64
     directions): maps with FP32 V-cycles in FP64 refinement + split-BF16 far
-    field and plain FP64 maps, each solved to 1e-10; the rate of the
-    finest-level post-smoothing (two z-marching launches per cycle: the
-    interpolation fused into the first 7-point sweep, then the second sweep;
-    8 e + e/8 bytes per point in all) from the library's events."""
+    field and plain FP64 maps, each solved to 1e-10 from the full multigrid
+    start (and, as `*_zero_start`, from u = 0); the rate of the finest-level
+    post-smoothing (two z-marching launches per cycle: the interpolation
+    fused into the first 7-point sweep, then the second sweep; 8 e + e/8 bytes
+    per point in all) from the library's events."""
     import numpy as np
     from paper_1211_4461_amd import autotune
     w = W.gauss_3d()
     out = {"workload": f"gauss_3d n={w.n} box=[-6,6]^3 k0=1 gamma=30deg eta=+x, "
                        f"{len(w.dirs)} directions (128 azimuth x 64 polar)", "unknowns": w.N}
+    out["start"] = f"full multigrid: {fmg_cycles} V(2,2) per coarse level"
     maps = {}
-    for name, prec, ffp, e in (("mixed", ff.FP32_IR, ff.FF_BF16X6, 8), ("plain_fp64", ff.FP64, ff.FF_FP64, 16)):
-        h = ff.setup_workload(w, options=ff.default_options(precision=prec, ff_precision=ffp))[0]
+    for name, prec, ffp, e, fk in (("mixed", ff.FP32_IR, ff.FF_BF16X6, 8, fmg_cycles),
+                                   ("plain_fp64", ff.FP64, ff.FF_FP64, 16, fmg_cycles),
+                                   ("mixed_zero_start", ff.FP32_IR, ff.FF_BF16X6, 8, 0),
+                                   ("plain_fp64_zero_start", ff.FP64, ff.FF_FP64, 16, 0)):
+        h = ff.setup_workload(w, options=ff.default_options(precision=prec, ff_precision=ffp, fmg_cycles=fk))[0]
         if ff.mg_tune_variants(h, ff.TUNE_FF_GEMM) > 1:
             autotune.tune_farfield(h, w.eta, None, w.dirs, ffp)
         b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
@@ -361,6 +366,8 @@ def run_3d(ff, torch, W, steps=2):
     out["speedup_vs_plain"] = round(out["mixed"]["maps_per_s"] / out["plain_fp64"]["maps_per_s"], 3)
     out["mixed_vs_plain_farfield_rel_err"] = float(np.linalg.norm(maps["mixed"] - maps["plain_fp64"]) /
                                                    np.linalg.norm(maps["plain_fp64"]))
+    out["fmg_vs_zero_start_farfield_rel_diff"] = float(np.linalg.norm(maps["mixed"] - maps["mixed_zero_start"]) /
+                                                       np.linalg.norm(maps["mixed_zero_start"]))
     return out
 
 
