@@ -10,7 +10,10 @@ field as a split-BF16 MFMA contraction with FP32 accumulation); the plain FP64
 path (FP64 V-cycles, FP64 MFMA far field) is timed beside it on the same map.
 Both solves start from the full multigrid guess (the nested iteration of
 V-cycles, FMG_K per coarse level); the same solves from u = 0 and with other
-cycle counts per level are timed as well (`start_forms`).
+cycle counts per level are timed as well (`start_forms`).  Consecutive maps
+alternate between two handles on two streams, so that one map's far field
+(queued on its stream) runs while the next map is solved; the one-stream
+rate is in `start_forms` too.
 
 Also reported: the roofline of the dominant kernel (the timed kernel with the
 largest total time per map), timed live with HIP events on its stream during
@@ -66,12 +69,14 @@ KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3), ("ffgemm", 4))
 NET_FLOP_PER_POINT = 8 * 2736
 
 
-def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0):
+def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0, streams=1):
     """Time `steps` maps.  The warm-up maps record every timed kernel; the one
     with the largest total time is the dominant kernel, and inside the timed
     region HIP events bracket only that kernel's launches.  fmg_cycles > 0:
     every solve starts from the full multigrid guess (k V-cycles per coarse
-    level) instead of u = 0."""
+    level) instead of u = 0.  streams = 2: maps alternate between two handles
+    on two streams, so that one map's far field (queued on its stream, the
+    host does not wait for it) runs while the next map is solved."""
     opts = ff.default_options(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles)
     h, coef = ff.setup_workload(w, options=opts)
     from paper_1211_4461_amd import autotune
@@ -108,27 +113,59 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
                         "cache": autotune.load().get(autotune.key(
                             autotune.device_arch(), ff.TUNE_TAIL, w.dim, [w.n - 1] * w.dim, 0, precision))}
     F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
+    lanes = [(h, b, u, F, torch.cuda.current_stream())]
+    if streams == 2:
+        # a second handle on its own stream (default priority): maps alternate
+        # between the two, so one map's far field overlaps the next map's solve
+        s2 = torch.cuda.Stream()
+        with torch.cuda.stream(s2):
+            h2, coef2 = ff.setup_workload(w, options=ff.default_options(precision=precision, ff_precision=ff_precision,
+                                                                        fmg_cycles=fmg_cycles))
+            lanes.append((h2, torch.empty_like(b), torch.empty_like(b), torch.empty_like(F), s2))
+        for tn in (ff.TUNE_FF_GEMM, ff.TUNE_SMOOTH, ff.TUNE_SMOOTH_COARSE, ff.TUNE_PRE, ff.TUNE_TAIL):
+            if ff.mg_tune_variants(h2, tn) > 1:
+                ff.mg_tune_set(h2, ff.mg_tune_get(h, tn), tn)
     info = None
+    last = [F]
+    nstep = [0]
 
     def step():
         nonlocal info
-        ff.mg_rhs_plane_wave(h, w.eta, b)
-        u.zero_()
-        info = ff.mg_solve(h, b, u, tol=w.tol)
-        ff.farfield_map(h, w.eta, u, w.dirs, out=F)
+        h_, b_, u_, F_, s_ = lanes[nstep[0] % len(lanes)]
+        nstep[0] += 1
+        ff.mg_rhs_plane_wave(h_, w.eta, b_)
+        if fmg_cycles == 0:
+            with torch.cuda.stream(s_):
+                u_.zero_()
+        info = ff.mg_solve(h_, b_, u_, tol=w.tol)
+        ff.farfield_map(h_, w.eta, u_, w.dirs, out=F_)   # device output: queued, not waited for
+        last[0] = F_
 
     def read_all():
-        return {name: ff.mg_profile_read(h, kid) for name, kid in KERNELS}
+        out_ = {}
+        for name, kid in KERNELS:
+            tot, cnt = 0.0, 0
+            for ln in lanes:
+                t_, c_ = ff.mg_profile_read(ln[0], kid)
+                tot, cnt = tot + t_, cnt + c_
+            out_[name] = (tot, cnt)
+        return out_
 
-    step()                       # first map: cold launches, not ranked
+    def enable(mask):
+        for ln in lanes:
+            ff.mg_profile_enable(ln[0], mask)
+
+    for _ in range(len(lanes)):
+        step()                   # first map per lane: cold launches, plans, not ranked
     torch.cuda.synchronize()
-    ff.mg_profile_enable(h, 0x1F)
+    enable(0x1F)
     read_all()
-    for _ in range(max(warmup - 1, 1)):
+    for _ in range(max(warmup - 1, 1) * len(lanes)):
         step()
+    torch.cuda.synchronize()
     allk = read_all()
     dominant = max(bytes_per_point, key=lambda k: allk[k][0])
-    ff.mg_profile_enable(h, 1 << dict(KERNELS)[dominant])
+    enable(1 << dict(KERNELS)[dominant])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -136,11 +173,12 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     live = read_all()[dominant]
-    ff.mg_profile_enable(h, 0)
+    enable(0)
     out = {"ms_per_step": 1e3 * dt / steps, "maps_per_s": steps / dt, "cycles": info.cycles, "vcycles": info.vcycles,
-           "rel_residual": info.rel_residual, "conv_factor": info.conv_factor, "F": F.cpu().numpy(),
-           "dominant": dominant, "live": live, "prof": allk, "tune": tune}
-    h.destroy()
+           "rel_residual": info.rel_residual, "conv_factor": info.conv_factor, "F": last[0].cpu().numpy(),
+           "dominant": dominant, "live": live, "prof": allk, "tune": tune, "streams": len(lanes)}
+    for ln in lanes:
+        ln[0].destroy()
     return out
 
 
@@ -422,6 +460,8 @@ def main():
     ap.add_argument("--no-start-forms", action="store_true",
                     help="skip the other starts (u = 0, other full-multigrid cycle counts)")
     ap.add_argument("--zero-start", action="store_true", help="time the solves from u = 0 instead of the FMG start")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="one handle on one stream (no overlap of a map's far field with the next solve)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -466,9 +506,11 @@ def main():
     # both forms start from the full multigrid guess (FMG_K V-cycles per
     # coarse level); the zero-start V-cycle solves are reported beside them
     fk = 0 if args.zero_start else FMG_K
-    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed, fmg_cycles=fk)
+    ns = 1 if args.one_stream else 2
+    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed, fmg_cycles=fk,
+                     streams=ns)
     plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2),
-                                                 args.warmup, bpp_plain, fmg_cycles=fk)
+                                                 args.warmup, bpp_plain, fmg_cycles=fk, streams=ns)
     names = {"pre": "finest-level pre-smoothing: 2 FP32 Jacobi sweeps, residual and full weighting in one pass "
                     "(k_smooth_rr2d<float,*,1,16>)",
              "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1,%d>, "
@@ -503,6 +545,8 @@ def main():
                    "unknowns": N, "angles": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
                    "start": (f"full multigrid: {fk} V(2,2) per coarse level, then V-cycles on the finest grid"
                              if fk else "u = 0"),
+                   "streams": (f"{ns}: consecutive maps alternate between two handles on two streams, one map's "
+                               "far field runs while the next map is solved" if ns == 2 else "1"),
                    "form": "FP32 V-cycles in FP64 refinement + "
                            + {"bf16x6": "split-BF16 (3 parts, 6 products) MFMA far field, FP32 accumulation",
                               "bf16x3": "split-BF16 (2 parts, 3 products) MFMA far field, FP32 accumulation",
@@ -535,16 +579,20 @@ def main():
         # the other starts of the same solve: u = 0 (plain V-cycles) and other
         # numbers of V-cycles per coarse level in the full multigrid start
         fm = {}
-        for prec, ffp_k, ks, tag, bpp in ((ffmg.FP32_IR, ffp, (0, 1, 2, 3), "mixed", bpp_mixed),
-                                           (ffmg.FP64, ffmg.FF_FP64, (0, 1, 2), "plain_fp64", bpp_plain)):
+        forms_m = [(0, 1), (1, ns), (2, ns), (3, ns), (fk, 1)]
+        forms_p = [(0, 1), (1, ns), (2, ns), (fk, 1)]
+        for prec, ffp_k, forms, tag, bpp in ((ffmg.FP32_IR, ffp, forms_m, "mixed", bpp_mixed),
+                                              (ffmg.FP64, ffmg.FF_FP64, forms_p, "plain_fp64", bpp_plain)):
             if tag == "plain_fp64" and plain is None:
                 continue
             ref = mixed if tag == "mixed" else plain
-            for k in ks:
-                if k == fk:
+            for k, nsk in forms:
+                if (k, nsk) == (fk, ns) or (k == 0 and nsk != 1 and fk != 0):
                     continue
-                r = run_path(ffmg, torch, w, prec, ffp_k, max(args.steps // 2, 2), args.warmup, bpp, fmg_cycles=k)
-                fm[f"{tag}_{'zero_start' if k == 0 else f'fmg_k{k}'}"] = {
+                r = run_path(ffmg, torch, w, prec, ffp_k, max(args.steps // 2, 2), args.warmup, bpp, fmg_cycles=k,
+                             streams=nsk)
+                name = f"{tag}_{'zero_start' if k == 0 else f'fmg_k{k}'}" + ("_one_stream" if nsk == 1 and k else "")
+                fm[name] = {
                     "maps_per_s": round(r["maps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
                     "cycles": r["cycles"], "vcycles_finest": r["vcycles"], "rel_residual": r["rel_residual"],
                     "headline_speedup_over_this": round(ref["maps_per_s"] / r["maps_per_s"], 3),

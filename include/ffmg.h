@@ -174,7 +174,11 @@ ffmg_status mg_solve(ffmg_handle *h, const void *b, void *u, double tol, ffmg_so
  * contraction (3D azimuth x polar grids).  eta: HOST double[3]; u: DEVICE
  * complex128[N] (NULL = zero scattered wave: the Born term); F: complex128
  * [n_dirs], HOST or DEVICE memory.  ff_precision selects FP64 MFMA or split
- * BF16 MFMA with FP32 accumulation.  Synchronises. */
+ * BF16 MFMA with FP32 accumulation.  With F in HOST memory the call
+ * synchronises; with F in DEVICE memory it returns once the work is queued
+ * on the handle's stream (later work on that stream sees F; other streams
+ * must wait for it).  The first call for a set of directions synchronises
+ * while it builds the plan. */
 ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs,
                          const double *dirs, void *F);
 

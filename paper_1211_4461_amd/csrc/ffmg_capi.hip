@@ -1097,9 +1097,12 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
         Fd = h->d_F;
     }
     TRY(farfield_enqueue(h, eta, u, n_dirs, dirs, Fd));
-    if (!on_device)
+    if (!on_device) {
         HIPCHK(h, hipMemcpyAsync(F, Fd, (size_t)n_dirs * sizeof(cd), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+    } else {
+        HIPCHK(h, hipGetLastError());   // device output: the work stays queued on the handle's stream
+    }
     return FFMG_OK;
 }
 
