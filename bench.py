@@ -182,6 +182,83 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
     return out
 
 
+def run_concurrent(ff, torch, w, precision, ff_precision, nthreads, maps_per_thread, fmg_cycles):
+    """Maps for several incoming directions in flight: `nthreads` host
+    threads, each with its own handle and stream and its own direction
+    (eta at angle 2 pi i / nthreads), each running the map loop (right-hand
+    side, solve, far field into device memory).  The library's calls release
+    the interpreter lock, so the solves overlap on the GPU: one map's
+    latency-bound coarse levels run beside another's finest-level sweeps.
+    Returns whole-job maps/s over nthreads x maps_per_thread maps."""
+    import threading
+    import numpy as np
+    from paper_1211_4461_amd import autotune
+    lanes = []
+    for i in range(nthreads):
+        s_ = torch.cuda.Stream()
+        with torch.cuda.stream(s_):
+            h_, coef_ = ff.setup_workload(w, options=ff.default_options(precision=precision, ff_precision=ff_precision,
+                                                                        fmg_cycles=fmg_cycles))
+            b_ = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
+            u_ = torch.zeros_like(b_)
+            F_ = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
+        lanes.append((h_, b_, u_, F_, s_, coef_))
+    h0, b0, u0 = lanes[0][0], lanes[0][1], lanes[0][2]
+    ff.mg_rhs_plane_wave(h0, w.eta, b0)
+    torch.cuda.synchronize()
+    for tn in (ff.TUNE_SMOOTH_COARSE, ff.TUNE_SMOOTH, ff.TUNE_PRE, ff.TUNE_TAIL):   # cached by run_path
+        if ff.mg_tune_variants(h0, tn) > 1:
+            autotune.tune_solve(h0, b0, u0, precision, tol=w.tol, tunable=tn)
+    if ff.mg_tune_variants(h0, ff.TUNE_FF_GEMM) > 1:
+        autotune.tune_farfield(h0, w.eta, None, w.dirs, ff_precision)
+    for ln in lanes[1:]:
+        for tn in (ff.TUNE_FF_GEMM, ff.TUNE_SMOOTH, ff.TUNE_SMOOTH_COARSE, ff.TUNE_PRE, ff.TUNE_TAIL):
+            if ff.mg_tune_variants(ln[0], tn) > 1:
+                ff.mg_tune_set(ln[0], ff.mg_tune_get(h0, tn), tn)
+    infos = [None] * nthreads
+    etas = [np.array([math.cos(2 * math.pi * i / nthreads), math.sin(2 * math.pi * i / nthreads), 0.0])
+            for i in range(nthreads)]
+
+    def one_map(i):
+        h_, b_, u_, F_, s_, _ = lanes[i]
+        ff.mg_rhs_plane_wave(h_, etas[i], b_)
+        infos[i] = ff.mg_solve(h_, b_, u_, tol=w.tol)
+        ff.farfield_map(h_, etas[i], u_, w.dirs, out=F_)
+
+    for i in range(nthreads):    # warm-up: plans, first launches
+        one_map(i)
+    torch.cuda.synchronize()
+    go = threading.Barrier(nthreads + 1)
+    errors = []
+
+    def worker(i):
+        try:
+            go.wait()
+            for _ in range(maps_per_thread):
+                one_map(i)
+        except Exception as e:   # reported after the join
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(nthreads)]
+    for t in threads:
+        t.start()
+    torch.cuda.synchronize()
+    go.wait()
+    t0 = time.perf_counter()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    if errors:
+        raise errors[0]
+    for ln in lanes:
+        ln[0].destroy()
+    n = nthreads * maps_per_thread
+    return {"maps": n, "host_threads": nthreads, "incoming_directions": nthreads, "maps_per_s": round(n / dt, 3),
+            "ms_per_map": round(1e3 * dt / n, 3), "cycles": [i.cycles for i in infos],
+            "max_rel_residual": max(i.rel_residual for i in infos)}
+
+
 def run_batched(ff, torch, W, steps):
     """The batched Schroedinger workload: 32 incoming directions x 3 energies
     on seed-drawn 255^2 / 511^2 / 1023^2 grids, all solved in one batched,
@@ -460,6 +537,7 @@ def main():
     ap.add_argument("--no-start-forms", action="store_true",
                     help="skip the other starts (u = 0, other full-multigrid cycle counts)")
     ap.add_argument("--zero-start", action="store_true", help="time the solves from u = 0 instead of the FMG start")
+    ap.add_argument("--no-concurrent", action="store_true", help="skip the many-maps-in-flight form")
     ap.add_argument("--one-stream", action="store_true",
                     help="one handle on one stream (no overlap of a map's far field with the next solve)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
@@ -599,6 +677,13 @@ def main():
                     "farfield_rel_diff_vs_headline_form": float(np.linalg.norm(r["F"] - ref["F"])
                                                                 / np.linalg.norm(ref["F"]))}
         line["start_forms"] = fm
+    if not args.no_concurrent:
+        # maps of several incoming directions in flight at once (host threads,
+        # one handle and stream each); the headline keeps one solve at a time
+        cc = {}
+        for nt in (2, 4):
+            cc[f"threads{nt}"] = run_concurrent(ffmg, torch, w, ffmg.FP32_IR, ffp, nt, max(args.steps // 2, 4), fk)
+        line["concurrent_maps"] = cc
     if not args.no_3d:
         line["gauss_3d"] = run_3d(ffmg, torch, W)
     if not args.no_batch:

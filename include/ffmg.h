@@ -33,7 +33,9 @@
  *
  * Device pointers are HIP device allocations on the current device; the
  * library never frees caller memory.  One handle is used by one host thread
- * and one stream at a time.  No C++ exception crosses this ABI: every call
+ * and one stream at a time; different handles (each with its own stream and
+ * workspace) may be used from different host threads at once, so that the
+ * solves of several maps overlap on the GPU.  No C++ exception crosses this ABI: every call
  * returns a status, and ffmg_last_error() gives the text of the last failure
  * on a handle.
  */

@@ -910,24 +910,24 @@ template <typename T>
 void launch_tail2d(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top, cx<T> *u_top, hipStream_t s,
                    const int *stop)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_tail2d<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr_set = true;
-    }
+    // once per instantiation (a thread-safe static initialisation)
+    static const bool attr_set = [] {
+        (void)hipFuncSetAttribute((const void *)k_tail2d<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        return true;
+    }();
+    (void)attr_set;
     hipLaunchKernelGGL((k_tail2d<T>), dim3(1), dim3(1024), lds_bytes, s, tp, b_top, u_top, stop);
 }
 template <typename T>
 void launch_tail2d_fmg(const TailParams<T> &tp, size_t lds_bytes, const cx<T> *b_top, cx<T> *u_top, int s0, int k,
                        hipStream_t s)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_tail2d_fmg<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr_set = true;
-    }
+    // once per instantiation (a thread-safe static initialisation)
+    static const bool attr_set = [] {
+        (void)hipFuncSetAttribute((const void *)k_tail2d_fmg<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        return true;
+    }();
+    (void)attr_set;
     hipLaunchKernelGGL((k_tail2d_fmg<T>), dim3(1), dim3(1024), lds_bytes, s, tp, b_top, u_top, s0, k);
 }
 template void launch_tail2d_fmg<double>(const TailParams<double> &, size_t, const cd *, cd *, int, int, hipStream_t);
@@ -1039,12 +1039,12 @@ void launch_refine2d_batch(const RefineJob *jobs, const int *tile_job, int ntile
 template <typename T>
 void launch_tail2d_batch(const TailJob<T> *jobs, int njobs, size_t lds_bytes, hipStream_t s)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)k_tail2d_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024);
-        attr_set = true;
-    }
+    // once per instantiation (a thread-safe static initialisation)
+    static const bool attr_set = [] {
+        (void)hipFuncSetAttribute((const void *)k_tail2d_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        return true;
+    }();
+    (void)attr_set;
     if (njobs <= 0) return;
     hipLaunchKernelGGL((k_tail2d_batch<T>), dim3(njobs), dim3(1024), lds_bytes, s, jobs);
 }

@@ -472,12 +472,13 @@ size_t train_lds_bytes() { return sizeof(TrainLds); }
 void launch_train_patches(const float2 *rt, const float2 *kt, const float2 *et, const float2 *Wq, float2 *dW_part,
                           float *loss_part, int count, int border, hipStream_t s)
 {
-    static bool attr = false;
-    if (!attr) {
+    // once (a thread-safe static initialisation)
+    static const bool attr = [] {
         (void)hipFuncSetAttribute((const void *)k_train_patch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)sizeof(TrainLds));
-        attr = true;
-    }
+        return true;
+    }();
+    (void)attr;
     hipLaunchKernelGGL(k_train_patch, dim3(count), dim3(256), sizeof(TrainLds), s, rt, kt, et, Wq, dW_part,
                        loss_part, border);
 }
