@@ -293,7 +293,9 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
  * learned smoother.  FFMG_TUNE_SMOOTH: the tile height of the fused 2D
  * smoothing kernel on the finest level (8, 16 or 4 rows of 64 points for
  * variants 0, 1, 2; the batched path keeps 8); FFMG_TUNE_SMOOTH_COARSE: the
- * same on the coarser levels; one variant each for 3D and tile_config 1.
+ * same on the coarser levels, where the one-pass pre-smoothing follows it
+ * (16 rows with the 16-row variant, else 8); one variant each for 3D and
+ * tile_config 1.
  * FFMG_TUNE_PRE: the pre-smoothing of a fused 2D level with nu1 = 2 as one
  * pass of two sweeps, residual and full weighting (variant 0) or as the
  * two-sweep launch followed by the residual + restriction launch (1); one

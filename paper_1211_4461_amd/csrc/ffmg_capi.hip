@@ -250,7 +250,10 @@ void vcycle_fused2d(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_g
         // two sweeps, residual and full weighting in one pass
         const bool finest = (l == 0);
         int pi = finest ? prof_begin(h, PROF_PRE) : -1;
-        launch_smooth_rr2d<T>(lv.g, LP::P(lv), zero_guess, u, b, LP::q(lv), t, LP::b(lc), h->stream, finest, stop);
+        // coarse levels: 16 rows with the 16-row smoothing tile, else 8
+        const int fh = finest ? 0 : (SMOOTH_TH[h->smooth_coarse_variant] >= 16 ? 16 : 8);
+        launch_smooth_rr2d<T>(lv.g, LP::P(lv), zero_guess, u, b, LP::q(lv), t, LP::b(lc), h->stream, finest, stop,
+                              fh);
         prof_end(h, PROF_PRE, pi);
         cur = t;
     } else {

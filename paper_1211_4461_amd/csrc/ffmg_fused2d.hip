@@ -858,17 +858,16 @@ template void launch_resid_restrict2d<float>(const LevelGeom &, const Stencil<fl
                                              const cf *, cf *, hipStream_t, const int *);
 
 // Fine tile height of the fused pre-smoothing + residual + restriction pass:
-// FP32 16 rows (48 KB of LDS, three blocks per CU), FP64 8 rows (60 KB, two).
+// 8 or 16 rows (FP32 16 rows: 25 KB of LDS; FP64 8 rows: 31 KB).
 template <typename T>
 struct SmoothRR {
     static constexpr int FH = sizeof(T) == 4 ? 16 : 8;
 };
 
-template <typename T>
-void launch_smooth_rr2d(const LevelGeom &g, const Stencil<T> &P, bool zero, const cx<T> *u, const cx<T> *b,
-                        const cx<T> *q, cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop)
+template <typename T, int FH>
+static void launch_smooth_rr2d_fh(const LevelGeom &g, const Stencil<T> &P, bool zero, const cx<T> *u, const cx<T> *b,
+                                  const cx<T> *q, cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop)
 {
-    constexpr int FH = SmoothRR<T>::FH;
     const int tx = (g.m[0] + FTX - 1) / FTX;
     const int nb = tx * ((g.m[1] + FH - 1) / FH);
 #define FFMG_SRR(Z, TG) \
@@ -882,10 +881,19 @@ void launch_smooth_rr2d(const LevelGeom &g, const Stencil<T> &P, bool zero, cons
     }
 #undef FFMG_SRR
 }
+
+template <typename T>
+void launch_smooth_rr2d(const LevelGeom &g, const Stencil<T> &P, bool zero, const cx<T> *u, const cx<T> *b,
+                        const cx<T> *q, cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop, int fh)
+{
+    if (fh <= 0) fh = SmoothRR<T>::FH;
+    if (fh == 16) launch_smooth_rr2d_fh<T, 16>(g, P, zero, u, b, q, out, bc, s, finest, stop);
+    else launch_smooth_rr2d_fh<T, 8>(g, P, zero, u, b, q, out, bc, s, finest, stop);
+}
 template void launch_smooth_rr2d<double>(const LevelGeom &, const Stencil<double> &, bool, const cd *, const cd *,
-                                         const cd *, cd *, cd *, hipStream_t, bool, const int *);
+                                         const cd *, cd *, cd *, hipStream_t, bool, const int *, int);
 template void launch_smooth_rr2d<float>(const LevelGeom &, const Stencil<float> &, bool, const cf *, const cf *,
-                                        const cf *, cf *, cf *, hipStream_t, bool, const int *);
+                                        const cf *, cf *, cf *, hipStream_t, bool, const int *, int);
 
 void launch_refine2d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *u_out, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t st,

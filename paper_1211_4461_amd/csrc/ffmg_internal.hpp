@@ -145,10 +145,11 @@ void launch_resid_restrict2d(const LevelGeom &g, const Stencil<T> &P, const cx<T
                              const cx<T> *q, cx<T> *bc, hipStream_t s, const int *stop);
 // Two Jacobi sweeps (zero: from u = 0, u not read) into out, the residual of
 // the smoothed iterate and its full weighting into bc, in one pass (the same
-// bits as launch_smooth2d with two sweeps followed by launch_resid_restrict2d).
+// bits as launch_smooth2d with two sweeps followed by launch_resid_restrict2d);
+// fh: tile height, 8 or 16 rows (0: 16 for FP32, 8 for FP64).
 template <typename T>
 void launch_smooth_rr2d(const LevelGeom &g, const Stencil<T> &P, bool zero, const cx<T> *u, const cx<T> *b,
-                        const cx<T> *q, cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop);
+                        const cx<T> *q, cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop, int fh);
 void launch_refine2d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *u_out, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t st,
                      const int *stop);
