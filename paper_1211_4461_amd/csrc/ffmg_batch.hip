@@ -94,7 +94,7 @@ namespace {
 
 // Host-side lists of the level launches of one FP32 V-cycle; uploaded once.
 struct LaunchRec {
-    int kind;            // 0 smooth, 1 resid+restrict, 2 tail
+    int kind;            // 0 smooth, 1 resid+restrict, 2 tail, 3 one-pass pre-smoothing + resid + restrict
     int ns = 0;          // smooth: sweeps in this launch
     bool zero = false, prol = false;
     size_t job_off = 0;  // index into the typed job array
@@ -105,6 +105,7 @@ struct LaunchRec {
 struct Plan {
     std::vector<SmoothJob<float>> sj;
     std::vector<RRJob<float>> rj;
+    std::vector<SRRJob<float>> srj;
     std::vector<TailJob<float>> tj;
     std::vector<int> tile_job;
     std::vector<LaunchRec> recs;   // one inner V-cycle with the finest guess nonzero
@@ -155,6 +156,42 @@ void add_smooth(Plan &pl, std::vector<LaunchRec> &out, Batch &B, const std::vect
     out.push_back(r);
 }
 
+// Append one one-pass pre-smoothing launch (two sweeps u32 -> t32, residual
+// and restriction into b32[l + 1]) over the (instance, level) entries.
+void add_srr(Plan &pl, std::vector<LaunchRec> &out, Batch &B, const std::vector<std::pair<int, int>> &es, bool zero)
+{
+    if (es.empty()) return;
+    LaunchRec r;
+    r.kind = 3;
+    r.zero = zero;
+    r.job_off = pl.srj.size();
+    r.tj_off = pl.tile_job.size();
+    int tot = 0;
+    for (const auto &e : es) {
+        BatchInst &I = B.inst[e.first];
+        const int l = e.second;
+        Level &lv = I.op->L[l];
+        int tx;
+        int nt = smooth_rr2d_tiles<float>(lv.g, &tx);
+        SRRJob<float> j;
+        j.u = I.u32[l];
+        j.b = I.b32[l];
+        j.q = lv.q32;
+        j.out = I.t32[l];
+        j.bc = I.b32[l + 1];
+        j.P = lv.P32;
+        j.tiles_x = tx;
+        j.tile0 = tot;
+        j.stop = &I.ctl->done;
+        int jid = (int)(pl.srj.size() - r.job_off);
+        pl.srj.push_back(j);
+        for (int t = 0; t < nt; ++t) pl.tile_job.push_back(jid);
+        tot += nt;
+    }
+    r.ntiles = tot;
+    out.push_back(r);
+}
+
 // The launches of one inner V-cycle (c = 0: zero guess on the finest level).
 void build_cycle(Plan &pl, std::vector<LaunchRec> &out, Batch &B, bool first)
 {
@@ -162,6 +199,18 @@ void build_cycle(Plan &pl, std::vector<LaunchRec> &out, Batch &B, bool first)
     auto level_of = [&](int i, int s) { return s - (Dmax - B.inst[i].D); };   // < 0: not active
     // down-sweep
     for (int s = 0; s < Dmax; ++s) {
+        if (B.nu1 == 2) {
+            // two sweeps, residual and restriction in one pass: u -> t, b_c
+            std::vector<std::pair<int, int>> ez, enz;
+            for (int i = 0; i < n; ++i) {
+                const int l = level_of(i, s);
+                if (l < 0) continue;
+                ((l > 0 || first) ? ez : enz).push_back({i, l});
+            }
+            add_srr(pl, out, B, ez, true);
+            add_srr(pl, out, B, enz, false);
+            continue;
+        }
         // pre-smoothing chain: nu1 sweeps, two per launch, u -> t (tmp r)
         const int nk = (B.nu1 + 1) / 2;
         int left = B.nu1;
@@ -262,10 +311,12 @@ hipError_t upload(Batch &B, J **d, const std::vector<J> &h)
 }
 
 void enqueue_cycle(const Batch &B, const std::vector<LaunchRec> &recs, const SmoothJob<float> *sj,
-                   const RRJob<float> *rj, const TailJob<float> *tj, const int *tile_job)
+                   const RRJob<float> *rj, const TailJob<float> *tj, const SRRJob<float> *srj, const int *tile_job)
 {
     for (const LaunchRec &r : recs) {
-        if (r.kind == 0)
+        if (r.kind == 3)
+            launch_smooth_rr2d_batch<float>(r.zero, srj + r.job_off, tile_job + r.tj_off, r.ntiles, B.stream);
+        else if (r.kind == 0)
             launch_smooth2d_batch<float>(r.ns, r.zero, r.prol, sj + r.job_off, tile_job + r.tj_off, r.ntiles,
                                          B.stream);
         else if (r.kind == 1)
@@ -366,10 +417,12 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
     SmoothJob<float> *d_sj = nullptr;
     RRJob<float> *d_rj = nullptr;
     TailJob<float> *d_tj = nullptr;
+    SRRJob<float> *d_srj = nullptr;
     int *d_tile_job = nullptr;
     BCHK(upload(B, &d_sj, pl.sj));
     BCHK(upload(B, &d_rj, pl.rj));
     BCHK(upload(B, &d_tj, pl.tj));
+    BCHK(upload(B, &d_srj, pl.srj));
     BCHK(upload(B, &d_tile_job, pl.tile_job));
     BCHK(upload(B, &B.d_ctl0, c0));
     BCHK(upload(B, &B.d_ctl, c1));
@@ -393,7 +446,7 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
     BCHK(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
     for (int step = 0; step < 2; ++step) {
         for (int c = 0; c < B.inner; ++c)
-            enqueue_cycle(B, c == 0 ? pl.recs0 : pl.recs, d_sj, d_rj, d_tj, d_tile_job);
+            enqueue_cycle(B, c == 0 ? pl.recs0 : pl.recs, d_sj, d_rj, d_tj, d_srj, d_tile_job);
         launch_refine2d_batch(step == 0 ? B.d_refA : B.d_refB, B.d_ref_tile_job, B.ref_ntiles, B.stream);
         launch_ctl_update_batch(B.d_ctl, count, B.stream);
     }

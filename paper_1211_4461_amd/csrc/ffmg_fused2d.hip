@@ -959,6 +959,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     smooth2d_body<T, NS, ZERO, PROL, SMOOTH_TH_BATCH>(J.u, J.ec, J.b, J.q, J.out, J.P, J.tiles_x, t - J.tile0);
 }
 
+// one-pass pre-smoothing tile height of the batched path
+constexpr int SMOOTH_RR_BATCH = 16;
+
+template <typename T, bool ZERO>
+__global__ __launch_bounds__(256) void k_smooth_rr2d_batch(const SRRJob<T> *__restrict__ jobs,
+                                                           const int *__restrict__ tile_job)
+{
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const SRRJob<T> J = jobs[tile_job[t]];
+    if (J.stop && *J.stop) return;
+    smooth_rr2d_body<T, ZERO, SMOOTH_RR_BATCH>(J.u, J.b, J.q, J.out, J.bc, J.P, J.tiles_x, t - J.tile0);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict2d_batch(const RRJob<T> *__restrict__ jobs,
                                                                 const int *__restrict__ tile_job)
@@ -998,6 +1011,15 @@ int smooth2d_tiles(const LevelGeom &g, int *tiles_x)
 template int smooth2d_tiles<double>(const LevelGeom &, int *);
 template int smooth2d_tiles<float>(const LevelGeom &, int *);
 
+template <typename T>
+int smooth_rr2d_tiles(const LevelGeom &g, int *tiles_x)
+{
+    *tiles_x = (g.m[0] + FTX - 1) / FTX;
+    return *tiles_x * ((g.m[1] + SMOOTH_RR_BATCH - 1) / SMOOTH_RR_BATCH);
+}
+template int smooth_rr2d_tiles<double>(const LevelGeom &, int *);
+template int smooth_rr2d_tiles<float>(const LevelGeom &, int *);
+
 int resid_restrict2d_tiles(const LevelGeom &g, int *ctiles_x)
 {
     int mxc = (g.m[0] - 1) / 2, myc = (g.m[1] - 1) / 2;
@@ -1028,6 +1050,18 @@ void launch_smooth2d_batch(int nsweeps, bool zero, bool prol, const SmoothJob<T>
 template void launch_smooth2d_batch<float>(int, bool, bool, const SmoothJob<float> *, const int *, int, hipStream_t);
 template void launch_smooth2d_batch<double>(int, bool, bool, const SmoothJob<double> *, const int *, int,
                                             hipStream_t);
+
+template <typename T>
+void launch_smooth_rr2d_batch(bool zero, const SRRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s)
+{
+    if (ntiles <= 0) return;
+    if (zero)
+        hipLaunchKernelGGL((k_smooth_rr2d_batch<T, true>), dim3(ntiles), dim3(256), 0, s, jobs, tile_job);
+    else
+        hipLaunchKernelGGL((k_smooth_rr2d_batch<T, false>), dim3(ntiles), dim3(256), 0, s, jobs, tile_job);
+}
+template void launch_smooth_rr2d_batch<float>(bool, const SRRJob<float> *, const int *, int, hipStream_t);
+template void launch_smooth_rr2d_batch<double>(bool, const SRRJob<double> *, const int *, int, hipStream_t);
 
 template <typename T>
 void launch_resid_restrict2d_batch(const RRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s)

@@ -205,6 +205,14 @@ struct RRJob {
     int ctiles_x, tile0;
     const int *stop;
 };
+template <typename T>
+struct SRRJob {             // one-pass pre-smoothing + residual + restriction
+    const cx<T> *u, *b, *q;
+    cx<T> *out, *bc;
+    Stencil<T> P;
+    int tiles_x, tile0;
+    const int *stop;
+};
 struct RefineJob {
     const cd *u;
     const cf *d;
@@ -228,10 +236,14 @@ struct TailJob {
 template <typename T>
 int smooth2d_tiles(const LevelGeom &g, int *tiles_x);
 int resid_restrict2d_tiles(const LevelGeom &g, int *ctiles_x);
+template <typename T>
+int smooth_rr2d_tiles(const LevelGeom &g, int *tiles_x);
 int refine2d_tiles(const LevelGeom &g, int *tiles_x);
 template <typename T>
 void launch_smooth2d_batch(int nsweeps, bool zero, bool prol, const SmoothJob<T> *jobs, const int *tile_job,
                            int ntiles, hipStream_t s);
+template <typename T>
+void launch_smooth_rr2d_batch(bool zero, const SRRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s);
 template <typename T>
 void launch_resid_restrict2d_batch(const RRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s);
 void launch_refine2d_batch(const RefineJob *jobs, const int *tile_job, int ntiles, hipStream_t s);
