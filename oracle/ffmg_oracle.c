@@ -146,6 +146,85 @@ void or_jacobi(int dim, const long *m, const double *h, double gamma,
             }
 }
 
+/* One GMRES(m) smoothing step from the guess u, in place (Sec. 3.3: GMRES(m),
+ * m = 2 or 3, as the smoother that replaces weighted Jacobi and keeps the
+ * V-cycle stable at rotation angles near 10 degrees).  It is one restart
+ * cycle of GMRES: with r0 = b - A u and the Krylov space
+ * K_m = span{r0, A r0, ..., A^{m-1} r0}, u is replaced by the u + z, z in
+ * K_m, of least residual norm.  The basis is built by Arnoldi's process with
+ * modified Gram-Schmidt and the Hermitian inner product sum conj(x) y; the
+ * (m+1) x m least-squares problem is reduced by complex Givens rotations.
+ * A breakdown (the Krylov space is invariant) ends the process early; the
+ * least-squares solution then solves A u = b. */
+void or_gmres(int dim, const long *m, const double *h, double gamma,
+              const cplx *kappa, const cplx *b, cplx *u, int mk)
+{
+    if (mk > 16) mk = 16;                                    /* the small arrays below */
+    long N = npts(dim, m);
+    cplx *V = malloc((size_t)(mk + 1) * (size_t)N * sizeof(cplx));
+    cplx *w = malloc((size_t)N * sizeof(cplx));
+    cplx H[17][16], g[17], cs[16], sn[16];
+    memset(H, 0, sizeof H);
+    or_residual(dim, m, h, gamma, kappa, b, u, V);          /* V_0 = r0 */
+    double beta = 0.0;
+    for (long j = 0; j < N; ++j) beta += creal(V[j]) * creal(V[j]) + cimag(V[j]) * cimag(V[j]);
+    beta = sqrt(beta);
+    if (beta == 0.0 || mk < 1) { free(V); free(w); return; }
+    for (long j = 0; j < N; ++j) V[j] /= beta;
+    int k = 0;
+    for (int jj = 0; jj < mk; ++jj) {
+        or_apply(dim, m, h, gamma, kappa, V + (size_t)jj * N, w);   /* w = A v_j */
+        for (int i = 0; i <= jj; ++i) {                              /* MGS */
+            const cplx *vi = V + (size_t)i * N;
+            cplx d = 0.0;
+            for (long j = 0; j < N; ++j) d += conj(vi[j]) * w[j];
+            H[i][jj] = d;
+            for (long j = 0; j < N; ++j) w[j] -= d * vi[j];
+        }
+        double nw = 0.0;
+        for (long j = 0; j < N; ++j) nw += creal(w[j]) * creal(w[j]) + cimag(w[j]) * cimag(w[j]);
+        nw = sqrt(nw);
+        H[jj + 1][jj] = nw;
+        k = jj + 1;
+        if (nw == 0.0) break;                                        /* invariant subspace */
+        cplx *vn = V + (size_t)(jj + 1) * N;
+        for (long j = 0; j < N; ++j) vn[j] = w[j] / nw;
+    }
+    /* least squares min || beta e1 - H y || by Givens rotations */
+    for (int i = 0; i <= k; ++i) g[i] = 0.0;
+    g[0] = beta;
+    for (int j = 0; j < k; ++j) {
+        for (int i = 0; i < j; ++i) {                                /* earlier rotations */
+            cplx t = cs[i] * H[i][j] + sn[i] * H[i + 1][j];
+            H[i + 1][j] = -conj(sn[i]) * H[i][j] + cs[i] * H[i + 1][j];
+            H[i][j] = t;
+        }
+        cplx a = H[j][j], c = H[j + 1][j];
+        double r = sqrt(creal(a) * creal(a) + cimag(a) * cimag(a) + creal(c) * creal(c) + cimag(c) * cimag(c));
+        if (r == 0.0) { cs[j] = 1.0; sn[j] = 0.0; continue; }
+        double aa = cabs(a);
+        if (aa == 0.0) { cs[j] = 0.0; sn[j] = conj(c) / r; }
+        else { cs[j] = aa / r; sn[j] = (a / aa) * conj(c) / r; }
+        H[j][j] = cs[j] * a + sn[j] * c;
+        H[j + 1][j] = 0.0;
+        cplx t = cs[j] * g[j] + sn[j] * g[j + 1];
+        g[j + 1] = -conj(sn[j]) * g[j] + cs[j] * g[j + 1];
+        g[j] = t;
+    }
+    cplx y[16];
+    for (int i = k - 1; i >= 0; --i) {                               /* back substitution */
+        cplx t = g[i];
+        for (int j = i + 1; j < k; ++j) t -= H[i][j] * y[j];
+        y[i] = (H[i][i] != 0.0) ? t / H[i][i] : 0.0;
+    }
+    for (int j = 0; j < k; ++j) {
+        const cplx *vj = V + (size_t)j * N;
+        for (long p = 0; p < N; ++p) u[p] += y[j] * vj[p];
+    }
+    free(V);
+    free(w);
+}
+
 /* Full-weighting restriction: 1D weights (1/4, 1/2, 1/4) at fine
  * 2I-1, 2I, 2I+1, tensorised over the axes (Sec. 4: full weighting).
  * mf = fine interior counts (odd: n_f - 1); coarse counts (mf-1)/2. */
@@ -314,6 +393,7 @@ void or_lu_solve(long N, const cplx *LU, const long *piv, cplx *x)
 
 typedef struct {
     int dim, nlev, nu1, nu2;
+    int smoother, krylov_m;   /* 0: omega-Jacobi; 1: GMRES(krylov_m) */
     double gamma, omega;
     long m[OR_MAXLEV][3];
     double h[OR_MAXLEV][3];
@@ -389,9 +469,22 @@ void or_mg_kappa(void *p, int l, cplx *out)
     memcpy(out, g->kappa[l], (size_t)npts(g->dim, g->m[l]) * sizeof(cplx));
 }
 
+/* Choose the smoother of every level below the coarsest: omega-Jacobi
+ * (smoother 0, the default) or GMRES(m) steps (smoother 1). */
+void or_mg_set_smoother(void *p, int smoother, int m)
+{
+    or_mg *g = p;
+    g->smoother = smoother;
+    g->krylov_m = m;
+}
+
 static void smooth(or_mg *g, int l, const cplx *b, cplx *u, int nu)
 {
     long N = npts(g->dim, g->m[l]);
+    if (g->smoother == 1) {
+        for (int s = 0; s < nu; ++s) or_gmres(g->dim, g->m[l], g->h[l], g->gamma, g->kappa[l], b, u, g->krylov_m);
+        return;
+    }
     for (int s = 0; s < nu; ++s) {
         or_jacobi(g->dim, g->m[l], g->h[l], g->gamma, g->kappa[l], b, u, g->omega, g->t[l]);
         memcpy(u, g->t[l], (size_t)N * sizeof(cplx));

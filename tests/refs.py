@@ -82,25 +82,49 @@ def inject_index(mf):
     return flat.ravel()
 
 
-def dense_vcycle(m, h, gamma, kappa, b, u, nu1, nu2, omega, coarsest_n=8):
-    """One V(nu1, nu2) cycle written with dense matrices."""
+def dense_gmres_step(A, b, u, m):
+    """The least-residual update of u in the Krylov space of its residual,
+    span{r, A r, ..., A^{m-1} r}, by a dense least-squares solve over the
+    explicit (column-normalised) power basis."""
+    r = b - A @ u
+    nr = np.linalg.norm(r)
+    if nr == 0.0:
+        return u
+    K = [r / nr]
+    for _ in range(1, m):
+        v = A @ K[-1]
+        K.append(v / np.linalg.norm(v))
+    K = np.stack(K, 1)
+    c, *_ = np.linalg.lstsq(A @ K, r, rcond=None)
+    return u + K @ c
+
+
+def dense_vcycle(m, h, gamma, kappa, b, u, nu1, nu2, omega, coarsest_n=8, krylov_m=0):
+    """One V(nu1, nu2) cycle written with dense matrices (krylov_m > 0:
+    GMRES(krylov_m) smoothing steps instead of omega-Jacobi sweeps)."""
     m = list(m)
     A = kron_operator(m, h, gamma, kappa).toarray()
     if min(mk + 1 for mk in m) <= coarsest_n:
         return np.linalg.solve(A, b)
     D = np.diag(A)
+
+    def smooth(u):
+        if krylov_m:
+            return dense_gmres_step(A, b, u, krylov_m)
+        return u + omega * (b - A @ u) / D
+
     for _ in range(nu1):
-        u = u + omega * (b - A @ u) / D
+        u = smooth(u)
     r = b - A @ u
     R = fw(m)
     bc = R @ r
     mc = [(mk - 1) // 2 for mk in m]
     kc = np.asarray(kappa).ravel()[inject_index(m)]
     ec = dense_vcycle(mc, [2 * hk for hk in h], gamma, kc, bc, np.zeros_like(bc),
-                      nu1, nu2, omega, coarsest_n)
+                      nu1, nu2, omega, coarsest_n, krylov_m)
     u = u + prolong(m) @ ec
     for _ in range(nu2):
-        u = u + omega * (b - A @ u) / D
+        u = smooth(u)
     return u
 
 

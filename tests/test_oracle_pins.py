@@ -207,6 +207,73 @@ def test_fmg_reaches_discretization_accuracy(orc):
     assert st0 == 0 and st1 == 0 and k_fmg < k_zero, (k_fmg, k_zero)
 
 
+@pytest.mark.parametrize("dim,n,m", [(2, (16, 16), 1), (2, (16, 32), 2), (2, (16, 16), 3), (3, (8, 8, 16), 3)])
+def test_gmres_step_is_least_squares_on_krylov_space(orc, dim, n, m):
+    """One GMRES(m) smoothing step (Sec. 3.3) is the least-residual update in
+    span{r, A r, ..., A^{m-1} r}: a dense least-squares solve over the
+    explicit power basis gives the same iterate."""
+    g = orc.Grid(dim, n, [-4.0] * dim, [4.0] * dim)
+    r = rng(6)
+    kappa = 4.0 * (1.0 + 0.5 * r.random(g.shape)) + 0.3j * r.random(g.shape)
+    b, u = crand(r, g.shape), crand(r, g.shape)
+    A = refs.kron_operator(list(g.m), list(g.h), G30, kappa).toarray()
+    got = orc.gmres_step(g, G30, kappa, b, u, m)
+    ref = refs.dense_gmres_step(A, b.ravel(), u.ravel(), m).reshape(g.shape)
+    assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref - u)
+    # the residual falls monotonically with m (nested Krylov spaces)
+    if m > 1:
+        prev = orc.gmres_step(g, G30, kappa, b, u, m - 1)
+        assert np.linalg.norm(b.ravel() - A @ got.ravel()) < np.linalg.norm(b.ravel() - A @ prev.ravel())
+
+
+def test_gmres_with_full_krylov_space_solves_exactly(orc):
+    """m = N (9 unknowns): the Krylov space holds the error, GMRES solves."""
+    g = orc.Grid(2, (4, 4), [-1.0, -1.0], [1.0, 1.0])
+    kappa = np.full(g.shape, 2.0 + 0.1j)
+    b = crand(rng(7), g.shape)
+    u = orc.gmres_step(g, G30, kappa, b, np.zeros(g.shape, dtype=np.complex128), 9)
+    A = refs.kron_operator(list(g.m), list(g.h), G30, kappa).toarray()
+    assert np.linalg.norm(b.ravel() - A @ u.ravel()) < 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("dim,n,nu,m", [(2, (32, 32), (1, 1), 3), (2, (32, 64), (1, 2), 2), (3, (16, 16, 16), (1, 1), 3)])
+def test_gmres_vcycle_matches_dense_matrix_cycle(orc, dim, n, nu, m):
+    """The V-cycle with GMRES(m) smoothing steps on every level above the
+    coarsest, written with dense Kronecker matrices and least-squares
+    smoothing steps."""
+    L = [4.0] * dim
+    g = orc.Grid(dim, n, [-l for l in L], L)
+    r = rng(8)
+    kappa = 4.0 * (1.0 + 0.5 * r.random(g.shape)) + 0.3j * r.random(g.shape)
+    b, u0 = crand(r, g.shape), crand(r, g.shape)
+    mg = orc.Multigrid(g, G30, kappa, nu1=nu[0], nu2=nu[1], smoother="gmres", krylov_m=m)
+    got = mg.vcycle(b, u0)
+    ref = refs.dense_vcycle(list(g.m), list(g.h), G30, kappa.ravel(), b.ravel(), u0.ravel(), nu[0], nu[1], 0.8,
+                            krylov_m=m).reshape(g.shape)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_gmres_smoother_converges_below_the_jacobi_angle(orc):
+    """Sec. 3.3: weighted Jacobi needs a rotation angle of about 13 degrees
+    or more; GMRES(3) smoothing keeps the V-cycle convergent at 10 degrees.
+    At 30 degrees V(1,1) with GMRES(3) needs fewer cycles than V(2,2) with
+    Jacobi."""
+    w = W.small_2d(n=128)
+    g = orc.Grid(2, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    res = {}
+    for deg in (30, 10):
+        gam = math.radians(deg)
+        b = orc.rhs_plane_wave(g, gam, k0, q, w.eta)
+        for sm, nu in (("jacobi", (2, 2)), ("gmres", (1, 1))):
+            mg = orc.Multigrid(g, gam, kappa, nu1=nu[0], nu2=nu[1], smoother=sm, krylov_m=3)
+            _, st, k, _ = mg.solve(b, tol=1e-10, max_cycles=100)
+            res[(deg, sm)] = (st, k)
+    assert res[(10, "jacobi")][0] == orc.ENOCONV
+    assert res[(10, "gmres")][0] == orc.OK and res[(10, "gmres")][1] <= 30
+    assert res[(30, "gmres")][0] == orc.OK and res[(30, "gmres")][1] < res[(30, "jacobi")][1]
+
+
 def test_coarse_kappa_is_injected(orc):
     g = orc.Grid(2, 32, -4, 4)
     r = rng(5)
