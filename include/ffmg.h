@@ -60,7 +60,7 @@ typedef enum {
 
 typedef enum { FFMG_HELMHOLTZ = 0, FFMG_SCHRODINGER = 1 } ffmg_kind;
 typedef enum { FFMG_FP64 = 0, FFMG_FP32_IR = 1 } ffmg_precision;
-typedef enum { FFMG_SMOOTH_JACOBI = 0, FFMG_SMOOTH_LEARNED = 1 } ffmg_smoother;
+typedef enum { FFMG_SMOOTH_JACOBI = 0, FFMG_SMOOTH_LEARNED = 1, FFMG_SMOOTH_GMRES = 2 } ffmg_smoother;
 typedef enum { FFMG_FF_FP64 = 0, FFMG_FF_BF16X3 = 1, FFMG_FF_BF16X6 = 2 } ffmg_ff_precision;
 
 /* The scattering problem (Sec. 2.1 Helmholtz; Sec. 5 Schroedinger). */
@@ -86,7 +86,9 @@ typedef struct ffmg_options {
     int coarsest_n;       /* intervals per axis on the coarsest grid (>= 4)    */
     int max_cycles;       /* mg_solve cycle limit (>= 1)                       */
     int precision;        /* ffmg_precision                                    */
-    int smoother;         /* ffmg_smoother                                     */
+    int smoother;         /* ffmg_smoother: weighted Jacobi (Sec. 4), the
+                             learned network, or GMRES(krylov_m) steps
+                             (Sec. 3.3) on every level above the coarsest    */
     const float *smoother_weights; /* HOST, learned smoother parameters, or NULL */
     int ff_precision;     /* ffmg_ff_precision                                 */
     int tile_config;      /* 0 = fused kernels (default; 2D: two sweeps per
@@ -104,6 +106,8 @@ typedef struct ffmg_options {
                              the network (0 = the finest level only; levels of
                              the LDS tail never do); the others use weighted
                              Jacobi                                            */
+    int krylov_m;         /* FFMG_SMOOTH_GMRES: the m of GMRES(m), 1..8
+                             (0 = 3); nu1 / nu2 then count GMRES(m) steps    */
     int fmg_cycles;       /* mg_solve starts from the full multigrid guess of
                              mg_fmg with this many V-cycles per coarse level
                              (0 = off: start from the caller's u)            */
@@ -265,6 +269,15 @@ ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out)
  * with Jacobi (info.fell_back = 1). */
 ffmg_status mg_learned_smooth(ffmg_handle *h, const void *b, void *u);
 double mg_jacobi_factor(const ffmg_handle *h);
+
+/* One GMRES(m) smoothing step on the finest level, in place, FP64 (Sec. 3.3:
+ * the Krylov smoother that keeps the V-cycle stable near 10 degrees): with
+ * r0 = b - A u, u becomes the u + z, z in span{r0, A r0, ..., A^{m-1} r0}, of
+ * least residual norm (one restart cycle of GMRES, m = options.krylov_m).
+ * b: DEVICE complex128[N], read; u: DEVICE complex128[N], updated.  EINVAL
+ * unless the handle was set up with smoother FFMG_SMOOTH_GMRES and has more
+ * than one level.  Queued on the handle's stream. */
+ffmg_status mg_gmres_smooth(ffmg_handle *h, const void *b, void *u);
 
 /* ||b - A u||_2 (FP64 accumulation) into *rnorm (host). */
 ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, double *rnorm);

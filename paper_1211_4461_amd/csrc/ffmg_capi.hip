@@ -129,6 +129,7 @@ struct LvlPtr<double> {
     static cd *r(Level &l) { return l.r; }
     static cd *t(Level &l) { return l.t; }
     static const Stencil<double> &P(Level &l) { return l.P64; }
+    static cd *gz(Level &l) { return l.gz; }
     static const TailParams<double> &tail(ffmg_handle *h) { return h->tail64; }
     static size_t tail_lds(ffmg_handle *h) { return h->tail_lds[0]; }
 };
@@ -140,6 +141,7 @@ struct LvlPtr<float> {
     static cf *r(Level &l) { return l.r32; }
     static cf *t(Level &l) { return l.t32; }
     static const Stencil<float> &P(Level &l) { return l.P32; }
+    static cf *gz(Level &l) { return l.gz32; }
     static const TailParams<float> &tail(ffmg_handle *h) { return h->tail32; }
     static size_t tail_lds(ffmg_handle *h) { return h->tail_lds[1]; }
 };
@@ -318,9 +320,11 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
         if (fabs(hx - hy) > 1e-12 * hx) return fail(tmp, FFMG_EINVAL, "the learned smoother needs square cells");
         for (int k = 0; k < 2 * FFMG_NET_WEIGHTS; ++k)
             if (!isfinite(o->smoother_weights[k])) return fail(tmp, FFMG_ENAN, "smoother weight %d is not finite", k);
-    } else if (o->smoother != FFMG_SMOOTH_JACOBI) {
+    } else if (o->smoother != FFMG_SMOOTH_JACOBI && o->smoother != FFMG_SMOOTH_GMRES) {
         return fail(tmp, FFMG_EINVAL, "unknown smoother %d", o->smoother);
     }
+    if (o->krylov_m < 0 || o->krylov_m > GMRES_MAX_M)
+        return fail(tmp, FFMG_EINVAL, "krylov_m must be in [0, %d]", GMRES_MAX_M);
     if (o->ff_precision != FFMG_FF_FP64 && o->ff_precision != FFMG_FF_BF16X3 && o->ff_precision != FFMG_FF_BF16X6)
         return fail(tmp, FFMG_EINVAL, "unknown far-field precision %d", o->ff_precision);
     if (o->tile_config < 0 || o->tile_config > 2) return fail(tmp, FFMG_EINVAL, "unknown tile_config");
@@ -350,7 +354,7 @@ void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
     tp = TailParams<T>{};
     lds = 0;
     const int nl = (int)h->L.size();
-    if (h->prob.dim != 2 || h->opt.tile_config != TILE_FUSED || nl < 3) return;
+    if (h->prob.dim != 2 || h->opt.tile_config != TILE_FUSED || nl < 3 || h->opt.smoother == FFMG_SMOOTH_GMRES) return;
     const size_t budget = 144 * 1024;
     size_t bytes = 0;
     int top = nl;   // first tail level
@@ -467,6 +471,11 @@ ffmg_status setup_impl(ffmg_handle *h)
             TRY(dalloc(h, &lv.u, N * sizeof(cd)));
             TRY(dalloc(h, &lv.b, N * sizeof(cd)));
         }
+        if (h->opt.smoother == FFMG_SMOOTH_GMRES && l + 1 < h->L.size()) {
+            const int mk = h->opt.krylov_m > 0 ? h->opt.krylov_m : 3;
+            TRY(dalloc(h, &lv.gz, (size_t)(mk + 1) * N * sizeof(cd)));
+            if (ir) TRY(dalloc(h, &lv.gz32, (size_t)(mk + 1) * N * sizeof(cf)));
+        }
         if (ir) {
             TRY(dalloc(h, &lv.q32, N * sizeof(cf)));
             TRY(dalloc(h, &lv.u32, N * sizeof(cf)));
@@ -476,6 +485,11 @@ ffmg_status setup_impl(ffmg_handle *h)
         }
     }
     h->nparts = (int)maxparts;
+    if (h->opt.smoother == FFMG_SMOOTH_GMRES) {
+        h->krylov_m = h->opt.krylov_m > 0 ? h->opt.krylov_m : 3;
+        TRY(dalloc(h, &h->d_gm, GM_S * sizeof(double)));
+        TRY(dalloc(h, &h->d_gm_parts, GM_PARTS * sizeof(double)));
+    }
     TRY(dalloc(h, &h->d_parts, maxparts * sizeof(double)));
     TRY(dalloc(h, &h->d_scalar, sizeof(double)));
     TRY(dalloc(h, &h->d_info, sizeof(int)));
@@ -587,6 +601,36 @@ static void vcycle_learned(ffmg_handle *h, int l, const cd *b, cd *u, bool zero_
     for (int s = 0; s < nu_post(h, l); ++s) learned_step(h, l, b, u, stop);
 }
 
+// One level of a V-cycle with GMRES(m) smoothing steps (Sec. 3.3): nu1
+// steps, residual + restriction, the coarse correction, interpolation, nu2
+// steps.
+template <typename T>
+static void vcycle_gmres(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop)
+{
+    using LP = LvlPtr<T>;
+    Level &lv = h->L[l];
+    Level &lc = h->L[l + 1];
+    const int nu1 = nu_pre(h, l), nu2 = nu_post(h, l);
+    bool zero = zero_guess;
+    if (nu1 == 0 && zero) launch_zero<T>(u, lv.g.N(), h->stream, stop);
+    for (int s = 0; s < nu1; ++s, zero = false)
+        launch_gmres_step<T>(lv.g, LP::P(lv), b, LP::q(lv), u, zero, h->krylov_m, LP::gz(lv), h->d_gm, h->d_gm_parts,
+                             h->stream, stop);
+    if (h->opt.tile_config == TILE_REFERENCE) {
+        launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
+        launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream, stop);
+    } else if (lv.g.dim == 2) {
+        launch_resid_restrict2d<T>(lv.g, LP::P(lv), u, b, LP::q(lv), LP::b(lc), h->stream, stop);
+    } else {
+        launch_resid_restrict3d<T>(lv.g, LP::P(lv), u, b, LP::q(lv), LP::b(lc), h->stream, stop);
+    }
+    vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
+    launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
+    for (int s = 0; s < nu2; ++s)
+        launch_gmres_step<T>(lv.g, LP::P(lv), b, LP::q(lv), u, false, h->krylov_m, LP::gz(lv), h->d_gm, h->d_gm_parts,
+                             h->stream, stop);
+}
+
 template <typename T>
 void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop)
 {
@@ -595,6 +639,10 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
     const int last = (int)h->L.size() - 1;
     if (l == last) {
         launch_coarse_apply<T>(h->aug, h->nc, b, u, h->stream, stop);
+        return;
+    }
+    if (h->opt.smoother == FFMG_SMOOTH_GMRES) {
+        vcycle_gmres<T>(h, l, b, u, zero_guess, stop);
         return;
     }
     if constexpr (sizeof(T) == 8) {
@@ -845,6 +893,18 @@ ffmg_status mg_learned_smooth(ffmg_handle *h, const void *b, void *u)
     if (h->opt.smoother != FFMG_SMOOTH_LEARNED) return fail(h, FFMG_EINVAL, "the handle has no learned smoother");
     if (!learned_level(h, 0)) return fail(h, FFMG_EINVAL, "the finest level does not use the learned smoother");
     learned_step(h, 0, (const cd *)b, (cd *)u, nullptr);
+    HIPCHK(h, hipGetLastError());
+    return FFMG_OK;
+}
+
+ffmg_status mg_gmres_smooth(ffmg_handle *h, const void *b, void *u)
+{
+    if (!h || !b || !u) return fail(h, FFMG_EINVAL, "null argument");
+    if (h->opt.smoother != FFMG_SMOOTH_GMRES) return fail(h, FFMG_EINVAL, "the handle does not smooth with GMRES(m)");
+    if (h->L.size() < 2) return fail(h, FFMG_EINVAL, "a one-level hierarchy is solved exactly, not smoothed");
+    Level &l0 = h->L[0];
+    launch_gmres_step<double>(l0.g, l0.P64, (const cd *)b, l0.q, (cd *)u, false, h->krylov_m, l0.gz, h->d_gm,
+                              h->d_gm_parts, h->stream, nullptr);
     HIPCHK(h, hipGetLastError());
     return FFMG_OK;
 }

@@ -21,6 +21,8 @@ struct Level {
     cd *r = nullptr, *t = nullptr;   // residual / scratch, ping-pong buffer
     cf *q32 = nullptr;               // FP32 copies for the refinement inner cycle
     cf *u32 = nullptr, *b32 = nullptr, *r32 = nullptr, *t32 = nullptr;
+    cd *gz = nullptr;                // GMRES(m) smoother: m + 1 basis vectors (FP64)
+    cf *gz32 = nullptr;              // and their FP32 copies for the inner cycle
 };
 
 // tile_config values
@@ -52,6 +54,9 @@ struct ffmg_handle {
     ffmg::SolveCtl *d_ctl = nullptr; // device solve control
     ffmg::SolveCtl *h_ctl = nullptr; // pinned copy
     int last_cycles = 0;             // cycles of the previous solve (batch sizing)
+    int krylov_m = 0;                // GMRES(m) smoother: m
+    double *d_gm = nullptr;          // its per-step scalars (GM_S doubles)
+    double *d_gm_parts = nullptr;    // and partial sums (GM_PARTS doubles)
     hipStream_t stream = nullptr;
     // coarse end of the 2D cycle run by one workgroup in LDS (levels >= tail_l)
     int tail_l = -1;

@@ -108,6 +108,20 @@ template <typename T>
 void launch_inject(const LevelGeom &fine, const cx<T> *qf, cx<T> *qc, hipStream_t s);
 template <typename To, typename Ti>
 void launch_convert(const cx<Ti> *in, cx<To> *out, size_t N, hipStream_t s);
+// GMRES(m) smoothing (ffmg_krylov.hip).  Scalars of one step (doubles):
+// n_i = |Z_i|^2 at [0, GMRES_MAX_M], d_ij = <Z_i, A Z_j> at GM_D + 2 (j
+// GMRES_MAX_M + i) (re, im), the coefficients at GM_C + 2 j.
+constexpr int GMRES_MAX_M = 8;
+constexpr int GM_D = 16;
+constexpr int GM_C = GM_D + 2 * GMRES_MAX_M * GMRES_MAX_M;
+constexpr int GM_S = GM_C + 2 * GMRES_MAX_M;
+constexpr int GM_PARTS = 2 * GMRES_MAX_M * 1024;
+// One GMRES(m) smoothing step in place on a level (zero: u is 0 on entry);
+// Z: m + 1 vectors of the level, S: GM_S doubles, parts: GM_PARTS doubles.
+template <typename T>
+void launch_gmres_step(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero,
+                       int m, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop);
+
 // Full multigrid transfers: the finest right-hand side at the first coarse
 // level's nodes, divided by s = sqrt(*bnorm2 / N) (s = 1 when bnorm2 is
 // null), and uf = s P ec overwriting uf (inv_sqN = 1 / sqrt(N) of the finest

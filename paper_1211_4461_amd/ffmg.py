@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libffmg.so")
 FFMG_OK, FFMG_EINVAL, FFMG_ENOMEM, FFMG_EDEVICE, FFMG_ENOCONV, FFMG_ERANGE, FFMG_ENAN = range(7)
 HELMHOLTZ, SCHRODINGER = 0, 1
 FP64, FP32_IR = 0, 1
-SMOOTH_JACOBI, SMOOTH_LEARNED = 0, 1
+SMOOTH_JACOBI, SMOOTH_LEARNED, SMOOTH_GMRES = 0, 1, 2
 FF_FP64, FF_BF16X3, FF_BF16X6 = 0, 1, 2
 
 
@@ -38,7 +38,8 @@ class Options(ctypes.Structure):
                 ("coarsest_n", ctypes.c_int), ("max_cycles", ctypes.c_int), ("precision", ctypes.c_int),
                 ("smoother", ctypes.c_int), ("smoother_weights", ctypes.c_void_p),
                 ("ff_precision", ctypes.c_int), ("tile_config", ctypes.c_int), ("inner_cycles", ctypes.c_int),
-                ("nu_coarse", ctypes.c_int), ("learned_levels", ctypes.c_int), ("fmg_cycles", ctypes.c_int),
+                ("nu_coarse", ctypes.c_int), ("learned_levels", ctypes.c_int), ("krylov_m", ctypes.c_int),
+                ("fmg_cycles", ctypes.c_int),
                 ("stream", ctypes.c_void_p)]
 
 
@@ -64,7 +65,8 @@ EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup
            "mg_num_levels", "mg_level_shape", "mg_destroy", "mg_profile_enable", "mg_profile_read",
            "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_tune_solve", "mg_solve_batched",
            "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights", "ml_loss_grad",
-           "ml_train_step", "ml_net_last_error", "ml_net_destroy", "mg_learned_smooth", "mg_jacobi_factor"]
+           "ml_train_step", "ml_net_last_error", "ml_net_destroy", "mg_learned_smooth", "mg_jacobi_factor",
+           "mg_gmres_smooth"]
 
 
 def lib():
@@ -116,6 +118,8 @@ def lib():
     L.mg_learned_smooth.argtypes = [vp, vp, vp]
     L.mg_learned_smooth.restype = ip
     L.mg_jacobi_factor.argtypes = [vp]
+    L.mg_gmres_smooth.argtypes = [vp, vp, vp]
+    L.mg_gmres_smooth.restype = ip
     L.mg_jacobi_factor.restype = ctypes.c_double
     L.farfield_map_batched.argtypes = [vp, ip, vp, vp, ip, vp, vp]
     for name in ("mg_setup", "mg_rhs_plane_wave", "mg_vcycle", "mg_fmg", "mg_solve", "farfield_map", "mg_apply",
@@ -126,9 +130,6 @@ def lib():
         getattr(L, name).restype = ip
     _lib = L
     return L
-
-
-SMOOTH_JACOBI, SMOOTH_LEARNED = 0, 1
 
 
 def default_options(**kw) -> Options:
@@ -372,6 +373,12 @@ def mg_apply(h: Handle, u, Au):
 def mg_learned_smooth(h: Handle, b, u):
     """One learned smoothing step on the finest level, in place on u."""
     h._check(lib().mg_learned_smooth(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u")), "mg_learned_smooth")
+    return u
+
+
+def mg_gmres_smooth(h: Handle, b, u):
+    """One GMRES(m) smoothing step on the finest level, in place on u."""
+    h._check(lib().mg_gmres_smooth(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u")), "mg_gmres_smooth")
     return u
 
 
