@@ -259,6 +259,52 @@ def run_concurrent(ff, torch, w, precision, ff_precision, nthreads, maps_per_thr
             "max_rel_residual": max(i.rel_residual for i in infos)}
 
 
+def run_gmres(ff, torch, W, n, steps=6):
+    """The 2048^2 bumps workload solved with GMRES(3) smoothing steps (V(1,1),
+    Sec. 3.3) from the full multigrid start, FP32 cycles in FP64 refinement,
+    on contours of 10 and 30 degrees; weighted Jacobi is tried at 10 degrees
+    (below its stability limit of about 13) with a cycle budget."""
+    out = {"workload": f"bumps_2d n={n} box=[-10,10]^2 k0=1 8 bumps seed=1, 360 angles",
+           "cycle": "V(1,1), GMRES(3) smoothing steps", "start": f"full multigrid, {FMG_K} V per coarse level"}
+    for deg in (10, 30):
+        w = W.bumps_2d(n=n, seed=1, k0=1.0, M=360)
+        w.gamma = math.radians(deg)
+        h = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, ff_precision=ff.FF_BF16X6,
+                                                            smoother=ff.SMOOTH_GMRES, krylov_m=3, nu1=1, nu2=1,
+                                                            fmg_cycles=FMG_K))[0]
+        b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
+        u = torch.empty_like(b)
+        F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
+        info = None
+
+        def step():
+            nonlocal info
+            ff.mg_rhs_plane_wave(h, w.eta, b)
+            info = ff.mg_solve(h, b, u, tol=w.tol)
+            ff.farfield_map(h, w.eta, u, w.dirs, out=F)
+
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        r = {"maps_per_s": round(1.0 / dt, 3), "ms_per_map": round(1e3 * dt, 3), "refinement_steps": info.cycles,
+             "vcycles": info.vcycles, "rel_residual": info.rel_residual, "conv_factor": round(info.conv_factor, 4)}
+        h.destroy()
+        if deg == 10:
+            hj = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, max_cycles=30))[0]
+            ff.mg_rhs_plane_wave(hj, w.eta, b)
+            u.zero_()
+            ij = ff.mg_solve(hj, b, u, tol=w.tol, raise_on_noconv=False)
+            r["jacobi_v22_status"] = {"status": ij.status, "steps": ij.cycles, "rel_residual": ij.rel_residual,
+                                      "converged": ij.status == 0}
+            hj.destroy()
+        out[f"gamma_{deg}deg"] = r
+    return out
+
+
 def run_batched(ff, torch, W, steps):
     """The batched Schroedinger workload: 32 incoming directions x 3 energies
     on seed-drawn 255^2 / 511^2 / 1023^2 grids, all solved in one batched,
@@ -538,6 +584,7 @@ def main():
                     help="skip the other starts (u = 0, other full-multigrid cycle counts)")
     ap.add_argument("--zero-start", action="store_true", help="time the solves from u = 0 instead of the FMG start")
     ap.add_argument("--no-concurrent", action="store_true", help="skip the many-maps-in-flight form")
+    ap.add_argument("--no-gmres", action="store_true", help="skip the GMRES(3)-smoother workload")
     ap.add_argument("--one-stream", action="store_true",
                     help="one handle on one stream (no overlap of a map's far field with the next solve)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
@@ -684,6 +731,8 @@ def main():
         for nt in (2, 4):
             cc[f"threads{nt}"] = run_concurrent(ffmg, torch, w, ffmg.FP32_IR, ffp, nt, max(args.steps // 2, 4), fk)
         line["concurrent_maps"] = cc
+    if not args.no_gmres:
+        line["gmres_smoother"] = run_gmres(ffmg, torch, W, args.n)
     if not args.no_3d:
         line["gauss_3d"] = run_3d(ffmg, torch, W)
     if not args.no_batch:

@@ -115,7 +115,7 @@ constexpr int GMRES_MAX_M = 8;
 constexpr int GM_D = 16;
 constexpr int GM_C = GM_D + 2 * GMRES_MAX_M * GMRES_MAX_M;
 constexpr int GM_S = GM_C + 2 * GMRES_MAX_M;
-constexpr int GM_PARTS = 2 * GMRES_MAX_M * 1024;
+constexpr int GM_PARTS = (GMRES_MAX_M + 1 + 2 * GMRES_MAX_M * GMRES_MAX_M) * 1024;
 // One GMRES(m) smoothing step in place on a level (zero: u is 0 on entry);
 // Z: m + 1 vectors of the level, S: GM_S doubles, parts: GM_PARTS doubles.
 template <typename T>

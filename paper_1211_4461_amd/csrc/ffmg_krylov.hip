@@ -15,11 +15,12 @@
 //
 // Kernels (one point per thread, grid-stride, neighbours read from global
 // memory): the residual with its partial norm; A Z_j fused with the partial
-// products <Z_i, A Z_j>; the orthogonalisation with its partial norm; a
-// deterministic single-block reduction after each of them; the small solve;
-// the update.  Partial sums are FP64 in both precisions.  A V-cycle level is
-// latency-bound here (16 launches per step for m = 3), which is the price of
-// the smoother's robustness.
+// products <Z_i, A Z_j>; the orthogonalisation with its partial norm; the
+// update, each partial sum finished by a one-block kernel that adds the
+// blocks' partials in block order (the last one also solves the small
+// problem): 4 m + 3 launches per step.  Partial sums are FP64 in both
+// precisions.  A level of at most GM_BLOCK_MAX_POINTS points runs the whole
+// step in one 1024-thread workgroup.
 #include "ffmg_internal.hpp"
 #include "ffmg_point.hpp"
 
@@ -28,6 +29,8 @@ namespace ffmg {
 namespace {
 
 constexpr int GM_BLOCKS = 1024;   // grid-stride blocks (and partial sums per value)
+// partial-sum slots: n_i at slot i (i <= m), d_ij (re, im) at NSLOT_D + 2 (j GMRES_MAX_M + i)
+constexpr int NSLOT_D = GMRES_MAX_M + 1;
 
 __device__ __forceinline__ void grid_coords(size_t j, int mx, int my, int &ix, int &iy, int &iz)
 {
@@ -57,12 +60,13 @@ __device__ __forceinline__ cx<T> apply_at(const Stencil<T> &P, const cx<T> *__re
     return apply_point(P, L, uc, qj);
 }
 
-// Block sum of NV doubles per thread into parts[v * gridDim.x + blockIdx.x]
-// (256 threads; wave shuffles, then the four waves in order).
+// Sums of NV doubles per thread of a 256-thread block into
+// parts[slot[v] * GM_BLOCKS + blockIdx.x] (wave shuffles, then the four
+// waves in order).
 template <int NV>
-__device__ __forceinline__ void block_sums(double (&acc)[NV], double *__restrict__ parts)
+__device__ __forceinline__ void block_partials(double (&acc)[NV], const int (&slot)[NV], double *__restrict__ parts)
 {
-    __shared__ double red[4][NV > 0 ? NV : 1];
+    __shared__ double red[4][NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
         for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_down(acc[v], off, 64);
@@ -73,13 +77,86 @@ __device__ __forceinline__ void block_sums(double (&acc)[NV], double *__restrict
     __syncthreads();
     if (threadIdx.x < NV) {
         const int v = threadIdx.x;
-        parts[(size_t)v * gridDim.x + blockIdx.x] = (red[0][v] + red[1][v]) + (red[2][v] + red[3][v]);
+        parts[(size_t)slot[v] * GM_BLOCKS + blockIdx.x] = (red[0][v] + red[1][v]) + (red[2][v] + red[3][v]);
     }
 }
 
-// Z0 = b - A u (u null: Z0 = b), partial |Z0|^2.
+// The small least-squares problem (one thread, FP64, working arrays in LDS):
+// from the squared norms n[0..m] and the products d[2 (j GMRES_MAX_M + i)] =
+// <Z_i, A Z_j> (re, im), the coefficients c[2 j] (re, im) of the
+// unnormalised basis vectors, c_j = y_j / sqrt(n_j), zero past a breakdown.
+struct GmWork {
+    cd H[GMRES_MAX_M + 1][GMRES_MAX_M], g[GMRES_MAX_M + 1], cs[GMRES_MAX_M], sn[GMRES_MAX_M], y[GMRES_MAX_M];
+};
+
+__device__ void gm_solve_small(const double *n, const double *d, int m, double *c, GmWork &W)
+{
+    for (int j = 0; j < m; ++j) c[2 * j] = c[2 * j + 1] = 0.0;
+    const double n0 = n[0];
+    if (!(n0 > 0.0)) return;
+    int k = m;
+    for (int j = 0; j < m; ++j) {
+        const double nj = n[j];
+        for (int i = 0; i <= j; ++i) {
+            const double sc = 1.0 / sqrt(n[i] * nj);
+            W.H[i][j] = cd{d[2 * (j * GMRES_MAX_M + i)] * sc, d[2 * (j * GMRES_MAX_M + i) + 1] * sc};
+        }
+        for (int i = j + 1; i <= m; ++i) W.H[i][j] = cd{0.0, 0.0};
+        const double nn = n[j + 1];
+        W.H[j + 1][j] = cd{nn > 0.0 ? sqrt(nn / nj) : 0.0, 0.0};
+        if (!(nn > 0.0)) {   // the Krylov space is invariant: solve with j + 1 columns
+            k = j + 1;
+            break;
+        }
+    }
+    for (int i = 0; i <= k; ++i) W.g[i] = cd{0.0, 0.0};
+    W.g[0] = cd{sqrt(n0), 0.0};
+    for (int j = 0; j < k; ++j) {
+        for (int i = 0; i < j; ++i) {
+            cd t = W.cs[i] * W.H[i][j] + W.sn[i] * W.H[i + 1][j];
+            W.H[i + 1][j] = cd{-W.sn[i].re, W.sn[i].im} * W.H[i][j] + W.cs[i] * W.H[i + 1][j];
+            W.H[i][j] = t;
+        }
+        const cd a = W.H[j][j], cc = W.H[j + 1][j];
+        const double r = sqrt(a.re * a.re + a.im * a.im + cc.re * cc.re + cc.im * cc.im);
+        if (r == 0.0) {
+            W.cs[j] = cd{1.0, 0.0};
+            W.sn[j] = cd{0.0, 0.0};
+            continue;
+        }
+        const double aa = sqrt(a.re * a.re + a.im * a.im);
+        if (aa == 0.0) {
+            W.cs[j] = cd{0.0, 0.0};
+            W.sn[j] = cd{cc.re / r, -cc.im / r};
+        } else {
+            W.cs[j] = cd{aa / r, 0.0};
+            const cd ph = {a.re / aa, a.im / aa};
+            W.sn[j] = ph * cd{cc.re / r, -cc.im / r};
+        }
+        W.H[j][j] = W.cs[j] * a + W.sn[j] * cc;
+        W.H[j + 1][j] = cd{0.0, 0.0};
+        cd t = W.cs[j] * W.g[j] + W.sn[j] * W.g[j + 1];
+        W.g[j + 1] = cd{-W.sn[j].re, W.sn[j].im} * W.g[j] + W.cs[j] * W.g[j + 1];
+        W.g[j] = t;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        cd t = W.g[i];
+        for (int j = i + 1; j < k; ++j) t = t - W.H[i][j] * W.y[j];
+        const cd dd_ = W.H[i][i];
+        const double dd = dd_.re * dd_.re + dd_.im * dd_.im;
+        W.y[i] = dd > 0.0 ? cd{(t.re * dd_.re + t.im * dd_.im) / dd, (t.im * dd_.re - t.re * dd_.im) / dd}
+                          : cd{0.0, 0.0};
+    }
+    for (int j = 0; j < k; ++j) {
+        const double sc = 1.0 / sqrt(n[j]);
+        c[2 * j] = W.y[j].re * sc;
+        c[2 * j + 1] = W.y[j].im * sc;
+    }
+}
+
+// Z0 = b - A u (zero: u is 0 and is set to 0), n_0 = |Z0|^2.
 template <typename T, int DIM>
-__global__ __launch_bounds__(256) void k_gm_resid(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+__global__ __launch_bounds__(256) void k_gm_resid(cx<T> *__restrict__ u, int zero, const cx<T> *__restrict__ b,
                                                   const cx<T> *__restrict__ q, cx<T> *__restrict__ z0, Stencil<T> P,
                                                   size_t N, double *__restrict__ parts, const int *__restrict__ stop)
 {
@@ -87,45 +164,50 @@ __global__ __launch_bounds__(256) void k_gm_resid(const cx<T> *__restrict__ u, c
     double acc[1] = {0.0};
     for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
         cx<T> r = b[j];
-        if (u) {
+        if (zero) {
+            u[j] = cx<T>{T(0), T(0)};
+        } else {
             cx<T> Au = apply_at<T, DIM>(P, u, q[j], j);
             r = cx<T>{r.re - Au.re, r.im - Au.im};
         }
         z0[j] = r;
         acc[0] += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
     }
-    block_sums<1>(acc, parts);
+    const int slot[1] = {0};
+    block_partials<1>(acc, slot, parts);
 }
 
-// W = A Z_j into Z_{j+1}'s slot; partial <Z_i, W> for i <= j (re, im).
+// W = A Z_j into Z_{j+1}'s slot; d_ij = <Z_i, W> for i <= j (j = NJ - 1).
 template <typename T, int DIM, int NJ>
 __global__ __launch_bounds__(256) void k_gm_apply_dots(cx<T> *__restrict__ Z, size_t N, const cx<T> *__restrict__ q,
                                                        Stencil<T> P, double *__restrict__ parts,
                                                        const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    const cx<T> *zj = Z + (size_t)(NJ - 1) * N;
+    constexpr int j = NJ - 1;
+    const cx<T> *zj = Z + (size_t)j * N;
     cx<T> *w = Z + (size_t)NJ * N;
     double acc[2 * NJ];
 #pragma unroll
     for (int v = 0; v < 2 * NJ; ++v) acc[v] = 0.0;
-    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
-        cx<T> Wj = apply_at<T, DIM>(P, zj, q[j], j);
-        w[j] = Wj;
-        const double wr = Wj.re, wi = Wj.im;
+    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
+        cx<T> Wp = apply_at<T, DIM>(P, zj, q[p], p);
+        w[p] = Wp;
+        const double wr = Wp.re, wi = Wp.im;
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
-            const cx<T> zi = Z[(size_t)i * N + j];
-            // conj(z_i) w
-            acc[2 * i] += (double)zi.re * wr + (double)zi.im * wi;
+            const cx<T> zi = Z[(size_t)i * N + p];
+            acc[2 * i] += (double)zi.re * wr + (double)zi.im * wi;       // conj(z_i) w
             acc[2 * i + 1] += (double)zi.re * wi - (double)zi.im * wr;
         }
     }
-    block_sums<2 * NJ>(acc, parts);
+    int slot[2 * NJ];
+#pragma unroll
+    for (int v = 0; v < 2 * NJ; ++v) slot[v] = NSLOT_D + 2 * (j * GMRES_MAX_M) + v;
+    block_partials<2 * NJ>(acc, slot, parts);
 }
 
-// Z_{j+1} = W - sum_{i<=j} (d_ij / n_i) Z_i in place; partial |Z_{j+1}|^2.
-// S: n_i at S[i], d_ij at S[GM_D + 2 (j MAXM + i)] (re, im).
+// Z_{j+1} = W - sum_{i<=j} (d_ij / n_i) Z_i in place, partial |Z_{j+1}|^2.
 template <typename T, int NJ>
 __global__ __launch_bounds__(256) void k_gm_orth(cx<T> *__restrict__ Z, size_t N, const double *__restrict__ S,
                                                  double *__restrict__ parts, const int *__restrict__ stop)
@@ -151,104 +233,44 @@ __global__ __launch_bounds__(256) void k_gm_orth(cx<T> *__restrict__ Z, size_t N
         w[p] = v;
         acc[0] += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
     }
-    block_sums<1>(acc, parts);
+    const int slot[1] = {NJ};
+    block_partials<1>(acc, slot, parts);
 }
 
-// out[v] = sum of the nb partials of value v (one block per value, fixed order).
-__global__ __launch_bounds__(256) void k_gm_reduce(const double *__restrict__ parts, int nb, double *__restrict__ out,
+// out[v] = sum over the nb blocks of the partials of slot0 + v, in block order
+// (one block, one wave per value); solve_m > 0: then the small problem.
+__global__ __launch_bounds__(256) void k_gm_reduce(const double *__restrict__ parts, int nb, int slot0, int nv,
+                                                   double *__restrict__ out, int solve_m, double *__restrict__ S,
                                                    const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    const int v = blockIdx.x;
-    double a = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 256) a += parts[(size_t)v * nb + i];
-    __shared__ double red[4];
-    for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
-    __syncthreads();
-    if (threadIdx.x == 0) out[v] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// The small least-squares problem (one thread, FP64): coefficients of the
-// unnormalised basis vectors, c_j = y_j / sqrt(n_j), zero past a breakdown.
-__global__ void k_gm_small(double *__restrict__ S, int m, const int *__restrict__ stop)
-{
-    if (stop && *stop) return;
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    cd H[GMRES_MAX_M + 1][GMRES_MAX_M], g[GMRES_MAX_M + 1], cs[GMRES_MAX_M], sn[GMRES_MAX_M], y[GMRES_MAX_M];
-    for (int j = 0; j < m; ++j) S[GM_C + 2 * j] = S[GM_C + 2 * j + 1] = 0.0;
-    const double n0 = S[0];
-    if (!(n0 > 0.0)) return;
-    int k = m;
-    for (int j = 0; j < m; ++j) {
-        const double nj = S[j];
-        for (int i = 0; i <= j; ++i) {
-            const double ni = S[i], sc = 1.0 / sqrt(ni * nj);
-            H[i][j] = cd{S[GM_D + 2 * (j * GMRES_MAX_M + i)] * sc, S[GM_D + 2 * (j * GMRES_MAX_M + i) + 1] * sc};
-        }
-        for (int i = j + 1; i <= m; ++i) H[i][j] = cd{0.0, 0.0};
-        const double nn = S[j + 1];
-        H[j + 1][j] = cd{nn > 0.0 ? sqrt(nn / nj) : 0.0, 0.0};
-        if (!(nn > 0.0)) {   // the Krylov space is invariant: solve with j + 1 columns
-            k = j + 1;
-            break;
-        }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int v = wv; v < nv; v += 4) {
+        double a = 0.0;
+        for (int i = lane; i < nb; i += 64) a += parts[(size_t)(slot0 + v) * GM_BLOCKS + i];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+        if (lane == 0) out[v] = a;
     }
-    for (int i = 0; i <= k; ++i) g[i] = cd{0.0, 0.0};
-    g[0] = cd{sqrt(n0), 0.0};
-    for (int j = 0; j < k; ++j) {
-        for (int i = 0; i < j; ++i) {
-            cd t = cs[i] * H[i][j] + sn[i] * H[i + 1][j];
-            H[i + 1][j] = cd{-sn[i].re, sn[i].im} * H[i][j] + cs[i] * H[i + 1][j];
-            H[i][j] = t;
-        }
-        const cd a = H[j][j], c = H[j + 1][j];
-        const double r = sqrt(a.re * a.re + a.im * a.im + c.re * c.re + c.im * c.im);
-        if (r == 0.0) {
-            cs[j] = cd{1.0, 0.0};
-            sn[j] = cd{0.0, 0.0};
-            continue;
-        }
-        const double aa = sqrt(a.re * a.re + a.im * a.im);
-        if (aa == 0.0) {
-            cs[j] = cd{0.0, 0.0};
-            sn[j] = cd{c.re / r, -c.im / r};
-        } else {
-            cs[j] = cd{aa / r, 0.0};
-            const cd ph = {a.re / aa, a.im / aa};
-            sn[j] = ph * cd{c.re / r, -c.im / r};
-        }
-        H[j][j] = cs[j] * a + sn[j] * c;
-        H[j + 1][j] = cd{0.0, 0.0};
-        cd t = cs[j] * g[j] + sn[j] * g[j + 1];
-        g[j + 1] = cd{-sn[j].re, sn[j].im} * g[j] + cs[j] * g[j + 1];
-        g[j] = t;
-    }
-    for (int i = k - 1; i >= 0; --i) {
-        cd t = g[i];
-        for (int j = i + 1; j < k; ++j) t = t - H[i][j] * y[j];
-        const cd d = H[i][i];
-        const double dd = d.re * d.re + d.im * d.im;
-        y[i] = dd > 0.0 ? cd{(t.re * d.re + t.im * d.im) / dd, (t.im * d.re - t.re * d.im) / dd} : cd{0.0, 0.0};
-    }
-    for (int j = 0; j < k; ++j) {
-        const double sc = 1.0 / sqrt(S[j]);
-        S[GM_C + 2 * j] = y[j].re * sc;
-        S[GM_C + 2 * j + 1] = y[j].im * sc;
+    if (solve_m > 0) {
+        __shared__ GmWork W;
+        __syncthreads();
+        if (threadIdx.x == 0) gm_solve_small(S, S + GM_D, solve_m, S + GM_C, W);
     }
 }
 
 // u += sum_j c_j Z_j.
-template <typename T>
+template <typename T, int M>
 __global__ __launch_bounds__(256) void k_gm_update(cx<T> *__restrict__ u, const cx<T> *__restrict__ Z, size_t N,
-                                                   int m, const double *__restrict__ S, const int *__restrict__ stop)
+                                                   const double *__restrict__ S, const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    cx<T> c[GMRES_MAX_M];
-    for (int j = 0; j < m; ++j) c[j] = cx<T>{T(S[GM_C + 2 * j]), T(S[GM_C + 2 * j + 1])};
+    cx<T> c[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) c[j] = cx<T>{T(S[GM_C + 2 * j]), T(S[GM_C + 2 * j + 1])};
     for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
         cx<T> v = u[p];
-        for (int j = 0; j < m; ++j) {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
             const cx<T> zj = Z[(size_t)j * N + p];
             v = cx<T>{v.re + (c[j].re * zj.re - c[j].im * zj.im), v.im + (c[j].re * zj.im + c[j].im * zj.re)};
         }
@@ -256,78 +278,180 @@ __global__ __launch_bounds__(256) void k_gm_update(cx<T> *__restrict__ u, const 
     }
 }
 
-template <typename T, int DIM, int NJ>
-void launch_apply_dots(cx<T> *Z, size_t N, const cx<T> *q, const Stencil<T> &P, double *parts, int nb, hipStream_t s,
-                       const int *stop)
+// A whole GMRES(M) step on a small level in one 1024-thread workgroup: the
+// same passes, separated by workgroup barriers (global memory written before
+// a barrier is seen after it within the workgroup), the sums reduced in LDS
+// and the small solve by thread 0.
+constexpr int GM_BLOCK_THREADS = 1024;
+constexpr size_t GM_BLOCK_MAX_POINTS = 4096;
+
+template <int NV>
+__device__ __forceinline__ void block_reduce_1024(double (&acc)[NV], double *out, double (*red)[2 * GMRES_MAX_M])
 {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+        for (int off = 32; off > 0; off >>= 1) acc[v] += __shfl_down(acc[v], off, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) red[wv][v] = acc[v];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double a = 0.0;
+        for (int w_ = 0; w_ < GM_BLOCK_THREADS / 64; ++w_) a += red[w_][threadIdx.x];
+        out[threadIdx.x] = a;
+    }
+    __syncthreads();
+}
+
+template <typename T, int DIM, int NJ>
+__device__ __forceinline__ void gm_block_arnoldi(cx<T> *__restrict__ Z, size_t N, const cx<T> *__restrict__ q,
+                                                 const Stencil<T> &P, double *n, double *d,
+                                                 double (*red)[2 * GMRES_MAX_M])
+{
+    constexpr int j = NJ - 1;
+    const cx<T> *zj = Z + (size_t)j * N;
+    cx<T> *w = Z + (size_t)NJ * N;
+    double acc[2 * NJ];
+#pragma unroll
+    for (int v = 0; v < 2 * NJ; ++v) acc[v] = 0.0;
+    for (size_t p = threadIdx.x; p < N; p += GM_BLOCK_THREADS) {
+        cx<T> Wp = apply_at<T, DIM>(P, zj, q[p], p);
+        w[p] = Wp;
+        const double wr = Wp.re, wi = Wp.im;
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+            const cx<T> zi = Z[(size_t)i * N + p];
+            acc[2 * i] += (double)zi.re * wr + (double)zi.im * wi;
+            acc[2 * i + 1] += (double)zi.re * wi - (double)zi.im * wr;
+        }
+    }
+    block_reduce_1024<2 * NJ>(acc, d + 2 * (j * GMRES_MAX_M), red);
+    cx<T> g[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        const double ni = n[i];
+        const double dr = d[2 * (j * GMRES_MAX_M + i)], di = d[2 * (j * GMRES_MAX_M + i) + 1];
+        g[i] = cx<T>{T(ni > 0.0 ? dr / ni : 0.0), T(ni > 0.0 ? di / ni : 0.0)};
+    }
+    double nacc[1] = {0.0};
+    for (size_t p = threadIdx.x; p < N; p += GM_BLOCK_THREADS) {
+        cx<T> v = w[p];
+#pragma unroll
+        for (int i = 0; i < NJ; ++i) {
+            const cx<T> zi = Z[(size_t)i * N + p];
+            v = cx<T>{v.re - (g[i].re * zi.re - g[i].im * zi.im), v.im - (g[i].re * zi.im + g[i].im * zi.re)};
+        }
+        w[p] = v;
+        nacc[0] += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    }
+    block_reduce_1024<1>(nacc, n + NJ, red);
+}
+
+template <typename T, int DIM, int NJ, int M>
+__device__ __forceinline__ void gm_block_arnoldi_all(cx<T> *Z, size_t N, const cx<T> *q, const Stencil<T> &P,
+                                                     double *n, double *d, double (*red)[2 * GMRES_MAX_M])
+{
+    gm_block_arnoldi<T, DIM, NJ>(Z, N, q, P, n, d, red);
+    if constexpr (NJ < M) gm_block_arnoldi_all<T, DIM, NJ + 1, M>(Z, N, q, P, n, d, red);
+}
+
+template <typename T, int DIM, int M>
+__global__ __launch_bounds__(1024) void k_gm_step_block(const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                                        cx<T> *__restrict__ u, int zero, cx<T> *__restrict__ Z,
+                                                        Stencil<T> P, size_t N, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    __shared__ double red[GM_BLOCK_THREADS / 64][2 * GMRES_MAX_M];
+    __shared__ double n[GMRES_MAX_M + 1], d[2 * GMRES_MAX_M * GMRES_MAX_M], c[2 * GMRES_MAX_M];
+    __shared__ GmWork W;
+    double acc[1] = {0.0};
+    for (size_t p = threadIdx.x; p < N; p += GM_BLOCK_THREADS) {
+        cx<T> r = b[p];
+        if (zero) {
+            u[p] = cx<T>{T(0), T(0)};
+        } else {
+            cx<T> Au = apply_at<T, DIM>(P, u, q[p], p);
+            r = cx<T>{r.re - Au.re, r.im - Au.im};
+        }
+        Z[p] = r;
+        acc[0] += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+    }
+    block_reduce_1024<1>(acc, n, red);
+    gm_block_arnoldi_all<T, DIM, 1, M>(Z, N, q, P, n, d, red);
+    if (threadIdx.x == 0) gm_solve_small(n, d, M, c, W);
+    __syncthreads();
+    cx<T> cc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) cc[j] = cx<T>{T(c[2 * j]), T(c[2 * j + 1])};
+    for (size_t p = threadIdx.x; p < N; p += GM_BLOCK_THREADS) {
+        cx<T> v = u[p];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const cx<T> zj = Z[(size_t)j * N + p];
+            v = cx<T>{v.re + (cc[j].re * zj.re - cc[j].im * zj.im), v.im + (cc[j].re * zj.im + cc[j].im * zj.re)};
+        }
+        u[p] = v;
+    }
+}
+
+template <typename T, int DIM, int NJ, int M>
+void launch_arnoldi_all(cx<T> *Z, size_t N, const cx<T> *q, const Stencil<T> &P, double *S, double *parts, int nb,
+                        hipStream_t s, const int *stop)
+{
+    constexpr int j = NJ - 1;
     hipLaunchKernelGGL((k_gm_apply_dots<T, DIM, NJ>), dim3(nb), dim3(256), 0, s, Z, N, q, P, parts, stop);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, NSLOT_D + 2 * (j * GMRES_MAX_M), 2 * NJ,
+                       S + GM_D + 2 * (j * GMRES_MAX_M), 0, S, stop);
+    hipLaunchKernelGGL((k_gm_orth<T, NJ>), dim3(nb), dim3(256), 0, s, Z, N, S, parts, stop);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, NJ, 1, S + NJ, NJ == M ? M : 0, S, stop);
+    if constexpr (NJ < M) launch_arnoldi_all<T, DIM, NJ + 1, M>(Z, N, q, P, S, parts, nb, s, stop);
+}
+
+template <typename T, int DIM, int M>
+void launch_step_m(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero,
+                   cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop)
+{
+    const size_t N = g.N();
+    if (N <= GM_BLOCK_MAX_POINTS) {   // small level: the whole step in one workgroup
+        hipLaunchKernelGGL((k_gm_step_block<T, DIM, M>), dim3(1), dim3(GM_BLOCK_THREADS), 0, s, b, q, u,
+                           zero ? 1 : 0, Z, P, N, stop);
+        return;
+    }
+    const int nb = (int)std::min<size_t>((N + 255) / 256, GM_BLOCKS);
+    hipLaunchKernelGGL((k_gm_resid<T, DIM>), dim3(nb), dim3(256), 0, s, u, zero ? 1 : 0, b, q, Z, P, N, parts, stop);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, 0, 1, S, 0, S, stop);
+    launch_arnoldi_all<T, DIM, 1, M>(Z, N, q, P, S, parts, nb, s, stop);
+    hipLaunchKernelGGL((k_gm_update<T, M>), dim3(nb), dim3(256), 0, s, u, Z, N, S, stop);
 }
 
 template <typename T, int DIM>
-void apply_dots_dispatch(int nj, cx<T> *Z, size_t N, const cx<T> *q, const Stencil<T> &P, double *parts, int nb,
-                         hipStream_t s, const int *stop)
+void launch_step_dim(int m, const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u,
+                     bool zero, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop)
 {
-    switch (nj) {
-    case 1: launch_apply_dots<T, DIM, 1>(Z, N, q, P, parts, nb, s, stop); break;
-    case 2: launch_apply_dots<T, DIM, 2>(Z, N, q, P, parts, nb, s, stop); break;
-    case 3: launch_apply_dots<T, DIM, 3>(Z, N, q, P, parts, nb, s, stop); break;
-    case 4: launch_apply_dots<T, DIM, 4>(Z, N, q, P, parts, nb, s, stop); break;
-    case 5: launch_apply_dots<T, DIM, 5>(Z, N, q, P, parts, nb, s, stop); break;
-    case 6: launch_apply_dots<T, DIM, 6>(Z, N, q, P, parts, nb, s, stop); break;
-    case 7: launch_apply_dots<T, DIM, 7>(Z, N, q, P, parts, nb, s, stop); break;
-    default: launch_apply_dots<T, DIM, 8>(Z, N, q, P, parts, nb, s, stop); break;
+    switch (m) {
+    case 1: launch_step_m<T, DIM, 1>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
+    case 2: launch_step_m<T, DIM, 2>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
+    case 3: launch_step_m<T, DIM, 3>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
+    case 4: launch_step_m<T, DIM, 4>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
+    case 5: launch_step_m<T, DIM, 5>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
+    case 6: launch_step_m<T, DIM, 6>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
+    case 7: launch_step_m<T, DIM, 7>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
+    default: launch_step_m<T, DIM, 8>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
     }
-}
-
-template <typename T>
-void orth_dispatch(int nj, cx<T> *Z, size_t N, const double *S, double *parts, int nb, hipStream_t s,
-                   const int *stop)
-{
-#define GM_ORTH(J) hipLaunchKernelGGL((k_gm_orth<T, J>), dim3(nb), dim3(256), 0, s, Z, N, S, parts, stop)
-    switch (nj) {
-    case 1: GM_ORTH(1); break;
-    case 2: GM_ORTH(2); break;
-    case 3: GM_ORTH(3); break;
-    case 4: GM_ORTH(4); break;
-    case 5: GM_ORTH(5); break;
-    case 6: GM_ORTH(6); break;
-    case 7: GM_ORTH(7); break;
-    default: GM_ORTH(8); break;
-    }
-#undef GM_ORTH
 }
 
 }  // namespace
 
 // One GMRES(m) smoothing step in place on a level: Z holds m + 1 vectors of
-// N points, S the step's scalars (GM_S doubles), parts GM_BLOCKS x (2m + 1)
-// partial sums.  zero: u is 0 on entry (not read).
+// N points, S the step's scalars (GM_S doubles), parts the partial sums
+// (GM_PARTS doubles).  zero: u is 0 on entry (not read).
 template <typename T>
 void launch_gmres_step(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero,
                        int m, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop)
 {
-    const size_t N = g.N();
-    const int nb = (int)std::min<size_t>((N + 255) / 256, GM_BLOCKS);
-    const bool d3 = (g.dim == 3);
-    if (zero) launch_zero<T>(u, N, s, stop);
-    if (d3)
-        hipLaunchKernelGGL((k_gm_resid<T, 3>), dim3(nb), dim3(256), 0, s, zero ? nullptr : u, b, q, Z, P, N, parts,
-                           stop);
-    else
-        hipLaunchKernelGGL((k_gm_resid<T, 2>), dim3(nb), dim3(256), 0, s, zero ? nullptr : u, b, q, Z, P, N, parts,
-                           stop);
-    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, S, stop);
-    for (int j = 0; j < m; ++j) {
-        const int nj = j + 1;
-        if (d3) apply_dots_dispatch<T, 3>(nj, Z, N, q, P, parts, nb, s, stop);
-        else apply_dots_dispatch<T, 2>(nj, Z, N, q, P, parts, nb, s, stop);
-        hipLaunchKernelGGL(k_gm_reduce, dim3(2 * nj), dim3(256), 0, s, parts, nb,
-                           S + GM_D + 2 * (j * GMRES_MAX_M), stop);
-        orth_dispatch<T>(nj, Z, N, S, parts, nb, s, stop);
-        hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, S + j + 1, stop);
-    }
-    hipLaunchKernelGGL(k_gm_small, dim3(1), dim3(64), 0, s, S, m, stop);
-    hipLaunchKernelGGL((k_gm_update<T>), dim3(nb), dim3(256), 0, s, u, Z, N, m, S, stop);
+    if (g.dim == 3) launch_step_dim<T, 3>(m, g, P, b, q, u, zero, Z, S, parts, s, stop);
+    else launch_step_dim<T, 2>(m, g, P, b, q, u, zero, Z, S, parts, s, stop);
 }
 template void launch_gmres_step<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *, cd *, bool,
                                         int, cd *, double *, double *, hipStream_t, const int *);
