@@ -146,6 +146,35 @@ void or_jacobi(int dim, const long *m, const double *h, double gamma,
             }
 }
 
+/* One red-black Gauss-Seidel sweep, in place (Sec. 3.3 names Gauss-Seidel
+ * beside weighted Jacobi as the standard relaxation of the V-cycle): the
+ * points with ix + iy + iz even (0-based interior indices, "red") are
+ * relaxed first, u_j <- u_j + (b_j - (A u)_j) / D_j, then the others with
+ * the red values already updated.  A red point's stencil neighbours are all
+ * black and the other way round, so each half sweep is a set of independent
+ * point updates. */
+void or_rbgs(int dim, const long *m, const double *h, double gamma,
+             const cplx *kappa, const cplx *b, cplx *u)
+{
+    long e[3];
+    cplx c[3];
+    extents(dim, m, e);
+    stencil_coefs(dim, h, gamma, c);
+    cplx csum = 0.0;
+    for (int k = 0; k < dim; ++k) csum += 2.0 * c[k];
+    for (int color = 0; color < 2; ++color) {
+        #pragma omp parallel for schedule(static)
+        for (long iz = 0; iz < e[2]; ++iz)
+            for (long iy = 0; iy < e[1]; ++iy)
+                for (long ix = 0; ix < e[0]; ++ix) {
+                    if (((ix + iy + iz) & 1) != color) continue;
+                    long j = ix + e[0] * (iy + e[1] * iz);
+                    cplx D = csum - kappa[j];
+                    u[j] += (b[j] - apply_point(dim, e, c, kappa, u, ix, iy, iz)) / D;
+                }
+    }
+}
+
 /* One GMRES(m) smoothing step from the guess u, in place (Sec. 3.3: GMRES(m),
  * m = 2 or 3, as the smoother that replaces weighted Jacobi and keeps the
  * V-cycle stable at rotation angles near 10 degrees).  It is one restart
@@ -393,7 +422,7 @@ void or_lu_solve(long N, const cplx *LU, const long *piv, cplx *x)
 
 typedef struct {
     int dim, nlev, nu1, nu2;
-    int smoother, krylov_m;   /* 0: omega-Jacobi; 1: GMRES(krylov_m) */
+    int smoother, krylov_m;   /* 0: omega-Jacobi; 1: GMRES(krylov_m); 2: red-black Gauss-Seidel */
     double gamma, omega;
     long m[OR_MAXLEV][3];
     double h[OR_MAXLEV][3];
@@ -470,7 +499,8 @@ void or_mg_kappa(void *p, int l, cplx *out)
 }
 
 /* Choose the smoother of every level below the coarsest: omega-Jacobi
- * (smoother 0, the default) or GMRES(m) steps (smoother 1). */
+ * (smoother 0, the default), GMRES(m) steps (smoother 1) or red-black
+ * Gauss-Seidel sweeps (smoother 2). */
 void or_mg_set_smoother(void *p, int smoother, int m)
 {
     or_mg *g = p;
@@ -483,6 +513,10 @@ static void smooth(or_mg *g, int l, const cplx *b, cplx *u, int nu)
     long N = npts(g->dim, g->m[l]);
     if (g->smoother == 1) {
         for (int s = 0; s < nu; ++s) or_gmres(g->dim, g->m[l], g->h[l], g->gamma, g->kappa[l], b, u, g->krylov_m);
+        return;
+    }
+    if (g->smoother == 2) {
+        for (int s = 0; s < nu; ++s) or_rbgs(g->dim, g->m[l], g->h[l], g->gamma, g->kappa[l], b, u);
         return;
     }
     for (int s = 0; s < nu; ++s) {

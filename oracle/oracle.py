@@ -58,6 +58,7 @@ def lib():
         L.or_mg_fmg.argtypes = [vp, vp, vp, ip]
         L.or_mg_set_smoother.argtypes = [vp, ip, ip]
         L.or_gmres.argtypes = [ip, vp, vp, dp, vp, vp, vp, ip]
+        L.or_rbgs.argtypes = [ip, vp, vp, dp, vp, vp, vp]
         L.or_mg_solve.argtypes = [vp, vp, vp, dp, ip, vp, vp]
         L.or_mg_solve.restype = ip
         L.or_apply.argtypes = [ip, vp, vp, dp, vp, vp, vp]
@@ -168,6 +169,16 @@ def gmres_step(g: Grid, gamma, kappa, b, u, m):
     return out.reshape(np.shape(u))
 
 
+def rbgs_sweep(g: Grid, gamma, kappa, b, u):
+    """One red-black Gauss-Seidel sweep (red: ix + iy + iz even), a copy."""
+    m3, h3 = _m3(g.m), _d3(g.h, 1.0)
+    kap, kp = _c(kappa.ravel(), np.complex128)
+    bb, bp = _c(b.ravel(), np.complex128)
+    out = np.array(u, dtype=np.complex128, copy=True).ravel()
+    lib().or_rbgs(g.dim, m3.ctypes.data, h3.ctypes.data, gamma, kp, bp, out.ctypes.data)
+    return out.reshape(np.shape(u))
+
+
 def restrict(dim, mf, rf):
     """Full-weighting restriction from a fine grid with interior counts mf."""
     mf = np.asarray(mf, dtype=np.int64).reshape(-1)
@@ -212,9 +223,9 @@ def lu_solve_dense(A, b):
 # ---------------------------------------------------------------- multigrid
 
 class Multigrid:
-    """V(nu1, nu2) multigrid with omega-Jacobi (or GMRES(m), Sec. 3.3)
-    smoothing on the contour grid (Sec. 4), coarsest grid with 7^d unknowns
-    solved by dense LU."""
+    """V(nu1, nu2) multigrid with omega-Jacobi (or GMRES(m) / red-black
+    Gauss-Seidel, Sec. 3.3) smoothing on the contour grid (Sec. 4), coarsest
+    grid with 7^d unknowns solved by dense LU."""
 
     def __init__(self, g: Grid, gamma, kappa, nu1=2, nu2=2, omega=0.8, coarsest_n=8, smoother="jacobi",
                  krylov_m=3):
@@ -229,6 +240,8 @@ class Multigrid:
         self.nlev = lib().or_mg_nlev(self._h)
         if smoother == "gmres":
             lib().or_mg_set_smoother(self._h, 1, int(krylov_m))
+        elif smoother == "rbgs":
+            lib().or_mg_set_smoother(self._h, 2, 0)
         elif smoother != "jacobi":
             raise ValueError(f"unknown smoother {smoother}")
 

@@ -99,18 +99,41 @@ def dense_gmres_step(A, b, u, m):
     return u + K @ c
 
 
-def dense_vcycle(m, h, gamma, kappa, b, u, nu1, nu2, omega, coarsest_n=8, krylov_m=0):
+def color_mask(m):
+    """True at the "red" points (0-based interior indices summing to an even
+    number), x fastest."""
+    idx = np.meshgrid(*[np.arange(mk) for mk in m[::-1]], indexing="ij")
+    return (sum(idx) % 2 == 0).ravel()
+
+
+def dense_rbgs(A, b, u, red):
+    """Red-black Gauss-Seidel as a block solve in the red/black ordering:
+    u_r = D_r^{-1} (b_r - A_rb u_b), then u_b = D_b^{-1} (b_b - A_br u_r)."""
+    u = u.copy()
+    for c in (red, ~red):
+        o = ~c
+        D = np.diag(A)[c]
+        u[c] = (b[c] - A[np.ix_(c, o)] @ u[o]) / D
+    return u
+
+
+def dense_vcycle(m, h, gamma, kappa, b, u, nu1, nu2, omega, coarsest_n=8, krylov_m=0, rbgs=False):
     """One V(nu1, nu2) cycle written with dense matrices (krylov_m > 0:
-    GMRES(krylov_m) smoothing steps instead of omega-Jacobi sweeps)."""
+    GMRES(krylov_m) smoothing steps, rbgs: red-black Gauss-Seidel sweeps
+    instead of omega-Jacobi sweeps)."""
     m = list(m)
     A = kron_operator(m, h, gamma, kappa).toarray()
     if min(mk + 1 for mk in m) <= coarsest_n:
         return np.linalg.solve(A, b)
     D = np.diag(A)
 
+    red = color_mask(m)
+
     def smooth(u):
         if krylov_m:
             return dense_gmres_step(A, b, u, krylov_m)
+        if rbgs:
+            return dense_rbgs(A, b, u, red)
         return u + omega * (b - A @ u) / D
 
     for _ in range(nu1):
@@ -121,7 +144,7 @@ def dense_vcycle(m, h, gamma, kappa, b, u, nu1, nu2, omega, coarsest_n=8, krylov
     mc = [(mk - 1) // 2 for mk in m]
     kc = np.asarray(kappa).ravel()[inject_index(m)]
     ec = dense_vcycle(mc, [2 * hk for hk in h], gamma, kc, bc, np.zeros_like(bc),
-                      nu1, nu2, omega, coarsest_n, krylov_m)
+                      nu1, nu2, omega, coarsest_n, krylov_m, rbgs)
     u = u + prolong(m) @ ec
     for _ in range(nu2):
         u = smooth(u)

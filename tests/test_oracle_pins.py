@@ -274,6 +274,58 @@ def test_gmres_smoother_converges_below_the_jacobi_angle(orc):
     assert res[(30, "gmres")][0] == orc.OK and res[(30, "gmres")][1] < res[(30, "jacobi")][1]
 
 
+@pytest.mark.parametrize("dim,n", [(2, (16, 32)), (3, (8, 16, 8))])
+def test_rbgs_sweep_is_the_red_black_block_solve(orc, dim, n):
+    """A red-black Gauss-Seidel sweep (Sec. 3.3) is, in the red/black
+    ordering of the 5/7-point stencil, u_r = D_r^-1 (b_r - A_rb u_b) followed
+    by u_b = D_b^-1 (b_b - A_br u_r), written with the dense matrix."""
+    g = orc.Grid(dim, n, [-4.0] * dim, [4.0] * dim)
+    r = rng(9)
+    kappa = 4.0 * (1.0 + 0.5 * r.random(g.shape)) + 0.3j * r.random(g.shape)
+    b, u = crand(r, g.shape), crand(r, g.shape)
+    A = refs.kron_operator(list(g.m), list(g.h), G30, kappa).toarray()
+    red = refs.color_mask(list(g.m))
+    # the stencil couples no two points of one colour
+    off = A - np.diag(np.diag(A))
+    assert np.abs(off[np.ix_(red, red)]).max() == 0 and np.abs(off[np.ix_(~red, ~red)]).max() == 0
+    got = orc.rbgs_sweep(g, G30, kappa, b, u)
+    ref = refs.dense_rbgs(A, b.ravel(), u.ravel(), red).reshape(g.shape)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dim,n,nu", [(2, (32, 32), (2, 2)), (2, (32, 64), (1, 1)), (3, (16, 16, 16), (1, 2))])
+def test_rbgs_vcycle_matches_dense_matrix_cycle(orc, dim, n, nu):
+    L = [4.0] * dim
+    g = orc.Grid(dim, n, [-l for l in L], L)
+    r = rng(10)
+    kappa = 4.0 * (1.0 + 0.5 * r.random(g.shape)) + 0.3j * r.random(g.shape)
+    b, u0 = crand(r, g.shape), crand(r, g.shape)
+    mg = orc.Multigrid(g, G30, kappa, nu1=nu[0], nu2=nu[1], smoother="rbgs")
+    got = mg.vcycle(b, u0)
+    ref = refs.dense_vcycle(list(g.m), list(g.h), G30, kappa.ravel(), b.ravel(), u0.ravel(), nu[0], nu[1], 0.8,
+                            rbgs=True).reshape(g.shape)
+    assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+def test_rbgs_needs_the_jacobi_angle(orc):
+    """Sec. 3.3: the angle limit of about 13 degrees holds for Gauss-Seidel as
+    for weighted Jacobi: red-black GS V(1,1) converges at 30 degrees and
+    diverges at 10.  (Undamped GS is the weaker smoother on this indefinite
+    operator: V(2,2) converges more slowly than V(1,1) at 30 degrees.)"""
+    w = W.small_2d(n=128)
+    g = orc.Grid(2, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    res = {}
+    for deg in (30, 10):
+        gam = math.radians(deg)
+        b = orc.rhs_plane_wave(g, gam, k0, q, w.eta)
+        _, st, k, _ = orc.Multigrid(g, gam, kappa, nu1=1, nu2=1, smoother="rbgs").solve(b, tol=1e-10,
+                                                                                        max_cycles=100)
+        res[deg] = (st, k)
+    assert res[30][0] == orc.OK and res[30][1] <= 40, res
+    assert res[10][0] == orc.ENOCONV, res
+
+
 def test_coarse_kappa_is_injected(orc):
     g = orc.Grid(2, 32, -4, 4)
     r = rng(5)
