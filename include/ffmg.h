@@ -60,7 +60,12 @@ typedef enum {
 
 typedef enum { FFMG_HELMHOLTZ = 0, FFMG_SCHRODINGER = 1 } ffmg_kind;
 typedef enum { FFMG_FP64 = 0, FFMG_FP32_IR = 1 } ffmg_precision;
-typedef enum { FFMG_SMOOTH_JACOBI = 0, FFMG_SMOOTH_LEARNED = 1, FFMG_SMOOTH_GMRES = 2 } ffmg_smoother;
+typedef enum {
+    FFMG_SMOOTH_JACOBI = 0,
+    FFMG_SMOOTH_LEARNED = 1,
+    FFMG_SMOOTH_GMRES = 2,
+    FFMG_SMOOTH_RBGS = 3
+} ffmg_smoother;
 typedef enum { FFMG_FF_FP64 = 0, FFMG_FF_BF16X3 = 1, FFMG_FF_BF16X6 = 2 } ffmg_ff_precision;
 
 /* The scattering problem (Sec. 2.1 Helmholtz; Sec. 5 Schroedinger). */
@@ -87,8 +92,9 @@ typedef struct ffmg_options {
     int max_cycles;       /* mg_solve cycle limit (>= 1)                       */
     int precision;        /* ffmg_precision                                    */
     int smoother;         /* ffmg_smoother: weighted Jacobi (Sec. 4), the
-                             learned network, or GMRES(krylov_m) steps
-                             (Sec. 3.3) on every level above the coarsest    */
+                             learned network, GMRES(krylov_m) steps or
+                             red-black Gauss-Seidel sweeps (Sec. 3.3) on
+                             every level above the coarsest                  */
     const float *smoother_weights; /* HOST, learned smoother parameters, or NULL */
     int ff_precision;     /* ffmg_ff_precision                                 */
     int tile_config;      /* 0 = fused kernels (default; 2D: two sweeps per
@@ -255,7 +261,10 @@ void ml_net_destroy(ffmg_net *net);
 /* Au = A u (the operator of eq. csg), DEVICE complex128[N] each. */
 ffmg_status mg_apply(ffmg_handle *h, const void *u, void *Au);
 
-/* One omega-Jacobi sweep u_out = u + omega D^{-1} (b - A u), out of place. */
+/* One smoothing step on the finest level, FP64, out of place: an
+ * omega-Jacobi sweep u_out = u + omega D^{-1} (b - A u) (smoothers Jacobi and
+ * learned), a red-black Gauss-Seidel sweep (FFMG_SMOOTH_RBGS) or a GMRES(m)
+ * step (FFMG_SMOOTH_GMRES) from u into u_out.  u, u_out must not alias. */
 ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out);
 
 /* One learned smoothing step on the finest level, in place on u (DEVICE

@@ -320,7 +320,8 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
         if (fabs(hx - hy) > 1e-12 * hx) return fail(tmp, FFMG_EINVAL, "the learned smoother needs square cells");
         for (int k = 0; k < 2 * FFMG_NET_WEIGHTS; ++k)
             if (!isfinite(o->smoother_weights[k])) return fail(tmp, FFMG_ENAN, "smoother weight %d is not finite", k);
-    } else if (o->smoother != FFMG_SMOOTH_JACOBI && o->smoother != FFMG_SMOOTH_GMRES) {
+    } else if (o->smoother != FFMG_SMOOTH_JACOBI && o->smoother != FFMG_SMOOTH_GMRES &&
+               o->smoother != FFMG_SMOOTH_RBGS) {
         return fail(tmp, FFMG_EINVAL, "unknown smoother %d", o->smoother);
     }
     if (o->krylov_m < 0 || o->krylov_m > GMRES_MAX_M)
@@ -354,7 +355,9 @@ void plan_tail(ffmg_handle *h, TailParams<T> &tp, size_t &lds)
     tp = TailParams<T>{};
     lds = 0;
     const int nl = (int)h->L.size();
-    if (h->prob.dim != 2 || h->opt.tile_config != TILE_FUSED || nl < 3 || h->opt.smoother == FFMG_SMOOTH_GMRES) return;
+    if (h->prob.dim != 2 || h->opt.tile_config != TILE_FUSED || nl < 3 || h->opt.smoother == FFMG_SMOOTH_GMRES ||
+        h->opt.smoother == FFMG_SMOOTH_RBGS)
+        return;
     const size_t budget = 144 * 1024;
     size_t bytes = 0;
     int top = nl;   // first tail level
@@ -601,11 +604,26 @@ static void vcycle_learned(ffmg_handle *h, int l, const cd *b, cd *u, bool zero_
     for (int s = 0; s < nu_post(h, l); ++s) learned_step(h, l, b, u, stop);
 }
 
-// One level of a V-cycle with GMRES(m) smoothing steps (Sec. 3.3): nu1
-// steps, residual + restriction, the coarse correction, interpolation, nu2
-// steps.
+// One smoothing step of the GMRES(m) or red-black Gauss-Seidel smoother
+// (Sec. 3.3) in place on a level (zero: u is 0 on entry).
 template <typename T>
-static void vcycle_gmres(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop)
+static void other_smooth_step(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *u, bool zero, const int *stop)
+{
+    using LP = LvlPtr<T>;
+    if (h->opt.smoother == FFMG_SMOOTH_GMRES) {
+        launch_gmres_step<T>(lv.g, LP::P(lv), b, LP::q(lv), u, zero, h->krylov_m, LP::gz(lv), h->d_gm, h->d_gm_parts,
+                             h->stream, stop);
+    } else {
+        if (zero) launch_zero<T>(u, lv.g.N(), h->stream, stop);
+        launch_rbgs_sweep<T>(lv.g, LP::P(lv), b, LP::q(lv), u, h->stream, stop);
+    }
+}
+
+// One level of a V-cycle with GMRES(m) steps or red-black Gauss-Seidel
+// sweeps (Sec. 3.3): nu1 steps, residual + restriction, the coarse
+// correction, interpolation, nu2 steps.
+template <typename T>
+static void vcycle_other(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, const int *stop)
 {
     using LP = LvlPtr<T>;
     Level &lv = h->L[l];
@@ -613,9 +631,7 @@ static void vcycle_gmres(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool z
     const int nu1 = nu_pre(h, l), nu2 = nu_post(h, l);
     bool zero = zero_guess;
     if (nu1 == 0 && zero) launch_zero<T>(u, lv.g.N(), h->stream, stop);
-    for (int s = 0; s < nu1; ++s, zero = false)
-        launch_gmres_step<T>(lv.g, LP::P(lv), b, LP::q(lv), u, zero, h->krylov_m, LP::gz(lv), h->d_gm, h->d_gm_parts,
-                             h->stream, stop);
+    for (int s = 0; s < nu1; ++s, zero = false) other_smooth_step<T>(h, lv, b, u, zero, stop);
     if (h->opt.tile_config == TILE_REFERENCE) {
         launch_stencil<T>(MODE_RESID, lv.g, LP::P(lv), u, b, LP::q(lv), LP::r(lv), nullptr, h->stream, false, stop);
         launch_restrict<T>(lv.g, LP::r(lv), LP::b(lc), h->stream, stop);
@@ -626,9 +642,7 @@ static void vcycle_gmres(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool z
     }
     vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
     launch_prolong_add<T>(lv.g, LP::u(lc), u, h->stream, stop);
-    for (int s = 0; s < nu2; ++s)
-        launch_gmres_step<T>(lv.g, LP::P(lv), b, LP::q(lv), u, false, h->krylov_m, LP::gz(lv), h->d_gm, h->d_gm_parts,
-                             h->stream, stop);
+    for (int s = 0; s < nu2; ++s) other_smooth_step<T>(h, lv, b, u, false, stop);
 }
 
 template <typename T>
@@ -641,8 +655,8 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
         launch_coarse_apply<T>(h->aug, h->nc, b, u, h->stream, stop);
         return;
     }
-    if (h->opt.smoother == FFMG_SMOOTH_GMRES) {
-        vcycle_gmres<T>(h, l, b, u, zero_guess, stop);
+    if (h->opt.smoother == FFMG_SMOOTH_GMRES || h->opt.smoother == FFMG_SMOOTH_RBGS) {
+        vcycle_other<T>(h, l, b, u, zero_guess, stop);
         return;
     }
     if constexpr (sizeof(T) == 8) {
@@ -881,6 +895,13 @@ ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out)
 {
     if (!h || !b || !u || !u_out || u == u_out) return fail(h, FFMG_EINVAL, "null or aliased argument");
     Level &l0 = h->L[0];
+    if (h->opt.smoother == FFMG_SMOOTH_GMRES || h->opt.smoother == FFMG_SMOOTH_RBGS) {
+        if (h->L.size() < 2) return fail(h, FFMG_EINVAL, "a one-level hierarchy is solved exactly, not smoothed");
+        HIPCHK(h, hipMemcpyAsync(u_out, u, l0.g.N() * sizeof(cd), hipMemcpyDeviceToDevice, h->stream));
+        other_smooth_step<double>(h, l0, (const cd *)b, (cd *)u_out, false, nullptr);
+        HIPCHK(h, hipGetLastError());
+        return FFMG_OK;
+    }
     launch_stencil<double>(MODE_JACOBI, l0.g, l0.P64, (const cd *)u, (const cd *)b, l0.q, (cd *)u_out, nullptr,
                            h->stream);
     HIPCHK(h, hipGetLastError());

@@ -122,6 +122,12 @@ template <typename T>
 void launch_gmres_step(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero,
                        int m, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop);
 
+// One red-black Gauss-Seidel sweep in place on a level (red points, then
+// black; ffmg_rbgs.hip).
+template <typename T>
+void launch_rbgs_sweep(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u,
+                       hipStream_t s, const int *stop);
+
 // Full multigrid transfers: the finest right-hand side at the first coarse
 // level's nodes, divided by s = sqrt(*bnorm2 / N) (s = 1 when bnorm2 is
 // null), and uf = s P ec overwriting uf (inv_sqN = 1 / sqrt(N) of the finest

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libffmg.so")
 FFMG_OK, FFMG_EINVAL, FFMG_ENOMEM, FFMG_EDEVICE, FFMG_ENOCONV, FFMG_ERANGE, FFMG_ENAN = range(7)
 HELMHOLTZ, SCHRODINGER = 0, 1
 FP64, FP32_IR = 0, 1
-SMOOTH_JACOBI, SMOOTH_LEARNED, SMOOTH_GMRES = 0, 1, 2
+SMOOTH_JACOBI, SMOOTH_LEARNED, SMOOTH_GMRES, SMOOTH_RBGS = 0, 1, 2, 3
 FF_FP64, FF_BF16X3, FF_BF16X6 = 0, 1, 2
 
 

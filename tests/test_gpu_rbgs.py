@@ -1,0 +1,124 @@
+"""GPU parity of the red-black Gauss-Seidel smoother (Sec. 3.3) against the
+FP64 oracle: one sweep to 1e-12 (the update u + r / D in another rounding
+order), V-cycle iterates to 1e-11, solves in the oracle's cycle count at 30
+degrees (FP64; FP32-in-FP64 to the tolerance) and no convergence at 10 degrees
+on either side."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1211_4461_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ff():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1211_4461_amd import ffmg
+    ffmg.lib()
+    return ffmg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex128)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300)
+
+
+CASES = [
+    ("2d-63", lambda: W.small_2d(n=64)),
+    ("2d-127-ragged", lambda: W.bumps_2d(n=128, seed=5, k0=1.3, M=40)),
+    ("3d-31", lambda: W.radial_3d(32, L=6.0, n_az=8, n_pol=5)),
+]
+
+
+def problem(ff, orc, w, **opt):
+    h, _ = ff.setup_workload(w, options=ff.default_options(smoother=ff.SMOOTH_RBGS, **opt))
+    g = orc.Grid(w.dim, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+    return h, g, kappa, q, k0, b
+
+
+@pytest.mark.parametrize("name,mk", CASES)
+def test_rbgs_sweep_matches_oracle(ff, orc, name, mk):
+    w = mk()
+    h, g, kappa, q, k0, b = problem(ff, orc, w)
+    u0 = np.random.default_rng(5).standard_normal(g.shape) * (1 + 0.5j)
+    uo = torch.empty(g.shape, dtype=torch.complex128, device="cuda")
+    ff.mg_smooth(h, dev(b), dev(u0), uo)
+    ref = orc.rbgs_sweep(g, w.gamma, kappa, b, u0)
+    assert rel(host(uo) - u0, ref - u0) < 1e-12
+    h.destroy()
+
+
+@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("name,mk", CASES)
+def test_rbgs_vcycle_iterates_match_oracle(ff, orc, name, mk, tile):
+    w = mk()
+    h, g, kappa, q, k0, b = problem(ff, orc, w, nu1=1, nu2=1, tile_config=tile)
+    mg = orc.Multigrid(g, w.gamma, kappa, nu1=1, nu2=1, smoother="rbgs")
+    ud = torch.zeros(g.shape, dtype=torch.complex128, device="cuda")
+    bd = dev(b)
+    uo = np.zeros(g.shape, dtype=np.complex128)
+    for k in range(3):
+        ff.mg_vcycle(h, bd, ud)
+        uo = mg.vcycle(b, uo)
+        assert rel(host(ud), uo) < 1e-11, f"cycle {k + 1}"
+    h.destroy()
+
+
+def test_rbgs_solves_at_30_and_not_at_10_degrees(ff, orc):
+    w = W.small_2d(n=128)
+    g = orc.Grid(2, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    for deg in (30, 10):
+        w.gamma = math.radians(deg)
+        b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
+        uo, st, k, _ = orc.Multigrid(g, w.gamma, kappa, nu1=1, nu2=1, smoother="rbgs").solve(b, tol=1e-10,
+                                                                                           max_cycles=60)
+        h, _ = ff.setup_workload(w, options=ff.default_options(smoother=ff.SMOOTH_RBGS, nu1=1, nu2=1, max_cycles=60))
+        ud = torch.zeros(g.shape, dtype=torch.complex128, device="cuda")
+        info = ff.mg_solve(h, dev(b), ud, tol=1e-10, raise_on_noconv=False)
+        if deg == 30:
+            assert st == 0 and info.status == 0 and info.cycles == k
+            assert rel(host(ud), uo) < 1e-10
+            h32, _ = ff.setup_workload(w, options=ff.default_options(smoother=ff.SMOOTH_RBGS, nu1=1, nu2=1,
+                                                                     precision=ff.FP32_IR))
+            u32 = torch.zeros_like(ud)
+            i32 = ff.mg_solve(h32, dev(b), u32, tol=1e-10)
+            assert i32.status == 0 and i32.rel_residual <= 1e-10 and rel(host(u32), uo) < 1e-8
+            h32.destroy()
+        else:
+            assert st == orc.ENOCONV and info.status == ff.FFMG_ENOCONV
+        h.destroy()
+
+
+def test_mg_smooth_runs_the_handles_smoother(ff, orc):
+    """mg_smooth with a GMRES(m) handle is one GMRES(m) step (out of place),
+    bit for bit mg_gmres_smooth (in place)."""
+    w = W.small_2d(n=64)
+    h, _ = ff.setup_workload(w, options=ff.default_options(smoother=ff.SMOOTH_GMRES))
+    g = orc.Grid(2, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    b = dev(orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta))
+    u0 = dev(np.random.default_rng(6).standard_normal(g.shape) + 0j)
+    uo = torch.empty_like(u0)
+    ff.mg_smooth(h, b, u0, uo)
+    u1 = u0.clone()
+    ff.mg_gmres_smooth(h, b, u1)
+    torch.cuda.synchronize()
+    assert torch.equal(uo, u1)
+    h.destroy()
