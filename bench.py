@@ -23,6 +23,7 @@ same workload).
 from __future__ import annotations
 
 import argparse
+import collections
 import hashlib
 import json
 import math
@@ -69,14 +70,19 @@ KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3), ("ffgemm", 4))
 NET_FLOP_PER_POINT = 8 * 2736
 
 
-def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0, streams=1):
+def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0, streams=1,
+             pipelined=False):
     """Time `steps` maps.  The warm-up maps record every timed kernel; the one
     with the largest total time is the dominant kernel, and inside the timed
     region HIP events bracket only that kernel's launches.  fmg_cycles > 0:
     every solve starts from the full multigrid guess (k V-cycles per coarse
-    level) instead of u = 0.  streams = 2: maps alternate between two handles
-    on two streams, so that one map's far field (queued on its stream, the
-    host does not wait for it) runs while the next map is solved."""
+    level) instead of u = 0.  streams = D > 1: maps cycle through D handles on
+    D streams, so that one map's far field (queued on its stream, the host
+    does not wait for it) runs while the next map is solved.  pipelined: each
+    step begins its map's solve (mg_solve_begin) before it finishes the map
+    begun D - 1 steps earlier (mg_solve_end, far field queued), so D solves
+    are in flight from this one host thread; the timed region ends when every
+    map begun in it is finished."""
     opts = ff.default_options(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles)
     h, coef = ff.setup_workload(w, options=opts)
     from paper_1211_4461_amd import autotune
@@ -114,9 +120,8 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
                             autotune.device_arch(), ff.TUNE_TAIL, w.dim, [w.n - 1] * w.dim, 0, precision))}
     F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
     lanes = [(h, b, u, F, torch.cuda.current_stream())]
-    if streams == 2:
-        # a second handle on its own stream (default priority): maps alternate
-        # between the two, so one map's far field overlaps the next map's solve
+    for _ in range(streams - 1):
+        # further handles, each on its own stream (default priority)
         s2 = torch.cuda.Stream()
         with torch.cuda.stream(s2):
             h2, coef2 = ff.setup_workload(w, options=ff.default_options(precision=precision, ff_precision=ff_precision,
@@ -128,18 +133,40 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
     info = None
     last = [F]
     nstep = [0]
+    pending = collections.deque()
 
-    def step():
-        nonlocal info
-        h_, b_, u_, F_, s_ = lanes[nstep[0] % len(lanes)]
+    def begin_map():
+        ln = lanes[nstep[0] % len(lanes)]
         nstep[0] += 1
+        h_, b_, u_, F_, s_ = ln
         ff.mg_rhs_plane_wave(h_, w.eta, b_)
         if fmg_cycles == 0:
             with torch.cuda.stream(s_):
                 u_.zero_()
-        info = ff.mg_solve(h_, b_, u_, tol=w.tol)
+        return ln
+
+    def finish_map(info_, ln):
+        nonlocal info
+        h_, b_, u_, F_, s_ = ln
+        info = info_
         ff.farfield_map(h_, w.eta, u_, w.dirs, out=F_)   # device output: queued, not waited for
         last[0] = F_
+
+    def step():
+        ln = begin_map()
+        if not pipelined:
+            finish_map(ff.mg_solve(ln[0], ln[1], ln[2], tol=w.tol), ln)
+            return
+        ff.mg_solve_begin(ln[0], ln[1], ln[2], tol=w.tol)
+        pending.append(ln)
+        if len(pending) == len(lanes):   # the oldest lane is next: finish its map
+            old = pending.popleft()
+            finish_map(ff.mg_solve_end(old[0]), old)
+
+    def drain():
+        while pending:
+            old = pending.popleft()
+            finish_map(ff.mg_solve_end(old[0]), old)
 
     def read_all():
         out_ = {}
@@ -157,11 +184,13 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
 
     for _ in range(len(lanes)):
         step()                   # first map per lane: cold launches, plans, not ranked
+    drain()
     torch.cuda.synchronize()
     enable(0x1F)
     read_all()
     for _ in range(max(warmup - 1, 1) * len(lanes)):
         step()
+    drain()
     torch.cuda.synchronize()
     allk = read_all()
     dominant = max(bytes_per_point, key=lambda k: allk[k][0])
@@ -170,13 +199,15 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_poi
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
+    drain()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     live = read_all()[dominant]
     enable(0)
     out = {"ms_per_step": 1e3 * dt / steps, "maps_per_s": steps / dt, "cycles": info.cycles, "vcycles": info.vcycles,
            "rel_residual": info.rel_residual, "conv_factor": info.conv_factor, "F": last[0].cpu().numpy(),
-           "dominant": dominant, "live": live, "prof": allk, "tune": tune, "streams": len(lanes)}
+           "dominant": dominant, "live": live, "prof": allk, "tune": tune, "streams": len(lanes),
+           "pipelined": pipelined}
     for ln in lanes:
         ln[0].destroy()
     return out
@@ -587,6 +618,8 @@ def main():
     ap.add_argument("--no-gmres", action="store_true", help="skip the GMRES(3)-smoother workload")
     ap.add_argument("--one-stream", action="store_true",
                     help="one handle on one stream (no overlap of a map's far field with the next solve)")
+    ap.add_argument("--blocking", action="store_true",
+                    help="two streams, but each solve finished (mg_solve) before the next map is begun")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -632,10 +665,11 @@ def main():
     # coarse level); the zero-start V-cycle solves are reported beside them
     fk = 0 if args.zero_start else FMG_K
     ns = 1 if args.one_stream else 2
+    pipe = ns == 2 and not args.blocking
     mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed, fmg_cycles=fk,
-                     streams=ns)
+                     streams=ns, pipelined=pipe)
     plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2),
-                                                 args.warmup, bpp_plain, fmg_cycles=fk, streams=ns)
+                                                 args.warmup, bpp_plain, fmg_cycles=fk, streams=ns, pipelined=pipe)
     names = {"pre": "finest-level pre-smoothing: 2 FP32 Jacobi sweeps, residual and full weighting in one pass "
                     "(k_smooth_rr2d<float,*,1,16>)",
              "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1,%d>, "
@@ -650,6 +684,8 @@ def main():
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(dom, (mixed["tune"]["smooth"] or {}).get("tile_rows", 8)),
             "bytes_per_launch": bytes_alg, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": mixed["live"][1],
+            "timed_in": ("the headline's timed region, where each launch shares the GPU with the other solve in "
+                         "flight" if pipe else "the headline's timed region"),
             "warmup_GBs": {k: round(bpp_mixed[k] * N / (pr[k][0] / max(pr[k][1], 1) * 1e-3) / 1e9, 1)
                            for k in bpp_mixed if pr[k][1] > 0}}
 
@@ -670,8 +706,12 @@ def main():
                    "unknowns": N, "angles": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
                    "start": (f"full multigrid: {fk} V(2,2) per coarse level, then V-cycles on the finest grid"
                              if fk else "u = 0"),
-                   "streams": (f"{ns}: consecutive maps alternate between two handles on two streams, one map's "
-                               "far field runs while the next map is solved" if ns == 2 else "1"),
+                   "streams": ("2, pipelined: consecutive maps alternate between two handles on two streams; "
+                               "each map's solve is begun (mg_solve_begin) before the previous map is finished "
+                               "(mg_solve_end) and its far field queued, so two solves are in flight from one host "
+                               "thread" if pipe else
+                               "2: consecutive maps alternate between two handles on two streams, one map's far "
+                               "field runs while the next map is solved" if ns == 2 else "1"),
                    "form": "FP32 V-cycles in FP64 refinement + "
                            + {"bf16x6": "split-BF16 (3 parts, 6 products) MFMA far field, FP32 accumulation",
                               "bf16x3": "split-BF16 (2 parts, 3 products) MFMA far field, FP32 accumulation",
@@ -704,19 +744,29 @@ def main():
         # the other starts of the same solve: u = 0 (plain V-cycles) and other
         # numbers of V-cycles per coarse level in the full multigrid start
         fm = {}
-        forms_m = [(0, 1), (1, ns), (2, ns), (3, ns), (fk, 1)]
-        forms_p = [(0, 1), (1, ns), (2, ns), (fk, 1)]
+        # (V-cycles per coarse level, lanes, pipelined); k = 0: u = 0
+        forms_m = [(0, 1, False), (1, ns, pipe), (3, ns, pipe), (fk, 1, False), (fk, 2, False)]
+        forms_p = [(0, 1, False), (1, ns, pipe), (fk, 1, False), (fk, 2, False)]
         for prec, ffp_k, forms, tag, bpp in ((ffmg.FP32_IR, ffp, forms_m, "mixed", bpp_mixed),
                                               (ffmg.FP64, ffmg.FF_FP64, forms_p, "plain_fp64", bpp_plain)):
             if tag == "plain_fp64" and plain is None:
                 continue
             ref = mixed if tag == "mixed" else plain
-            for k, nsk in forms:
-                if (k, nsk) == (fk, ns) or (k == 0 and nsk != 1 and fk != 0):
+            for k, nsk, pk in forms:
+                if (k, nsk, pk) == (fk, ns, pipe) or (k == 0 and nsk != 1 and fk != 0):
                     continue
                 r = run_path(ffmg, torch, w, prec, ffp_k, max(args.steps // 2, 2), args.warmup, bpp, fmg_cycles=k,
-                             streams=nsk)
-                name = f"{tag}_{'zero_start' if k == 0 else f'fmg_k{k}'}" + ("_one_stream" if nsk == 1 and k else "")
+                             streams=nsk, pipelined=pk)
+                name = (f"{tag}_{'zero_start' if k == 0 else f'fmg_k{k}'}" + ("_one_stream" if nsk == 1 and k else "")
+                        + ("_blocking" if nsk == 2 and not pk else ""))
+                if tag == "mixed" and (k, nsk, pk) == (fk, 1, False) and r["dominant"] == dom:
+                    # the dominant kernel with no other solve beside it
+                    a_ms = r["live"][0] / max(r["live"][1], 1)
+                    a_gbs = bytes_alg / (a_ms * 1e-3) / 1e9
+                    line["roofline"]["isolated"] = {
+                        "form": "one solve in flight (one handle, one stream)", "achieved": round(a_gbs, 1),
+                        "frac": round(a_gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(a_ms * 1e3, 2),
+                        "launches": r["live"][1]}
                 fm[name] = {
                     "maps_per_s": round(r["maps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
                     "cycles": r["cycles"], "vcycles_finest": r["vcycles"], "rel_residual": r["rel_residual"],
@@ -726,7 +776,7 @@ def main():
         line["start_forms"] = fm
     if not args.no_concurrent:
         # maps of several incoming directions in flight at once (host threads,
-        # one handle and stream each); the headline keeps one solve at a time
+        # one handle and stream each, one host thread per direction)
         cc = {}
         for nt in (2, 4):
             cc[f"threads{nt}"] = run_concurrent(ffmg, torch, w, ffmg.FP32_IR, ffp, nt, max(args.steps // 2, 4), fk)

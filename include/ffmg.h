@@ -178,6 +178,25 @@ ffmg_status mg_fmg(ffmg_handle *h, const void *b, void *u, int k);
  * b = 0 returns u = 0 after 0 cycles.  info may be NULL.  Synchronises. */
 ffmg_status mg_solve(ffmg_handle *h, const void *b, void *u, double tol, ffmg_solve_info *info);
 
+/* mg_solve in two halves, for callers that keep several solves in flight from
+ * one host thread (one handle and stream each).  mg_solve_begin queues, on the
+ * handle's stream, everything mg_solve would run up to the end of its first
+ * batch of cycles (||b|| is formed and tested on the device), then returns
+ * without waiting for the GPU.  mg_solve_end waits for that batch, queues and
+ * waits for further batches until the stopping test holds, and returns what
+ * mg_solve would: the same u, bit for bit, the same status and info.  Until
+ * mg_solve_end returns, b and u must stay allocated and unmodified by the
+ * caller, and every other entry point that works on the handle's buffers
+ * (mg_solve, mg_vcycle, mg_fmg, the smoothers, mg_residual_norm,
+ * mg_rhs_plane_wave, farfield_map, mg_tune_*, mg_solve_batched) returns
+ * EINVAL for it.  mg_solve_begin: EINVAL for a null argument, tol outside
+ * (0, 1), a solve already pending, or the learned smoother (its fallback is
+ * decided on the host between cycles: use mg_solve).  mg_solve_end: EINVAL
+ * if no solve is pending; for a non-finite b it returns ENAN with u
+ * unspecified.  info may be NULL. */
+ffmg_status mg_solve_begin(ffmg_handle *h, const void *b, void *u, double tol);
+ffmg_status mg_solve_end(ffmg_handle *h, ffmg_solve_info *info);
+
 /* Far-field map (eq. FFmap moved onto the contour, eq. I2complex):
  *   F_m = e^{i d gamma} prod h_k sum_j exp(-i k0 alpha_m.z_j) q_j (u_in,j + u_j)
  * for n_dirs directions alpha_m (HOST double[n_dirs][dim], unit vectors).

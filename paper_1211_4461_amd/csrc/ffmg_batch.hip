@@ -477,6 +477,8 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
     if (!(tol > 0.0) || !(tol < 1.0)) return fail(h0, FFMG_EINVAL, "tol must lie in (0, 1)");
     for (int i = 0; i < count; ++i) {
         if (!hs[i] || !u[i]) return fail(h0, FFMG_EINVAL, "hs[%d] or u[%d] is null", i, i);
+        if (hs[i]->pend.active)
+            return fail(h0, FFMG_EINVAL, "hs[%d] has a solve begun by mg_solve_begin pending", i);
         for (int k = 0; k < 3; ++k)
             if (!isfinite(etas[3 * i + k])) return fail(h0, FFMG_EINVAL, "eta of instance %d is not finite", i);
     }

@@ -98,13 +98,23 @@ __global__ __launch_bounds__(256) void k_norm2(const cd *__restrict__ v, size_t 
 }
 
 // ||v||_2^2 into h->d_scalar (device) and *out (host).
+int norm2_blocks(size_t N) { return (int)std::min<size_t>((N + 255) / 256, 1024); }
+
 ffmg_status norm2_of(ffmg_handle *h, const cd *v, size_t N, double *out)
 {
-    int nb = (int)std::min<size_t>((N + 255) / 256, 1024);
+    const int nb = norm2_blocks(N);
     hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, h->stream, v, N, h->d_parts);
     HIPCHK(h, hipGetLastError());
     TRY(reduce_to_host(h, nb, out));
     return FFMG_OK;
+}
+
+// ||v||^2 into h->d_scalar, queued on the stream; the host does not wait.
+void enqueue_norm2(ffmg_handle *h, const cd *v, size_t N)
+{
+    const int nb = norm2_blocks(N);
+    hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, h->stream, v, N, h->d_parts);
+    launch_sum(h->d_parts, nb, h->d_scalar, h->stream);
 }
 
 // ||b - A u||_2 on the finest level, FP64.
@@ -755,6 +765,52 @@ void fmg_enqueue(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2
     else fmg_start<double>(h, b, u, k, nullptr);
 }
 
+// The fused FP32 2D refinement step writes the new iterate into the other of
+// two buffers (u and l0.t).
+bool fp32_pingpong(const ffmg_handle *h)
+{
+    return h->opt.precision == FFMG_FP32_IR && h->L[0].g.dim == 2 && h->opt.tile_config != TILE_REFERENCE;
+}
+
+// Queue nb steps (V-cycles, or FP32_IR refinement steps) of the pending solve,
+// each skipped on the device once the control block has stopped the solve,
+// then the copy of the control block into pinned host memory.
+ffmg_status enqueue_batch(ffmg_handle *h, int nb)
+{
+    PendingSolve &p = h->pend;
+    const int *stop = &h->d_ctl->done;
+    for (int i = 0; i < nb; ++i) {
+        enqueue_step(h, p.b, p.ua, p.ub, stop);
+        if (fp32_pingpong(h)) std::swap(p.ua, p.ub);
+    }
+    p.queued += nb;
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(h->h_ctl, h->d_ctl, sizeof(SolveCtl), hipMemcpyDeviceToHost, h->stream));
+    return FFMG_OK;
+}
+
+// Cycle counts, relative residual and rate of a finished solve.
+void fill_info(ffmg_handle *h, const SolveCtl &c, double bn2, int k_before_restart, ffmg_solve_info *inf)
+{
+    inf->cycles = std::max(c.k, 0) + k_before_restart;
+    inf->vcycles = inf->cycles * ((h->opt.precision == FFMG_FP32_IR)
+                                      ? (h->opt.inner_cycles > 0 ? h->opt.inner_cycles : DEFAULT_INNER_CYCLES) : 1);
+    const double bn = sqrt(bn2), rk = sqrt(c.rk2), r0 = sqrt(c.r0_2);
+    inf->rel_residual = rk / bn;
+    inf->conv_factor = (inf->cycles > 0 && r0 > 0) ? pow(rk / r0, 1.0 / inf->cycles) : 0.0;
+    h->last_cycles = inf->cycles;
+}
+
+ffmg_status done_status(ffmg_handle *h, const SolveCtl &c, int maxc)
+{
+    switch (c.done) {
+    case 1: return FFMG_OK;
+    case 2: return fail(h, FFMG_ENOCONV, "residual grew on 3 consecutive cycles");
+    case 4: return fail(h, FFMG_ENOCONV, "residual became non-finite at cycle %d", c.k);
+    default: return fail(h, FFMG_ENOCONV, "no convergence in %d cycles", maxc);
+    }
+}
+
 }  // namespace ffmg
 
 // =========================================================================
@@ -873,6 +929,7 @@ ffmg_status mg_level_shape(const ffmg_handle *h, int level, int64_t m[3])
 
 ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b)
 {
+    NOT_PENDING(h);
     if (!h || !eta || !b) return fail(h, FFMG_EINVAL, "null argument");
     double e[3] = {0, 0, 0};
     for (int k = 0; k < h->prob.dim; ++k) e[k] = eta[k];
@@ -893,6 +950,7 @@ ffmg_status mg_apply(ffmg_handle *h, const void *u, void *Au)
 
 ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out)
 {
+    NOT_PENDING(h);
     if (!h || !b || !u || !u_out || u == u_out) return fail(h, FFMG_EINVAL, "null or aliased argument");
     Level &l0 = h->L[0];
     if (h->opt.smoother == FFMG_SMOOTH_GMRES || h->opt.smoother == FFMG_SMOOTH_RBGS) {
@@ -910,6 +968,7 @@ ffmg_status mg_smooth(ffmg_handle *h, const void *b, const void *u, void *u_out)
 
 ffmg_status mg_learned_smooth(ffmg_handle *h, const void *b, void *u)
 {
+    NOT_PENDING(h);
     if (!h || !b || !u) return fail(h, FFMG_EINVAL, "null argument");
     if (h->opt.smoother != FFMG_SMOOTH_LEARNED) return fail(h, FFMG_EINVAL, "the handle has no learned smoother");
     if (!learned_level(h, 0)) return fail(h, FFMG_EINVAL, "the finest level does not use the learned smoother");
@@ -920,6 +979,7 @@ ffmg_status mg_learned_smooth(ffmg_handle *h, const void *b, void *u)
 
 ffmg_status mg_gmres_smooth(ffmg_handle *h, const void *b, void *u)
 {
+    NOT_PENDING(h);
     if (!h || !b || !u) return fail(h, FFMG_EINVAL, "null argument");
     if (h->opt.smoother != FFMG_SMOOTH_GMRES) return fail(h, FFMG_EINVAL, "the handle does not smooth with GMRES(m)");
     if (h->L.size() < 2) return fail(h, FFMG_EINVAL, "a one-level hierarchy is solved exactly, not smoothed");
@@ -934,12 +994,14 @@ double mg_jacobi_factor(const ffmg_handle *h) { return h ? h->rho_jacobi : 0.0; 
 
 ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, double *rnorm)
 {
+    NOT_PENDING(h);
     if (!h || !b || !u || !rnorm) return fail(h, FFMG_EINVAL, "null argument");
     return resid_norm(h, (const cd *)b, (const cd *)u, rnorm);
 }
 
 ffmg_status mg_vcycle(ffmg_handle *h, const void *b, void *u)
 {
+    NOT_PENDING(h);
     if (!h || !b || !u) return fail(h, FFMG_EINVAL, "null argument");
     vcycle<double>(h, 0, (const cd *)b, (cd *)u, false, nullptr);
     HIPCHK(h, hipGetLastError());
@@ -948,6 +1010,7 @@ ffmg_status mg_vcycle(ffmg_handle *h, const void *b, void *u)
 
 ffmg_status mg_fmg(ffmg_handle *h, const void *bv, void *uv, int k)
 {
+    NOT_PENDING(h);
     if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
     if (k < 0 || k > 64) return fail(h, FFMG_EINVAL, "k must be in [0, 64]");
     const cd *b = (const cd *)bv;
@@ -964,7 +1027,10 @@ ffmg_status mg_fmg(ffmg_handle *h, const void *bv, void *uv, int k)
     return FFMG_OK;
 }
 
-ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_solve_info *info)
+// The learned smoother's solve: the host reads the control block after each
+// batch of cycles and may switch the rest of the solve to Jacobi.
+static ffmg_status solve_host_controlled(ffmg_handle *h, const void *bv, void *uv, double tol,
+                                         ffmg_solve_info *info)
 {
     if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
     if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, FFMG_EINVAL, "tol must lie in (0, 1)");
@@ -1029,8 +1095,7 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
         int nb = std::min(batch, maxc - queued);
         for (int i = 0; i < nb; ++i) {
             enqueue_step(h, b, ua, ub, stop);
-            if (h->opt.precision == FFMG_FP32_IR && l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE)
-                std::swap(ua, ub);
+            if (fp32_pingpong(h)) std::swap(ua, ub);
         }
         queued += nb;
         HIPCHK(h, hipGetLastError());
@@ -1077,22 +1142,103 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
     }
     // the fused refinement step alternates u between u and l0.t: after an odd
     // number of completed steps the iterate is in l0.t
-    const bool pingpong = (h->opt.precision == FFMG_FP32_IR && l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE);
-    if (pingpong && (c.k % 2) == 1) HIPCHK(h, hipMemcpyAsync(u, l0.t, N * sizeof(cd), hipMemcpyDeviceToDevice, h->stream));
+    if (fp32_pingpong(h) && (c.k % 2) == 1) HIPCHK(h, hipMemcpyAsync(u, l0.t, N * sizeof(cd), hipMemcpyDeviceToDevice, h->stream));
     h->learned_on = (h->opt.smoother == FFMG_SMOOTH_LEARNED);   // the fallback lasts for this solve only
-    inf.cycles = std::max(c.k, 0) + k_before_restart;
-    inf.vcycles = inf.cycles * ((h->opt.precision == FFMG_FP32_IR)
-                                    ? (h->opt.inner_cycles > 0 ? h->opt.inner_cycles : DEFAULT_INNER_CYCLES) : 1);
-    const double bn = sqrt(bn2), rk = sqrt(c.rk2), r0 = sqrt(c.r0_2);
-    inf.rel_residual = rk / bn;
-    inf.conv_factor = (inf.cycles > 0 && r0 > 0) ? pow(rk / r0, 1.0 / inf.cycles) : 0.0;
-    h->last_cycles = inf.cycles;
-    switch (c.done) {
-    case 1: return finish(FFMG_OK);
-    case 2: return finish(fail(h, FFMG_ENOCONV, "residual grew on 3 consecutive cycles"));
-    case 4: return finish(fail(h, FFMG_ENOCONV, "residual became non-finite at cycle %d", c.k));
-    default: return finish(fail(h, FFMG_ENOCONV, "no convergence in %d cycles", maxc));
+    fill_info(h, c, bn2, k_before_restart, &inf);
+    return finish(done_status(h, c, maxc));
+}
+
+
+ffmg_status mg_solve_begin(ffmg_handle *h, const void *bv, void *uv, double tol)
+{
+    if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
+    NOT_PENDING(h);
+    if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, FFMG_EINVAL, "tol must lie in (0, 1)");
+    if (h->opt.smoother == FFMG_SMOOTH_LEARNED)
+        return fail(h, FFMG_EINVAL, "the learned smoother's fallback is decided on the host between cycles: use mg_solve");
+    const cd *b = (const cd *)bv;
+    cd *u = (cd *)uv;
+    PendingSolve &p = h->pend;
+    Level &l0 = h->L[0];
+    const size_t N = l0.g.N();
+    if (!p.e0) {
+        HIPCHK(h, hipEventCreate(&p.e0));
+        HIPCHK(h, hipEventCreate(&p.e1));
     }
+    HIPCHK(h, hipEventRecord(p.e0, h->stream));
+    enqueue_norm2(h, b, N);   // ||b||^2 -> h->d_scalar; b = 0 or non-finite sets the stop code 5 in the control block
+    launch_ctl_init(h->d_ctl, h->d_scalar, tol, N, h->opt.max_cycles, h->stream);
+    h->learned_on = false;
+    if (h->opt.fmg_cycles > 0) fmg_enqueue(h, b, u, h->opt.fmg_cycles, h->d_scalar);
+    // initial residual (cycle 0)
+    if (h->opt.precision == FFMG_FP64)
+        launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
+    else
+        launch_resid_to_f32_ctl(l0.g, l0.P64, u, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, nullptr);
+    launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
+    HIPCHK(h, hipGetLastError());
+    p.b = b;
+    p.u = p.ua = u;
+    p.ub = l0.t;
+    p.queued = 0;
+    // the first batch: as many steps as the previous solve took (4 at first)
+    const int batch = std::min(h->last_cycles > 0 ? h->last_cycles : 4, h->opt.max_cycles);
+    TRY(enqueue_batch(h, batch));
+    p.active = true;
+    return FFMG_OK;
+}
+
+ffmg_status mg_solve_end(ffmg_handle *h, ffmg_solve_info *info)
+{
+    if (!h) return FFMG_EINVAL;
+    PendingSolve &p = h->pend;
+    if (!p.active) return fail(h, FFMG_EINVAL, "no solve begun by mg_solve_begin is pending on this handle");
+    p.active = false;
+    ffmg_solve_info inf{};
+    auto finish = [&](ffmg_status s) {
+        (void)hipEventRecord(p.e1, h->stream);
+        (void)hipEventSynchronize(p.e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, p.e0, p.e1);
+        inf.status = s;
+        inf.t_solve_ms = ms;
+        if (info) *info = inf;
+        return s;
+    };
+    Level &l0 = h->L[0];
+    const size_t N = l0.g.N();
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    SolveCtl c = *h->h_ctl;
+    if (c.done == 5) {
+        if (c.b2 == 0.0) {   // b = 0: u = 0 after 0 cycles
+            launch_zero<double>(p.u, N, h->stream, nullptr);
+            HIPCHK(h, hipGetLastError());
+            return finish(FFMG_OK);
+        }
+        return finish(fail(h, FFMG_ENAN, "right-hand side holds non-finite values"));
+    }
+    // further batches of two steps until the control block stops the solve
+    const int maxc = h->opt.max_cycles;
+    while (!c.done && p.queued < maxc) {
+        TRY(enqueue_batch(h, std::min(2, maxc - p.queued)));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        c = *h->h_ctl;
+    }
+    // the fused refinement step alternates the iterate between u and l0.t:
+    // after an odd number of completed steps it is in l0.t
+    if (fp32_pingpong(h) && (c.k % 2) == 1)
+        HIPCHK(h, hipMemcpyAsync(p.u, l0.t, N * sizeof(cd), hipMemcpyDeviceToDevice, h->stream));
+    fill_info(h, c, c.b2, 0, &inf);
+    return finish(done_status(h, c, maxc));
+}
+
+ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_solve_info *info)
+{
+    if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
+    NOT_PENDING(h);
+    if (h->opt.smoother == FFMG_SMOOTH_LEARNED) return solve_host_controlled(h, bv, uv, tol, info);
+    TRY(mg_solve_begin(h, bv, uv, tol));
+    return mg_solve_end(h, info);
 }
 
 // Validation, the plane-wave factors and the far-field plan for n_dirs
@@ -1164,6 +1310,7 @@ extern "C" {
 ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
                          void *F)
 {
+    NOT_PENDING(h);
     if (!F) return fail(h, FFMG_EINVAL, "F is null");
     // output: device pointer directly, host pointer through a staging buffer
     hipPointerAttribute_t attr;
@@ -1245,6 +1392,7 @@ ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant)
 
 ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant)
 {
+    NOT_PENDING(h);
     if (!h) return FFMG_EINVAL;
     if (variant < 0 || variant >= mg_tune_variants(h, tunable))
         return fail(h, FFMG_EINVAL, "variant %d out of range for tunable %d", variant, tunable);
@@ -1265,6 +1413,7 @@ ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant)
 ffmg_status mg_tune_farfield(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
                              int reps, double *times_ms, int n_times, int *best)
 {
+    NOT_PENDING(h);
     if (!h || reps < 1) return fail(h, FFMG_EINVAL, "null handle or reps < 1");
     int pi = -1;
     TRY(ff_begin(h, eta, u, n_dirs, dirs, &pi));
@@ -1314,6 +1463,7 @@ ffmg_status mg_tune_farfield(ffmg_handle *h, const double eta[3], const void *u,
 ffmg_status mg_tune_solve(ffmg_handle *h, int tunable, const void *b, void *u, double tol, int reps, double *times_ms,
                           int n_times, int *best)
 {
+    NOT_PENDING(h);
     if (!h || !b || !u || reps < 1) return fail(h, FFMG_EINVAL, "null argument or reps < 1");
     if (tunable != FFMG_TUNE_TAIL && tunable != FFMG_TUNE_SMOOTH && tunable != FFMG_TUNE_PRE &&
         tunable != FFMG_TUNE_SMOOTH_COARSE)

@@ -38,6 +38,18 @@ struct Batch;   // batched-solve workspace (ffmg_batch.hip)
 
 }  // namespace ffmg
 
+namespace ffmg {
+// A solve started by mg_solve_begin and not yet finished by mg_solve_end.
+struct PendingSolve {
+    bool active = false;
+    const cd *b = nullptr;
+    cd *u = nullptr;
+    cd *ua = nullptr, *ub = nullptr; // current iterate / the other buffer of the FP32 2D step
+    int queued = 0;                  // steps queued so far
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+}  // namespace ffmg
+
 struct ffmg_handle {
     uint64_t serial = 0;             // unique per handle of this process
     ffmg_problem prob{};
@@ -54,6 +66,7 @@ struct ffmg_handle {
     ffmg::SolveCtl *d_ctl = nullptr; // device solve control
     ffmg::SolveCtl *h_ctl = nullptr; // pinned copy
     int last_cycles = 0;             // cycles of the previous solve (batch sizing)
+    ffmg::PendingSolve pend;         // mg_solve_begin .. mg_solve_end
     int krylov_m = 0;                // GMRES(m) smoother: m
     double *d_gm = nullptr;          // its per-step scalars (GM_S doubles)
     double *d_gm_parts = nullptr;    // and partial sums (GM_PARTS doubles)
@@ -127,6 +140,15 @@ bool learned_level(const ffmg_handle *h, int l);
         if (e_ != hipSuccess)                                                                                       \
             return ffmg::fail((h), e_ == hipErrorOutOfMemory ? FFMG_ENOMEM : FFMG_EDEVICE, "%s: %s (%s:%d)", #x,    \
                               hipGetErrorString(e_), __FILE__, __LINE__);                                           \
+    } while (0)
+
+// Entry points that touch a handle's buffers refuse to run while a solve
+// begun by mg_solve_begin is still pending on it.
+#define NOT_PENDING(h)                                                                                              \
+    do {                                                                                                            \
+        if ((h) && (h)->pend.active)                                                                                \
+            return ffmg::fail((h), FFMG_EINVAL,                                                                     \
+                              "a solve begun by mg_solve_begin is pending on this handle: call mg_solve_end first"); \
     } while (0)
 
 #define TRY(x)                                                                                                      \

@@ -40,7 +40,8 @@ struct SolveCtl {
     double prev2;      // ||r_{k-1}||^2
     double scale_cur;  // the FP32 right-hand side now in use is r / scale_cur
     double scale_next; // the next one is written as r / scale_next
-    int done;          // 0 running, 1 converged, 2 residual grew 3 times, 3 cycle limit, 4 non-finite
+    int done;          // 0 running, 1 converged, 2 residual grew 3 times, 3 cycle limit, 4 non-finite,
+                       // 5 b = 0 or non-finite (set at init: nothing runs)
     int k;             // completed cycles / refinement steps
     int grow;
     int max_cycles;

@@ -742,7 +742,11 @@ __global__ void k_ctl_init(SolveCtl *ctl, const double *__restrict__ bnorm2, dou
                            int max_cycles)
 {
     if (threadIdx.x != 0) return;
-    ctl_init_store(ctl, bnorm2[0], tol, inv_sqN, max_cycles);
+    const double b2 = bnorm2[0];
+    ctl_init_store(ctl, b2, tol, inv_sqN, max_cycles);
+    // b = 0 (solution 0) or a non-finite b: every later kernel of the solve
+    // sees the stop flag and does nothing; the host decides from b2
+    if (!(b2 > 0.0) || !isfinite(b2)) ctl->done = 5;
 }
 
 // One update from the n per-block partial sums of |r_k|^2 (256 threads).

@@ -66,7 +66,7 @@ EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup
            "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_tune_solve", "mg_solve_batched",
            "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights", "ml_loss_grad",
            "ml_train_step", "ml_net_last_error", "ml_net_destroy", "mg_learned_smooth", "mg_jacobi_factor",
-           "mg_gmres_smooth"]
+           "mg_gmres_smooth", "mg_solve_begin", "mg_solve_end"]
 
 
 def lib():
@@ -88,6 +88,8 @@ def lib():
     L.mg_vcycle.argtypes = [vp, vp, vp]
     L.mg_fmg.argtypes = [vp, vp, vp, ip]
     L.mg_solve.argtypes = [vp, vp, vp, dp, ctypes.POINTER(SolveInfo)]
+    L.mg_solve_begin.argtypes = [vp, vp, vp, dp]
+    L.mg_solve_end.argtypes = [vp, ctypes.POINTER(SolveInfo)]
     L.farfield_map.argtypes = [vp, vp, vp, ip, vp, vp]
     L.mg_apply.argtypes = [vp, vp, vp]
     L.mg_smooth.argtypes = [vp, vp, vp, vp]
@@ -256,6 +258,21 @@ def mg_solve(h: Handle, b, u, tol=1e-10, raise_on_noconv=True):
     st = lib().mg_solve(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol), ctypes.byref(info))
     if st != FFMG_OK and (st != FFMG_ENOCONV or raise_on_noconv):
         h._check(st, "mg_solve")
+    return info
+
+
+def mg_solve_begin(h: Handle, b, u, tol=1e-10):
+    """Queue a solve on the handle's stream and return without waiting;
+    b and u must stay untouched until mg_solve_end."""
+    h._check(lib().mg_solve_begin(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol)), "mg_solve_begin")
+
+
+def mg_solve_end(h: Handle, raise_on_noconv=True):
+    """Finish the solve begun by mg_solve_begin; returns its SolveInfo."""
+    info = SolveInfo()
+    st = lib().mg_solve_end(h.ptr, ctypes.byref(info))
+    if st != FFMG_OK and (st != FFMG_ENOCONV or raise_on_noconv):
+        h._check(st, "mg_solve_end")
     return info
 
 
