@@ -675,19 +675,33 @@ def main():
              "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1,%d>, "
                      "the tuned tile height)" % (mixed["tune"]["smooth"] or {}).get("tile_rows", 8),
              "refine": "FP64 update + residual of the refinement loop (k_refine2d)"}
-    pr = mixed["prof"]
-    dom = mixed["dominant"]
-    avg_ms = mixed["live"][0] / max(mixed["live"][1], 1)
+    # The dominant kernel's duration.  Its launches are timed by events the
+    # runtime stamps on the launch itself.  With two solves in flight those
+    # stamps also count the time a launch waits behind the other stream's
+    # workgroups, so the kernel is timed in the same maps with one solve in
+    # flight (one handle, one stream); the figure from the headline's own
+    # timed region is reported beside it.
+    iso = (run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, max(args.steps // 2, 2), args.warmup, bpp_mixed,
+                    fmg_cycles=fk, streams=1) if ns > 1 else mixed)
+    pr = iso["prof"]
+    dom = iso["dominant"]
+    avg_ms = iso["live"][0] / max(iso["live"][1], 1)
     bytes_alg = bpp_mixed[dom] * N
     achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
     roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom, (mixed["tune"]["smooth"] or {}).get("tile_rows", 8)),
-            "bytes_per_launch": bytes_alg, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": mixed["live"][1],
-            "timed_in": ("the headline's timed region, where each launch shares the GPU with the other solve in "
-                         "flight" if pipe else "the headline's timed region"),
+            "traffic": measured_traffic(dom, (iso["tune"]["smooth"] or {}).get("tile_rows", 8)),
+            "bytes_per_launch": bytes_alg, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": iso["live"][1],
+            "timed_in": "the same maps with one solve in flight (one handle, one stream), timed after the headline",
             "warmup_GBs": {k: round(bpp_mixed[k] * N / (pr[k][0] / max(pr[k][1], 1) * 1e-3) / 1e9, 1)
                            for k in bpp_mixed if pr[k][1] > 0}}
+    if ns > 1 and mixed["dominant"] == dom:
+        h_ms = mixed["live"][0] / max(mixed["live"][1], 1)
+        h_gbs = bytes_alg / (h_ms * 1e-3) / 1e9
+        roof["in_headline_region"] = {
+            "avg_launch_us": round(h_ms * 1e3, 2), "achieved": round(h_gbs, 1), "frac": round(h_gbs / HBM_PEAK_GBS, 4),
+            "launches": mixed["live"][1],
+            "note": "two solves in flight: each launch's interval includes its wait behind the other stream"}
 
     line = {
         "metric": "far-field maps/sec at 1e-6 rel error: plain FP64 MG vs mixed-prec/learned MG",
@@ -755,18 +769,13 @@ def main():
             for k, nsk, pk in forms:
                 if (k, nsk, pk) == (fk, ns, pipe) or (k == 0 and nsk != 1 and fk != 0):
                     continue
-                r = run_path(ffmg, torch, w, prec, ffp_k, max(args.steps // 2, 2), args.warmup, bpp, fmg_cycles=k,
-                             streams=nsk, pipelined=pk)
+                if tag == "mixed" and (k, nsk, pk) == (fk, 1, False) and iso is not mixed:
+                    r = iso     # already timed for the roofline
+                else:
+                    r = run_path(ffmg, torch, w, prec, ffp_k, max(args.steps // 2, 2), args.warmup, bpp,
+                                 fmg_cycles=k, streams=nsk, pipelined=pk)
                 name = (f"{tag}_{'zero_start' if k == 0 else f'fmg_k{k}'}" + ("_one_stream" if nsk == 1 and k else "")
                         + ("_blocking" if nsk == 2 and not pk else ""))
-                if tag == "mixed" and (k, nsk, pk) == (fk, 1, False) and r["dominant"] == dom:
-                    # the dominant kernel with no other solve beside it
-                    a_ms = r["live"][0] / max(r["live"][1], 1)
-                    a_gbs = bytes_alg / (a_ms * 1e-3) / 1e9
-                    line["roofline"]["isolated"] = {
-                        "form": "one solve in flight (one handle, one stream)", "achieved": round(a_gbs, 1),
-                        "frac": round(a_gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(a_ms * 1e3, 2),
-                        "launches": r["live"][1]}
                 fm[name] = {
                     "maps_per_s": round(r["maps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
                     "cycles": r["cycles"], "vcycles_finest": r["vcycles"], "rel_residual": r["rel_residual"],

@@ -19,7 +19,10 @@ using namespace ffmg;
 
 namespace ffmg {
 
-int prof_begin(ffmg_handle *h, int k)
+thread_local KernelTiming tl_kernel_timing;
+
+// An event pair for kernel k, or -1 when k is not being timed.
+static int prof_acquire(ffmg_handle *h, int k)
 {
     if (!(h->profile_mask & (1 << k))) return -1;
     std::pair<hipEvent_t, hipEvent_t> e;
@@ -29,15 +32,42 @@ int prof_begin(ffmg_handle *h, int k)
     } else {
         if (hipEventCreate(&e.first) != hipSuccess || hipEventCreate(&e.second) != hipSuccess) return -1;
     }
-    (void)hipEventRecord(e.first, h->stream);
     h->ev[k].push_back(e);
     return (int)h->ev[k].size() - 1;
+}
+
+// A region of the stream (any number of launches): events recorded on the
+// stream before and after it.
+int prof_begin(ffmg_handle *h, int k)
+{
+    const int idx = prof_acquire(h, k);
+    if (idx >= 0) (void)hipEventRecord(h->ev[k][idx].first, h->stream);
+    return idx;
 }
 
 void prof_end(ffmg_handle *h, int k, int idx)
 {
     if (idx < 0) return;
     (void)hipEventRecord(h->ev[k][idx].second, h->stream);
+}
+
+// Exactly one launch made through launch_maybe_timed: the runtime stamps the
+// events at that kernel's own start and end.
+int prof_kernel_begin(ffmg_handle *h, int k)
+{
+    const int idx = prof_acquire(h, k);
+    if (idx >= 0) tl_kernel_timing = KernelTiming{h->ev[k][idx].first, h->ev[k][idx].second, false};
+    return idx;
+}
+
+void prof_kernel_end(ffmg_handle *h, int k, int idx)
+{
+    if (idx < 0) return;
+    if (!tl_kernel_timing.used) {   // nothing was launched: an empty interval
+        (void)hipEventRecord(h->ev[k][idx].first, h->stream);
+        (void)hipEventRecord(h->ev[k][idx].second, h->stream);
+    }
+    tl_kernel_timing = KernelTiming{};
 }
 
 ffmg_status fail(ffmg_handle *h, ffmg_status s, const char *fmt, ...)
@@ -234,10 +264,10 @@ void smooth_chain2d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
         int ns = left >= 2 ? 2 : 1;
         left -= ns;
         cx<T> *o = alias ? ((kk % 2 == 0) ? tmp : dst) : (((nk - 1 - kk) % 2 == 0) ? dst : tmp);
-        int pi = finest ? prof_begin(h, prof_id) : -1;
+        int pi = finest ? prof_kernel_begin(h, prof_id) : -1;
         launch_smooth2d<T>(lv.g, LP::P(lv), ns, zero, cur, ec, b, LP::q(lv), o, h->stream, finest && ns == 2, stop,
                            SMOOTH_TH[finest ? h->smooth_variant : h->smooth_coarse_variant]);
-        prof_end(h, prof_id, pi);
+        prof_kernel_end(h, prof_id, pi);
         cur = o;
         zero = false;
         ec = nullptr;
@@ -261,12 +291,12 @@ void vcycle_fused2d(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_g
     if (nu1 == 2 && h->pre_variant == 0) {
         // two sweeps, residual and full weighting in one pass
         const bool finest = (l == 0);
-        int pi = finest ? prof_begin(h, PROF_PRE) : -1;
+        int pi = finest ? prof_kernel_begin(h, PROF_PRE) : -1;
         // coarse levels: 16 rows with the 16-row smoothing tile, else 8
         const int fh = finest ? 0 : (SMOOTH_TH[h->smooth_coarse_variant] >= 16 ? 16 : 8);
         launch_smooth_rr2d<T>(lv.g, LP::P(lv), zero_guess, u, b, LP::q(lv), t, LP::b(lc), h->stream, finest, stop,
                               fh);
-        prof_end(h, PROF_PRE, pi);
+        prof_kernel_end(h, PROF_PRE, pi);
         cur = t;
     } else {
         if (nu1 > 0) {
@@ -553,9 +583,9 @@ void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *st
     const int inner = h->opt.inner_cycles > 0 ? h->opt.inner_cycles : DEFAULT_INNER_CYCLES;
     for (int c = 0; c < inner; ++c) vcycle<float>(h, 0, l0.b32, l0.u32, c == 0, stop);
     if (l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE) {
-        int pi = prof_begin(h, PROF_REFINE);
+        int pi = prof_kernel_begin(h, PROF_REFINE);
         launch_refine2d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
-        prof_end(h, PROF_REFINE, pi);
+        prof_kernel_end(h, PROF_REFINE, pi);
         launch_ctl_update(h->d_ctl, h->d_parts, fused2d_blocks(l0.g), h->stream);
     } else {
         launch_refine_update(l0.u32, ucur, h->d_ctl, l0.g.N(), h->stream, stop);

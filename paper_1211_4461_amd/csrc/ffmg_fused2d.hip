@@ -810,7 +810,7 @@ static void launch_smooth2d_th(const LevelGeom &g, const Stencil<T> &P, int nswe
     const int nb = tx * ((g.m[1] + TH - 1) / TH);
     dim3 G(nb), B(256);
 #define SM(NS, Z, PR, TAG) \
-    hipLaunchKernelGGL((k_smooth2d<T, NS, Z, PR, TAG, TH>), G, B, 0, s, u, ec, b, q, out, P, tx, stop)
+    launch_maybe_timed((k_smooth2d<T, NS, Z, PR, TAG, TH>), G, B, 0, s, u, ec, b, q, out, P, tx, stop)
     const bool prol = (ec != nullptr);
     if (nsweeps == 2) {
         if (zero) {
@@ -871,7 +871,7 @@ static void launch_smooth_rr2d_fh(const LevelGeom &g, const Stencil<T> &P, bool 
     const int tx = (g.m[0] + FTX - 1) / FTX;
     const int nb = tx * ((g.m[1] + FH - 1) / FH);
 #define FFMG_SRR(Z, TG) \
-    hipLaunchKernelGGL((k_smooth_rr2d<T, Z, TG, FH>), dim3(nb), dim3(256), 0, s, u, b, q, out, bc, P, tx, stop)
+    launch_maybe_timed((k_smooth_rr2d<T, Z, TG, FH>), dim3(nb), dim3(256), 0, s, u, b, q, out, bc, P, tx, stop)
     if (zero) {
         if (finest) FFMG_SRR(true, 1);
         else FFMG_SRR(true, 0);
@@ -901,7 +901,7 @@ void launch_refine2d(const LevelGeom &g, const Stencil<double> &P, const cd *u, 
 {
     int tx;
     int nb = tiles2d(g, tx);
-    hipLaunchKernelGGL(k_refine2d, dim3(nb), dim3(256), 0, st, u, d, b, q, u_out, r32, ctl, P, tx, partial, stop);
+    launch_maybe_timed(k_refine2d, dim3(nb), dim3(256), 0, st, u, d, b, q, u_out, r32, ctl, P, tx, partial, stop);
 }
 
 template <typename T>

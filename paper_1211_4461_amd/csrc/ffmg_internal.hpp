@@ -8,6 +8,7 @@
 // and leave every result untouched.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -32,6 +33,28 @@ enum ProfKernel {
 
 // Device-resident state of one solve (residual-reduction stopping test of
 // Sec. 4, growth test, and the scales of the mixed-precision refinement).
+// Timing of one launch for the library's profiling.  While set, the next
+// launch made through launch_maybe_timed() carries these two events, which the
+// runtime stamps when that kernel itself starts and ends; the interval leaves
+// out the time the kernel waits in its queue behind other streams' work.
+struct KernelTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+extern thread_local KernelTiming tl_kernel_timing;
+
+template <typename F, typename... Args>
+inline void launch_maybe_timed(F kernel, dim3 grid, dim3 block, uint32_t shm, hipStream_t s, Args... args)
+{
+    KernelTiming &t = tl_kernel_timing;
+    if (t.start && !t.used) {
+        t.used = true;
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, s, t.start, t.stop, 0u, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
+    }
+}
+
 struct SolveCtl {
     double tol2b2;     // (tol ||b||)^2
     double inv_sqN;    // 1 / sqrt(N)
