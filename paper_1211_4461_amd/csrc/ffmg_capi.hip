@@ -940,6 +940,8 @@ void mg_destroy(ffmg_handle *h)
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
     }
+    if (h->pend.e0) (void)hipEventDestroy(h->pend.e0);
+    if (h->pend.e1) (void)hipEventDestroy(h->pend.e1);
     if (h->ff) ff_plan_destroy(h->ff);
     if (h->batch) batch_destroy(h->batch);
     for (void *p : h->allocs) (void)hipFree(p);
