@@ -1201,17 +1201,25 @@ ffmg_status mg_solve_begin(ffmg_handle *h, const void *bv, void *uv, double tol)
     enqueue_norm2(h, b, N);   // ||b||^2 -> h->d_scalar; b = 0 or non-finite sets the stop code 5 in the control block
     launch_ctl_init(h->d_ctl, h->d_scalar, tol, N, h->opt.max_cycles, h->stream);
     h->learned_on = false;
-    if (h->opt.fmg_cycles > 0) fmg_enqueue(h, b, u, h->opt.fmg_cycles, h->d_scalar);
+    // The fused FP32 step alternates the iterate between u and l0.t.  The
+    // full multigrid start overwrites u, so it may as well be written into
+    // l0.t: when the previous solve took an odd number of steps, starting
+    // there makes the iterate of a solve with the same count end in u, with
+    // no copy at the end.
+    p.flip = h->opt.fmg_cycles > 0 && fp32_pingpong(h) && (h->last_cycles % 2) == 1;
+    cd *u0 = p.flip ? l0.t : u;
+    if (h->opt.fmg_cycles > 0) fmg_enqueue(h, b, u0, h->opt.fmg_cycles, h->d_scalar);
     // initial residual (cycle 0)
     if (h->opt.precision == FFMG_FP64)
-        launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
+        launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u0, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
     else
-        launch_resid_to_f32_ctl(l0.g, l0.P64, u, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, nullptr);
+        launch_resid_to_f32_ctl(l0.g, l0.P64, u0, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, nullptr);
     launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
     HIPCHK(h, hipGetLastError());
     p.b = b;
-    p.u = p.ua = u;
-    p.ub = l0.t;
+    p.u = u;
+    p.ua = u0;
+    p.ub = p.flip ? u : l0.t;
     p.queued = 0;
     // the first batch: as many steps as the previous solve took (4 at first)
     const int batch = std::min(h->last_cycles > 0 ? h->last_cycles : 4, h->opt.max_cycles);
@@ -1256,9 +1264,10 @@ ffmg_status mg_solve_end(ffmg_handle *h, ffmg_solve_info *info)
         HIPCHK(h, hipStreamSynchronize(h->stream));
         c = *h->h_ctl;
     }
-    // the fused refinement step alternates the iterate between u and l0.t:
-    // after an odd number of completed steps it is in l0.t
-    if (fp32_pingpong(h) && (c.k % 2) == 1)
+    // the fused refinement step alternates the iterate between the start
+    // buffer and the other one: after an odd number of completed steps it is
+    // in the other
+    if (fp32_pingpong(h) && ((c.k % 2) == 1) != p.flip)
         HIPCHK(h, hipMemcpyAsync(p.u, l0.t, N * sizeof(cd), hipMemcpyDeviceToDevice, h->stream));
     fill_info(h, c, c.b2, 0, &inf);
     return finish(done_status(h, c, maxc));

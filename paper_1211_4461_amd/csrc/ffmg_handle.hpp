@@ -46,6 +46,7 @@ struct PendingSolve {
     cd *u = nullptr;
     cd *ua = nullptr, *ub = nullptr; // current iterate / the other buffer of the FP32 2D step
     int queued = 0;                  // steps queued so far
+    bool flip = false;               // the start was written into l0.t instead of u
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 }  // namespace ffmg

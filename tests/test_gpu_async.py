@@ -206,3 +206,43 @@ def test_pending_solve_guards(ff):
     assert info.status == 0 and info.rel_residual <= 1e-10
     assert ff.mg_solve(h, b, u, tol=1e-10).status == 0
     h.destroy()
+
+
+def test_start_buffer_parity_matches_a_fresh_handle(ff):
+    """With the full multigrid start the first buffer of the FP32 ping-pong
+    follows the previous solve's step count; a solve whose count differs from
+    the previous one's (the iterate then ends in the work buffer and is
+    copied) and one whose count agrees give the bits of a fresh handle."""
+    w = W.bumps_2d(n=256, seed=9, M=8)
+    opt = dict(precision=1, fmg_cycles=2)
+
+    def fresh(tol):
+        (h, b, u, s, _), = _lanes(ff, w, 1, **opt)
+        ff.mg_rhs_plane_wave(h, w.eta, b)
+        info = ff.mg_solve(h, b, u, tol=tol)
+        torch.cuda.synchronize()
+        out = (info.cycles, info.rel_residual, u.clone())
+        h.destroy()
+        return out
+
+    ref, odd, even = {}, None, None
+    for tol in (1e-10, 1e-9, 1e-8, 1e-7, 1e-6, 1e-5, 1e-4, 1e-11):
+        r = fresh(tol)
+        if r[0] % 2 == 1 and odd is None:
+            odd, ref[tol] = tol, r
+        elif r[0] % 2 == 0 and r[0] > 0 and even is None:
+            even, ref[tol] = tol, r
+        if odd is not None and even is not None:
+            break
+    assert odd is not None and even is not None, ref
+    (h, b, u, s, _), = _lanes(ff, w, 1, **opt)
+    ff.mg_rhs_plane_wave(h, w.eta, b)
+    # (start flipped, count agrees): (no, -), (yes, yes), (yes, no), (no, no),
+    # (yes, no), (no, yes)
+    for tol in (odd, odd, even, odd, even, even):
+        info = ff.mg_solve(h, b, u, tol=tol)
+        torch.cuda.synchronize()
+        c, rr, uref = ref[tol]
+        assert (info.cycles, info.rel_residual) == (c, rr), tol
+        assert torch.equal(u, uref), tol
+    h.destroy()
