@@ -464,16 +464,18 @@ __global__ __launch_bounds__(256) void k_ff_gemm_bf16(const GemmGroupB *__restri
         }
 }
 
-// F_m = pre * sum_x P[m][x] T[m][x]; one wave per direction.
+// F_m = pre * sum_x P[m][x] T[m][x]; one block per direction, the sums of
+// its four waves combined in a fixed order.
 __global__ __launch_bounds__(256) void k_ff_final(const cd *__restrict__ P, const cd *__restrict__ T, int M, int K,
                                                   cd pre, cd *__restrict__ F)
 {
-    int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
+    __shared__ double red[2][4];
+    const int m = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (m >= M) return;
     double re = 0.0, im = 0.0;
     const cd *pr = P + (size_t)m * K, *tr = T + (size_t)m * K;
-    for (int k = lane; k < K; k += 64) {
+    for (int k = threadIdx.x; k < K; k += 256) {
         cd v = pr[k] * tr[k];
         re += v.re;
         im += v.im;
@@ -482,7 +484,14 @@ __global__ __launch_bounds__(256) void k_ff_final(const cd *__restrict__ P, cons
         re += __shfl_down(re, off, 64);
         im += __shfl_down(im, off, 64);
     }
-    if (lane == 0) F[m] = pre * cd{re, im};
+    if (lane == 0) {
+        red[0][wave] = re;
+        red[1][wave] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        F[m] = pre * cd{(red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
+                        (red[1][0] + red[1][1]) + (red[1][2] + red[1][3])};
 }
 
 // Scatter the sorted result into the caller's direction order.
@@ -856,7 +865,7 @@ hipError_t ff_plan_finish(FarFieldPlan *p, const LevelGeom &g, double gamma, cd 
     double vol = 1.0;
     for (int k = 0; k < d; ++k) vol *= g.h[k];
     cd pre = {vol * cos(d * gamma), vol * sin(d * gamma)};
-    hipLaunchKernelGGL(k_ff_final, dim3(ceil_div(M, 4)), dim3(256), 0, s, p->d_Plast, p->d_T2, M, mx, pre, p->d_F);
+    hipLaunchKernelGGL(k_ff_final, dim3(M), dim3(256), 0, s, p->d_Plast, p->d_T2, M, mx, pre, p->d_F);
     hipLaunchKernelGGL(k_unpermute, dim3(ceil_div(M, 256)), dim3(256), 0, s, p->d_F, p->d_perm, M, F_out);
     return hipGetLastError();
 }
