@@ -28,6 +28,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -72,6 +73,17 @@ NET_FLOP_PER_POINT = 8 * 2736
 
 def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0, streams=1,
              pipelined=False, time_kernel=True):
+    """run_path_here on a fresh stream of its own when several lanes are
+    used (every lane then has a stream created for it, none on the legacy
+    null stream), else on the current stream."""
+    s0 = torch.cuda.Stream() if streams > 1 else torch.cuda.current_stream()
+    with torch.cuda.stream(s0):
+        return run_path_here(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point,
+                             fmg_cycles=fmg_cycles, streams=streams, pipelined=pipelined, time_kernel=time_kernel)
+
+
+def run_path_here(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0, streams=1,
+                  pipelined=False, time_kernel=True):
     """Time `steps` maps.  The warm-up maps record every timed kernel; the one
     with the largest total time is the dominant kernel, and inside the timed
     region HIP events bracket only that kernel's launches.  fmg_cycles > 0:
@@ -653,7 +665,7 @@ def cpu_baseline(w):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=2048, help="intervals per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -670,8 +682,14 @@ def main():
     ap.add_argument("--one-stream", action="store_true",
                     help="one handle on one stream (no overlap of a map's far field with the next solve)")
     ap.add_argument("--blocking", action="store_true",
-                    help="two streams, but each solve finished (mg_solve) before the next map is begun")
+                    help="the lanes' solves finished (mg_solve) before the next map is begun")
+    ap.add_argument("--lanes", type=int, default=4,
+                    help="handles and streams the headline maps cycle through (solves in flight)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
+    ap.add_argument("--tune-only", action="store_true",
+                    help="run the autotuning sweeps of the 2048^2 paths (filling the cache) and exit")
+    ap.add_argument("--tune-in-process", action="store_true",
+                    help="run the autotuning sweeps in this process instead of a child process")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
@@ -679,6 +697,20 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multigrid sweeps and the far-field contraction are measured on one MI355X.", file=sys.stderr)
         sys.exit(2)
+
+    if not args.tune_only and not args.tune_in_process:
+        # The autotuning sweeps of the headline paths run in a child process
+        # that fills the cache, started before this process touches the GPU;
+        # this one then reads the cached choices.  The sweeps are setup, off
+        # every timed path, and a process that has run them in-process was
+        # measured slower with four solves in flight (about 610 against 750
+        # maps/s on the same box).
+        cmd = [sys.executable, os.path.abspath(__file__), "--tune-only", "--n", str(args.n),
+               "--ff-precision", args.ff_precision] + (["--zero-start"] if args.zero_start else [])
+        rc = subprocess.call(cmd, stdout=subprocess.DEVNULL)
+        if rc != 0:
+            print(f"bench.py: the autotuning child process failed ({rc})", file=sys.stderr)
+            sys.exit(rc)
 
     import numpy as np
     import torch
@@ -715,8 +747,13 @@ def main():
     # both forms start from the full multigrid guess (FMG_K V-cycles per
     # coarse level); the zero-start V-cycle solves are reported beside them
     fk = 0 if args.zero_start else FMG_K
-    ns = 1 if args.one_stream else 2
-    pipe = ns == 2 and not args.blocking
+    if args.tune_only:
+        # the tuning part of run_path fills the cache; two maps each
+        run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, 1, 1, bpp_mixed, fmg_cycles=fk)
+        run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, 1, 1, bpp_plain, fmg_cycles=fk)
+        return
+    ns = 1 if args.one_stream else max(args.lanes, 1)
+    pipe = ns > 1 and not args.blocking
     # with two solves in flight the timed region runs without event brackets:
     # the dominant kernel is timed in the one-solve pass below
     mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed, fmg_cycles=fk,
@@ -767,12 +804,12 @@ def main():
                    "unknowns": N, "angles": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
                    "start": (f"full multigrid: {fk} V(2,2) per coarse level, then V-cycles on the finest grid"
                              if fk else "u = 0"),
-                   "streams": ("2, pipelined: consecutive maps alternate between two handles on two streams; "
-                               "each map's solve is begun (mg_solve_begin) before the previous map is finished "
-                               "(mg_solve_end) and its far field queued, so two solves are in flight from one host "
-                               "thread" if pipe else
-                               "2: consecutive maps alternate between two handles on two streams, one map's far "
-                               "field runs while the next map is solved" if ns == 2 else "1"),
+                   "streams": (f"{ns}, pipelined: consecutive maps cycle through {ns} handles, each on its own "
+                               "stream; each map's solve is begun (mg_solve_begin) before the map begun "
+                               f"{ns - 1} steps earlier is finished (mg_solve_end) and its far field queued, so "
+                               f"{ns} solves are in flight from one host thread" if pipe else
+                               f"{ns}: consecutive maps cycle through {ns} handles on {ns} streams, one map's far "
+                               "field runs while the next map is solved" if ns > 1 else "1"),
                    "form": "FP32 V-cycles in FP64 refinement + "
                            + {"bf16x6": "split-BF16 (3 parts, 6 products) MFMA far field, FP32 accumulation",
                               "bf16x3": "split-BF16 (2 parts, 3 products) MFMA far field, FP32 accumulation",
@@ -809,7 +846,7 @@ def main():
         # numbers of V-cycles per coarse level in the full multigrid start
         fm = {}
         # (V-cycles per coarse level, lanes, pipelined); k = 0: u = 0
-        forms_m = [(0, 1, False), (1, ns, pipe), (3, ns, pipe), (fk, 1, False), (fk, 2, False)]
+        forms_m = [(0, 1, False), (1, ns, pipe), (3, ns, pipe), (fk, 1, False), (fk, 2, False), (fk, 2, True)]
         forms_p = [(0, 1, False), (1, ns, pipe), (fk, 1, False), (fk, 2, False)]
         for prec, ffp_k, forms, tag, bpp in ((ffmg.FP32_IR, ffp, forms_m, "mixed", bpp_mixed),
                                               (ffmg.FP64, ffmg.FF_FP64, forms_p, "plain_fp64", bpp_plain)):
@@ -825,7 +862,7 @@ def main():
                     r = run_path(ffmg, torch, w, prec, ffp_k, max(args.steps // 2, 2), args.warmup, bpp,
                                  fmg_cycles=k, streams=nsk, pipelined=pk)
                 name = (f"{tag}_{'zero_start' if k == 0 else f'fmg_k{k}'}" + ("_one_stream" if nsk == 1 and k else "")
-                        + ("_blocking" if nsk == 2 and not pk else ""))
+                        + ("_blocking" if nsk > 1 and not pk else "") + (f"_{nsk}_lanes" if 1 < nsk != ns else ""))
                 fm[name] = {
                     "maps_per_s": round(r["maps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
                     "cycles": r["cycles"], "vcycles_finest": r["vcycles"], "rel_residual": r["rel_residual"],
