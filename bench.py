@@ -512,7 +512,7 @@ def run_learned(ff, torch, W, reps=3, oracle_check=False):
     return out
 
 
-def run_3d(ff, torch, W, steps=2, fmg_cycles=FMG_K):
+def run_3d(ff, torch, W, steps=2, fmg_cycles=FMG_K, lanes=2):
     """The 3D workload (512^3 intervals, chi = 0.5 exp(-z.z/2), 128 x 64
     directions): maps with FP32 V-cycles in FP64 refinement + split-BF16 far
     field and plain FP64 maps, each solved to 1e-10 from the full multigrid
@@ -569,11 +569,12 @@ def run_3d(ff, torch, W, steps=2, fmg_cycles=FMG_K):
         h.destroy()
         del b, u
         torch.cuda.empty_cache()
-    # the mixed maps again with two solves in flight from this thread (two
-    # handles on two streams, mg_solve_begin / mg_solve_end, far field into
-    # device memory), as in the 2D headline
+    # the mixed maps again with `lanes` solves in flight from this thread
+    # (one handle and stream each, mg_solve_begin / mg_solve_end, far field
+    # into device memory), as in the 2D headline
+    nl = lanes
     lanes = []
-    for _ in range(2):
+    for _ in range(nl):
         s_ = torch.cuda.Stream()
         with torch.cuda.stream(s_):
             h_ = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, ff_precision=ff.FF_BF16X6,
@@ -584,17 +585,18 @@ def run_3d(ff, torch, W, steps=2, fmg_cycles=FMG_K):
         lanes.append((h_, b_, u_, F_))
     if ff.mg_tune_variants(lanes[0][0], ff.TUNE_FF_GEMM) > 1:
         v = autotune.tune_farfield(lanes[0][0], w.eta, None, w.dirs, ff.FF_BF16X6)
-        ff.mg_tune_set(lanes[1][0], v, ff.TUNE_FF_GEMM)
+        for ln in lanes[1:]:
+            ff.mg_tune_set(ln[0], v, ff.TUNE_FF_GEMM)
     pinfo = []
 
     def run_pipelined(nmaps):
         pend = []
         for k in range(nmaps):
-            h_, b_, u_, F_ = lanes[k % 2]
+            h_, b_, u_, F_ = lanes[k % nl]
             ff.mg_rhs_plane_wave(h_, w.eta, b_)
             ff.mg_solve_begin(h_, b_, u_, tol=w.tol)
-            pend.append(lanes[k % 2])
-            if len(pend) == 2:
+            pend.append(lanes[k % nl])
+            if len(pend) == nl:
                 o = pend.pop(0)
                 pinfo.append(ff.mg_solve_end(o[0]))
                 ff.farfield_map(o[0], w.eta, o[2], w.dirs, out=o[3])
@@ -603,14 +605,15 @@ def run_3d(ff, torch, W, steps=2, fmg_cycles=FMG_K):
             ff.farfield_map(o[0], w.eta, o[2], w.dirs, out=o[3])
         torch.cuda.synchronize()
 
-    run_pipelined(2)
-    nm = 2 * steps
+    run_pipelined(nl)
+    nm = nl * steps
     t0 = time.perf_counter()
     run_pipelined(nm)
     dt = (time.perf_counter() - t0) / nm
-    Fp = lanes[(nm - 1) % 2][3].cpu().numpy()
+    Fp = lanes[(nm - 1) % nl][3].cpu().numpy()
     out["mixed_pipelined"] = {"maps_per_s": round(1.0 / dt, 3), "ms_per_map": round(1e3 * dt, 2),
-                              "maps": nm, "cycles": pinfo[-1].cycles, "rel_residual": pinfo[-1].rel_residual,
+                              "maps": nm, "lanes": nl, "cycles": pinfo[-1].cycles,
+                              "rel_residual": pinfo[-1].rel_residual,
                               "farfield_rel_diff_vs_mixed": float(np.linalg.norm(Fp - maps["mixed"]) /
                                                                   np.linalg.norm(maps["mixed"])),
                               "speedup_over_one_at_a_time": round(out["mixed"]["ms_per_map"] / (1e3 * dt), 3)}
