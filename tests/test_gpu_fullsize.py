@@ -5,6 +5,8 @@ times, on outputs the FP64 oracle can afford there:
   right-hand side element by element, the residual of the GPU solution under
   the oracle's operator, and the map against the oracle's map of the GPU
   solution and of its own converged solution (1e-6, the mixed forms' bar);
+  and the benchmark's pipelined form (full multigrid start, four solves in
+  flight), every map bit for bit the map solved alone;
 * 512^3 Gaussian (3D, 7-point stencil), same form: right-hand side, residual
   under the oracle's operator, and 16 sampled directions of the 128 x 64 map
   against the oracle's quadrature of the GPU solution;
@@ -73,6 +75,56 @@ def test_bumps_2048_mixed_map(ff, orc):
           f"{relerr(F, Fo):.2e} (oracle {k} cycles)")
     assert relerr(F, Fo) < 1e-6
     h.destroy()
+
+
+def test_bumps_2048_pipelined_headline_configuration(ff, orc):
+    """The benchmark's launch configuration: full multigrid start, four
+    handles on four streams, each map begun before the map three steps
+    earlier is finished.  Every map equals, bit for bit, the same map solved
+    alone with mg_solve; the last solution meets the tolerance under the
+    oracle's operator and its map matches the oracle's quadrature of it."""
+    w = W.bumps_2d()
+    opts = dict(precision=ff.FP32_IR, ff_precision=ff.FF_BF16X6, fmg_cycles=2)
+    lanes = []
+    for _ in range(4):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            h = ff.setup_workload(w, options=ff.default_options(**opts))[0]
+            b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
+            u = torch.empty_like(b)
+            F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
+        lanes.append((h, b, u, F))
+    # one map alone
+    h, b, u, F = lanes[0]
+    ff.mg_rhs_plane_wave(h, w.eta, b)
+    info0 = ff.mg_solve(h, b, u, tol=w.tol)
+    ff.farfield_map(h, w.eta, u, w.dirs, out=F)
+    torch.cuda.synchronize()
+    assert info0.status == 0
+    F0, u0 = F.clone(), u.clone()
+    # eight maps, four in flight
+    pend, infos, maps = [], [], []
+    for k in range(8):
+        ln = lanes[k % 4]
+        ff.mg_rhs_plane_wave(ln[0], w.eta, ln[1])
+        ff.mg_solve_begin(ln[0], ln[1], ln[2], tol=w.tol)
+        pend.append(ln)
+        if len(pend) == 4 or k == 7:
+            while pend and (len(pend) == 4 or k == 7):
+                o = pend.pop(0)
+                infos.append(ff.mg_solve_end(o[0]))
+                ff.farfield_map(o[0], w.eta, o[2], w.dirs, out=o[3])
+                torch.cuda.synchronize()
+                maps.append((o[3].clone(), o[2].clone()))
+    assert len(maps) == 8
+    for i, (inf, (Fk, uk)) in enumerate(zip(infos, maps)):
+        assert inf.status == 0 and (inf.cycles, inf.rel_residual) == (info0.cycles, info0.rel_residual), i
+        assert torch.equal(Fk, F0) and torch.equal(uk, u0), i
+    g, kappa, q, k0, bo, ug = check_solution(orc, w, lanes[3][1], maps[-1][1], infos[-1], w.tol)
+    Fu = orc.farfield(g, w.gamma, k0, q, w.eta, ug, w.dirs)
+    assert relerr(maps[-1][0].cpu().numpy(), Fu) < 1e-6
+    for ln in lanes:
+        ln[0].destroy()
 
 
 def test_gauss3d_512_mixed(ff, orc):
