@@ -123,7 +123,7 @@ def run_path_here(ff, torch, w, precision, ff_precision, steps, warmup, bytes_pe
     if ff.mg_tune_variants(h, ff.TUNE_PRE) > 1:       # pre-smoothing + residual + restriction in one pass or two
         ff.mg_rhs_plane_wave(h, w.eta, b)
         v = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=ff.TUNE_PRE)
-        tune["pre"] = {"variant": v, "form": ("one pass", "two launches")[v],
+        tune["pre"] = {"variant": v, "form": ("one pass", "two launches", "one pass, other finest tile height")[v],
                        "cache": autotune.load().get(autotune.key(
                            autotune.device_arch(), ff.TUNE_PRE, w.dim, [w.n - 1] * w.dim, 0, precision))}
     if ff.mg_tune_variants(h, ff.TUNE_TAIL) > 1:      # size of the one-workgroup LDS tail, off the timed path

@@ -338,9 +338,10 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
  * (16 rows with the 16-row variant, else 8); one variant each for 3D and
  * tile_config 1.
  * FFMG_TUNE_PRE: the pre-smoothing of a fused 2D level with nu1 = 2 as one
- * pass of two sweeps, residual and full weighting (variant 0) or as the
- * two-sweep launch followed by the residual + restriction launch (1); one
- * variant for 3D and tile_config 1.
+ * pass of two sweeps, residual and full weighting (variant 0: 16-row tiles on
+ * the finest level for FP32 cycles, 8-row for FP64; 2: the other height) or
+ * as the two-sweep launch followed by the residual + restriction launch (1);
+ * one variant for 3D and tile_config 1.
  * mg_tune_variants returns the number of variants (0 for an unknown
  * tunable); mg_tune_get / mg_tune_set read and select one (a cached choice).
  * mg_tune_farfield builds the integrand of (eta, u) for the n_dirs

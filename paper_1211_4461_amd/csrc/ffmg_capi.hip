@@ -288,12 +288,16 @@ void vcycle_fused2d(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_g
     cx<T> *t = LP::t(lv), *scratch = LP::r(lv);
     cx<T> *cur = u;
     const int nu1 = nu_pre(h, l), nu2 = nu_post(h, l);
-    if (nu1 == 2 && h->pre_variant == 0) {
+    if (nu1 == 2 && h->pre_variant != 1) {
         // two sweeps, residual and full weighting in one pass
         const bool finest = (l == 0);
         int pi = finest ? prof_kernel_begin(h, PROF_PRE) : -1;
-        // coarse levels: 16 rows with the 16-row smoothing tile, else 8
-        const int fh = finest ? 0 : (SMOOTH_TH[h->smooth_coarse_variant] >= 16 ? 16 : 8);
+        // finest level: the type's default tile height (16 rows FP32, 8 FP64;
+        // variant 0) or the other one (variant 2); coarse levels: 16 rows
+        // with the 16-row smoothing tile, else 8
+        const int fdef = sizeof(T) == 4 ? 16 : 8;
+        const int fh = finest ? (h->pre_variant == 2 ? 24 - fdef : fdef)
+                              : (SMOOTH_TH[h->smooth_coarse_variant] >= 16 ? 16 : 8);
         launch_smooth_rr2d<T>(lv.g, LP::P(lv), zero_guess, u, b, LP::q(lv), t, LP::b(lc), h->stream, finest, stop,
                               fh);
         prof_kernel_end(h, PROF_PRE, pi);
@@ -1407,7 +1411,7 @@ int mg_tune_variants(const ffmg_handle *h, int tunable)
                    : 1;
     case FFMG_TUNE_SMOOTH:
         return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
-    case FFMG_TUNE_PRE: return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? 2 : 1;
+    case FFMG_TUNE_PRE: return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? 3 : 1;
     case FFMG_TUNE_SMOOTH_COARSE:
         return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
     default: return 0;

@@ -438,8 +438,9 @@ def test_smoothing_tile_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp
 
 @pytest.mark.parametrize("n", [64, 128, 512])
 def test_pre_pass_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path):
-    """The one-pass pre-smoothing (two sweeps, residual, full weighting) and
-    the two launches it replaces agree bit for bit: FP64 V-cycles from zero and
+    """The one-pass pre-smoothing (two sweeps, residual, full weighting; 16-
+    or 8-row tiles on the finest level, FP32 and FP64) and the two launches it replaces agree
+    bit for bit: FP64 V-cycles from zero and
     from a nonzero guess, FP32-in-FP64 solves and the full multigrid start
     (ragged last tiles and the grid border included); the solve-timing sweep
     selects one and the cache applies it to a second handle."""
@@ -447,12 +448,12 @@ def test_pre_pass_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path)
     w = W.bumps_2d(n=n, seed=n + 7, k0=1.2, M=8)
     for prec in (ff.FP64, ff.FP32_IR):
         h, _, g, _, _, _ = setup(ff, orc, w, precision=prec)
-        assert ff.mg_tune_variants(h, ff.TUNE_PRE) == 2
+        assert ff.mg_tune_variants(h, ff.TUNE_PRE) == 3
         assert ff.mg_tune_get(h, ff.TUNE_PRE) == 0
         b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
         u0 = dev(0.3 * crand(n, g.shape))
         outs = []
-        for v in (0, 1):
+        for v in (0, 1, 2):
             ff.mg_tune_set(h, v, ff.TUNE_PRE)
             if prec == ff.FP64:
                 u = torch.zeros_like(b)
@@ -469,11 +470,12 @@ def test_pre_pass_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path)
                 ff.mg_fmg(h, b, u2, 2)
             torch.cuda.synchronize()
             outs.append((key, u.clone(), u2.clone()))
-        assert outs[0][0] == outs[1][0]
-        assert torch.equal(outs[0][1], outs[1][1]) and torch.equal(outs[0][2], outs[1][2]), prec
+        for o in outs[1:]:
+            assert o[0] == outs[0][0]
+            assert torch.equal(o[1], outs[0][1]) and torch.equal(o[2], outs[0][2]), prec
     ws = torch.zeros_like(b)
     best, times = ff.mg_tune_solve(h, b, ws, reps=1, tunable=ff.TUNE_PRE)
-    assert best in (0, 1) and times[best] == min(times) and ff.mg_tune_get(h, ff.TUNE_PRE) == best
+    assert best in (0, 1, 2) and times[best] == min(times) and ff.mg_tune_get(h, ff.TUNE_PRE) == best
     assert torch.equal(ws, outs[0][1])
     cache = str(tmp_path / "tune.json")
     v1 = autotune.tune_solve(h, b, ws, ff.FP32_IR, path=cache, reps=1, tunable=ff.TUNE_PRE)
