@@ -11,14 +11,15 @@ path (FP64 V-cycles, FP64 MFMA far field) is timed beside it on the same map.
 Both solves start from the full multigrid guess (the nested iteration of
 V-cycles, FMG_K per coarse level); the same solves from u = 0 and with other
 cycle counts per level are timed as well (`start_forms`).  Consecutive maps
-alternate between two handles on two streams, so that one map's far field
-(queued on its stream) runs while the next map is solved; the one-stream
-rate is in `start_forms` too.
+cycle through four handles, each on a stream of its own: each map's solve is
+begun (mg_solve_begin) before the map begun three steps earlier is finished
+(mg_solve_end) and its far field queued, so four solves are in flight from
+this one thread; the one-stream and two-lane rates are in `start_forms` too.
 
 Also reported: the roofline of the dominant kernel (the timed kernel with the
-largest total time per map), timed live with HIP events on its stream during
-the timed region, and the FP64 CPU oracle on the host cores (one map of the
-same workload).
+largest total time per map), timed live with events stamped on its launches
+in a one-solve-in-flight pass of the same maps, and the FP64 CPU oracle on the
+host cores (one map of the same workload).
 """
 from __future__ import annotations
 
@@ -756,7 +757,7 @@ def main():
         return
     ns = 1 if args.one_stream else max(args.lanes, 1)
     pipe = ns > 1 and not args.blocking
-    # with two solves in flight the timed region runs without event brackets:
+    # with several solves in flight the timed region runs without event brackets:
     # the dominant kernel is timed in the one-solve pass below
     mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed, fmg_cycles=fk,
                      streams=ns, pipelined=pipe, time_kernel=(ns == 1))
@@ -769,7 +770,7 @@ def main():
                      "the tuned tile height)" % (mixed["tune"]["smooth"] or {}).get("tile_rows", 8),
              "refine": "FP64 update + residual of the refinement loop (k_refine2d)"}
     # The dominant kernel's duration.  Its launches are timed by events the
-    # runtime stamps on the launch itself.  With two solves in flight those
+    # runtime stamps on the launch itself.  With several solves in flight those
     # stamps also count the time a launch waits behind the other stream's
     # workgroups, so the kernel is timed in the same maps with one solve in
     # flight (one handle, one stream); the figure from the headline's own
@@ -839,7 +840,7 @@ def main():
                               "lds_tail": plain["tune"]["tail"],
                               "ff_ms_per_map": round(pp["ff"][0] / max(pp["ff"][1], 1), 3),
                               "farfield_gemm": gemm_report(pp, w, "fp64"),
-                              "kernel_times_from": ("warm-up maps with two solves in flight (intervals include "
+                              "kernel_times_from": ("warm-up maps with several solves in flight (intervals include "
                                                     "waits behind the other stream)" if pipe else "warm-up maps")}
         line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
         line["mixed_vs_plain_farfield_rel_err"] = ef
