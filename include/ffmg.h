@@ -248,8 +248,13 @@ ffmg_status farfield_map_batched(ffmg_handle *const *hs, int count, const double
  * the finest level; the paper smooths with weighted Jacobi, Sec. 4).  One
  * smoothing step is u += s h^2 N(r / s, kappa h^2), r = b - A u, s = RMS(r),
  * where N is a three-layer 3x3 complex convolutional network with 2 -> 16 ->
- * 16 -> 1 complex channels, CReLU activations and no biases, stored in BF16
- * and accumulated in FP32.  Weights: FFMG_NET_WEIGHTS complex values as
+ * 16 -> 1 complex channels, no activation function and no biases, stored in
+ * BF16 and accumulated in FP32.  Layer 1 is a gate: with
+ * a = W1[:, :, 0] * r~ and m = W1[:, :, 1] * kappa~ (3x3 convolutions of
+ * the two inputs), its output is x1 = a (1 + m); then x2 = W2 * x1 and
+ * N = W3 * x2.  N is complex-linear in r~, so the step is a linear iteration
+ * whose stencil (radius 3) adapts to the local coefficient, and weighted
+ * Jacobi is one point of the weight space.  Weights: FFMG_NET_WEIGHTS complex values as
  * interleaved (re, im) floats: W1 [9][16][2], W2 [9][16][16], W3 [9][1][16],
  * indexed (tap, output channel, input channel), tap 3 (dy + 1) + (dx + 1)
  * reading the point (y + dy, x + dx).
@@ -258,7 +263,10 @@ ffmg_status farfield_map_batched(ffmg_handle *const *hs, int count, const double
  * [count][32][32] each: the scaled residual r / s, kappa h^2 and the scaled
  * error e / (s h^2).  The loss of a patch is the mean over its points at
  * least `border` from the patch edge of |L5 (e~ - N)|^2 (L5 the 5-point
- * Laplacian stencil), the minibatch loss the mean over patches.
+ * Laplacian stencil), plus the growth penalty
+ * max(0, ||e~ - N||^2 / ||e~||^2 - 1) over the same points (the error left
+ * after the step must not be larger than the error before it); the
+ * minibatch loss is the mean over patches.
  * ml_loss_grad returns the loss and its gradient (host, 2 * FFMG_NET_WEIGHTS
  * floats, may be NULL) at the current weights; ml_train_step also applies
  * one Adam step (beta1 0.9, beta2 0.999, eps 1e-8) to the FP32 master

@@ -3,8 +3,9 @@
 The library exposes tunable kernel families (``mg_tune_variants``); every
 variant of a family computes the same bits with a different tile shape, and
 which one is fastest depends on the device and on the problem's shapes.  This
-module keys a choice by (device architecture, tunable, dimension, interior
-extents, number of directions, precision), runs the library's own timing
+module keys a choice by (device architecture, tunable and its number of
+variants, dimension, interior extents, number of directions, precision, the
+solve options that change the timed work), runs the library's own timing
 sweep (``mg_tune_farfield``, ``mg_tune_solve``) on a cache miss, and stores
 the winner.
 
@@ -44,9 +45,21 @@ def save(cache: dict, path: Optional[str] = None) -> None:
     os.replace(tmp, p)
 
 
-def key(arch: str, tunable: int, dim: int, shape, n_dirs: int, precision: int) -> str:
+# solve options that change what a tuning sweep times (the cycle, the start,
+# the smoother and the kernel configuration)
+KEY_OPTIONS = ("nu1", "nu2", "nu_coarse", "inner_cycles", "fmg_cycles", "smoother", "krylov_m", "tile_config",
+               "ff_precision")
+
+
+def key(arch: str, tunable: int, dim: int, shape, n_dirs: int, precision: int, n_variants: int = 0,
+        options: Optional[dict] = None) -> str:
+    """Cache key: device, tunable and its variant count (a family that gains
+    a variant is tuned again), grid, directions, precision and the solve
+    options that affect timing."""
     ext = "x".join(str(int(m)) for m in shape)
-    return f"{arch}|tunable={int(tunable)}|d={int(dim)}|m={ext}|M={int(n_dirs)}|prec={int(precision)}"
+    opts = ",".join(f"{k}={int((options or {}).get(k, 0))}" for k in KEY_OPTIONS)
+    return (f"{arch}|tunable={int(tunable)}|nv={int(n_variants)}|d={int(dim)}|m={ext}|M={int(n_dirs)}"
+            f"|prec={int(precision)}|{opts}")
 
 
 def device_arch() -> str:
@@ -63,7 +76,8 @@ def tune_farfield(h: "ffmg.Handle", eta, u, dirs, ff_precision: int, path: Optio
     if nv <= 1:
         return 0
     shape = [m for m in h.level_shape(0) if m > 1]
-    k = key(device_arch(), ffmg.TUNE_FF_GEMM, len(shape), shape, len(dirs), ff_precision)
+    k = key(device_arch(), ffmg.TUNE_FF_GEMM, len(shape), shape, len(dirs), ff_precision, nv,
+            getattr(h, "options", None))
     cache = load(path)
     hit = cache.get(k)
     if not force and isinstance(hit, dict) and isinstance(hit.get("variant"), int) and 0 <= hit["variant"] < nv:
@@ -86,7 +100,7 @@ def tune_solve(h: "ffmg.Handle", b, u, precision: int, tol: float = 1e-10, path:
     if nv <= 1:
         return 0
     shape = [m for m in h.level_shape(0) if m > 1]
-    k = key(device_arch(), tunable, len(shape), shape, 0, precision)
+    k = key(device_arch(), tunable, len(shape), shape, 0, precision, nv, getattr(h, "options", None))
     cache = load(path)
     hit = cache.get(k)
     if not force and isinstance(hit, dict) and isinstance(hit.get("variant"), int) and 0 <= hit["variant"] < nv:

@@ -169,9 +169,12 @@ class Handle:
     """Owns one ``ffmg_handle``.  Arrays are complex128 device tensors whose
     memory layout is x fastest (numpy/torch shape (ny, nx) or (nz, ny, nx))."""
 
-    def __init__(self, ptr, shape):
+    def __init__(self, ptr, shape, options=None):
         self._p = ptr
         self.shape = shape
+        # the options the handle was set up with (plain values, no pointers)
+        self.options = {} if options is None else {
+            k: getattr(options, k) for k, _ in Options._fields_ if k not in ("stream", "smoother_weights")}
 
     def _check(self, st, what):
         if st != FFMG_OK:
@@ -227,7 +230,7 @@ def mg_setup(dim, n, lo, hi, gamma, coef, kind=HELMHOLTZ, k0=1.0, energy=0.0, op
     if st != FFMG_OK:
         raise FfmgError(st, "mg_setup: " + lib().ffmg_strerror(st).decode())
     shape = tuple(int(v) - 1 for v in nn[:dim][::-1])
-    return Handle(h, shape)
+    return Handle(h, shape, o)
 
 
 def _eta3(eta):

@@ -280,6 +280,32 @@ def radial_3d(n: int, L: float = 12.0, k0: float = 1.0, amp: float = 0.5,
                     params={"amp": amp, "width": width})
 
 
+def gamma_from_ecs(theta: float) -> float:
+    """Rotation angle of the full complex grid linked to an ECS layer angle
+    theta (Sec. 3.3, eq. thetagamma; Table gammatheta: pi/6 -> 9.9 deg,
+    pi/4 -> 14.6 deg)."""
+    return math.atan(math.sin(theta) / (2.0 + math.cos(theta)))
+
+
+def two_spheres(dim: int, n: int, k0: float, gamma: float, L: float = 20.0,
+                M: int = 360, n_az: int = 16, n_pol: int = 8) -> Workload:
+    """The model scatterer of the paper's Helmholtz experiments (Sec. 4):
+    k0^2 chi = -1/5 (exp(-|x - c+|^2) + exp(-|x - c-|^2)), c+- = (0, +-4[, 0])
+    (eq. chi2D in 2D, eq. chi3D in 3D), continued to z = e^{i gamma} x, on
+    [-L, L]^d with eta = +x.  The contrast k0^2 chi does not depend on k0."""
+    X = mesh([n] * dim, [-L] * dim, [L] * dim)
+    coef = np.zeros(X[0].shape, dtype=np.complex128)
+    for cy in (4.0, -4.0):
+        c = (0.0, cy, 0.0)[:dim]
+        coef += gauss_continued(X, gamma, -0.2, 1.0, c)
+    dirs = directions_2d(M) if dim == 2 else directions_3d(n_az, n_pol)
+    eta = np.zeros(dim)
+    eta[0] = 1.0
+    return Workload(f"two_spheres_{dim}d", dim, n, -L, L, gamma, HELMHOLTZ, k0, 0.0,
+                    np.ascontiguousarray(coef, dtype=np.complex128), eta, dirs,
+                    tol=1e-6, nu1=1, nu2=1)
+
+
 def random_field(n: int, seed: int, kh: float, lo: float = -10.0, hi: float = 10.0):
     """A random bump field (the bumps_2d law) at wavenumber k0 = kh / h;
     used as training input for the learned smoother."""
