@@ -213,6 +213,32 @@ ffmg_status mg_solve_end(ffmg_handle *h, ffmg_solve_info *info);
 ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs,
                          const double *dirs, void *F);
 
+/* Far-field map that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It computes what farfield_map computes
+ * on a handle with ff_precision FFMG_FF_FP64 (the FP64 MFMA contraction,
+ * whatever the handle's ff_precision), bit for bit, with the same arguments:
+ * eta HOST double[3]; u DEVICE complex128[N] or NULL (Born term); dirs HOST
+ * double[n_dirs][dim] unit vectors; F complex128[n_dirs] in HOST memory (the
+ * call synchronises) or DEVICE memory (returns once queued on the handle's
+ * stream).  Every work buffer (axis factors, direction table, packed factors,
+ * integrand, stage results) lives in one static device array of
+ * FFMG_NOALLOC_SCRATCH_BYTES per GPU, held from the library's load until the
+ * process ends; it calls no hipMalloc/hipFree and builds no plan.  The array
+ * is shared by every call on that GPU: calls that overlap on one GPU (other
+ * streams or host threads) race and must be serialised by the caller; the
+ * next call on the handle's stream may start as soon as this one's work is
+ * queued.  Limits (EINVAL, nothing written): n_dirs <= FFMG_NOALLOC_MAX_DIRS,
+ * and the buffers must fit the array, roughly
+ * 16 (N + 3 n_dirs (n_x - 1) + NG (n_x - 1)(n_y - 1)) bytes with NG the
+ * number of distinct last components in 3D (e.g. a 1023^2 grid with 360
+ * directions, or a 63^3 grid with 128 x 64 directions); the message states
+ * the bytes needed.  Other errors as farfield_map. */
+#define FFMG_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define FFMG_NOALLOC_MAX_DIRS 8192
+ffmg_status farfield_map_noalloc(ffmg_handle *h, const double eta[3], const void *u, int n_dirs,
+                                 const double *dirs, void *F);
+
 /* Batched solve: count instances, instance i being the plane wave of
  * direction etas[3i..3i+2] (the right-hand side of Sec. 2.1, built on the
  * device) scattered by the operator of handle hs[i]; handles may repeat

@@ -483,6 +483,9 @@ ffmg_status setup_impl(ffmg_handle *h)
 {
     const ffmg_problem &p = h->prob;
     HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipGetDevice(&h->device));
+    // the no-allocation far field's scratch array: its address on this device
+    HIPCHK(h, ff_scratch_init(h->device));
     // hierarchy n/2^l down to min_k n_k == coarsest_n
     int64_t nl[3] = {p.n[0], p.dim >= 2 ? p.n[1] : 2, p.dim >= 3 ? p.n[2] : 2};
     for (;;) {
@@ -1288,8 +1291,7 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
 
 // Validation, the plane-wave factors and the far-field plan for n_dirs
 // directions; then the integrand (inside the PROF_FF bracket started here).
-static ffmg_status ff_begin(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
-                            int *prof_idx)
+static ffmg_status ff_check_args(ffmg_handle *h, const double eta[3], int n_dirs, const double *dirs, int ff_prec)
 {
     if (!h || !eta || !dirs || n_dirs < 1) return fail(h, FFMG_EINVAL, "null argument or n_dirs < 1");
     const int d = h->prob.dim;
@@ -1306,8 +1308,16 @@ static ffmg_status ff_begin(ffmg_handle *h, const double eta[3], const void *u, 
     // the split BF16 contraction forms that product in FP32
     if (2.0 * exponent_budget(h) > 700.0)
         return fail(h, FFMG_ERANGE, "contour exponentials exceed the FP64 range on this box");
-    if (h->opt.ff_precision != FFMG_FF_FP64 && 2.0 * exponent_budget(h) > 60.0)
+    if (ff_prec != FFMG_FF_FP64 && 2.0 * exponent_budget(h) > 60.0)
         return fail(h, FFMG_ERANGE, "contour exponentials exceed the FP32 range of the split BF16 contraction");
+    return FFMG_OK;
+}
+
+static ffmg_status ff_begin(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
+                            int *prof_idx)
+{
+    TRY(ff_check_args(h, eta, n_dirs, dirs, h ? h->opt.ff_precision : FFMG_FF_FP64));
+    const int d = h->prob.dim;
     Level &l0 = h->L[0];
     const LevelGeom &g = l0.g;
     if (!h->d_E) TRY(dalloc(h, &h->d_E, (size_t)(g.m[0] + g.m[1] + g.m[2]) * sizeof(cd)));
@@ -1380,6 +1390,38 @@ ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int
         HIPCHK(h, hipGetLastError());   // device output: the work stays queued on the handle's stream
     }
     return FFMG_OK;
+}
+
+ffmg_status farfield_map_noalloc(ffmg_handle *h, const double eta[3], const void *u, int n_dirs,
+                                 const double *dirs, void *F)
+{
+    NOT_PENDING(h);
+    if (!F) return fail(h, FFMG_EINVAL, "F is null");
+    TRY(ff_check_args(h, eta, n_dirs, dirs, FFMG_FF_FP64));
+    if (n_dirs > FFMG_NOALLOC_MAX_DIRS)
+        return fail(h, FFMG_EINVAL, "n_dirs = %d exceeds FFMG_NOALLOC_MAX_DIRS (%d)", n_dirs, FFMG_NOALLOC_MAX_DIRS);
+    hipPointerAttribute_t attr;
+    bool on_device = false;
+    if (hipPointerGetAttributes(&attr, F) == hipSuccess)
+        on_device = (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged);
+    else
+        (void)hipGetLastError();
+    const Level &l0 = h->L[0];
+    size_t need = 0;
+    hipError_t he = hipSuccess;
+    const int rc = ff_noalloc_map(l0.g, h->k0, h->prob.gamma, eta, l0.q, (const cd *)u, n_dirs, dirs, (cd *)F,
+                                  on_device, h->device, h->stream, &need, &he);
+    switch (rc) {
+    case 0: return FFMG_OK;
+    case 1:
+        return fail(h, FFMG_EINVAL, "the map needs %zu bytes of scratch, more than FFMG_NOALLOC_SCRATCH_BYTES (%zu)",
+                    need, (size_t)FFMG_NOALLOC_SCRATCH_BYTES);
+    case 2: return fail(h, FFMG_EDEVICE, "the scratch array was not set up on device %d", h->device);
+    case 3: return fail(h, FFMG_EINVAL, "n_dirs out of range");
+    default:
+        return fail(h, he == hipErrorOutOfMemory ? FFMG_ENOMEM : FFMG_EDEVICE, "farfield_map_noalloc: %s",
+                    hipGetErrorString(he));
+    }
 }
 
 }  // extern "C"

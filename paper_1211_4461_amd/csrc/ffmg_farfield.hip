@@ -29,8 +29,10 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
+#include "../../include/ffmg.h"
 #include "ffmg_internal.hpp"
 
 namespace ffmg {
@@ -868,6 +870,194 @@ hipError_t ff_plan_finish(FarFieldPlan *p, const LevelGeom &g, double gamma, cd 
     hipLaunchKernelGGL(k_ff_final, dim3(M), dim3(256), 0, s, p->d_Plast, p->d_T2, M, mx, pre, p->d_F);
     hipLaunchKernelGGL(k_unpermute, dim3(ceil_div(M, 256)), dim3(256), 0, s, p->d_F, p->d_perm, M, F_out);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Far-field map without device allocation (farfield_map_noalloc).  The FP64
+// MFMA contraction of ff_plan_* with the same kernels and launch shapes, but
+// every device buffer (axis factors, direction table, packed factors, GEMM
+// descriptors, integrand, stage results, F) is carved from one file-scope
+// device array.  Its device address is taken once per device at set-up
+// (ff_scratch_init, called by mg_setup with the device current) and only that
+// address is used on the host.  The direction grouping is staged in
+// file-scope host arrays under a mutex, so no host heap is used either.
+static __device__ __align__(256) unsigned char scratch[FFMG_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+struct NoAllocHost {
+    int perm[FFMG_NOALLOC_MAX_DIRS];
+    int gstart[FFMG_NOALLOC_MAX_DIRS + 1];
+    double gval[FFMG_NOALLOC_MAX_DIRS];
+    double al[4 * FFMG_NOALLOC_MAX_DIRS];
+    GemmGroup gr[FFMG_NOALLOC_MAX_DIRS + 1];
+};
+static NoAllocHost g_na_host;
+static std::mutex g_na_mu;
+
+hipError_t ff_scratch_init(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+namespace {
+// bump allocation inside the scratch array (256-byte aligned offsets)
+struct Carve {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t count)
+    {
+        size_t o = off;
+        off = (size_t)round_up((long)(o + count * sizeof(T)), 256);
+        return o;
+    }
+};
+}  // namespace
+
+int ff_noalloc_map(const LevelGeom &g, double k0, double gamma, const double eta[3], const cd *q, const cd *u,
+                   int M, const double *dirs, cd *F_out, bool out_on_device, int device, hipStream_t s,
+                   size_t *need, hipError_t *herr)
+{
+    *herr = hipSuccess;
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (device >= 0 && device < NOALLOC_MAX_DEVICES) base = (unsigned char *)g_scratch_ptr[device];
+    }
+    if (!base) return 2;   // set-up did not run on this device
+    if (M < 1 || M > FFMG_NOALLOC_MAX_DIRS) return 3;
+    const int d = g.dim, mx = g.m[0], my = g.m[1], mz = g.m[2];
+    const long N = (long)g.N();
+
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    NoAllocHost &H = g_na_host;
+    // group directions by their last component (exact equality) in 3D, in the
+    // order a stable sort gives (ties keep the caller's order)
+    for (int i = 0; i < M; ++i) H.perm[i] = i;
+    if (d == 3)
+        std::sort(H.perm, H.perm + M, [&](int a, int b) {
+            const double za = dirs[a * 3 + 2], zb = dirs[b * 3 + 2];
+            return za < zb || (za == zb && a < b);
+        });
+    int NG = 0;
+    for (int i = 0; i < M; ++i) {
+        double v = (d == 3) ? dirs[H.perm[i] * 3 + 2] : 0.0;
+        if (i == 0 || (d == 3 && v != H.gval[NG - 1])) {
+            H.gstart[NG] = i;
+            H.gval[NG] = v;
+            ++NG;
+        }
+    }
+    H.gstart[NG] = M;
+    int maxM = 0;
+    for (int gi = 0; gi < NG; ++gi) maxM = std::max(maxM, H.gstart[gi + 1] - H.gstart[gi]);
+
+    // layout
+    const int ks_y = ceil_div(my, 4), ks_z = ceil_div(mz, 4);
+    const int rt1 = ceil_div(2L * NG, 16);
+    Carve c;
+    const size_t oE = c.take<cd>((size_t)mx + my + mz);
+    const size_t oAl = c.take<double>((size_t)3 * M + NG);
+    const size_t oPerm = c.take<int>((size_t)M);
+    const size_t oPl = c.take<cd>((size_t)M * mx);
+    const size_t oT2 = c.take<cd>((size_t)M * mx);
+    const size_t oF = c.take<cd>((size_t)M);
+    const size_t oFo = out_on_device ? 0 : c.take<cd>((size_t)M);
+    const size_t oS = c.take<cd>((size_t)N);
+    size_t a2tot = 0;
+    for (int gi = 0; gi < NG; ++gi) a2tot += (size_t)ceil_div(2L * (H.gstart[gi + 1] - H.gstart[gi]), 16) * ks_y * 64;
+    const size_t oA2 = c.take<double>(a2tot);
+    const size_t oA1 = (d == 3) ? c.take<double>((size_t)rt1 * ks_z * 64) : 0;
+    const size_t oT1 = (d == 3) ? c.take<cd>((size_t)NG * mx * my) : 0;
+    const size_t oGr = c.take<GemmGroup>((size_t)NG + 1);
+    *need = c.off;
+    if (c.off > (size_t)FFMG_NOALLOC_SCRATCH_BYTES) return 1;
+
+    cd *dE = (cd *)(base + oE), *dPl = (cd *)(base + oPl), *dT2 = (cd *)(base + oT2), *dF = (cd *)(base + oF);
+    cd *dS = (cd *)(base + oS), *dT1 = (cd *)(base + oT1);
+    double *dAl = (double *)(base + oAl), *dA2 = (double *)(base + oA2), *dA1 = (double *)(base + oA1);
+    int *dPerm = (int *)(base + oPerm);
+    GemmGroup *dGr = (GemmGroup *)(base + oGr);
+    cd *Fd = out_on_device ? F_out : (cd *)(base + oFo);
+
+    // direction table: sorted alphas per axis [3][M], then one alpha_z per group
+    for (size_t i = 0; i < (size_t)3 * M + NG; ++i) H.al[i] = 0.0;
+    for (int i = 0; i < M; ++i)
+        for (int k = 0; k < d; ++k) H.al[(size_t)k * M + i] = dirs[(size_t)H.perm[i] * d + k];
+    for (int gi = 0; gi < NG; ++gi) H.al[(size_t)3 * M + gi] = H.gval[gi];
+    // GEMM descriptors (device addresses inside the scratch array)
+    int ng = 0;
+    size_t off2 = 0;
+    if (d == 3) H.gr[ng++] = GemmGroup{dA1, (const double *)dS, dT1, NG, rt1};
+    for (int gi = 0; gi < NG; ++gi) {
+        const int Mg = H.gstart[gi + 1] - H.gstart[gi], rt = ceil_div(2L * Mg, 16);
+        const double *S = (d == 3) ? (const double *)(dT1 + (size_t)gi * mx * my) : (const double *)dS;
+        H.gr[ng++] = GemmGroup{dA2 + off2, S, dT2 + (size_t)H.gstart[gi] * mx, Mg, rt};
+        off2 += (size_t)rt * ks_y * 64;
+    }
+#define NA_CHECK(x)                                                                                                  \
+    do {                                                                                                             \
+        hipError_t e_ = (x);                                                                                         \
+        if (e_ != hipSuccess) {                                                                                      \
+            *herr = e_;                                                                                              \
+            return 4;                                                                                                \
+        }                                                                                                            \
+    } while (0)
+    // pageable host sources: each copy has consumed its source when it returns
+    NA_CHECK(hipMemcpyAsync(dAl, H.al, ((size_t)3 * M + NG) * sizeof(double), hipMemcpyHostToDevice, s));
+    NA_CHECK(hipMemcpyAsync(dPerm, H.perm, (size_t)M * sizeof(int), hipMemcpyHostToDevice, s));
+    NA_CHECK(hipMemcpyAsync(dGr, H.gr, (size_t)ng * sizeof(GemmGroup), hipMemcpyHostToDevice, s));
+
+    // plane-wave axis factors exp(i k0 e^{ig} eta_k x): c = -k0 sin g eta_k + i k0 cos g eta_k
+    int eo = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double ek = (k < d) ? eta[k] : 0.0;
+        hipLaunchKernelGGL(k_axis_exp, dim3(ceil_div(g.m[k], 256)), dim3(256), 0, s, dE + eo, g.m[k], g.lo[k],
+                           g.h[k], -(k0 * sin(gamma)) * ek, (k0 * cos(gamma)) * ek);
+        eo += g.m[k];
+    }
+    hipLaunchKernelGGL(k_plain_factor, dim3(grid_for((long)M * mx)), dim3(256), 0, s, dPl, dAl, M, mx, g.lo[0],
+                       g.h[0], k0, gamma);
+    off2 = 0;
+    for (int gi = 0; gi < NG; ++gi) {
+        const int Mg = H.gstart[gi + 1] - H.gstart[gi], rt = ceil_div(2L * Mg, 16);
+        hipLaunchKernelGGL(k_pack_factor, dim3(grid_for((long)rt * ks_y * 64)), dim3(256), 0, s, dA2 + off2,
+                           dAl + (size_t)1 * M + H.gstart[gi], Mg, my, rt, ks_y, g.lo[1], g.h[1], k0, gamma);
+        off2 += (size_t)rt * ks_y * 64;
+    }
+    if (d == 3)
+        hipLaunchKernelGGL(k_pack_factor, dim3(grid_for((long)rt1 * ks_z * 64)), dim3(256), 0, s, dA1,
+                           dAl + (size_t)3 * M, NG, mz, rt1, ks_z, g.lo[2], g.h[2], k0, gamma);
+    hipLaunchKernelGGL(k_ff_integrand, dim3(grid_for(N)), dim3(256), 0, s, q, u, (const cd *)dE, dS, mx, my,
+                       (d == 3) ? mz : 1);
+    if (d == 3) {
+        launch_gemm(GemmLaunch{dGr, 1, mz, mx * my, NG, 2L * mx * my, (long)mx * my}, s);
+        launch_gemm(GemmLaunch{dGr + 1, NG, my, mx, maxM, 2L * mx, (long)mx}, s);
+    } else {
+        launch_gemm(GemmLaunch{dGr, 1, my, mx, maxM, 2L * mx, (long)mx}, s);
+    }
+    double vol = 1.0;
+    for (int k = 0; k < d; ++k) vol *= g.h[k];
+    const cd pre = {vol * cos(d * gamma), vol * sin(d * gamma)};
+    hipLaunchKernelGGL(k_ff_final, dim3(M), dim3(256), 0, s, (const cd *)dPl, (const cd *)dT2, M, mx, pre, dF);
+    hipLaunchKernelGGL(k_unpermute, dim3(ceil_div(M, 256)), dim3(256), 0, s, (const cd *)dF, (const int *)dPerm, M,
+                       Fd);
+    NA_CHECK(hipGetLastError());
+    if (!out_on_device) {
+        NA_CHECK(hipMemcpyAsync(F_out, Fd, (size_t)M * sizeof(cd), hipMemcpyDeviceToHost, s));
+        NA_CHECK(hipStreamSynchronize(s));
+    }
+#undef NA_CHECK
+    return 0;
 }
 
 void launch_axis_exp(cd *out, int m, double lo, double h, double cr, double ci, hipStream_t s)

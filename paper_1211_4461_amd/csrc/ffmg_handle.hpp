@@ -72,6 +72,7 @@ struct ffmg_handle {
     double *d_gm = nullptr;          // its per-step scalars (GM_S doubles)
     double *d_gm_parts = nullptr;    // and partial sums (GM_PARTS doubles)
     hipStream_t stream = nullptr;
+    int device = 0;                  // HIP device current at setup (owns every buffer)
     // coarse end of the 2D cycle run by one workgroup in LDS (levels >= tail_l)
     int tail_l = -1;
     size_t tail_lds[2] = {0, 0};     // [FP64, FP32]

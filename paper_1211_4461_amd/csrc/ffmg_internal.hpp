@@ -347,4 +347,13 @@ int ff_plan_default_variant();
 void ff_plan_set_variant(FarFieldPlan *p, int v);
 int ff_plan_variant(const FarFieldPlan *p);
 void launch_axis_exp(cd *out, int m, double lo, double h, double cr, double ci, hipStream_t s);
+// No-allocation far field: take the scratch array's address on `device` (the
+// current device; once per device), then run the FP64 map from it.  Returns 0
+// on success, 1 if the problem needs more than the scratch array (*need set),
+// 2 if the scratch was not set up on this device, 3 for n_dirs out of range,
+// 4 for a HIP error (*herr).
+hipError_t ff_scratch_init(int device);
+int ff_noalloc_map(const LevelGeom &g, double k0, double gamma, const double eta[3], const cd *q, const cd *u,
+                   int M, const double *dirs, cd *F_out, bool out_on_device, int device, hipStream_t s,
+                   size_t *need, hipError_t *herr);
 }  // namespace ffmg

@@ -66,7 +66,7 @@ EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup
            "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_tune_solve", "mg_solve_batched",
            "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights", "ml_loss_grad",
            "ml_train_step", "ml_net_last_error", "ml_net_destroy", "mg_learned_smooth", "mg_jacobi_factor",
-           "mg_gmres_smooth", "mg_solve_begin", "mg_solve_end"]
+           "mg_gmres_smooth", "mg_solve_begin", "mg_solve_end", "farfield_map_noalloc"]
 
 
 def lib():
@@ -91,6 +91,7 @@ def lib():
     L.mg_solve_begin.argtypes = [vp, vp, vp, dp]
     L.mg_solve_end.argtypes = [vp, ctypes.POINTER(SolveInfo)]
     L.farfield_map.argtypes = [vp, vp, vp, ip, vp, vp]
+    L.farfield_map_noalloc.argtypes = [vp, vp, vp, ip, vp, vp]
     L.mg_apply.argtypes = [vp, vp, vp]
     L.mg_smooth.argtypes = [vp, vp, vp, vp]
     L.mg_residual_norm.argtypes = [vp, vp, vp, ctypes.POINTER(dp)]
@@ -292,6 +293,28 @@ def farfield_map(h: Handle, eta, u, dirs, out=None):
         F = out
         fp = _dev_ptr(out, "F")
     h._check(lib().farfield_map(h.ptr, _eta3(eta), up, M, ctypes.c_void_p(d.ctypes.data), fp), "farfield_map")
+    return F
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # FFMG_NOALLOC_SCRATCH_BYTES
+NOALLOC_MAX_DIRS = 8192            # FFMG_NOALLOC_MAX_DIRS
+
+
+def farfield_map_noalloc(h: Handle, eta, u, dirs, out=None):
+    """farfield_map (FP64 contraction) with every work buffer in the
+    library's static scratch array: no device allocation.  out: complex128
+    device tensor or None (returns a host numpy array)."""
+    d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64))
+    M = d.shape[0]
+    up = None if u is None else _dev_ptr(u, "u")
+    if out is None:
+        F = np.empty(M, dtype=np.complex128)
+        fp = ctypes.c_void_p(F.ctypes.data)
+    else:
+        F = out
+        fp = _dev_ptr(out, "F")
+    h._check(lib().farfield_map_noalloc(h.ptr, _eta3(eta), up, M, ctypes.c_void_p(d.ctypes.data), fp),
+             "farfield_map_noalloc")
     return F
 
 

@@ -67,3 +67,13 @@ def test_struct_layout_matches_header():
     assert fields("ffmg_problem") == [f for f, _ in ffmg.Problem._fields_]
     assert fields("ffmg_options") == [f for f, _ in ffmg.Options._fields_]
     assert fields("ffmg_solve_info") == [f for f, _ in ffmg.SolveInfo._fields_]
+
+
+def test_noalloc_limits_match_header():
+    """The binding's limits of farfield_map_noalloc are the header's."""
+    from paper_1211_4461_amd import ffmg
+    text = open(HEADER).read()
+    scratch = re.search(r"#define FFMG_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert int(scratch.group(1)) << int(scratch.group(2)) == ffmg.NOALLOC_SCRATCH_BYTES
+    dirs = re.search(r"#define FFMG_NOALLOC_MAX_DIRS (\d+)", text)
+    assert int(dirs.group(1)) == ffmg.NOALLOC_MAX_DIRS
