@@ -376,6 +376,11 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
  * the finest level for FP32 cycles, 8-row for FP64; 2: the other height) or
  * as the two-sweep launch followed by the residual + restriction launch (1);
  * one variant for 3D and tile_config 1.
+ * FFMG_TUNE_SWEEP3D: the weighted-Jacobi sweeps of a fused 3D level from a
+ * nonzero guess as one z-marching pass per pair of sweeps (variant 0; the
+ * first sweep's planes held in LDS, the interpolation of the coarse
+ * correction formed inside the first pass) or one pass per sweep (1); one
+ * variant for 2D and tile_config 1.
  * mg_tune_variants returns the number of variants (0 for an unknown
  * tunable); mg_tune_get / mg_tune_set read and select one (a cached choice).
  * mg_tune_farfield builds the integrand of (eta, u) for the n_dirs
@@ -384,8 +389,8 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
  * *best and the mean time of variant v in times_ms[v] (v < n_times; times_ms
  * may be NULL).  Synchronises.
  * mg_tune_solve times `reps` solves of b from u = 0 to tol per variant of
- * `tunable` (FFMG_TUNE_TAIL, FFMG_TUNE_SMOOTH, FFMG_TUNE_PRE or
- * FFMG_TUNE_SMOOTH_COARSE; after one untimed solve),
+ * `tunable` (FFMG_TUNE_TAIL, FFMG_TUNE_SMOOTH, FFMG_TUNE_PRE,
+ * FFMG_TUNE_SMOOTH_COARSE or FFMG_TUNE_SWEEP3D; after one untimed solve),
  * selects the fastest and reports like mg_tune_farfield; u is the caller's
  * workspace and holds the last solution on return.  Synchronises. */
 typedef enum {
@@ -393,7 +398,8 @@ typedef enum {
     FFMG_TUNE_TAIL = 1,
     FFMG_TUNE_SMOOTH = 2,
     FFMG_TUNE_PRE = 3,
-    FFMG_TUNE_SMOOTH_COARSE = 4
+    FFMG_TUNE_SMOOTH_COARSE = 4,
+    FFMG_TUNE_SWEEP3D = 5
 } ffmg_tunable;
 int mg_tune_variants(const ffmg_handle *h, int tunable);
 ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant);

@@ -213,11 +213,13 @@ constexpr int SMOOTH_TH[] = {8, 16, 4};
 constexpr int SMOOTH_VARIANTS = (int)(sizeof(SMOOTH_TH) / sizeof(SMOOTH_TH[0]));
 
 // Fused 3D smoothing chain: nu sweeps from src (0 when zero; src + P ec when
-// ec is given) into dst: from a zero guess the first two sweeps are one pass
-// reading b and q only; with ec the interpolation is formed inside the first
-// sweep; the other sweeps are single z-marching passes (a pass doing two
-// sweeps through LDS planes was slower than two single passes).  tmp is a
-// third buffer, so that the last launch lands in dst without a copy.
+// ec is given) into dst.  From a zero guess the first two sweeps are one
+// pass reading b and q only.  Otherwise, with the two-sweep form (tunable
+// FFMG_TUNE_SWEEP3D, variant 0) every pair of sweeps is one z-marching pass
+// with the planes of the first sweep in LDS (the interpolation formed inside
+// the first pass when ec is given); with variant 1 every sweep is its own
+// pass (the interpolation inside the first one).  tmp is a third buffer, so
+// that the last launch lands in dst without a copy.
 template <typename T>
 void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src, cx<T> *dst, cx<T> *tmp, int nu,
                     bool zero, const cx<T> *ec, int prof_id, const int *stop)
@@ -226,19 +228,28 @@ void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
     const bool finest = (&lv == &h->L[0]);
     const Stencil<T> &P = LP::P(lv);
     const cx<T> *q = LP::q(lv);
-    const bool zero2 = zero && nu >= 2;
-    const int nk = zero2 ? nu - 1 : nu;   // launches
+    const bool pairs = (h->sweep3d_variant == 0);
+    // sweeps done by launch kk of the chain
+    auto sweeps_of = [&](int kk, int left) { return ((kk == 0 && zero) || pairs) ? std::min(2, left) : 1; };
+    int nk = 0;
+    for (int left = nu; left > 0; ++nk) left -= sweeps_of(nk, left);
     const bool alias = (src == dst);      // then launches alternate tmp, dst, ... (a copy ends an odd count)
     const cx<T> *cur = src;
+    int left = nu;
     for (int kk = 0; kk < nk; ++kk) {
+        const int ns = sweeps_of(kk, left);
+        left -= ns;
         cx<T> *o = alias ? ((kk % 2 == 0) ? tmp : dst) : (((nk - 1 - kk) % 2 == 0) ? dst : tmp);
+        const cx<T> *e = (kk == 0) ? ec : nullptr;
         const int pi = finest ? prof_begin(h, prof_id) : -1;
-        if (kk == 0 && zero2)
+        if (kk == 0 && zero && ns == 2)
             launch_sweep3d_fused<T>(true, lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop);
         else if (kk == 0 && zero)
             launch_stencil<T>(MODE_JACOBI0, lv.g, P, cur, b, q, o, nullptr, h->stream, finest, stop);
-        else if (kk == 0 && ec)
-            launch_sweep3d_fused<T>(false, lv.g, P, cur, ec, b, q, o, h->stream, finest, stop);
+        else if (ns == 2)
+            launch_sweep2_3d<T>(lv.g, P, cur, e, b, q, o, h->stream, finest, stop);
+        else if (e)
+            launch_sweep3d_fused<T>(false, lv.g, P, cur, e, b, q, o, h->stream, finest, stop);
         else
             launch_stencil<T>(MODE_JACOBI, lv.g, P, cur, b, q, o, nullptr, h->stream, finest, stop);
         prof_end(h, prof_id, pi);
@@ -594,6 +605,11 @@ void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *st
         launch_refine2d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
         prof_kernel_end(h, PROF_REFINE, pi);
         launch_ctl_update(h->d_ctl, h->d_parts, fused2d_blocks(l0.g), h->stream);
+    } else if (l0.g.dim == 3 && h->opt.tile_config != TILE_REFERENCE) {
+        int pi = prof_kernel_begin(h, PROF_REFINE);
+        launch_refine3d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
+        prof_kernel_end(h, PROF_REFINE, pi);
+        launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
     } else {
         launch_refine_update(l0.u32, ucur, h->d_ctl, l0.g.N(), h->stream, stop);
         launch_resid_to_f32_ctl(l0.g, l0.P64, ucur, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
@@ -806,7 +822,7 @@ void fmg_enqueue(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2
 // two buffers (u and l0.t).
 bool fp32_pingpong(const ffmg_handle *h)
 {
-    return h->opt.precision == FFMG_FP32_IR && h->L[0].g.dim == 2 && h->opt.tile_config != TILE_REFERENCE;
+    return h->opt.precision == FFMG_FP32_IR && h->opt.tile_config != TILE_REFERENCE;
 }
 
 // Queue nb steps (V-cycles, or FP32_IR refinement steps) of the pending solve,
@@ -1456,6 +1472,7 @@ int mg_tune_variants(const ffmg_handle *h, int tunable)
     case FFMG_TUNE_PRE: return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? 3 : 1;
     case FFMG_TUNE_SMOOTH_COARSE:
         return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
+    case FFMG_TUNE_SWEEP3D: return (h->prob.dim == 3 && h->opt.tile_config != TILE_REFERENCE) ? 2 : 1;
     default: return 0;
     }
 }
@@ -1473,6 +1490,7 @@ ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant)
     case FFMG_TUNE_SMOOTH: *variant = h->smooth_variant; return FFMG_OK;
     case FFMG_TUNE_PRE: *variant = h->pre_variant; return FFMG_OK;
     case FFMG_TUNE_SMOOTH_COARSE: *variant = h->smooth_coarse_variant; return FFMG_OK;
+    case FFMG_TUNE_SWEEP3D: *variant = h->sweep3d_variant; return FFMG_OK;
     default: return FFMG_EINVAL;
     }
 }
@@ -1493,6 +1511,7 @@ ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant)
     case FFMG_TUNE_SMOOTH: h->smooth_variant = variant; return FFMG_OK;
     case FFMG_TUNE_PRE: h->pre_variant = variant; return FFMG_OK;
     case FFMG_TUNE_SMOOTH_COARSE: h->smooth_coarse_variant = variant; return FFMG_OK;
+    case FFMG_TUNE_SWEEP3D: h->sweep3d_variant = variant; return FFMG_OK;
     default: return fail(h, FFMG_EINVAL, "unknown tunable %d", tunable);
     }
 }
@@ -1553,7 +1572,7 @@ ffmg_status mg_tune_solve(ffmg_handle *h, int tunable, const void *b, void *u, d
     NOT_PENDING(h);
     if (!h || !b || !u || reps < 1) return fail(h, FFMG_EINVAL, "null argument or reps < 1");
     if (tunable != FFMG_TUNE_TAIL && tunable != FFMG_TUNE_SMOOTH && tunable != FFMG_TUNE_PRE &&
-        tunable != FFMG_TUNE_SMOOTH_COARSE)
+        tunable != FFMG_TUNE_SMOOTH_COARSE && tunable != FFMG_TUNE_SWEEP3D)
         return fail(h, FFMG_EINVAL, "mg_tune_solve tunes the solve's tunables (got %d)", tunable);
     const int nv = mg_tune_variants(h, tunable);
     const size_t bytes = h->L[0].g.N() * sizeof(cd);

@@ -171,6 +171,15 @@ void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const do
 // Mixed-precision refinement (one-operation form): u64 += s * d32 with
 // s = ctl->scale_cur; r64 = b - A u64 written as r64 / ctl->scale_next.
 void launch_refine_update(const cf *d, cd *u, const SolveCtl *ctl, size_t N, hipStream_t s, const int *stop);
+// 3D refinement step in one pass: unew = u + s d, r32 = (b - A unew) / scale_next, block sums of |b - A unew|^2
+// (stencil_blocks(g) partials)
+void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
+                     const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
+                     const int *stop);
+// two Jacobi sweeps in one 3D pass from u (ec: from u + P ec)
+template <typename T>
+void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
+                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop);
 void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
                          cf *r32, double inv_scale, double *partial, hipStream_t s);
 void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,

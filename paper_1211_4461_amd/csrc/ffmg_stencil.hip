@@ -20,7 +20,18 @@ namespace ffmg {
 
 constexpr int TY2 = 16;   // 2D tile: 64 x 16 points per 256-thread block
 constexpr int TY3 = 8;    // 3D tile: 64 x 8 points per plane
-constexpr int TZ3 = 32;   // 3D: planes per block
+constexpr int TZ3 = 32;   // 3D: planes per block on large grids (fewer on small ones, planes_per_block)
+// A z-marching block is latency bound (one plane after the other), so small
+// grids get fewer planes per block and more blocks: the planes per block
+// halve from the maximum until the grid has at least MIN_BLOCKS3 blocks.
+constexpr int MIN_BLOCKS3 = 2048;
+
+static int planes_per_block(long xy_tiles, int mz, int maxp)
+{
+    int tz = maxp;
+    while (tz > 1 && xy_tiles * ((mz + tz - 1) / tz) < MIN_BLOCKS3) tz >>= 1;
+    return tz;
+}
 
 template <typename T>
 Stencil<T> make_stencil(const LevelGeom &g, double gamma, double k02, double omega)
@@ -190,13 +201,19 @@ __device__ __forceinline__ cx<T> prolong_at(const cx<T> *__restrict__ ec, int ix
 //             LDS) add exact zeros here.
 // The per-point arithmetic is that of the separate kernels, so the fused
 // passes reproduce them bit for bit.
-enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2 };
+//   SRC_UPD   u + s d, the FP64 update of the mixed-precision refinement
+//             with the FP32 correction d (the residual of the updated
+//             iterate is formed in the same pass, and the updated iterate
+//             written to unew at the block's own points).
+enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2, SRC_UPD = 3 };
 
 template <typename T, typename TO, int MODE, int SRC>
 __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                cx<TO> *__restrict__ out, const Stencil<T> &P, T rscale, int tiles_x,
-                                               int tiles_y, double *__restrict__ partial)
+                                               int tiles_y, int tz, double *__restrict__ partial,
+                                               const cf *__restrict__ dcorr = nullptr, double dscale = 0.0,
+                                               cx<T> *__restrict__ unew = nullptr)
 {
     constexpr int PY = TY3 / 4;
     // coarse tile of the fine tile plus its one-point halo: 34 x (TY3/2 + 2)
@@ -209,8 +226,8 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
     int txi = tile % tiles_x;
     int rest = tile / tiles_x;
     int tyi = rest % tiles_y, tzi = rest / tiles_y;
-    const int x0 = txi * 64, y0 = tyi * TY3, z0 = tzi * TZ3;
-    const int z1 = min(z0 + TZ3, mz);
+    const int x0 = txi * 64, y0 = tyi * TY3, z0 = tzi * tz;
+    const int z1 = min(z0 + tz, mz);
     const int lx = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
     const int gx = x0 + lx;
     const size_t plane = (size_t)mx * my;
@@ -253,6 +270,12 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
         }
         cx<T> v = ld_masked(u, j, in);
         if (SRC == SRC_PROL && in) v = v + interp(x, y, z);
+        if constexpr (SRC == SRC_UPD) {
+            if (in) {
+                const cf dj = dcorr[j];
+                v = cx<T>{v.re + dscale * (double)dj.re, v.im + dscale * (double)dj.im};
+            }
+        }
         return v;
     };
     // coarse planes a = ((iz + 1) >> 1) - 1 .. (iz + 1) >> 1 serve fine plane iz
@@ -318,6 +341,7 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                     }
                 }
                 point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
+                if constexpr (SRC == SRC_UPD) unew[j] = uc;
             }
         }
         if (!zero_u) {
@@ -335,13 +359,13 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
 template <typename T, typename TO, int MODE, int TAG>
 __global__ __launch_bounds__(256) void k_stencil3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
                                                    const cx<T> *__restrict__ q, cx<TO> *__restrict__ out,
-                                                   Stencil<T> P, T rscale, int tiles_x, int tiles_y,
+                                                   Stencil<T> P, T rscale, int tiles_x, int tiles_y, int tz,
                                                    double *__restrict__ partial, const SolveCtl *__restrict__ ctl,
                                                    const int *__restrict__ stop)
 {
     if (stop && *stop) return;
     if (ctl) rscale = T(1.0 / ctl->scale_next);
-    stencil3d_body<T, TO, MODE, SRC_MEM>(u, nullptr, b, q, out, P, rscale, tiles_x, tiles_y, partial);
+    stencil3d_body<T, TO, MODE, SRC_MEM>(u, nullptr, b, q, out, P, rscale, tiles_x, tiles_y, tz, partial);
 }
 
 // One Jacobi sweep whose input is formed on the fly (SRC_ZERO2, SRC_PROL).
@@ -349,36 +373,212 @@ template <typename T, int SRC, int TAG>
 __global__ __launch_bounds__(256) void k_sweep3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                  const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                  cx<T> *__restrict__ out, Stencil<T> P, int tiles_x, int tiles_y,
-                                                 const int *__restrict__ stop)
+                                                 int tz, const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    stencil3d_body<T, T, MODE_JACOBI, SRC>(u, ec, b, q, out, P, T(1), tiles_x, tiles_y, nullptr);
+    stencil3d_body<T, T, MODE_JACOBI, SRC>(u, ec, b, q, out, P, T(1), tiles_x, tiles_y, tz, nullptr);
 }
 
-static void grid_of(const LevelGeom &g, int &nb, int &tx, int &ty)
+// Two weighted-Jacobi sweeps in one z-marching pass (temporal blocking).  A
+// block owns a 64 x TY output tile of tz planes.  Its 256 threads cover the
+// tile with a two-point halo, (64 + 4) x (TY + 4) columns, thread t taking
+// the columns t, t + 256, ...; every thread keeps a column's last three
+// values of each stage in registers (the z-neighbours) and the stage's
+// current plane goes through LDS for the x/y neighbours:
+//   stage 0  the input at plane z: u (SRC_MEM) or u + P e_c (SRC_PROL, the
+//            coarse planes staged in an LDS ring as in stencil3d_body);
+//   stage 1  the first sweep at plane z - 1 on the tile with a one-point
+//            halo (zero outside the grid);
+//   stage 2  the second sweep at plane z - 2 on the tile, written to out.
+// The planes of each stage alternate between two LDS buffers, so one
+// barrier per plane orders every write before the reads of the next plane.
+// b and omega/D of a column are read at stage 1 and kept for stage 2.  The
+// per-point arithmetic and its order are those of the single sweeps, so the
+// result is bit for bit that of two k_stencil3d / k_sweep3d passes.
+template <typename T, int SRC, int TY, int TAG>
+__global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
+                                                   const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                                   cx<T> *__restrict__ out, Stencil<T> P, int tiles_x, int tiles_y,
+                                                   int tz, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    constexpr int W = 64 + 4, H = TY + 4, NP = W * H, NS = (NP + 255) / 256;
+    constexpr bool PROL = (SRC == SRC_PROL);
+    constexpr int CW = 36, CH = TY / 2 + 4, NCS = PROL ? 4 : 1;
+    __shared__ cx<T> L0[2][NP], L1[2][NP];
+    __shared__ cx<T> cs[NCS][PROL ? CH : 1][PROL ? CW : 1];
+    const int mx = P.mx, my = P.my, mz = P.mz;
+    const int mxc = (mx - 1) / 2, myc = (my - 1) / 2, mzc = (mz - 1) / 2;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int txi = tile % tiles_x, rest = tile / tiles_x;
+    const int tyi = rest % tiles_y, tzi = rest / tiles_y;
+    const int x0 = txi * 64, y0 = tyi * TY, z0 = tzi * tz, z1 = min(z0 + tz, mz);
+    const size_t plane = (size_t)mx * my;
+    const cx<T> zero = {T(0), T(0)};
+    const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;   // coarse origin of cs
+
+    auto load_coarse = [&](int a) {
+        for (int t = threadIdx.x; t < CH * CW; t += 256) {
+            const int yy = t / CW, xx = t - yy * CW;
+            const int ax = cx0 + xx, ay = cy0 + yy;
+            const bool in = a >= 0 && a < mzc && ax >= 0 && ax < mxc && ay >= 0 && ay < myc;
+            cs[a & (NCS - 1)][yy][xx] = ld_masked(ec, ((size_t)a * myc + ay) * mxc + ax, in);
+        }
+    };
+    auto interp = [&](int x, int y, int z) -> cx<T> {
+        const int fx = x + 1, fy = y + 1, fz = z + 1;
+        const int ex = (fx >> 1) - 1 - cx0, ey = (fy >> 1) - 1 - cy0, az = (fz >> 1) - 1;
+        const T wx[2] = {(fx & 1) ? T(0.5) : T(1), (fx & 1) ? T(0.5) : T(0)};
+        const T wy[2] = {(fy & 1) ? T(0.5) : T(1), (fy & 1) ? T(0.5) : T(0)};
+        const T wz[2] = {(fz & 1) ? T(0.5) : T(1), (fz & 1) ? T(0.5) : T(0)};
+        cx<T> acc = {T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int jy = 0; jy < 2; ++jy)
+#pragma unroll
+                for (int ix = 0; ix < 2; ++ix)
+                    acc = acc + ((wx[ix] * wy[jy]) * wz[k]) * cs[(az + k) & (NCS - 1)][ey + jy][ex + ix];
+        return acc;
+    };
+    // column of slot k: region row r, column c; grid point (gx, gy)
+    auto col = [&](int k, int &r, int &c, int &gx, int &gy) {
+        const int t = threadIdx.x + 256 * k;
+        r = t / W;
+        c = t - r * W;
+        gx = x0 - 2 + c;
+        gy = y0 - 2 + r;
+    };
+
+    int a_hi = 0;
+    if (PROL) {
+        const int A0 = (z0 - 1) >> 1;   // coarse planes of the first stage-0 plane z0 - 2
+        load_coarse(A0 - 1);
+        load_coarse(A0);
+        a_hi = A0;
+        __syncthreads();
+    }
+    cx<T> a0[NS], a1[NS], a2[NS];   // stage 0 at planes z - 2, z - 1, z
+    cx<T> c0[NS], c1[NS], c2[NS];   // stage 1 at planes z - 3, z - 2, z - 1
+    cx<T> bA[NS], wA[NS];           // b, omega / D at plane z - 1
+    cx<T> bB[NS], wB[NS];           // the same at plane z - 2
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        a0[k] = a1[k] = a2[k] = zero;
+        c0[k] = c1[k] = c2[k] = zero;
+        bA[k] = wA[k] = bB[k] = wB[k] = zero;
+    }
+    for (int z = z0 - 2; z <= z1 + 1; ++z) {
+        // the coarse plane the next stage-0 plane needs (read after the barrier)
+        if (PROL && ((z + 2) >> 1) > a_hi) load_coarse(++a_hi);
+        // stage 0: the input at plane z
+        cx<T> *l0w = L0[z & 1];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            int r, c, gx, gy;
+            col(k, r, c, gx, gy);
+            const int t = threadIdx.x + 256 * k;
+            const bool in = t < NP && gx >= 0 && gx < mx && gy >= 0 && gy < my && z >= 0 && z < mz;
+            cx<T> v = ld_masked(u, (size_t)z * plane + (size_t)gy * mx + gx, in);
+            if (PROL && in) v = v + interp(gx, gy, z);
+            a0[k] = a1[k];
+            a1[k] = a2[k];
+            a2[k] = v;
+            if (t < NP) l0w[t] = v;
+        }
+        // stage 1: the first sweep at plane p1 = z - 1
+        const int p1 = z - 1;
+        if (p1 >= z0 - 1) {
+            const cx<T> *l0r = L0[p1 & 1];
+            cx<T> *l1w = L1[p1 & 1];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                int r, c, gx, gy;
+                col(k, r, c, gx, gy);
+                const int t = threadIdx.x + 256 * k;
+                const bool s1 = t < NP && r >= 1 && r < H - 1 && c >= 1 && c < W - 1;
+                bB[k] = bA[k];
+                wB[k] = wA[k];
+                c0[k] = c1[k];
+                c1[k] = c2[k];
+                cx<T> v = zero;
+                if (s1 && gx >= 0 && gx < mx && gy >= 0 && gy < my && p1 >= 0 && p1 < mz) {
+                    const size_t j = (size_t)p1 * plane + (size_t)gy * mx + gx;
+                    const cx<T> bj = b[j], wj = jweight(P, q[j]);
+                    bA[k] = bj;
+                    wA[k] = wj;
+                    cx<T> N = nsum_xy(P, l0r[t - 1], l0r[t + 1], l0r[t - W], l0r[t + W]);
+                    N = nsum_add_z(P, N, a0[k], a2[k]);
+                    v = jacobi_n(P, N, a1[k], bj, wj);
+                }
+                c2[k] = v;
+                if (s1) l1w[t] = v;
+            }
+        }
+        // stage 2: the second sweep at plane p2 = z - 2, the block's output
+        const int p2 = z - 2;
+        if (p2 >= z0) {
+            const cx<T> *l1r = L1[p2 & 1];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                int r, c, gx, gy;
+                col(k, r, c, gx, gy);
+                const int t = threadIdx.x + 256 * k;
+                const bool s2 = t < NP && r >= 2 && r < H - 2 && c >= 2 && c < W - 2 && gx < mx && gy < my;
+                if (s2) {
+                    cx<T> N = nsum_xy(P, l1r[t - 1], l1r[t + 1], l1r[t - W], l1r[t + W]);
+                    N = nsum_add_z(P, N, c0[k], c2[k]);
+                    out[(size_t)p2 * plane + (size_t)gy * mx + gx] = jacobi_n(P, N, c1[k], bB[k], wB[k]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The FP64 step of the mixed-precision refinement in one pass: u' = u + s d
+// (s = ctl->scale_cur) into unew, and the residual b - A u' written as FP32
+// scaled by 1 / ctl->scale_next, with the per-block FP64 sums of |b - A u'|^2.
+// The same arithmetic as k_refine_update followed by the FP64 residual.
+__global__ __launch_bounds__(256) void k_refine3d(const cd *__restrict__ u, const cf *__restrict__ d,
+                                                  const cd *__restrict__ b, const cd *__restrict__ q,
+                                                  cd *__restrict__ unew, cf *__restrict__ r32, Stencil<double> P,
+                                                  int tiles_x, int tiles_y, int tz, double *__restrict__ partial,
+                                                  const SolveCtl *__restrict__ ctl, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    const double rscale = 1.0 / ctl->scale_next;
+    stencil3d_body<double, float, MODE_RESID, SRC_UPD>(u, nullptr, b, q, r32, P, rscale, tiles_x, tiles_y, tz,
+                                                       partial, d, ctl->scale_cur, unew);
+}
+
+// Blocks of a stencil launch on grid g: tiles in x (tx) and y (ty) and, in
+// 3D, the planes each block marches through (tz).
+static void grid_of(const LevelGeom &g, int &nb, int &tx, int &ty, int &tz)
 {
     tx = (g.m[0] + 63) / 64;
     if (g.dim == 2) {
         ty = (g.m[1] + TY2 - 1) / TY2;
+        tz = 1;
         nb = tx * ty;
     } else {
         ty = (g.m[1] + TY3 - 1) / TY3;
-        int tz = (g.m[2] + TZ3 - 1) / TZ3;
-        nb = tx * ty * tz;
+        tz = planes_per_block((long)tx * ty, g.m[2], TZ3);
+        nb = tx * ty * ((g.m[2] + tz - 1) / tz);
     }
 }
 
 int stencil_blocks(const LevelGeom &g)
 {
-    int nb, tx, ty;
-    grid_of(g, nb, tx, ty);
+    int nb, tx, ty, tz;
+    grid_of(g, nb, tx, ty, tz);
     return nb;
 }
 
 void stencil_grid2d(const LevelGeom &g, int *nb, int *tiles_x)
 {
-    int ty;
-    grid_of(g, *nb, *tiles_x, ty);
+    int ty, tz;
+    grid_of(g, *nb, *tiles_x, ty, tz);
 }
 
 template <typename T, typename TO, int MODE, int TAG = 0>
@@ -386,14 +586,14 @@ static void launch_mode(const LevelGeom &g, const Stencil<T> &P, T rscale, const
                         const cx<T> *q, cx<TO> *out, double *partial, hipStream_t s, const SolveCtl *ctl = nullptr,
                         const int *stop = nullptr)
 {
-    int nb, tx, ty;
-    grid_of(g, nb, tx, ty);
+    int nb, tx, ty, tz;
+    grid_of(g, nb, tx, ty, tz);
     if (g.dim == 2)
         hipLaunchKernelGGL((k_stencil2d<T, TO, MODE, TAG>), dim3(nb), dim3(256), 0, s, u, b, q, out, P, rscale, tx,
                            partial, ctl, stop);
     else
         hipLaunchKernelGGL((k_stencil3d<T, TO, MODE, TAG>), dim3(nb), dim3(256), 0, s, u, b, q, out, P, rscale, tx,
-                           ty, partial, ctl, stop);
+                           ty, tz, partial, ctl, stop);
 }
 
 template <typename T>
@@ -422,24 +622,67 @@ template <typename T>
 void launch_sweep3d_fused(bool zero2, const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec,
                           const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop)
 {
-    int nb, tx, ty;
-    grid_of(g, nb, tx, ty);
+    int nb, tx, ty, tz;
+    grid_of(g, nb, tx, ty, tz);
     if (zero2) {
         if (finest)
             hipLaunchKernelGGL((k_sweep3d<T, SRC_ZERO2, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx, ty,
-                               stop);
+                               tz, stop);
         else
             hipLaunchKernelGGL((k_sweep3d<T, SRC_ZERO2, 0>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx, ty,
-                               stop);
+                               tz, stop);
     } else {
         if (finest)
             hipLaunchKernelGGL((k_sweep3d<T, SRC_PROL, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx, ty,
-                               stop);
+                               tz, stop);
         else
             hipLaunchKernelGGL((k_sweep3d<T, SRC_PROL, 0>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx, ty,
-                               stop);
+                               tz, stop);
     }
 }
+// Output rows per block of the fused two-sweep 3D kernel (its LDS and
+// registers grow with the tile: 4 rows in FP64).
+template <typename T> constexpr int sweep2_rows() { return sizeof(T) == 4 ? 8 : 4; }
+
+template <typename T>
+void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
+                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop)
+{
+    constexpr int TY = sweep2_rows<T>();
+    const int tx = (g.m[0] + 63) / 64, ty = (g.m[1] + TY - 1) / TY;
+    const int tz = planes_per_block((long)tx * ty, g.m[2], TZ3);
+    const int nb = tx * ty * ((g.m[2] + tz - 1) / tz);
+    if (ec) {
+        if (finest)
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
+                               ty, tz, stop);
+        else
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 0>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
+                               ty, tz, stop);
+    } else {
+        if (finest)
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
+                               ty, tz, stop);
+        else
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 0>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
+                               ty, tz, stop);
+    }
+}
+template void launch_sweep2_3d<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *, const cd *,
+                                       const cd *, cd *, hipStream_t, bool, const int *);
+template void launch_sweep2_3d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *, const cf *,
+                                      const cf *, cf *, hipStream_t, bool, const int *);
+
+void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
+                     const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
+                     const int *stop)
+{
+    int nb, tx, ty, tz;
+    grid_of(g, nb, tx, ty, tz);
+    hipLaunchKernelGGL(k_refine3d, dim3(nb), dim3(256), 0, s, u, d, b, q, unew, r32, P, tx, ty, tz, partial, ctl,
+                       stop);
+}
+
 template void launch_sweep3d_fused<double>(bool, const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
                                            const cd *, const cd *, cd *, hipStream_t, bool, const int *);
 template void launch_sweep3d_fused<float>(bool, const LevelGeom &, const Stencil<float> &, const cf *, const cf *,
@@ -530,14 +773,14 @@ template void launch_restrict<float>(const LevelGeom &, const cf *, cf *, hipStr
 // fine plane is done.  The residual and the weighted sum are those of
 // k_stencil3d (MODE_RESID) and k_restrict, in the same order, so the result
 // is bit for bit that of the two passes.
-constexpr int RX3 = 32, RY3 = 4, RZ3 = 16;
+constexpr int RX3 = 32, RY3 = 4, RZ3 = 16;   // RZ3: coarse planes per block on large grids
 constexpr int RFW = 2 * RX3 + 1, RFH = 2 * RY3 + 1;   // fine residual region of a plane
 constexpr int RUW = RFW + 2, RUH = RFH + 2;           // u region (one halo)
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
                                                           const cx<T> *__restrict__ q, cx<T> *__restrict__ bc,
-                                                          Stencil<T> P, int tiles_x, int tiles_y,
+                                                          Stencil<T> P, int tiles_x, int tiles_y, int rz,
                                                           const int *__restrict__ stop)
 {
     if (stop && *stop) return;
@@ -548,8 +791,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restric
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int txi = tile % tiles_x, rest = tile / tiles_x;
     const int tyi = rest % tiles_y, tzi = rest / tiles_y;
-    const int I0 = txi * RX3, J0 = tyi * RY3, K0 = tzi * RZ3;
-    const int K1 = min(K0 + RZ3, mzc);
+    const int I0 = txi * RX3, J0 = tyi * RY3, K0 = tzi * rz;
+    const int K1 = min(K0 + rz, mzc);
     const int fx0 = 2 * I0, fy0 = 2 * J0;                 // fine origin of the residual region
     const size_t plane = (size_t)mx * my;
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
@@ -658,8 +901,9 @@ void launch_resid_restrict3d(const LevelGeom &f, const Stencil<T> &P, const cx<T
                              cx<T> *bc, hipStream_t s, const int *stop)
 {
     const int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.m[2] - 1) / 2;
-    const int tx = (mxc + RX3 - 1) / RX3, ty = (myc + RY3 - 1) / RY3, tz = (mzc + RZ3 - 1) / RZ3;
-    hipLaunchKernelGGL(k_resid_restrict3d<T>, dim3(tx * ty * tz), dim3(256), 0, s, u, b, q, bc, P, tx, ty, stop);
+    const int tx = (mxc + RX3 - 1) / RX3, ty = (myc + RY3 - 1) / RY3;
+    const int rz = planes_per_block((long)tx * ty, mzc, RZ3), tz = (mzc + rz - 1) / rz;
+    hipLaunchKernelGGL(k_resid_restrict3d<T>, dim3(tx * ty * tz), dim3(256), 0, s, u, b, q, bc, P, tx, ty, rz, stop);
 }
 template void launch_resid_restrict3d<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
                                               const cd *, cd *, hipStream_t, const int *);

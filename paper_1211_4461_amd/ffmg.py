@@ -323,6 +323,7 @@ TUNE_TAIL = 1
 TUNE_SMOOTH = 2
 TUNE_PRE = 3
 TUNE_SMOOTH_COARSE = 4
+TUNE_SWEEP3D = 5
 
 
 def _etas(etas):

@@ -308,31 +308,45 @@ def test_fused_2d_path_is_bitwise_identical(ff, orc, n):
             assert torch.equal(uf, ur2)
 
 
-@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("n", [32, 64, 128])
 def test_fused_3d_path_is_bitwise_identical(ff, orc, n):
-    """The fused 3D sweeps (two sweeps from a zero guess in one pass, the
-    interpolation formed inside the first post-smoothing sweep) perform the
-    per-point arithmetic of the one-operation kernels: iterates agree bit for
-    bit with the reference path, for FP64 V-cycles with several (nu1, nu2)
-    and for FP32-in-FP64 solves."""
+    """The fused 3D sweeps (two sweeps from a zero guess in one pass; two
+    sweeps from a nonzero guess in one pass with the first sweep's planes in
+    LDS, or one pass per sweep; the interpolation formed inside the first
+    post-smoothing pass) and the one-pass FP64 refinement step (update +
+    residual, iterate ping-ponged between two buffers) perform the per-point
+    arithmetic of the one-operation kernels: iterates agree bit for bit with
+    the reference path, for FP64 V-cycles with several (nu1, nu2) and for
+    FP32-in-FP64 solves from u = 0 and from the full multigrid start (odd and
+    even step counts), on grids with ragged x, y and z tiles."""
     w = W.radial_3d(n, L=5.0, k0=1.3, n_az=4, n_pol=3)
     for nu1, nu2 in [(2, 2), (1, 1), (3, 1), (0, 2), (0, 1), (0, 3), (2, 0), (4, 3)]:
-        hf, _, g, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2)
-        hr, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2, tile_config=1)
-        b = ff.mg_rhs_plane_wave(hf, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
-        uf, ur = torch.zeros_like(b), torch.zeros_like(b)
+        hr, _, g, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2, tile_config=1)
+        b = ff.mg_rhs_plane_wave(hr, w.eta, torch.empty(g.shape, dtype=torch.complex128, device="cuda"))
+        ur = torch.zeros_like(b)
         for _ in range(2):
-            ff.mg_vcycle(hf, b, uf)
             ff.mg_vcycle(hr, b, ur)
-        torch.cuda.synchronize()
-        assert torch.equal(uf, ur), (nu1, nu2)
-    hf, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR)
-    hr, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, tile_config=1)
-    uf, ur = torch.zeros_like(b), torch.zeros_like(b)
-    i1 = ff.mg_solve(hf, b, uf)
-    i2 = ff.mg_solve(hr, b, ur)
-    assert i1.cycles == i2.cycles and i1.rel_residual == i2.rel_residual
-    assert torch.equal(uf, ur)
+        for v in range(2):
+            hf, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2)
+            assert ff.mg_tune_variants(hf, ff.TUNE_SWEEP3D) == 2
+            ff.mg_tune_set(hf, v, ff.TUNE_SWEEP3D)
+            uf = torch.zeros_like(b)
+            for _ in range(2):
+                ff.mg_vcycle(hf, b, uf)
+            torch.cuda.synchronize()
+            assert torch.equal(uf, ur), (nu1, nu2, v)
+    for fk in (0, 1, 2):
+        hr, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, tile_config=1, fmg_cycles=fk)
+        ur = torch.zeros_like(b)
+        i2 = ff.mg_solve(hr, b, ur)
+        for v in range(2):
+            hf, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, fmg_cycles=fk)
+            ff.mg_tune_set(hf, v, ff.TUNE_SWEEP3D)
+            for rep in range(2):          # the second solve starts from the other buffer when the count is odd
+                uf = torch.zeros_like(b)
+                i1 = ff.mg_solve(hf, b, uf)
+                assert i1.cycles == i2.cycles and i1.rel_residual == i2.rel_residual, (fk, v, rep)
+                assert torch.equal(uf, ur), (fk, v, rep)
 
 
 @pytest.mark.parametrize("n", [256, 512])
