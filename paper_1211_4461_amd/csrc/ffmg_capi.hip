@@ -242,7 +242,9 @@ void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
         cx<T> *o = alias ? ((kk % 2 == 0) ? tmp : dst) : (((nk - 1 - kk) % 2 == 0) ? dst : tmp);
         const cx<T> *e = (kk == 0) ? ec : nullptr;
         const int pi = finest ? prof_begin(h, prof_id) : -1;
-        if (kk == 0 && zero && ns == 2)
+        if (kk == 0 && zero && ns == 2 && pairs)
+            launch_sweep2_3d<T>(lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop, true);
+        else if (kk == 0 && zero && ns == 2)
             launch_sweep3d_fused<T>(true, lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop);
         else if (kk == 0 && zero)
             launch_stencil<T>(MODE_JACOBI0, lv.g, P, cur, b, q, o, nullptr, h->stream, finest, stop);

@@ -71,6 +71,41 @@ __device__ __forceinline__ cx<T> ld_masked(const cx<T> *__restrict__ p, size_t j
     return in ? v : cx<T>{T(0), T(0)};
 }
 
+// Loads through a buffer resource (a base address and a byte range held in
+// scalar registers): a load whose byte offset lies outside the range returns
+// zeros instead of touching memory, so a kernel can issue every load of a
+// tile unconditionally (no branch around it, no wait right after it) and get
+// the zero values of points outside the grid for free.  BUF_OOB is an offset
+// outside every range the kernels build (arrays are addressed per plane).
+constexpr unsigned BUF_OOB = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *base, unsigned bytes)
+{
+    // dword 3: raw (stride 0) 32-bit data format, range-checked by offset
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> ld_buf(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    else
+        return __builtin_bit_cast(cx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// Barrier of a workgroup whose threads exchange data through LDS only: the
+// fences order LDS accesses around it and leave global loads in flight (a
+// full __syncthreads also waits for every outstanding global load, which
+// defeats loads issued a plane ahead).  Not for data passed through global
+// memory.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Block index -> tile index such that each XCD (blocks are dispatched
 // round-robin over the 8 XCDs) receives a contiguous run of tiles, so halo
 // rows shared by neighbouring tiles are served by the same L2.

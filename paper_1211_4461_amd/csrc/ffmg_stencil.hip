@@ -207,6 +207,31 @@ __device__ __forceinline__ cx<T> prolong_at(const cx<T> *__restrict__ ec, int ix
 //             written to unew at the block's own points).
 enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2, SRC_UPD = 3 };
 
+// The point update of a 3D pass with b_j and q_j already in registers.
+template <typename T, typename TO, int MODE>
+__device__ __forceinline__ void point_update_v(const Stencil<T> &P, T rscale, cx<T> uc, cx<T> L, size_t j, cx<T> bj,
+                                               cx<T> qj, cx<TO> *__restrict__ out, double &acc)
+{
+    if (MODE == MODE_APPLY) {
+        out[j] = cvt<TO>(apply_point(P, L, uc, qj));
+    } else if (MODE == MODE_JACOBI0) {
+        out[j] = cvt<TO>(jacobi0_w(bj, jweight(P, qj)));
+    } else if (MODE == MODE_JACOBI) {
+        out[j] = cvt<TO>(jacobi_n(P, L, uc, bj, jweight(P, qj)));
+    } else {
+        cx<T> r = resid_from(P, L, uc, bj, qj);
+        if (MODE == MODE_RESID) out[j] = cvt<TO>(rscale * r);
+        acc += (double)abs2(r);
+    }
+}
+
+// Raw loads of one stencil value (the source form is applied when it is used).
+template <typename T>
+struct Raw3 {
+    cx<T> a;   // u (SRC_MEM, SRC_PROL, SRC_UPD) or b (SRC_ZERO2)
+    cx<T> c;   // d widened exactly (SRC_UPD) or q (SRC_ZERO2)
+};
+
 template <typename T, typename TO, int MODE, int SRC>
 __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
@@ -216,8 +241,11 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                                                cx<T> *__restrict__ unew = nullptr)
 {
     constexpr int PY = TY3 / 4;
+    constexpr int NH = 2 * TY3 + 2 * 66;   // halo values of a plane: the x sides, then the y rows
     // coarse tile of the fine tile plus its one-point halo: 34 x (TY3/2 + 2)
     constexpr int CW = 34, CH = TY3 / 2 + 2, NCS = SRC == SRC_PROL ? 4 : 1;
+    constexpr bool ZU = (MODE == MODE_JACOBI0);   // the stencil's u is zero: no u is read
+    constexpr bool NEED_B = (MODE != MODE_APPLY);
     __shared__ cx<T> s[2][TY3 + 2][66];
     __shared__ cx<T> cs[NCS][SRC == SRC_PROL ? CH : 1][SRC == SRC_PROL ? CW : 1];
     const int mx = P.mx, my = P.my, mz = P.mz;
@@ -231,7 +259,7 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
     const int lx = threadIdx.x & 63, ly0 = threadIdx.x >> 6;
     const int gx = x0 + lx;
     const size_t plane = (size_t)mx * my;
-    const bool zero_u = (MODE == MODE_JACOBI0);
+    const unsigned pbytes = (unsigned)(plane * sizeof(cx<T>));
     const cx<T> zero = {T(0), T(0)};
     const int cx0 = (x0 >> 1) - 1, cy0 = (y0 >> 1) - 1;   // coarse origin of cs
 
@@ -261,23 +289,69 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                     acc = acc + ((wx[ix] * wy[jy]) * wz[k]) * cs[(az + k) & (NCS - 1)][ey + jy][ex + ix];
         return acc;
     };
-    auto ld = [&](int x, int y, int z) -> cx<T> {
-        bool in = !zero_u && x >= 0 && x < mx && y >= 0 && y < my && z >= 0 && z < mz;
-        const size_t j = (size_t)z * plane + (size_t)y * mx + x;
-        if (SRC == SRC_ZERO2) {
-            if (!in) return zero;
-            return jacobi0_w(b[j], jweight(P, q[j]));
+
+    // own points (gx, y0 + ly0 + 4 i) and this thread's halo value of a plane
+    unsigned offo[PY];
+    bool ino[PY];
+#pragma unroll
+    for (int i = 0; i < PY; ++i) {
+        const int gy = y0 + ly0 + 4 * i;
+        ino[i] = gx < mx && gy < my;
+        offo[i] = ino[i] ? (unsigned)(gy * mx + gx) * (unsigned)sizeof(cx<T>) : BUF_OOB;
+    }
+    const bool hact = threadIdx.x < NH;   // this thread loads a halo value
+    int hly = 0, hlx = 0;                 // its LDS position
+    {
+        const int t = threadIdx.x;
+        if (t < 2 * TY3) {
+            const int side = t / TY3, yy = t - side * TY3;
+            hlx = side ? 65 : 0;
+            hly = yy + 1;
+        } else {
+            const int t2 = t - 2 * TY3;
+            const int side = t2 / 66, xx = t2 - side * 66;
+            hly = side ? TY3 + 1 : 0;
+            hlx = xx;
         }
-        cx<T> v = ld_masked(u, j, in);
-        if (SRC == SRC_PROL && in) v = v + interp(x, y, z);
-        if constexpr (SRC == SRC_UPD) {
-            if (in) {
-                const cf dj = dcorr[j];
-                v = cx<T>{v.re + dscale * (double)dj.re, v.im + dscale * (double)dj.im};
+    }
+    const int hx = x0 + hlx - 1, hy = y0 + hly - 1;
+    const bool inh = hact && hx >= 0 && hx < mx && hy >= 0 && hy < my;
+    const unsigned offh = inh ? (unsigned)(hy * mx + hx) * (unsigned)sizeof(cx<T>) : BUF_OOB;
+
+    // raw loads of a plane at the byte offset off (zero outside the grid)
+    auto fetch = [&](int z, unsigned off) -> Raw3<T> {
+        const bool zin = z >= 0 && z < mz;
+        const size_t o = zin ? (size_t)z * plane : 0;
+        const unsigned nb = zin ? pbytes : 0u;
+        Raw3<T> r;
+        r.c = zero;
+        if constexpr (SRC == SRC_ZERO2) {
+            r.a = ld_buf<T>(buf_rsrc(b + o, nb), off);
+            r.c = ld_buf<T>(buf_rsrc(q + o, nb), off);
+        } else {
+            r.a = ld_buf<T>(buf_rsrc(u + o, nb), off);
+            if constexpr (SRC == SRC_UPD) {
+                const unsigned offd = (off == BUF_OOB) ? BUF_OOB : off / 2u;   // FP32 complex: half the bytes
+                const cf dj = ld_buf<float>(buf_rsrc(dcorr + o, nb / 2u), offd);
+                r.c = cx<T>{(T)dj.re, (T)dj.im};
             }
         }
-        return v;
+        return r;
     };
+    // the stencil value from its raw loads (in: the point lies in the grid)
+    auto finish = [&](const Raw3<T> &r, bool in, int x, int y, int z) -> cx<T> {
+        if constexpr (SRC == SRC_ZERO2) {
+            return in ? jacobi0_w(r.a, jweight(P, r.c)) : zero;
+        } else if constexpr (SRC == SRC_PROL) {
+            return in ? r.a + interp(x, y, z) : r.a;
+        } else if constexpr (SRC == SRC_UPD) {
+            return in ? cx<T>{r.a.re + dscale * r.c.re, r.a.im + dscale * r.c.im} : r.a;
+        } else {
+            return r.a;
+        }
+    };
+    auto zin_of = [&](int z) { return z >= 0 && z < mz; };
+
     // coarse planes a = ((iz + 1) >> 1) - 1 .. (iz + 1) >> 1 serve fine plane iz
     int a_hi = 0;
     if (SRC == SRC_PROL) {
@@ -287,11 +361,33 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
     }
 
     cx<T> prev[PY], cur[PY], nxt[PY];
+    Raw3<T> rn[PY], rh;   // loads of the next plane (own points) and of this plane's halo, one plane ahead
+    cx<T> bo[PY], qo[PY];  // b, q of the own points of the next plane
+    if (!ZU) {
 #pragma unroll
-    for (int i = 0; i < PY; ++i) {
-        prev[i] = ld(gx, y0 + ly0 + 4 * i, z0 - 1);
-        cur[i] = ld(gx, y0 + ly0 + 4 * i, z0);
+        for (int i = 0; i < PY; ++i) {
+            const int gy = y0 + ly0 + 4 * i;
+            prev[i] = finish(fetch(z0 - 1, offo[i]), ino[i] && zin_of(z0 - 1), gx, gy, z0 - 1);
+            cur[i] = finish(fetch(z0, offo[i]), ino[i] && zin_of(z0), gx, gy, z0);
+            rn[i] = fetch(z0 + 1, offo[i]);
+        }
+        rh = fetch(z0, offh);
     }
+    auto fetch_bq = [&](int z) {
+        const bool zin = zin_of(z);
+        const size_t o = zin ? (size_t)z * plane : 0;
+        const unsigned nb = zin ? pbytes : 0u;
+        const auto rb = buf_rsrc(b + o, nb), rq = buf_rsrc(q + o, nb);
+#pragma unroll
+        for (int i = 0; i < PY; ++i) {
+            if (NEED_B) bo[i] = ld_buf<T>(rb, offo[i]);
+            qo[i] = ld_buf<T>(rq, offo[i]);
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < PY; ++i) bo[i] = qo[i] = zero;
+    fetch_bq(z0);
+
     double acc = 0.0;
     int it = 0;
     for (int z = z0; z < z1; ++z, ++it) {
@@ -302,33 +398,36 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
             load_coarse(++a_hi);
             __syncthreads();
         }
-        if (!zero_u) {
+        cx<T> bc[PY], qc[PY];
+#pragma unroll
+        for (int i = 0; i < PY; ++i) {
+            bc[i] = bo[i];
+            qc[i] = qo[i];
+        }
+        if (!ZU) {
 #pragma unroll
             for (int i = 0; i < PY; ++i) s[buf][ly0 + 4 * i + 1][lx + 1] = cur[i];
-            for (int t = threadIdx.x; t < 2 * TY3 + 2 * 66; t += 256) {
-                if (t < 2 * TY3) {
-                    int side = t / TY3, yy = t - side * TY3;
-                    int xx = side ? 65 : 0;
-                    s[buf][yy + 1][xx] = ld(x0 + xx - 1, y0 + yy, z);
-                } else {
-                    int t2 = t - 2 * TY3;
-                    int side = t2 / 66, xx = t2 - side * 66;
-                    int yy = side ? TY3 + 1 : 0;
-                    s[buf][yy][xx] = ld(x0 + xx - 1, y0 + yy - 1, z);
-                }
-            }
+            if (hact) s[buf][hly][hlx] = finish(rh, inh && zin_of(z), hx, hy, z);
 #pragma unroll
-            for (int i = 0; i < PY; ++i) nxt[i] = ld(gx, y0 + ly0 + 4 * i, z + 1);
-            __syncthreads();
+            for (int i = 0; i < PY; ++i)
+                nxt[i] = finish(rn[i], ino[i] && zin_of(z + 1), gx, y0 + ly0 + 4 * i, z + 1);
+            // the next plane's loads, in flight across the barrier
+            if (z + 1 < z1) {
+#pragma unroll
+                for (int i = 0; i < PY; ++i) rn[i] = fetch(z + 2, offo[i]);
+                rh = fetch(z + 1, offh);
+            }
         }
+        if (z + 1 < z1) fetch_bq(z + 1);
+        if (!ZU) lds_barrier();
 #pragma unroll
         for (int i = 0; i < PY; ++i) {
             int ly = ly0 + 4 * i;
             int gy = y0 + ly;
-            if (gx < mx && gy < my) {
+            if (ino[i]) {
                 size_t j = (size_t)z * plane + (size_t)gy * mx + gx;
                 cx<T> uc = {T(0), T(0)}, lap = {T(0), T(0)};
-                if (!zero_u) {
+                if (!ZU) {
                     uc = cur[i];
                     if (MODE == MODE_JACOBI) {
                         lap = nsum_xy(P, s[buf][ly + 1][lx], s[buf][ly + 1][lx + 2], s[buf][ly][lx + 1],
@@ -340,11 +439,11 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                         lap = lap_add_z(P, lap, uc, prev[i], nxt[i]);
                     }
                 }
-                point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
+                point_update_v<T, TO, MODE>(P, rscale, uc, lap, j, bc[i], qc[i], out, acc);
                 if constexpr (SRC == SRC_UPD) unew[j] = uc;
             }
         }
-        if (!zero_u) {
+        if (!ZU) {
 #pragma unroll
             for (int i = 0; i < PY; ++i) {
                 prev[i] = cur[i];
@@ -386,15 +485,20 @@ __global__ __launch_bounds__(256) void k_sweep3d(const cx<T> *__restrict__ u, co
 // values of each stage in registers (the z-neighbours) and the stage's
 // current plane goes through LDS for the x/y neighbours:
 //   stage 0  the input at plane z: u (SRC_MEM) or u + P e_c (SRC_PROL, the
-//            coarse planes staged in an LDS ring as in stencil3d_body);
+//            coarse planes staged in an LDS ring), or zero (SRC_ZERO2: the
+//            first sweep from a zero guess is omega b / D, which needs no
+//            neighbour, so stage 0 does nothing);
 //   stage 1  the first sweep at plane z - 1 on the tile with a one-point
 //            halo (zero outside the grid);
 //   stage 2  the second sweep at plane z - 2 on the tile, written to out.
 // The planes of each stage alternate between two LDS buffers, so one
-// barrier per plane orders every write before the reads of the next plane.
-// b and omega/D of a column are read at stage 1 and kept for stage 2.  The
-// per-point arithmetic and its order are those of the single sweeps, so the
-// result is bit for bit that of two k_stencil3d / k_sweep3d passes.
+// barrier per plane orders every write before the reads of the next plane;
+// the barrier fences LDS only, and every global load (u of the next plane, b
+// and q of the plane stage 1 takes next, the next coarse plane) is issued one
+// plane ahead, so that it is in flight across the barrier.  b and omega/D of
+// a column are read at stage 1 and kept for stage 2.  The per-point
+// arithmetic and its order are those of the single sweeps, so the result is
+// bit for bit that of two k_stencil3d / k_sweep3d passes.
 template <typename T, int SRC, int TY, int TAG>
 __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                    const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
@@ -403,9 +507,10 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
 {
     if (stop && *stop) return;
     constexpr int W = 64 + 4, H = TY + 4, NP = W * H, NS = (NP + 255) / 256;
-    constexpr bool PROL = (SRC == SRC_PROL);
+    constexpr bool PROL = (SRC == SRC_PROL), ZERO = (SRC == SRC_ZERO2);
     constexpr int CW = 36, CH = TY / 2 + 4, NCS = PROL ? 4 : 1;
-    __shared__ cx<T> L0[2][NP], L1[2][NP];
+    constexpr int NCL = PROL ? (CH * CW + 255) / 256 : 1;   // coarse values per thread and plane
+    __shared__ cx<T> L0[ZERO ? 1 : 2][ZERO ? 1 : NP], L1[2][NP];
     __shared__ cx<T> cs[NCS][PROL ? CH : 1][PROL ? CW : 1];
     const int mx = P.mx, my = P.my, mz = P.mz;
     const int mxc = (mx - 1) / 2, myc = (my - 1) / 2, mzc = (mz - 1) / 2;
@@ -417,12 +522,54 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
     const cx<T> zero = {T(0), T(0)};
     const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;   // coarse origin of cs
 
-    auto load_coarse = [&](int a) {
-        for (int t = threadIdx.x; t < CH * CW; t += 256) {
-            const int yy = t / CW, xx = t - yy * CW;
-            const int ax = cx0 + xx, ay = cy0 + yy;
-            const bool in = a >= 0 && a < mzc && ax >= 0 && ax < mxc && ay >= 0 && ay < myc;
-            cs[a & (NCS - 1)][yy][xx] = ld_masked(ec, ((size_t)a * myc + ay) * mxc + ax, in);
+    // column of slot k: region row r, column c; grid point (gx, gy).  Byte
+    // offsets inside a plane for the buffer loads (BUF_OOB outside the grid,
+    // or, for b and q, outside the stage-1 region).
+    int ofs[NS];            // gy * mx + gx (valid where `ing` holds)
+    unsigned offu[NS], offbq[NS];
+    unsigned ing = 0, st1 = 0, st2 = 0;   // per slot: in the grid (x, y), stage-1 region, output
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        const int r = t / W, c = t - r * W;
+        const int gx = x0 - 2 + c, gy = y0 - 2 + r;
+        const bool v = t < NP;
+        const bool in = v && gx >= 0 && gx < mx && gy >= 0 && gy < my;
+        const bool s1 = v && r >= 1 && r < H - 1 && c >= 1 && c < W - 1;
+        ofs[k] = in ? gy * mx + gx : 0;
+        offu[k] = in ? (unsigned)ofs[k] * (unsigned)sizeof(cx<T>) : BUF_OOB;
+        offbq[k] = (in && s1) ? offu[k] : BUF_OOB;
+        ing |= (unsigned)in << k;
+        st1 |= (unsigned)s1 << k;
+        st2 |= (unsigned)(in && r >= 2 && r < H - 2 && c >= 2 && c < W - 2) << k;
+    }
+    auto slot_in = [&](unsigned m, int k) { return ((m >> k) & 1u) != 0u; };
+    const unsigned pbytes = (unsigned)(plane * sizeof(cx<T>));
+
+    // coarse planes: values of plane a into registers (one plane ahead), then LDS
+    cx<T> creg[NCL];
+    unsigned offc[NCL];
+#pragma unroll
+    for (int i = 0; i < NCL; ++i) {
+        const int t = threadIdx.x + 256 * i;
+        const int yy = t / CW, xx = t - yy * CW;
+        const int ax = cx0 + xx, ay = cy0 + yy;
+        const bool in = t < CH * CW && ax >= 0 && ax < mxc && ay >= 0 && ay < myc;
+        offc[i] = in ? (unsigned)(ay * mxc + ax) * (unsigned)sizeof(cx<T>) : BUF_OOB;
+    }
+    auto fetch_coarse = [&](int a) {
+        const bool ain = a >= 0 && a < mzc;
+        const size_t cpl = (size_t)mxc * myc;
+        const auto rc = buf_rsrc(ec + (ain ? (size_t)a * cpl : 0), ain ? (unsigned)(cpl * sizeof(cx<T>)) : 0u);
+#pragma unroll
+        for (int i = 0; i < NCL; ++i) creg[i] = ld_buf<T>(rc, offc[i]);
+    };
+    auto store_coarse = [&](int a) {
+        cx<T> *dst = &cs[a & (NCS - 1)][0][0];
+#pragma unroll
+        for (int i = 0; i < NCL; ++i) {
+            const int t = threadIdx.x + 256 * i;
+            if (t < CH * CW) dst[t] = creg[i];
         }
     };
     auto interp = [&](int x, int y, int z) -> cx<T> {
@@ -441,78 +588,117 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
                     acc = acc + ((wx[ix] * wy[jy]) * wz[k]) * cs[(az + k) & (NCS - 1)][ey + jy][ex + ix];
         return acc;
     };
-    // column of slot k: region row r, column c; grid point (gx, gy)
-    auto col = [&](int k, int &r, int &c, int &gx, int &gy) {
-        const int t = threadIdx.x + 256 * k;
-        r = t / W;
-        c = t - r * W;
-        gx = x0 - 2 + c;
-        gy = y0 - 2 + r;
+    // global loads of one plane: u (stage 0) and b, q (stage 1)
+    cx<T> pu[NS], pb[NS], pq[NS];
+    auto fetch_u = [&](int z) {
+        const bool zin = z >= 0 && z < mz;
+        const auto ru = buf_rsrc(u + (zin ? (size_t)z * plane : 0), zin ? pbytes : 0u);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) pu[k] = ld_buf<T>(ru, offu[k]);
+    };
+    auto fetch_bq = [&](int z) {
+        const bool zin = z >= 0 && z < mz;
+        const size_t o = zin ? (size_t)z * plane : 0;
+        const auto rb = buf_rsrc(b + o, zin ? pbytes : 0u), rq = buf_rsrc(q + o, zin ? pbytes : 0u);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            pb[k] = ld_buf<T>(rb, offbq[k]);
+            pq[k] = ld_buf<T>(rq, offbq[k]);
+        }
     };
 
-    int a_hi = 0;
+    // prologue: coarse planes of the first two stage-0 planes in LDS, the
+    // next one in registers; u of plane z0 - 2 and b, q of plane z0 - 1
+    int a_reg = 0;
+    bool c_pending = false;
     if (PROL) {
-        const int A0 = (z0 - 1) >> 1;   // coarse planes of the first stage-0 plane z0 - 2
-        load_coarse(A0 - 1);
-        load_coarse(A0);
-        a_hi = A0;
-        __syncthreads();
+        const int Alo = ((z0 - 1) >> 1) - 1;
+        for (int a = Alo; a <= (z0 >> 1); ++a) {
+            fetch_coarse(a);
+            store_coarse(a);
+        }
+        a_reg = z0 >> 1;
+        lds_barrier();
     }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) pu[k] = pb[k] = pq[k] = zero;
+    if (!ZERO) fetch_u(z0 - 2);
+
     cx<T> a0[NS], a1[NS], a2[NS];   // stage 0 at planes z - 2, z - 1, z
     cx<T> c0[NS], c1[NS], c2[NS];   // stage 1 at planes z - 3, z - 2, z - 1
-    cx<T> bA[NS], wA[NS];           // b, omega / D at plane z - 1
-    cx<T> bB[NS], wB[NS];           // the same at plane z - 2
+    cx<T> bB[NS], wB[NS];           // b, omega / D at plane z - 2 (kept from stage 1)
+    cx<T> wn[NS];                   // omega / D at plane z - 1
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         a0[k] = a1[k] = a2[k] = zero;
         c0[k] = c1[k] = c2[k] = zero;
-        bA[k] = wA[k] = bB[k] = wB[k] = zero;
+        bB[k] = wB[k] = wn[k] = zero;
     }
     for (int z = z0 - 2; z <= z1 + 1; ++z) {
-        // the coarse plane the next stage-0 plane needs (read after the barrier)
-        if (PROL && ((z + 2) >> 1) > a_hi) load_coarse(++a_hi);
-        // stage 0: the input at plane z
-        cx<T> *l0w = L0[z & 1];
+        // this plane's loads (issued last iteration), then the next plane's
+        cx<T> un[NS], bn[NS], qn[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            int r, c, gx, gy;
-            col(k, r, c, gx, gy);
-            const int t = threadIdx.x + 256 * k;
-            const bool in = t < NP && gx >= 0 && gx < mx && gy >= 0 && gy < my && z >= 0 && z < mz;
-            cx<T> v = ld_masked(u, (size_t)z * plane + (size_t)gy * mx + gx, in);
-            if (PROL && in) v = v + interp(gx, gy, z);
-            a0[k] = a1[k];
-            a1[k] = a2[k];
-            a2[k] = v;
-            if (t < NP) l0w[t] = v;
+            un[k] = pu[k];
+            bn[k] = pb[k];
+            qn[k] = pq[k];
+        }
+        if (PROL) {
+            if (c_pending) {   // fetched last iteration; read from the next iteration on
+                store_coarse(a_reg);
+                c_pending = false;
+            }
+            if (((z + 3) >> 1) > a_reg) {
+                fetch_coarse(++a_reg);
+                c_pending = true;
+            }
+        }
+        if (!ZERO && z + 1 <= z1 + 1) fetch_u(z + 1);
+        if (z >= z0 - 1 && z <= z1) fetch_bq(z);
+
+        // stage 0: the input at plane z
+        if (!ZERO) {
+            cx<T> *l0w = L0[z & 1];
+            const bool zin = z >= 0 && z < mz;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int t = threadIdx.x + 256 * k;
+                cx<T> v = un[k];
+                if (PROL && zin && slot_in(ing, k)) {
+                    const int r = t / W, c = t - r * W;
+                    v = v + interp(x0 - 2 + c, y0 - 2 + r, z);
+                }
+                a0[k] = a1[k];
+                a1[k] = a2[k];
+                a2[k] = v;
+                if (t < NP) l0w[t] = v;
+            }
         }
         // stage 1: the first sweep at plane p1 = z - 1
         const int p1 = z - 1;
         if (p1 >= z0 - 1) {
-            const cx<T> *l0r = L0[p1 & 1];
+            const cx<T> *l0r = L0[ZERO ? 0 : (p1 & 1)];
             cx<T> *l1w = L1[p1 & 1];
+            const bool pin = p1 >= 0 && p1 < mz;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                int r, c, gx, gy;
-                col(k, r, c, gx, gy);
                 const int t = threadIdx.x + 256 * k;
-                const bool s1 = t < NP && r >= 1 && r < H - 1 && c >= 1 && c < W - 1;
-                bB[k] = bA[k];
-                wB[k] = wA[k];
                 c0[k] = c1[k];
                 c1[k] = c2[k];
-                cx<T> v = zero;
-                if (s1 && gx >= 0 && gx < mx && gy >= 0 && gy < my && p1 >= 0 && p1 < mz) {
-                    const size_t j = (size_t)p1 * plane + (size_t)gy * mx + gx;
-                    const cx<T> bj = b[j], wj = jweight(P, q[j]);
-                    bA[k] = bj;
-                    wA[k] = wj;
-                    cx<T> N = nsum_xy(P, l0r[t - 1], l0r[t + 1], l0r[t - W], l0r[t + W]);
-                    N = nsum_add_z(P, N, a0[k], a2[k]);
-                    v = jacobi_n(P, N, a1[k], bj, wj);
+                cx<T> v = zero, wj = zero;
+                if (pin && slot_in(ing & st1, k)) {
+                    wj = jweight(P, qn[k]);
+                    if (ZERO) {
+                        v = jacobi0_w(bn[k], wj);
+                    } else {
+                        cx<T> N = nsum_xy(P, l0r[t - 1], l0r[t + 1], l0r[t - W], l0r[t + W]);
+                        N = nsum_add_z(P, N, a0[k], a2[k]);
+                        v = jacobi_n(P, N, a1[k], bn[k], wj);
+                    }
                 }
+                wn[k] = wj;
                 c2[k] = v;
-                if (s1) l1w[t] = v;
+                if (slot_in(st1, k)) l1w[t] = v;
             }
         }
         // stage 2: the second sweep at plane p2 = z - 2, the block's output
@@ -521,18 +707,23 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
             const cx<T> *l1r = L1[p2 & 1];
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                int r, c, gx, gy;
-                col(k, r, c, gx, gy);
                 const int t = threadIdx.x + 256 * k;
-                const bool s2 = t < NP && r >= 2 && r < H - 2 && c >= 2 && c < W - 2 && gx < mx && gy < my;
-                if (s2) {
+                if (slot_in(st2, k)) {
                     cx<T> N = nsum_xy(P, l1r[t - 1], l1r[t + 1], l1r[t - W], l1r[t + W]);
                     N = nsum_add_z(P, N, c0[k], c2[k]);
-                    out[(size_t)p2 * plane + (size_t)gy * mx + gx] = jacobi_n(P, N, c1[k], bB[k], wB[k]);
+                    out[(size_t)p2 * plane + ofs[k]] = jacobi_n(P, N, c1[k], bB[k], wB[k]);
                 }
             }
         }
-        __syncthreads();
+        // b, omega / D of plane z - 1 serve stage 2 next iteration
+        if (p1 >= z0 - 1) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                bB[k] = bn[k];
+                wB[k] = wn[k];
+            }
+        }
+        lds_barrier();
     }
 }
 
@@ -646,13 +837,21 @@ template <typename T> constexpr int sweep2_rows() { return sizeof(T) == 4 ? 8 : 
 
 template <typename T>
 void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
-                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop)
+                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero)
 {
     constexpr int TY = sweep2_rows<T>();
     const int tx = (g.m[0] + 63) / 64, ty = (g.m[1] + TY - 1) / TY;
     const int tz = planes_per_block((long)tx * ty, g.m[2], TZ3);
     const int nb = tx * ty * ((g.m[2] + tz - 1) / tz);
-    if (ec) {
+    if (zero) {
+        // u is not read: any valid pointer serves the unused loads' base
+        if (finest)
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 1>), dim3(nb), dim3(256), 0, s, b, ec, b, q, out, P,
+                               tx, ty, tz, stop);
+        else
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 0>), dim3(nb), dim3(256), 0, s, b, ec, b, q, out, P,
+                               tx, ty, tz, stop);
+    } else if (ec) {
         if (finest)
             hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
                                ty, tz, stop);
@@ -669,9 +868,9 @@ void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, c
     }
 }
 template void launch_sweep2_3d<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *, const cd *,
-                                       const cd *, cd *, hipStream_t, bool, const int *);
+                                       const cd *, cd *, hipStream_t, bool, const int *, bool);
 template void launch_sweep2_3d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *, const cf *,
-                                      const cf *, cf *, hipStream_t, bool, const int *);
+                                      const cf *, cf *, hipStream_t, bool, const int *, bool);
 
 void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
@@ -798,18 +997,34 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restric
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
 
     // Loads run one plane ahead through registers: while residual plane fz is
-    // formed, u of plane fz + 2 and b, q of plane fz + 1 are in flight.
+    // formed, u of plane fz + 2 and b, q of plane fz + 1 are in flight (buffer
+    // loads, zero outside the grid; the barriers fence LDS only, so the loads
+    // stay in flight across them).
     constexpr int NUL = (RUH * RUW + 255) / 256, NRL = (RFH * RFW + 255) / 256;
     cx<T> un[NUL], bn[NRL], qn[NRL];
-    auto issue_u = [&](int fz) {
+    unsigned offu[NUL], offr[NRL];
+    const unsigned pbytes = (unsigned)(plane * sizeof(cx<T>));
 #pragma unroll
-        for (int k = 0; k < NUL; ++k) {
-            const int t = threadIdx.x + 256 * k;
-            const int yy = t / RUW, xx = t - yy * RUW;
-            const int gx = fx0 - 1 + xx, gy = fy0 - 1 + yy;
-            const bool in = t < RUH * RUW && gx >= 0 && gx < mx && gy >= 0 && gy < my && fz >= 0 && fz < mz;
-            un[k] = ld_masked(u, (size_t)fz * plane + (size_t)gy * mx + gx, in);
-        }
+    for (int k = 0; k < NUL; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        const int yy = t / RUW, xx = t - yy * RUW;
+        const int gx = fx0 - 1 + xx, gy = fy0 - 1 + yy;
+        const bool in = t < RUH * RUW && gx >= 0 && gx < mx && gy >= 0 && gy < my;
+        offu[k] = in ? (unsigned)(gy * mx + gx) * (unsigned)sizeof(cx<T>) : BUF_OOB;
+    }
+#pragma unroll
+    for (int k = 0; k < NRL; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        const int yy = t / RFW, xx = t - yy * RFW;
+        const int gx = fx0 + xx, gy = fy0 + yy;
+        const bool in = t < RFH * RFW && gx < mx && gy < my;
+        offr[k] = in ? (unsigned)(gy * mx + gx) * (unsigned)sizeof(cx<T>) : BUF_OOB;
+    }
+    auto issue_u = [&](int fz) {
+        const bool zin = fz >= 0 && fz < mz;
+        const auto ru = buf_rsrc(u + (zin ? (size_t)fz * plane : 0), zin ? pbytes : 0u);
+#pragma unroll
+        for (int k = 0; k < NUL; ++k) un[k] = ld_buf<T>(ru, offu[k]);
     };
     auto store_u = [&](int fz) {
         cx<T> *dst = &us[(fz + 3) % 3][0][0];
@@ -820,15 +1035,13 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restric
         }
     };
     auto issue_bq = [&](int fz) {
+        const bool zin = fz >= 0 && fz < mz;
+        const size_t o = zin ? (size_t)fz * plane : 0;
+        const auto rb = buf_rsrc(b + o, zin ? pbytes : 0u), rq = buf_rsrc(q + o, zin ? pbytes : 0u);
 #pragma unroll
         for (int k = 0; k < NRL; ++k) {
-            const int t = threadIdx.x + 256 * k;
-            const int yy = t / RFW, xx = t - yy * RFW;
-            const int gx = fx0 + xx, gy = fy0 + yy;
-            const bool in = t < RFH * RFW && gx < mx && gy < my && fz < mz;
-            const size_t j = (size_t)fz * plane + (size_t)gy * mx + gx;
-            bn[k] = ld_masked(b, j, in);
-            qn[k] = ld_masked(q, j, in);
+            bn[k] = ld_buf<T>(rb, offr[k]);
+            qn[k] = ld_buf<T>(rq, offr[k]);
         }
     };
     const int fz_first = 2 * K0, fz_last = 2 * K1;        // fine residual planes of the block
@@ -846,7 +1059,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restric
             bc_[k] = bn[k];
             qc_[k] = qn[k];
         }
-        __syncthreads();
+        lds_barrier();
         if (fz < fz_last) {
             issue_u(fz + 2);
             issue_bq(fz + 1);
@@ -873,7 +1086,7 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restric
                 rd[t] = r;
             }
         }
-        __syncthreads();
+        lds_barrier();
         // coarse plane K = (fz - 2) / 2 once fine planes 2K .. 2K + 2 are done
         if (fz >= fz_first + 2 && ((fz - fz_first) & 1) == 0) {
             const int K = (fz - 2) / 2;
