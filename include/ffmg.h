@@ -148,6 +148,15 @@ ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle *
  * overflow double. */
 ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b);
 
+/* b_j = q_j exp(i k0 cos(gamma) eta.x_j): the incoming wave's phase along
+ * eta on the real coordinates, without the factor exp(-k0 sin(gamma) eta.x)
+ * that the contour adds to it.  It oscillates like the right-hand side of
+ * eq. helmholtz_cc and stays bounded where that one leaves the double range
+ * (k0 h = 1/2 on the large boxes), so it serves to time and check solves at
+ * such wavenumbers; far fields need the true plane wave (mg_rhs_plane_wave).
+ * eta: HOST double[3]; b: DEVICE complex128[N], written. */
+ffmg_status mg_rhs_phase(ffmg_handle *h, const double eta[3], void *b);
+
 /* One V(nu1, nu2) cycle in place (Sec. 4): omega-Jacobi smoothing,
  * full-weighting restriction of the residual, recursive coarse correction,
  * bilinear/trilinear interpolation, exact coarsest solve.  b: DEVICE
@@ -314,6 +323,9 @@ void ml_net_destroy(ffmg_net *net);
 /* Au = A u (the operator of eq. csg), DEVICE complex128[N] each. */
 ffmg_status mg_apply(ffmg_handle *h, const void *u, void *Au);
 
+/* r = b - A u in FP64, DEVICE complex128[N] each (r must not alias b or u). */
+ffmg_status mg_residual(ffmg_handle *h, const void *b, const void *u, void *r);
+
 /* One smoothing step on the finest level, FP64, out of place: an
  * omega-Jacobi sweep u_out = u + omega D^{-1} (b - A u) (smoothers Jacobi and
  * learned), a red-black Gauss-Seidel sweep (FFMG_SMOOTH_RBGS) or a GMRES(m)
@@ -350,11 +362,15 @@ ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, doubl
  * 1 far-field map (integrand, contraction, final sum), 2 finest-level
  * interpolation + post-smoothing, 3 FP64 update + residual of the
  * mixed-precision refinement, 4 the far-field GEMM stages alone, 5 the
- * learned smoother's network on the finest level.  mask = 0
- * disables.  mg_profile_read synchronises, returns the summed duration (ms)
- * and launch count of one kernel, and clears its record. */
+ * learned smoother's network on the finest level, 6 the finest-level
+ * residual + restriction (3D).  mask = 0 disables.  mg_profile_read
+ * synchronises, returns the summed duration (ms) and launch count of one
+ * kernel, and clears its record.  mg_profile_durations does the same but
+ * writes each launch's duration (ms, in launch order) into ms[0 .. cap - 1]
+ * (HOST) and the number of launches into *count (which may exceed cap). */
 ffmg_status mg_profile_enable(ffmg_handle *h, int mask);
 ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_t *count);
+ffmg_status mg_profile_durations(ffmg_handle *h, int kernel, double *ms, int64_t cap, int64_t *count);
 
 /* Autotuning of kernel tile shapes.  A tunable is a family of kernel
  * variants that compute the same result (bit for bit) with different tile

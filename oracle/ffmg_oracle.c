@@ -38,6 +38,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double _Complex cplx;
 
@@ -665,6 +668,30 @@ void or_rhs_plane_wave(int dim, const long *m, const double *lo, const double *h
             }
 }
 
+/* b_j = q_j exp(i k0 cos(gamma) eta.x_j): the phase of the incoming wave
+ * along the real coordinates without the contour's growth factor
+ * exp(-k0 sin(gamma) eta.x) -- a bounded right-hand side with the
+ * oscillation of eq. helmholtz_cc, for solves at wavenumbers where the
+ * contour plane wave exceeds the double range. */
+void or_rhs_phase(int dim, const long *m, const double *lo, const double *h,
+                  double gamma, double k0, const cplx *q,
+                  const double *eta, cplx *b)
+{
+    long e[3];
+    extents(dim, m, e);
+    const double kc = k0 * cos(gamma);
+    #pragma omp parallel for schedule(static)
+    for (long iz = 0; iz < e[2]; ++iz)
+        for (long iy = 0; iy < e[1]; ++iy)
+            for (long ix = 0; ix < e[0]; ++ix) {
+                long j = ix + e[0] * (iy + e[1] * iz);
+                double ex = eta[0] * coord(lo, h, 0, ix);
+                if (dim >= 2) ex += eta[1] * coord(lo, h, 1, iy);
+                if (dim >= 3) ex += eta[2] * coord(lo, h, 2, iz);
+                b[j] = q[j] * cexp(I * kc * ex);
+            }
+}
+
 /* Far-field integrand s_j = q_j (u_in(z_j) + u_j): the source and the
  * scattered wave together, g = k0^2 chi (u_in + u) of eq. FFmap, i.e. the
  * integrands of eq. i1 and eq. i2 summed. */
@@ -750,4 +777,14 @@ void or_ff_separable(int dim, const long *m, const double *lo, const double *h,
         F[d] = pre * accz;
         for (int k = 0; k < 3; ++k) free(P[k]);
     }
+}
+
+/* Threads the OpenMP loops of this build run on (1 without OpenMP). */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -26,25 +26,45 @@ OK = 0
 ENOCONV = 4
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle shared library (portable -O2, OpenMP, IEEE math)."""
-    if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
-               "-o", _LIB + ".tmp", _SRC, "-lm"]
+def build(force: bool = True, native: bool = False, path: str = None) -> str:
+    """Compile the oracle shared library: -O3, OpenMP, IEEE arithmetic with
+    no contraction into fused multiply-adds.  The library that the tests load
+    is portable; native=True builds one for the host's own instruction set
+    (-march=native) at `path`, for timing the oracle on the machine it runs
+    on (a native build is not carried to another machine)."""
+    out = path or _LIB
+    if force or not os.path.exists(out):
+        cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off"]
+        if native:
+            cmd.append("-march=native")
+        cmd += ["-o", out + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(_LIB + ".tmp", _LIB)
-    return _LIB
+        os.replace(out + ".tmp", out)
+    return out
 
 
 _lib = None
+_lib_path = None
+
+
+def load(path: str):
+    """Use the oracle library at `path` (e.g. a native build) from now on."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
+
+
+def num_threads() -> int:
+    """Threads of the oracle's OpenMP loops."""
+    return int(lib().or_num_threads())
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = ctypes.CDLL(_LIB)
+        p = _lib_path or _LIB
+        if not os.path.exists(p):
+            build(path=p)
+        L = ctypes.CDLL(p)
         vp, ip, lp, dp = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_double
         L.or_mg_create.restype = vp
         L.or_mg_create.argtypes = [ip, vp, vp, vp, dp, vp, ip, ip, dp, lp]
@@ -72,9 +92,11 @@ def lib():
         L.or_lu_factor.restype = ip
         L.or_lu_solve.argtypes = [lp, vp, vp, vp]
         L.or_rhs_plane_wave.argtypes = [ip, vp, vp, vp, dp, dp, vp, vp, vp]
+        L.or_rhs_phase.argtypes = [ip, vp, vp, vp, dp, dp, vp, vp, vp]
         L.or_ff_integrand.argtypes = [ip, vp, vp, vp, dp, dp, vp, vp, vp, vp]
         L.or_ff_dense.argtypes = [ip, vp, vp, vp, dp, dp, vp, lp, vp, vp, vp]
         L.or_ff_separable.argtypes = [ip, vp, vp, vp, dp, dp, vp, lp, vp, vp]
+        L.or_num_threads.restype = ip
         _lib = L
     return _lib
 
@@ -306,6 +328,18 @@ def rhs_plane_wave(g: Grid, gamma, k0, q, eta):
     b = np.empty(g.N, dtype=np.complex128)
     lib().or_rhs_plane_wave(g.dim, m3.ctypes.data, lo3.ctypes.data, h3.ctypes.data,
                             float(gamma), float(k0), kp, e3.ctypes.data, b.ctypes.data)
+    return b.reshape(g.shape)
+
+
+def rhs_phase(g: Grid, gamma, k0, q, eta):
+    """b_j = q_j exp(i k0 cos(gamma) eta.x_j): the bounded stress
+    right-hand side (the incoming phase without the contour's growth)."""
+    m3, h3, lo3 = _m3(g.m), _d3(g.h, 1.0), _d3(g.lo)
+    kap, kp = _c(q.ravel(), np.complex128)
+    e3 = _d3(eta)
+    b = np.empty(g.N, dtype=np.complex128)
+    lib().or_rhs_phase(g.dim, m3.ctypes.data, lo3.ctypes.data, h3.ctypes.data,
+                       float(gamma), float(k0), kp, e3.ctypes.data, b.ctypes.data)
     return b.reshape(g.shape)
 
 

@@ -747,7 +747,9 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
         } else if (zero_guess) {
             launch_zero<T>(u, lv.g.N(), h->stream, stop);
         }
+        const int pr = (l == 0) ? prof_begin(h, PROF_RR) : -1;
         launch_resid_restrict3d<T>(lv.g, LP::P(lv), cur, b, LP::q(lv), LP::b(lc), h->stream, stop);
+        prof_end(h, PROF_RR, pr);
         vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
         if (nu2 > 0) {
             smooth_chain3d<T>(h, lv, b, cur, u, scratch, nu2, false, LP::u(lc), PROF_POST, stop);
@@ -954,6 +956,24 @@ ffmg_status mg_profile_read(ffmg_handle *h, int kernel, double *total_ms, int64_
     return FFMG_OK;
 }
 
+ffmg_status mg_profile_durations(ffmg_handle *h, int kernel, double *ms, int64_t cap, int64_t *count)
+{
+    if (!h || kernel < 0 || kernel >= PROF_N || !count || cap < 0 || (cap > 0 && !ms))
+        return fail(h, FFMG_EINVAL, "bad argument");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    int64_t n = 0;
+    for (auto &e : h->ev[kernel]) {
+        float t = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&t, e.first, e.second));
+        if (n < cap) ms[n] = t;
+        ++n;
+        h->ev_free.push_back(e);
+    }
+    *count = n;
+    h->ev[kernel].clear();
+    return FFMG_OK;
+}
+
 void mg_destroy(ffmg_handle *h)
 {
     if (!h) return;
@@ -992,6 +1012,28 @@ ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b)
     for (int k = 0; k < h->prob.dim; ++k) e[k] = eta[k];
     if (exponent_budget(h) > 700.0) return fail(h, FFMG_ERANGE, "exp(i k0 eta.z) overflows double on this box");
     launch_rhs_plane_wave(h->L[0].g, h->prob.gamma, h->k0, e, h->L[0].q, (cd *)b, h->stream);
+    HIPCHK(h, hipGetLastError());
+    return FFMG_OK;
+}
+
+ffmg_status mg_rhs_phase(ffmg_handle *h, const double eta[3], void *b)
+{
+    NOT_PENDING(h);
+    if (!h || !eta || !b) return fail(h, FFMG_EINVAL, "null argument");
+    double e[3] = {0, 0, 0};
+    for (int k = 0; k < h->prob.dim; ++k) e[k] = eta[k];
+    launch_rhs_phase(h->L[0].g, h->prob.gamma, h->k0, e, h->L[0].q, (cd *)b, h->stream);
+    HIPCHK(h, hipGetLastError());
+    return FFMG_OK;
+}
+
+ffmg_status mg_residual(ffmg_handle *h, const void *b, const void *u, void *r)
+{
+    NOT_PENDING(h);
+    if (!h || !b || !u || !r || r == u || r == b) return fail(h, FFMG_EINVAL, "null or aliased argument");
+    Level &l0 = h->L[0];
+    launch_stencil<double>(MODE_RESID, l0.g, l0.P64, (const cd *)u, (const cd *)b, l0.q, (cd *)r, nullptr, h->stream,
+                           false, nullptr);
     HIPCHK(h, hipGetLastError());
     return FFMG_OK;
 }

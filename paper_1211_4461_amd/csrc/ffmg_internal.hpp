@@ -28,7 +28,8 @@ enum ProfKernel {
     PROF_REFINE = 3,   // FP64 update + residual of the refinement loop (fused)
     PROF_FFGEMM = 4,   // far-field GEMM stages alone
     PROF_NET = 5,      // learned-smoother network application (finest level)
-    PROF_N = 6
+    PROF_RR = 6,       // finest-level residual + full-weighting restriction (3D)
+    PROF_N = 7
 };
 
 // Device-resident state of one solve (residual-reduction stopping test of
@@ -167,6 +168,8 @@ template <typename T>
 void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s, const int *stop = nullptr);
 void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
                            hipStream_t s);
+void launch_rhs_phase(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
+                      hipStream_t s);
 
 // Mixed-precision refinement (one-operation form): u64 += s * d32 with
 // s = ctl->scale_cur; r64 = b - A u64 written as r64 / ctl->scale_next.

@@ -1583,6 +1583,19 @@ void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const do
                        g.lo[1], g.lo[2], g.h[0], g.h[1], g.h[2], eta[0], eta[1], eta[2], ar_s, ai_s);
 }
 
+// b = q exp(i k0 cos(gamma) eta.x): the plane wave's phase along the real
+// coordinates without the contour's growth factor (the stress right-hand side
+// at k0 h = 1/2, where exp(i k0 eta.z) leaves the floating-point range).
+void launch_rhs_phase(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
+                      hipStream_t s)
+{
+    size_t N = g.N();
+    size_t nb = (N + 255) / 256;
+    if (nb > 65536) nb = 65536;
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)nb), dim3(256), 0, s, q, b, g.m[0], g.m[1], g.m[2], g.dim, g.lo[0],
+                       g.lo[1], g.lo[2], g.h[0], g.h[1], g.h[2], eta[0], eta[1], eta[2], 0.0, k0 * cos(gamma));
+}
+
 // ---------------------------------------------------------------------------
 // Mixed-precision refinement kernels (one-operation form).  The FP64 update
 // u += s d uses s = ctl->scale_cur, the scale of the FP32 right-hand side the

@@ -66,7 +66,8 @@ EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup
            "mg_tune_variants", "mg_tune_get", "mg_tune_set", "mg_tune_farfield", "mg_tune_solve", "mg_solve_batched",
            "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights", "ml_loss_grad",
            "ml_train_step", "ml_net_last_error", "ml_net_destroy", "mg_learned_smooth", "mg_jacobi_factor",
-           "mg_gmres_smooth", "mg_solve_begin", "mg_solve_end", "farfield_map_noalloc"]
+           "mg_gmres_smooth", "mg_solve_begin", "mg_solve_end", "farfield_map_noalloc", "mg_rhs_phase",
+           "mg_residual", "mg_profile_durations"]
 
 
 def lib():
@@ -85,6 +86,8 @@ def lib():
     L.ffmg_last_error.argtypes = [vp]
     L.mg_setup.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.POINTER(vp)]
     L.mg_rhs_plane_wave.argtypes = [vp, vp, vp]
+    L.mg_rhs_phase.argtypes = [vp, vp, vp]
+    L.mg_residual.argtypes = [vp, vp, vp, vp]
     L.mg_vcycle.argtypes = [vp, vp, vp]
     L.mg_fmg.argtypes = [vp, vp, vp, ip]
     L.mg_solve.argtypes = [vp, vp, vp, dp, ctypes.POINTER(SolveInfo)]
@@ -102,6 +105,7 @@ def lib():
     L.mg_destroy.restype = None
     L.mg_profile_enable.argtypes = [vp, ip]
     L.mg_profile_read.argtypes = [vp, ip, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64)]
+    L.mg_profile_durations.argtypes = [vp, ip, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.mg_tune_variants.argtypes = [vp, ip]
     L.mg_tune_get.argtypes = [vp, ip, ctypes.POINTER(ip)]
     L.mg_tune_set.argtypes = [vp, ip, ip]
@@ -244,6 +248,18 @@ def _eta3(eta):
 def mg_rhs_plane_wave(h: Handle, eta, b):
     h._check(lib().mg_rhs_plane_wave(h.ptr, _eta3(eta), _dev_ptr(b, "b")), "mg_rhs_plane_wave")
     return b
+
+
+def mg_rhs_phase(h: Handle, eta, b):
+    """b = q exp(i k0 cos(gamma) eta.x) (the bounded stress right-hand side)."""
+    h._check(lib().mg_rhs_phase(h.ptr, _eta3(eta), _dev_ptr(b, "b")), "mg_rhs_phase")
+    return b
+
+
+def mg_residual(h: Handle, b, u, r):
+    """r = b - A u (FP64)."""
+    h._check(lib().mg_residual(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), _dev_ptr(r, "r")), "mg_residual")
+    return r
 
 
 def mg_vcycle(h: Handle, b, u):
@@ -449,10 +465,20 @@ def mg_destroy(h: Handle):
 KERNEL_SWEEP, KERNEL_FARFIELD = 0, 1
 
 
-PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE, PROF_FFGEMM, PROF_NET = 0, 1, 2, 3, 4, 5
+PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE, PROF_FFGEMM, PROF_NET, PROF_RR = 0, 1, 2, 3, 4, 5, 6
 
 
-def mg_profile_enable(h: Handle, mask=0x3F):
+def mg_profile_durations(h: Handle, kernel, cap=1 << 16):
+    """Per-launch durations (ms, numpy array) recorded for kernel PROF_*
+    since the last read."""
+    buf = np.empty(cap, dtype=np.float64)
+    n = ctypes.c_int64()
+    h._check(lib().mg_profile_durations(h.ptr, int(kernel), ctypes.c_void_p(buf.ctypes.data), int(cap),
+                                        ctypes.byref(n)), "mg_profile_durations")
+    return buf[: min(n.value, cap)].copy()
+
+
+def mg_profile_enable(h: Handle, mask=0x7F):
     """Time kernel k when bit k of mask is set (0 disables)."""
     h._check(lib().mg_profile_enable(h.ptr, int(mask)), "mg_profile_enable")
 

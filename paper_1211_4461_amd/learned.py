@@ -53,15 +53,20 @@ def jacobi_init(seed: int, gamma: float = math.pi / 6, omega: float = 0.8, noise
     return [W1, W2, W3]
 
 
-def phase_rhs(w, torch, device="cuda"):
-    """b = q exp(i k0 cos(gamma) eta.x): the plane wave's phase without the
-    contour's exponential growth, for k0 h near 0.5 where the contour wave
-    itself would exceed the floating-point range."""
-    X = W.mesh([w.n] * w.dim, [w.lo] * w.dim, [w.hi] * w.dim)
-    t = sum(w.eta[k] * X[k] for k in range(w.dim))
-    q = w.coef
-    b = q * np.exp(1j * w.k0 * math.cos(w.gamma) * t)
-    return torch.from_numpy(np.ascontiguousarray(b)).to(device)
+def phase_rhs(w, torch, device="cuda", h=None):
+    """b = q exp(i k0 cos(gamma) eta.x) from the library (mg_rhs_phase): the
+    plane wave's phase without the contour's exponential growth, for k0 h
+    near 0.5 where the contour wave itself would exceed the floating-point
+    range.  h: a handle of the workload (one is set up if None)."""
+    own = h is None
+    if own:
+        h = ffmg.setup_workload(w, device=device, options=ffmg.default_options())[0]
+    b = torch.empty((w.n - 1,) * w.dim, dtype=torch.complex128, device=device)
+    ffmg.mg_rhs_phase(h, w.eta, b)
+    if own:
+        torch.cuda.synchronize()
+        h.destroy()
+    return b
 
 
 @dataclass
@@ -112,7 +117,7 @@ def make_patches(torch, n_fields=48, n=256, kh=(0.02, 0.6), iterates=3, patches_
         hs = [ffmg.setup_workload(w, device=device, options=ffmg.default_options())[0],
               ffmg.setup_workload(w, device=device, options=ffmg.default_options(nu2=0))[0]]
         hh = (w.hi - w.lo) / w.n
-        b = phase_rhs(w, torch, device)
+        b = phase_rhs(w, torch, device, h=hs[0])
         kap = torch.from_numpy(np.ascontiguousarray((w.k0 ** 2 + w.coef) * hh * hh)).to(device)
         Au = torch.empty_like(b)
         if khf <= iterate_kh_max:
@@ -122,8 +127,7 @@ def make_patches(torch, n_fields=48, n=256, kh=(0.02, 0.6), iterates=3, patches_
             u = torch.zeros_like(b)
             for k in range(iterates):
                 ffmg.mg_vcycle(h, b, u)
-                ffmg.mg_apply(h, u, Au)
-                r = b - Au
+                r = ffmg.mg_residual(h, b, u, Au)
                 e = ustar - u
                 s = float(torch.sqrt(torch.mean(torch.abs(r) ** 2)))
                 if s > 0:

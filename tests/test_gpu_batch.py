@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from paper_1211_4461_amd import workloads as W
+from tests.compare import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -27,8 +28,6 @@ def ff():
     return ffmg
 
 
-def rel(a, b):
-    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(np.asarray(b).ravel())
 
 
 def operators(ff, insts, **opt):

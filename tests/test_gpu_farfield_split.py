@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 from paper_1211_4461_amd import workloads as W
+from tests.compare import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -40,8 +41,6 @@ def host(t):
     return t.cpu().numpy()
 
 
-def rel(a, b):
-    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(np.asarray(b).ravel())
 
 
 def crand(seed, shape):

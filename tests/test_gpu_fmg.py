@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from paper_1211_4461_amd import workloads as W
+from tests.compare import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -36,8 +37,6 @@ def host(t):
     return t.cpu().numpy()
 
 
-def rel(a, b):
-    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300)
 
 
 def nan_like(shape):

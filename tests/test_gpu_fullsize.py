@@ -20,6 +20,7 @@ import numpy as np
 import pytest
 
 from paper_1211_4461_amd import workloads as W
+from tests.compare import rel as relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -35,8 +36,6 @@ def ff():
     return ffmg
 
 
-def relerr(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
 def check_solution(orc, w, b_gpu, u_gpu, info, tol):

@@ -10,6 +10,7 @@ import pytest
 
 from oracle import convnet as cn
 from paper_1211_4461_amd import workloads as W
+from tests.compare import rel as relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -34,8 +35,6 @@ def c64(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).cuda()
 
 
-def relerr(a, b):
-    return np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b))
 
 
 def patches(seed, count):

@@ -536,3 +536,26 @@ def test_schrodinger_rewrite_matches_helmholtz(orc):
     X = W.mesh(g.n, g.lo, g.hi)
     uin = np.exp(1j * math.sqrt(2 * E) * np.exp(1j * G30) * X[0])
     np.testing.assert_allclose(b, -2.0 * V * uin, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_phase_rhs_is_the_real_axis_plane_wave(orc, dim):
+    """The stress right-hand side q exp(i k0 cos(g) eta.x) is the plane-wave
+    right-hand side of the unrotated grid (gamma = 0) at the wavenumber
+    k0 cos(g): its modulus is |q| at every node and it carries no growth."""
+    n = 16 if dim == 2 else 8
+    g = orc.Grid(dim, n, [-3.0] * dim, [2.5] * dim)
+    r = rng(11)
+    q = crand(r, g.shape)
+    eta = np.zeros(dim)
+    eta[0], eta[1] = math.cos(0.4), math.sin(0.4)
+    k0, gam = 3.7, 0.45
+    bp = orc.rhs_phase(g, gam, k0, q, eta)
+    bw = orc.rhs_plane_wave(g, 0.0, k0 * math.cos(gam), q, eta)
+    assert np.abs(bp - bw).max() <= 1e-14 * np.abs(q).max()
+    np.testing.assert_allclose(np.abs(bp), np.abs(q), rtol=1e-14)
+    # and the contour plane wave at the same gamma differs from it exactly by the growth factor
+    bc = orc.rhs_plane_wave(g, gam, k0, q, eta)
+    X = W.mesh(list(g.n), list(g.lo), list(g.hi))
+    t = sum(e * x for e, x in zip(eta, X))
+    np.testing.assert_allclose(np.abs(bc), np.abs(q) * np.exp(-k0 * math.sin(gam) * t), rtol=1e-13)
