@@ -4,7 +4,8 @@
   fused kernels with every tuned tile variant): every variant bit for bit the
   same; the iterate against the oracle's nested iteration and V-cycles of
   the same count (element-wise 1e-12); the map against the oracle's map of
-  its own solution converged to 1e-13 (1e-10, norm- and element-wise).
+  its own solution converged to its FP64 residual floor (2e-12; 1e-10, norm-
+  and element-wise).
 * The stress points the workloads name, k0 h = 1/2: 2048^2 (k0 = 51.2) and
   512^3 (k0 = 21.33), solve only, with the bounded phase right-hand side
   q exp(i k0 cos(gamma) eta.x) (the contour plane wave leaves the double range
@@ -67,12 +68,13 @@ def test_bumps_2048_plain_fp64(ff, orc):
     ug = u.cpu().numpy()
     err_it = rel(ug, uo)
     assert err_it <= 1e-12, err_it
-    # converged parity of the map
-    uc, st, kc, _ = mg.solve(bo, u0=uo, tol=1e-13)
+    # converged parity of the map: the oracle's solution taken to its FP64
+    # residual floor (about 1.4e-12 relative on 2047^2; 1e-13 is out of reach)
+    uc, st, kc, _ = mg.solve(bo, u0=uo, tol=2e-12)
     assert st == 0
     Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uc, w.dirs)
     print(f"2048^2 plain FP64: {info.cycles} cycles from the full multigrid start, iterate vs oracle {err_it:.2e}, "
-          f"map vs oracle at 1e-13: {rel(F, Fo):.2e}")
+          f"map vs oracle at 2e-12: {rel(F, Fo):.2e}")
     assert rel(F, Fo) <= 1e-10
     h.destroy()
 
