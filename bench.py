@@ -1,25 +1,36 @@
 #!/usr/bin/env python3
 """Far-field maps per second on one MI355X.
 
-One step = one far-field map of the 2D bumps workload (2048 intervals per
-axis on [-10,10]^2, 8 seeded Gaussian bumps, k0 = 1, contour angle 30 deg):
-plane-wave right-hand side, multigrid solve to ||r|| <= 1e-10 ||b|| and the
-far field at 360 outgoing angles, with every input already in HBM.  `value`
-is the mixed-precision path (FP32 V(2,2) cycles inside FP64 refinement, far
-field as a split-BF16 MFMA contraction with FP32 accumulation); the plain FP64
-path (FP64 V-cycles, FP64 MFMA far field) is timed beside it on the same map.
-Both solves start from the full multigrid guess (the nested iteration of
-V-cycles, FMG_K per coarse level); the same solves from u = 0 and with other
-cycle counts per level are timed as well (`start_forms`).  Consecutive maps
-cycle through four handles, each on a stream of its own: each map's solve is
-begun (mg_solve_begin) before the map begun three steps earlier is finished
-(mg_solve_end) and its far field queued, so four solves are in flight from
-this one thread; the one-stream and two-lane rates are in `start_forms` too.
+One step = one far-field map of the 3D Gaussian workload (512 intervals per
+axis on [-6,6]^3, 133.4 M unknowns, chi = 0.5 exp(-z.z/2) continued onto the
+contour, k0 = 1, contour angle 30 deg, eta = +x): plane-wave right-hand side,
+multigrid solve to ||r|| <= 1e-10 ||b|| and the far field on a 128 (azimuth)
+x 64 (polar) direction grid, with every input already in HBM.  `value` is the
+mixed-precision path (FP32 V(2,2) cycles inside FP64 refinement, far field as
+a split-BF16 MFMA contraction with FP32 accumulation); the plain FP64 path
+(FP64 V-cycles, FP64 MFMA far field) is timed beside it on the same maps.
+Both start from the full multigrid guess (FMG_K V-cycles per coarse level)
+and keep `--lanes` solves in flight from this one host thread: consecutive
+maps cycle through that many handles, each on its own stream, and each map's
+solve is begun (mg_solve_begin) before the map begun lanes - 1 steps earlier
+is finished (mg_solve_end) and its far field queued.
 
-Also reported: the roofline of the dominant kernel (the timed kernel with the
-largest total time per map), timed live with events stamped on its launches
-in a one-solve-in-flight pass of the same maps, and the FP64 CPU oracle on the
-host cores (one map of the same workload).
+Also reported:
+  * the roofline of the dominant kernel: the finest-level kernels the library
+    brackets with HIP events (interpolation + post-smoothing, residual +
+    restriction, refinement step) are timed launch by launch in a
+    one-solve-in-flight pass of the same maps, early-exit launches of an
+    already converged solve dropped; the one with the largest total time is
+    the dominant kernel (the committed rocprofv3 kernel trace of the same
+    command ranks every kernel of a map, coarse levels included);
+  * the same kernel rates for the plain FP64 path (its own one-solve pass);
+  * the solve-only stress points at k0 h = 1/2 (2048^2 and 512^3) with the
+    bounded phase right-hand side;
+  * the 2D 2048^2 bumps workload (the former headline) with its pipelined
+    mixed and plain rates, the GMRES(3) smoother, the batched Schroedinger
+    workload and the learned smoother;
+  * the FP64 CPU oracle on the host cores, on a bounded sample of the
+    headline workload (run in a child process).
 """
 from __future__ import annotations
 
@@ -31,141 +42,142 @@ import math
 import os
 import subprocess
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# V-cycles per coarse level of the full multigrid start (the F(k) cycle):
-# two gave the fewest finest-level steps per unit of time on the 2048^2
-# workload (1: 4 refinement steps, 2 and 3: 3 steps)
+# V-cycles per coarse level of the full multigrid start (the F(k) cycle)
 FMG_K = 2
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bumps2d_2048.json")
-STENCIL_SRC = os.path.join(ROOT, "paper_1211_4461_amd", "csrc", "ffmg_fused2d.hip")
+CSRC = os.path.join(ROOT, "paper_1211_4461_amd", "csrc")
+# committed rocprofv3 FETCH_SIZE / WRITE_SIZE records, keyed by kernel source
+TRAFFIC = {3: (os.path.join(ROOT, "profiles", "traffic_gauss3d_512.json"), os.path.join(CSRC, "ffmg_stencil.hip")),
+           2: (os.path.join(ROOT, "profiles", "traffic_bumps2d_2048.json"), os.path.join(CSRC, "ffmg_fused2d.hip"))}
+# the 2D record predates the per-dimension keys
+TRAFFIC_FILE, STENCIL_SRC = TRAFFIC[2]
 
-
-def src_hash():
-    with open(STENCIL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
-
-
-def measured_traffic(kernel, tile_rows):
-    """HBM bytes per launch of `kernel` (the variant with `tile_rows` rows)
-    from committed rocprofv3 --pmc counters, or None if absent or taken on a
-    different kernel source."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("src_sha") != src_hash() or t.get("kernel") != kernel:
-        return None
-    v = t.get("per_tile_rows", {}).get(str(tile_rows))
-    return None if v is None else v.get("bytes_per_launch")
-
-
-KERNELS = (("pre", 0), ("ff", 1), ("post", 2), ("refine", 3), ("ffgemm", 4))
+# PROF_* ids of the kernels the library brackets (mg_profile_*)
+KERNELS = {"pre": 0, "ff": 1, "post": 2, "refine": 3, "ffgemm": 4, "net": 5, "rr": 6}
+# Algorithmic bytes per finest-level point of the bracketed kernels (complex
+# values: FP32 8 B, FP64 16 B; the coarse level has 1/8 (3D) or 1/4 (2D) of
+# the points):
+#   post    interpolation + two Jacobi sweeps: read u, b, q, e_c; write u
+#   rr      residual + full weighting: read u, b, q; write b_c
+#   refine  FP64 update + residual: read u, b, q (16 each), d (8); write u (16), r (8)
+# "pre" brackets two passes (two sweeps from a zero guess, 3e; two sweeps
+# from a guess, 4e) and is reported, not ranked.
+BPP = {3: {"mixed": {"post": 33.0, "rr": 25.0, "refine": 80.0}, "plain": {"post": 66.0, "rr": 50.0}},
+       2: {"mixed": {"post": 34.0, "refine": 80.0}, "plain": {"post": 68.0}}}
+KERNEL_NAMES = {
+    3: {"post": "k_sweep2_3d<%s, SRC_PROL> (finest level: interpolation of the coarse correction + two Jacobi sweeps "
+                "in one z-marching pass)",
+        "rr": "k_resid_restrict3d<%s> (finest level: residual + full weighting in one pass)",
+        "refine": "k_refine3d (FP64 update + residual of the refinement step, one pass)",
+        "pre": "k_sweep2_3d<%s, SRC_ZERO2 / SRC_MEM> (finest level: two Jacobi sweeps per pass)"},
+    2: {"post": "k_smooth2d<%s, 2, false, true, 1, TH> (finest level: interpolation + two fused Jacobi sweeps)",
+        "refine": "k_refine2d (FP64 update + residual)",
+        "pre": "k_smooth_rr2d<%s, *, 1, *> (finest level: two sweeps + residual + full weighting)"},
+}
 # Useful flops of one learned-smoother application per point: 2736 complex
-# multiply-adds (one per complex weight: 3x3 taps, 1 + 1 -> 16 -> 16 -> 1
-# channels), 8 real flops each.
+# multiply-adds (one per complex weight), 8 real flops each.
 NET_FLOP_PER_POINT = 8 * 2736
 
 
-def run_path(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0, streams=1,
-             pipelined=False, time_kernel=True):
-    """run_path_here on a fresh stream of its own when several lanes are
-    used (every lane then has a stream created for it, none on the legacy
-    null stream), else on the current stream."""
-    s0 = torch.cuda.Stream() if streams > 1 else torch.cuda.current_stream()
-    with torch.cuda.stream(s0):
-        return run_path_here(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point,
-                             fmg_cycles=fmg_cycles, streams=streams, pipelined=pipelined, time_kernel=time_kernel)
+def src_hash(path=STENCIL_SRC):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def run_path_here(ff, torch, w, precision, ff_precision, steps, warmup, bytes_per_point, fmg_cycles=0, streams=1,
-                  pipelined=False, time_kernel=True):
-    """Time `steps` maps.  The warm-up maps record every timed kernel; the one
-    with the largest total time is the dominant kernel, and inside the timed
-    region HIP events bracket only that kernel's launches.  fmg_cycles > 0:
-    every solve starts from the full multigrid guess (k V-cycles per coarse
-    level) instead of u = 0.  streams = D > 1: maps cycle through D handles on
-    D streams, so that one map's far field (queued on its stream, the host
-    does not wait for it) runs while the next map is solved.  pipelined: each
-    step begins its map's solve (mg_solve_begin) before it finishes the map
-    begun D - 1 steps earlier (mg_solve_end, far field queued), so D solves
-    are in flight from this one host thread; the timed region ends when every
-    map begun in it is finished.  time_kernel = False: no event brackets
-    inside the timed region (the dominant kernel is still ranked from the
-    warm-up maps)."""
-    opts = ff.default_options(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles)
-    h, coef = ff.setup_workload(w, options=opts)
+def measured_traffic(kernel, key, dim=2):
+    """HBM bytes per launch of `kernel` (variant `key`) from committed
+    rocprofv3 --pmc counters, or None if absent or taken on a different
+    kernel source."""
+    path, src = TRAFFIC[dim]
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("src_sha") != src_hash(src) or t.get("kernel") != kernel:
+        return None
+    v = t.get("per_tile_rows", {}).get(str(key))
+    return None if v is None else v.get("bytes_per_launch")
+
+
+# ---------------------------------------------------------------------------
+# tuning and the timed map loop
+
+def tune_handle(ff, torch, h, w, precision, ff_precision):
+    """Apply the autotuner's choices (from the cache, or by timing every
+    variant, then cached) to handle h; returns what was chosen."""
     from paper_1211_4461_amd import autotune
-    tune = {"ff_gemm": None, "smooth": None, "smooth_coarse": None, "pre": None, "tail": None}
-    if ff.mg_tune_variants(h, ff.TUNE_FF_GEMM) > 1:   # tile shape of the split GEMM, off the timed path
-        v = autotune.tune_farfield(h, w.eta, None, w.dirs, ff_precision)
-        tune["ff_gemm"] = {"variant": v, "cache": autotune.load().get(autotune.key(
-            autotune.device_arch(), ff.TUNE_FF_GEMM, w.dim, [w.n - 1] * w.dim, len(w.dirs), ff_precision))}
+    tune = {}
     b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
     u = torch.empty_like(b)
-    if ff.mg_tune_variants(h, ff.TUNE_SMOOTH_COARSE) > 1:   # tile height of the smoothing kernel, coarse levels
-        ff.mg_rhs_plane_wave(h, w.eta, b)
-        v = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=ff.TUNE_SMOOTH_COARSE)
-        tune["smooth_coarse"] = {"variant": v, "tile_rows": (8, 16, 4)[v],
-                                 "cache": autotune.load().get(autotune.key(
-                                     autotune.device_arch(), ff.TUNE_SMOOTH_COARSE, w.dim, [w.n - 1] * w.dim, 0,
-                                     precision))}
-    if ff.mg_tune_variants(h, ff.TUNE_SMOOTH) > 1:    # tile height of the fused smoothing kernel, finest level
-        ff.mg_rhs_plane_wave(h, w.eta, b)
-        v = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=ff.TUNE_SMOOTH)
-        tune["smooth"] = {"variant": v, "tile_rows": (8, 16, 4)[v],
-                          "cache": autotune.load().get(autotune.key(
-                              autotune.device_arch(), ff.TUNE_SMOOTH, w.dim, [w.n - 1] * w.dim, 0, precision))}
-    if ff.mg_tune_variants(h, ff.TUNE_PRE) > 1:       # pre-smoothing + residual + restriction in one pass or two
-        ff.mg_rhs_plane_wave(h, w.eta, b)
-        v = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=ff.TUNE_PRE)
-        tune["pre"] = {"variant": v, "form": ("one pass", "two launches", "one pass, other finest tile height")[v],
-                       "cache": autotune.load().get(autotune.key(
-                           autotune.device_arch(), ff.TUNE_PRE, w.dim, [w.n - 1] * w.dim, 0, precision))}
-    if ff.mg_tune_variants(h, ff.TUNE_TAIL) > 1:      # size of the one-workgroup LDS tail, off the timed path
-        ff.mg_rhs_plane_wave(h, w.eta, b)
-        v = autotune.tune_solve(h, b, u, precision, tol=w.tol)
-        tune["tail"] = {"variant": v, "max_tail_points": (4096, 1024, 256)[v],
-                        "cache": autotune.load().get(autotune.key(
-                            autotune.device_arch(), ff.TUNE_TAIL, w.dim, [w.n - 1] * w.dim, 0, precision))}
-    F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
-    lanes = [(h, b, u, F, torch.cuda.current_stream())]
-    for _ in range(streams - 1):
-        # further handles, each on its own stream (default priority)
-        s2 = torch.cuda.Stream()
-        with torch.cuda.stream(s2):
-            h2, coef2 = ff.setup_workload(w, options=ff.default_options(precision=precision, ff_precision=ff_precision,
-                                                                        fmg_cycles=fmg_cycles))
-            lanes.append((h2, torch.empty_like(b), torch.empty_like(b), torch.empty_like(F), s2))
-        for tn in (ff.TUNE_FF_GEMM, ff.TUNE_SMOOTH, ff.TUNE_SMOOTH_COARSE, ff.TUNE_PRE, ff.TUNE_TAIL):
-            if ff.mg_tune_variants(h2, tn) > 1:
-                ff.mg_tune_set(h2, ff.mg_tune_get(h, tn), tn)
+    if ff.mg_tune_variants(h, ff.TUNE_FF_GEMM) > 1:
+        tune["ff_gemm"] = autotune.tune_farfield(h, w.eta, None, w.dirs, ff_precision)
+    for name, tn in (("smooth_coarse", ff.TUNE_SMOOTH_COARSE), ("smooth", ff.TUNE_SMOOTH), ("pre", ff.TUNE_PRE),
+                     ("tail", ff.TUNE_TAIL), ("sweep3d", ff.TUNE_SWEEP3D)):
+        if ff.mg_tune_variants(h, tn) > 1:
+            ff.mg_rhs_plane_wave(h, w.eta, b)
+            tune[name] = autotune.tune_solve(h, b, u, precision, tol=w.tol, tunable=tn)
+    del b, u
+    return tune
+
+
+def copy_tuning(ff, src, dst):
+    for tn in (ff.TUNE_FF_GEMM, ff.TUNE_SMOOTH, ff.TUNE_SMOOTH_COARSE, ff.TUNE_PRE, ff.TUNE_TAIL, ff.TUNE_SWEEP3D):
+        if ff.mg_tune_variants(dst, tn) > 1:
+            ff.mg_tune_set(dst, ff.mg_tune_get(src, tn), tn)
+
+
+def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FMG_K, lanes=1, pipelined=False,
+             etas=None):
+    """Time `steps` maps (right-hand side, solve, far field into device
+    memory) after `warmup` rounds.  lanes = D > 1: maps cycle through D
+    handles, each on its own stream; pipelined: each step begins its map's
+    solve (mg_solve_begin) before it finishes the map begun D - 1 steps
+    earlier (mg_solve_end, far field queued), so D solves are in flight from
+    this host thread; the timed region ends when every map begun in it is
+    finished.  etas: incoming directions cycled through map by map (default
+    the workload's)."""
+    etas = [w.eta] if etas is None else etas
+    opts = dict(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles)
+    ln_ = []
+    for i in range(lanes):
+        s_ = torch.cuda.Stream() if lanes > 1 else torch.cuda.current_stream()
+        with torch.cuda.stream(s_):
+            h_ = ff.setup_workload(w, options=ff.default_options(**opts))[0]
+            b_ = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
+            u_ = torch.empty_like(b_)
+            F_ = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
+        ln_.append([h_, b_, u_, F_, s_, None])
+    tune = tune_handle(ff, torch, ln_[0][0], w, precision, ff_precision)
+    for ln in ln_[1:]:
+        copy_tuning(ff, ln_[0][0], ln[0])
+    torch.cuda.synchronize()
     info = None
-    last = [F]
+    last = []
     nstep = [0]
     pending = collections.deque()
 
     def begin_map():
-        ln = lanes[nstep[0] % len(lanes)]
+        ln = ln_[nstep[0] % lanes]
+        ln[5] = etas[nstep[0] % len(etas)]
         nstep[0] += 1
-        h_, b_, u_, F_, s_ = ln
-        ff.mg_rhs_plane_wave(h_, w.eta, b_)
+        ff.mg_rhs_plane_wave(ln[0], ln[5], ln[1])
         if fmg_cycles == 0:
-            with torch.cuda.stream(s_):
-                u_.zero_()
+            with torch.cuda.stream(ln[4]):
+                ln[2].zero_()
         return ln
 
     def finish_map(info_, ln):
         nonlocal info
-        h_, b_, u_, F_, s_ = ln
         info = info_
-        ff.farfield_map(h_, w.eta, u_, w.dirs, out=F_)   # device output: queued, not waited for
-        last[0] = F_
+        ff.farfield_map(ln[0], ln[5], ln[2], w.dirs, out=ln[3])   # device output: queued, not waited for
+        last.append(ln)
 
     def step():
         ln = begin_map()
@@ -174,7 +186,7 @@ def run_path_here(ff, torch, w, precision, ff_precision, steps, warmup, bytes_pe
             return
         ff.mg_solve_begin(ln[0], ln[1], ln[2], tol=w.tol)
         pending.append(ln)
-        if len(pending) == len(lanes):   # the oldest lane is next: finish its map
+        if len(pending) == lanes:   # the oldest lane is next: finish its map
             old = pending.popleft()
             finish_map(ff.mg_solve_end(old[0]), old)
 
@@ -183,33 +195,9 @@ def run_path_here(ff, torch, w, precision, ff_precision, steps, warmup, bytes_pe
             old = pending.popleft()
             finish_map(ff.mg_solve_end(old[0]), old)
 
-    def read_all():
-        out_ = {}
-        for name, kid in KERNELS:
-            tot, cnt = 0.0, 0
-            for ln in lanes:
-                t_, c_ = ff.mg_profile_read(ln[0], kid)
-                tot, cnt = tot + t_, cnt + c_
-            out_[name] = (tot, cnt)
-        return out_
-
-    def enable(mask):
-        for ln in lanes:
-            ff.mg_profile_enable(ln[0], mask)
-
-    for _ in range(len(lanes)):
-        step()                   # first map per lane: cold launches, plans, not ranked
-    drain()
-    torch.cuda.synchronize()
-    enable(0x1F)
-    read_all()
-    for _ in range(max(warmup - 1, 1) * len(lanes)):
+    for _ in range(max(warmup, 1) * lanes):
         step()
     drain()
-    torch.cuda.synchronize()
-    allk = read_all()
-    dominant = max(bytes_per_point, key=lambda k: allk[k][0])
-    enable((1 << dict(KERNELS)[dominant]) if time_kernel else 0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -217,92 +205,172 @@ def run_path_here(ff, torch, w, precision, ff_precision, steps, warmup, bytes_pe
     drain()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    live = read_all()[dominant]
-    enable(0)
-    out = {"ms_per_step": 1e3 * dt / steps, "maps_per_s": steps / dt, "cycles": info.cycles, "vcycles": info.vcycles,
-           "rel_residual": info.rel_residual, "conv_factor": info.conv_factor, "F": last[0].cpu().numpy(),
-           "dominant": dominant, "live": live, "prof": allk, "tune": tune, "streams": len(lanes),
-           "pipelined": pipelined}
-    for ln in lanes:
+    F = last[-1][3].cpu().numpy()
+    eta_last = last[-1][5]
+    out = {"ms_per_step": 1e3 * dt / steps, "maps_per_s": steps / dt, "cycles": info.cycles,
+           "vcycles": info.vcycles, "rel_residual": info.rel_residual, "conv_factor": info.conv_factor, "F": F,
+           "eta": eta_last, "tune": tune, "lanes": lanes, "pipelined": pipelined}
+    for ln in ln_:
         ln[0].destroy()
+    del ln_
+    torch.cuda.empty_cache()
     return out
 
 
-def run_concurrent(ff, torch, w, precision, ff_precision, nthreads, maps_per_thread, fmg_cycles):
-    """Maps for several incoming directions in flight: `nthreads` host
-    threads, each with its own handle and stream and its own direction
-    (eta at angle 2 pi i / nthreads), each running the map loop (right-hand
-    side, solve, far field into device memory).  The library's calls release
-    the interpreter lock, so the solves overlap on the GPU: one map's
-    latency-bound coarse levels run beside another's finest-level sweeps.
-    Returns whole-job maps/s over nthreads x maps_per_thread maps."""
-    import threading
+def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp):
+    """The same maps one at a time (one handle, one stream) with HIP events
+    around every launch of the finest-level kernels the library brackets:
+    per-launch durations, early-exit launches (a batch step queued after the
+    solve had stopped: under a fifth of the median) dropped, GB/s from the
+    algorithmic bytes.  Returns per-kernel statistics and the dominant
+    kernel among `bpp` (the largest total time per map)."""
+    h = ff.setup_workload(w, options=ff.default_options(precision=precision, ff_precision=ff_precision,
+                                                        fmg_cycles=fmg_cycles))[0]
+    tune_handle(ff, torch, h, w, precision, ff_precision)
+    b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
+    u = torch.empty_like(b)
+    F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
+
+    def one():
+        ff.mg_rhs_plane_wave(h, w.eta, b)
+        if fmg_cycles == 0:
+            u.zero_()
+        inf = ff.mg_solve(h, b, u, tol=w.tol)
+        ff.farfield_map(h, w.eta, u, w.dirs, out=F)
+        return inf
+
+    one()
+    torch.cuda.synchronize()
+    mask = 0
+    for k in ("pre", "post", "refine", "rr", "ff", "ffgemm"):
+        mask |= 1 << KERNELS[k]
+    ff.mg_profile_enable(h, mask)
+    for k in KERNELS.values():
+        ff.mg_profile_durations(h, k)
+    for _ in range(maps):
+        info = one()
+    torch.cuda.synchronize()
+    stats = {}
+    for name in ("pre", "post", "refine", "rr", "ff", "ffgemm"):
+        d = ff.mg_profile_durations(h, KERNELS[name])
+        if d.size == 0:
+            continue
+        med = float(sorted(d)[d.size // 2])
+        keep = d[d >= 0.2 * med]
+        st = {"launches": int(keep.size), "early_exit_launches_dropped": int(d.size - keep.size),
+              "avg_us": round(1e3 * float(keep.mean()), 2), "min_us": round(1e3 * float(keep.min()), 2),
+              "max_us": round(1e3 * float(keep.max()), 2), "ms_per_map": round(float(keep.sum()) / maps, 3)}
+        if name in bpp:
+            gbs = bpp[name] * w.N / (keep.mean() * 1e-3) / 1e9
+            st.update({"bytes_per_point": bpp[name], "bytes_per_launch": int(bpp[name] * w.N),
+                       "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        stats[name] = st
+    ff.mg_profile_enable(h, 0)
+    dominant = max((k for k in bpp if k in stats), key=lambda k: stats[k]["ms_per_map"])
+    out = {"kernels": stats, "dominant": dominant, "cycles": info.cycles, "vcycles": info.vcycles, "maps": maps}
+    h.destroy()
+    del b, u, F
+    torch.cuda.empty_cache()
+    return out
+
+
+def gemm_report(stats, w, prec):
+    """MFMA rate of the far-field GEMM stages (useful flops: 2D 8 M N; 3D the
+    separable chain 8 N M_pol + 8 M (n-1)^2; a split precision issues
+    `products` times as many)."""
+    g = stats.get("ffgemm")
+    if not g:
+        return None
+    t = g["avg_us"] * 1e-6
+    M = len(w.dirs)
+    m = w.n - 1
+    if w.dim == 2:
+        flop = 8.0 * M * w.N
+    else:
+        n_pol = len(set(round(float(z), 12) for z in w.dirs[:, 2]))
+        flop = 8.0 * w.N * n_pol + 8.0 * M * m * m
+    products, peak = {"bf16x6": (6, 2500.0), "bf16x3": (3, 2500.0), "fp64": (1, 78.6)}[prec]
+    issued = products * flop / t / 1e12
+    return {"us": g["avg_us"], "useful_flop_per_map": flop, "products": products,
+            "useful_TFLOPs": round(flop / t / 1e12, 2), "mfma_TFLOPs": round(issued, 1), "peak_TFLOPs": peak,
+            "mfma_frac": round(issued / peak, 4)}
+
+
+# ---------------------------------------------------------------------------
+# extra workloads
+
+def run_stress(ff, torch, W, reps=3):
+    """Solve-only at k0 h = 1/2 (the workloads' literal wavenumbers) with the
+    bounded phase right-hand side: cycles, time per solve and the
+    mixed-versus-plain speedup, and the finest post-smoothing kernel's rate."""
+    out = {}
+    for name, w, bpp in (("bumps_2d_2048", W.bumps_2d(k0=None, M=8), BPP[2]),
+                         ("gauss_3d_512", W.gauss_3d(k0=None, n_az=4, n_pol=2), BPP[3])):
+        r = {"k0": round(w.k0, 4), "k0h": 0.5, "rhs": "q exp(i k0 cos(gamma) eta.x) (mg_rhs_phase)",
+             "start": f"full multigrid, {FMG_K} V(2,2) per coarse level"}
+        for form, prec in (("mixed", ff.FP32_IR), ("plain_fp64", ff.FP64)):
+            h = ff.setup_workload(w, options=ff.default_options(precision=prec, fmg_cycles=FMG_K))[0]
+            b = ff.mg_rhs_phase(h, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+            u = torch.empty_like(b)
+            info = ff.mg_solve(h, b, u, tol=w.tol)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                info = ff.mg_solve(h, b, u, tol=w.tol)
+                ts.append(time.perf_counter() - t0)
+            ff.mg_profile_enable(h, 1 << KERNELS["post"])
+            ff.mg_profile_durations(h, KERNELS["post"])
+            ff.mg_solve(h, b, u, tol=w.tol)
+            d = ff.mg_profile_durations(h, KERNELS["post"])
+            ff.mg_profile_enable(h, 0)
+            d = d[d >= 0.2 * float(sorted(d)[d.size // 2])] if d.size else d
+            bp = bpp["mixed" if form == "mixed" else "plain"]["post"]
+            gbs = bp * w.N / (d.mean() * 1e-3) / 1e9 if d.size else None
+            r[form] = {"ms_per_solve": round(1e3 * min(ts), 3), "steps": info.cycles, "vcycles": info.vcycles,
+                       "rel_residual": info.rel_residual, "conv_factor": round(info.conv_factor, 4),
+                       "post_smoothing_GB_s": None if gbs is None else round(gbs, 1)}
+            h.destroy()
+            del b, u
+            torch.cuda.empty_cache()
+        r["speedup_vs_plain"] = round(r["plain_fp64"]["ms_per_solve"] / r["mixed"]["ms_per_solve"], 3)
+        out[name] = r
+    return out
+
+
+def run_bumps2d(ff, torch, W, steps, warmup, lanes, ff_prec):
+    """The 2048^2 bumps workload (k0 = 1, 360 angles): pipelined mixed and
+    plain maps over four incoming directions, and the dominant kernel of its
+    one-solve pass.  Its FP32 working set (about 142 MB per launch of the
+    dominant kernel) fits the 256 MB Infinity Cache, so that rate is
+    cache-assisted, not an HBM figure."""
     import numpy as np
-    from paper_1211_4461_amd import autotune
-    lanes = []
-    for i in range(nthreads):
-        s_ = torch.cuda.Stream()
-        with torch.cuda.stream(s_):
-            h_, coef_ = ff.setup_workload(w, options=ff.default_options(precision=precision, ff_precision=ff_precision,
-                                                                        fmg_cycles=fmg_cycles))
-            b_ = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
-            u_ = torch.zeros_like(b_)
-            F_ = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
-        lanes.append((h_, b_, u_, F_, s_, coef_))
-    h0, b0, u0 = lanes[0][0], lanes[0][1], lanes[0][2]
-    ff.mg_rhs_plane_wave(h0, w.eta, b0)
-    torch.cuda.synchronize()
-    for tn in (ff.TUNE_SMOOTH_COARSE, ff.TUNE_SMOOTH, ff.TUNE_PRE, ff.TUNE_TAIL):   # cached by run_path
-        if ff.mg_tune_variants(h0, tn) > 1:
-            autotune.tune_solve(h0, b0, u0, precision, tol=w.tol, tunable=tn)
-    if ff.mg_tune_variants(h0, ff.TUNE_FF_GEMM) > 1:
-        autotune.tune_farfield(h0, w.eta, None, w.dirs, ff_precision)
-    for ln in lanes[1:]:
-        for tn in (ff.TUNE_FF_GEMM, ff.TUNE_SMOOTH, ff.TUNE_SMOOTH_COARSE, ff.TUNE_PRE, ff.TUNE_TAIL):
-            if ff.mg_tune_variants(ln[0], tn) > 1:
-                ff.mg_tune_set(ln[0], ff.mg_tune_get(h0, tn), tn)
-    infos = [None] * nthreads
-    etas = [np.array([math.cos(2 * math.pi * i / nthreads), math.sin(2 * math.pi * i / nthreads), 0.0])
-            for i in range(nthreads)]
-
-    def one_map(i):
-        h_, b_, u_, F_, s_, _ = lanes[i]
-        ff.mg_rhs_plane_wave(h_, etas[i], b_)
-        infos[i] = ff.mg_solve(h_, b_, u_, tol=w.tol)
-        ff.farfield_map(h_, etas[i], u_, w.dirs, out=F_)
-
-    for i in range(nthreads):    # warm-up: plans, first launches
-        one_map(i)
-    torch.cuda.synchronize()
-    go = threading.Barrier(nthreads + 1)
-    errors = []
-
-    def worker(i):
-        try:
-            go.wait()
-            for _ in range(maps_per_thread):
-                one_map(i)
-        except Exception as e:   # reported after the join
-            errors.append(e)
-
-    threads = [threading.Thread(target=worker, args=(i,)) for i in range(nthreads)]
-    for t in threads:
-        t.start()
-    torch.cuda.synchronize()
-    go.wait()
-    t0 = time.perf_counter()
-    for t in threads:
-        t.join()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    if errors:
-        raise errors[0]
-    for ln in lanes:
-        ln[0].destroy()
-    n = nthreads * maps_per_thread
-    return {"maps": n, "host_threads": nthreads, "incoming_directions": nthreads, "maps_per_s": round(n / dt, 3),
-            "ms_per_map": round(1e3 * dt / n, 3), "cycles": [i.cycles for i in infos],
-            "max_rel_residual": max(i.rel_residual for i in infos)}
+    w = W.bumps_2d(n=2048, seed=1, k0=1.0, M=360)
+    etas = [np.array([math.cos(a), math.sin(a)]) for a in (0.0, 0.5 * math.pi, math.pi, 1.5 * math.pi)]
+    ffp = {"bf16x6": ff.FF_BF16X6, "bf16x3": ff.FF_BF16X3, "fp64": ff.FF_FP64}[ff_prec]
+    m = run_path(ff, torch, w, ff.FP32_IR, ffp, steps, warmup, lanes=lanes, pipelined=lanes > 1, etas=etas)
+    p = run_path(ff, torch, w, ff.FP64, ff.FF_FP64, max(steps // 2, 2), warmup, lanes=lanes, pipelined=lanes > 1,
+                 etas=etas)
+    km = kernel_pass(ff, torch, w, ff.FP32_IR, ffp, 8, FMG_K, BPP[2]["mixed"])
+    kp = kernel_pass(ff, torch, w, ff.FP64, ff.FF_FP64, 4, FMG_K, BPP[2]["plain"])
+    dom = km["dominant"]
+    th = (8, 16, 4)[m["tune"].get("smooth", 0)]
+    return {"workload": "bumps_2d n=2048 box=[-10,10]^2 k0=1 gamma=30deg 8 bumps seed=1, 360 angles, "
+                        "4 incoming directions cycled map by map",
+            "lanes": lanes, "mixed": {"maps_per_s": round(m["maps_per_s"], 3), "ms_per_step": round(m["ms_per_step"], 3),
+                                      "refinement_steps": m["cycles"], "vcycles": m["vcycles"],
+                                      "rel_residual": m["rel_residual"], "tune": m["tune"]},
+            "plain_fp64": {"maps_per_s": round(p["maps_per_s"], 3), "ms_per_step": round(p["ms_per_step"], 3),
+                           "cycles": p["cycles"], "rel_residual": p["rel_residual"], "tune": p["tune"]},
+            "speedup_vs_plain": round(m["maps_per_s"] / p["maps_per_s"], 3),
+            "mixed_vs_plain_farfield_rel_err": float(np.linalg.norm(m["F"] - p["F"]) / np.linalg.norm(p["F"])),
+            "kernels_mixed_one_solve": km["kernels"], "kernels_plain_one_solve": kp["kernels"],
+            "dominant_kernel_roofline": {
+                "kernel": KERNEL_NAMES[2][dom] % "float", "frac_of_hbm": km["kernels"][dom]["hbm_frac"],
+                "GB_s": km["kernels"][dom]["GB_s"], "traffic": measured_traffic(dom, th, 2),
+                "note": "cache-assisted: one launch moves about 142 MB, which fits the 256 MB Infinity Cache; "
+                        "the HBM roofline is judged on the 512^3 headline"},
+            "farfield_gemm": gemm_report(km["kernels"], w, ff_prec)}
 
 
 def run_gmres(ff, torch, W, n, steps=6):
@@ -408,7 +476,8 @@ def run_batched(ff, torch, W, steps):
     for w in insts:
         sizes[f"{w.n - 1}^2"] = sizes.get(f"{w.n - 1}^2", 0) + 1
     out = {"workload": "schrodinger_batch seed=3: 32 directions x E in {0.5,1,2}, grids drawn from "
-                       "{255^2, 511^2, 1023^2}, box [-10,10]^2, gamma=30deg, 360 angles",
+                       "{255^2, 511^2, 1023^2}, box [-10,10]^2, gamma=30deg, 360 angles; wells at 1/10 of the "
+                       "literal depths (weighted-Jacobi V-cycles diverge on the literal bound states)",
            "instances": len(insts), "grids": sizes, "operators": len(cache),
            "maps_per_s": round(len(insts) / tb, 2), "ms_per_batch": round(1e3 * tb, 2),
            "sequential_maps_per_s": round(len(insts) / ts, 2),
@@ -422,7 +491,7 @@ def run_batched(ff, torch, W, steps):
     return out
 
 
-def run_learned(ff, torch, W, reps=3, oracle_check=False):
+def run_learned(ff, torch, W, reps=3):
     """The learned-smoother workload: a network trained on the GPU (the
     library's kernels) from weighted Jacobi on (error, residual) patches of
     plain V-cycle iterates and white noise on 255^2 fields (k0 h in
@@ -463,7 +532,7 @@ def run_learned(ff, torch, W, reps=3, oracle_check=False):
             info = ff.mg_solve(h, b, u, tol=tol)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t)
-        net = None
+        net_ = None
         if learned:   # the network kernel alone, bracketed by HIP events in one more solve
             ff.mg_profile_enable(h, 1 << ff.PROF_NET)
             ff.mg_profile_read(h, ff.PROF_NET)
@@ -473,23 +542,22 @@ def run_learned(ff, torch, W, reps=3, oracle_check=False):
             ff.mg_profile_enable(h, 0)
             us = 1e3 * ms / max(cnt, 1)
             useful = NET_FLOP_PER_POINT * w.N
-            net = {"applications": cnt, "avg_us": round(us, 2), "useful_flop": useful,
-                   "useful_TFLOPs": round(useful / (us * 1e-6) / 1e12, 1),
-                   "mfma_frac_useful": round(useful / (us * 1e-6) / 1e12 / 2500.0, 4)}
-        return h, u, info, 1e3 * min(ts), net
+            net_ = {"applications": cnt, "avg_us": round(us, 2), "useful_flop": useful,
+                    "useful_TFLOPs": round(useful / (us * 1e-6) / 1e12, 1),
+                    "mfma_frac_useful": round(useful / (us * 1e-6) / 1e12 / 2500.0, 4)}
+        return h, u, info, 1e3 * min(ts), net_
 
     for kh in (0.5, 0.2):
         w = W.random_field(1024, 4, kh)
         b = LS.phase_rhs(w, torch)
         hj, uj, ij, tj, _ = solve(w, b, False)
-        hl, ul, il, tl, net = solve(w, b, True)
+        hl, ul, il, tl, net_ = solve(w, b, True)
         out[f"k0h={kh}"] = {"jacobi": {"cycles": ij.cycles, "conv_factor": round(ij.conv_factor, 4), "ms": round(tj, 3)},
                             "learned": {"cycles": il.cycles, "conv_factor": round(il.conv_factor, 4), "ms": round(tl, 3),
-                                        "fell_back": il.fell_back, "network_kernel": net},
+                                        "fell_back": il.fell_back, "network_kernel": net_},
                             "solution_rel_diff": float(torch.linalg.norm(ul - uj) / torch.linalg.norm(uj))}
         hj.destroy()
         hl.destroy()
-    # far field at k0 = 1 (the contour plane wave)
     w = W.random_field(1024, 4, 20.0 / 1024)
     maps = {}
     for learned in (False, True):
@@ -502,217 +570,126 @@ def run_learned(ff, torch, W, reps=3, oracle_check=False):
         h.destroy()
     out["k0=1"] = {"farfield_rel_err_vs_plain_fp64": float(np.linalg.norm(maps[True] - maps[False]) /
                                                              np.linalg.norm(maps[False]))}
-    if oracle_check:
-        from oracle import oracle as orc
-        g = orc.Grid(2, w.n, w.lo, w.hi)
-        kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
-        bo = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
-        uo, st, k, _ = orc.Multigrid(g, w.gamma, kappa).solve(bo, tol=1e-10)
-        Fo = orc.farfield(g, w.gamma, k0, q, w.eta, uo, w.dirs)
-        out["k0=1"]["farfield_rel_err_vs_oracle"] = float(np.linalg.norm(maps[True] - Fo) / np.linalg.norm(Fo))
     return out
 
 
-def run_3d(ff, torch, W, steps=2, fmg_cycles=FMG_K, lanes=2):
-    """The 3D workload (512^3 intervals, chi = 0.5 exp(-z.z/2), 128 x 64
-    directions): maps with FP32 V-cycles in FP64 refinement + split-BF16 far
-    field and plain FP64 maps, each solved to 1e-10 from the full multigrid
-    start (and, as `*_zero_start`, from u = 0); the rate of the finest-level
-    post-smoothing (two z-marching launches per cycle: the interpolation
-    fused into the first 7-point sweep, then the second sweep; 8 e + e/8 bytes
-    per point in all) from the library's events."""
+# ---------------------------------------------------------------------------
+# CPU baseline (child process: the oracle, built for this host)
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_sample(n, plain_cycles, n_dirs_sample, out_path):
+    """Child process: the FP64 oracle as it stands, built -O3 -march=native
+    for this host, on a bounded sample of the 3D workload at n intervals:
+    setup, the full multigrid start, one V(2,2)-cycle and the far field of
+    n_dirs_sample of the 128 x 64 directions, each timed; the map time is
+    estimated as start + plain_cycles V-cycles + the far field scaled to all
+    directions (the cycle count is the plain FP64 GPU path's, which equals
+    the oracle's iteration: parity tests)."""
     import numpy as np
-    from paper_1211_4461_amd import autotune
-    w = W.gauss_3d()
-    out = {"workload": f"gauss_3d n={w.n} box=[-6,6]^3 k0=1 gamma=30deg eta=+x, "
-                       f"{len(w.dirs)} directions (128 azimuth x 64 polar)", "unknowns": w.N}
-    out["start"] = f"full multigrid: {fmg_cycles} V(2,2) per coarse level"
-    maps = {}
-    for name, prec, ffp, e, fk in (("mixed", ff.FP32_IR, ff.FF_BF16X6, 8, fmg_cycles),
-                                   ("plain_fp64", ff.FP64, ff.FF_FP64, 16, fmg_cycles),
-                                   ("mixed_zero_start", ff.FP32_IR, ff.FF_BF16X6, 8, 0),
-                                   ("plain_fp64_zero_start", ff.FP64, ff.FF_FP64, 16, 0)):
-        h = ff.setup_workload(w, options=ff.default_options(precision=prec, ff_precision=ffp, fmg_cycles=fk))[0]
-        if ff.mg_tune_variants(h, ff.TUNE_FF_GEMM) > 1:
-            autotune.tune_farfield(h, w.eta, None, w.dirs, ffp)
-        b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
-        u = torch.empty_like(b)
-        info = None
-
-        def step():
-            nonlocal info
-            ff.mg_rhs_plane_wave(h, w.eta, b)
-            u.zero_()
-            info = ff.mg_solve(h, b, u, tol=w.tol)
-            return ff.farfield_map(h, w.eta, u, w.dirs)
-
-        step()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            F = step()
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        ff.mg_profile_enable(h, (1 << ff.PROF_POST) | (1 << ff.PROF_FF) | (1 << ff.PROF_FFGEMM))
-        step()
-        post, ffm, gem = (ff.mg_profile_read(h, k) for k in (ff.PROF_POST, ff.PROF_FF, ff.PROF_FFGEMM))
-        ff.mg_profile_enable(h, 0)
-        post_us = 1e3 * post[0] / max(post[1], 1) * 2   # per post-smoothing (two launches)
-        bpp = 8 * e + e / 8
-        gbs = bpp * w.N / (post_us * 1e-6) / 1e9
-        out[name] = {"maps_per_s": round(1.0 / dt, 3), "ms_per_map": round(1e3 * dt, 2), "cycles": info.cycles,
-                     "vcycles": info.vcycles, "rel_residual": info.rel_residual,
-                     "finest_post_smoothing": {"avg_us": round(post_us, 1), "GB_s": round(gbs, 1),
-                                               "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_point": bpp},
-                     "ff_ms_per_map": round(ffm[0] / max(ffm[1], 1), 3),
-                     "ff_gemm_ms": round(gem[0] / max(gem[1], 1), 3)}
-        maps[name] = F
-        h.destroy()
-        del b, u
-        torch.cuda.empty_cache()
-    # the mixed maps again with `lanes` solves in flight from this thread
-    # (one handle and stream each, mg_solve_begin / mg_solve_end, far field
-    # into device memory), as in the 2D headline
-    nl = lanes
-    lanes = []
-    for _ in range(nl):
-        s_ = torch.cuda.Stream()
-        with torch.cuda.stream(s_):
-            h_ = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, ff_precision=ff.FF_BF16X6,
-                                                                 fmg_cycles=fmg_cycles))[0]
-            b_ = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
-            u_ = torch.empty_like(b_)
-            F_ = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
-        lanes.append((h_, b_, u_, F_))
-    if ff.mg_tune_variants(lanes[0][0], ff.TUNE_FF_GEMM) > 1:
-        v = autotune.tune_farfield(lanes[0][0], w.eta, None, w.dirs, ff.FF_BF16X6)
-        for ln in lanes[1:]:
-            ff.mg_tune_set(ln[0], v, ff.TUNE_FF_GEMM)
-    pinfo = []
-
-    def run_pipelined(nmaps):
-        pend = []
-        for k in range(nmaps):
-            h_, b_, u_, F_ = lanes[k % nl]
-            ff.mg_rhs_plane_wave(h_, w.eta, b_)
-            ff.mg_solve_begin(h_, b_, u_, tol=w.tol)
-            pend.append(lanes[k % nl])
-            if len(pend) == nl:
-                o = pend.pop(0)
-                pinfo.append(ff.mg_solve_end(o[0]))
-                ff.farfield_map(o[0], w.eta, o[2], w.dirs, out=o[3])
-        for o in pend:
-            pinfo.append(ff.mg_solve_end(o[0]))
-            ff.farfield_map(o[0], w.eta, o[2], w.dirs, out=o[3])
-        torch.cuda.synchronize()
-
-    run_pipelined(nl)
-    nm = nl * steps
-    t0 = time.perf_counter()
-    run_pipelined(nm)
-    dt = (time.perf_counter() - t0) / nm
-    Fp = lanes[(nm - 1) % nl][3].cpu().numpy()
-    out["mixed_pipelined"] = {"maps_per_s": round(1.0 / dt, 3), "ms_per_map": round(1e3 * dt, 2),
-                              "maps": nm, "lanes": nl, "cycles": pinfo[-1].cycles,
-                              "rel_residual": pinfo[-1].rel_residual,
-                              "farfield_rel_diff_vs_mixed": float(np.linalg.norm(Fp - maps["mixed"]) /
-                                                                  np.linalg.norm(maps["mixed"])),
-                              "speedup_over_one_at_a_time": round(out["mixed"]["ms_per_map"] / (1e3 * dt), 3)}
-    for ln in lanes:
-        ln[0].destroy()
-    del lanes
-    torch.cuda.empty_cache()
-    out["speedup_vs_plain"] = round(out["mixed"]["maps_per_s"] / out["plain_fp64"]["maps_per_s"], 3)
-    out["mixed_vs_plain_farfield_rel_err"] = float(np.linalg.norm(maps["mixed"] - maps["plain_fp64"]) /
-                                                   np.linalg.norm(maps["plain_fp64"]))
-    out["fmg_vs_zero_start_farfield_rel_diff"] = float(np.linalg.norm(maps["mixed"] - maps["mixed_zero_start"]) /
-                                                       np.linalg.norm(maps["mixed_zero_start"]))
-    return out
-
-
-def gemm_report(prof, w, prec, tune=None):
-    """MFMA rate of the far-field GEMM stage (2D: 8 M N flop per map as a
-    complex GEMM; a split precision issues `products` times as many)."""
-    t_ms, cnt = prof["ffgemm"]
-    if cnt == 0:
-        return None
-    t = t_ms / cnt * 1e-3
-    flop = 8.0 * len(w.dirs) * w.N
-    products, peak = {"bf16x6": (6, 2500.0), "bf16x3": (3, 2500.0), "fp64": (1, 78.6)}[prec]
-    issued = products * flop / t / 1e12
-    return {"us": round(t * 1e6, 1), "flop_per_map": flop, "products": products,
-            "complex_TFLOPs": round(flop / t / 1e12, 2), "mfma_TFLOPs": round(issued, 1),
-            "peak_TFLOPs": peak, "mfma_frac": round(issued / peak, 4), "tuned": tune}
-
-
-def cpu_baseline(w):
-    """The FP64 oracle, as it stands, on one map of the same workload."""
-    import numpy as np
-
     from oracle import oracle as orc
-    cores = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    from paper_1211_4461_amd import workloads as W
+    lib = orc.build(force=True, native=True, path=os.path.join(tempfile.gettempdir(), "libffmg_oracle_native.so"))
+    orc.load(lib)
+    w = W.gauss_3d(n=n)
     g = orc.Grid(w.dim, w.n, w.lo, w.hi)
     kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
     t0 = time.perf_counter()
     mg = orc.Multigrid(g, w.gamma, kappa, nu1=w.nu1, nu2=w.nu2, omega=w.omega)
-    t1 = time.perf_counter()
     b = orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta)
-    u, st, k, _ = mg.solve(b, tol=w.tol)
-    F = orc.farfield(g, w.gamma, k0, q, w.eta, u, w.dirs)
+    t1 = time.perf_counter()
+    u = mg.fmg(b, FMG_K)
     t2 = time.perf_counter()
-    return {"value": 1.0 / (t2 - t1), "unit": "maps/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 map of the same workload ({w.n}^2 intervals, solve to {w.tol:g} in {k} V(2,2) cycles "
-                      f"+ {len(w.dirs)}-angle far field), setup ({t1 - t0:.2f} s) excluded",
-            "seconds": t2 - t1}, np.asarray(F)
+    u = mg.vcycle(b, u)
+    t3 = time.perf_counter()
+    idx = np.linspace(0, len(w.dirs) - 1, n_dirs_sample).astype(int)
+    orc.farfield(g, w.gamma, k0, q, w.eta, u, w.dirs[idx])
+    t4 = time.perf_counter()
+    t_ff = (t4 - t3) * len(w.dirs) / n_dirs_sample
+    est = (t2 - t1) + plain_cycles * (t3 - t2) + t_ff
+    res = {"threads": orc.num_threads(), "setup_s": round(t1 - t0, 3), "fmg_start_s": round(t2 - t1, 3),
+           "vcycle_s": round(t3 - t2, 3), "farfield_sample_s": round(t4 - t3, 3), "farfield_est_s": round(t_ff, 2),
+           "map_est_s": round(est, 2), "map_est_zero_start_s": None}
+    with open(out_path, "w") as f:
+        json.dump(res, f)
 
+
+def cpu_baseline(plain_cycles_fmg, plain_cycles_zero):
+    """The oracle on the host cores (all of them, then one thread on a
+    smaller instance of the same law), in child processes."""
+    out = {}
+    runs = {}
+    for tag, n, threads, ndir in (("all", 512, None, 16), ("one", 128, 1, 8)):
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = str(threads)
+        path = os.path.join(tempfile.gettempdir(), f"ffmg_cpu_{tag}.json")
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-sample", str(n), str(plain_cycles_fmg), str(ndir),
+               path]
+        subprocess.check_call(cmd, env=env, stdout=subprocess.DEVNULL)
+        with open(path) as f:
+            runs[tag] = json.load(f)
+    a = runs["all"]
+    zero_est = a["map_est_s"] - a["fmg_start_s"] + (plain_cycles_zero - plain_cycles_fmg) * a["vcycle_s"]
+    return {"value": round(1.0 / a["map_est_s"], 5), "unit": "maps/s", "cores": a["threads"], "kind": "oracle",
+            "sample": (f"512^3 (the headline workload), the oracle built -O3 -march=native on this host: setup, the "
+                       f"full multigrid start and one V(2,2)-cycle timed, the far field timed on 16 of the 8192 "
+                       f"directions; map = start + {plain_cycles_fmg} V-cycles (the plain FP64 count from that start) "
+                       f"+ far field scaled to 8192 directions"),
+            "cpu_model": cpu_model(), "measured": a,
+            "map_est_zero_start_s": round(zero_est, 2),
+            "one_thread": {"instance": "gauss_3d n=128 (the same law, 1/64 of the points)", **runs["one"]}}
+
+
+# ---------------------------------------------------------------------------
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=2048, help="intervals per axis")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path")
+    ap.add_argument("--steps", type=int, default=16, help="timed maps of the headline")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--lanes", type=int, default=2, help="solves in flight (handles and streams) of the headline")
     ap.add_argument("--ff-precision", choices=("bf16x6", "bf16x3", "fp64"), default="bf16x6",
                     help="far-field contraction of the mixed path")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched Schroedinger workload")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 512^3 workload")
-    ap.add_argument("--no-start-forms", action="store_true",
-                    help="skip the other starts (u = 0, other full-multigrid cycle counts)")
-    ap.add_argument("--zero-start", action="store_true", help="time the solves from u = 0 instead of the FMG start")
-    ap.add_argument("--no-concurrent", action="store_true", help="skip the many-maps-in-flight form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 path of the headline")
+    ap.add_argument("--no-stress", action="store_true", help="skip the k0h = 1/2 solve-only points")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2048^2 bumps workload")
     ap.add_argument("--no-gmres", action="store_true", help="skip the GMRES(3)-smoother workload")
-    ap.add_argument("--one-stream", action="store_true",
-                    help="one handle on one stream (no overlap of a map's far field with the next solve)")
-    ap.add_argument("--blocking", action="store_true",
-                    help="the lanes' solves finished (mg_solve) before the next map is begun")
-    ap.add_argument("--lanes", type=int, default=4,
-                    help="handles and streams the headline maps cycle through (solves in flight)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched Schroedinger workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
-    ap.add_argument("--tune-only", action="store_true",
-                    help="run the autotuning sweeps of the 2048^2 paths (filling the cache) and exit")
+    ap.add_argument("--tune-only", action="store_true", help="fill the autotuning cache for the headline and exit")
     ap.add_argument("--tune-in-process", action="store_true",
                     help="run the autotuning sweeps in this process instead of a child process")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--cpu-sample", nargs=4, metavar=("N", "CYCLES", "NDIRS", "OUT"), help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multigrid sweeps and the far-field contraction are measured on one MI355X.", file=sys.stderr)
         sys.exit(2)
+    if args.cpu_sample:
+        n, cyc, nd, outp = args.cpu_sample
+        cpu_sample(int(n), int(cyc), int(nd), outp)
+        return
 
     if not args.tune_only and not args.tune_in_process:
-        # The autotuning sweeps of the headline paths run in a child process
-        # that fills the cache, started before this process touches the GPU;
-        # this one then reads the cached choices.  The sweeps are setup, off
-        # every timed path, and a process that has run them in-process was
-        # measured slower with four solves in flight (about 610 against 750
-        # maps/s on the same box).
-        cmd = [sys.executable, os.path.abspath(__file__), "--tune-only", "--n", str(args.n),
-               "--ff-precision", args.ff_precision] + (["--zero-start"] if args.zero_start else [])
+        # the autotuning sweeps run in a child process that fills the cache
+        # before this process touches the GPU; this one reads the cache
+        cmd = [sys.executable, os.path.abspath(__file__), "--tune-only", "--ff-precision", args.ff_precision] + (
+            ["--no-2d"] if args.no_2d else [])
         rc = subprocess.call(cmd, stdout=subprocess.DEVNULL)
-        if rc != 0:   # the sweeps then run in this process, as with --tune-in-process
+        if rc != 0:
             print(f"bench.py: the autotuning child process failed ({rc}); tuning in this process", file=sys.stderr)
 
     import numpy as np
@@ -725,9 +702,19 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     ffmg.lib()
-    w = W.bumps_2d(n=args.n, seed=1, k0=1.0, M=360)
-    N = w.N
-
+    ffp_name = args.ff_precision
+    ffp = {"bf16x6": ffmg.FF_BF16X6, "bf16x3": ffmg.FF_BF16X3, "fp64": ffmg.FF_FP64}[ffp_name]
+    w = W.gauss_3d()
+    if args.tune_only:
+        wl = [w] + ([] if args.no_2d else [W.bumps_2d(n=2048, seed=1, k0=1.0, M=360)])
+        for wk in wl:
+            for prec, fp in ((ffmg.FP32_IR, ffp), (ffmg.FP64, ffmg.FF_FP64)):
+                h = ffmg.setup_workload(wk, options=ffmg.default_options(precision=prec, ff_precision=fp,
+                                                                         fmg_cycles=FMG_K))[0]
+                tune_handle(ffmg, torch, h, wk, prec, fp)
+                h.destroy()
+                torch.cuda.empty_cache()
+        return
     if args.calib_copy:
         x = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
         y = torch.empty_like(x)
@@ -736,60 +723,23 @@ def main():
         torch.cuda.synchronize()
         del x, y
 
-    # Algorithmic bytes per point of the timed kernels (FP32 complex 8 B, FP64 16 B):
-    #   pre    2 sweeps + residual + full weighting in one pass, from a zero guess (FP32
-    #          inner cycle): read b, q; write u, b_c (N/4)                                 = 26
-    #          (nonzero guess: also read u: 34 FP32, 68 FP64)
-    #   post   interpolation + 2 fused sweeps: read u, b, q, e_c (N/4); write u          = 34 / 68
-    #   refine FP64 update + residual: read u, b, q (16 each), d (8); write u (16), r (8) = 80
-    # "pre" brackets two kernel symbols (the pass from zero, 26 B, and the
-    # pass from a nonzero guess, 34 B) and is reported, not ranked.
-    bpp_mixed = {"post": 34.0, "refine": 80.0}
-    bpp_plain = {"post": 68.0}
-    ffp = {"bf16x6": ffmg.FF_BF16X6, "bf16x3": ffmg.FF_BF16X3, "fp64": ffmg.FF_FP64}[args.ff_precision]
-    # both forms start from the full multigrid guess (FMG_K V-cycles per
-    # coarse level); the zero-start V-cycle solves are reported beside them
-    fk = 0 if args.zero_start else FMG_K
-    if args.tune_only:
-        # the tuning part of run_path fills the cache; two maps each
-        run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, 1, 1, bpp_mixed, fmg_cycles=fk)
-        run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, 1, 1, bpp_plain, fmg_cycles=fk)
-        return
-    ns = 1 if args.one_stream else max(args.lanes, 1)
-    pipe = ns > 1 and not args.blocking
-    # with several solves in flight the timed region runs without event brackets:
-    # the dominant kernel is timed in the one-solve pass below
-    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, bpp_mixed, fmg_cycles=fk,
-                     streams=ns, pipelined=pipe, time_kernel=(ns == 1))
-    plain = None if args.no_plain else run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2),
-                                                 args.warmup, bpp_plain, fmg_cycles=fk, streams=ns, pipelined=pipe,
-                                                 time_kernel=(ns == 1))
-    names = {"pre": "finest-level pre-smoothing: 2 FP32 Jacobi sweeps, residual and full weighting in one pass "
-                    "(k_smooth_rr2d<float,*,1,16>)",
-             "post": "finest-level interpolation + 2 fused FP32 Jacobi sweeps (k_smooth2d<float,2,false,true,1,%d>, "
-                     "the tuned tile height)" % (mixed["tune"]["smooth"] or {}).get("tile_rows", 8),
-             "refine": "FP64 update + residual of the refinement loop (k_refine2d)"}
-    # The dominant kernel's duration.  Its launches are timed by events the
-    # runtime stamps on the launch itself.  With several solves in flight those
-    # stamps also count the time a launch waits behind the other stream's
-    # workgroups, so the kernel is timed in the same maps with one solve in
-    # flight (one handle, one stream); the figure from the headline's own
-    # timed region is reported beside it.
-    iso = (run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, max(args.steps // 2, 2), args.warmup, bpp_mixed,
-                    fmg_cycles=fk, streams=1) if ns > 1 else mixed)
-    pr = iso["prof"]
-    dom = iso["dominant"]
-    avg_ms = iso["live"][0] / max(iso["live"][1], 1)
-    bytes_alg = bpp_mixed[dom] * N
-    achieved = bytes_alg / (avg_ms * 1e-3) / 1e9
-    roof = {"kernel": names[dom], "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom, (iso["tune"]["smooth"] or {}).get("tile_rows", 8)),
-            "bytes_per_launch": bytes_alg, "avg_launch_us": round(avg_ms * 1e3, 2), "launches": iso["live"][1],
-            "timed_in": "the same maps with one solve in flight (one handle, one stream), timed after the headline",
-            "warmup_GBs": {k: round(bpp_mixed[k] * N / (pr[k][0] / max(pr[k][1], 1) * 1e-3) / 1e9, 1)
-                           for k in bpp_mixed if pr[k][1] > 0}}
-
+    lanes = max(args.lanes, 1)
+    pipe = lanes > 1
+    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, lanes=lanes, pipelined=pipe)
+    # the dominant kernel and the finest-level kernel rates: one solve in flight
+    km = kernel_pass(ffmg, torch, w, ffmg.FP32_IR, ffp, 4, FMG_K, BPP[3]["mixed"])
+    dom = km["dominant"]
+    dk = km["kernels"][dom]
+    roof = {"kernel": KERNEL_NAMES[3][dom] % "float", "bound": "hbm", "achieved": dk["GB_s"], "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": dk["hbm_frac"], "traffic": measured_traffic(dom, "float", 3),
+            "bytes_per_launch": dk["bytes_per_launch"], "bytes_per_point": dk["bytes_per_point"],
+            "avg_launch_us": dk["avg_us"], "launches": dk["launches"],
+            "early_exit_launches_dropped": dk["early_exit_launches_dropped"],
+            "timed_in": "a one-solve-in-flight pass of the same maps after the headline: HIP events around every "
+                        "launch of the finest-level kernels the library brackets",
+            "ranked_by": "largest time per map among the bracketed finest-level kernels; "
+                         "profiles/kernels_gauss3d_512_mixed.md ranks every kernel of a map (rocprofv3)",
+            "working_set": "HBM-resident: one FP32 field is 1.07 GB, far above the 256 MB Infinity Cache"}
     line = {
         "metric": "far-field maps/sec at 1e-6 rel error: plain FP64 MG vs mixed-prec/learned MG",
         "value": round(mixed["maps_per_s"], 3),
@@ -803,95 +753,55 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"bumps_2d n={args.n} box=[-10,10]^2 k0=1 gamma=30deg 8 bumps seed=1",
-                   "unknowns": N, "angles": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
-                   "start": (f"full multigrid: {fk} V(2,2) per coarse level, then V-cycles on the finest grid"
-                             if fk else "u = 0"),
-                   "streams": (f"{ns}, pipelined: consecutive maps cycle through {ns} handles, each on its own "
-                               "stream; each map's solve is begun (mg_solve_begin) before the map begun "
-                               f"{ns - 1} steps earlier is finished (mg_solve_end) and its far field queued, so "
-                               f"{ns} solves are in flight from one host thread" if pipe else
-                               f"{ns}: consecutive maps cycle through {ns} handles on {ns} streams, one map's far "
-                               "field runs while the next map is solved" if ns > 1 else "1"),
+        "config": {"workload": f"gauss_3d n=512 box=[-6,6]^3 chi=0.5exp(-z.z/2) k0=1 gamma=30deg eta=+x, "
+                               f"128 azimuth x 64 polar directions",
+                   "unknowns": w.N, "directions": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
+                   "start": f"full multigrid: {FMG_K} V(2,2) per coarse level, then the finest-level iteration",
+                   "lanes": (f"{lanes} solves in flight from one host thread (one handle and stream each, "
+                             "mg_solve_begin / mg_solve_end)" if pipe else "1"),
                    "form": "FP32 V-cycles in FP64 refinement + "
                            + {"bf16x6": "split-BF16 (3 parts, 6 products) MFMA far field, FP32 accumulation",
                               "bf16x3": "split-BF16 (2 parts, 3 products) MFMA far field, FP32 accumulation",
-                              "fp64": "FP64 MFMA far field"}[args.ff_precision]},
-        "mixed": {"refinement_steps": mixed["cycles"], "vcycles": mixed["vcycles"], "rel_residual": mixed["rel_residual"],
-                  "conv_factor": round(mixed["conv_factor"], 4),
-                  "ff_ms_per_map": round(pr["ff"][0] / max(pr["ff"][1], 1), 3),
-                  "farfield_gemm": gemm_report(pr, w, args.ff_precision, mixed["tune"]["ff_gemm"]),
-                  "kernel_times_from": "warm-up maps of the one-solve pass",
-                  "smooth_tile": mixed["tune"]["smooth"], "smooth_tile_coarse": mixed["tune"]["smooth_coarse"],
-                  "pre_pass": mixed["tune"]["pre"],
-                  "lds_tail": mixed["tune"]["tail"]},
+                              "fp64": "FP64 MFMA far field"}[ffp_name]},
+        "mixed": {"refinement_steps": mixed["cycles"], "vcycles": mixed["vcycles"],
+                  "rel_residual": mixed["rel_residual"], "conv_factor": round(mixed["conv_factor"], 4),
+                  "tune": mixed["tune"], "kernels_one_solve": km["kernels"],
+                  "farfield_gemm": gemm_report(km["kernels"], w, ffp_name)},
         "roofline": roof,
     }
-    if plain is not None:
-        ef = float(np.linalg.norm(mixed["F"] - plain["F"]) / np.linalg.norm(plain["F"]))
-        pp = plain["prof"]
-        p_gbs = {k: round(b_ * N / (pp[k][0] / max(pp[k][1], 1) * 1e-3) / 1e9, 1)
-                 for k, b_ in bpp_plain.items() if pp[k][1] > 0}
+    if not args.no_plain:
+        plain = run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2), args.warmup, lanes=lanes,
+                         pipelined=pipe)
+        kp = kernel_pass(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, 2, FMG_K, BPP[3]["plain"])
         line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
-                              "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
-                              "finest_kernels_GBs": p_gbs, "smooth_tile": plain["tune"]["smooth"],
-                              "smooth_tile_coarse": plain["tune"]["smooth_coarse"],
-                              "pre_pass": plain["tune"]["pre"],
-                              "lds_tail": plain["tune"]["tail"],
-                              "ff_ms_per_map": round(pp["ff"][0] / max(pp["ff"][1], 1), 3),
-                              "farfield_gemm": gemm_report(pp, w, "fp64"),
-                              "kernel_times_from": ("warm-up maps with several solves in flight (intervals include "
-                                                    "waits behind the other stream)" if pipe else "warm-up maps")}
+                              "cycles": plain["cycles"], "rel_residual": plain["rel_residual"], "tune": plain["tune"],
+                              "kernels_one_solve": kp["kernels"], "farfield_gemm": gemm_report(kp["kernels"], w, "fp64")}
         line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
-        line["mixed_vs_plain_farfield_rel_err"] = ef
-    if not args.no_start_forms:
-        # the other starts of the same solve: u = 0 (plain V-cycles) and other
-        # numbers of V-cycles per coarse level in the full multigrid start
-        fm = {}
-        # (V-cycles per coarse level, lanes, pipelined); k = 0: u = 0
-        forms_m = [(0, 1, False), (1, ns, pipe), (3, ns, pipe), (fk, 1, False), (fk, 2, False), (fk, 2, True)]
-        forms_p = [(0, 1, False), (1, ns, pipe), (fk, 1, False), (fk, 2, False)]
-        for prec, ffp_k, forms, tag, bpp in ((ffmg.FP32_IR, ffp, forms_m, "mixed", bpp_mixed),
-                                              (ffmg.FP64, ffmg.FF_FP64, forms_p, "plain_fp64", bpp_plain)):
-            if tag == "plain_fp64" and plain is None:
-                continue
-            ref = mixed if tag == "mixed" else plain
-            for k, nsk, pk in forms:
-                if (k, nsk, pk) == (fk, ns, pipe) or (k == 0 and nsk != 1 and fk != 0):
-                    continue
-                if tag == "mixed" and (k, nsk, pk) == (fk, 1, False) and iso is not mixed:
-                    r = iso     # already timed for the roofline
-                else:
-                    r = run_path(ffmg, torch, w, prec, ffp_k, max(args.steps // 2, 2), args.warmup, bpp,
-                                 fmg_cycles=k, streams=nsk, pipelined=pk)
-                name = (f"{tag}_{'zero_start' if k == 0 else f'fmg_k{k}'}" + ("_one_stream" if nsk == 1 and k else "")
-                        + ("_blocking" if nsk > 1 and not pk else "") + (f"_{nsk}_lanes" if 1 < nsk != ns else ""))
-                fm[name] = {
-                    "maps_per_s": round(r["maps_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
-                    "cycles": r["cycles"], "vcycles_finest": r["vcycles"], "rel_residual": r["rel_residual"],
-                    "headline_speedup_over_this": round(ref["maps_per_s"] / r["maps_per_s"], 3),
-                    "farfield_rel_diff_vs_headline_form": float(np.linalg.norm(r["F"] - ref["F"])
-                                                                / np.linalg.norm(ref["F"]))}
-        line["start_forms"] = fm
-    if not args.no_concurrent:
-        # maps of several incoming directions in flight at once (host threads,
-        # one handle and stream each, one host thread per direction)
-        cc = {}
-        for nt in (2, 4):
-            cc[f"threads{nt}"] = run_concurrent(ffmg, torch, w, ffmg.FP32_IR, ffp, nt, max(args.steps // 2, 4), fk)
-        line["concurrent_maps"] = cc
+        line["mixed_vs_plain_farfield_rel_err"] = float(np.linalg.norm(mixed["F"] - plain["F"])
+                                                        / np.linalg.norm(plain["F"]))
+        # the plain iteration from u = 0, for the CPU baseline's zero-start estimate
+        h0 = ffmg.setup_workload(w, options=ffmg.default_options())[0]
+        b0 = ffmg.mg_rhs_plane_wave(h0, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+        u0 = torch.zeros_like(b0)
+        zero_cycles = ffmg.mg_solve(h0, b0, u0, tol=w.tol).cycles
+        h0.destroy()
+        del b0, u0
+        torch.cuda.empty_cache()
+        line["plain_fp64"]["cycles_zero_start"] = zero_cycles
+    if not args.no_stress:
+        line["stress_k0h_half"] = run_stress(ffmg, torch, W)
+    if not args.no_2d:
+        line["bumps_2d"] = run_bumps2d(ffmg, torch, W, 40, 3, 4, ffp_name)
     if not args.no_gmres:
-        line["gmres_smoother"] = run_gmres(ffmg, torch, W, args.n)
-    if not args.no_3d:
-        line["gauss_3d"] = run_3d(ffmg, torch, W)
+        line["gmres_smoother"] = run_gmres(ffmg, torch, W, 2048)
     if not args.no_batch:
-        line["batched"] = run_batched(ffmg, torch, W, max(args.steps // 4, 2))
+        line["batched"] = run_batched(ffmg, torch, W, 4)
     if not args.no_learned:
-        line["learned"] = run_learned(ffmg, torch, W, oracle_check=not args.no_cpu_baseline)
+        line["learned"] = run_learned(ffmg, torch, W)
     if not args.no_cpu_baseline:
-        cb, Fo = cpu_baseline(w)
-        line["cpu_baseline"] = {k: v for k, v in cb.items() if k != "seconds"}
-        line["farfield_rel_err_vs_oracle"] = float(np.linalg.norm(mixed["F"] - Fo) / np.linalg.norm(Fo))
+        pc = line.get("plain_fp64", {}).get("cycles", 14)
+        pz = line.get("plain_fp64", {}).get("cycles_zero_start", 21)
+        line["cpu_baseline"] = cpu_baseline(pc, pz)
     print(json.dumps(line))
 
 

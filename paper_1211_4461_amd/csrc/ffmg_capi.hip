@@ -228,7 +228,7 @@ void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
     const bool finest = (&lv == &h->L[0]);
     const Stencil<T> &P = LP::P(lv);
     const cx<T> *q = LP::q(lv);
-    const bool pairs = (h->sweep3d_variant == 0);
+    const bool pairs = (h->sweep3d_variant != 1), rows2 = (h->sweep3d_variant == 2);
     // sweeps done by launch kk of the chain
     auto sweeps_of = [&](int kk, int left) { return ((kk == 0 && zero) || pairs) ? std::min(2, left) : 1; };
     int nk = 0;
@@ -243,13 +243,13 @@ void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
         const cx<T> *e = (kk == 0) ? ec : nullptr;
         const int pi = finest ? prof_begin(h, prof_id) : -1;
         if (kk == 0 && zero && ns == 2 && pairs)
-            launch_sweep2_3d<T>(lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop, true);
+            launch_sweep2_3d<T>(lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop, true, rows2);
         else if (kk == 0 && zero && ns == 2)
             launch_sweep3d_fused<T>(true, lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop);
         else if (kk == 0 && zero)
             launch_stencil<T>(MODE_JACOBI0, lv.g, P, cur, b, q, o, nullptr, h->stream, finest, stop);
         else if (ns == 2)
-            launch_sweep2_3d<T>(lv.g, P, cur, e, b, q, o, h->stream, finest, stop);
+            launch_sweep2_3d<T>(lv.g, P, cur, e, b, q, o, h->stream, finest, stop, false, rows2);
         else if (e)
             launch_sweep3d_fused<T>(false, lv.g, P, cur, e, b, q, o, h->stream, finest, stop);
         else
@@ -608,9 +608,9 @@ void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *st
         prof_kernel_end(h, PROF_REFINE, pi);
         launch_ctl_update(h->d_ctl, h->d_parts, fused2d_blocks(l0.g), h->stream);
     } else if (l0.g.dim == 3 && h->opt.tile_config != TILE_REFERENCE) {
-        int pi = prof_kernel_begin(h, PROF_REFINE);
+        int pi = prof_begin(h, PROF_REFINE);
         launch_refine3d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
-        prof_kernel_end(h, PROF_REFINE, pi);
+        prof_end(h, PROF_REFINE, pi);
         launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
     } else {
         launch_refine_update(l0.u32, ucur, h->d_ctl, l0.g.N(), h->stream, stop);
@@ -1516,7 +1516,7 @@ int mg_tune_variants(const ffmg_handle *h, int tunable)
     case FFMG_TUNE_PRE: return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? 3 : 1;
     case FFMG_TUNE_SMOOTH_COARSE:
         return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
-    case FFMG_TUNE_SWEEP3D: return (h->prob.dim == 3 && h->opt.tile_config != TILE_REFERENCE) ? 2 : 1;
+    case FFMG_TUNE_SWEEP3D: return (h->prob.dim == 3 && h->opt.tile_config != TILE_REFERENCE) ? 3 : 1;
     default: return 0;
     }
 }

@@ -182,7 +182,8 @@ void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, 
 // two Jacobi sweeps in one 3D pass from u (ec: from u + P ec; zero: from a zero guess, u not read)
 template <typename T>
 void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
-                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero = false);
+                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero = false,
+                      bool other_rows = false);
 void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
                          cf *r32, double inv_scale, double *partial, hipStream_t s);
 void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,

@@ -832,14 +832,15 @@ void launch_sweep3d_fused(bool zero2, const LevelGeom &g, const Stencil<T> &P, c
     }
 }
 // Output rows per block of the fused two-sweep 3D kernel (its LDS and
-// registers grow with the tile: 4 rows in FP64).
-template <typename T> constexpr int sweep2_rows() { return sizeof(T) == 4 ? 8 : 4; }
+// registers grow with the tile): the default per type, or the other
+// (FFMG_TUNE_SWEEP3D variant 2).
+template <typename T> constexpr int sweep2_rows(bool other) { return sizeof(T) == 4 ? (other ? 16 : 8) : (other ? 8 : 4); }
 
-template <typename T>
-void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
-                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero)
+template <typename T, int TY>
+static void launch_sweep2_3d_rows(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec,
+                                  const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
+                                  const int *stop, bool zero)
 {
-    constexpr int TY = sweep2_rows<T>();
     const int tx = (g.m[0] + 63) / 64, ty = (g.m[1] + TY - 1) / TY;
     const int tz = planes_per_block((long)tx * ty, g.m[2], TZ3);
     const int nb = tx * ty * ((g.m[2] + tz - 1) / tz);
@@ -867,10 +868,21 @@ void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, c
                                ty, tz, stop);
     }
 }
+
+template <typename T>
+void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
+                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero,
+                      bool other_rows)
+{
+    if (other_rows)
+        launch_sweep2_3d_rows<T, sweep2_rows<T>(true)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
+    else
+        launch_sweep2_3d_rows<T, sweep2_rows<T>(false)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
+}
 template void launch_sweep2_3d<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *, const cd *,
-                                       const cd *, cd *, hipStream_t, bool, const int *, bool);
+                                       const cd *, cd *, hipStream_t, bool, const int *, bool, bool);
 template void launch_sweep2_3d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *, const cf *,
-                                      const cf *, cf *, hipStream_t, bool, const int *, bool);
+                                      const cf *, cf *, hipStream_t, bool, const int *, bool, bool);
 
 void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,

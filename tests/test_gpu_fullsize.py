@@ -77,12 +77,16 @@ def test_bumps_2048_mixed_map(ff, orc):
 
 
 def test_bumps_2048_pipelined_headline_configuration(ff, orc):
-    """The benchmark's launch configuration: full multigrid start, four
-    handles on four streams, each map begun before the map three steps
-    earlier is finished.  Every map equals, bit for bit, the same map solved
-    alone with mg_solve; the last solution meets the tolerance under the
-    oracle's operator and its map matches the oracle's quadrature of it."""
+    """The pipelined launch configuration of the 2D workload: full multigrid
+    start, four handles on four streams, each map begun before the map three
+    steps earlier is finished, and every map with an incoming direction of its
+    own (four directions).  Every map equals, bit for bit, the map of its
+    direction solved alone with mg_solve (so no lane reads another lane's
+    buffers); the last solution meets the tolerance under the oracle's
+    operator and its map matches the oracle's quadrature of it."""
+    import math
     w = W.bumps_2d()
+    etas = [np.array([math.cos(a), math.sin(a)]) for a in (0.0, 0.5 * math.pi, 0.25 * math.pi, math.pi)]
     opts = dict(precision=ff.FP32_IR, ff_precision=ff.FF_BF16X6, fmg_cycles=2)
     lanes = []
     for _ in range(4):
@@ -93,35 +97,41 @@ def test_bumps_2048_pipelined_headline_configuration(ff, orc):
             u = torch.empty_like(b)
             F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
         lanes.append((h, b, u, F))
-    # one map alone
+    # each direction alone (on lane 0)
     h, b, u, F = lanes[0]
-    ff.mg_rhs_plane_wave(h, w.eta, b)
-    info0 = ff.mg_solve(h, b, u, tol=w.tol)
-    ff.farfield_map(h, w.eta, u, w.dirs, out=F)
-    torch.cuda.synchronize()
-    assert info0.status == 0
-    F0, u0 = F.clone(), u.clone()
-    # eight maps, four in flight
-    pend, infos, maps = [], [], []
+    solo = []
+    for e in etas:
+        ff.mg_rhs_plane_wave(h, e, b)
+        inf = ff.mg_solve(h, b, u, tol=w.tol)
+        ff.farfield_map(h, e, u, w.dirs, out=F)
+        torch.cuda.synchronize()
+        assert inf.status == 0
+        solo.append((inf, F.clone(), u.clone()))
+    # eight maps, four in flight, map k along etas[(k + 1) % 4] (a lane never repeats its last direction)
+    pend, done = [], []
     for k in range(8):
         ln = lanes[k % 4]
-        ff.mg_rhs_plane_wave(ln[0], w.eta, ln[1])
+        d = (k + 1) % 4
+        ff.mg_rhs_plane_wave(ln[0], etas[d], ln[1])
         ff.mg_solve_begin(ln[0], ln[1], ln[2], tol=w.tol)
-        pend.append(ln)
+        pend.append((ln, d))
         if len(pend) == 4 or k == 7:
             while pend and (len(pend) == 4 or k == 7):
-                o = pend.pop(0)
-                infos.append(ff.mg_solve_end(o[0]))
-                ff.farfield_map(o[0], w.eta, o[2], w.dirs, out=o[3])
+                o, do = pend.pop(0)
+                inf = ff.mg_solve_end(o[0])
+                ff.farfield_map(o[0], etas[do], o[2], w.dirs, out=o[3])
                 torch.cuda.synchronize()
-                maps.append((o[3].clone(), o[2].clone()))
-    assert len(maps) == 8
-    for i, (inf, (Fk, uk)) in enumerate(zip(infos, maps)):
-        assert inf.status == 0 and (inf.cycles, inf.rel_residual) == (info0.cycles, info0.rel_residual), i
-        assert torch.equal(Fk, F0) and torch.equal(uk, u0), i
-    g, kappa, q, k0, bo, ug = check_solution(orc, w, lanes[3][1], maps[-1][1], infos[-1], w.tol)
+                done.append((do, inf, o[3].clone(), o[2].clone(), o[1].clone()))
+    assert len(done) == 8
+    for i, (d, inf, Fk, uk, bk) in enumerate(done):
+        s_inf, s_F, s_u = solo[d]
+        assert inf.status == 0 and (inf.cycles, inf.rel_residual) == (s_inf.cycles, s_inf.rel_residual), i
+        assert torch.equal(Fk, s_F) and torch.equal(uk, s_u), i
+    d, inf, Fk, uk, bk = done[-1]
+    w.eta = etas[d]
+    g, kappa, q, k0, bo, ug = check_solution(orc, w, bk, uk, inf, w.tol)
     Fu = orc.farfield(g, w.gamma, k0, q, w.eta, ug, w.dirs)
-    assert relerr(maps[-1][0].cpu().numpy(), Fu) < 1e-6
+    assert relerr(Fk.cpu().numpy(), Fu) < 1e-6
     for ln in lanes:
         ln[0].destroy()
 

@@ -325,9 +325,9 @@ def test_fused_3d_path_is_bitwise_identical(ff, orc, n):
         ur = torch.zeros_like(b)
         for _ in range(2):
             ff.mg_vcycle(hr, b, ur)
-        for v in range(2):
+        for v in range(3):
             hf, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2)
-            assert ff.mg_tune_variants(hf, ff.TUNE_SWEEP3D) == 2
+            assert ff.mg_tune_variants(hf, ff.TUNE_SWEEP3D) == 3
             ff.mg_tune_set(hf, v, ff.TUNE_SWEEP3D)
             uf = torch.zeros_like(b)
             for _ in range(2):
@@ -338,7 +338,7 @@ def test_fused_3d_path_is_bitwise_identical(ff, orc, n):
         hr, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, tile_config=1, fmg_cycles=fk)
         ur = torch.zeros_like(b)
         i2 = ff.mg_solve(hr, b, ur)
-        for v in range(2):
+        for v in range(3):
             hf, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, fmg_cycles=fk)
             ff.mg_tune_set(hf, v, ff.TUNE_SWEEP3D)
             for rep in range(2):          # the second solve starts from the other buffer when the count is odd
