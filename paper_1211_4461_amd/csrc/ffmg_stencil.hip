@@ -165,12 +165,50 @@ __device__ __forceinline__ T iw(int f, int C)
     return d == 0 ? T(1) : ((d == 1 || d == -1) ? T(0.5) : T(0));
 }
 
+// Trilinear weights of a fine node along one axis (1-based fine index f):
+// the lower coarse node (f >> 1) - 1 (0-based) and the next one take 1 and 0
+// (f even: the fine node lies on the coarse one) or 1/2 and 1/2 (f odd).
+template <typename T>
+__device__ __forceinline__ void lin_w(int f, T (&w)[2])
+{
+    w[0] = (f & 1) ? T(0.5) : T(1);
+    w[1] = (f & 1) ? T(0.5) : T(0);
+}
+
+// The 3D interpolation in the order every 3D kernel uses (so that the fused
+// and the one-operation paths agree bit for bit): at each of the four coarse
+// (x, y) neighbours the two coarse planes are combined first,
+//   ez = wz0 c(az) + wz1 c(az + 1),
+// then acc = sum over (y, x) neighbours of (wx wy) ez, y outer, from zero;
+// every term is formed, coarse values outside the grid being zero.
+template <typename T>
+__device__ __forceinline__ cx<T> zpair(T w0, cx<T> c0, T w1, cx<T> c1)
+{
+    return w0 * c0 + w1 * c1;
+}
+
 // (P e_c) at fine interior point (ix, iy, iz) (0-based).
 template <typename T, int DIM>
 __device__ __forceinline__ cx<T> prolong_at(const cx<T> *__restrict__ ec, int ix, int iy, int iz, int mxc, int myc,
                                             int mzc)
 {
     int fx = ix + 1, fy = iy + 1, fz = iz + 1;
+    if constexpr (DIM == 3) {
+        T wx[2], wy[2], wz[2];
+        lin_w(fx, wx);
+        lin_w(fy, wy);
+        lin_w(fz, wz);
+        const int ax = (fx >> 1) - 1, ay = (fy >> 1) - 1, az = (fz >> 1) - 1;
+        auto c = [&](int x, int y, int z) -> cx<T> {
+            const bool in = x >= 0 && y >= 0 && z >= 0 && x < mxc && y < myc && z < mzc;
+            return in ? ec[((size_t)z * myc + y) * mxc + x] : cx<T>{T(0), T(0)};
+        };
+        cx<T> acc = {T(0), T(0)};
+        for (int jy = 0; jy < 2; ++jy)
+            for (int jx = 0; jx < 2; ++jx)
+                acc = acc + (wx[jx] * wy[jy]) * zpair(wz[0], c(ax + jx, ay + jy, az), wz[1], c(ax + jx, ay + jy, az + 1));
+        return acc;
+    }
     cx<T> acc = {T(0), T(0)};
     int zlo = (DIM == 3) ? fz / 2 : 1, zhi = (DIM == 3) ? (fz + 1) / 2 : 1;
     for (int Cz = zlo; Cz <= zhi; ++Cz)
@@ -272,21 +310,22 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
             cs[a & (NCS - 1)][yy][xx] = ld_masked(ec, ((size_t)a * myc + ay) * mxc + ax, in);
         }
     };
-    // (P e_c) at fine point (x, y, z) from the staged coarse planes
+    // (P e_c) at fine point (x, y, z) from the staged coarse planes (the
+    // order of prolong_at<T, 3>)
     auto interp = [&](int x, int y, int z) -> cx<T> {
         const int fx = x + 1, fy = y + 1, fz = z + 1;
         const int ex = (fx >> 1) - 1 - cx0, ey = (fy >> 1) - 1 - cy0, az = (fz >> 1) - 1;
-        const T wx[2] = {(fx & 1) ? T(0.5) : T(1), (fx & 1) ? T(0.5) : T(0)};
-        const T wy[2] = {(fy & 1) ? T(0.5) : T(1), (fy & 1) ? T(0.5) : T(0)};
-        const T wz[2] = {(fz & 1) ? T(0.5) : T(1), (fz & 1) ? T(0.5) : T(0)};
+        T wx[2], wy[2], wz[2];
+        lin_w(fx, wx);
+        lin_w(fy, wy);
+        lin_w(fz, wz);
+        const int s0 = az & (NCS - 1), s1 = (az + 1) & (NCS - 1);
         cx<T> acc = {T(0), T(0)};
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+        for (int jy = 0; jy < 2; ++jy)
 #pragma unroll
-            for (int jy = 0; jy < 2; ++jy)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix)
-                    acc = acc + ((wx[ix] * wy[jy]) * wz[k]) * cs[(az + k) & (NCS - 1)][ey + jy][ex + ix];
+            for (int jx = 0; jx < 2; ++jx)
+                acc = acc + (wx[jx] * wy[jy]) * zpair(wz[0], cs[s0][ey + jy][ex + jx], wz[1], cs[s1][ey + jy][ex + jx]);
         return acc;
     };
 
@@ -512,6 +551,9 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
     constexpr int NCL = PROL ? (CH * CW + 255) / 256 : 1;   // coarse values per thread and plane
     __shared__ cx<T> L0[ZERO ? 1 : 2][ZERO ? 1 : NP], L1[2][NP];
     __shared__ cx<T> cs[NCS][PROL ? CH : 1][PROL ? CW : 1];
+    // the coarse correction combined in z for a fine plane (the first step of
+    // the interpolation), double-buffered by the fine plane's parity
+    __shared__ cx<T> ezs[PROL ? 2 : 1][PROL ? CH * CW : 1];
     const int mx = P.mx, my = P.my, mz = P.mz;
     const int mxc = (mx - 1) / 2, myc = (my - 1) / 2, mzc = (mz - 1) / 2;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -572,20 +614,39 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
             if (t < CH * CW) dst[t] = creg[i];
         }
     };
-    auto interp = [&](int x, int y, int z) -> cx<T> {
-        const int fx = x + 1, fy = y + 1, fz = z + 1;
-        const int ex = (fx >> 1) - 1 - cx0, ey = (fy >> 1) - 1 - cy0, az = (fz >> 1) - 1;
-        const T wx[2] = {(fx & 1) ? T(0.5) : T(1), (fx & 1) ? T(0.5) : T(0)};
-        const T wy[2] = {(fy & 1) ? T(0.5) : T(1), (fy & 1) ? T(0.5) : T(0)};
-        const T wz[2] = {(fz & 1) ? T(0.5) : T(1), (fz & 1) ? T(0.5) : T(0)};
+    // the z step of the interpolation for fine plane z: ezs = wz0 c(az) + wz1 c(az + 1)
+    auto combine_z = [&](int z) {
+        T wz[2];
+        lin_w(z + 1, wz);
+        const int az = ((z + 1) >> 1) - 1;
+        const cx<T> *c0 = &cs[az & (NCS - 1)][0][0], *c1 = &cs[(az + 1) & (NCS - 1)][0][0];
+        cx<T> *dst = ezs[z & 1];
+        for (int t = threadIdx.x; t < CH * CW; t += 256) dst[t] = zpair(wz[0], c0[t], wz[1], c1[t]);
+    };
+    // the x/y step at slot k: sum over (y, x) neighbours of (wx wy) ez, y outer
+    int eoff[NS];        // LDS offset of the slot's lower coarse (x, y) neighbour in ezs
+    T wxy[NS][4];        // (wx wy) for (jy, jx) = (0,0), (0,1), (1,0), (1,1)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        const int r = t / W, c = t - r * W;
+        const int fx = x0 - 2 + c + 1, fy = y0 - 2 + r + 1;
+        T wx[2], wy[2];
+        lin_w(fx, wx);
+        lin_w(fy, wy);
+        eoff[k] = (t < NP) ? ((fy >> 1) - 1 - cy0) * CW + ((fx >> 1) - 1 - cx0) : 0;
+        wxy[k][0] = wx[0] * wy[0];
+        wxy[k][1] = wx[1] * wy[0];
+        wxy[k][2] = wx[0] * wy[1];
+        wxy[k][3] = wx[1] * wy[1];
+    }
+    auto interp_xy = [&](int k, const cx<T> *ez) -> cx<T> {
+        const cx<T> *e = ez + eoff[k];
         cx<T> acc = {T(0), T(0)};
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int jy = 0; jy < 2; ++jy)
-#pragma unroll
-                for (int ix = 0; ix < 2; ++ix)
-                    acc = acc + ((wx[ix] * wy[jy]) * wz[k]) * cs[(az + k) & (NCS - 1)][ey + jy][ex + ix];
+        acc = acc + wxy[k][0] * e[0];
+        acc = acc + wxy[k][1] * e[1];
+        acc = acc + wxy[k][2] * e[CW];
+        acc = acc + wxy[k][3] * e[CW + 1];
         return acc;
     };
     // global loads of one plane: u (stage 0) and b, q (stage 1)
@@ -607,17 +668,22 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
         }
     };
 
-    // prologue: coarse planes of the first two stage-0 planes in LDS, the
-    // next one in registers; u of plane z0 - 2 and b, q of plane z0 - 1
+    // prologue: the coarse planes of the first three stage-0 planes in LDS
+    // and the z step of the first; u of plane z0 - 2.  In the loop, the coarse
+    // plane the z step will need two planes later is fetched into registers,
+    // stored into the ring the next iteration and combined (at the end of
+    // an iteration, for the next stage-0 plane) after a barrier.
     int a_reg = 0;
     bool c_pending = false;
     if (PROL) {
         const int Alo = ((z0 - 1) >> 1) - 1;
-        for (int a = Alo; a <= (z0 >> 1); ++a) {
+        for (int a = Alo; a <= ((z0 + 1) >> 1); ++a) {
             fetch_coarse(a);
             store_coarse(a);
         }
-        a_reg = z0 >> 1;
+        a_reg = (z0 + 1) >> 1;
+        lds_barrier();
+        combine_z(z0 - 2);
         lds_barrier();
     }
 #pragma unroll
@@ -644,11 +710,11 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
             qn[k] = pq[k];
         }
         if (PROL) {
-            if (c_pending) {   // fetched last iteration; read from the next iteration on
+            if (c_pending) {   // fetched last iteration; combined from the next iteration on
                 store_coarse(a_reg);
                 c_pending = false;
             }
-            if (((z + 3) >> 1) > a_reg) {
+            if (((z + 4) >> 1) > a_reg) {
                 fetch_coarse(++a_reg);
                 c_pending = true;
             }
@@ -664,10 +730,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
             for (int k = 0; k < NS; ++k) {
                 const int t = threadIdx.x + 256 * k;
                 cx<T> v = un[k];
-                if (PROL && zin && slot_in(ing, k)) {
-                    const int r = t / W, c = t - r * W;
-                    v = v + interp(x0 - 2 + c, y0 - 2 + r, z);
-                }
+                if (PROL && zin && slot_in(ing, k)) v = v + interp_xy(k, ezs[z & 1]);
                 a0[k] = a1[k];
                 a1[k] = a2[k];
                 a2[k] = v;
@@ -723,6 +786,8 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
                 wB[k] = wn[k];
             }
         }
+        // the z step of the next stage-0 plane (its coarse planes have passed a barrier)
+        if (PROL && z + 1 <= z1 + 1) combine_z(z + 1);
         lds_barrier();
     }
 }
