@@ -76,7 +76,10 @@ typedef struct ffmg_problem {
     double gamma;         /* contour angle (rad), 0 < gamma < pi/2 (Sec. 3.3)  */
     int kind;             /* ffmg_kind                                         */
     double k0;            /* Helmholtz: outer wavenumber (> 0); Schroedinger: ignored */
-    double energy;        /* Schroedinger: E > 0 (k0 = sqrt(2E)); Helmholtz: ignored  */
+    double energy;        /* Schroedinger: total energy E, any finite value;
+                             k0 = sqrt(2E) for E > 0 (the plane-wave right-
+                             hand sides, far field and batch need E > 0);
+                             Helmholtz: ignored                             */
     const void *coef;     /* DEVICE complex128[N], x fastest:
                              Helmholtz: contrast k^2(z_j) - k0^2 = k0^2 chi(z_j);
                              Schroedinger: V(z_j).  Copied at setup; the caller
@@ -221,6 +224,68 @@ ffmg_status mg_solve_end(ffmg_handle *h, ffmg_solve_info *info);
  * while it builds the plan. */
 ffmg_status farfield_map(ffmg_handle *h, const double eta[3], const void *u, int n_dirs,
                          const double *dirs, void *F);
+
+/* ---- Ionisation observables of the 2D radial partial-wave Schroedinger
+ * model (Sec. 5.1-5.4; eq. partialwave2d solved on the contour grid of a
+ * handle of kind FFMG_SCHRODINGER with lo = 0 on both axes, whose Dirichlet
+ * boundary is the condition u = 0 at x = 0 and y = 0).  1D arrays along an
+ * axis are DEVICE complex128[n[axis] - 1] at the interior contour nodes
+ * z_i = lo + i h e^{i gamma}; h~ = h e^{i gamma}. */
+
+/* Source right-hand side of (-1/2 Lap + V - E) u = phi: the library solves
+ * the Helmholtz form (-Lap - 2(E - V)) u = 2 phi (Sec. 5, introduction), so
+ * b = 2 src for FFMG_SCHRODINGER and b = src for FFMG_HELMHOLTZ.  src, b:
+ * DEVICE complex128[N] (may alias).  Queued on the handle's stream. */
+ffmg_status mg_rhs_source(ffmg_handle *h, const void *src, void *b);
+
+/* eq. boundstate on axis `axis`: the eigenpair of the rotated 1D Hamiltonian
+ * -1/2 e^{-2i gamma} D2/h^2 + diag(v) (Sec. 5.2) nearest to the real `shift`,
+ * by inverse iteration and Rayleigh-quotient shifts.  v: the one-body
+ * potential at the axis nodes.  Outputs lambda (HOST double[2], re/im) and
+ * phi (DEVICE complex128[m]) normalised by sum phi^2 h~ = 1 (the contour
+ * continuation of int phi^2 dx = 1), sign with Re phi_1 > 0.  ENOCONV when
+ * the iteration does not converge in 60 steps.  Synchronises. */
+ffmg_status ion_bound_state(ffmg_handle *h, int axis, const void *v, double shift, double lambda[2], void *phi);
+
+/* Channel wavenumbers at total energy E (HOST arrays): *kn = sqrt(2(E - Re
+ * lambda)) for the single-ionisation channel of the bound state lambda (0 if
+ * E <= Re lambda: closed); for E > 0 the M midpoint nodes of the
+ * double-ionisation integral over eps in [0, E] (eq. double-ionization):
+ * k1 = sqrt(2 eps_i), k2 = sqrt(2(E - eps_i)), eps_i = (i + 1/2) E / M, and
+ * weights w = E/M (all zero for E <= 0).  Host arithmetic, no handle. */
+ffmg_status ion_wavenumbers(double energy, const double lambda[2], int M, double *kn, double *k1, double *k2,
+                            double *w);
+
+/* eq. testfunction on axis `axis` for the M wavenumbers k (HOST double[M],
+ * > 0): the regular solution of (-1/2 d^2/dz^2 + v - k^2/2) phi = 0 with
+ * phi = 0 at the axis' lower end, by the recurrence of the rotated
+ * three-point stencil, normalised to free-wave amplitude 1/sqrt(k): at the
+ * first node r past the last one with |v| > 1e-13, A^2 = (p_r^2 + p_{r+1}^2
+ * - 2c p_r p_{r+1})/(1 - c^2), c = 1 - h~^2 k^2/2, is the squared amplitude
+ * of the free recurrence, and phi = p/(A sqrt k) with Re A > 0.
+ * out: DEVICE complex128[M][m] (row per wavenumber).  EINVAL if v does not
+ * die out before the last two nodes.  Synchronises. */
+ffmg_status ion_test_functions(ffmg_handle *h, int axis, const void *v, int M, const double *k, void *out);
+
+/* eq. single-ionization / eq. double-ionization on the contour (2D):
+ *   amp_m = h~x h~y sum_{y,x} tx[m][x] ty[m][y] (src - v12 u)[y][x]
+ * for M pairs of DEVICE tables tx (complex128[M][nx-1]) and ty
+ * (complex128[M][ny-1]), and the optical-theorem product
+ *   opt = h~x h~y sum src u
+ * (src: the source phi, v12: the two-body potential, u: the solution; DEVICE
+ * complex128[N]).  The y contraction runs on the FP64 MFMA GEMM of the far
+ * field.  amp: HOST complex128[M]; opt: HOST double[2].  Synchronises. */
+ffmg_status ion_amplitudes(ffmg_handle *h, const void *src, const void *v12, const void *u, int M, const void *tx,
+                           const void *ty, double *amp, double opt[2]);
+
+/* Cross sections (Fig. single_and_double) from the amplitudes, as half the
+ * outgoing probability flux of each kind of channel (the scale of the
+ * printed points): sigma[0] = 4 |s0|^2 (single; 0 if !open_single),
+ * sigma[1] = (4/pi) sum_i w_i |f_i|^2 (double), sigma[2] = Im opt (total,
+ * the optical theorem).  s0: HOST double[2]; f: HOST complex128[M]; w: the
+ * weights of ion_wavenumbers.  Host arithmetic, no handle. */
+ffmg_status ion_cross_sections(int open_single, const double s0[2], int M, const double *f, const double *w,
+                               const double opt[2], double sigma[3]);
 
 /* Far-field map that allocates nothing, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops,

@@ -269,8 +269,8 @@ class Multigrid:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            lib().or_mg_destroy(h)
+        if h and _lib is not None:
+            _lib.or_mg_destroy(h)
             self._h = None
 
     def kappa_level(self, l):

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libffmg.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 SOURCES = ["ffmg_stencil.hip", "ffmg_fused2d.hip", "ffmg_farfield.hip", "ffmg_capi.hip", "ffmg_batch.hip", "ffmg_learned.hip",
-           "ffmg_krylov.hip", "ffmg_rbgs.hip"]
+           "ffmg_krylov.hip", "ffmg_rbgs.hip", "ffmg_ion.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

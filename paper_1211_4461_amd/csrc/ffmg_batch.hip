@@ -493,6 +493,7 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
     Batch &B = *h0->batch;
     for (int i = 0; i < count; ++i) {
         ffmg_handle *h = hs[i];
+        if (!(h->k0 > 0.0)) return fail(h0, FFMG_EINVAL, "instance %d: a plane wave needs E > 0", i);
         if (exponent_budget(h) > 700.0)
             return fail(h0, FFMG_ERANGE, "instance %d: exp(i k0 eta.z) overflows double on this box", i);
         BatchInst &I = B.inst[i];

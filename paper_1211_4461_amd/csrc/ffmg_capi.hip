@@ -355,8 +355,7 @@ ffmg_status validate_problem(const ffmg_problem *p, const ffmg_options *o, ffmg_
     if (p->kind == FFMG_HELMHOLTZ) {
         if (!(p->k0 > 0.0) || !isfinite(p->k0)) return fail(tmp, FFMG_EINVAL, "k0 must be positive");
     } else if (p->kind == FFMG_SCHRODINGER) {
-        if (!(p->energy > 0.0) || !isfinite(p->energy))
-            return fail(tmp, FFMG_EINVAL, "energy must be positive (scattering regime)");
+        if (!isfinite(p->energy)) return fail(tmp, FFMG_EINVAL, "energy must be finite");
     } else {
         return fail(tmp, FFMG_EINVAL, "unknown problem kind %d", p->kind);
     }
@@ -575,7 +574,9 @@ ffmg_status setup_impl(ffmg_handle *h)
     Level &lc = h->L.back();
     TRY(dalloc(h, &h->aug, (size_t)h->nc * 2 * h->nc * sizeof(cd)));
     launch_build_coarse(lc.g, lc.P64, lc.q, h->aug, h->stream);
-    launch_gauss_jordan(h->aug, h->nc, h->d_info, h->stream);
+    cd *fcol = nullptr;
+    if (h->nc > GJ_ONE_BLOCK_MAX) TRY(dalloc(h, &fcol, (size_t)h->nc * sizeof(cd)));
+    launch_gauss_jordan(h->aug, h->nc, h->d_info, h->stream, fcol);
     HIPCHK(h, hipGetLastError());
     int info = 0;
     HIPCHK(h, hipMemcpyAsync(&info, h->d_info, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -916,8 +917,10 @@ ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle *
         h->opt = *o;
         h->stream = (hipStream_t)o->stream;
         if (p->kind == FFMG_SCHRODINGER) {
+            // kappa = 2(E - V) = k02 + q for any E; k0 (the incoming plane
+            // wave's wavenumber) exists only above the breakup threshold
             h->k02 = 2.0 * p->energy;
-            h->k0 = sqrt(h->k02);
+            h->k0 = (p->energy > 0.0) ? sqrt(h->k02) : 0.0;
         } else {
             h->k0 = p->k0;
             h->k02 = p->k0 * p->k0;
@@ -990,6 +993,8 @@ void mg_destroy(ffmg_handle *h)
     if (h->ff) ff_plan_destroy(h->ff);
     if (h->batch) batch_destroy(h->batch);
     for (void *p : h->allocs) (void)hipFree(p);
+    for (void *p : h->ion_buf)
+        if (p) (void)hipFree(p);
     if (h->h_scalar) (void)hipHostFree(h->h_scalar);
     if (h->h_ctl) (void)hipHostFree(h->h_ctl);
     delete h;
@@ -1008,6 +1013,7 @@ ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b)
 {
     NOT_PENDING(h);
     if (!h || !eta || !b) return fail(h, FFMG_EINVAL, "null argument");
+    if (!(h->k0 > 0.0)) return fail(h, FFMG_EINVAL, "a plane wave needs E > 0");
     double e[3] = {0, 0, 0};
     for (int k = 0; k < h->prob.dim; ++k) e[k] = eta[k];
     if (exponent_budget(h) > 700.0) return fail(h, FFMG_ERANGE, "exp(i k0 eta.z) overflows double on this box");
@@ -1020,6 +1026,7 @@ ffmg_status mg_rhs_phase(ffmg_handle *h, const double eta[3], void *b)
 {
     NOT_PENDING(h);
     if (!h || !eta || !b) return fail(h, FFMG_EINVAL, "null argument");
+    if (!(h->k0 > 0.0)) return fail(h, FFMG_EINVAL, "a plane wave needs E > 0");
     double e[3] = {0, 0, 0};
     for (int k = 0; k < h->prob.dim; ++k) e[k] = eta[k];
     launch_rhs_phase(h->L[0].g, h->prob.gamma, h->k0, e, h->L[0].q, (cd *)b, h->stream);
@@ -1354,6 +1361,7 @@ ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_
 static ffmg_status ff_check_args(ffmg_handle *h, const double eta[3], int n_dirs, const double *dirs, int ff_prec)
 {
     if (!h || !eta || !dirs || n_dirs < 1) return fail(h, FFMG_EINVAL, "null argument or n_dirs < 1");
+    if (!(h->k0 > 0.0)) return fail(h, FFMG_EINVAL, "the far field needs an incoming plane wave (E > 0)");
     const int d = h->prob.dim;
     for (int i = 0; i < n_dirs; ++i) {
         double s = 0.0;

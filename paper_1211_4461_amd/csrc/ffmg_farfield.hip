@@ -1065,4 +1065,59 @@ void launch_axis_exp(cd *out, int m, double lo, double h, double cr, double ci, 
     hipLaunchKernelGGL(k_axis_exp, dim3(ceil_div(m, 256)), dim3(256), 0, s, out, m, lo, h, cr, ci);
 }
 
+// ---------------------------------------------------------------------------
+// The same FP64 MFMA contraction for a caller's factor table instead of the
+// plane-wave exponentials (the test-function integrals of the ionisation
+// amplitudes): C[m][n] = sum_k A[m][k] S[k][n].  A is packed into the A'
+// layout of k_ff_gemm_f64 (Re / Im rows per tile_row_map), the group
+// descriptor is written on the device, and one launch runs the GEMM.
+__global__ __launch_bounds__(256) void k_pack_table(double *__restrict__ out, const cd *__restrict__ A, int M, int K,
+                                                    int rtiles, int ksteps)
+{
+    size_t tot = (size_t)rtiles * ksteps * 64;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (size_t)gridDim.x * 256) {
+        int l = (int)(e % 64);
+        size_t t = e / 64;
+        int ks = (int)(t % ksteps), rt = (int)(t / ksteps);
+        int mloc, c;
+        tile_row_map(l % 16, mloc, c);
+        int m = 8 * rt + mloc, k = 4 * ks + l / 16;
+        double v = 0.0;
+        if (m < M && k < K) {
+            cd a = A[(size_t)m * K + k];
+            v = c ? a.im : a.re;
+        }
+        out[e] = v;
+    }
+}
+
+__global__ void k_set_group(GemmGroup *g, const double *A, const double *S, cd *C, int M, int rtiles)
+{
+    *g = GemmGroup{A, S, C, M, rtiles};
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t table_gemm_ws_bytes(int M, int K)
+{
+    const int rt = ceil_div(2L * M, 16), ks = ceil_div(K, 4);
+    return align256(sizeof(GemmGroup)) + align256((size_t)rt * ks * 64 * sizeof(double));
+}
+
+void table_gemm_f64(const cd *A, int M, int K, const cd *S, int Nc, cd *C, void *ws, hipStream_t s)
+{
+    const int rt = ceil_div(2L * M, 16), ks = ceil_div(K, 4);
+    GemmGroup *dg = (GemmGroup *)ws;
+    double *Ap = (double *)((char *)ws + align256(sizeof(GemmGroup)));
+    hipLaunchKernelGGL(k_pack_table, dim3(grid_for((long)rt * ks * 64)), dim3(256), 0, s, Ap, A, M, K, rt, ks);
+    hipLaunchKernelGGL(k_set_group, dim3(1), dim3(1), 0, s, dg, (const double *)Ap, (const double *)S, C, M, rt);
+    GemmLaunch L{dg, 1, K, Nc, M, 2L * Nc, (long)Nc};
+    launch_gemm(L, s);
+}
+
+void launch_rows_dot(const cd *P, const cd *T, int M, int K, cd pre, cd *F, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ff_final, dim3(M), dim3(256), 0, s, P, T, M, K, pre, F);
+}
+
 }  // namespace ffmg

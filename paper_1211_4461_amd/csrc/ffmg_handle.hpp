@@ -88,6 +88,9 @@ struct ffmg_handle {
     ffmg::cd *d_E = nullptr;         // plane-wave axis factors
     ffmg::cd *d_F = nullptr;         // far-field staging
     int d_F_cap = 0;
+    // ionisation observables: workspace slots grown on demand, freed at destroy
+    void *ion_buf[6] = {};
+    size_t ion_cap[6] = {};
     // learned smoother on the finest level (smoother FFMG_SMOOTH_LEARNED)
     unsigned short *d_wfrag = nullptr;   // MFMA weight fragments (BF16)
     std::vector<unsigned *> d_kh2;       // kappa h^2 per level, BF16 complex (learned levels)

@@ -163,7 +163,11 @@ template <typename TC, typename TF>
 void launch_prolong_set(const LevelGeom &fine, const cx<TC> *ec, cx<TF> *uf, const double *bnorm2, double inv_sqN,
                         hipStream_t s);
 void launch_build_coarse(const LevelGeom &g, const Stencil<double> &P, const cd *q, cd *aug, hipStream_t s);
-void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s);
+// Gauss-Jordan inverse of the coarsest operator: one block up to
+// GJ_ONE_BLOCK_MAX unknowns, above that one pass per pivot over the whole
+// device (fcol: n complex of workspace), the same bits either way.
+constexpr int GJ_ONE_BLOCK_MAX = 256;
+void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s, cd *fcol);
 template <typename T>
 void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s, const int *stop = nullptr);
 void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
@@ -360,6 +364,12 @@ int ff_plan_default_variant();
 void ff_plan_set_variant(FarFieldPlan *p, int v);
 int ff_plan_variant(const FarFieldPlan *p);
 void launch_axis_exp(cd *out, int m, double lo, double h, double cr, double ci, hipStream_t s);
+// FP64 MFMA contraction C[m][n] = sum_k A[m][k] S[k][n] for a complex table A
+// (M x K, row stride K) and S (K x Nc), C (M x Nc); ws: table_gemm_ws_bytes.
+size_t table_gemm_ws_bytes(int M, int K);
+void table_gemm_f64(const cd *A, int M, int K, const cd *S, int Nc, cd *C, void *ws, hipStream_t s);
+// F[m] = pre sum_k P[m][k] T[m][k] (one block per row, fixed summation order).
+void launch_rows_dot(const cd *P, const cd *T, int M, int K, cd pre, cd *F, hipStream_t s);
 // No-allocation far field: take the scratch array's address on `device` (the
 // current device; once per device), then run the FP64 map from it.  Returns 0
 // on success, 1 if the problem needs more than the scratch array (*need set),

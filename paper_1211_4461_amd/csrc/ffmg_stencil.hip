@@ -1582,9 +1582,96 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(cd *__restrict__ a, int n
     if (t == 0) info[0] = 0;
 }
 
-void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s)
+// The same elimination spread over the device, for coarsest grids too large
+// for one block to stream: per pivot k, k_gj_pivot (one block) picks the
+// pivot, swaps, scales the pivot row and saves the column of multipliers,
+// then k_gj_elim updates every other row.  Each element goes through the
+// operations of k_gauss_jordan in the same order, so the inverse is the same
+// bits.  info[0] must be 0 on entry; a zero pivot sets it and the remaining
+// launches return at once.
+__global__ void k_gj_init(int *__restrict__ info) { info[0] = 0; }
+
+__global__ __launch_bounds__(1024) void k_gj_pivot(cd *__restrict__ a, int n, int k, cd *__restrict__ fcol,
+                                                   int *__restrict__ info)
 {
-    hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, aug, n, info);
+    __shared__ double bestv[1024];
+    __shared__ int besti[1024];
+    __shared__ cd pivrow_scale;
+    if (info[0] != 0) return;
+    const int W = 2 * n;
+    const int t = threadIdx.x;
+    double bv = -1.0;
+    int bi = k;
+    for (int i = k + t; i < n; i += 1024) {
+        double v = abs2(a[(size_t)i * W + k]);
+        if (v > bv) {
+            bv = v;
+            bi = i;
+        }
+    }
+    bestv[t] = bv;
+    besti[t] = bi;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (t < off) {
+            double o = bestv[t + off];
+            int oi = besti[t + off];
+            if (o > bestv[t] || (o == bestv[t] && oi < besti[t])) {
+                bestv[t] = o;
+                besti[t] = oi;
+            }
+        }
+        __syncthreads();
+    }
+    const int p = besti[0];
+    if (bestv[0] <= 0.0) {
+        if (t == 0) info[0] = k + 1;
+        return;
+    }
+    if (p != k)
+        for (int j = t; j < W; j += 1024) {
+            cd tmp = a[(size_t)k * W + j];
+            a[(size_t)k * W + j] = a[(size_t)p * W + j];
+            a[(size_t)p * W + j] = tmp;
+        }
+    __syncthreads();
+    if (t == 0) pivrow_scale = recip(a[(size_t)k * W + k]);
+    __syncthreads();
+    const cd sc = pivrow_scale;
+    for (int j = t; j < W; j += 1024) a[(size_t)k * W + j] = a[(size_t)k * W + j] * sc;
+    for (int i = t; i < n; i += 1024) fcol[i] = a[(size_t)i * W + k];
+}
+
+// rows 4 blockIdx.y .. +3, columns k + 256 blockIdx.x + threadIdx.x
+__global__ __launch_bounds__(256) void k_gj_elim(cd *__restrict__ a, int n, int k, const cd *__restrict__ fcol,
+                                                 const int *__restrict__ info)
+{
+    if (info[0] != 0) return;
+    const int W = 2 * n;
+    const int j = k + blockIdx.x * 256 + threadIdx.x;
+    if (j >= W) return;
+    const cd pk = a[(size_t)k * W + j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = blockIdx.y * 4 + r;
+        if (i >= n || i == k) continue;
+        if (j == k) a[(size_t)i * W + k] = cd{0.0, 0.0};
+        else a[(size_t)i * W + j] = a[(size_t)i * W + j] - fcol[i] * pk;
+    }
+}
+
+void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s, cd *fcol)
+{
+    if (n <= GJ_ONE_BLOCK_MAX || !fcol) {
+        hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, aug, n, info);
+        return;
+    }
+    hipLaunchKernelGGL(k_gj_init, dim3(1), dim3(1), 0, s, info);
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, aug, n, k, fcol, info);
+        dim3 grid((unsigned)((2 * n - k + 255) / 256), (unsigned)((n + 3) / 4));
+        hipLaunchKernelGGL(k_gj_elim, grid, dim3(256), 0, s, aug, n, k, (const cd *)fcol, (const int *)info);
+    }
 }
 
 // Coarsest solve u = A^{-1} b with the stored inverse (right half of the

@@ -67,7 +67,8 @@ EXPORTS = ["ffmg_default_options", "ffmg_strerror", "ffmg_last_error", "mg_setup
            "farfield_map_batched", "ml_net_create", "ml_net_set_weights", "ml_net_get_weights", "ml_loss_grad",
            "ml_train_step", "ml_net_last_error", "ml_net_destroy", "mg_learned_smooth", "mg_jacobi_factor",
            "mg_gmres_smooth", "mg_solve_begin", "mg_solve_end", "farfield_map_noalloc", "mg_rhs_phase",
-           "mg_residual", "mg_profile_durations"]
+           "mg_residual", "mg_profile_durations", "mg_rhs_source", "ion_bound_state", "ion_wavenumbers",
+           "ion_test_functions", "ion_amplitudes", "ion_cross_sections"]
 
 
 def lib():
@@ -122,6 +123,12 @@ def lib():
     L.ml_net_last_error.restype = ctypes.c_char_p
     L.ml_net_destroy.argtypes = [vp]
     L.ml_net_destroy.restype = None
+    L.mg_rhs_source.argtypes = [vp, vp, vp]
+    L.ion_bound_state.argtypes = [vp, ip, vp, dp, vp, vp]
+    L.ion_wavenumbers.argtypes = [dp, vp, ip, vp, vp, vp, vp]
+    L.ion_test_functions.argtypes = [vp, ip, vp, ip, vp, vp]
+    L.ion_amplitudes.argtypes = [vp, vp, vp, vp, ip, vp, vp, vp, vp]
+    L.ion_cross_sections.argtypes = [ip, vp, ip, vp, vp, vp, vp]
     L.mg_learned_smooth.argtypes = [vp, vp, vp]
     L.mg_learned_smooth.restype = ip
     L.mg_jacobi_factor.argtypes = [vp]
@@ -254,6 +261,115 @@ def mg_rhs_phase(h: Handle, eta, b):
     """b = q exp(i k0 cos(gamma) eta.x) (the bounded stress right-hand side)."""
     h._check(lib().mg_rhs_phase(h.ptr, _eta3(eta), _dev_ptr(b, "b")), "mg_rhs_phase")
     return b
+
+
+def mg_rhs_source(h: Handle, src, b):
+    """b = 2 src (Schroedinger form) or src (Helmholtz)."""
+    h._check(lib().mg_rhs_source(h.ptr, _dev_ptr(src, "src"), _dev_ptr(b, "b")), "mg_rhs_source")
+    return b
+
+
+def _host_c128(a, n):
+    a = np.ascontiguousarray(a, dtype=np.complex128)
+    if a.size != n:
+        raise ValueError(f"expected {n} complex values")
+    return a
+
+
+def ion_bound_state(h: Handle, axis: int, v, shift: float = -1.0, phi=None):
+    """(lambda, phi): eq. boundstate on one axis (v: device potential at the
+    axis nodes); phi normalised by sum phi^2 h~ = 1."""
+    torch = _torch()
+    if phi is None:
+        phi = torch.empty(v.numel(), dtype=torch.complex128, device=v.device)
+    lam = np.zeros(2)
+    h._check(lib().ion_bound_state(h.ptr, int(axis), _dev_ptr(v, "v"), float(shift), lam.ctypes.data_as(ctypes.c_void_p),
+                                   _dev_ptr(phi, "phi")), "ion_bound_state")
+    return complex(lam[0], lam[1]), phi
+
+
+def ion_wavenumbers(E: float, lam: complex, M: int):
+    """(k_n or None, k1[M], k2[M], w[M]) of the single and double channels."""
+    lm = np.array([complex(lam).real, complex(lam).imag])
+    kn = ctypes.c_double(0.0)
+    k1, k2, w = np.zeros(M), np.zeros(M), np.zeros(M)
+    st = lib().ion_wavenumbers(float(E), lm.ctypes.data_as(ctypes.c_void_p), int(M), ctypes.byref(kn), k1.ctypes.data_as(ctypes.c_void_p),
+                               k2.ctypes.data_as(ctypes.c_void_p), w.ctypes.data_as(ctypes.c_void_p))
+    if st:
+        raise FfmgError(st, "ion_wavenumbers: bad argument")
+    n = M if E > 0 else 0
+    return (kn.value if kn.value > 0 else None), k1[:n], k2[:n], w[:n]
+
+
+def ion_test_functions(h: Handle, axis: int, v, ks, out=None):
+    """eq. testfunction: (M, m) device table of regular solutions with free
+    amplitude 1/sqrt(k)."""
+    torch = _torch()
+    ks = np.ascontiguousarray(ks, dtype=np.float64).ravel()
+    if out is None:
+        out = torch.empty((ks.size, v.numel()), dtype=torch.complex128, device=v.device)
+    h._check(lib().ion_test_functions(h.ptr, int(axis), _dev_ptr(v, "v"), int(ks.size), ks.ctypes.data_as(ctypes.c_void_p),
+                                      _dev_ptr(out, "out")), "ion_test_functions")
+    return out
+
+
+def ion_amplitudes(h: Handle, src, v12, u, tx, ty):
+    """(amp[M], opt): eq. single-ionization / eq. double-ionization for the
+    rows of tx, ty, and the optical-theorem product <phi, u>."""
+    M = int(tx.shape[0])
+    if int(ty.shape[0]) != M:
+        raise ValueError("tx and ty need the same number of rows")
+    amp = np.zeros(M, dtype=np.complex128)
+    opt = np.zeros(2)
+    h._check(lib().ion_amplitudes(h.ptr, _dev_ptr(src, "src"), _dev_ptr(v12, "v12"), _dev_ptr(u, "u"), M,
+                                  _dev_ptr(tx, "tx"), _dev_ptr(ty, "ty"), amp.ctypes.data_as(ctypes.c_void_p),
+                                  opt.ctypes.data_as(ctypes.c_void_p)), "ion_amplitudes")
+    return amp, complex(opt[0], opt[1])
+
+
+def ion_cross_sections(s0, f, w, opt):
+    """(single, double, total) cross sections from the amplitudes."""
+    f = _host_c128(f, len(w))
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    s = np.array([complex(s0).real, complex(s0).imag]) if s0 is not None else np.zeros(2)
+    o = np.array([complex(opt).real, complex(opt).imag])
+    sig = np.zeros(3)
+    st = lib().ion_cross_sections(int(s0 is not None), s.ctypes.data_as(ctypes.c_void_p), int(len(w)), f.ctypes.data_as(ctypes.c_void_p),
+                                  w.ctypes.data_as(ctypes.c_void_p), o.ctypes.data_as(ctypes.c_void_p), sig.ctypes.data_as(ctypes.c_void_p))
+    if st:
+        raise FfmgError(st, "ion_cross_sections: bad argument")
+    return float(sig[0]), float(sig[1]), float(sig[2])
+
+
+def ion_observables(h: Handle, src, v12, u, v1x, v1y, E: float, M: int, lam: complex, phi0):
+    """All cross sections at energy E from the solution u: one batch of
+    test functions per axis ([k_n] + k1 on x, k2 on y), one contraction of
+    M + 1 amplitudes (the bound state phi0 of the y axis pairs with k_n),
+    and the cross sections.  Returns a dict."""
+    torch = _torch()
+    kn, k1, k2, w = ion_wavenumbers(E, lam, M)
+    kx = ([kn] if kn else []) + list(k1)
+    out = dict(kn=kn, s0=None, f=np.zeros(0, dtype=np.complex128), k1=k1, k2=k2, w=w)
+    if kx:
+        tx = ion_test_functions(h, 0, v1x, kx)
+        rows = []
+        if kn:
+            rows.append(phi0.reshape(1, -1))
+        if len(k2):
+            rows.append(ion_test_functions(h, 1, v1y, k2))
+        ty = torch.cat(rows, 0) if len(rows) > 1 else rows[0].contiguous()
+        amp, opt = ion_amplitudes(h, src, v12, u, tx, ty)
+        if kn:
+            out["s0"], out["f"] = amp[0], amp[1:]
+        else:
+            out["f"] = amp
+    else:
+        z = torch.zeros((1, v1x.numel()), dtype=torch.complex128, device=v1x.device)
+        _, opt = ion_amplitudes(h, src, v12, u, z, torch.zeros((1, v1y.numel()), dtype=torch.complex128,
+                                                              device=v1y.device))
+    out["opt"] = opt
+    out["single"], out["double"], out["total"] = ion_cross_sections(out["s0"], out["f"], w, opt)
+    return out
 
 
 def mg_residual(h: Handle, b, u, r):

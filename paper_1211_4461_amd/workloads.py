@@ -306,6 +306,40 @@ def two_spheres(dim: int, n: int, k0: float, gamma: float, L: float = 20.0,
                     tol=1e-6, nu1=1, nu2=1)
 
 
+# The model of Sec. 5.2 (eq. partialwave2d) and the energies of the
+# complex-contour points of Fig. single_and_double: the bound-state energy
+# lambda_0 = -1.02150069 of the 1D Hamiltonian at h = 0.05 plus 0.2 j.
+ION_LAMBDA0 = -1.02150069
+ION_ENERGIES = tuple(ION_LAMBDA0 + 0.2 * j for j in range(1, 21))
+
+
+def ionization_2d(E: float, n: int = 256, h: float = 0.05, theta: float = math.pi / 7,
+                  coarsest_n: int = 32) -> Workload:
+    """The 2D radial partial-wave model of Sec. 5.2 at total energy E, on the
+    contour grid of [0, n h]^2: V1(x) = -4.5 exp(-x^2), V2(y) = -4.5 exp(-y^2),
+    V12 = 2 exp(-(x+y)^2), source phi = exp(-3 (x+y)^2), all continued to
+    z = e^{i gamma} x, with gamma from the ECS angle theta = pi/7 through
+    eq. thetagamma (8.5 deg, Sec. 5.4).  The paper's grid is [0,15]^2 with
+    300 points (h = 0.05); a power-of-two grid keeps h and takes the box
+    n h.  The coarsest multigrid level keeps h <= 0.4 (coarsest_n
+    intervals), fine enough for the wells' bound states.  params: src (phi),
+    v12, v1 (the one-body potential at the axis nodes, both axes)."""
+    L = n * h
+    gamma = gamma_from_ecs(theta)
+    X, Y = mesh([n, n], [0.0, 0.0], [L, L])
+    zx, zy = rotate([X, Y], gamma)
+    z = np.exp(1j * gamma) * interior_axes([n], [0.0], [L])[0]
+    v1 = -4.5 * np.exp(-z * z)
+    s = zx + zy
+    v12 = 2.0 * np.exp(-s * s)
+    V = -4.5 * np.exp(-zx * zx) - 4.5 * np.exp(-zy * zy) + v12
+    src = np.exp(-3.0 * s * s)
+    c = lambda a: np.ascontiguousarray(a, dtype=np.complex128)
+    return Workload(f"ionization_2d_E{E:+.4f}_n{n}", 2, n, 0.0, L, gamma, SCHRODINGER, 0.0, float(E), c(V),
+                    np.array([1.0, 0.0]), np.zeros((0, 2)), tol=1e-10, nu1=1, nu2=1,
+                    params={"src": c(src), "v12": c(v12), "v1": c(v1), "coarsest_n": coarsest_n, "h": h})
+
+
 def random_field(n: int, seed: int, kh: float, lo: float = -10.0, hi: float = 10.0):
     """A random bump field (the bumps_2d law) at wavenumber k0 = kh / h;
     used as training input for the learned smoother."""
