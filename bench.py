@@ -51,6 +51,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # V-cycles per coarse level of the full multigrid start (the F(k) cycle)
 FMG_K = 2
+# Residual-reduction tolerance of the headline maps (the paper's own Sec. 4
+# tolerance): the metric asks for maps within 1e-6 of the FP64 map, which
+# this reaches with two orders of magnitude to spare (the line reports the
+# measured map error against the FP64 map converged to FP64_TOL)
+MAP_TOL = 1e-6
+FP64_TOL = 1e-10
 CSRC = os.path.join(ROOT, "paper_1211_4461_amd", "csrc")
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE records, keyed by kernel source
 TRAFFIC = {3: (os.path.join(ROOT, "profiles", "traffic_gauss3d_512.json"), os.path.join(CSRC, "ffmg_stencil.hip")),
@@ -134,7 +140,7 @@ def copy_tuning(ff, src, dst):
 
 
 def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FMG_K, lanes=1, pipelined=False,
-             etas=None):
+             etas=None, tol=None):
     """Time `steps` maps (right-hand side, solve, far field into device
     memory) after `warmup` rounds.  lanes = D > 1: maps cycle through D
     handles, each on its own stream; pipelined: each step begins its map's
@@ -144,6 +150,7 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FM
     finished.  etas: incoming directions cycled through map by map (default
     the workload's)."""
     etas = [w.eta] if etas is None else etas
+    tol = w.tol if tol is None else tol
     opts = dict(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles)
     ln_ = []
     for i in range(lanes):
@@ -182,9 +189,9 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FM
     def step():
         ln = begin_map()
         if not pipelined:
-            finish_map(ff.mg_solve(ln[0], ln[1], ln[2], tol=w.tol), ln)
+            finish_map(ff.mg_solve(ln[0], ln[1], ln[2], tol=tol), ln)
             return
-        ff.mg_solve_begin(ln[0], ln[1], ln[2], tol=w.tol)
+        ff.mg_solve_begin(ln[0], ln[1], ln[2], tol=tol)
         pending.append(ln)
         if len(pending) == lanes:   # the oldest lane is next: finish its map
             old = pending.popleft()
@@ -217,7 +224,7 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FM
     return out
 
 
-def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp):
+def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp, tol=None):
     """The same maps one at a time (one handle, one stream) with HIP events
     around every launch of the finest-level kernels the library brackets:
     per-launch durations, early-exit launches (a batch step queued after the
@@ -235,7 +242,7 @@ def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp):
         ff.mg_rhs_plane_wave(h, w.eta, b)
         if fmg_cycles == 0:
             u.zero_()
-        inf = ff.mg_solve(h, b, u, tol=w.tol)
+        inf = ff.mg_solve(h, b, u, tol=w.tol if tol is None else tol)
         ff.farfield_map(h, w.eta, u, w.dirs, out=F)
         return inf
 
@@ -446,15 +453,16 @@ def run_bumps2d(ff, torch, W, steps, warmup, lanes, ff_prec):
     w = W.bumps_2d(n=2048, seed=1, k0=1.0, M=360)
     etas = [np.array([math.cos(a), math.sin(a)]) for a in (0.0, 0.5 * math.pi, math.pi, 1.5 * math.pi)]
     ffp = {"bf16x6": ff.FF_BF16X6, "bf16x3": ff.FF_BF16X3, "fp64": ff.FF_FP64}[ff_prec]
-    m = run_path(ff, torch, w, ff.FP32_IR, ffp, steps, warmup, lanes=lanes, pipelined=lanes > 1, etas=etas)
+    m = run_path(ff, torch, w, ff.FP32_IR, ffp, steps, warmup, lanes=lanes, pipelined=lanes > 1, etas=etas,
+                 tol=MAP_TOL)
     p = run_path(ff, torch, w, ff.FP64, ff.FF_FP64, max(steps // 2, 2), warmup, lanes=lanes, pipelined=lanes > 1,
-                 etas=etas)
-    km = kernel_pass(ff, torch, w, ff.FP32_IR, ffp, 8, FMG_K, BPP[2]["mixed"])
-    kp = kernel_pass(ff, torch, w, ff.FP64, ff.FF_FP64, 4, FMG_K, BPP[2]["plain"])
+                 etas=etas, tol=MAP_TOL)
+    km = kernel_pass(ff, torch, w, ff.FP32_IR, ffp, 8, FMG_K, BPP[2]["mixed"], tol=MAP_TOL)
+    kp = kernel_pass(ff, torch, w, ff.FP64, ff.FF_FP64, 4, FMG_K, BPP[2]["plain"], tol=MAP_TOL)
     dom = km["dominant"]
     th = (8, 16, 4)[m["tune"].get("smooth", 0)]
     return {"workload": "bumps_2d n=2048 box=[-10,10]^2 k0=1 gamma=30deg 8 bumps seed=1, 360 angles, "
-                        "4 incoming directions cycled map by map",
+                        "4 incoming directions cycled map by map", "tol": MAP_TOL,
             "lanes": lanes, "mixed": {"maps_per_s": round(m["maps_per_s"], 3), "ms_per_step": round(m["ms_per_step"], 3),
                                       "refinement_steps": m["cycles"], "vcycles": m["vcycles"],
                                       "rel_residual": m["rel_residual"], "tune": m["tune"]},
@@ -824,9 +832,10 @@ def main():
 
     lanes = max(args.lanes, 1)
     pipe = lanes > 1
-    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, lanes=lanes, pipelined=pipe)
+    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, lanes=lanes, pipelined=pipe,
+                     tol=MAP_TOL)
     # the dominant kernel and the finest-level kernel rates: one solve in flight
-    km = kernel_pass(ffmg, torch, w, ffmg.FP32_IR, ffp, 4, FMG_K, BPP[3]["mixed"])
+    km = kernel_pass(ffmg, torch, w, ffmg.FP32_IR, ffp, 4, FMG_K, BPP[3]["mixed"], tol=MAP_TOL)
     dom = km["dominant"]
     dk = km["kernels"][dom]
     roof = {"kernel": KERNEL_NAMES[3][dom] % "float", "bound": "hbm", "achieved": dk["GB_s"], "peak": HBM_PEAK_GBS,
@@ -854,7 +863,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"gauss_3d n=512 box=[-6,6]^3 chi=0.5exp(-z.z/2) k0=1 gamma=30deg eta=+x, "
                                f"128 azimuth x 64 polar directions",
-                   "unknowns": w.N, "directions": len(w.dirs), "tol": w.tol, "cycle": "V(2,2) omega=0.8 Jacobi",
+                   "unknowns": w.N, "directions": len(w.dirs), "tol": MAP_TOL,
+                   "accuracy": "maps within 1e-6 relative of the FP64 map converged to 1e-10 (measured: "
+                               "map_rel_err_vs_fp64)", "cycle": "V(2,2) omega=0.8 Jacobi",
                    "start": f"full multigrid: {FMG_K} V(2,2) per coarse level, then the finest-level iteration",
                    "lanes": (f"{lanes} solves in flight from one host thread (one handle and stream each, "
                              "mg_solve_begin / mg_solve_end)" if pipe else "1"),
@@ -869,20 +880,36 @@ def main():
         "roofline": roof,
     }
     if not args.no_plain:
+        def map_err(F, Fr):
+            return {"norm": float(np.linalg.norm(F - Fr) / np.linalg.norm(Fr)),
+                    "elementwise": float(np.abs(F - Fr).max() / np.abs(Fr).max())}
+        # plain FP64 at the same tolerance (equal accuracy), and converged to 1e-10 (the FP64 path's own
+        # tolerance, and the reference map of the accuracy figures)
         plain = run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2), args.warmup, lanes=lanes,
-                         pipelined=pipe)
-        kp = kernel_pass(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, 2, FMG_K, BPP[3]["plain"])
+                         pipelined=pipe, tol=MAP_TOL)
+        kp = kernel_pass(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, 2, FMG_K, BPP[3]["plain"], tol=MAP_TOL)
+        p10 = run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 4, 2), 1, lanes=lanes,
+                       pipelined=pipe, tol=FP64_TOL)
+        m10 = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, max(args.steps // 2, 2), 1, lanes=lanes, pipelined=pipe,
+                       tol=FP64_TOL)
+        line["map_rel_err_vs_fp64"] = map_err(mixed["F"], p10["F"])
         line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
-                              "cycles": plain["cycles"], "rel_residual": plain["rel_residual"], "tune": plain["tune"],
+                              "tol": MAP_TOL, "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
+                              "map_rel_err_vs_fp64": map_err(plain["F"], p10["F"]), "tune": plain["tune"],
                               "kernels_one_solve": kp["kernels"], "farfield_gemm": gemm_report(kp["kernels"], w, "fp64")}
         line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
-        line["mixed_vs_plain_farfield_rel_err"] = float(np.linalg.norm(mixed["F"] - plain["F"])
-                                                        / np.linalg.norm(plain["F"]))
+        line["at_tol_1e-10"] = {
+            "plain_fp64": {"value": round(p10["maps_per_s"], 3), "ms_per_step": round(p10["ms_per_step"], 3),
+                           "cycles": p10["cycles"], "rel_residual": p10["rel_residual"]},
+            "mixed": {"value": round(m10["maps_per_s"], 3), "ms_per_step": round(m10["ms_per_step"], 3),
+                      "refinement_steps": m10["cycles"], "vcycles": m10["vcycles"],
+                      "rel_residual": m10["rel_residual"], "map_rel_err_vs_fp64": map_err(m10["F"], p10["F"])},
+            "speedup_vs_plain": round(m10["maps_per_s"] / p10["maps_per_s"], 3)}
         # the plain iteration from u = 0, for the CPU baseline's zero-start estimate
         h0 = ffmg.setup_workload(w, options=ffmg.default_options())[0]
         b0 = ffmg.mg_rhs_plane_wave(h0, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
         u0 = torch.zeros_like(b0)
-        zero_cycles = ffmg.mg_solve(h0, b0, u0, tol=w.tol).cycles
+        zero_cycles = ffmg.mg_solve(h0, b0, u0, tol=MAP_TOL).cycles
         h0.destroy()
         del b0, u0
         torch.cuda.empty_cache()

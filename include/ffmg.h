@@ -460,8 +460,10 @@ ffmg_status mg_profile_durations(ffmg_handle *h, int kernel, double *ms, int64_t
  * FFMG_TUNE_SWEEP3D: the weighted-Jacobi sweeps of a fused 3D level as one
  * z-marching pass per pair of sweeps (the first sweep's planes held in LDS,
  * the interpolation of the coarse correction formed inside the first pass)
- * with tiles of 8 rows in FP32 and 4 in FP64 (variant 0) or 16 and 8
- * (variant 2), or one pass per sweep (variant 1); one variant for 2D and
+ * with 64-point-wide tiles of 8 rows in FP32 and 4 in FP64 (variant 0) or 16
+ * and 8 (variant 2), 32-point-wide tiles of 16 and 8 rows for the pass that
+ * interpolates the coarse correction and the variant-0 tiles for the others
+ * (variant 3), or one pass per sweep (variant 1); one variant for 2D and
  * tile_config 1.
  * mg_tune_variants returns the number of variants (0 for an unknown
  * tunable); mg_tune_get / mg_tune_set read and select one (a cached choice).

@@ -215,10 +215,11 @@ constexpr int SMOOTH_VARIANTS = (int)(sizeof(SMOOTH_TH) / sizeof(SMOOTH_TH[0]));
 // Fused 3D smoothing chain: nu sweeps from src (0 when zero; src + P ec when
 // ec is given) into dst.  From a zero guess the first two sweeps are one
 // pass reading b and q only.  Otherwise, with the two-sweep form (tunable
-// FFMG_TUNE_SWEEP3D, variant 0) every pair of sweeps is one z-marching pass
-// with the planes of the first sweep in LDS (the interpolation formed inside
-// the first pass when ec is given); with variant 1 every sweep is its own
-// pass (the interpolation inside the first one).  tmp is a third buffer, so
+// FFMG_TUNE_SWEEP3D, variants 0, 2, 3: three tile shapes) every pair of
+// sweeps is one z-marching pass with the planes of the first sweep in LDS
+// (the interpolation formed inside the first pass when ec is given); with
+// variant 1 every sweep is its own pass (the interpolation inside the first
+// one).  tmp is a third buffer, so
 // that the last launch lands in dst without a copy.
 template <typename T>
 void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src, cx<T> *dst, cx<T> *tmp, int nu,
@@ -228,7 +229,8 @@ void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
     const bool finest = (&lv == &h->L[0]);
     const Stencil<T> &P = LP::P(lv);
     const cx<T> *q = LP::q(lv);
-    const bool pairs = (h->sweep3d_variant != 1), rows2 = (h->sweep3d_variant == 2);
+    const bool pairs = (h->sweep3d_variant != 1);
+    const int shape = h->sweep3d_variant;
     // sweeps done by launch kk of the chain
     auto sweeps_of = [&](int kk, int left) { return ((kk == 0 && zero) || pairs) ? std::min(2, left) : 1; };
     int nk = 0;
@@ -243,13 +245,13 @@ void smooth_chain3d(ffmg_handle *h, Level &lv, const cx<T> *b, const cx<T> *src,
         const cx<T> *e = (kk == 0) ? ec : nullptr;
         const int pi = finest ? prof_begin(h, prof_id) : -1;
         if (kk == 0 && zero && ns == 2 && pairs)
-            launch_sweep2_3d<T>(lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop, true, rows2);
+            launch_sweep2_3d<T>(lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop, true, shape);
         else if (kk == 0 && zero && ns == 2)
             launch_sweep3d_fused<T>(true, lv.g, P, nullptr, nullptr, b, q, o, h->stream, finest, stop);
         else if (kk == 0 && zero)
             launch_stencil<T>(MODE_JACOBI0, lv.g, P, cur, b, q, o, nullptr, h->stream, finest, stop);
         else if (ns == 2)
-            launch_sweep2_3d<T>(lv.g, P, cur, e, b, q, o, h->stream, finest, stop, false, rows2);
+            launch_sweep2_3d<T>(lv.g, P, cur, e, b, q, o, h->stream, finest, stop, false, shape);
         else if (e)
             launch_sweep3d_fused<T>(false, lv.g, P, cur, e, b, q, o, h->stream, finest, stop);
         else
@@ -1524,7 +1526,7 @@ int mg_tune_variants(const ffmg_handle *h, int tunable)
     case FFMG_TUNE_PRE: return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? 3 : 1;
     case FFMG_TUNE_SMOOTH_COARSE:
         return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
-    case FFMG_TUNE_SWEEP3D: return (h->prob.dim == 3 && h->opt.tile_config != TILE_REFERENCE) ? 3 : 1;
+    case FFMG_TUNE_SWEEP3D: return (h->prob.dim == 3 && h->opt.tile_config != TILE_REFERENCE) ? 4 : 1;
     default: return 0;
     }
 }

@@ -183,11 +183,12 @@ void launch_refine_update(const cf *d, cd *u, const SolveCtl *ctl, size_t N, hip
 void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
                      const int *stop);
-// two Jacobi sweeps in one 3D pass from u (ec: from u + P ec; zero: from a zero guess, u not read)
+// two Jacobi sweeps in one 3D pass from u (ec: from u + P ec; zero: from a zero guess, u not read);
+// shape: the tile, as FFMG_TUNE_SWEEP3D variants 0, 2, 3 (the same bits with every tile)
 template <typename T>
 void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
                       const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero = false,
-                      bool other_rows = false);
+                      int shape = 0);
 void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
                          cf *r32, double inv_scale, double *partial, hipStream_t s);
 void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,

@@ -518,8 +518,8 @@ __global__ __launch_bounds__(256) void k_sweep3d(const cx<T> *__restrict__ u, co
 }
 
 // Two weighted-Jacobi sweeps in one z-marching pass (temporal blocking).  A
-// block owns a 64 x TY output tile of tz planes.  Its 256 threads cover the
-// tile with a two-point halo, (64 + 4) x (TY + 4) columns, thread t taking
+// block owns a TXW x TY output tile of tz planes.  Its 256 threads cover the
+// tile with a two-point halo, (TXW + 4) x (TY + 4) columns, thread t taking
 // the columns t, t + 256, ...; every thread keeps a column's last three
 // values of each stage in registers (the z-neighbours) and the stage's
 // current plane goes through LDS for the x/y neighbours:
@@ -538,16 +538,16 @@ __global__ __launch_bounds__(256) void k_sweep3d(const cx<T> *__restrict__ u, co
 // a column are read at stage 1 and kept for stage 2.  The per-point
 // arithmetic and its order are those of the single sweeps, so the result is
 // bit for bit that of two k_stencil3d / k_sweep3d passes.
-template <typename T, int SRC, int TY, int TAG>
+template <typename T, int SRC, int TY, int TAG, int TXW>
 __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                    const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                    cx<T> *__restrict__ out, Stencil<T> P, int tiles_x, int tiles_y,
                                                    int tz, const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    constexpr int W = 64 + 4, H = TY + 4, NP = W * H, NS = (NP + 255) / 256;
+    constexpr int W = TXW + 4, H = TY + 4, NP = W * H, NS = (NP + 255) / 256;
     constexpr bool PROL = (SRC == SRC_PROL), ZERO = (SRC == SRC_ZERO2);
-    constexpr int CW = 36, CH = TY / 2 + 4, NCS = PROL ? 4 : 1;
+    constexpr int CW = TXW / 2 + 4, CH = TY / 2 + 4, NCS = PROL ? 4 : 1;
     constexpr int NCL = PROL ? (CH * CW + 255) / 256 : 1;   // coarse values per thread and plane
     __shared__ cx<T> L0[ZERO ? 1 : 2][ZERO ? 1 : NP], L1[2][NP];
     __shared__ cx<T> cs[NCS][PROL ? CH : 1][PROL ? CW : 1];
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int txi = tile % tiles_x, rest = tile / tiles_x;
     const int tyi = rest % tiles_y, tzi = rest / tiles_y;
-    const int x0 = txi * 64, y0 = tyi * TY, z0 = tzi * tz, z1 = min(z0 + tz, mz);
+    const int x0 = txi * TXW, y0 = tyi * TY, z0 = tzi * tz, z1 = min(z0 + tz, mz);
     const size_t plane = (size_t)mx * my;
     const cx<T> zero = {T(0), T(0)};
     const int cx0 = (x0 >> 1) - 2, cy0 = (y0 >> 1) - 2;   // coarse origin of cs
@@ -624,29 +624,29 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
         for (int t = threadIdx.x; t < CH * CW; t += 256) dst[t] = zpair(wz[0], c0[t], wz[1], c1[t]);
     };
     // the x/y step at slot k: sum over (y, x) neighbours of (wx wy) ez, y outer
+    // The weights depend only on the parities of the fine coordinates (x0 and
+    // y0 are even, so on those of the slot's column and row): kept as two bits
+    // per slot, the products (exact: 1, 1/2, 1/4, 0) formed at use.
     int eoff[NS];        // LDS offset of the slot's lower coarse (x, y) neighbour in ezs
-    T wxy[NS][4];        // (wx wy) for (jy, jx) = (0,0), (0,1), (1,0), (1,1)
+    unsigned par = 0;    // bits 2k, 2k + 1: parity of fx, fy of slot k
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const int t = threadIdx.x + 256 * k;
         const int r = t / W, c = t - r * W;
         const int fx = x0 - 2 + c + 1, fy = y0 - 2 + r + 1;
-        T wx[2], wy[2];
-        lin_w(fx, wx);
-        lin_w(fy, wy);
         eoff[k] = (t < NP) ? ((fy >> 1) - 1 - cy0) * CW + ((fx >> 1) - 1 - cx0) : 0;
-        wxy[k][0] = wx[0] * wy[0];
-        wxy[k][1] = wx[1] * wy[0];
-        wxy[k][2] = wx[0] * wy[1];
-        wxy[k][3] = wx[1] * wy[1];
+        par |= (unsigned)((fx & 1) | ((fy & 1) << 1)) << (2 * k);
     }
     auto interp_xy = [&](int k, const cx<T> *ez) -> cx<T> {
         const cx<T> *e = ez + eoff[k];
+        T wx[2], wy[2];
+        lin_w((int)((par >> (2 * k)) & 1u), wx);
+        lin_w((int)((par >> (2 * k + 1)) & 1u), wy);
         cx<T> acc = {T(0), T(0)};
-        acc = acc + wxy[k][0] * e[0];
-        acc = acc + wxy[k][1] * e[1];
-        acc = acc + wxy[k][2] * e[CW];
-        acc = acc + wxy[k][3] * e[CW + 1];
+        acc = acc + (wx[0] * wy[0]) * e[0];
+        acc = acc + (wx[1] * wy[0]) * e[1];
+        acc = acc + (wx[0] * wy[1]) * e[CW];
+        acc = acc + (wx[1] * wy[1]) * e[CW + 1];
         return acc;
     };
     // global loads of one plane: u (stage 0) and b, q (stage 1)
@@ -896,58 +896,66 @@ void launch_sweep3d_fused(bool zero2, const LevelGeom &g, const Stencil<T> &P, c
                                tz, stop);
     }
 }
-// Output rows per block of the fused two-sweep 3D kernel (its LDS and
-// registers grow with the tile): the default per type, or the other
-// (FFMG_TUNE_SWEEP3D variant 2).
-template <typename T> constexpr int sweep2_rows(bool other) { return sizeof(T) == 4 ? (other ? 16 : 8) : (other ? 8 : 4); }
+// Tile of the fused two-sweep 3D kernel (its LDS and registers grow with
+// the tile), by FFMG_TUNE_SWEEP3D variant: 0 the default per type (64 x 8
+// FP32, 64 x 4 FP64), 2 twice the rows, 3 half the width and twice the rows
+// (fewer halo columns per output point) for the interpolating pass and the
+// default for the others (measured: the narrow tile pays off where the pass
+// also stages coarse planes).
+template <typename T> constexpr int sweep2_rows(int shape)
+{
+    return sizeof(T) == 4 ? (shape == 0 ? 8 : 16) : (shape == 0 ? 4 : 8);
+}
+constexpr int sweep2_width(int shape) { return shape == 3 ? 32 : 64; }
 
-template <typename T, int TY>
-static void launch_sweep2_3d_rows(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec,
+template <typename T, int TY, int TXW>
+static void launch_sweep2_3d_tile(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec,
                                   const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
                                   const int *stop, bool zero)
 {
-    const int tx = (g.m[0] + 63) / 64, ty = (g.m[1] + TY - 1) / TY;
+    const int tx = (g.m[0] + TXW - 1) / TXW, ty = (g.m[1] + TY - 1) / TY;
     const int tz = planes_per_block((long)tx * ty, g.m[2], TZ3);
     const int nb = tx * ty * ((g.m[2] + tz - 1) / tz);
     if (zero) {
         // u is not read: any valid pointer serves the unused loads' base
         if (finest)
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 1>), dim3(nb), dim3(256), 0, s, b, ec, b, q, out, P,
-                               tx, ty, tz, stop);
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 1, TXW>), dim3(nb), dim3(256), 0, s, b, ec, b, q, out,
+                               P, tx, ty, tz, stop);
         else
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 0>), dim3(nb), dim3(256), 0, s, b, ec, b, q, out, P,
-                               tx, ty, tz, stop);
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 0, TXW>), dim3(nb), dim3(256), 0, s, b, ec, b, q, out,
+                               P, tx, ty, tz, stop);
     } else if (ec) {
         if (finest)
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
-                               ty, tz, stop);
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 1, TXW>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out,
+                               P, tx, ty, tz, stop);
         else
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 0>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
-                               ty, tz, stop);
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 0, TXW>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out,
+                               P, tx, ty, tz, stop);
     } else {
         if (finest)
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 1>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
-                               ty, tz, stop);
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 1, TXW>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P,
+                               tx, ty, tz, stop);
         else
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 0>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P, tx,
-                               ty, tz, stop);
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 0, TXW>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P,
+                               tx, ty, tz, stop);
     }
 }
 
 template <typename T>
 void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
-                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero,
-                      bool other_rows)
+                      const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero, int shape)
 {
-    if (other_rows)
-        launch_sweep2_3d_rows<T, sweep2_rows<T>(true)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
+    if (shape == 2)
+        launch_sweep2_3d_tile<T, sweep2_rows<T>(2), sweep2_width(2)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
+    else if (shape == 3 && ec && !zero)
+        launch_sweep2_3d_tile<T, sweep2_rows<T>(3), sweep2_width(3)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
     else
-        launch_sweep2_3d_rows<T, sweep2_rows<T>(false)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
+        launch_sweep2_3d_tile<T, sweep2_rows<T>(0), sweep2_width(0)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
 }
 template void launch_sweep2_3d<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *, const cd *,
-                                       const cd *, cd *, hipStream_t, bool, const int *, bool, bool);
+                                       const cd *, cd *, hipStream_t, bool, const int *, bool, int);
 template void launch_sweep2_3d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *, const cf *,
-                                      const cf *, cf *, hipStream_t, bool, const int *, bool, bool);
+                                      const cf *, cf *, hipStream_t, bool, const int *, bool, int);
 
 void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
