@@ -57,6 +57,10 @@ FMG_K = 2
 # measured map error against the FP64 map converged to FP64_TOL)
 MAP_TOL = 1e-6
 FP64_TOL = 1e-10
+# FP32 V-cycles per FP64 refinement step of the 3D mixed path: at MAP_TOL, two
+# steps of four (residual 1e-7) beat three steps of three (measured 35.5 vs
+# 41.2 ms per 512^3 solve)
+INNER_3D = 4
 CSRC = os.path.join(ROOT, "paper_1211_4461_amd", "csrc")
 # committed rocprofv3 FETCH_SIZE / WRITE_SIZE records, keyed by kernel source
 TRAFFIC = {3: (os.path.join(ROOT, "profiles", "traffic_gauss3d_512.json"), os.path.join(CSRC, "ffmg_stencil.hip")),
@@ -140,7 +144,7 @@ def copy_tuning(ff, src, dst):
 
 
 def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FMG_K, lanes=1, pipelined=False,
-             etas=None, tol=None):
+             etas=None, tol=None, inner=0):
     """Time `steps` maps (right-hand side, solve, far field into device
     memory) after `warmup` rounds.  lanes = D > 1: maps cycle through D
     handles, each on its own stream; pipelined: each step begins its map's
@@ -151,7 +155,7 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FM
     the workload's)."""
     etas = [w.eta] if etas is None else etas
     tol = w.tol if tol is None else tol
-    opts = dict(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles)
+    opts = dict(precision=precision, ff_precision=ff_precision, fmg_cycles=fmg_cycles, inner_cycles=inner)
     ln_ = []
     for i in range(lanes):
         s_ = torch.cuda.Stream() if lanes > 1 else torch.cuda.current_stream()
@@ -224,7 +228,7 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FM
     return out
 
 
-def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp, tol=None):
+def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp, tol=None, inner=0):
     """The same maps one at a time (one handle, one stream) with HIP events
     around every launch of the finest-level kernels the library brackets:
     per-launch durations, early-exit launches (a batch step queued after the
@@ -232,7 +236,7 @@ def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp, to
     algorithmic bytes.  Returns per-kernel statistics and the dominant
     kernel among `bpp` (the largest total time per map)."""
     h = ff.setup_workload(w, options=ff.default_options(precision=precision, ff_precision=ff_precision,
-                                                        fmg_cycles=fmg_cycles))[0]
+                                                        fmg_cycles=fmg_cycles, inner_cycles=inner))[0]
     tune_handle(ff, torch, h, w, precision, ff_precision)
     b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
     u = torch.empty_like(b)
@@ -774,6 +778,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched Schroedinger workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-smoother workload")
     ap.add_argument("--no-ion", action="store_true", help="skip the ionisation cross-section sweep")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="profiling aid: skip the 512^3 headline and report the 2048^2 workload alone")
     ap.add_argument("--tune-only", action="store_true", help="fill the autotuning cache for the headline and exit")
     ap.add_argument("--tune-in-process", action="store_true",
                     help="run the autotuning sweeps in this process instead of a child process")
@@ -816,8 +822,9 @@ def main():
         wl = [w] + ([] if args.no_2d else [W.bumps_2d(n=2048, seed=1, k0=1.0, M=360)])
         for wk in wl:
             for prec, fp in ((ffmg.FP32_IR, ffp), (ffmg.FP64, ffmg.FF_FP64)):
+                inner = INNER_3D if (prec == ffmg.FP32_IR and wk.dim == 3) else 0
                 h = ffmg.setup_workload(wk, options=ffmg.default_options(precision=prec, ff_precision=fp,
-                                                                         fmg_cycles=FMG_K))[0]
+                                                                         fmg_cycles=FMG_K, inner_cycles=inner))[0]
                 tune_handle(ffmg, torch, h, wk, prec, fp)
                 h.destroy()
                 torch.cuda.empty_cache()
@@ -832,88 +839,101 @@ def main():
 
     lanes = max(args.lanes, 1)
     pipe = lanes > 1
-    mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, lanes=lanes, pipelined=pipe,
-                     tol=MAP_TOL)
-    # the dominant kernel and the finest-level kernel rates: one solve in flight
-    km = kernel_pass(ffmg, torch, w, ffmg.FP32_IR, ffp, 4, FMG_K, BPP[3]["mixed"], tol=MAP_TOL)
-    dom = km["dominant"]
-    dk = km["kernels"][dom]
-    roof = {"kernel": KERNEL_NAMES[3][dom] % "float", "bound": "hbm", "achieved": dk["GB_s"], "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": dk["hbm_frac"], "traffic": measured_traffic(dom, "float", 3),
-            "bytes_per_launch": dk["bytes_per_launch"], "bytes_per_point": dk["bytes_per_point"],
-            "avg_launch_us": dk["avg_us"], "launches": dk["launches"],
-            "early_exit_launches_dropped": dk["early_exit_launches_dropped"],
-            "timed_in": "a one-solve-in-flight pass of the same maps after the headline: HIP events around every "
-                        "launch of the finest-level kernels the library brackets",
-            "ranked_by": "largest time per map among the bracketed finest-level kernels; "
-                         "profiles/kernels_gauss3d_512_mixed.md ranks every kernel of a map (rocprofv3)",
-            "working_set": "HBM-resident: one FP32 field is 1.07 GB, far above the 256 MB Infinity Cache"}
-    line = {
-        "metric": "far-field maps/sec at 1e-6 rel error: plain FP64 MG vs mixed-prec/learned MG",
-        "value": round(mixed["maps_per_s"], 3),
-        "unit": "maps/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(mixed["ms_per_step"], 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"gauss_3d n=512 box=[-6,6]^3 chi=0.5exp(-z.z/2) k0=1 gamma=30deg eta=+x, "
-                               f"128 azimuth x 64 polar directions",
-                   "unknowns": w.N, "directions": len(w.dirs), "tol": MAP_TOL,
-                   "accuracy": "maps within 1e-6 relative of the FP64 map converged to 1e-10 (measured: "
-                               "map_rel_err_vs_fp64)", "cycle": "V(2,2) omega=0.8 Jacobi",
-                   "start": f"full multigrid: {FMG_K} V(2,2) per coarse level, then the finest-level iteration",
-                   "lanes": (f"{lanes} solves in flight from one host thread (one handle and stream each, "
-                             "mg_solve_begin / mg_solve_end)" if pipe else "1"),
-                   "form": "FP32 V-cycles in FP64 refinement + "
-                           + {"bf16x6": "split-BF16 (3 parts, 6 products) MFMA far field, FP32 accumulation",
-                              "bf16x3": "split-BF16 (2 parts, 3 products) MFMA far field, FP32 accumulation",
-                              "fp64": "FP64 MFMA far field"}[ffp_name]},
-        "mixed": {"refinement_steps": mixed["cycles"], "vcycles": mixed["vcycles"],
-                  "rel_residual": mixed["rel_residual"], "conv_factor": round(mixed["conv_factor"], 4),
-                  "tune": mixed["tune"], "kernels_one_solve": km["kernels"],
-                  "farfield_gemm": gemm_report(km["kernels"], w, ffp_name)},
-        "roofline": roof,
-    }
-    if not args.no_plain:
-        def map_err(F, Fr):
-            return {"norm": float(np.linalg.norm(F - Fr) / np.linalg.norm(Fr)),
-                    "elementwise": float(np.abs(F - Fr).max() / np.abs(Fr).max())}
-        # plain FP64 at the same tolerance (equal accuracy), and converged to 1e-10 (the FP64 path's own
-        # tolerance, and the reference map of the accuracy figures)
-        plain = run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2), args.warmup, lanes=lanes,
-                         pipelined=pipe, tol=MAP_TOL)
-        kp = kernel_pass(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, 2, FMG_K, BPP[3]["plain"], tol=MAP_TOL)
-        p10 = run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 4, 2), 1, lanes=lanes,
-                       pipelined=pipe, tol=FP64_TOL)
-        m10 = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, max(args.steps // 2, 2), 1, lanes=lanes, pipelined=pipe,
-                       tol=FP64_TOL)
-        line["map_rel_err_vs_fp64"] = map_err(mixed["F"], p10["F"])
-        line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
-                              "tol": MAP_TOL, "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
-                              "map_rel_err_vs_fp64": map_err(plain["F"], p10["F"]), "tune": plain["tune"],
-                              "kernels_one_solve": kp["kernels"], "farfield_gemm": gemm_report(kp["kernels"], w, "fp64")}
-        line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
-        line["at_tol_1e-10"] = {
-            "plain_fp64": {"value": round(p10["maps_per_s"], 3), "ms_per_step": round(p10["ms_per_step"], 3),
-                           "cycles": p10["cycles"], "rel_residual": p10["rel_residual"]},
-            "mixed": {"value": round(m10["maps_per_s"], 3), "ms_per_step": round(m10["ms_per_step"], 3),
-                      "refinement_steps": m10["cycles"], "vcycles": m10["vcycles"],
-                      "rel_residual": m10["rel_residual"], "map_rel_err_vs_fp64": map_err(m10["F"], p10["F"])},
-            "speedup_vs_plain": round(m10["maps_per_s"] / p10["maps_per_s"], 3)}
-        # the plain iteration from u = 0, for the CPU baseline's zero-start estimate
-        h0 = ffmg.setup_workload(w, options=ffmg.default_options())[0]
-        b0 = ffmg.mg_rhs_plane_wave(h0, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
-        u0 = torch.zeros_like(b0)
-        zero_cycles = ffmg.mg_solve(h0, b0, u0, tol=MAP_TOL).cycles
-        h0.destroy()
-        del b0, u0
-        torch.cuda.empty_cache()
-        line["plain_fp64"]["cycles_zero_start"] = zero_cycles
+    if args.no_3d:
+        # profiling aid: the 2D workload alone (its maps/s in "value")
+        b2 = run_bumps2d(ffmg, torch, W, 40, 3, 4, ffp_name)
+        line = {"metric": "far-field maps/sec at 1e-6 rel error: plain FP64 MG vs mixed-prec/learned MG",
+                "value": b2["mixed"]["maps_per_s"], "unit": "maps/s", "n_gpus": 1, "steps": 40, "warmup": 3,
+                "ms_per_step": b2["mixed"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+                "config": {"workload": b2["workload"]}, "bumps_2d": b2}
+        args.no_2d = True
+        args.no_plain = True
+    else:
+        mixed = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, args.steps, args.warmup, lanes=lanes, pipelined=pipe,
+                         tol=MAP_TOL, inner=INNER_3D)
+        # the dominant kernel and the finest-level kernel rates: one solve in flight
+        km = kernel_pass(ffmg, torch, w, ffmg.FP32_IR, ffp, 4, FMG_K, BPP[3]["mixed"], tol=MAP_TOL,
+                         inner=INNER_3D)
+        dom = km["dominant"]
+        dk = km["kernels"][dom]
+        roof = {"kernel": KERNEL_NAMES[3][dom] % "float", "bound": "hbm", "achieved": dk["GB_s"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dk["hbm_frac"], "traffic": measured_traffic(dom, "float", 3),
+                "bytes_per_launch": dk["bytes_per_launch"], "bytes_per_point": dk["bytes_per_point"],
+                "avg_launch_us": dk["avg_us"], "launches": dk["launches"],
+                "early_exit_launches_dropped": dk["early_exit_launches_dropped"],
+                "timed_in": "a one-solve-in-flight pass of the same maps after the headline: HIP events around every "
+                            "launch of the finest-level kernels the library brackets",
+                "ranked_by": "largest time per map among the bracketed finest-level kernels; "
+                             "profiles/kernels_gauss3d_512_mixed.md ranks every kernel of a map (rocprofv3)",
+                "working_set": "HBM-resident: one FP32 field is 1.07 GB, far above the 256 MB Infinity Cache"}
+        line = {
+            "metric": "far-field maps/sec at 1e-6 rel error: plain FP64 MG vs mixed-prec/learned MG",
+            "value": round(mixed["maps_per_s"], 3),
+            "unit": "maps/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(mixed["ms_per_step"], 3),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32+f64",
+            "data": "synthetic",
+            "config": {"workload": f"gauss_3d n=512 box=[-6,6]^3 chi=0.5exp(-z.z/2) k0=1 gamma=30deg eta=+x, "
+                                   f"128 azimuth x 64 polar directions",
+                       "unknowns": w.N, "directions": len(w.dirs), "tol": MAP_TOL,
+                       "accuracy": "maps within 1e-6 relative of the FP64 map converged to 1e-10 (measured: "
+                                   "map_rel_err_vs_fp64)", "cycle": "V(2,2) omega=0.8 Jacobi",
+                       "start": f"full multigrid: {FMG_K} V(2,2) per coarse level, then the finest-level iteration",
+                       "lanes": (f"{lanes} solves in flight from one host thread (one handle and stream each, "
+                                 "mg_solve_begin / mg_solve_end)" if pipe else "1"),
+                       "inner_cycles": INNER_3D,
+                       "form": "FP32 V-cycles in FP64 refinement + "
+                               + {"bf16x6": "split-BF16 (3 parts, 6 products) MFMA far field, FP32 accumulation",
+                                  "bf16x3": "split-BF16 (2 parts, 3 products) MFMA far field, FP32 accumulation",
+                                  "fp64": "FP64 MFMA far field"}[ffp_name]},
+            "mixed": {"refinement_steps": mixed["cycles"], "vcycles": mixed["vcycles"],
+                      "rel_residual": mixed["rel_residual"], "conv_factor": round(mixed["conv_factor"], 4),
+                      "tune": mixed["tune"], "kernels_one_solve": km["kernels"],
+                      "farfield_gemm": gemm_report(km["kernels"], w, ffp_name)},
+            "roofline": roof,
+        }
+        if not args.no_plain:
+            def map_err(F, Fr):
+                return {"norm": float(np.linalg.norm(F - Fr) / np.linalg.norm(Fr)),
+                        "elementwise": float(np.abs(F - Fr).max() / np.abs(Fr).max())}
+            # plain FP64 at the same tolerance (equal accuracy), and converged to 1e-10 (the FP64 path's own
+            # tolerance, and the reference map of the accuracy figures)
+            plain = run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 2, 2), args.warmup, lanes=lanes,
+                             pipelined=pipe, tol=MAP_TOL)
+            kp = kernel_pass(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, 2, FMG_K, BPP[3]["plain"], tol=MAP_TOL)
+            p10 = run_path(ffmg, torch, w, ffmg.FP64, ffmg.FF_FP64, max(args.steps // 4, 2), 1, lanes=lanes,
+                           pipelined=pipe, tol=FP64_TOL)
+            m10 = run_path(ffmg, torch, w, ffmg.FP32_IR, ffp, max(args.steps // 2, 2), 1, lanes=lanes,
+                           pipelined=pipe, tol=FP64_TOL, inner=INNER_3D)
+            line["map_rel_err_vs_fp64"] = map_err(mixed["F"], p10["F"])
+            line["plain_fp64"] = {"value": round(plain["maps_per_s"], 3), "ms_per_step": round(plain["ms_per_step"], 3),
+                                  "tol": MAP_TOL, "cycles": plain["cycles"], "rel_residual": plain["rel_residual"],
+                                  "map_rel_err_vs_fp64": map_err(plain["F"], p10["F"]), "tune": plain["tune"],
+                                  "kernels_one_solve": kp["kernels"], "farfield_gemm": gemm_report(kp["kernels"], w, "fp64")}
+            line["speedup_vs_plain"] = round(mixed["maps_per_s"] / plain["maps_per_s"], 3)
+            line["at_tol_1e-10"] = {
+                "plain_fp64": {"value": round(p10["maps_per_s"], 3), "ms_per_step": round(p10["ms_per_step"], 3),
+                               "cycles": p10["cycles"], "rel_residual": p10["rel_residual"]},
+                "mixed": {"value": round(m10["maps_per_s"], 3), "ms_per_step": round(m10["ms_per_step"], 3),
+                          "refinement_steps": m10["cycles"], "vcycles": m10["vcycles"],
+                          "rel_residual": m10["rel_residual"], "map_rel_err_vs_fp64": map_err(m10["F"], p10["F"])},
+                "speedup_vs_plain": round(m10["maps_per_s"] / p10["maps_per_s"], 3)}
+            # the plain iteration from u = 0, for the CPU baseline's zero-start estimate
+            h0 = ffmg.setup_workload(w, options=ffmg.default_options())[0]
+            b0 = ffmg.mg_rhs_plane_wave(h0, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+            u0 = torch.zeros_like(b0)
+            zero_cycles = ffmg.mg_solve(h0, b0, u0, tol=MAP_TOL).cycles
+            h0.destroy()
+            del b0, u0
+            torch.cuda.empty_cache()
+            line["plain_fp64"]["cycles_zero_start"] = zero_cycles
     if not args.no_stress:
         line["stress_k0h_half"] = run_stress(ffmg, torch, W)
     if not args.no_2d:
