@@ -4,11 +4,14 @@
 One step = one far-field map of the 3D Gaussian workload (512 intervals per
 axis on [-6,6]^3, 133.4 M unknowns, chi = 0.5 exp(-z.z/2) continued onto the
 contour, k0 = 1, contour angle 30 deg, eta = +x): plane-wave right-hand side,
-multigrid solve to ||r|| <= 1e-10 ||b|| and the far field on a 128 (azimuth)
-x 64 (polar) direction grid, with every input already in HBM.  `value` is the
+multigrid solve to ||r|| <= 1e-6 ||b|| (the paper's residual-reduction
+tolerance; the line reports the map's measured error against the FP64 map
+converged to 1e-10) and the far field on a 128 (azimuth) x 64 (polar)
+direction grid, with every input already in HBM.  `value` is the
 mixed-precision path (FP32 V(2,2) cycles inside FP64 refinement, far field as
 a split-BF16 MFMA contraction with FP32 accumulation); the plain FP64 path
-(FP64 V-cycles, FP64 MFMA far field) is timed beside it on the same maps.
+(FP64 V-cycles, FP64 MFMA far field) is timed beside it on the same maps at
+the same tolerance (equal accuracy), and both are timed again at 1e-10.
 Both start from the full multigrid guess (FMG_K V-cycles per coarse level)
 and keep `--lanes` solves in flight from this one host thread: consecutive
 maps cycle through that many handles, each on its own stream, and each map's
@@ -28,7 +31,8 @@ Also reported:
     bounded phase right-hand side;
   * the 2D 2048^2 bumps workload (the former headline) with its pipelined
     mixed and plain rates, the GMRES(3) smoother, the batched Schroedinger
-    workload and the learned smoother;
+    workload, the learned smoother and the ionisation cross-section sweep
+    of the partial-wave model;
   * the FP64 CPU oracle on the host cores, on a bounded sample of the
     headline workload (run in a child process).
 """
@@ -443,7 +447,7 @@ def run_ionization(ff, torch, W, lanes=4):
                      "max_rel_dev_from_printed_points_E_gt_-0.7": round(max(dev), 4)}
     out["speedup_vs_plain"] = round(out["plain_fp64"]["ms_per_energy"] / out["mixed"]["ms_per_energy"], 3)
     out["note"] = ("cross sections: [single, double, total] per energy, half the outgoing flux per kind of channel; "
-                   "the setup phase is dominated by the device-wide Gauss-Jordan inverse of the 31^2 coarsest level")
+                   "the setup phase is dominated by the blocked Gauss-Jordan inverse of the 31^2 coarsest level")
     return out
 
 
@@ -552,20 +556,30 @@ def run_batched(ff, torch, W, steps):
     F = torch.empty((len(insts), len(dirs)), dtype=torch.complex128, device="cuda")
     infos = None
 
-    def batch():
+    def batch(tol):
         nonlocal infos
-        infos = ff.mg_solve_batched(hs, etas, us)
+        infos = ff.mg_solve_batched(hs, etas, us, tol=tol)
         ff.farfield_map_batched(hs, etas, us, dirs, out=F)
 
-    batch()
-    batch()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        batch()
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / steps
+    def timed(tol):
+        batch(tol)
+        batch(tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch(tol)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    # at the maps' tolerance (the value), then converged to 1e-10 (the
+    # reference maps and the comparison with sequential solves)
+    tm = timed(MAP_TOL)
+    info_m = infos
+    Fm = F.clone()
+    tb = timed(FP64_TOL)
     Fb = F.clone()
+    err_m = float(max((torch.linalg.vector_norm(Fm[i] - Fb[i]) / torch.linalg.vector_norm(Fb[i])).item()
+                      for i in range(len(insts))))
     bs = [torch.empty_like(u) for u in us]
 
     def sequential():
@@ -589,12 +603,15 @@ def run_batched(ff, torch, W, steps):
                        "{255^2, 511^2, 1023^2}, box [-10,10]^2, gamma=30deg, 360 angles; wells at 1/10 of the "
                        "literal depths (weighted-Jacobi V-cycles diverge on the literal bound states)",
            "instances": len(insts), "grids": sizes, "operators": len(cache),
-           "maps_per_s": round(len(insts) / tb, 2), "ms_per_batch": round(1e3 * tb, 2),
-           "sequential_maps_per_s": round(len(insts) / ts, 2),
-           "speedup_vs_sequential": round(ts / tb, 3),
-           "refinement_steps": [min(i.cycles for i in infos), max(i.cycles for i in infos)],
-           "max_rel_residual": max(i.rel_residual for i in infos),
-           "maps_equal_to_sequential": same,
+           "tol": MAP_TOL, "maps_per_s": round(len(insts) / tm, 2), "ms_per_batch": round(1e3 * tm, 2),
+           "refinement_steps": [min(i.cycles for i in info_m), max(i.cycles for i in info_m)],
+           "max_map_rel_err_vs_tol_1e-10": err_m,
+           "at_tol_1e-10": {"maps_per_s": round(len(insts) / tb, 2), "ms_per_batch": round(1e3 * tb, 2),
+                            "refinement_steps": [min(i.cycles for i in infos), max(i.cycles for i in infos)],
+                            "max_rel_residual": max(i.rel_residual for i in infos),
+                            "sequential_maps_per_s": round(len(insts) / ts, 2),
+                            "speedup_vs_sequential": round(ts / tb, 3),
+                            "maps_equal_to_sequential": same},
            "form": "FP32 V-cycles in FP64 refinement, batched + graph-replayed; split-BF16 (x6) far field"}
     for h in cache.values():
         h.destroy()

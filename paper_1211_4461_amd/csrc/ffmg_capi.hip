@@ -576,9 +576,9 @@ ffmg_status setup_impl(ffmg_handle *h)
     Level &lc = h->L.back();
     TRY(dalloc(h, &h->aug, (size_t)h->nc * 2 * h->nc * sizeof(cd)));
     launch_build_coarse(lc.g, lc.P64, lc.q, h->aug, h->stream);
-    cd *fcol = nullptr;
-    if (h->nc > GJ_ONE_BLOCK_MAX) TRY(dalloc(h, &fcol, (size_t)h->nc * sizeof(cd)));
-    launch_gauss_jordan(h->aug, h->nc, h->d_info, h->stream, fcol);
+    cd *gjws = nullptr;
+    if (h->nc > GJ_ONE_BLOCK_MAX) TRY(dalloc(h, &gjws, gauss_jordan_ws(h->nc) * sizeof(cd)));
+    launch_gauss_jordan(h->aug, h->nc, h->d_info, h->stream, gjws);
     HIPCHK(h, hipGetLastError());
     int info = 0;
     HIPCHK(h, hipMemcpyAsync(&info, h->d_info, sizeof(int), hipMemcpyDeviceToHost, h->stream));

@@ -164,10 +164,11 @@ void launch_prolong_set(const LevelGeom &fine, const cx<TC> *ec, cx<TF> *uf, con
                         hipStream_t s);
 void launch_build_coarse(const LevelGeom &g, const Stencil<double> &P, const cd *q, cd *aug, hipStream_t s);
 // Gauss-Jordan inverse of the coarsest operator: one block up to
-// GJ_ONE_BLOCK_MAX unknowns, above that one pass per pivot over the whole
-// device (fcol: n complex of workspace), the same bits either way.
+// GJ_ONE_BLOCK_MAX unknowns, above that blocked over the whole device (ws:
+// gauss_jordan_ws(n) complex values of workspace).
 constexpr int GJ_ONE_BLOCK_MAX = 256;
-void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s, cd *fcol);
+void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s, cd *ws);
+size_t gauss_jordan_ws(int n);
 template <typename T>
 void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s, const int *stop = nullptr);
 void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,

@@ -1590,97 +1590,203 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(cd *__restrict__ a, int n
     if (t == 0) info[0] = 0;
 }
 
-// The same elimination spread over the device, for coarsest grids too large
-// for one block to stream: per pivot k, k_gj_pivot (one block) picks the
-// pivot, swaps, scales the pivot row and saves the column of multipliers,
-// then k_gj_elim updates every other row.  Each element goes through the
-// operations of k_gauss_jordan in the same order, so the inverse is the same
-// bits.  info[0] must be 0 on entry; a zero pivot sets it and the remaining
-// launches return at once.
+// Blocked Gauss-Jordan for coarsest grids too large for one block to stream
+// (up to 1024 unknowns): the columns are taken GJB at a time.  For a panel
+// [k0, k0 + GJB), k_gjb_panel (one block, thread t holding row t's panel
+// columns in registers) runs the panel's pivot steps with partial pivoting,
+// recording in each row the transformation the steps apply to the rows:
+// a row's new content is its old content (rows outside the pivot positions
+// k0 .. k0 + GJB - 1) plus sum_t Tr[row][t] (old pivot row t), where the
+// columns Tr start at zero and pivot step t sets Tr[pivot][t] = 1 before
+// scaling the pivot row, so the same row operations that clear the panel
+// build Tr.  It applies the recorded row swaps to the columns right of the
+// panel and copies the old pivot rows there (P); k_gjb_update then forms
+// every row's columns right of the panel as that combination, a rank-GJB
+// update.  The panel columns themselves are not written back: columns left of
+// the current panel are never read again, and the inverse is the right half.
+// info[0] = k + 1 for a zero pivot in column k (then later launches return).
+constexpr int GJB = 8;
+
 __global__ void k_gj_init(int *__restrict__ info) { info[0] = 0; }
 
-__global__ __launch_bounds__(1024) void k_gj_pivot(cd *__restrict__ a, int n, int k, cd *__restrict__ fcol,
-                                                   int *__restrict__ info)
+__global__ __launch_bounds__(1024) void k_gjb_panel(cd *__restrict__ a, int n, int k0, cd *__restrict__ P,
+                                                    cd *__restrict__ Tr, int *__restrict__ info)
 {
-    __shared__ double bestv[1024];
-    __shared__ int besti[1024];
-    __shared__ cd pivrow_scale;
+    __shared__ double wbest[16];
+    __shared__ int wbi[16];
+    __shared__ double bestv0;
+    __shared__ int besti0;
+    __shared__ cd prow[2 * GJB];          // the scaled pivot row: panel, then Tr
+    __shared__ cd xch[2][2 * GJB];        // row exchange
+    __shared__ int piv[GJB];
     if (info[0] != 0) return;
-    const int W = 2 * n;
-    const int t = threadIdx.x;
-    double bv = -1.0;
-    int bi = k;
-    for (int i = k + t; i < n; i += 1024) {
-        double v = abs2(a[(size_t)i * W + k]);
-        if (v > bv) {
-            bv = v;
-            bi = i;
-        }
+    const int W = 2 * n, t = threadIdx.x;
+    const int bw = min(GJB, n - k0);
+    const bool mine = t < n;
+    cd pan[GJB], tr[GJB];
+#pragma unroll
+    for (int j = 0; j < GJB; ++j) {
+        pan[j] = (mine && j < bw) ? a[(size_t)t * W + k0 + j] : cd{0.0, 0.0};
+        tr[j] = cd{0.0, 0.0};
     }
-    bestv[t] = bv;
-    besti[t] = bi;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-        if (t < off) {
-            double o = bestv[t + off];
-            int oi = besti[t + off];
-            if (o > bestv[t] || (o == bestv[t] && oi < besti[t])) {
-                bestv[t] = o;
-                besti[t] = oi;
+    // unrolled, so that every register index below is a constant
+#pragma unroll
+    for (int kk = 0; kk < GJB; ++kk) {
+        if (kk >= bw) break;
+        const int k = k0 + kk;
+        // pivot: the largest |a[i][k]|, i >= k (ties: the lowest row)
+        double v = -1.0;
+        int vi = t;
+        if (mine && t >= k) v = abs2(pan[kk]);
+        // arg-max within each wave (shuffles), then over the 16 waves
+#pragma unroll 1
+        for (int off = 32; off > 0; off >>= 1) {
+            const double o = __shfl_xor(v, off, 64);
+            const int oi = __shfl_xor(vi, off, 64);
+            if (o > v || (o == v && oi < vi)) {
+                v = o;
+                vi = oi;
+            }
+        }
+        if ((t & 63) == 0) {
+            wbest[t >> 6] = v;
+            wbi[t >> 6] = vi;
+        }
+        __syncthreads();
+        if (t < 64) {
+            v = (t < 16) ? wbest[t] : -2.0;
+            vi = (t < 16) ? wbi[t] : 0x7fffffff;
+#pragma unroll 1
+            for (int off = 8; off > 0; off >>= 1) {
+                const double o = __shfl_xor(v, off, 64);
+                const int oi = __shfl_xor(vi, off, 64);
+                if (o > v || (o == v && oi < vi)) {
+                    v = o;
+                    vi = oi;
+                }
+            }
+            if (t == 0) {
+                bestv0 = v;
+                besti0 = vi;
             }
         }
         __syncthreads();
-    }
-    const int p = besti[0];
-    if (bestv[0] <= 0.0) {
-        if (t == 0) info[0] = k + 1;
-        return;
-    }
-    if (p != k)
-        for (int j = t; j < W; j += 1024) {
-            cd tmp = a[(size_t)k * W + j];
-            a[(size_t)k * W + j] = a[(size_t)p * W + j];
-            a[(size_t)p * W + j] = tmp;
+        const int p = besti0;
+        if (bestv0 <= 0.0) {
+            if (t == 0) info[0] = k + 1;
+            return;
         }
-    __syncthreads();
-    if (t == 0) pivrow_scale = recip(a[(size_t)k * W + k]);
-    __syncthreads();
-    const cd sc = pivrow_scale;
-    for (int j = t; j < W; j += 1024) a[(size_t)k * W + j] = a[(size_t)k * W + j] * sc;
-    for (int i = t; i < n; i += 1024) fcol[i] = a[(size_t)i * W + k];
+        if (t == 0) piv[kk] = p;
+        // exchange the register rows of positions k and p
+        if (p != k) {
+            if (t == k || t == p) {
+                const int slot = (t == k) ? 0 : 1;
+#pragma unroll
+                for (int j = 0; j < GJB; ++j) {
+                    xch[slot][j] = pan[j];
+                    xch[slot][GJB + j] = tr[j];
+                }
+            }
+            __syncthreads();
+            if (t == k || t == p) {
+                const int slot = (t == k) ? 1 : 0;
+#pragma unroll
+                for (int j = 0; j < GJB; ++j) {
+                    pan[j] = xch[slot][j];
+                    tr[j] = xch[slot][GJB + j];
+                }
+            }
+        }
+        // the pivot row: Tr[k][kk] = 1, then scaled
+        if (t == k) {
+            tr[kk] = cd{1.0, 0.0};
+            const cd sc = recip(pan[kk]);
+#pragma unroll
+            for (int j = 0; j < GJB; ++j) {
+                pan[j] = pan[j] * sc;
+                tr[j] = tr[j] * sc;
+                prow[j] = pan[j];
+                prow[GJB + j] = tr[j];
+            }
+        }
+        __syncthreads();
+        // eliminate column k from every other row, in the panel and in Tr
+        if (mine && t != k) {
+            const cd f = pan[kk];
+#pragma unroll
+            for (int j = 0; j < GJB; ++j) {
+                pan[j] = (j == kk) ? cd{0.0, 0.0} : pan[j] - f * prow[j];
+                tr[j] = tr[j] - f * prow[GJB + j];
+            }
+        }
+        // (the next step rewrites prow only after its two reduction
+        // barriers, by which every thread has finished this elimination)
+    }
+    __syncthreads();   // piv[] complete
+    if (mine)
+#pragma unroll
+        for (int j = 0; j < GJB; ++j) Tr[(size_t)t * GJB + j] = tr[j];
+    // the recorded swaps on the columns right of the panel, in order
+    const int c0 = k0 + bw, nc = W - c0;
+    for (int kk = 0; kk < bw; ++kk) {
+        const int k = k0 + kk, p = piv[kk];
+        if (p != k)
+            for (int j = t; j < nc; j += 1024) {
+                const cd x = a[(size_t)k * W + c0 + j];
+                a[(size_t)k * W + c0 + j] = a[(size_t)p * W + c0 + j];
+                a[(size_t)p * W + c0 + j] = x;
+            }
+        __syncthreads();
+    }
+    // the old pivot rows (after the swaps), right of the panel
+    for (int e = t; e < bw * nc; e += 1024) {
+        const int r = e / nc, j = e - r * nc;
+        P[(size_t)r * nc + j] = a[(size_t)(k0 + r) * W + c0 + j];
+    }
 }
 
-// rows 4 blockIdx.y .. +3, columns k + 256 blockIdx.x + threadIdx.x
-__global__ __launch_bounds__(256) void k_gj_elim(cd *__restrict__ a, int n, int k, const cd *__restrict__ fcol,
-                                                 const int *__restrict__ info)
+// rows 4 blockIdx.y .. +3, columns c0 + 256 blockIdx.x + threadIdx.x
+__global__ __launch_bounds__(256) void k_gjb_update(cd *__restrict__ a, int n, int k0, const cd *__restrict__ P,
+                                                    const cd *__restrict__ Tr, const int *__restrict__ info)
 {
     if (info[0] != 0) return;
-    const int W = 2 * n;
-    const int j = k + blockIdx.x * 256 + threadIdx.x;
-    if (j >= W) return;
-    const cd pk = a[(size_t)k * W + j];
+    const int W = 2 * n, bw = min(GJB, n - k0), c0 = k0 + bw, nc = W - c0;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= nc) return;
+    cd pc[GJB];
+#pragma unroll
+    for (int q = 0; q < GJB; ++q) pc[q] = (q < bw) ? P[(size_t)q * nc + j] : cd{0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = blockIdx.y * 4 + r;
-        if (i >= n || i == k) continue;
-        if (j == k) a[(size_t)i * W + k] = cd{0.0, 0.0};
-        else a[(size_t)i * W + j] = a[(size_t)i * W + j] - fcol[i] * pk;
+        if (i >= n) continue;
+        cd acc = (i >= k0 && i < c0) ? cd{0.0, 0.0} : a[(size_t)i * W + c0 + j];
+#pragma unroll
+        for (int q = 0; q < GJB; ++q) acc = acc + Tr[(size_t)i * GJB + q] * pc[q];
+        a[(size_t)i * W + c0 + j] = acc;
     }
 }
 
-void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s, cd *fcol)
+void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s, cd *ws)
 {
-    if (n <= GJ_ONE_BLOCK_MAX || !fcol) {
+    if (n <= GJ_ONE_BLOCK_MAX || !ws) {
         hipLaunchKernelGGL(k_gauss_jordan, dim3(1), dim3(1024), 0, s, aug, n, info);
         return;
     }
+    cd *P = ws, *Tr = ws + (size_t)GJB * 2 * n;
     hipLaunchKernelGGL(k_gj_init, dim3(1), dim3(1), 0, s, info);
-    for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, aug, n, k, fcol, info);
-        dim3 grid((unsigned)((2 * n - k + 255) / 256), (unsigned)((n + 3) / 4));
-        hipLaunchKernelGGL(k_gj_elim, grid, dim3(256), 0, s, aug, n, k, (const cd *)fcol, (const int *)info);
+    for (int k0 = 0; k0 < n; k0 += GJB) {
+        hipLaunchKernelGGL(k_gjb_panel, dim3(1), dim3(1024), 0, s, aug, n, k0, P, Tr, info);
+        const int nc = 2 * n - std::min(n, k0 + GJB);
+        dim3 grid((unsigned)((nc + 255) / 256), (unsigned)((n + 3) / 4));
+        hipLaunchKernelGGL(k_gjb_update, grid, dim3(256), 0, s, aug, n, k0, (const cd *)P, (const cd *)Tr,
+                           (const int *)info);
     }
 }
+
+// Workspace of launch_gauss_jordan above the one-block size: the old pivot
+// rows (GJB x 2n) and the transformation columns (n x GJB), complex.
+size_t gauss_jordan_ws(int n) { return (size_t)GJB * 2 * n + (size_t)n * GJB; }
 
 // Coarsest solve u = A^{-1} b with the stored inverse (right half of the
 // augmented matrix, row stride 2n), in FP64 whatever T is.  One wave per row.

@@ -3,7 +3,7 @@
 * Schroedinger handles at E <= 0 (single ionisation only): set up and solve;
   the plane-wave calls refuse them; the source right-hand side b = 2 phi.
 * The coarsest level of the model's hierarchy (31^2 unknowns, inverted by
-  the device-wide Gauss-Jordan) and the one-block one (15^2): one V-cycle
+  the blocked device-wide Gauss-Jordan) and the one-block one (15^2): one V-cycle
   against the oracle's (dense LU on the coarsest level).
 * eq. boundstate, eq. testfunction and the amplitude contraction against the
   oracle element by element (amplitude counts 1, 7 and 33 span the 8-row
@@ -81,7 +81,7 @@ def test_nonpositive_energy(ff):
 
 @pytest.mark.parametrize("coarsest", [32, 16])
 def test_coarsest_inverse_large_and_small(ff, orc, coarsest):
-    """31^2 coarsest unknowns take the device-wide Gauss-Jordan, 15^2 the
+    """31^2 coarsest unknowns take the blocked device-wide Gauss-Jordan, 15^2 the
     one-block kernel; one V-cycle from zero against the oracle's."""
     w = W.ionization_2d(0.97849931, n=128, coarsest_n=coarsest)
     h, coef = _setup(ff, w)
