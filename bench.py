@@ -553,6 +553,7 @@ def run_batched(ff, torch, W, steps):
     us = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for w in insts]
     etas = [w.eta for w in insts]
     dirs = insts[0].dirs
+    tile_variant = autotune.tune_batch(hs, etas, us, tol=MAP_TOL)
     F = torch.empty((len(insts), len(dirs)), dtype=torch.complex128, device="cuda")
     infos = None
 
@@ -612,6 +613,7 @@ def run_batched(ff, torch, W, steps):
                             "sequential_maps_per_s": round(len(insts) / ts, 2),
                             "speedup_vs_sequential": round(ts / tb, 3),
                             "maps_equal_to_sequential": same},
+           "tune": {"batch_tiles": tile_variant},
            "form": "FP32 V-cycles in FP64 refinement, batched + graph-replayed; split-BF16 (x6) far field"}
     for h in cache.values():
         h.destroy()

@@ -448,7 +448,7 @@ ffmg_status mg_profile_durations(ffmg_handle *h, int kernel, double *ms, int64_t
  * variant for handles without the LDS tail (3D, tile_config != 0) and for the
  * learned smoother.  FFMG_TUNE_SMOOTH: the tile height of the fused 2D
  * smoothing kernel on the finest level (8, 16 or 4 rows of 64 points for
- * variants 0, 1, 2; the batched path keeps 8); FFMG_TUNE_SMOOTH_COARSE: the
+ * variants 0, 1, 2; the batched path has its own, FFMG_TUNE_BATCH); FFMG_TUNE_SMOOTH_COARSE: the
  * same on the coarser levels, where the one-pass pre-smoothing follows it
  * (16 rows with the 16-row variant, else 8); one variant each for 3D and
  * tile_config 1.
@@ -465,6 +465,11 @@ ffmg_status mg_profile_durations(ffmg_handle *h, int kernel, double *ms, int64_t
  * interpolates the coarse correction and the variant-0 tiles for the others
  * (variant 3), or one pass per sweep (variant 1); one variant for 2D and
  * tile_config 1.
+ * FFMG_TUNE_BATCH (set on the first handle of a batch, 2D FFMG_FP32_IR fused
+ * handles): the tile heights of mg_solve_batched's smoothing and one-pass
+ * pre-smoothing launches, (8, 16) rows (variant 0), (4, 16) (1), (16, 16) (2)
+ * or (8, 8) (3); the same bits with every variant; a batch built with another
+ * variant is rebuilt.  Tuned by timing mg_solve_batched (the autotuner).
  * mg_tune_variants returns the number of variants (0 for an unknown
  * tunable); mg_tune_get / mg_tune_set read and select one (a cached choice).
  * mg_tune_farfield builds the integrand of (eta, u) for the n_dirs
@@ -483,7 +488,8 @@ typedef enum {
     FFMG_TUNE_SMOOTH = 2,
     FFMG_TUNE_PRE = 3,
     FFMG_TUNE_SMOOTH_COARSE = 4,
-    FFMG_TUNE_SWEEP3D = 5
+    FFMG_TUNE_SWEEP3D = 5,
+    FFMG_TUNE_BATCH = 6
 } ffmg_tunable;
 int mg_tune_variants(const ffmg_handle *h, int tunable);
 ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant);

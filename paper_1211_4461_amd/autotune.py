@@ -110,3 +110,40 @@ def tune_solve(h: "ffmg.Handle", b, u, precision: int, tol: float = 1e-10, path:
     cache[k] = {"variant": best, "ms": [round(t, 4) for t in times]}
     save(cache, path)
     return best
+
+
+def tune_batch(hs, etas, us, tol: float = 1e-6, path: Optional[str] = None, reps: int = 3,
+               force: bool = False) -> int:
+    """Select the tile heights of batched solves led by hs[0]
+    (FFMG_TUNE_BATCH): from the cache, or by timing reps batched solves per
+    variant after one untimed solve (then cached; us is overwritten).  The
+    key holds the instances' grids and the number of instances.  Returns the
+    variant."""
+    import time
+    import torch
+    h0 = hs[0]
+    nv = ffmg.mg_tune_variants(h0, ffmg.TUNE_BATCH)
+    if nv <= 1:
+        return 0
+    shape = sorted(int(h.level_shape(0)[0]) for h in hs)
+    k = key(device_arch(), ffmg.TUNE_BATCH, 2, shape, len(hs), ffmg.FP32_IR, nv, getattr(h0, "options", None))
+    cache = load(path)
+    hit = cache.get(k)
+    if not force and isinstance(hit, dict) and isinstance(hit.get("variant"), int) and 0 <= hit["variant"] < nv:
+        ffmg.mg_tune_set(h0, hit["variant"], ffmg.TUNE_BATCH)
+        return hit["variant"]
+    times = []
+    for v in range(nv):
+        ffmg.mg_tune_set(h0, v, ffmg.TUNE_BATCH)
+        ffmg.mg_solve_batched(hs, etas, us, tol=tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ffmg.mg_solve_batched(hs, etas, us, tol=tol)
+        torch.cuda.synchronize()
+        times.append(1e3 * (time.perf_counter() - t0) / reps)
+    best = int(min(range(nv), key=lambda v: times[v]))
+    ffmg.mg_tune_set(h0, best, ffmg.TUNE_BATCH)
+    cache[k] = {"variant": best, "ms": [round(t, 4) for t in times]}
+    save(cache, path)
+    return best

@@ -43,6 +43,7 @@ struct Batch {
     std::vector<uint64_t> key;
     std::vector<BatchInst> inst;
     int count = 0, Dmax = 0, nu1 = 0, nu2 = 0, inner = 0;
+    int variant = 0, th_smooth = 8, th_srr = 16;   // FFMG_TUNE_BATCH and its tile heights
     size_t tail_lds = 0;
     int max_nb_norm = 0, max_nb_res = 0, ref_ntiles = 0;
     int last_steps = 0;
@@ -136,7 +137,7 @@ void add_smooth(Plan &pl, std::vector<LaunchRec> &out, Batch &B, const std::vect
         BatchInst &I = B.inst[e.i];
         Level &lv = I.op->L[e.l];
         int tx;
-        int nt = smooth2d_tiles<float>(lv.g, &tx);
+        int nt = smooth2d_tiles<float>(lv.g, &tx, B.th_smooth);
         SmoothJob<float> j;
         j.u = e.src;
         j.ec = e.ec;
@@ -172,7 +173,7 @@ void add_srr(Plan &pl, std::vector<LaunchRec> &out, Batch &B, const std::vector<
         const int l = e.second;
         Level &lv = I.op->L[l];
         int tx;
-        int nt = smooth_rr2d_tiles<float>(lv.g, &tx);
+        int nt = smooth_rr2d_tiles<float>(lv.g, &tx, B.th_srr);
         SRRJob<float> j;
         j.u = I.u32[l];
         j.b = I.b32[l];
@@ -315,10 +316,11 @@ void enqueue_cycle(const Batch &B, const std::vector<LaunchRec> &recs, const Smo
 {
     for (const LaunchRec &r : recs) {
         if (r.kind == 3)
-            launch_smooth_rr2d_batch<float>(r.zero, srj + r.job_off, tile_job + r.tj_off, r.ntiles, B.stream);
+            launch_smooth_rr2d_batch<float>(r.zero, srj + r.job_off, tile_job + r.tj_off, r.ntiles, B.stream,
+                                            B.th_srr);
         else if (r.kind == 0)
             launch_smooth2d_batch<float>(r.ns, r.zero, r.prol, sj + r.job_off, tile_job + r.tj_off, r.ntiles,
-                                         B.stream);
+                                         B.stream, B.th_smooth);
         else if (r.kind == 1)
             launch_resid_restrict2d_batch<float>(rj + r.job_off, tile_job + r.tj_off, r.ntiles, B.stream);
         else
@@ -336,6 +338,8 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
         return s;
     };
     B.count = count;
+    B.variant = h0->batch_variant;
+    batch_tiles(B.variant, &B.th_smooth, &B.th_srr);
     const ffmg_options &o0 = h0->opt;
     B.nu1 = o0.nu1;
     B.nu2 = o0.nu2;
@@ -485,7 +489,7 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
     // the workspace and graph are cached on hs[0] for this list of handles
     std::vector<uint64_t> key;
     for (int i = 0; i < count; ++i) key.push_back(hs[i]->serial);
-    if (!h0->batch || h0->batch->key != key) {
+    if (!h0->batch || h0->batch->key != key || h0->batch->variant != h0->batch_variant) {
         if (h0->batch) batch_destroy(h0->batch);
         h0->batch = nullptr;
         TRY(build_batch(hs, count, &h0->batch));

@@ -1527,6 +1527,10 @@ int mg_tune_variants(const ffmg_handle *h, int tunable)
     case FFMG_TUNE_SMOOTH_COARSE:
         return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
     case FFMG_TUNE_SWEEP3D: return (h->prob.dim == 3 && h->opt.tile_config != TILE_REFERENCE) ? 4 : 1;
+    case FFMG_TUNE_BATCH:
+        return (h->prob.dim == 2 && h->opt.precision == FFMG_FP32_IR && h->opt.tile_config == TILE_FUSED)
+                   ? BATCH_TUNE_VARIANTS
+                   : 1;
     default: return 0;
     }
 }
@@ -1545,6 +1549,7 @@ ffmg_status mg_tune_get(const ffmg_handle *h, int tunable, int *variant)
     case FFMG_TUNE_PRE: *variant = h->pre_variant; return FFMG_OK;
     case FFMG_TUNE_SMOOTH_COARSE: *variant = h->smooth_coarse_variant; return FFMG_OK;
     case FFMG_TUNE_SWEEP3D: *variant = h->sweep3d_variant; return FFMG_OK;
+    case FFMG_TUNE_BATCH: *variant = h->batch_variant; return FFMG_OK;
     default: return FFMG_EINVAL;
     }
 }
@@ -1566,6 +1571,7 @@ ffmg_status mg_tune_set(ffmg_handle *h, int tunable, int variant)
     case FFMG_TUNE_PRE: h->pre_variant = variant; return FFMG_OK;
     case FFMG_TUNE_SMOOTH_COARSE: h->smooth_coarse_variant = variant; return FFMG_OK;
     case FFMG_TUNE_SWEEP3D: h->sweep3d_variant = variant; return FFMG_OK;
+    case FFMG_TUNE_BATCH: h->batch_variant = variant; return FFMG_OK;
     default: return fail(h, FFMG_EINVAL, "unknown tunable %d", tunable);
     }
 }

@@ -59,9 +59,13 @@ __device__ __forceinline__ cx<T> interp2d(const cx<T> *ec, int ld, int ox, int o
 }
 
 // Tile heights of the smoothing kernel (rows of 64 points): a tunable of the
-// handle (FFMG_TUNE_SMOOTH); the batched path uses SMOOTH_TH_BATCH.  Every
+// handle (FFMG_TUNE_SMOOTH); the batched path its own (FFMG_TUNE_BATCH).  Every
 // height computes the same bits.
-constexpr int SMOOTH_TH_BATCH = 8;
+// (smoothing, one-pass pre-smoothing) tile heights of the batched path, by
+// FFMG_TUNE_BATCH variant
+constexpr int BATCH_TILES[][2] = {{8, 16}, {4, 16}, {16, 16}, {8, 8}};
+constexpr int BATCH_VARIANTS = (int)(sizeof(BATCH_TILES) / sizeof(BATCH_TILES[0]));
+static_assert(BATCH_VARIANTS == BATCH_TUNE_VARIANTS, "batch tile table");
 
 // k_smooth2d runs in four phases separated by barriers:
 //   1. every global load of the block is issued together (fully unrolled
@@ -949,27 +953,24 @@ template void launch_tail2d<float>(const TailParams<float> &, size_t, const cf *
 // partial sum are those of the single-instance launch (block b of that launch
 // owns tile xcd_tile(b, n) and writes partial[b]), so the results, sums
 // included, are bit for bit those of one launch per instance.
-template <typename T, int NS, bool ZERO, bool PROL>
+template <typename T, int NS, bool ZERO, bool PROL, int TH>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_smooth2d_batch(const SmoothJob<T> *__restrict__ jobs,
                                                         const int *__restrict__ tile_job)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const SmoothJob<T> J = jobs[tile_job[t]];
     if (J.stop && *J.stop) return;
-    smooth2d_body<T, NS, ZERO, PROL, SMOOTH_TH_BATCH>(J.u, J.ec, J.b, J.q, J.out, J.P, J.tiles_x, t - J.tile0);
+    smooth2d_body<T, NS, ZERO, PROL, TH>(J.u, J.ec, J.b, J.q, J.out, J.P, J.tiles_x, t - J.tile0);
 }
 
-// one-pass pre-smoothing tile height of the batched path
-constexpr int SMOOTH_RR_BATCH = 16;
-
-template <typename T, bool ZERO>
+template <typename T, bool ZERO, int TH>
 __global__ __launch_bounds__(256) void k_smooth_rr2d_batch(const SRRJob<T> *__restrict__ jobs,
                                                            const int *__restrict__ tile_job)
 {
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const SRRJob<T> J = jobs[tile_job[t]];
     if (J.stop && *J.stop) return;
-    smooth_rr2d_body<T, ZERO, SMOOTH_RR_BATCH>(J.u, J.b, J.q, J.out, J.bc, J.P, J.tiles_x, t - J.tile0);
+    smooth_rr2d_body<T, ZERO, TH>(J.u, J.b, J.q, J.out, J.bc, J.P, J.tiles_x, t - J.tile0);
 }
 
 template <typename T>
@@ -1002,23 +1003,30 @@ __global__ __launch_bounds__(1024) void k_tail2d_batch(const TailJob<T> *__restr
     tail2d_body<T>(J.tp, J.b_top, J.u_top, reinterpret_cast<cx<T> *>(tail_lds_b));
 }
 
-template <typename T>
-int smooth2d_tiles(const LevelGeom &g, int *tiles_x)
+void batch_tiles(int variant, int *th_smooth, int *th_srr)
 {
-    *tiles_x = (g.m[0] + FTX - 1) / FTX;
-    return *tiles_x * ((g.m[1] + SMOOTH_TH_BATCH - 1) / SMOOTH_TH_BATCH);
+    const int v = (variant >= 0 && variant < BATCH_VARIANTS) ? variant : 0;
+    *th_smooth = BATCH_TILES[v][0];
+    *th_srr = BATCH_TILES[v][1];
 }
-template int smooth2d_tiles<double>(const LevelGeom &, int *);
-template int smooth2d_tiles<float>(const LevelGeom &, int *);
 
 template <typename T>
-int smooth_rr2d_tiles(const LevelGeom &g, int *tiles_x)
+int smooth2d_tiles(const LevelGeom &g, int *tiles_x, int th)
 {
     *tiles_x = (g.m[0] + FTX - 1) / FTX;
-    return *tiles_x * ((g.m[1] + SMOOTH_RR_BATCH - 1) / SMOOTH_RR_BATCH);
+    return *tiles_x * ((g.m[1] + th - 1) / th);
 }
-template int smooth_rr2d_tiles<double>(const LevelGeom &, int *);
-template int smooth_rr2d_tiles<float>(const LevelGeom &, int *);
+template int smooth2d_tiles<double>(const LevelGeom &, int *, int);
+template int smooth2d_tiles<float>(const LevelGeom &, int *, int);
+
+template <typename T>
+int smooth_rr2d_tiles(const LevelGeom &g, int *tiles_x, int th)
+{
+    *tiles_x = (g.m[0] + FTX - 1) / FTX;
+    return *tiles_x * ((g.m[1] + th - 1) / th);
+}
+template int smooth_rr2d_tiles<double>(const LevelGeom &, int *, int);
+template int smooth_rr2d_tiles<float>(const LevelGeom &, int *, int);
 
 int resid_restrict2d_tiles(const LevelGeom &g, int *ctiles_x)
 {
@@ -1029,13 +1037,12 @@ int resid_restrict2d_tiles(const LevelGeom &g, int *ctiles_x)
 
 int refine2d_tiles(const LevelGeom &g, int *tiles_x) { return tiles2d(g, *tiles_x); }
 
-template <typename T>
-void launch_smooth2d_batch(int nsweeps, bool zero, bool prol, const SmoothJob<T> *jobs, const int *tile_job,
-                           int ntiles, hipStream_t s)
+template <typename T, int TH>
+static void launch_smooth2d_batch_th(int nsweeps, bool zero, bool prol, const SmoothJob<T> *jobs, const int *tile_job,
+                                     int ntiles, hipStream_t s)
 {
-    if (ntiles <= 0) return;
     dim3 G(ntiles), B(256);
-#define SMB(NS, Z, PR) hipLaunchKernelGGL((k_smooth2d_batch<T, NS, Z, PR>), G, B, 0, s, jobs, tile_job)
+#define SMB(NS, Z, PR) hipLaunchKernelGGL((k_smooth2d_batch<T, NS, Z, PR, TH>), G, B, 0, s, jobs, tile_job)
     if (nsweeps == 2) {
         if (zero) SMB(2, true, false);
         else if (prol) SMB(2, false, true);
@@ -1047,21 +1054,37 @@ void launch_smooth2d_batch(int nsweeps, bool zero, bool prol, const SmoothJob<T>
     }
 #undef SMB
 }
-template void launch_smooth2d_batch<float>(int, bool, bool, const SmoothJob<float> *, const int *, int, hipStream_t);
-template void launch_smooth2d_batch<double>(int, bool, bool, const SmoothJob<double> *, const int *, int,
-                                            hipStream_t);
 
 template <typename T>
-void launch_smooth_rr2d_batch(bool zero, const SRRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s)
+void launch_smooth2d_batch(int nsweeps, bool zero, bool prol, const SmoothJob<T> *jobs, const int *tile_job,
+                           int ntiles, hipStream_t s, int th)
 {
     if (ntiles <= 0) return;
-    if (zero)
-        hipLaunchKernelGGL((k_smooth_rr2d_batch<T, true>), dim3(ntiles), dim3(256), 0, s, jobs, tile_job);
-    else
-        hipLaunchKernelGGL((k_smooth_rr2d_batch<T, false>), dim3(ntiles), dim3(256), 0, s, jobs, tile_job);
+    if (th == 4) launch_smooth2d_batch_th<T, 4>(nsweeps, zero, prol, jobs, tile_job, ntiles, s);
+    else if (th == 16) launch_smooth2d_batch_th<T, 16>(nsweeps, zero, prol, jobs, tile_job, ntiles, s);
+    else launch_smooth2d_batch_th<T, 8>(nsweeps, zero, prol, jobs, tile_job, ntiles, s);
 }
-template void launch_smooth_rr2d_batch<float>(bool, const SRRJob<float> *, const int *, int, hipStream_t);
-template void launch_smooth_rr2d_batch<double>(bool, const SRRJob<double> *, const int *, int, hipStream_t);
+template void launch_smooth2d_batch<float>(int, bool, bool, const SmoothJob<float> *, const int *, int, hipStream_t,
+                                           int);
+template void launch_smooth2d_batch<double>(int, bool, bool, const SmoothJob<double> *, const int *, int,
+                                            hipStream_t, int);
+
+template <typename T>
+void launch_smooth_rr2d_batch(bool zero, const SRRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s, int th)
+{
+    if (ntiles <= 0) return;
+#define SRB(Z, TH) hipLaunchKernelGGL((k_smooth_rr2d_batch<T, Z, TH>), dim3(ntiles), dim3(256), 0, s, jobs, tile_job)
+    if (th == 8) {
+        if (zero) SRB(true, 8);
+        else SRB(false, 8);
+    } else {
+        if (zero) SRB(true, 16);
+        else SRB(false, 16);
+    }
+#undef SRB
+}
+template void launch_smooth_rr2d_batch<float>(bool, const SRRJob<float> *, const int *, int, hipStream_t, int);
+template void launch_smooth_rr2d_batch<double>(bool, const SRRJob<double> *, const int *, int, hipStream_t, int);
 
 template <typename T>
 void launch_resid_restrict2d_batch(const RRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s)

@@ -295,18 +295,22 @@ struct TailJob {
     cx<T> *u_top;
     const int *stop;
 };
-// Tile counts (and tiles per row) of the fused kernels on a level.
+// Tile counts (and tiles per row) of the fused kernels on a level, for a
+// tile height th (the batched path's heights: batch_tiles of its variant).
 template <typename T>
-int smooth2d_tiles(const LevelGeom &g, int *tiles_x);
+int smooth2d_tiles(const LevelGeom &g, int *tiles_x, int th);
 int resid_restrict2d_tiles(const LevelGeom &g, int *ctiles_x);
 template <typename T>
-int smooth_rr2d_tiles(const LevelGeom &g, int *tiles_x);
+int smooth_rr2d_tiles(const LevelGeom &g, int *tiles_x, int th);
 int refine2d_tiles(const LevelGeom &g, int *tiles_x);
+constexpr int BATCH_TUNE_VARIANTS = 4;
+void batch_tiles(int variant, int *th_smooth, int *th_srr);
 template <typename T>
 void launch_smooth2d_batch(int nsweeps, bool zero, bool prol, const SmoothJob<T> *jobs, const int *tile_job,
-                           int ntiles, hipStream_t s);
+                           int ntiles, hipStream_t s, int th);
 template <typename T>
-void launch_smooth_rr2d_batch(bool zero, const SRRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s);
+void launch_smooth_rr2d_batch(bool zero, const SRRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s,
+                              int th);
 template <typename T>
 void launch_resid_restrict2d_batch(const RRJob<T> *jobs, const int *tile_job, int ntiles, hipStream_t s);
 void launch_refine2d_batch(const RefineJob *jobs, const int *tile_job, int ntiles, hipStream_t s);

@@ -456,6 +456,7 @@ TUNE_SMOOTH = 2
 TUNE_PRE = 3
 TUNE_SMOOTH_COARSE = 4
 TUNE_SWEEP3D = 5
+TUNE_BATCH = 6
 
 
 def _etas(etas):

@@ -72,6 +72,38 @@ def test_batch_equals_single_solves(ff, orc, sizes):
     assert rel(us[-1].cpu().numpy(), uo) < 1e-8
 
 
+def test_batch_tile_variants_and_tuning(ff, orc, tmp_path):
+    """Every FFMG_TUNE_BATCH variant (tile heights of the batched smoothing
+    launches) gives the same bits (the batch is rebuilt when the variant
+    changes); the autotuner times them, keeps one and applies the cached
+    choice to another batch led by the same operator."""
+    from paper_1211_4461_amd import autotune
+    insts = W.schrodinger_batch(seed=3, n_dirs=4, sizes=(128, 256, 512), M=24)
+    hs, cache = operators(ff, insts)
+    etas = [w.eta for w in insts]
+    nv = ff.mg_tune_variants(hs[0], ff.TUNE_BATCH)
+    assert nv == 4
+    ref = None
+    for v in range(nv):
+        ff.mg_tune_set(hs[0], v, ff.TUNE_BATCH)
+        us = [torch.full(w.shape, 3.0, dtype=torch.complex128, device="cuda") for w in insts]
+        infos = ff.mg_solve_batched(hs, etas, us, tol=1e-10)
+        if ref is None:
+            ref = ([u.clone() for u in us], [i.cycles for i in infos])
+        else:
+            assert [i.cycles for i in infos] == ref[1], v
+            assert all(torch.equal(a, b) for a, b in zip(us, ref[0])), v
+    path = str(tmp_path / "tune.json")
+    us = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for w in insts]
+    best = autotune.tune_batch(hs, etas, us, tol=1e-6, path=path, reps=2)
+    assert 0 <= best < nv and ff.mg_tune_get(hs[0], ff.TUNE_BATCH) == best
+    ff.mg_tune_set(hs[0], (best + 1) % nv, ff.TUNE_BATCH)
+    assert autotune.tune_batch(hs, etas, us, tol=1e-6, path=path) == best
+    assert ff.mg_tune_get(hs[0], ff.TUNE_BATCH) == best
+    for h in cache.values():
+        h.destroy()
+
+
 def test_batch_reuse_and_far_fields(ff, orc):
     """A second call with new directions reuses the graph; batched far fields
     equal per-instance maps; a different handle list rebuilds the batch."""
