@@ -318,22 +318,22 @@ ffmg_status farfield_map_noalloc(ffmg_handle *h, const double eta[3], const void
  * device) scattered by the operator of handle hs[i]; handles may repeat
  * (several directions of one energy and grid) and may differ in grid size
  * (e.g. the Schroedinger maps of Sec. 5 at several energies on 255^2 ..
- * 1023^2 grids).  Every instance is solved from u = 0 to
- * ||b - A u||_2 <= tol ||b||_2 with the FP32-in-FP64 refinement of mg_solve,
+ * 1023^2 grids).  Every instance is solved to ||b - A u||_2 <= tol ||b||_2
+ * with the FP32-in-FP64 refinement of mg_solve, from u = 0 or, with
+ * options.fmg_cycles = k > 0, from the full multigrid start F(k) (Sec. 4;
+ * the batch runs every instance's start together, level by level),
  * and its result u[i] (DEVICE complex128[N_i], output) and info (infos[i],
  * may be NULL) equal those of mg_solve on that handle bit for bit.  All
  * instances advance together: one launch per kernel for the whole batch, the
  * refinement step captured once in a HIP graph and replayed until every
  * instance has met its stopping test on the device.  Requirements (EINVAL
  * otherwise): 2D handles set up with precision FFMG_FP32_IR and tile_config
- * 0, all with the same nu1 >= 1, nu2 >= 1 and inner cycles and the same
- * coarse-level shapes (grids n = 2^k on one coarsest_n).  The workspace and
+ * 0, all with the same nu1 >= 1, nu2 >= 1, inner cycles and fmg_cycles and
+ * the same coarse-level shapes (grids n = 2^k on one coarsest_n).  The workspace and
  * graph are owned by hs[0] (freed by mg_destroy(hs[0])) and reused while the
  * same list of handles is passed; the call is ordered after work on hs[0]'s
  * stream and synchronises.  Returns ENOCONV if an instance did not converge
- * (infos tells which), ENAN if a right-hand side is not finite.  Handles
- * with options.fmg_cycles > 0 are refused (EINVAL): the batch starts from
- * u = 0. */
+ * (infos tells which), ENAN if a right-hand side is not finite. */
 ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *etas, void *const *u, double tol,
                              ffmg_solve_info *infos);
 

@@ -44,12 +44,18 @@ struct Batch {
     std::vector<BatchInst> inst;
     int count = 0, Dmax = 0, nu1 = 0, nu2 = 0, inner = 0;
     int variant = 0, th_smooth = 8, th_srr = 16;   // FFMG_TUNE_BATCH and its tile heights
+    int fmg = 0;                          // V-cycles per level of the full multigrid start (0: u = 0)
     size_t tail_lds = 0;
     int max_nb_norm = 0, max_nb_res = 0, ref_ntiles = 0;
     int last_steps = 0;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraph_t fmg_graph = nullptr;       // the full multigrid start of every instance
+    hipGraphExec_t fmg_exec = nullptr;
+    XferJob *d_xfin = nullptr;            // its last transfer, into the caller's u (written per call)
+    std::vector<XferJob> xfin;
+    size_t max_n0 = 0;
     std::vector<void *> allocs;
     InitJob *d_init = nullptr;
     CtlJob *d_ctl0 = nullptr, *d_ctl = nullptr;
@@ -74,6 +80,8 @@ struct Batch {
         if (stream) (void)hipStreamSynchronize(stream);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (fmg_exec) (void)hipGraphExecDestroy(fmg_exec);
+        if (fmg_graph) (void)hipGraphDestroy(fmg_graph);
         for (void *p : allocs) (void)hipFree(p);
         if (h_ndone) (void)hipHostFree(h_ndone);
         if (h_ctls) (void)hipHostFree(h_ctls);
@@ -95,12 +103,14 @@ namespace {
 
 // Host-side lists of the level launches of one FP32 V-cycle; uploaded once.
 struct LaunchRec {
-    int kind;            // 0 smooth, 1 resid+restrict, 2 tail, 3 one-pass pre-smoothing + resid + restrict
-    int ns = 0;          // smooth: sweeps in this launch
+    int kind;            // 0 smooth, 1 resid+restrict, 2 tail, 3 one-pass pre-smoothing + resid + restrict,
+                         // 4 grid transfer of the start, 5 the tail's full multigrid start
+    int ns = 0;          // smooth: sweeps in this launch; transfer: its kind; tail start: cycles per level
     bool zero = false, prol = false;
     size_t job_off = 0;  // index into the typed job array
     size_t tj_off = 0;   // index into tile_job
-    int ntiles = 0;      // tiles (or jobs for the tail)
+    int ntiles = 0;      // tiles (or jobs for the tail and the transfers)
+    size_t max_n = 0;    // transfer: largest output grid
 };
 
 struct Plan {
@@ -111,6 +121,9 @@ struct Plan {
     std::vector<int> tile_job;
     std::vector<LaunchRec> recs;   // one inner V-cycle with the finest guess nonzero
     std::vector<LaunchRec> recs0;  // the first inner V-cycle (zero finest guess)
+    std::vector<XferJob> xj;
+    std::vector<TailJob<float>> tfj;
+    std::vector<LaunchRec> fmg;    // the full multigrid start up to level 1
 };
 
 // Append one smooth launch over the given (instance, level, src, dst, ec, zero) entries.
@@ -193,20 +206,29 @@ void add_srr(Plan &pl, std::vector<LaunchRec> &out, Batch &B, const std::vector<
     out.push_back(r);
 }
 
-// The launches of one inner V-cycle (c = 0: zero guess on the finest level).
-void build_cycle(Plan &pl, std::vector<LaunchRec> &out, Batch &B, bool first)
+// The launches of one V-cycle.  S = 0: the inner V-cycle of a refinement
+// step from each instance's finest level (first: zero guess there).  S >= 1:
+// a V-cycle of the full multigrid start rooted at step S, i.e. at level
+// S - (Dmax - D) >= 1 of each instance that has that level, with the
+// interpolated coarser solution as its guess.
+void build_cycle(Plan &pl, std::vector<LaunchRec> &out, Batch &B, bool first, int S = 0)
 {
     const int Dmax = B.Dmax, n = B.count;
-    auto level_of = [&](int i, int s) { return s - (Dmax - B.inst[i].D); };   // < 0: not active
+    auto root_of = [&](int i) { return S == 0 ? 0 : S - (Dmax - B.inst[i].D); };
+    auto in_cycle = [&](int i) { return S == 0 || root_of(i) >= 1; };
+    auto level_of = [&](int i, int s) {   // < 0: not active at step s
+        const int l = s - (Dmax - B.inst[i].D);
+        return (in_cycle(i) && l >= root_of(i)) ? l : -1;
+    };
     // down-sweep
-    for (int s = 0; s < Dmax; ++s) {
+    for (int s = S; s < Dmax; ++s) {
         if (B.nu1 == 2) {
             // two sweeps, residual and restriction in one pass: u -> t, b_c
             std::vector<std::pair<int, int>> ez, enz;
             for (int i = 0; i < n; ++i) {
                 const int l = level_of(i, s);
                 if (l < 0) continue;
-                ((l > 0 || first) ? ez : enz).push_back({i, l});
+                ((l > root_of(i) || first) ? ez : enz).push_back({i, l});
             }
             add_srr(pl, out, B, ez, true);
             add_srr(pl, out, B, enz, false);
@@ -227,7 +249,7 @@ void build_cycle(Plan &pl, std::vector<LaunchRec> &out, Batch &B, bool first)
                 const cf *src;
                 if (kk == 0) src = I.u32[l];
                 else src = ((nk - 1 - (kk - 1)) % 2 == 0) ? I.t32[l] : I.r32[l];
-                const bool zero = (kk == 0) && (l > 0 || first);
+                const bool zero = (kk == 0) && (l > root_of(i) || first);
                 (zero ? ez : enz).push_back(SmoothEntry{i, l, src, dst, nullptr});
             }
             add_smooth(pl, out, B, ez, ns, true, false);
@@ -268,8 +290,10 @@ void build_cycle(Plan &pl, std::vector<LaunchRec> &out, Batch &B, bool first)
         LaunchRec r;
         r.kind = 2;
         r.job_off = pl.tj.size();
-        r.ntiles = n;
+        r.ntiles = 0;
         for (int i = 0; i < n; ++i) {
+            if (!in_cycle(i)) continue;
+            ++r.ntiles;
             BatchInst &I = B.inst[i];
             TailJob<float> j;
             j.tp = I.op->tail32;
@@ -281,7 +305,7 @@ void build_cycle(Plan &pl, std::vector<LaunchRec> &out, Batch &B, bool first)
         out.push_back(r);
     }
     // up-sweep: interpolation + post-smoothing chain t -> u (tmp r)
-    for (int s = Dmax - 1; s >= 0; --s) {
+    for (int s = Dmax - 1; s >= S; --s) {
         const int nk = (B.nu2 + 1) / 2;
         int left = B.nu2;
         for (int kk = 0; kk < nk; ++kk) {
@@ -303,6 +327,92 @@ void build_cycle(Plan &pl, std::vector<LaunchRec> &out, Batch &B, bool first)
     }
 }
 
+// One transfer launch of the start over the given jobs.
+void add_xfer(Plan &pl, std::vector<LaunchRec> &out, int kind, const std::vector<XferJob> &js)
+{
+    if (js.empty()) return;
+    LaunchRec r;
+    r.kind = 4;
+    r.ns = kind;
+    r.job_off = pl.xj.size();
+    r.ntiles = (int)js.size();
+    for (const XferJob &j : js) {
+        const size_t n = (kind <= 1) ? (size_t)j.mxc * j.myc : (size_t)j.mxf * j.myf;
+        r.max_n = std::max(r.max_n, n);
+        pl.xj.push_back(j);
+    }
+    out.push_back(r);
+}
+
+XferJob xfer_job(const BatchInst &I, int l, const void *src, void *dst, bool f64_end)
+{
+    const LevelGeom &f = I.op->L[l].g, &c = I.op->L[l + 1].g;
+    XferJob j;
+    j.src = src;
+    j.dst = dst;
+    j.mxf = f.m[0];
+    j.myf = f.m[1];
+    j.mxc = c.m[0];
+    j.myc = c.m[1];
+    j.bnorm2 = f64_end ? &I.ctl->b2 : nullptr;
+    j.inv_sqN = 1.0 / sqrt((double)I.op->L[0].g.N());
+    j.stop = &I.ctl->done;
+    return j;
+}
+
+// The full multigrid start of every instance in the order of the
+// single-instance start: the finest right-hand side (scaled to unit RMS)
+// injected level by level down to the first tail level, the tails' nested
+// iteration, then level by level finest-ward the interpolated coarser
+// solution and k V-cycles, down to level 1; the last interpolation (into
+// the caller's FP64 u) is added per call.
+void build_fmg(Plan &pl, Batch &B, int k)
+{
+    const int Dmax = B.Dmax, n = B.count;
+    std::vector<XferJob> js;
+    for (int i = 0; i < n; ++i) {
+        BatchInst &I = B.inst[i];
+        js.push_back(xfer_job(I, 0, I.b, I.b32[1], true));
+    }
+    add_xfer(pl, pl.fmg, 0, js);
+    for (int s = 1; s < Dmax; ++s) {
+        js.clear();
+        for (int i = 0; i < n; ++i) {
+            BatchInst &I = B.inst[i];
+            const int l = s - (Dmax - I.D);
+            if (l >= 1 && l < I.D) js.push_back(xfer_job(I, l, I.b32[l], I.b32[l + 1], false));
+        }
+        add_xfer(pl, pl.fmg, 1, js);
+    }
+    LaunchRec r;
+    r.kind = 5;
+    r.ns = k;
+    r.job_off = pl.tfj.size();
+    r.ntiles = n;
+    for (int i = 0; i < n; ++i) {
+        BatchInst &I = B.inst[i];
+        TailJob<float> j;
+        j.tp = I.op->tail32;
+        j.b_top = I.b32[I.D];
+        j.u_top = I.u32[I.D];
+        j.stop = &I.ctl->done;
+        pl.tfj.push_back(j);
+    }
+    pl.fmg.push_back(r);
+    for (int S = Dmax - 1; S >= 1; --S) {
+        js.clear();
+        for (int i = 0; i < n; ++i) {
+            BatchInst &I = B.inst[i];
+            const int l = S - (Dmax - I.D);
+            if (l >= 1) js.push_back(xfer_job(I, l, I.u32[l + 1], I.u32[l], false));
+        }
+        add_xfer(pl, pl.fmg, 2, js);
+        std::vector<LaunchRec> cyc;
+        build_cycle(pl, cyc, B, false, S);
+        for (int c = 0; c < k; ++c) pl.fmg.insert(pl.fmg.end(), cyc.begin(), cyc.end());
+    }
+}
+
 template <typename J>
 hipError_t upload(Batch &B, J **d, const std::vector<J> &h)
 {
@@ -311,11 +421,28 @@ hipError_t upload(Batch &B, J **d, const std::vector<J> &h)
     return hipMemcpy(*d, h.data(), h.size() * sizeof(J), hipMemcpyHostToDevice);
 }
 
-void enqueue_cycle(const Batch &B, const std::vector<LaunchRec> &recs, const SmoothJob<float> *sj,
-                   const RRJob<float> *rj, const TailJob<float> *tj, const SRRJob<float> *srj, const int *tile_job)
+struct DevPlan {
+    SmoothJob<float> *sj = nullptr;
+    RRJob<float> *rj = nullptr;
+    TailJob<float> *tj = nullptr, *tfj = nullptr;
+    SRRJob<float> *srj = nullptr;
+    XferJob *xj = nullptr;
+    int *tile_job = nullptr;
+};
+
+void enqueue_cycle(const Batch &B, const std::vector<LaunchRec> &recs, const DevPlan &d)
 {
+    const SmoothJob<float> *sj = d.sj;
+    const RRJob<float> *rj = d.rj;
+    const TailJob<float> *tj = d.tj;
+    const SRRJob<float> *srj = d.srj;
+    const int *tile_job = d.tile_job;
     for (const LaunchRec &r : recs) {
-        if (r.kind == 3)
+        if (r.kind == 4)
+            launch_xfer_batch(r.ns, d.xj + r.job_off, r.ntiles, r.max_n, B.stream);
+        else if (r.kind == 5)
+            launch_tail2d_fmg_batch<float>(d.tfj + r.job_off, r.ntiles, r.ns, B.tail_lds, B.stream);
+        else if (r.kind == 3)
             launch_smooth_rr2d_batch<float>(r.zero, srj + r.job_off, tile_job + r.tj_off, r.ntiles, B.stream,
                                             B.th_srr);
         else if (r.kind == 0)
@@ -344,6 +471,7 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
     B.nu1 = o0.nu1;
     B.nu2 = o0.nu2;
     B.inner = o0.inner_cycles > 0 ? o0.inner_cycles : DEFAULT_INNER_CYCLES;
+    B.fmg = o0.fmg_cycles;
     for (int i = 0; i < count; ++i) {
         ffmg_handle *h = hs[i];
         if (!h) return bail(fail(h0, FFMG_EINVAL, "hs[%d] is null", i));
@@ -353,9 +481,8 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
             return bail(fail(h0, FFMG_EINVAL,
                              "instance %d: batched solves need 2D operators set up with precision FP32_IR and the "
                              "fused kernels (tile_config 0)", i));
-        if (o.fmg_cycles != 0)
-            return bail(fail(h0, FFMG_EINVAL, "instance %d: batched solves start from u = 0 (fmg_cycles must be 0)",
-                             i));
+        if (o.fmg_cycles != o0.fmg_cycles || o.fmg_cycles < 0)
+            return bail(fail(h0, FFMG_EINVAL, "instance %d: every operator needs the same fmg_cycles", i));
         if (o.nu1 != B.nu1 || o.nu2 != B.nu2 || o.nu1 < 1 || o.nu2 < 1 ||
             (o.nu_coarse != 0 && (o.nu_coarse != o.nu1 || o.nu_coarse != o.nu2)) ||
             (o.inner_cycles > 0 ? o.inner_cycles : DEFAULT_INNER_CYCLES) != B.inner || o.smoother != FFMG_SMOOTH_JACOBI)
@@ -409,6 +536,7 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
     Plan pl;
     build_cycle(pl, pl.recs0, B, true);
     build_cycle(pl, pl.recs, B, false);
+    if (B.fmg > 0) build_fmg(pl, B, B.fmg);
     std::vector<CtlJob> c0, c1;
     std::vector<int> rtj;
     for (int i = 0; i < count; ++i) {
@@ -418,16 +546,14 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
         for (int t = 0; t < I.ref_tiles; ++t) rtj.push_back(i);
         B.ref_ntiles += I.ref_tiles;
     }
-    SmoothJob<float> *d_sj = nullptr;
-    RRJob<float> *d_rj = nullptr;
-    TailJob<float> *d_tj = nullptr;
-    SRRJob<float> *d_srj = nullptr;
-    int *d_tile_job = nullptr;
-    BCHK(upload(B, &d_sj, pl.sj));
-    BCHK(upload(B, &d_rj, pl.rj));
-    BCHK(upload(B, &d_tj, pl.tj));
-    BCHK(upload(B, &d_srj, pl.srj));
-    BCHK(upload(B, &d_tile_job, pl.tile_job));
+    DevPlan dp;
+    BCHK(upload(B, &dp.sj, pl.sj));
+    BCHK(upload(B, &dp.rj, pl.rj));
+    BCHK(upload(B, &dp.tj, pl.tj));
+    BCHK(upload(B, &dp.srj, pl.srj));
+    BCHK(upload(B, &dp.tile_job, pl.tile_job));
+    BCHK(upload(B, &dp.xj, pl.xj));
+    BCHK(upload(B, &dp.tfj, pl.tfj));
     BCHK(upload(B, &B.d_ctl0, c0));
     BCHK(upload(B, &B.d_ctl, c1));
     BCHK(upload(B, &B.d_ref_tile_job, rtj));
@@ -440,17 +566,24 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
     BCHK(B.alloc((void **)&B.d_refB, count * sizeof(RefineJob)));
     BCHK(B.alloc((void **)&B.d_finish, count * sizeof(FinishJob)));
     BCHK(B.alloc((void **)&B.d_ndone, sizeof(int)));
+    BCHK(B.alloc((void **)&B.d_xfin, count * sizeof(XferJob)));
+    B.xfin.resize(count);
+    for (int i = 0; i < count; ++i) {
+        B.xfin[i] = xfer_job(B.inst[i], 0, B.inst[i].u32[1], nullptr, true);
+        B.max_n0 = std::max(B.max_n0, B.inst[i].op->L[0].g.N());
+    }
     BCHK(hipHostMalloc((void **)&B.h_ndone, sizeof(int), hipHostMallocDefault));
     BCHK(hipHostMalloc((void **)&B.h_ctls, count * sizeof(SolveCtl), hipHostMallocDefault));
     BCHK(hipStreamCreateWithFlags(&B.stream, hipStreamNonBlocking));
-    // the tail kernel's LDS limit must be raised before capture
+    // the tail kernels' LDS limit must be raised before capture
     launch_tail2d_batch<float>(nullptr, 0, 0, B.stream);
+    launch_tail2d_fmg_batch<float>(nullptr, 0, 0, 0, B.stream);
     // the graph: two refinement steps (u -> t, t -> u) and the count of
     // finished instances
     BCHK(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
     for (int step = 0; step < 2; ++step) {
         for (int c = 0; c < B.inner; ++c)
-            enqueue_cycle(B, c == 0 ? pl.recs0 : pl.recs, d_sj, d_rj, d_tj, d_srj, d_tile_job);
+            enqueue_cycle(B, c == 0 ? pl.recs0 : pl.recs, dp);
         launch_refine2d_batch(step == 0 ? B.d_refA : B.d_refB, B.d_ref_tile_job, B.ref_ntiles, B.stream);
         launch_ctl_update_batch(B.d_ctl, count, B.stream);
     }
@@ -461,6 +594,19 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
         return bail(fail(h0, FFMG_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce)));
     }
     BCHK(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+    if (B.fmg > 0) {
+        // the start: its static part, then the interpolation into the
+        // caller's u from the job table written before each launch
+        BCHK(hipStreamBeginCapture(B.stream, hipStreamCaptureModeThreadLocal));
+        enqueue_cycle(B, pl.fmg, dp);
+        launch_xfer_batch(3, B.d_xfin, count, B.max_n0, B.stream);
+        ce = hipStreamEndCapture(B.stream, &B.fmg_graph);
+        if (ce != hipSuccess) {
+            (void)hipGetLastError();
+            return bail(fail(h0, FFMG_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce)));
+        }
+        BCHK(hipGraphInstantiate(&B.fmg_exec, B.fmg_graph, nullptr, nullptr, 0));
+    }
     *out = Bp;
     return FFMG_OK;
 }
@@ -544,6 +690,7 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
         R.u_out = (cd *)u[i];
         B.refB[i] = R;
         B.fin[i] = FinishJob{I.t, (cd *)u[i], I.ctl, g.N()};
+        B.xfin[i].dst = u[i];
     }
     hipEvent_t e0, e1, ein;
     BCHK(hipEventCreate(&e0));
@@ -556,8 +703,12 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
     BCHK(hipMemcpyAsync(B.d_refA, B.refA.data(), count * sizeof(RefineJob), hipMemcpyHostToDevice, B.stream));
     BCHK(hipMemcpyAsync(B.d_refB, B.refB.data(), count * sizeof(RefineJob), hipMemcpyHostToDevice, B.stream));
     BCHK(hipMemcpyAsync(B.d_finish, B.fin.data(), count * sizeof(FinishJob), hipMemcpyHostToDevice, B.stream));
+    if (B.fmg > 0)
+        BCHK(hipMemcpyAsync(B.d_xfin, B.xfin.data(), count * sizeof(XferJob), hipMemcpyHostToDevice, B.stream));
     BCHK(hipEventRecord(e0, B.stream));
-    launch_init_batch(B.d_init, count, B.max_nb_norm, B.max_nb_res, B.stream);
+    launch_init_batch(B.d_init, count, B.max_nb_norm, B.stream);
+    if (B.fmg > 0) BCHK(hipGraphLaunch(B.fmg_exec, B.stream));
+    launch_init_resid_batch(B.d_init, count, B.max_nb_res, B.stream);
     launch_ctl_update_batch(B.d_ctl0, count, B.stream);
     BCHK(hipGetLastError());
     int maxc = 0;

@@ -750,11 +750,9 @@ __device__ __forceinline__ void tail2d_body(const TailParams<T> &tp, const cx<T>
 // solve there, then on each level up to s0 the interpolated coarser solution
 // as the guess and k V-cycles; u_top receives level s0's solution.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_tail2d_fmg(TailParams<T> tp, const cx<T> *__restrict__ b_top,
-                                                     cx<T> *__restrict__ u_top, int s0, int k)
+__device__ __forceinline__ void tail2d_fmg_body(const TailParams<T> &tp, const cx<T> *__restrict__ b_top,
+                                                cx<T> *__restrict__ u_top, int s0, int k, cx<T> *lds)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds_f[];
-    cx<T> *lds = reinterpret_cast<cx<T> *>(tail_lds_f);
     const int nt = tp.nt;
     tail_load<T>(tp, b_top, lds, s0);
     for (int i = s0; i + 1 < nt; ++i) {
@@ -781,6 +779,14 @@ __global__ __launch_bounds__(1024) void k_tail2d_fmg(TailParams<T> tp, const cx<
         for (int c2 = 0; c2 < k; ++c2) tail_vcycle<T>(tp, lds, i, false);
     }
     tail_store<T>(tp, lds, s0, u_top);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail2d_fmg(TailParams<T> tp, const cx<T> *__restrict__ b_top,
+                                                     cx<T> *__restrict__ u_top, int s0, int k)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds_f[];
+    tail2d_fmg_body<T>(tp, b_top, u_top, s0, k, reinterpret_cast<cx<T> *>(tail_lds_f));
 }
 
 template <typename T>
@@ -1003,6 +1009,17 @@ __global__ __launch_bounds__(1024) void k_tail2d_batch(const TailJob<T> *__restr
     tail2d_body<T>(J.tp, J.b_top, J.u_top, reinterpret_cast<cx<T> *>(tail_lds_b));
 }
 
+// The full multigrid start of every tail in one launch (one workgroup per
+// job, from the first tail level).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_tail2d_fmg_batch(const TailJob<T> *__restrict__ jobs, int k)
+{
+    const TailJob<T> &J = jobs[blockIdx.x];
+    if (J.stop && *J.stop) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned char tail_lds_fb[];
+    tail2d_fmg_body<T>(J.tp, J.b_top, J.u_top, 0, k, reinterpret_cast<cx<T> *>(tail_lds_fb));
+}
+
 void batch_tiles(int variant, int *th_smooth, int *th_srr)
 {
     const int v = (variant >= 0 && variant < BATCH_VARIANTS) ? variant : 0;
@@ -1113,6 +1130,20 @@ void launch_tail2d_batch(const TailJob<T> *jobs, int njobs, size_t lds_bytes, hi
     if (njobs <= 0) return;
     hipLaunchKernelGGL((k_tail2d_batch<T>), dim3(njobs), dim3(1024), lds_bytes, s, jobs);
 }
+template <typename T>
+void launch_tail2d_fmg_batch(const TailJob<T> *jobs, int njobs, int k, size_t lds_bytes, hipStream_t s)
+{
+    // once per instantiation (a thread-safe static initialisation)
+    static const bool attr_set = [] {
+        (void)hipFuncSetAttribute((const void *)k_tail2d_fmg_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024);
+        return true;
+    }();
+    (void)attr_set;
+    if (njobs <= 0) return;
+    hipLaunchKernelGGL((k_tail2d_fmg_batch<T>), dim3(njobs), dim3(1024), lds_bytes, s, jobs, k);
+}
+template void launch_tail2d_fmg_batch<float>(const TailJob<float> *, int, int, size_t, hipStream_t);
 template void launch_tail2d_batch<float>(const TailJob<float> *, int, size_t, hipStream_t);
 template void launch_tail2d_batch<double>(const TailJob<double> *, int, size_t, hipStream_t);
 

@@ -316,6 +316,10 @@ void launch_resid_restrict2d_batch(const RRJob<T> *jobs, const int *tile_job, in
 void launch_refine2d_batch(const RefineJob *jobs, const int *tile_job, int ntiles, hipStream_t s);
 template <typename T>
 void launch_tail2d_batch(const TailJob<T> *jobs, int njobs, size_t lds_bytes, hipStream_t s);
+// the full multigrid start of each job's tail (from its first level), k
+// V-cycles per level
+template <typename T>
+void launch_tail2d_fmg_batch(const TailJob<T> *jobs, int njobs, int k, size_t lds_bytes, hipStream_t s);
 
 // Per-instance setup of a batched solve (ffmg_stencil.hip): plane-wave
 // right-hand side, zero guess, ||b||^2, control init and the initial scaled
@@ -345,10 +349,31 @@ struct FinishJob {
     const SolveCtl *ctl;
     size_t N;
 };
+// One 2D grid transfer of the batched full multigrid start (ffmg_stencil.hip),
+// with the arithmetic of the single-instance k_inject_rhs / k_inject /
+// k_prolong_set: injection of a right-hand side onto the next coarser level
+// (from the FP64 finest level: divided by the RMS scale), or the coarse
+// solution interpolated onto the next finer level (into the FP64 finest
+// level: multiplied by it).
+struct XferJob {
+    const void *src;
+    void *dst;
+    int mxf, myf, mxc, myc;   // fine and coarse interior extents
+    const double *bnorm2;     // ||b||^2 of the finest level when an FP64 end is involved, else null
+    double inv_sqN;           // 1 / sqrt(N) of the finest level
+    const int *stop;          // the instance's control flag: nonzero skips the job
+};
+// kind 0: FP64 -> FP32 right-hand-side injection; 1: FP32 injection;
+// 2: FP32 -> FP32 interpolation; 3: FP32 -> FP64 interpolation.  max_n: the
+// largest output grid among the jobs.
+void launch_xfer_batch(int kind, const XferJob *jobs, int njobs, size_t max_n, hipStream_t s);
 int norm2_blocks(size_t N);
 void launch_hash_fill(cd *out, size_t N, unsigned long long seed, hipStream_t s);
 void stencil_grid2d(const LevelGeom &g, int *nb, int *tiles_x);   // blocks and tiles per row of k_stencil2d
-void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_nb_res, hipStream_t s);
+// plane-wave right-hand side, u = 0, ||b||^2 and the control block
+void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, hipStream_t s);
+// the initial residual b - A u as the scaled FP32 right-hand side
+void launch_init_resid_batch(const InitJob *jobs, int n, int max_nb_res, hipStream_t s);
 void launch_ctl_update_batch(const CtlJob *jobs, int n, hipStream_t s);
 void launch_count_done(const CtlJob *jobs, int n, int *ndone, hipStream_t s);
 void launch_finish_batch(const FinishJob *jobs, int n, hipStream_t s);

@@ -1991,13 +1991,66 @@ __global__ __launch_bounds__(256) void k_finish_batch(const FinishJob *__restric
     for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < J.N; j += (size_t)gridDim.x * 256) J.u[j] = J.t[j];
 }
 
-void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_nb_res, hipStream_t s)
+void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_init_rhs_batch, dim3(1024, n), dim3(256), 0, s, jobs);
     hipLaunchKernelGGL(k_init_norm_batch, dim3(max_nb_norm, n), dim3(256), 0, s, jobs);
     hipLaunchKernelGGL(k_init_ctl_batch, dim3(n), dim3(256), 0, s, jobs);
-    hipLaunchKernelGGL(k_init_resid_batch, dim3(max_nb_res, n), dim3(256), 0, s, jobs);
+}
+
+void launch_init_resid_batch(const InitJob *jobs, int n, int max_nb_res, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_init_resid_batch, dim3(max_nb_res, n), dim3(256), 0, s, jobs);
+}
+
+// Batched full multigrid transfers (blockIdx.y = job), point for point the
+// arithmetic of k_inject_rhs, k_inject and k_prolong_set on a 2D level.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_xfer_batch(const XferJob *__restrict__ jobs)
+{
+    const XferJob &J = jobs[blockIdx.y];
+    if (J.stop && *J.stop) return;
+    const int mxf = J.mxf, mxc = J.mxc;
+    if constexpr (KIND <= 1) {
+        const size_t Nc = (size_t)mxc * J.myc;
+        for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < Nc; idx += (size_t)gridDim.x * 256) {
+            const int I = (int)(idx % mxc), K = (int)(idx / mxc);
+            const size_t f = (size_t)(2 * K + 1) * mxf + (2 * I + 1);
+            if constexpr (KIND == 0) {
+                const double inv = 1.0 / fmg_scale(J.bnorm2, J.inv_sqN);
+                const cd v = static_cast<const cd *>(J.src)[f];
+                static_cast<cf *>(J.dst)[idx] = cvt<float>(cd{v.re * inv, v.im * inv});
+            } else {
+                static_cast<cf *>(J.dst)[idx] = static_cast<const cf *>(J.src)[f];
+            }
+        }
+    } else {
+        const size_t Nf = (size_t)mxf * J.myf;
+        const cf *ec = static_cast<const cf *>(J.src);
+        for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < Nf; idx += (size_t)gridDim.x * 256) {
+            const int ix = (int)(idx % mxf), iy = (int)(idx / mxf);
+            const cf v = prolong_at<float, 2>(ec, ix, iy, 0, mxc, J.myc, 1);
+            if constexpr (KIND == 3) {
+                const double sc = fmg_scale(J.bnorm2, J.inv_sqN);
+                static_cast<cd *>(J.dst)[idx] = cd{(double)v.re * sc, (double)v.im * sc};
+            } else {
+                static_cast<cf *>(J.dst)[idx] = v;
+            }
+        }
+    }
+}
+
+void launch_xfer_batch(int kind, const XferJob *jobs, int njobs, size_t max_n, hipStream_t s)
+{
+    if (njobs <= 0 || max_n == 0) return;
+    const dim3 grid((unsigned)std::min<size_t>((max_n + 255) / 256, 1024), (unsigned)njobs);
+    switch (kind) {
+    case 0: hipLaunchKernelGGL(k_xfer_batch<0>, grid, dim3(256), 0, s, jobs); break;
+    case 1: hipLaunchKernelGGL(k_xfer_batch<1>, grid, dim3(256), 0, s, jobs); break;
+    case 2: hipLaunchKernelGGL(k_xfer_batch<2>, grid, dim3(256), 0, s, jobs); break;
+    default: hipLaunchKernelGGL(k_xfer_batch<3>, grid, dim3(256), 0, s, jobs); break;
+    }
 }
 
 void launch_ctl_update_batch(const CtlJob *jobs, int n, hipStream_t s)

@@ -72,6 +72,31 @@ def test_batch_equals_single_solves(ff, orc, sizes):
     assert rel(us[-1].cpu().numpy(), uo) < 1e-8
 
 
+@pytest.mark.parametrize("sizes,k", [((128, 256, 512), 1), ((256,), 2), ((128, 512), 1)])
+def test_batch_fmg_start_equals_single_solves(ff, orc, sizes, k):
+    """With the full multigrid start F(k) every instance of a batch (grids of
+    different depths: the starts of all instances run level by level
+    together) equals mg_solve with the same start bit for bit and converges
+    to the solution of the batch from u = 0."""
+    insts = W.schrodinger_batch(seed=4, n_dirs=3, sizes=sizes, M=24)
+    hs, cache = operators(ff, insts, fmg_cycles=k)
+    etas = [w.eta for w in insts]
+    us = [torch.full(w.shape, 5.0, dtype=torch.complex128, device="cuda") for w in insts]   # overwritten
+    infos = ff.mg_solve_batched(hs, etas, us, tol=1e-10)
+    hz, cz = operators(ff, insts)
+    uz = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for w in insts]
+    iz = ff.mg_solve_batched(hz, etas, uz, tol=1e-10)
+    for i, w in enumerate(insts):
+        u1, i1 = single(ff, hs[i], w, 1e-10)
+        torch.cuda.synchronize()
+        assert infos[i].status == 0 and infos[i].cycles == i1.cycles, (i, infos[i].cycles, i1.cycles)
+        assert infos[i].rel_residual == i1.rel_residual and infos[i].rel_residual <= 1e-10
+        assert torch.equal(us[i], u1), i
+        assert iz[i].status == 0 and rel(us[i].cpu().numpy(), uz[i].cpu().numpy()) < 1e-8
+    for h in list(cache.values()) + list(cz.values()):
+        h.destroy()
+
+
 def test_batch_tile_variants_and_tuning(ff, orc, tmp_path):
     """Every FFMG_TUNE_BATCH variant (tile heights of the batched smoothing
     launches) gives the same bits (the batch is rebuilt when the variant
@@ -158,8 +183,9 @@ def test_batch_rejects_unsupported_handles(ff, orc):
     h64 = ff.setup_workload(w, options=ff.default_options())[0]
     hir = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR))[0]
     hnu = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, nu1=1, nu2=1))[0]
+    hfmg = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, fmg_cycles=1))[0]
     u = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for _ in range(2)]
-    for hs in ([h64, hir], [hir, hnu]):
+    for hs in ([h64, hir], [hir, hnu], [hir, hfmg]):
         with pytest.raises(ff.FfmgError) as e:
             ff.mg_solve_batched(hs, [w.eta, w.eta], u)
         assert e.value.status == ff.FFMG_EINVAL

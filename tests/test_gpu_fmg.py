@@ -152,7 +152,7 @@ def test_fmg_mixed_precision_solve(ff, orc, name, mk):
 
 def test_fmg_edge_cases(ff, orc):
     """b = 0 gives u = 0 in both precisions; k outside [0, 64], fmg_cycles
-    outside [0, 64] and FMG handles in a batched solve are refused; k = 0 is
+    outside [0, 64] and a batched solve mixing starts are refused; k = 0 is
     the interpolated hierarchy without cycles (as the oracle's)."""
     w = W.small_2d(n=64)
     for prec in (0, 1):
@@ -171,12 +171,22 @@ def test_fmg_edge_cases(ff, orc):
     with pytest.raises(ff.FfmgError) as e:
         ff.setup_workload(w, options=ff.default_options(fmg_cycles=65))
     assert e.value.status == ff.FFMG_EINVAL
+    # a batched solve takes FMG handles (the start of every instance run
+    # together, equal to the single solve's) but not a mix of starts
     h, _ = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, fmg_cycles=1))
+    h0, _ = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR))
     u = torch.empty((63, 63), dtype=torch.complex128, device="cuda")
+    info = ff.mg_solve_batched([h], [w.eta], [u])[0]
+    b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty_like(u))
+    u1 = torch.zeros_like(u)
+    info1 = ff.mg_solve(h, b, u1)
+    torch.cuda.synchronize()
+    assert info.cycles == info1.cycles and torch.equal(u, u1)
     with pytest.raises(ff.FfmgError) as e:
-        ff.mg_solve_batched([h], [w.eta], [u])
+        ff.mg_solve_batched([h, h0], [w.eta, w.eta], [u, torch.empty_like(u)])
     assert e.value.status == ff.FFMG_EINVAL
     h.destroy()
+    h0.destroy()
 
 
 @pytest.mark.parametrize("prec", [0, 1])
