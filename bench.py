@@ -30,9 +30,10 @@ Also reported:
   * the solve-only stress points at k0 h = 1/2 (2048^2 and 512^3) with the
     bounded phase right-hand side;
   * the 2D 2048^2 bumps workload (the former headline) with its pipelined
-    mixed and plain rates, the GMRES(3) smoother, the batched Schroedinger
-    workload, the learned smoother and the ionisation cross-section sweep
-    of the partial-wave model;
+    mixed and plain rates and its four directions as one batched solve, the
+    GMRES(3) smoother, the batched Schroedinger workload (full multigrid
+    start), the learned smoother and the ionisation cross-section sweep of
+    the partial-wave model;
   * the FP64 CPU oracle on the host cores, on a bounded sample of the
     headline workload (run in a child process).
 """
@@ -470,6 +471,7 @@ def run_bumps2d(ff, torch, W, steps, warmup, lanes, ff_prec):
                  tol=MAP_TOL)
     p = run_path(ff, torch, w, ff.FP64, ff.FF_FP64, max(steps // 2, 2), warmup, lanes=lanes, pipelined=lanes > 1,
                  etas=etas, tol=MAP_TOL)
+    bt = run_bumps2d_batched(ff, torch, w, etas, steps, ffp, m)
     km = kernel_pass(ff, torch, w, ff.FP32_IR, ffp, 8, FMG_K, BPP[2]["mixed"], tol=MAP_TOL)
     kp = kernel_pass(ff, torch, w, ff.FP64, ff.FF_FP64, 4, FMG_K, BPP[2]["plain"], tol=MAP_TOL)
     dom = km["dominant"]
@@ -482,6 +484,7 @@ def run_bumps2d(ff, torch, W, steps, warmup, lanes, ff_prec):
             "plain_fp64": {"maps_per_s": round(p["maps_per_s"], 3), "ms_per_step": round(p["ms_per_step"], 3),
                            "cycles": p["cycles"], "rel_residual": p["rel_residual"], "tune": p["tune"]},
             "speedup_vs_plain": round(m["maps_per_s"] / p["maps_per_s"], 3),
+            "batched_directions": bt,
             "mixed_vs_plain_farfield_rel_err": float(np.linalg.norm(m["F"] - p["F"]) / np.linalg.norm(p["F"])),
             "kernels_mixed_one_solve": km["kernels"], "kernels_plain_one_solve": kp["kernels"],
             "dominant_kernel_roofline": {
@@ -490,6 +493,47 @@ def run_bumps2d(ff, torch, W, steps, warmup, lanes, ff_prec):
                 "note": "cache-assisted: one launch moves about 142 MB, which fits the 256 MB Infinity Cache; "
                         "the HBM roofline is judged on the 512^3 headline"},
             "farfield_gemm": gemm_report(km["kernels"], w, ff_prec)}
+
+
+def run_bumps2d_batched(ff, torch, w, etas, steps, ffp, m):
+    """The same mixed maps with the incoming directions solved together: one
+    mg_solve_batched over the directions of one operator (full multigrid
+    start, FP32 V-cycles in FP64 refinement: every level of every direction
+    in one launch) and one farfield_map_batched.  Each map equals the
+    single-solve map of its direction bit for bit (checked on the direction
+    the pipelined run `m` ended with)."""
+    import numpy as np
+    from paper_1211_4461_amd import autotune
+    h = ff.setup_workload(w, options=ff.default_options(precision=ff.FP32_IR, ff_precision=ffp,
+                                                        fmg_cycles=FMG_K))[0]
+    tune = tune_handle(ff, torch, h, w, ff.FP32_IR, ffp)
+    hs = [h] * len(etas)
+    us = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for _ in etas]
+    tune["batch_tiles"] = autotune.tune_batch(hs, etas, us, tol=MAP_TOL)
+    F = torch.empty((len(etas), len(w.dirs)), dtype=torch.complex128, device="cuda")
+    infos = None
+
+    def batch():
+        nonlocal infos
+        infos = ff.mg_solve_batched(hs, etas, us, tol=MAP_TOL)
+        ff.farfield_map_batched(hs, etas, us, w.dirs, out=F)
+
+    batch()
+    batch()
+    torch.cuda.synchronize()
+    nb = max(steps // len(etas), 2)
+    t0 = time.perf_counter()
+    for _ in range(nb):
+        batch()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / nb
+    j = [i for i, e in enumerate(etas) if np.array_equal(np.asarray(e), np.asarray(m["eta"]))][0]
+    same = bool(np.array_equal(F[j].cpu().numpy(), m["F"]))
+    h.destroy()
+    return {"directions": len(etas), "maps_per_s": round(len(etas) / dt, 3), "ms_per_batch": round(1e3 * dt, 3),
+            "refinement_steps": [min(i.cycles for i in infos), max(i.cycles for i in infos)],
+            "max_rel_residual": max(i.rel_residual for i in infos), "map_equal_to_single_solve": same,
+            "tune": tune}
 
 
 def run_gmres(ff, torch, W, n, steps=6):
