@@ -88,13 +88,16 @@ KERNELS = {"pre": 0, "ff": 1, "post": 2, "refine": 3, "ffgemm": 4, "net": 5, "rr
 #   refine  FP64 update + residual: read u, b, q (16 each), d (8); write u (16), r (8)
 # "pre" brackets two passes (two sweeps from a zero guess, 3e; two sweeps
 # from a guess, 4e) and is reported, not ranked.
-BPP = {3: {"mixed": {"post": 33.0, "rr": 25.0, "refine": 80.0}, "plain": {"post": 66.0, "rr": 50.0}},
+# (the 3D refinement pass forms the plane-wave right-hand side from q instead
+# of reading it: read u, q (16 B each), d (8); write u, r (16 + 8))
+BPP = {3: {"mixed": {"post": 33.0, "rr": 25.0, "refine": 64.0}, "plain": {"post": 66.0, "rr": 50.0}},
        2: {"mixed": {"post": 34.0, "refine": 80.0}, "plain": {"post": 68.0}}}
 KERNEL_NAMES = {
     3: {"post": "k_sweep2_3d<%s, SRC_PROL> (finest level: interpolation of the coarse correction + two Jacobi sweeps "
                 "in one z-marching pass)",
         "rr": "k_resid_restrict3d<%s> (finest level: residual + full weighting in one pass)",
-        "refine": "k_refine3d (FP64 update + residual of the refinement step, one pass)",
+        "refine": "k_refine3d<true> (FP64 update + residual of the refinement step, one pass; the plane-wave "
+                  "right-hand side formed from q)",
         "pre": "k_sweep2_3d<%s, SRC_ZERO2 / SRC_MEM> (finest level: two Jacobi sweeps per pass)"},
     2: {"post": "k_smooth2d<%s, 2, false, true, 1, TH> (finest level: interpolation + two fused Jacobi sweeps)",
         "refine": "k_refine2d (FP64 update + residual)",
@@ -171,10 +174,11 @@ def run_path(ff, torch, w, precision, ff_precision, steps, warmup, fmg_cycles=FM
         s_ = torch.cuda.Stream() if lanes > 1 else torch.cuda.current_stream()
         with torch.cuda.stream(s_):
             h_ = ff.setup_workload(w, options=ff.default_options(**opts))[0]
-            b_ = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
-            u_ = torch.empty_like(b_)
+            u_ = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
             F_ = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
-        ln_.append([h_, b_, u_, F_, s_, None])
+        # the right-hand side is the handle's plane wave (b = None): not stored
+        # where the solve forms it in its kernels
+        ln_.append([h_, None, u_, F_, s_, None])
     tune = tune_handle(ff, torch, ln_[0][0], w, precision, ff_precision)
     for ln in ln_[1:]:
         copy_tuning(ff, ln_[0][0], ln[0])
@@ -248,15 +252,14 @@ def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp, to
     h = ff.setup_workload(w, options=ff.default_options(precision=precision, ff_precision=ff_precision,
                                                         fmg_cycles=fmg_cycles, inner_cycles=inner))[0]
     tune_handle(ff, torch, h, w, precision, ff_precision)
-    b = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
-    u = torch.empty_like(b)
+    u = torch.empty(w.shape, dtype=torch.complex128, device="cuda")
     F = torch.empty(len(w.dirs), dtype=torch.complex128, device="cuda")
 
     def one():
-        ff.mg_rhs_plane_wave(h, w.eta, b)
+        ff.mg_rhs_plane_wave(h, w.eta, None)
         if fmg_cycles == 0:
             u.zero_()
-        inf = ff.mg_solve(h, b, u, tol=w.tol if tol is None else tol)
+        inf = ff.mg_solve(h, None, u, tol=w.tol if tol is None else tol)
         ff.farfield_map(h, w.eta, u, w.dirs, out=F)
         return inf
 
@@ -290,7 +293,7 @@ def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp, to
     dominant = max((k for k in bpp if k in stats), key=lambda k: stats[k]["ms_per_map"])
     out = {"kernels": stats, "dominant": dominant, "cycles": info.cycles, "vcycles": info.vcycles, "maps": maps}
     h.destroy()
-    del b, u, F
+    del u, F
     torch.cuda.empty_cache()
     return out
 

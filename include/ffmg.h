@@ -146,9 +146,12 @@ void ffmg_default_options(ffmg_options *o);
 ffmg_status mg_setup(const ffmg_problem *p, const ffmg_options *o, ffmg_handle **out);
 
 /* b_j = q_j exp(i k0 eta.z_j): the plane-wave right-hand side of
- * eq. helmholtz_cc.  eta: HOST double[3] unit vector (first dim entries used).
- * b: DEVICE complex128[N], written.  ERANGE if |exp(i k0 eta.z)| would
- * overflow double. */
+ * eq. helmholtz_cc, with exp(i k0 eta.z) formed as the product of one factor
+ * per axis (the grid is a tensor grid).  eta: HOST double[3] unit vector
+ * (first dim entries used, finite).  b: DEVICE complex128[N], written; or
+ * NULL.  Either way the call records eta as the handle's plane wave, the
+ * right-hand side of mg_solve / mg_solve_begin with b = NULL.  ERANGE if
+ * |exp(i k0 eta.z)| would overflow double. */
 ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b);
 
 /* b_j = q_j exp(i k0 cos(gamma) eta.x_j): the incoming wave's phase along
@@ -187,7 +190,15 @@ ffmg_status mg_fmg(ffmg_handle *h, const void *b, void *u, int k);
  * ||b - A u||_2 <= tol ||b||_2 (residual-reduction tolerance, Sec. 4).
  * u: DEVICE complex128[N], in: guess, out: solution.  ENOCONV after max_cycles or when the residual grows
  * on 3 consecutive cycles; u then holds the last iterate and info is filled.
- * b = 0 returns u = 0 after 0 cycles.  info may be NULL.  Synchronises. */
+ * b = 0 returns u = 0 after 0 cycles.  info may be NULL.  Synchronises.
+ * b: DEVICE complex128[N], read; or NULL for the plane-wave right-hand side
+ * of the eta last given to mg_rhs_plane_wave on this handle (EINVAL if
+ * none), with the same result, bit for bit, as passing what
+ * mg_rhs_plane_wave writes.  The FP32_IR solve of a 3D handle with the fused
+ * kernels and the Jacobi smoother never stores that b: its FP64 kernels form
+ * q exp(i k0 eta.z) where they read it, which saves 16 bytes per point in
+ * each FP64 residual pass; other configurations store it once in the handle
+ * (N complex128, allocated on first use). */
 ffmg_status mg_solve(ffmg_handle *h, const void *b, void *u, double tol, ffmg_solve_info *info);
 
 /* mg_solve in two halves, for callers that keep several solves in flight from
@@ -203,7 +214,8 @@ ffmg_status mg_solve(ffmg_handle *h, const void *b, void *u, double tol, ffmg_so
  * mg_rhs_plane_wave, farfield_map, mg_tune_*, mg_solve_batched) returns
  * EINVAL for it.  mg_solve_begin: EINVAL for a null argument, tol outside
  * (0, 1), a solve already pending, or the learned smoother (its fallback is
- * decided on the host between cycles: use mg_solve).  mg_solve_end: EINVAL
+ * decided on the host between cycles: use mg_solve).  b = NULL: the handle's
+ * plane wave, as in mg_solve.  mg_solve_end: EINVAL
  * if no solve is pending; for a non-finite b it returns ENAN with u
  * unspecified.  info may be NULL. */
 ffmg_status mg_solve_begin(ffmg_handle *h, const void *b, void *u, double tol);

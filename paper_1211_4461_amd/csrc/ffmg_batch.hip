@@ -33,6 +33,7 @@ struct BatchInst {
     ffmg_handle *op = nullptr;
     int D = 0;                            // levels above the tail (tail starts at level D)
     cd *b = nullptr, *t = nullptr;        // FP64 right-hand side, iterate ping-pong
+    cd *f = nullptr;                      // the plane wave's per-axis factors
     std::vector<cf *> u32, b32, t32, r32; // FP32 cycle: levels 0..D (t32, r32: 0..D-1)
     double *parts = nullptr;
     SolveCtl *ctl = nullptr;
@@ -46,7 +47,7 @@ struct Batch {
     int variant = 0, th_smooth = 8, th_srr = 16;   // FFMG_TUNE_BATCH and its tile heights
     int fmg = 0;                          // V-cycles per level of the full multigrid start (0: u = 0)
     size_t tail_lds = 0;
-    int max_nb_norm = 0, max_nb_res = 0, ref_ntiles = 0;
+    int max_nb_norm = 0, max_nb_res = 0, ref_ntiles = 0, max_m = 0;
     int last_steps = 0;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -508,6 +509,8 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
         const size_t N0 = g0.N();
         BCHK(B.alloc((void **)&I.b, N0 * sizeof(cd)));
         BCHK(B.alloc((void **)&I.t, N0 * sizeof(cd)));
+        BCHK(B.alloc((void **)&I.f, (size_t)(g0.m[0] + g0.m[1]) * sizeof(cd)));
+        B.max_m = std::max(B.max_m, std::max(g0.m[0], g0.m[1]));
         I.u32.assign(I.D + 1, nullptr);
         I.b32.assign(I.D + 1, nullptr);
         I.t32.assign(I.D, nullptr);
@@ -653,6 +656,7 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
         J.q = l0.q;
         J.b = I.b;
         J.u = (cd *)u[i];
+        J.f = I.f;
         J.r32 = I.b32[0];
         J.ctl = I.ctl;
         J.partial = I.parts;
@@ -706,7 +710,7 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
     if (B.fmg > 0)
         BCHK(hipMemcpyAsync(B.d_xfin, B.xfin.data(), count * sizeof(XferJob), hipMemcpyHostToDevice, B.stream));
     BCHK(hipEventRecord(e0, B.stream));
-    launch_init_batch(B.d_init, count, B.max_nb_norm, B.stream);
+    launch_init_batch(B.d_init, count, B.max_nb_norm, B.max_m, B.stream);
     if (B.fmg > 0) BCHK(hipGraphLaunch(B.fmg_exec, B.stream));
     launch_init_resid_batch(B.d_init, count, B.max_nb_res, B.stream);
     launch_ctl_update_batch(B.d_ctl0, count, B.stream);

@@ -127,13 +127,43 @@ __global__ __launch_bounds__(256) void k_norm2(const cd *__restrict__ v, size_t 
     if (threadIdx.x == 0) parts[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// The same sums for the plane-wave right-hand side q u_in (the values
+// k_rhs would store, in the same order).
+__global__ __launch_bounds__(256) void k_norm2_pw(const cd *__restrict__ q, const cd *__restrict__ f, int mx, int my,
+                                                  int dim, size_t N, double *__restrict__ parts)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
+        const int ix = (int)(j % mx);
+        const size_t rest = j / mx;
+        acc += abs2(q[j] * pw_uin(f, ix, (int)(rest % my), (int)(rest / my), mx, my, dim));
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) parts[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // ||v||_2^2 into h->d_scalar (device) and *out (host).
 int norm2_blocks(size_t N) { return (int)std::min<size_t>((N + 255) / 256, 1024); }
+
+// per-block partial sums of ||v||^2 (v = null: the plane-wave right-hand side)
+void launch_norm2_parts(ffmg_handle *h, const cd *v, size_t N, int nb)
+{
+    if (v) {
+        hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, h->stream, v, N, h->d_parts);
+    } else {
+        const LevelGeom &g = h->L[0].g;
+        hipLaunchKernelGGL(k_norm2_pw, dim3(nb), dim3(256), 0, h->stream, h->L[0].q, h->pw_f, g.m[0], g.m[1], g.dim,
+                           N, h->d_parts);
+    }
+}
 
 ffmg_status norm2_of(ffmg_handle *h, const cd *v, size_t N, double *out)
 {
     const int nb = norm2_blocks(N);
-    hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, h->stream, v, N, h->d_parts);
+    launch_norm2_parts(h, v, N, nb);
     HIPCHK(h, hipGetLastError());
     TRY(reduce_to_host(h, nb, out));
     return FFMG_OK;
@@ -143,7 +173,7 @@ ffmg_status norm2_of(ffmg_handle *h, const cd *v, size_t N, double *out)
 void enqueue_norm2(ffmg_handle *h, const cd *v, size_t N)
 {
     const int nb = norm2_blocks(N);
-    hipLaunchKernelGGL(k_norm2, dim3(nb), dim3(256), 0, h->stream, v, N, h->d_parts);
+    launch_norm2_parts(h, v, N, nb);
     launch_sum(h->d_parts, nb, h->d_scalar, h->stream);
 }
 
@@ -556,6 +586,10 @@ ffmg_status setup_impl(ffmg_handle *h)
     }
     TRY(dalloc(h, &h->d_parts, maxparts * sizeof(double)));
     TRY(dalloc(h, &h->d_scalar, sizeof(double)));
+    {
+        const LevelGeom &g0 = h->L[0].g;
+        TRY(dalloc(h, &h->pw_f, (size_t)(g0.m[0] + g0.m[1] + g0.m[2]) * sizeof(cd)));
+    }
     TRY(dalloc(h, &h->d_info, sizeof(int)));
     TRY(dalloc(h, &h->d_ctl, sizeof(SolveCtl)));
     HIPCHK(h, hipHostMalloc((void **)&h->h_scalar, sizeof(double), hipHostMallocDefault));
@@ -612,7 +646,8 @@ void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *st
         launch_ctl_update(h->d_ctl, h->d_parts, fused2d_blocks(l0.g), h->stream);
     } else if (l0.g.dim == 3 && h->opt.tile_config != TILE_REFERENCE) {
         int pi = prof_begin(h, PROF_REFINE);
-        launch_refine3d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
+        launch_refine3d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop,
+                        h->pw_f);
         prof_end(h, PROF_REFINE, pi);
         launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
     } else {
@@ -798,7 +833,7 @@ void fmg_start(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2)
     const int s0 = (t0 == 0) ? 1 : 0;                      // its first level the start runs on
     const int top = tail ? t0 + s0 : last;                 // right-hand sides injected down to here
     const bool tail_fmg = tail && top < last;
-    launch_inject_rhs<T>(l0.g, b, LP::b(h->L[1]), bnorm2, h->stream);
+    launch_inject_rhs<T>(l0.g, b, LP::b(h->L[1]), bnorm2, h->stream, l0.q, h->pw_f);
     for (int l = 1; l < top; ++l) launch_inject<T>(h->L[l].g, LP::b(h->L[l]), LP::b(h->L[l + 1]), h->stream);
     int from;
     if (tail_fmg) {
@@ -1014,13 +1049,41 @@ ffmg_status mg_level_shape(const ffmg_handle *h, int level, int64_t m[3])
 ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b)
 {
     NOT_PENDING(h);
-    if (!h || !eta || !b) return fail(h, FFMG_EINVAL, "null argument");
+    if (!h || !eta) return fail(h, FFMG_EINVAL, "null argument");
     if (!(h->k0 > 0.0)) return fail(h, FFMG_EINVAL, "a plane wave needs E > 0");
     double e[3] = {0, 0, 0};
-    for (int k = 0; k < h->prob.dim; ++k) e[k] = eta[k];
+    for (int k = 0; k < h->prob.dim; ++k) {
+        if (!isfinite(eta[k])) return fail(h, FFMG_EINVAL, "eta is not finite");
+        e[k] = eta[k];
+    }
     if (exponent_budget(h) > 700.0) return fail(h, FFMG_ERANGE, "exp(i k0 eta.z) overflows double on this box");
-    launch_rhs_plane_wave(h->L[0].g, h->prob.gamma, h->k0, e, h->L[0].q, (cd *)b, h->stream);
+    launch_pw_factors(h->L[0].g, h->prob.gamma, h->k0, e, h->pw_f, h->stream);
+    h->pw_set = true;
+    if (b) launch_rhs_plane_wave(h->L[0].g, h->L[0].q, h->pw_f, (cd *)b, h->stream);
     HIPCHK(h, hipGetLastError());
+    return FFMG_OK;
+}
+
+// Solves with b = NULL take the plane wave of the last mg_rhs_plane_wave.
+// The FP32-in-FP64 3D solve with the fused kernels forms it where its FP64
+// kernels need it (the norm, the start's injection, the residuals of the
+// refinement); every other path gets it stored once in the handle.
+static bool pw_implicit(const ffmg_handle *h)
+{
+    return h->opt.precision == FFMG_FP32_IR && h->opt.tile_config != TILE_REFERENCE && h->prob.dim == 3 &&
+           h->opt.smoother == FFMG_SMOOTH_JACOBI && h->L.size() > 1;
+}
+
+static ffmg_status pw_resolve(ffmg_handle *h, const cd **b)
+{
+    if (*b) return FFMG_OK;
+    if (!h->pw_set)
+        return fail(h, FFMG_EINVAL, "b is NULL but no plane wave was set on this handle (mg_rhs_plane_wave)");
+    if (pw_implicit(h)) return FFMG_OK;
+    if (!h->pw_b) TRY(dalloc(h, &h->pw_b, h->L[0].g.N() * sizeof(cd)));
+    launch_rhs_plane_wave(h->L[0].g, h->L[0].q, h->pw_f, h->pw_b, h->stream);
+    HIPCHK(h, hipGetLastError());
+    *b = h->pw_b;
     return FFMG_OK;
 }
 
@@ -1140,9 +1203,10 @@ ffmg_status mg_fmg(ffmg_handle *h, const void *bv, void *uv, int k)
 static ffmg_status solve_host_controlled(ffmg_handle *h, const void *bv, void *uv, double tol,
                                          ffmg_solve_info *info)
 {
-    if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
+    if (!h || !uv) return fail(h, FFMG_EINVAL, "null argument");
     if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, FFMG_EINVAL, "tol must lie in (0, 1)");
     const cd *b = (const cd *)bv;
+    TRY(pw_resolve(h, &b));
     cd *u = (cd *)uv;
     ffmg_solve_info inf{};
     hipEvent_t e0, e1;
@@ -1259,12 +1323,13 @@ static ffmg_status solve_host_controlled(ffmg_handle *h, const void *bv, void *u
 
 ffmg_status mg_solve_begin(ffmg_handle *h, const void *bv, void *uv, double tol)
 {
-    if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
+    if (!h || !uv) return fail(h, FFMG_EINVAL, "null argument");
     NOT_PENDING(h);
     if (!(tol > 0.0) || !(tol < 1.0)) return fail(h, FFMG_EINVAL, "tol must lie in (0, 1)");
     if (h->opt.smoother == FFMG_SMOOTH_LEARNED)
         return fail(h, FFMG_EINVAL, "the learned smoother's fallback is decided on the host between cycles: use mg_solve");
     const cd *b = (const cd *)bv;
+    TRY(pw_resolve(h, &b));
     cd *u = (cd *)uv;
     PendingSolve &p = h->pend;
     Level &l0 = h->L[0];
@@ -1288,6 +1353,8 @@ ffmg_status mg_solve_begin(ffmg_handle *h, const void *bv, void *uv, double tol)
     // initial residual (cycle 0)
     if (h->opt.precision == FFMG_FP64)
         launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u0, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
+    else if (!b)
+        launch_resid3d_pw(l0.g, l0.P64, u0, l0.q, l0.b32, h->d_ctl, h->d_parts, h->pw_f, h->stream);
     else
         launch_resid_to_f32_ctl(l0.g, l0.P64, u0, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, nullptr);
     launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
@@ -1351,7 +1418,7 @@ ffmg_status mg_solve_end(ffmg_handle *h, ffmg_solve_info *info)
 
 ffmg_status mg_solve(ffmg_handle *h, const void *bv, void *uv, double tol, ffmg_solve_info *info)
 {
-    if (!h || !bv || !uv) return fail(h, FFMG_EINVAL, "null argument");
+    if (!h || !uv) return fail(h, FFMG_EINVAL, "null argument");
     NOT_PENDING(h);
     if (h->opt.smoother == FFMG_SMOOTH_LEARNED) return solve_host_controlled(h, bv, uv, tol, info);
     TRY(mg_solve_begin(h, bv, uv, tol));

@@ -134,4 +134,26 @@ __host__ __device__ __forceinline__ int xcd_tile_inv(int t, int nb)
     return local * X + xcd;
 }
 
+// The incoming plane wave exp(i k0 e^{i gamma} eta.x) of the right-hand side
+// (Sec. 2.1) is a product of one factor per axis on the tensor grid:
+// E_k[i] = exp(c_k x_i), c_k = cr_k + i ci_k = i k0 e^{i gamma} eta_k, at
+// x_i = lo_k + (i + 1) h_k.  A level's factors are stored [E_x | E_y | E_z]
+// (mx + my + mz values).
+__device__ __forceinline__ cd pw_factor(int i, double lo, double h, double cr, double ci)
+{
+    const double x = lo + (double)(i + 1) * h;
+    const double mag = exp(cr * x), ph = ci * x;
+    return cd{mag * cos(ph), mag * sin(ph)};
+}
+
+// The plane wave at interior point (ix, iy, iz): (E_x E_y) E_z, or E_x E_y in
+// 2D.  Every kernel that forms the right-hand side q u_in takes it from here,
+// in this order, so a stored and a recomputed right-hand side agree bit for
+// bit.
+__device__ __forceinline__ cd pw_uin(const cd *__restrict__ f, int ix, int iy, int iz, int mx, int my, int dim)
+{
+    const cd v = f[ix] * f[mx + iy];
+    return dim == 3 ? v * f[mx + my + iz] : v;
+}
+
 }  // namespace ffmg

@@ -86,7 +86,13 @@ struct ffmg_handle {
     ffmg::TailParams<float> tail32{};
     ffmg::FarFieldPlan *ff = nullptr;
     int ff_variant = -1;             // split-GEMM tile variant (-1: default; autotuned)
-    ffmg::cd *d_E = nullptr;         // plane-wave axis factors
+    ffmg::cd *d_E = nullptr;         // plane-wave axis factors (far field)
+    // the plane wave of the last mg_rhs_plane_wave: its per-axis factors on the
+    // finest level (the right-hand side q u_in of mg_solve(h, NULL, ...)), and
+    // that right-hand side stored for the paths that read b (on first use)
+    ffmg::cd *pw_f = nullptr;
+    bool pw_set = false;
+    ffmg::cd *pw_b = nullptr;
     ffmg::cd *d_F = nullptr;         // far-field staging
     int d_F_cap = 0;
     // ionisation observables: workspace slots grown on demand, freed at destroy

@@ -156,9 +156,11 @@ void launch_rbgs_sweep(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, 
 // Full multigrid transfers: the finest right-hand side at the first coarse
 // level's nodes, divided by s = sqrt(*bnorm2 / N) (s = 1 when bnorm2 is
 // null), and uf = s P ec overwriting uf (inv_sqN = 1 / sqrt(N) of the finest
-// level; s = 1 when bnorm2 is null).
+// level; s = 1 when bnorm2 is null).  bf = null: the finest right-hand side
+// is the plane wave's q u_in, from the finest q (qf) and its factors (pwf).
 template <typename TO>
-void launch_inject_rhs(const LevelGeom &fine, const cd *bf, cx<TO> *bc, const double *bnorm2, hipStream_t s);
+void launch_inject_rhs(const LevelGeom &fine, const cd *bf, cx<TO> *bc, const double *bnorm2, hipStream_t s,
+                       const cd *qf = nullptr, const cd *pwf = nullptr);
 template <typename TC, typename TF>
 void launch_prolong_set(const LevelGeom &fine, const cx<TC> *ec, cx<TF> *uf, const double *bnorm2, double inv_sqN,
                         hipStream_t s);
@@ -171,8 +173,10 @@ void launch_gauss_jordan(cd *aug, int n, int *info, hipStream_t s, cd *ws);
 size_t gauss_jordan_ws(int n);
 template <typename T>
 void launch_coarse_apply(const cd *Ainv, int n, const cx<T> *b, cx<T> *u, hipStream_t s, const int *stop = nullptr);
-void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
-                           hipStream_t s);
+// The incoming plane wave's per-axis factors on g into f (g.m[0] + g.m[1] +
+// g.m[2] values, the layout of pw_uin), and b = q u_in from them.
+void launch_pw_factors(const LevelGeom &g, double gamma, double k0, const double eta[3], cd *f, hipStream_t s);
+void launch_rhs_plane_wave(const LevelGeom &g, const cd *q, const cd *f, cd *b, hipStream_t s);
 void launch_rhs_phase(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
                       hipStream_t s);
 
@@ -180,10 +184,13 @@ void launch_rhs_phase(const LevelGeom &g, double gamma, double k0, const double 
 // s = ctl->scale_cur; r64 = b - A u64 written as r64 / ctl->scale_next.
 void launch_refine_update(const cf *d, cd *u, const SolveCtl *ctl, size_t N, hipStream_t s, const int *stop);
 // 3D refinement step in one pass: unew = u + s d, r32 = (b - A unew) / scale_next, block sums of |b - A unew|^2
-// (stencil_blocks(g) partials)
+// (stencil_blocks(g) partials); b = null: the plane-wave right-hand side q u_in from the factors pwf
 void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
-                     const int *stop);
+                     const int *stop, const cd *pwf = nullptr);
+// r32 = (q u_in - A u) / ctl->scale_next with block sums of its FP64 square (3D)
+void launch_resid3d_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,
+                       const SolveCtl *ctl, double *partial, const cd *pwf, hipStream_t s);
 // two Jacobi sweeps in one 3D pass from u (ec: from u + P ec; zero: from a zero guess, u not read);
 // shape: the tile, as FFMG_TUNE_SWEEP3D variants 0, 2, 3 (the same bits with every tile)
 template <typename T>
@@ -327,6 +334,7 @@ void launch_tail2d_fmg_batch(const TailJob<T> *jobs, int njobs, int k, size_t ld
 struct InitJob {
     const cd *q;
     cd *b, *u;
+    cd *f;                 // the plane wave's per-axis factors (mx + my values)
     cf *r32;
     SolveCtl *ctl;
     double *partial;
@@ -370,8 +378,9 @@ void launch_xfer_batch(int kind, const XferJob *jobs, int njobs, size_t max_n, h
 int norm2_blocks(size_t N);
 void launch_hash_fill(cd *out, size_t N, unsigned long long seed, hipStream_t s);
 void stencil_grid2d(const LevelGeom &g, int *nb, int *tiles_x);   // blocks and tiles per row of k_stencil2d
-// plane-wave right-hand side, u = 0, ||b||^2 and the control block
-void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, hipStream_t s);
+// plane-wave right-hand side, u = 0, ||b||^2 and the control block (max_m:
+// the largest grid extent among the instances)
+void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_m, hipStream_t s);
 // the initial residual b - A u as the scaled FP32 right-hand side
 void launch_init_resid_batch(const InitJob *jobs, int n, int max_nb_res, hipStream_t s);
 void launch_ctl_update_batch(const CtlJob *jobs, int n, hipStream_t s);

@@ -270,14 +270,17 @@ struct Raw3 {
     cx<T> c;   // d widened exactly (SRC_UPD) or q (SRC_ZERO2)
 };
 
-template <typename T, typename TO, int MODE, int SRC>
+// PW: the right-hand side is the plane-wave one, formed as q u_in from the
+// per-axis factors pwf where a point needs it (b is not read; FP64 only).
+template <typename T, typename TO, int MODE, int SRC, bool PW = false>
 __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                cx<TO> *__restrict__ out, const Stencil<T> &P, T rscale, int tiles_x,
                                                int tiles_y, int tz, double *__restrict__ partial,
                                                const cf *__restrict__ dcorr = nullptr, double dscale = 0.0,
-                                               cx<T> *__restrict__ unew = nullptr)
+                                               cx<T> *__restrict__ unew = nullptr, const cd *__restrict__ pwf = nullptr)
 {
+    static_assert(!PW || (sizeof(T) == 8 && MODE != MODE_APPLY && SRC != SRC_ZERO2), "plane-wave b: FP64 residuals");
     constexpr int PY = TY3 / 4;
     constexpr int NH = 2 * TY3 + 2 * 66;   // halo values of a plane: the x sides, then the y rows
     // coarse tile of the fine tile plus its one-point halo: 34 x (TY3/2 + 2)
@@ -412,15 +415,33 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
         }
         rh = fetch(z0, offh);
     }
+    // plane-wave b: E_x E_y of the own points (fixed through the march)
+    cx<T> exy[PY];
+#pragma unroll
+    for (int i = 0; i < PY; ++i) {
+        exy[i] = zero;
+        if constexpr (PW)
+            if (ino[i]) exy[i] = pwf[gx] * pwf[mx + y0 + ly0 + 4 * i];
+    }
     auto fetch_bq = [&](int z) {
         const bool zin = zin_of(z);
         const size_t o = zin ? (size_t)z * plane : 0;
         const unsigned nb = zin ? pbytes : 0u;
-        const auto rb = buf_rsrc(b + o, nb), rq = buf_rsrc(q + o, nb);
+        const auto rq = buf_rsrc(q + o, nb);
+        if constexpr (PW) {
+            const cx<T> ez = zin ? pwf[mx + my + z] : zero;
 #pragma unroll
-        for (int i = 0; i < PY; ++i) {
-            if (NEED_B) bo[i] = ld_buf<T>(rb, offo[i]);
-            qo[i] = ld_buf<T>(rq, offo[i]);
+            for (int i = 0; i < PY; ++i) {
+                qo[i] = ld_buf<T>(rq, offo[i]);
+                bo[i] = qo[i] * (exy[i] * ez);
+            }
+        } else {
+            const auto rb = buf_rsrc(b + o, nb);
+#pragma unroll
+            for (int i = 0; i < PY; ++i) {
+                if (NEED_B) bo[i] = ld_buf<T>(rb, offo[i]);
+                qo[i] = ld_buf<T>(rq, offo[i]);
+            }
         }
     };
 #pragma unroll
@@ -796,16 +817,30 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
 // (s = ctl->scale_cur) into unew, and the residual b - A u' written as FP32
 // scaled by 1 / ctl->scale_next, with the per-block FP64 sums of |b - A u'|^2.
 // The same arithmetic as k_refine_update followed by the FP64 residual.
+template <bool PW>
 __global__ __launch_bounds__(256) void k_refine3d(const cd *__restrict__ u, const cf *__restrict__ d,
                                                   const cd *__restrict__ b, const cd *__restrict__ q,
                                                   cd *__restrict__ unew, cf *__restrict__ r32, Stencil<double> P,
                                                   int tiles_x, int tiles_y, int tz, double *__restrict__ partial,
-                                                  const SolveCtl *__restrict__ ctl, const int *__restrict__ stop)
+                                                  const SolveCtl *__restrict__ ctl, const int *__restrict__ stop,
+                                                  const cd *__restrict__ pwf)
 {
     if (stop && *stop) return;
     const double rscale = 1.0 / ctl->scale_next;
-    stencil3d_body<double, float, MODE_RESID, SRC_UPD>(u, nullptr, b, q, r32, P, rscale, tiles_x, tiles_y, tz,
-                                                       partial, d, ctl->scale_cur, unew);
+    stencil3d_body<double, float, MODE_RESID, SRC_UPD, PW>(u, nullptr, b, q, r32, P, rscale, tiles_x, tiles_y, tz,
+                                                           partial, d, ctl->scale_cur, unew, pwf);
+}
+
+// The FP64 residual of the plane-wave right-hand side written as scaled FP32
+// (the 3D form of launch_resid_to_f32_ctl with b formed from pwf).
+__global__ __launch_bounds__(256) void k_resid3d_pw(const cd *__restrict__ u, const cd *__restrict__ q,
+                                                    cf *__restrict__ r32, Stencil<double> P, int tiles_x,
+                                                    int tiles_y, int tz, double *__restrict__ partial,
+                                                    const SolveCtl *__restrict__ ctl, const cd *__restrict__ pwf)
+{
+    const double rscale = 1.0 / ctl->scale_next;
+    stencil3d_body<double, float, MODE_RESID, SRC_MEM, true>(u, nullptr, nullptr, q, r32, P, rscale, tiles_x,
+                                                             tiles_y, tz, partial, nullptr, 0.0, nullptr, pwf);
 }
 
 // Blocks of a stencil launch on grid g: tiles in x (tx) and y (ty) and, in
@@ -959,12 +994,24 @@ template void launch_sweep2_3d<float>(const LevelGeom &, const Stencil<float> &,
 
 void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
-                     const int *stop)
+                     const int *stop, const cd *pwf)
 {
     int nb, tx, ty, tz;
     grid_of(g, nb, tx, ty, tz);
-    hipLaunchKernelGGL(k_refine3d, dim3(nb), dim3(256), 0, s, u, d, b, q, unew, r32, P, tx, ty, tz, partial, ctl,
-                       stop);
+    if (b)
+        hipLaunchKernelGGL(k_refine3d<false>, dim3(nb), dim3(256), 0, s, u, d, b, q, unew, r32, P, tx, ty, tz,
+                           partial, ctl, stop, nullptr);
+    else
+        hipLaunchKernelGGL(k_refine3d<true>, dim3(nb), dim3(256), 0, s, u, d, nullptr, q, unew, r32, P, tx, ty, tz,
+                           partial, ctl, stop, pwf);
+}
+
+void launch_resid3d_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,
+                       const SolveCtl *ctl, double *partial, const cd *pwf, hipStream_t s)
+{
+    int nb, tx, ty, tz;
+    grid_of(g, nb, tx, ty, tz);
+    hipLaunchKernelGGL(k_resid3d_pw, dim3(nb), dim3(256), 0, s, u, q, r32, P, tx, ty, tz, partial, ctl, pwf);
 }
 
 template void launch_sweep3d_fused<double>(bool, const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
@@ -1393,10 +1440,13 @@ __device__ __forceinline__ double fmg_scale(const double *bnorm2, double inv_sqN
 }
 
 // b_1 = b_0 / s at the coarse nodes (injection of the finest right-hand side).
+// (bf = null: b is the plane-wave right-hand side q u_in, formed from q and
+// the factors pwf at the injected points.)
 template <typename TO>
 __global__ __launch_bounds__(256) void k_inject_rhs(const cd *__restrict__ bf, cx<TO> *__restrict__ bc, int mxf,
                                                     int myf, int mxc, int myc, int mzc, int dim,
-                                                    const double *__restrict__ bnorm2, double inv_sqN)
+                                                    const double *__restrict__ bnorm2, double inv_sqN,
+                                                    const cd *__restrict__ qf, const cd *__restrict__ pwf)
 {
     size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     size_t Nc = (size_t)mxc * myc * mzc;
@@ -1407,20 +1457,24 @@ __global__ __launch_bounds__(256) void k_inject_rhs(const cd *__restrict__ bf, c
     int J = (int)(rest % myc);
     int K = (int)(rest / myc);
     int z = (dim == 3) ? 2 * K + 1 : 0;
-    cd v = bf[((size_t)z * myf + (2 * J + 1)) * mxf + (2 * I + 1)];
+    const size_t j = ((size_t)z * myf + (2 * J + 1)) * mxf + (2 * I + 1);
+    cd v = bf ? bf[j] : qf[j] * pw_uin(pwf, 2 * I + 1, 2 * J + 1, z, mxf, myf, dim);
     bc[idx] = cvt<TO>(cd{v.re * inv, v.im * inv});
 }
 
 template <typename TO>
-void launch_inject_rhs(const LevelGeom &f, const cd *bf, cx<TO> *bc, const double *bnorm2, hipStream_t s)
+void launch_inject_rhs(const LevelGeom &f, const cd *bf, cx<TO> *bc, const double *bnorm2, hipStream_t s,
+                       const cd *qf, const cd *pwf)
 {
     int mxc = (f.m[0] - 1) / 2, myc = (f.m[1] - 1) / 2, mzc = (f.dim == 3) ? (f.m[2] - 1) / 2 : 1;
     size_t Nc = (size_t)mxc * myc * mzc;
     hipLaunchKernelGGL((k_inject_rhs<TO>), dim3((unsigned)((Nc + 255) / 256)), dim3(256), 0, s, bf, bc, f.m[0],
-                       f.m[1], mxc, myc, mzc, f.dim, bnorm2, 1.0 / sqrt((double)f.N()));
+                       f.m[1], mxc, myc, mzc, f.dim, bnorm2, 1.0 / sqrt((double)f.N()), qf, pwf);
 }
-template void launch_inject_rhs<double>(const LevelGeom &, const cd *, cd *, const double *, hipStream_t);
-template void launch_inject_rhs<float>(const LevelGeom &, const cd *, cf *, const double *, hipStream_t);
+template void launch_inject_rhs<double>(const LevelGeom &, const cd *, cd *, const double *, hipStream_t, const cd *,
+                                        const cd *);
+template void launch_inject_rhs<float>(const LevelGeom &, const cd *, cf *, const double *, hipStream_t, const cd *,
+                                       const cd *);
 
 // uf = s P ec: the interpolated coarse solution overwrites uf (the initial
 // guess of the next finer level).
@@ -1824,9 +1878,13 @@ template void launch_coarse_apply<float>(const cd *, int, const cf *, cf *, hipS
 
 // ---------------------------------------------------------------------------
 // b_j = q_j exp(i k0 e^{i gamma} eta.x_j): the plane wave on the contour.
-__device__ __forceinline__ cd rhs_point(const cd *__restrict__ q, size_t j, int mx, int my, int dim, double lx,
-                                        double ly, double lz, double hx, double hy, double hz, double ex, double ey,
-                                        double ez, double ar_s, double ai_s)
+// b = q exp(i k0 cos(gamma) eta.x) at point j: the plane wave's phase along
+// the real coordinates without the contour's growth factor (the stress
+// right-hand side at k0 h = 1/2, where exp(i k0 eta.z) leaves the
+// floating-point range).
+__device__ __forceinline__ cd phase_rhs_point(const cd *__restrict__ q, size_t j, int mx, int my, int dim,
+                                              double lx, double ly, double lz, double hx, double hy, double hz,
+                                              double ex, double ey, double ez, double ai_s)
 {
     int ix = (int)(j % mx);
     size_t rest = j / mx;
@@ -1834,44 +1892,72 @@ __device__ __forceinline__ cd rhs_point(const cd *__restrict__ q, size_t j, int 
     double t = ex * (lx + (double)(ix + 1) * hx);
     if (dim >= 2) t += ey * (ly + (double)(iy + 1) * hy);
     if (dim >= 3) t += ez * (lz + (double)(iz + 1) * hz);
-    double mag = exp(ar_s * t);
     double ph = ai_s * t;
-    cd uin = {mag * cos(ph), mag * sin(ph)};
-    return q[j] * uin;
+    return q[j] * cd{cos(ph), sin(ph)};
 }
 
-__global__ __launch_bounds__(256) void k_rhs(const cd *__restrict__ q, cd *__restrict__ b, int mx, int my, int mz,
-                                             int dim, double lx, double ly, double lz, double hx, double hy,
-                                             double hz, double ex, double ey, double ez, double ar_s, double ai_s)
+__global__ __launch_bounds__(256) void k_rhs_phase(const cd *__restrict__ q, cd *__restrict__ b, int mx, int my,
+                                                   int mz, int dim, double lx, double ly, double lz, double hx,
+                                                   double hy, double hz, double ex, double ey, double ez,
+                                                   double ai_s)
 {
     size_t N = (size_t)mx * my * mz;
     for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256)
-        b[j] = rhs_point(q, j, mx, my, dim, lx, ly, lz, hx, hy, hz, ex, ey, ez, ar_s, ai_s);
+        b[j] = phase_rhs_point(q, j, mx, my, dim, lx, ly, lz, hx, hy, hz, ex, ey, ez, ai_s);
 }
 
-void launch_rhs_plane_wave(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
-                           hipStream_t s)
+// The plane wave's per-axis factors on grid g (the layout of pw_uin), from
+// c_k = cr_k + i ci_k.
+__global__ __launch_bounds__(256) void k_pw_factors(cd *__restrict__ f, int mx, int my, int mz, double lx,
+                                                    double ly, double lz, double hx, double hy, double hz,
+                                                    double crx, double cix, double cry, double ciy, double crz,
+                                                    double ciz)
 {
-    // i k0 e^{i gamma} t = (-k0 sin gamma) t + i (k0 cos gamma) t
-    double ar_s = -(k0 * sin(gamma)), ai_s = k0 * cos(gamma);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < mx) f[i] = pw_factor(i, lx, hx, crx, cix);
+    else if (i < mx + my) f[i] = pw_factor(i - mx, ly, hy, cry, ciy);
+    else if (i < mx + my + mz) f[i] = pw_factor(i - mx - my, lz, hz, crz, ciz);
+}
+
+void launch_pw_factors(const LevelGeom &g, double gamma, double k0, const double eta[3], cd *f, hipStream_t s)
+{
+    // i k0 e^{i gamma} eta_k = (-k0 sin gamma) eta_k + i (k0 cos gamma) eta_k
+    const double ar = -(k0 * sin(gamma)), ai = k0 * cos(gamma);
+    const int n = g.m[0] + g.m[1] + g.m[2];
+    hipLaunchKernelGGL(k_pw_factors, dim3((n + 255) / 256), dim3(256), 0, s, f, g.m[0], g.m[1], g.m[2], g.lo[0],
+                       g.lo[1], g.lo[2], g.h[0], g.h[1], g.h[2], ar * eta[0], ai * eta[0], ar * eta[1], ai * eta[1],
+                       ar * eta[2], ai * eta[2]);
+}
+
+// b = q u_in point by point from the factors f.
+__global__ __launch_bounds__(256) void k_rhs(const cd *__restrict__ q, const cd *__restrict__ f, cd *__restrict__ b,
+                                             int mx, int my, int mz, int dim)
+{
+    size_t N = (size_t)mx * my * mz;
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
+        const int ix = (int)(j % mx);
+        const size_t rest = j / mx;
+        const int iy = (int)(rest % my), iz = (int)(rest / my);
+        b[j] = q[j] * pw_uin(f, ix, iy, iz, mx, my, dim);
+    }
+}
+
+void launch_rhs_plane_wave(const LevelGeom &g, const cd *q, const cd *f, cd *b, hipStream_t s)
+{
     size_t N = g.N();
     size_t nb = (N + 255) / 256;
     if (nb > 65536) nb = 65536;
-    hipLaunchKernelGGL(k_rhs, dim3((unsigned)nb), dim3(256), 0, s, q, b, g.m[0], g.m[1], g.m[2], g.dim, g.lo[0],
-                       g.lo[1], g.lo[2], g.h[0], g.h[1], g.h[2], eta[0], eta[1], eta[2], ar_s, ai_s);
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)nb), dim3(256), 0, s, q, f, b, g.m[0], g.m[1], g.m[2], g.dim);
 }
 
-// b = q exp(i k0 cos(gamma) eta.x): the plane wave's phase along the real
-// coordinates without the contour's growth factor (the stress right-hand side
-// at k0 h = 1/2, where exp(i k0 eta.z) leaves the floating-point range).
 void launch_rhs_phase(const LevelGeom &g, double gamma, double k0, const double eta[3], const cd *q, cd *b,
                       hipStream_t s)
 {
     size_t N = g.N();
     size_t nb = (N + 255) / 256;
     if (nb > 65536) nb = 65536;
-    hipLaunchKernelGGL(k_rhs, dim3((unsigned)nb), dim3(256), 0, s, q, b, g.m[0], g.m[1], g.m[2], g.dim, g.lo[0],
-                       g.lo[1], g.lo[2], g.h[0], g.h[1], g.h[2], eta[0], eta[1], eta[2], 0.0, k0 * cos(gamma));
+    hipLaunchKernelGGL(k_rhs_phase, dim3((unsigned)nb), dim3(256), 0, s, q, b, g.m[0], g.m[1], g.m[2], g.dim,
+                       g.lo[0], g.lo[1], g.lo[2], g.h[0], g.h[1], g.h[2], eta[0], eta[1], eta[2], k0 * cos(gamma));
 }
 
 // ---------------------------------------------------------------------------
@@ -1920,15 +2006,27 @@ void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const
 // formed in the same order.
 int norm2_blocks(size_t N) { return (int)std::min<size_t>((N + 255) / 256, 1024); }
 
-// b = q exp(i k0 e^{i gamma} eta.x) and u = 0.
+// The plane wave's per-axis factors of every instance (the values of
+// k_pw_factors for its grid and direction).
+__global__ __launch_bounds__(256) void k_init_pw_batch(const InitJob *__restrict__ jobs)
+{
+    const InitJob &J = jobs[blockIdx.y];
+    const LevelGeom &g = J.g;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < g.m[0]) J.f[i] = pw_factor(i, g.lo[0], g.h[0], J.ar_s * J.eta[0], J.ai_s * J.eta[0]);
+    else if (i < g.m[0] + g.m[1])
+        J.f[i] = pw_factor(i - g.m[0], g.lo[1], g.h[1], J.ar_s * J.eta[1], J.ai_s * J.eta[1]);
+}
+
+// b = q u_in and u = 0.
 __global__ __launch_bounds__(256) void k_init_rhs_batch(const InitJob *__restrict__ jobs)
 {
     const InitJob &J = jobs[blockIdx.y];
     const LevelGeom &g = J.g;
-    const size_t N = (size_t)g.m[0] * g.m[1];
+    const int mx = g.m[0];
+    const size_t N = (size_t)mx * g.m[1];
     for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
-        J.b[j] = rhs_point(J.q, j, g.m[0], g.m[1], 2, g.lo[0], g.lo[1], 0.0, g.h[0], g.h[1], 0.0, J.eta[0],
-                           J.eta[1], 0.0, J.ar_s, J.ai_s);
+        J.b[j] = J.q[j] * pw_uin(J.f, (int)(j % mx), (int)(j / mx), 0, mx, g.m[1], 2);
         J.u[j] = cd{0.0, 0.0};
     }
 }
@@ -1991,9 +2089,10 @@ __global__ __launch_bounds__(256) void k_finish_batch(const FinishJob *__restric
     for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < J.N; j += (size_t)gridDim.x * 256) J.u[j] = J.t[j];
 }
 
-void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, hipStream_t s)
+void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_m, hipStream_t s)
 {
     if (n <= 0) return;
+    hipLaunchKernelGGL(k_init_pw_batch, dim3((2 * max_m + 255) / 256, n), dim3(256), 0, s, jobs);
     hipLaunchKernelGGL(k_init_rhs_batch, dim3(1024, n), dim3(256), 0, s, jobs);
     hipLaunchKernelGGL(k_init_norm_batch, dim3(max_nb_norm, n), dim3(256), 0, s, jobs);
     hipLaunchKernelGGL(k_init_ctl_batch, dim3(n), dim3(256), 0, s, jobs);

@@ -252,8 +252,15 @@ def _eta3(eta):
     return e
 
 
+def _opt_dev_ptr(t, name):
+    return ctypes.c_void_p(None) if t is None else _dev_ptr(t, name)
+
+
 def mg_rhs_plane_wave(h: Handle, eta, b):
-    h._check(lib().mg_rhs_plane_wave(h.ptr, _eta3(eta), _dev_ptr(b, "b")), "mg_rhs_plane_wave")
+    """b = q exp(i k0 eta.z) (Sec. 2.1); also records eta as the handle's
+    plane wave.  b = None records it only: mg_solve(h, None, u) then solves
+    for that right-hand side without storing it."""
+    h._check(lib().mg_rhs_plane_wave(h.ptr, _eta3(eta), _opt_dev_ptr(b, "b")), "mg_rhs_plane_wave")
     return b
 
 
@@ -391,7 +398,7 @@ def mg_fmg(h: Handle, b, u, k):
 
 def mg_solve(h: Handle, b, u, tol=1e-10, raise_on_noconv=True):
     info = SolveInfo()
-    st = lib().mg_solve(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol), ctypes.byref(info))
+    st = lib().mg_solve(h.ptr, _opt_dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol), ctypes.byref(info))
     if st != FFMG_OK and (st != FFMG_ENOCONV or raise_on_noconv):
         h._check(st, "mg_solve")
     return info
@@ -399,8 +406,9 @@ def mg_solve(h: Handle, b, u, tol=1e-10, raise_on_noconv=True):
 
 def mg_solve_begin(h: Handle, b, u, tol=1e-10):
     """Queue a solve on the handle's stream and return without waiting;
-    b and u must stay untouched until mg_solve_end."""
-    h._check(lib().mg_solve_begin(h.ptr, _dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol)), "mg_solve_begin")
+    b and u must stay untouched until mg_solve_end (b = None: the handle's
+    plane wave, as mg_solve)."""
+    h._check(lib().mg_solve_begin(h.ptr, _opt_dev_ptr(b, "b"), _dev_ptr(u, "u"), float(tol)), "mg_solve_begin")
 
 
 def mg_solve_end(h: Handle, raise_on_noconv=True):
