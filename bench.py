@@ -88,10 +88,10 @@ KERNELS = {"pre": 0, "ff": 1, "post": 2, "refine": 3, "ffgemm": 4, "net": 5, "rr
 #   refine  FP64 update + residual: read u, b, q (16 each), d (8); write u (16), r (8)
 # "pre" brackets two passes (two sweeps from a zero guess, 3e; two sweeps
 # from a guess, 4e) and is reported, not ranked.
-# (the 3D refinement pass forms the plane-wave right-hand side from q instead
-# of reading it: read u, q (16 B each), d (8); write u, r (16 + 8))
+# (the refinement pass forms the plane-wave right-hand side from q instead of
+# reading it: read u, q (16 B each), d (8); write u, r (16 + 8))
 BPP = {3: {"mixed": {"post": 33.0, "rr": 25.0, "refine": 64.0}, "plain": {"post": 66.0, "rr": 50.0}},
-       2: {"mixed": {"post": 34.0, "refine": 80.0}, "plain": {"post": 68.0}}}
+       2: {"mixed": {"post": 34.0, "refine": 64.0}, "plain": {"post": 68.0}}}
 KERNEL_NAMES = {
     3: {"post": "k_sweep2_3d<%s, SRC_PROL> (finest level: interpolation of the coarse correction + two Jacobi sweeps "
                 "in one z-marching pass)",
@@ -100,7 +100,7 @@ KERNEL_NAMES = {
                   "right-hand side formed from q)",
         "pre": "k_sweep2_3d<%s, SRC_ZERO2 / SRC_MEM> (finest level: two Jacobi sweeps per pass)"},
     2: {"post": "k_smooth2d<%s, 2, false, true, 1, TH> (finest level: interpolation + two fused Jacobi sweeps)",
-        "refine": "k_refine2d (FP64 update + residual)",
+        "refine": "k_refine2d (FP64 update + residual; the plane-wave right-hand side formed from q)",
         "pre": "k_smooth_rr2d<%s, *, 1, *> (finest level: two sweeps + residual + full weighting)"},
 }
 # Useful flops of one learned-smoother application per point: 2736 complex

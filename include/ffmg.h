@@ -194,8 +194,8 @@ ffmg_status mg_fmg(ffmg_handle *h, const void *b, void *u, int k);
  * b: DEVICE complex128[N], read; or NULL for the plane-wave right-hand side
  * of the eta last given to mg_rhs_plane_wave on this handle (EINVAL if
  * none), with the same result, bit for bit, as passing what
- * mg_rhs_plane_wave writes.  The FP32_IR solve of a 3D handle with the fused
- * kernels and the Jacobi smoother never stores that b: its FP64 kernels form
+ * mg_rhs_plane_wave writes.  The FP32_IR solve with the fused kernels and
+ * the Jacobi smoother never stores that b: its FP64 kernels form
  * q exp(i k0 eta.z) where they read it, which saves 16 bytes per point in
  * each FP64 residual pass; other configurations store it once in the handle
  * (N complex128, allocated on first use). */

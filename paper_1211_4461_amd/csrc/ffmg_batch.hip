@@ -32,8 +32,8 @@ namespace ffmg {
 struct BatchInst {
     ffmg_handle *op = nullptr;
     int D = 0;                            // levels above the tail (tail starts at level D)
-    cd *b = nullptr, *t = nullptr;        // FP64 right-hand side, iterate ping-pong
-    cd *f = nullptr;                      // the plane wave's per-axis factors
+    cd *t = nullptr;                      // the other buffer of the FP64 iterate
+    cd *f = nullptr;                      // the plane wave's per-axis factors (b = q u_in is never stored)
     std::vector<cf *> u32, b32, t32, r32; // FP32 cycle: levels 0..D (t32, r32: 0..D-1)
     double *parts = nullptr;
     SolveCtl *ctl = nullptr;
@@ -351,6 +351,8 @@ XferJob xfer_job(const BatchInst &I, int l, const void *src, void *dst, bool f64
     XferJob j;
     j.src = src;
     j.dst = dst;
+    j.qf = nullptr;
+    j.pwf = nullptr;
     j.mxf = f.m[0];
     j.myf = f.m[1];
     j.mxc = c.m[0];
@@ -373,7 +375,10 @@ void build_fmg(Plan &pl, Batch &B, int k)
     std::vector<XferJob> js;
     for (int i = 0; i < n; ++i) {
         BatchInst &I = B.inst[i];
-        js.push_back(xfer_job(I, 0, I.b, I.b32[1], true));
+        XferJob j = xfer_job(I, 0, nullptr, I.b32[1], true);   // b = q u_in formed at the injected points
+        j.qf = I.op->L[0].q;
+        j.pwf = I.f;
+        js.push_back(j);
     }
     add_xfer(pl, pl.fmg, 0, js);
     for (int s = 1; s < Dmax; ++s) {
@@ -507,7 +512,6 @@ ffmg_status build_batch(ffmg_handle *const *hs, int count, Batch **out)
     for (BatchInst &I : B.inst) {
         const LevelGeom &g0 = I.op->L[0].g;
         const size_t N0 = g0.N();
-        BCHK(B.alloc((void **)&I.b, N0 * sizeof(cd)));
         BCHK(B.alloc((void **)&I.t, N0 * sizeof(cd)));
         BCHK(B.alloc((void **)&I.f, (size_t)(g0.m[0] + g0.m[1]) * sizeof(cd)));
         B.max_m = std::max(B.max_m, std::max(g0.m[0], g0.m[1]));
@@ -654,7 +658,6 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
         const LevelGeom &g = l0.g;
         InitJob &J = B.init[i];
         J.q = l0.q;
-        J.b = I.b;
         J.u = (cd *)u[i];
         J.f = I.f;
         J.r32 = I.b32[0];
@@ -675,7 +678,8 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
         J.tiles_x = stx;
         RefineJob R;
         R.d = I.u32[0];
-        R.b = I.b;
+        R.b = nullptr;   // the plane wave's q u_in from I.f
+        R.f = I.f;
         R.q = l0.q;
         R.r32 = I.b32[0];
         R.ctl = I.ctl;
@@ -710,7 +714,7 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
     if (B.fmg > 0)
         BCHK(hipMemcpyAsync(B.d_xfin, B.xfin.data(), count * sizeof(XferJob), hipMemcpyHostToDevice, B.stream));
     BCHK(hipEventRecord(e0, B.stream));
-    launch_init_batch(B.d_init, count, B.max_nb_norm, B.max_m, B.stream);
+    launch_init_batch(B.d_init, count, B.max_nb_norm, B.max_m, B.fmg == 0, B.stream);
     if (B.fmg > 0) BCHK(hipGraphLaunch(B.fmg_exec, B.stream));
     launch_init_resid_batch(B.d_init, count, B.max_nb_res, B.stream);
     launch_ctl_update_batch(B.d_ctl0, count, B.stream);

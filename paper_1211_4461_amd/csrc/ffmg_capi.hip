@@ -134,11 +134,9 @@ __global__ __launch_bounds__(256) void k_norm2_pw(const cd *__restrict__ q, cons
 {
     __shared__ double red[4];
     double acc = 0.0;
-    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
-        const int ix = (int)(j % mx);
-        const size_t rest = j / mx;
-        acc += abs2(q[j] * pw_uin(f, ix, (int)(rest % my), (int)(rest / my), mx, my, dim));
-    }
+    const size_t j0 = (size_t)blockIdx.x * 256 + threadIdx.x, S = (size_t)gridDim.x * 256;
+    GridWalk w(j0, S, mx, my);
+    for (size_t j = j0; j < N; j += S, w.step()) acc += abs2(q[j] * pw_uin(f, w.x, w.y, w.z, mx, my, dim));
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -641,7 +639,8 @@ void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *st
     for (int c = 0; c < inner; ++c) vcycle<float>(h, 0, l0.b32, l0.u32, c == 0, stop);
     if (l0.g.dim == 2 && h->opt.tile_config != TILE_REFERENCE) {
         int pi = prof_kernel_begin(h, PROF_REFINE);
-        launch_refine2d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop);
+        launch_refine2d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop,
+                        h->pw_f);
         prof_kernel_end(h, PROF_REFINE, pi);
         launch_ctl_update(h->d_ctl, h->d_parts, fused2d_blocks(l0.g), h->stream);
     } else if (l0.g.dim == 3 && h->opt.tile_config != TILE_REFERENCE) {
@@ -1065,12 +1064,12 @@ ffmg_status mg_rhs_plane_wave(ffmg_handle *h, const double eta[3], void *b)
 }
 
 // Solves with b = NULL take the plane wave of the last mg_rhs_plane_wave.
-// The FP32-in-FP64 3D solve with the fused kernels forms it where its FP64
+// The FP32-in-FP64 solve with the fused kernels forms it where its FP64
 // kernels need it (the norm, the start's injection, the residuals of the
 // refinement); every other path gets it stored once in the handle.
 static bool pw_implicit(const ffmg_handle *h)
 {
-    return h->opt.precision == FFMG_FP32_IR && h->opt.tile_config != TILE_REFERENCE && h->prob.dim == 3 &&
+    return h->opt.precision == FFMG_FP32_IR && h->opt.tile_config != TILE_REFERENCE &&
            h->opt.smoother == FFMG_SMOOTH_JACOBI && h->L.size() > 1;
 }
 
@@ -1354,7 +1353,7 @@ ffmg_status mg_solve_begin(ffmg_handle *h, const void *bv, void *uv, double tol)
     if (h->opt.precision == FFMG_FP64)
         launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u0, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
     else if (!b)
-        launch_resid3d_pw(l0.g, l0.P64, u0, l0.q, l0.b32, h->d_ctl, h->d_parts, h->pw_f, h->stream);
+        launch_resid_pw(l0.g, l0.P64, u0, l0.q, l0.b32, h->d_ctl, h->d_parts, h->pw_f, h->stream);
     else
         launch_resid_to_f32_ctl(l0.g, l0.P64, u0, b, l0.q, l0.b32, h->d_ctl, h->d_parts, h->stream, nullptr);
     launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);

@@ -146,6 +146,39 @@ __device__ __forceinline__ cd pw_factor(int i, double lo, double h, double cr, d
     return cd{mag * cos(ph), mag * sin(ph)};
 }
 
+// (x, y, z) of flat index j = x + mx (y + my z) stepped by a fixed stride
+// without a division per step (grid-stride loops): the stride's own digits
+// are added with carries.
+struct GridWalk {
+    int x, y, z, sx, sy, sz, mx, my;
+    __device__ __forceinline__ GridWalk(size_t j, size_t stride, int mx_, int my_) : mx(mx_), my(my_)
+    {
+        const size_t pl = (size_t)mx_ * my_;
+        x = (int)(j % mx_);
+        y = (int)((j / mx_) % my_);
+        z = (int)(j / pl);
+        sx = (int)(stride % mx_);
+        sy = (int)((stride / mx_) % my_);
+        sz = (int)(stride / pl);
+    }
+    __device__ __forceinline__ void step()
+    {
+        x += sx;
+        int c = 0;
+        if (x >= mx) {
+            x -= mx;
+            c = 1;
+        }
+        y += sy + c;
+        c = 0;
+        if (y >= my) {
+            y -= my;
+            c = 1;
+        }
+        z += sz + c;
+    }
+};
+
 // The plane wave at interior point (ix, iy, iz): (E_x E_y) E_z, or E_x E_y in
 // 2D.  Every kernel that forms the right-hand side q u_in takes it from here,
 // in this order, so a stored and a recomputed right-hand side agree bit for

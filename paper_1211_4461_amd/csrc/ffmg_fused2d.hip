@@ -471,11 +471,13 @@ __global__ __launch_bounds__(256) void k_smooth_rr2d(const cx<T> *__restrict__ u
 // Mixed-precision outer step: u' = u + s d with s = ctl->scale_cur;
 // r = b - A u' (FP64); r32 = r / ctl->scale_next; per-block sum |r|^2.
 // Out of place in u.
+// b = null: the right-hand side is the plane wave's q u_in from the factors pwf.
 __device__ __forceinline__ void refine2d_body(const cd *__restrict__ u, const cf *__restrict__ d,
                                               const cd *__restrict__ b, const cd *__restrict__ q,
                                               cd *__restrict__ u_out, cf *__restrict__ r32,
                                               const SolveCtl *__restrict__ ctl, const Stencil<double> &P,
-                                              int tiles_x, int tile, double *__restrict__ partial_slot)
+                                              int tiles_x, int tile, double *__restrict__ partial_slot,
+                                              const cd *__restrict__ pwf)
 {
     const double s = ctl->scale_cur;
     const double inv_scale = 1.0 / ctl->scale_next;
@@ -506,8 +508,10 @@ __device__ __forceinline__ void refine2d_body(const cd *__restrict__ u, const cf
         if (gx < mx && gy < my) {
             size_t j = (size_t)gy * mx + gx;
             cd uc = U[ly + 1][lx + 1];
+            const cd qj = q[j];
+            const cd bj = b ? b[j] : qj * pw_uin(pwf, gx, gy, 0, mx, my, 2);
             cd r = resid_point<double>(P, uc, U[ly + 1][lx], U[ly + 1][lx + 2], U[ly][lx + 1], U[ly + 2][lx + 1],
-                                       b[j], q[j]);
+                                       bj, qj);
             u_out[j] = uc;
             r32[j] = cvt<float>(inv_scale * r);
             acc += abs2(r);
@@ -524,10 +528,12 @@ __global__ __launch_bounds__(256) void k_refine2d(const cd *__restrict__ u, cons
                                                   const cd *__restrict__ b, const cd *__restrict__ q,
                                                   cd *__restrict__ u_out, cf *__restrict__ r32,
                                                   const SolveCtl *__restrict__ ctl, Stencil<double> P, int tiles_x,
-                                                  double *__restrict__ partial, const int *__restrict__ stop)
+                                                  double *__restrict__ partial, const int *__restrict__ stop,
+                                                  const cd *__restrict__ pwf)
 {
     if (stop && *stop) return;
-    refine2d_body(u, d, b, q, u_out, r32, ctl, P, tiles_x, xcd_tile(blockIdx.x, gridDim.x), partial + blockIdx.x);
+    refine2d_body(u, d, b, q, u_out, r32, ctl, P, tiles_x, xcd_tile(blockIdx.x, gridDim.x), partial + blockIdx.x,
+                  pwf);
 }
 
 // ---------------------------------------------------------------------------
@@ -907,11 +913,12 @@ template void launch_smooth_rr2d<float>(const LevelGeom &, const Stencil<float> 
 
 void launch_refine2d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *u_out, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t st,
-                     const int *stop)
+                     const int *stop, const cd *pwf)
 {
     int tx;
     int nb = tiles2d(g, tx);
-    launch_maybe_timed(k_refine2d, dim3(nb), dim3(256), 0, st, u, d, b, q, u_out, r32, ctl, P, tx, partial, stop);
+    launch_maybe_timed(k_refine2d, dim3(nb), dim3(256), 0, st, u, d, b, q, u_out, r32, ctl, P, tx, partial, stop,
+                       pwf);
 }
 
 template <typename T>
@@ -997,7 +1004,7 @@ __global__ __launch_bounds__(256) void k_refine2d_batch(const RefineJob *__restr
     if (J.stop && *J.stop) return;
     const int tile = t - J.tile0;
     refine2d_body(J.u, J.d, J.b, J.q, J.u_out, J.r32, J.ctl, J.P, J.tiles_x, tile,
-                  J.partial + xcd_tile_inv(tile, J.ntiles));
+                  J.partial + xcd_tile_inv(tile, J.ntiles), J.f);
 }
 
 template <typename T>

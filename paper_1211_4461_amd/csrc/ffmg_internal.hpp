@@ -188,9 +188,10 @@ void launch_refine_update(const cf *d, cd *u, const SolveCtl *ctl, size_t N, hip
 void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
                      const int *stop, const cd *pwf = nullptr);
-// r32 = (q u_in - A u) / ctl->scale_next with block sums of its FP64 square (3D)
-void launch_resid3d_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,
-                       const SolveCtl *ctl, double *partial, const cd *pwf, hipStream_t s);
+// r32 = (q u_in - A u) / ctl->scale_next with block sums of its FP64 square
+// (the blocks of launch_resid_to_f32_ctl)
+void launch_resid_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,
+                     const SolveCtl *ctl, double *partial, const cd *pwf, hipStream_t s);
 // two Jacobi sweeps in one 3D pass from u (ec: from u + P ec; zero: from a zero guess, u not read);
 // shape: the tile, as FFMG_TUNE_SWEEP3D variants 0, 2, 3 (the same bits with every tile)
 template <typename T>
@@ -222,7 +223,7 @@ void launch_smooth_rr2d(const LevelGeom &g, const Stencil<T> &P, bool zero, cons
                         const cx<T> *q, cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop, int fh);
 void launch_refine2d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *u_out, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t st,
-                     const int *stop);
+                     const int *stop, const cd *pwf = nullptr);
 
 // The coarse end of a 2D V-cycle in one workgroup, all fields in LDS: the
 // levels lt .. L-1 of the hierarchy (small enough for LDS) and the exact
@@ -286,7 +287,8 @@ struct SRRJob {             // one-pass pre-smoothing + residual + restriction
 struct RefineJob {
     const cd *u;
     const cf *d;
-    const cd *b, *q;
+    const cd *b, *q;       // b = null: the plane wave's q u_in from f
+    const cd *f;
     cd *u_out;
     cf *r32;
     const SolveCtl *ctl;
@@ -328,13 +330,14 @@ void launch_tail2d_batch(const TailJob<T> *jobs, int njobs, size_t lds_bytes, hi
 template <typename T>
 void launch_tail2d_fmg_batch(const TailJob<T> *jobs, int njobs, int k, size_t lds_bytes, hipStream_t s);
 
-// Per-instance setup of a batched solve (ffmg_stencil.hip): plane-wave
-// right-hand side, zero guess, ||b||^2, control init and the initial scaled
-// FP32 residual, in the block structure of the single-instance kernels.
+// Per-instance setup of a batched solve (ffmg_stencil.hip): the plane wave's
+// factors, zero guess, ||b||^2, control init and the initial scaled FP32
+// residual, in the block structure of the single-instance kernels (b = q u_in
+// formed where it is read).
 struct InitJob {
     const cd *q;
-    cd *b, *u;
-    cd *f;                 // the plane wave's per-axis factors (mx + my values)
+    cd *u;
+    cd *f;                 // the plane wave's per-axis factors (mx + my values); b = q u_in is not stored
     cf *r32;
     SolveCtl *ctl;
     double *partial;
@@ -364,8 +367,9 @@ struct FinishJob {
 // solution interpolated onto the next finer level (into the FP64 finest
 // level: multiplied by it).
 struct XferJob {
-    const void *src;
+    const void *src;          // kind 0 with src = null: the plane wave's q u_in (qf, pwf)
     void *dst;
+    const cd *qf, *pwf;
     int mxf, myf, mxc, myc;   // fine and coarse interior extents
     const double *bnorm2;     // ||b||^2 of the finest level when an FP64 end is involved, else null
     double inv_sqN;           // 1 / sqrt(N) of the finest level
@@ -378,9 +382,9 @@ void launch_xfer_batch(int kind, const XferJob *jobs, int njobs, size_t max_n, h
 int norm2_blocks(size_t N);
 void launch_hash_fill(cd *out, size_t N, unsigned long long seed, hipStream_t s);
 void stencil_grid2d(const LevelGeom &g, int *nb, int *tiles_x);   // blocks and tiles per row of k_stencil2d
-// plane-wave right-hand side, u = 0, ||b||^2 and the control block (max_m:
-// the largest grid extent among the instances)
-void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_m, hipStream_t s);
+// the plane wave's factors, u = 0 (zero), ||b||^2 and the control block
+// (max_m: the largest grid extent among the instances)
+void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_m, bool zero, hipStream_t s);
 // the initial residual b - A u as the scaled FP32 right-hand side
 void launch_init_resid_batch(const InitJob *jobs, int n, int max_nb_res, hipStream_t s);
 void launch_ctl_update_batch(const CtlJob *jobs, int n, hipStream_t s);

@@ -88,6 +88,24 @@ __device__ __forceinline__ void point_update(const Stencil<T> &P, T rscale, cx<T
     }
 }
 
+// The point update of a 3D pass with b_j and q_j already in registers.
+template <typename T, typename TO, int MODE>
+__device__ __forceinline__ void point_update_v(const Stencil<T> &P, T rscale, cx<T> uc, cx<T> L, size_t j, cx<T> bj,
+                                               cx<T> qj, cx<TO> *__restrict__ out, double &acc)
+{
+    if (MODE == MODE_APPLY) {
+        out[j] = cvt<TO>(apply_point(P, L, uc, qj));
+    } else if (MODE == MODE_JACOBI0) {
+        out[j] = cvt<TO>(jacobi0_w(bj, jweight(P, qj)));
+    } else if (MODE == MODE_JACOBI) {
+        out[j] = cvt<TO>(jacobi_n(P, L, uc, bj, jweight(P, qj)));
+    } else {
+        cx<T> r = resid_from(P, L, uc, bj, qj);
+        if (MODE == MODE_RESID) out[j] = cvt<TO>(rscale * r);
+        acc += (double)abs2(r);
+    }
+}
+
 __device__ __forceinline__ void block_sum_256(double acc, double *slot)
 {
     __shared__ double red[4];
@@ -101,12 +119,15 @@ __device__ __forceinline__ void block_sum_256(double acc, double *slot)
 // 2D: 256 threads as 64 (x) x 4 (y), tile 64 x TY2, u tile + halo in LDS.
 // TAG only separates the finest-level launches into their own kernel symbol
 // (so a profiler's per-kernel statistics cover exactly those launches).
-template <typename T, typename TO, int MODE>
+// PW: the right-hand side is the plane wave's q u_in from the factors pwf
+// (b not read; FP64 residuals only).
+template <typename T, typename TO, int MODE, bool PW = false>
 __device__ __forceinline__ void stencil2d_body(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
                                                const cx<T> *__restrict__ q, cx<TO> *__restrict__ out,
                                                const Stencil<T> &P, T rscale, int tiles_x, int tile,
-                                               double *__restrict__ slot)
+                                               double *__restrict__ slot, const cd *__restrict__ pwf = nullptr)
 {
+    static_assert(!PW || (sizeof(T) == 8 && MODE == MODE_RESID), "plane-wave b: FP64 residuals");
     __shared__ cx<T> s[TY2 + 2][66];
     const int mx = P.mx, my = P.my;
     int tx0 = (tile % tiles_x) * 64, ty0 = (tile / tiles_x) * TY2;
@@ -136,7 +157,13 @@ __device__ __forceinline__ void stencil2d_body(const cx<T> *__restrict__ u, cons
                 else
                     lap = lap_xy(P, uc, s[ly + 1][lx], s[ly + 1][lx + 2], s[ly][lx + 1], s[ly + 2][lx + 1]);
             }
-            point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
+            if constexpr (PW) {
+                const cx<T> qj = q[j];
+                point_update_v<T, TO, MODE>(P, rscale, uc, lap, j, qj * pw_uin(pwf, gx, gy, 0, mx, my, 2), qj, out,
+                                            acc);
+            } else {
+                point_update<T, TO, MODE>(P, rscale, uc, lap, j, b, q, out, acc);
+            }
         }
     }
     if (MODE == MODE_RESID || MODE == MODE_RNORM)
@@ -245,23 +272,6 @@ __device__ __forceinline__ cx<T> prolong_at(const cx<T> *__restrict__ ec, int ix
 //             written to unew at the block's own points).
 enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2, SRC_UPD = 3 };
 
-// The point update of a 3D pass with b_j and q_j already in registers.
-template <typename T, typename TO, int MODE>
-__device__ __forceinline__ void point_update_v(const Stencil<T> &P, T rscale, cx<T> uc, cx<T> L, size_t j, cx<T> bj,
-                                               cx<T> qj, cx<TO> *__restrict__ out, double &acc)
-{
-    if (MODE == MODE_APPLY) {
-        out[j] = cvt<TO>(apply_point(P, L, uc, qj));
-    } else if (MODE == MODE_JACOBI0) {
-        out[j] = cvt<TO>(jacobi0_w(bj, jweight(P, qj)));
-    } else if (MODE == MODE_JACOBI) {
-        out[j] = cvt<TO>(jacobi_n(P, L, uc, bj, jweight(P, qj)));
-    } else {
-        cx<T> r = resid_from(P, L, uc, bj, qj);
-        if (MODE == MODE_RESID) out[j] = cvt<TO>(rscale * r);
-        acc += (double)abs2(r);
-    }
-}
 
 // Raw loads of one stencil value (the source form is applied when it is used).
 template <typename T>
@@ -1006,12 +1016,25 @@ void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, 
                            partial, ctl, stop, pwf);
 }
 
-void launch_resid3d_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,
-                       const SolveCtl *ctl, double *partial, const cd *pwf, hipStream_t s)
+__global__ __launch_bounds__(256) void k_resid2d_pw(const cd *__restrict__ u, const cd *__restrict__ q,
+                                                    cf *__restrict__ r32, Stencil<double> P, int tiles_x,
+                                                    double *__restrict__ partial, const SolveCtl *__restrict__ ctl,
+                                                    const cd *__restrict__ pwf)
+{
+    const double rscale = 1.0 / ctl->scale_next;
+    stencil2d_body<double, float, MODE_RESID, true>(u, nullptr, q, r32, P, rscale, tiles_x,
+                                                    xcd_tile(blockIdx.x, gridDim.x), partial + blockIdx.x, pwf);
+}
+
+void launch_resid_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,
+                     const SolveCtl *ctl, double *partial, const cd *pwf, hipStream_t s)
 {
     int nb, tx, ty, tz;
     grid_of(g, nb, tx, ty, tz);
-    hipLaunchKernelGGL(k_resid3d_pw, dim3(nb), dim3(256), 0, s, u, q, r32, P, tx, ty, tz, partial, ctl, pwf);
+    if (g.dim == 2)
+        hipLaunchKernelGGL(k_resid2d_pw, dim3(nb), dim3(256), 0, s, u, q, r32, P, tx, partial, ctl, pwf);
+    else
+        hipLaunchKernelGGL(k_resid3d_pw, dim3(nb), dim3(256), 0, s, u, q, r32, P, tx, ty, tz, partial, ctl, pwf);
 }
 
 template void launch_sweep3d_fused<double>(bool, const LevelGeom &, const Stencil<double> &, const cd *, const cd *,
@@ -1933,13 +1956,10 @@ void launch_pw_factors(const LevelGeom &g, double gamma, double k0, const double
 __global__ __launch_bounds__(256) void k_rhs(const cd *__restrict__ q, const cd *__restrict__ f, cd *__restrict__ b,
                                              int mx, int my, int mz, int dim)
 {
-    size_t N = (size_t)mx * my * mz;
-    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
-        const int ix = (int)(j % mx);
-        const size_t rest = j / mx;
-        const int iy = (int)(rest % my), iz = (int)(rest / my);
-        b[j] = q[j] * pw_uin(f, ix, iy, iz, mx, my, dim);
-    }
+    const size_t N = (size_t)mx * my * mz;
+    const size_t j0 = (size_t)blockIdx.x * 256 + threadIdx.x, S = (size_t)gridDim.x * 256;
+    GridWalk w(j0, S, mx, my);
+    for (size_t j = j0; j < N; j += S, w.step()) b[j] = q[j] * pw_uin(f, w.x, w.y, w.z, mx, my, dim);
 }
 
 void launch_rhs_plane_wave(const LevelGeom &g, const cd *q, const cd *f, cd *b, hipStream_t s)
@@ -2018,28 +2038,27 @@ __global__ __launch_bounds__(256) void k_init_pw_batch(const InitJob *__restrict
         J.f[i] = pw_factor(i - g.m[0], g.lo[1], g.h[1], J.ar_s * J.eta[1], J.ai_s * J.eta[1]);
 }
 
-// b = q u_in and u = 0.
-__global__ __launch_bounds__(256) void k_init_rhs_batch(const InitJob *__restrict__ jobs)
+// u = 0 (the start when there is no full multigrid start).
+__global__ __launch_bounds__(256) void k_init_zero_batch(const InitJob *__restrict__ jobs)
 {
     const InitJob &J = jobs[blockIdx.y];
-    const LevelGeom &g = J.g;
-    const int mx = g.m[0];
-    const size_t N = (size_t)mx * g.m[1];
-    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256) {
-        J.b[j] = J.q[j] * pw_uin(J.f, (int)(j % mx), (int)(j / mx), 0, mx, g.m[1], 2);
+    const size_t N = (size_t)J.g.m[0] * J.g.m[1];
+    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)gridDim.x * 256)
         J.u[j] = cd{0.0, 0.0};
-    }
 }
 
-// per-block |b|^2 with the partition of the single-instance norm
+// per-block |b|^2, b = q u_in, with the partition of the single-instance norm
 __global__ __launch_bounds__(256) void k_init_norm_batch(const InitJob *__restrict__ jobs)
 {
     const InitJob &J = jobs[blockIdx.y];
     const int nb = J.nb_norm;
     if ((int)blockIdx.x >= nb) return;
-    const size_t N = (size_t)J.g.m[0] * J.g.m[1];
+    const int mx = J.g.m[0], my = J.g.m[1];
+    const size_t N = (size_t)mx * my;
     double acc = 0.0;
-    for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < N; j += (size_t)nb * 256) acc += abs2(J.b[j]);
+    const size_t j0 = (size_t)blockIdx.x * 256 + threadIdx.x, S = (size_t)nb * 256;
+    GridWalk w(j0, S, mx, my);
+    for (size_t j = j0; j < N; j += S, w.step()) acc += abs2(J.q[j] * pw_uin(J.f, w.x, w.y, 0, mx, my, 2));
     block_sum_256(acc, J.partial + blockIdx.x);
 }
 
@@ -2059,8 +2078,8 @@ __global__ __launch_bounds__(256) void k_init_resid_batch(const InitJob *__restr
     const int nb = J.nb_res;
     if ((int)blockIdx.x >= nb) return;
     const double rscale = 1.0 / J.ctl->scale_next;
-    stencil2d_body<double, float, MODE_RESID>(J.u, J.b, J.q, J.r32, J.P, rscale, J.tiles_x,
-                                              xcd_tile(blockIdx.x, nb), J.partial + blockIdx.x);
+    stencil2d_body<double, float, MODE_RESID, true>(J.u, nullptr, J.q, J.r32, J.P, rscale, J.tiles_x,
+                                                    xcd_tile(blockIdx.x, nb), J.partial + blockIdx.x, J.f);
 }
 
 __global__ __launch_bounds__(256) void k_ctl_update_batch(const CtlJob *__restrict__ jobs)
@@ -2089,11 +2108,11 @@ __global__ __launch_bounds__(256) void k_finish_batch(const FinishJob *__restric
     for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < J.N; j += (size_t)gridDim.x * 256) J.u[j] = J.t[j];
 }
 
-void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_m, hipStream_t s)
+void launch_init_batch(const InitJob *jobs, int n, int max_nb_norm, int max_m, bool zero, hipStream_t s)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_init_pw_batch, dim3((2 * max_m + 255) / 256, n), dim3(256), 0, s, jobs);
-    hipLaunchKernelGGL(k_init_rhs_batch, dim3(1024, n), dim3(256), 0, s, jobs);
+    if (zero) hipLaunchKernelGGL(k_init_zero_batch, dim3(1024, n), dim3(256), 0, s, jobs);
     hipLaunchKernelGGL(k_init_norm_batch, dim3(max_nb_norm, n), dim3(256), 0, s, jobs);
     hipLaunchKernelGGL(k_init_ctl_batch, dim3(n), dim3(256), 0, s, jobs);
 }
@@ -2118,7 +2137,8 @@ __global__ __launch_bounds__(256) void k_xfer_batch(const XferJob *__restrict__ 
             const size_t f = (size_t)(2 * K + 1) * mxf + (2 * I + 1);
             if constexpr (KIND == 0) {
                 const double inv = 1.0 / fmg_scale(J.bnorm2, J.inv_sqN);
-                const cd v = static_cast<const cd *>(J.src)[f];
+                const cd v = J.src ? static_cast<const cd *>(J.src)[f]
+                                   : J.qf[f] * pw_uin(J.pwf, 2 * I + 1, 2 * K + 1, 0, mxf, J.myf, 2);
                 static_cast<cf *>(J.dst)[idx] = cvt<float>(cd{v.re * inv, v.im * inv});
             } else {
                 static_cast<cf *>(J.dst)[idx] = static_cast<const cf *>(J.src)[f];
