@@ -146,6 +146,23 @@ __device__ __forceinline__ cd pw_factor(int i, double lo, double h, double cr, d
     return cd{mag * cos(ph), mag * sin(ph)};
 }
 
+// (x, y, z) of flat index j = x + mx (y + my z), in 32-bit arithmetic when j
+// fits (a 64-bit division costs several times a 32-bit one).
+__device__ __forceinline__ void split3(size_t j, int mx, int my, int &x, int &y, int &z)
+{
+    if (j <= 0xffffffffull) {
+        const unsigned u = (unsigned)j, r = u / (unsigned)mx;
+        x = (int)(u - r * (unsigned)mx);
+        y = (int)(r % (unsigned)my);
+        z = (int)(r / (unsigned)my);
+    } else {
+        const size_t r = j / mx;
+        x = (int)(j - r * mx);
+        y = (int)(r % my);
+        z = (int)(r / my);
+    }
+}
+
 // (x, y, z) of flat index j = x + mx (y + my z) stepped by a fixed stride
 // without a division per step (grid-stride loops): the stride's own digits
 // are added with carries.

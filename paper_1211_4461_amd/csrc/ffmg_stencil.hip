@@ -1081,10 +1081,8 @@ __global__ __launch_bounds__(256) void k_restrict(const cx<T> *__restrict__ rf, 
     size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     size_t Nc = (size_t)mxc * myc * mzc;
     if (idx >= Nc) return;
-    int I = (int)(idx % mxc);
-    size_t rest = idx / mxc;
-    int J = (int)(rest % myc);
-    int K = (int)(rest / myc);
+    int I, J, K;
+    split3(idx, mxc, myc, I, J, K);
     const T w[3] = {T(0.25), T(0.5), T(0.25)};
     int fx = 2 * I + 1, fy = 2 * J + 1, fz = 2 * K + 1;
     cx<T> acc = {T(0), T(0)};
@@ -1287,10 +1285,8 @@ __global__ __launch_bounds__(256) void k_prolong_add(const cx<T> *__restrict__ e
     size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     size_t Nf = (size_t)mxf * myf * mzf;
     if (idx >= Nf) return;
-    int ix = (int)(idx % mxf);
-    size_t rest = idx / mxf;
-    int iy = (int)(rest % myf);
-    int iz = (int)(rest / myf);
+    int ix, iy, iz;
+    split3(idx, mxf, myf, ix, iy, iz);
     uf[idx] = uf[idx] + prolong_at<T, DIM>(ec, ix, iy, iz, mxc, myc, mzc);
 }
 
@@ -1433,10 +1429,8 @@ __global__ __launch_bounds__(256) void k_inject(const cx<T> *__restrict__ qf, cx
     size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     size_t Nc = (size_t)mxc * myc * mzc;
     if (idx >= Nc) return;
-    int I = (int)(idx % mxc);
-    size_t rest = idx / mxc;
-    int J = (int)(rest % myc);
-    int K = (int)(rest / myc);
+    int I, J, K;
+    split3(idx, mxc, myc, I, J, K);
     int z = (dim == 3) ? 2 * K + 1 : 0;
     qc[idx] = qf[((size_t)z * myf + (2 * J + 1)) * mxf + (2 * I + 1)];
 }
@@ -1475,10 +1469,8 @@ __global__ __launch_bounds__(256) void k_inject_rhs(const cd *__restrict__ bf, c
     size_t Nc = (size_t)mxc * myc * mzc;
     if (idx >= Nc) return;
     const double inv = 1.0 / fmg_scale(bnorm2, inv_sqN);
-    int I = (int)(idx % mxc);
-    size_t rest = idx / mxc;
-    int J = (int)(rest % myc);
-    int K = (int)(rest / myc);
+    int I, J, K;
+    split3(idx, mxc, myc, I, J, K);
     int z = (dim == 3) ? 2 * K + 1 : 0;
     const size_t j = ((size_t)z * myf + (2 * J + 1)) * mxf + (2 * I + 1);
     cd v = bf ? bf[j] : qf[j] * pw_uin(pwf, 2 * I + 1, 2 * J + 1, z, mxf, myf, dim);
@@ -1509,10 +1501,8 @@ __global__ __launch_bounds__(256) void k_prolong_set(const cx<TC> *__restrict__ 
     size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
     size_t Nf = (size_t)mxf * myf * mzf;
     if (idx >= Nf) return;
-    int ix = (int)(idx % mxf);
-    size_t rest = idx / mxf;
-    int iy = (int)(rest % myf);
-    int iz = (int)(rest / myf);
+    int ix, iy, iz;
+    split3(idx, mxf, myf, ix, iy, iz);
     cx<TC> v = prolong_at<TC, DIM>(ec, ix, iy, iz, mxc, myc, mzc);
     if (bnorm2) {
         const double sc = fmg_scale(bnorm2, inv_sqN);
