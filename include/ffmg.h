@@ -453,7 +453,8 @@ ffmg_status mg_profile_durations(ffmg_handle *h, int kernel, double *ms, int64_t
  * variants that compute the same result (bit for bit) with different tile
  * shapes; the best one depends on the device, the grid and the number of
  * directions.  FFMG_TUNE_FF_GEMM: the split-BF16 far-field GEMM (row tiles x
- * column tiles per wave); with ff_precision FP64 it has one variant.
+ * column tiles per wave, or a block tile staged in LDS and shared by its four
+ * waves); with ff_precision FP64 it has one variant.
  * FFMG_TUNE_TAIL: the largest coarse level (4096, 1024 or 256 interior
  * points for variants 0, 1, 2) run inside the one-workgroup LDS tail of the
  * fused 2D cycle; the levels above it run as grid-wide launches.  It has one

@@ -466,6 +466,138 @@ __global__ __launch_bounds__(256) void k_ff_gemm_bf16(const GemmGroupB *__restri
         }
 }
 
+// The same contraction with a block tile staged in LDS: BR row tiles x BC
+// column tiles per 256-thread block, the four waves arranged WR x WC, each
+// computing (BR / WR) x (BC / WC) tiles.  Per k-step the block copies its
+// A fragments ([plane][row tile][lane], 1 KB each) and the BC * 16 columns of
+// its four k-blocks of every S plane into one of two LDS buffers (the next
+// k-step's loads are in flight while the MFMAs run on the current one), so
+// each operand byte leaves L2 once per block instead of once per wave.  The
+// MFMA sequence of every (tile, k-step) and the FP64 accumulation order are
+// those of k_ff_gemm_bf16: the results are the same bits.  Rows are padded to
+// a multiple of BR (BF_RT_PAD) and columns to a multiple of BC * 16.
+template <int NS, int BR, int BC, int WR, int WC>
+__global__ __launch_bounds__(256) void k_ff_gemm_bf16_lds(const GemmGroupB *__restrict__ groups, int ksteps,
+                                                          long ldP, int gx, int gy)
+{
+    static_assert(WR * WC == 4 && BR % WR == 0 && BC % WC == 0, "four waves");
+    constexpr int RW = BR / WR, CW = BC / WC;
+    constexpr int A_EL = NS * BR * 64;        // 16-byte elements of A per k-step
+    constexpr int B_EL = NS * 4 * BC * 16;    // and of S
+    constexpr int NLD = (A_EL + B_EL + 255) / 256;
+    // two buffers of A_EL + B_EL elements (dynamic: above the 64 KB of static LDS)
+    extern __shared__ __attribute__((aligned(16))) unsigned char gemm_lds[];
+    bf8(*lds)[A_EL + B_EL] = reinterpret_cast<bf8(*)[A_EL + B_EL]>(gemm_lds);
+    const GemmGroupB G = groups[blockIdx.y];
+    const int t = xcd_tile(blockIdx.x, gx * gy);
+    const int bx = t / gy, by = t % gy;
+    const int rt0 = by * BR;
+    if (rt0 >= G.rtiles) return;
+    const long col0 = (long)bx * (BC * 16);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave / WC, wc = wave % WC;
+    const int lr = lane & 15, g = lane >> 4;
+
+    bf8 pre[NLD];
+    auto gload = [&](int ks) {
+#pragma unroll
+        for (int r = 0; r < NLD; ++r) {
+            const int e = threadIdx.x + 256 * r;
+            if (e < A_EL) {
+                const int sp = e / (BR * 64), rem = e - sp * (BR * 64), i = rem >> 6, l = rem & 63;
+                pre[r] = G.A[sp * G.a_split + ((long)(rt0 + i) * ksteps + ks) * 64 + l];
+            } else if (e < A_EL + B_EL) {
+                const int e2 = e - A_EL;
+                const int sp = e2 / (4 * BC * 16), rem = e2 - sp * (4 * BC * 16);
+                const int kb = rem / (BC * 16), c = rem - kb * (BC * 16);
+                pre[r] = G.S[sp * G.s_split + (long)(4 * ks + kb) * ldP + col0 + c];
+            }
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < NLD; ++r) {
+            const int e = threadIdx.x + 256 * r;
+            if (e < A_EL + B_EL) lds[buf][e] = pre[r];
+        }
+    };
+
+    double acc[RW][CW][4];
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[i][j][v] = 0.0;
+
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int ks = 0; ks < ksteps; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < ksteps) gload(ks + 1);
+        const bf8 *LA = lds[cur];
+        const bf8 *LB = lds[cur] + A_EL;
+        bf8 a[RW][NS], b[CW][NS];
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) a[i][sp] = LA[(sp * BR + wr * RW + i) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < CW; ++j)
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) b[j][sp] = LB[(sp * 4 + g) * (BC * 16) + (wc * CW + j) * 16 + lr];
+        f4 c[RW][CW];
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int j = 0; j < CW; ++j) c[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        // part products, smallest first: orders 2 (NS = 3), 1, then 0
+        if constexpr (NS == 3) {
+#pragma unroll
+            for (int i = 0; i < RW; ++i)
+#pragma unroll
+                for (int j = 0; j < CW; ++j) {
+                    c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][2], b[j][0], c[i][j], 0, 0, 0);
+                    c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][1], c[i][j], 0, 0, 0);
+                    c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][2], c[i][j], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int j = 0; j < CW; ++j) {
+                c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][1], b[j][0], c[i][j], 0, 0, 0);
+                c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][1], c[i][j], 0, 0, 0);
+                c[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i][0], b[j][0], c[i][j], 0, 0, 0);
+            }
+#pragma unroll
+        for (int i = 0; i < RW; ++i)
+#pragma unroll
+            for (int j = 0; j < CW; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[i][j][v] += (double)c[i][j][v];
+        if (ks + 1 < ksteps) sstore(cur ^ 1);
+        __syncthreads();
+    }
+    // epilogue as k_ff_gemm_bf16
+    const bool odd = (lane & 1) != 0;
+#pragma unroll
+    for (int i = 0; i < RW; ++i)
+#pragma unroll
+        for (int j = 0; j < CW; ++j) {
+            const double m0 = acc[i][j][0], m1 = acc[i][j][1], m2 = acc[i][j][2], m3 = acc[i][j][3];
+            double p0 = __shfl_xor(m0, 1, 64), p1 = __shfl_xor(m1, 1, 64);
+            double p2 = __shfl_xor(m2, 1, 64), p3 = __shfl_xor(m3, 1, 64);
+            int m = 8 * (rt0 + wr * RW + i) + 2 * g + (odd ? 1 : 0);
+            long n = (col0 + (wc * CW + j) * 16 + lr) >> 1;
+            cd v;
+            if (!odd) v = cd{m0 - p1, p0 + m1};
+            else v = cd{p2 - m3, m2 + p3};
+            if (m < G.M && n < G.Nc) G.C[(size_t)m * G.ldC + n] = v;
+        }
+}
+
 // F_m = pre * sum_x P[m][x] T[m][x]; one block per direction, the sums of
 // its four waves combined in a fixed order.
 __global__ __launch_bounds__(256) void k_ff_final(const cd *__restrict__ P, const cd *__restrict__ T, int M, int K,
@@ -525,17 +657,20 @@ static void launch_gemm(const GemmLaunch &L, hipStream_t s)
                        L.ldS, L.ldC);
 }
 
-// Split-GEMM tile variants (RT row tiles x CT column tiles per wave).  Row
-// tiles are padded to a multiple of BF_RT_PAD and columns to a multiple of
-// BF_COL_PAD, which every variant divides.
+// Split-GEMM tile variants: RT row tiles x CT column tiles per wave (four
+// waves side by side in n), or (lds) an LDS-staged block of RT x CT tiles.
+// Row tiles are padded to a multiple of BF_RT_PAD and columns to a multiple
+// of BF_COL_PAD, which every variant divides.
 struct BfVariant {
     int rt, ct;
+    bool lds;
 };
-static const BfVariant BF_VARIANTS[] = {{2, 1}, {2, 2}, {4, 1}, {4, 2}, {2, 4}, {4, 4}};
+static const BfVariant BF_VARIANTS[] = {{2, 1, false}, {2, 2, false}, {4, 1, false}, {4, 2, false}, {2, 4, false},
+                                        {4, 4, false}, {8, 4, true},  {4, 8, true},  {8, 8, true}};
 constexpr int BF_NVARIANTS = (int)(sizeof(BF_VARIANTS) / sizeof(BF_VARIANTS[0]));
 constexpr int BF_DEFAULT_VARIANT = 3;
-constexpr int BF_RT_PAD = 4;
-constexpr long BF_COL_PAD = 4 * 4 * 16;   // 4 waves x CT <= 4 tiles x 16 columns
+constexpr int BF_RT_PAD = 8;
+constexpr long BF_COL_PAD = 4 * 4 * 16;   // 4 waves x CT <= 4 tiles x 16 columns (LDS blocks: <= 8 x 16)
 
 struct GemmLaunchB {
     GemmGroupB *d_groups = nullptr;
@@ -543,10 +678,37 @@ struct GemmLaunchB {
     long ldP = 0;
 };
 
+// An LDS-staged variant: its two operand buffers (the attribute is raised
+// once per instantiation, by a thread-safe static initialisation).
+template <int NS, int BR, int BC>
+static void launch_gemm_lds(dim3 grid, const GemmLaunchB &L, hipStream_t s)
+{
+    constexpr size_t bytes = 2 * (size_t)(NS * BR * 64 + NS * 4 * BC * 16) * 16;
+    static const bool attr_set = [] {
+        (void)hipFuncSetAttribute((const void *)k_ff_gemm_bf16_lds<NS, BR, BC, 2, 2>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        return true;
+    }();
+    (void)attr_set;
+    hipLaunchKernelGGL((k_ff_gemm_bf16_lds<NS, BR, BC, 2, 2>), grid, dim3(256), bytes, s, L.d_groups, L.ksteps, L.ldP,
+                       (int)(grid.x / ceil_div(L.rtiles, BR)), ceil_div(L.rtiles, BR));
+}
+
 template <int NS>
 static void launch_gemm_bf16_ns(const GemmLaunchB &L, int variant, hipStream_t s)
 {
     const BfVariant V = BF_VARIANTS[variant];
+    if (V.lds) {
+        const int gx = (int)(L.ldP / (V.ct * 16L)), gy = ceil_div(L.rtiles, V.rt);
+        dim3 grid((unsigned)(gx * gy), (unsigned)L.ngroups);
+        if (V.rt == 8 && V.ct == 4)
+            launch_gemm_lds<NS, 8, 4>(grid, L, s);
+        else if (V.rt == 4 && V.ct == 8)
+            launch_gemm_lds<NS, 4, 8>(grid, L, s);
+        else
+            launch_gemm_lds<NS, 8, 8>(grid, L, s);
+        return;
+    }
     const int gx = (int)(L.ldP / (4L * V.ct * 16)), gy = ceil_div(L.rtiles, V.rt);
     dim3 grid((unsigned)(gx * gy), (unsigned)L.ngroups);
 #define FF_BF_CASE(R, C)                                                                                             \

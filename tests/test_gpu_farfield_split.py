@@ -169,3 +169,16 @@ def test_gemm_variants_agree_and_tuner_selects(ff, orc, tmp_path):
         ff.mg_tune_set(h2, nv)
     h64, _, _, _, _, _ = setup(ff, orc, w)
     assert ff.mg_tune_variants(h64) == 1
+    # 3D (both GEMM stages, one group per polar angle): the same bits with
+    # every variant, LDS-staged block tiles included
+    w3 = W.radial_3d(32, L=6.0, n_az=12, n_pol=5)
+    h3, _, g3, _, _, _ = setup(ff, orc, w3, ff_precision=2)
+    u3 = dev(crand(6, g3.shape) * 0.1)
+    ref3 = None
+    for v in range(ff.mg_tune_variants(h3)):
+        ff.mg_tune_set(h3, v)
+        F3 = ff.farfield_map(h3, w3.eta, u3, w3.dirs)
+        if ref3 is None:
+            ref3 = F3
+        np.testing.assert_array_equal(F3, ref3)
+    assert np.all(np.isfinite(ref3)) and np.abs(ref3).max() > 0
