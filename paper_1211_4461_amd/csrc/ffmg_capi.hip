@@ -816,8 +816,10 @@ template void vcycle<float>(ffmg_handle *, int, const cf *, cf *, bool, const in
 // With the LDS tail (2D fused kernels) the levels it covers (from level 1 at
 // the finest) run their whole part of the nested iteration in one launch.
 // T = float works on b / s, s = sqrt(*bnorm2 / N) (unit RMS).
+// defer_last: leave out the final interpolation into u (the caller fuses it
+// into the initial residual pass).
 template <typename T>
-void fmg_start(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2)
+void fmg_start(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2, bool defer_last = false)
 {
     using LP = LvlPtr<T>;
     const int last = (int)h->L.size() - 1;
@@ -848,15 +850,24 @@ void fmg_start(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2)
         launch_prolong_set<T, T>(lv.g, LP::u(h->L[l + 1]), LP::u(lv), nullptr, 1.0, h->stream);
         for (int c = 0; c < k; ++c) vcycle<T>(h, l, LP::b(lv), LP::u(lv), false, nullptr);
     }
-    launch_prolong_set<T, double>(l0.g, LP::u(h->L[1]), u, bnorm2, 1.0 / sqrt((double)l0.g.N()), h->stream);
+    if (!defer_last)
+        launch_prolong_set<T, double>(l0.g, LP::u(h->L[1]), u, bnorm2, 1.0 / sqrt((double)l0.g.N()), h->stream);
 }
 
 // The FMG start in the handle's precision; bnorm2: ||b||^2 on the device
 // (read by the FP32 form only).
-void fmg_enqueue(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2)
+void fmg_enqueue(ffmg_handle *h, const cd *b, cd *u, int k, const double *bnorm2, bool defer_last = false)
 {
-    if (h->opt.precision == FFMG_FP32_IR) fmg_start<float>(h, b, u, k, bnorm2);
+    if (h->opt.precision == FFMG_FP32_IR) fmg_start<float>(h, b, u, k, bnorm2, defer_last);
     else fmg_start<double>(h, b, u, k, nullptr);
+}
+
+// The FP32-in-FP64 3D solve with the fused kernels writes the start's last
+// interpolation in its initial residual pass.
+bool fmg_fused_resid(const ffmg_handle *h)
+{
+    return h->opt.fmg_cycles > 0 && h->opt.precision == FFMG_FP32_IR && h->opt.tile_config != TILE_REFERENCE &&
+           h->prob.dim == 3 && h->L.size() > 1;
 }
 
 // The fused FP32 2D refinement step writes the new iterate into the other of
@@ -1348,10 +1359,14 @@ ffmg_status mg_solve_begin(ffmg_handle *h, const void *bv, void *uv, double tol)
     // no copy at the end.
     p.flip = h->opt.fmg_cycles > 0 && fp32_pingpong(h) && (h->last_cycles % 2) == 1;
     cd *u0 = p.flip ? l0.t : u;
-    if (h->opt.fmg_cycles > 0) fmg_enqueue(h, b, u0, h->opt.fmg_cycles, h->d_scalar);
+    const bool fused_start = fmg_fused_resid(h);
+    if (h->opt.fmg_cycles > 0) fmg_enqueue(h, b, u0, h->opt.fmg_cycles, h->d_scalar, fused_start);
     // initial residual (cycle 0)
     if (h->opt.precision == FFMG_FP64)
         launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u0, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
+    else if (fused_start)
+        launch_fmg_resid3d(l0.g, l0.P64, h->L[1].u32, b, l0.q, u0, l0.b32, h->d_ctl, h->d_parts, h->d_scalar,
+                           h->pw_f, h->stream);
     else if (!b)
         launch_resid_pw(l0.g, l0.P64, u0, l0.q, l0.b32, h->d_ctl, h->d_parts, h->pw_f, h->stream);
     else

@@ -188,6 +188,13 @@ void launch_refine_update(const cf *d, cd *u, const SolveCtl *ctl, size_t N, hip
 void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cf *d, const cd *b,
                      const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
                      const int *stop, const cd *pwf = nullptr);
+// The FP32 full multigrid start's last interpolation fused with the initial
+// residual (3D): u = s P ec (s from bnorm2, as launch_prolong_set<float,
+// double>) and r32 = (b - A u) / ctl->scale_next with the block sums of
+// launch_resid_to_f32_ctl (b = null: the plane wave's q u_in from pwf).
+void launch_fmg_resid3d(const LevelGeom &g, const Stencil<double> &P, const cf *ec, const cd *b, const cd *q, cd *u,
+                        cf *r32, const SolveCtl *ctl, double *partial, const double *bnorm2, const cd *pwf,
+                        hipStream_t s);
 // r32 = (q u_in - A u) / ctl->scale_next with block sums of its FP64 square
 // (the blocks of launch_resid_to_f32_ctl)
 void launch_resid_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,

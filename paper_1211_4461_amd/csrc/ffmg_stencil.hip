@@ -270,7 +270,23 @@ __device__ __forceinline__ cx<T> prolong_at(const cx<T> *__restrict__ ec, int ix
 //             with the FP32 correction d (the residual of the updated
 //             iterate is formed in the same pass, and the updated iterate
 //             written to unew at the block's own points).
-enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2, SRC_UPD = 3 };
+enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2, SRC_UPD = 3, SRC_PSET = 4 };
+
+// SRC_PSET: u = s P e_c, the full multigrid start's interpolation of the FP32
+// first-level solution e_c scaled by s (the arithmetic of k_prolong_set<float,
+// double, 3>), formed in the pass and stored.
+struct PsetArgs {
+    const cf *ec = nullptr;
+    double sc = 1.0;
+};
+template <int SRC, typename T>
+struct CoarseType {
+    using type = T;
+};
+template <typename T>
+struct CoarseType<SRC_PSET, T> {
+    using type = float;
+};
 
 
 // Raw loads of one stencil value (the source form is applied when it is used).
@@ -288,17 +304,21 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                                                cx<TO> *__restrict__ out, const Stencil<T> &P, T rscale, int tiles_x,
                                                int tiles_y, int tz, double *__restrict__ partial,
                                                const cf *__restrict__ dcorr = nullptr, double dscale = 0.0,
-                                               cx<T> *__restrict__ unew = nullptr, const cd *__restrict__ pwf = nullptr)
+                                               cx<T> *__restrict__ unew = nullptr, const cd *__restrict__ pwf = nullptr,
+                                               PsetArgs pset = PsetArgs())
 {
     static_assert(!PW || (sizeof(T) == 8 && MODE != MODE_APPLY && SRC != SRC_ZERO2), "plane-wave b: FP64 residuals");
+    static_assert(SRC != SRC_PSET || sizeof(T) == 8, "the start's interpolation: FP64 residuals");
+    using TC = typename CoarseType<SRC, T>::type;   // number type of the staged coarse planes
+    constexpr bool STAGE = (SRC == SRC_PROL || SRC == SRC_PSET);
     constexpr int PY = TY3 / 4;
     constexpr int NH = 2 * TY3 + 2 * 66;   // halo values of a plane: the x sides, then the y rows
     // coarse tile of the fine tile plus its one-point halo: 34 x (TY3/2 + 2)
-    constexpr int CW = 34, CH = TY3 / 2 + 2, NCS = SRC == SRC_PROL ? 4 : 1;
+    constexpr int CW = 34, CH = TY3 / 2 + 2, NCS = STAGE ? 4 : 1;
     constexpr bool ZU = (MODE == MODE_JACOBI0);   // the stencil's u is zero: no u is read
     constexpr bool NEED_B = (MODE != MODE_APPLY);
     __shared__ cx<T> s[2][TY3 + 2][66];
-    __shared__ cx<T> cs[NCS][SRC == SRC_PROL ? CH : 1][SRC == SRC_PROL ? CW : 1];
+    __shared__ cx<TC> cs[NCS][STAGE ? CH : 1][STAGE ? CW : 1];
     const int mx = P.mx, my = P.my, mz = P.mz;
     const int mxc = (mx - 1) / 2, myc = (my - 1) / 2, mzc = (mz - 1) / 2;
     int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -320,20 +340,22 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
             const int yy = t / CW, xx = t - yy * CW;
             const int ax = cx0 + xx, ay = cy0 + yy;
             const bool in = a >= 0 && a < mzc && ax >= 0 && ax < mxc && ay >= 0 && ay < myc;
-            cs[a & (NCS - 1)][yy][xx] = ld_masked(ec, ((size_t)a * myc + ay) * mxc + ax, in);
+            const size_t ci = ((size_t)a * myc + ay) * mxc + ax;
+            if constexpr (SRC == SRC_PSET) cs[a & (NCS - 1)][yy][xx] = ld_masked(pset.ec, ci, in);
+            else cs[a & (NCS - 1)][yy][xx] = ld_masked(ec, ci, in);
         }
     };
     // (P e_c) at fine point (x, y, z) from the staged coarse planes (the
     // order of prolong_at<T, 3>)
-    auto interp = [&](int x, int y, int z) -> cx<T> {
+    auto interp = [&](int x, int y, int z) -> cx<TC> {
         const int fx = x + 1, fy = y + 1, fz = z + 1;
         const int ex = (fx >> 1) - 1 - cx0, ey = (fy >> 1) - 1 - cy0, az = (fz >> 1) - 1;
-        T wx[2], wy[2], wz[2];
+        TC wx[2], wy[2], wz[2];
         lin_w(fx, wx);
         lin_w(fy, wy);
         lin_w(fz, wz);
         const int s0 = az & (NCS - 1), s1 = (az + 1) & (NCS - 1);
-        cx<T> acc = {T(0), T(0)};
+        cx<TC> acc = {TC(0), TC(0)};
 #pragma unroll
         for (int jy = 0; jy < 2; ++jy)
 #pragma unroll
@@ -380,6 +402,8 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
         if constexpr (SRC == SRC_ZERO2) {
             r.a = ld_buf<T>(buf_rsrc(b + o, nb), off);
             r.c = ld_buf<T>(buf_rsrc(q + o, nb), off);
+        } else if constexpr (SRC == SRC_PSET) {
+            r.a = zero;   // u is formed from the staged coarse planes
         } else {
             r.a = ld_buf<T>(buf_rsrc(u + o, nb), off);
             if constexpr (SRC == SRC_UPD) {
@@ -396,6 +420,10 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
             return in ? jacobi0_w(r.a, jweight(P, r.c)) : zero;
         } else if constexpr (SRC == SRC_PROL) {
             return in ? r.a + interp(x, y, z) : r.a;
+        } else if constexpr (SRC == SRC_PSET) {
+            if (!in) return zero;
+            const cx<TC> v = interp(x, y, z);
+            return cx<T>{(T)v.re * pset.sc, (T)v.im * pset.sc};
         } else if constexpr (SRC == SRC_UPD) {
             return in ? cx<T>{r.a.re + dscale * r.c.re, r.a.im + dscale * r.c.im} : r.a;
         } else {
@@ -406,7 +434,7 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
 
     // coarse planes a = ((iz + 1) >> 1) - 1 .. (iz + 1) >> 1 serve fine plane iz
     int a_hi = 0;
-    if (SRC == SRC_PROL) {
+    if (STAGE) {
         for (int a = (z0 >> 1) - 1; a <= ((z0 + 1) >> 1); ++a) load_coarse(a);
         a_hi = (z0 + 1) >> 1;
         __syncthreads();
@@ -462,7 +490,7 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
     int it = 0;
     for (int z = z0; z < z1; ++z, ++it) {
         const int buf = it & 1;
-        if (SRC == SRC_PROL && ((z + 2) >> 1) > a_hi) {
+        if (STAGE && ((z + 2) >> 1) > a_hi) {
             // the slot it takes held plane a_hi - 3, which no fine plane >= z
             // reads; every thread has passed the barrier after its last use
             load_coarse(++a_hi);
@@ -510,7 +538,7 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                     }
                 }
                 point_update_v<T, TO, MODE>(P, rscale, uc, lap, j, bc[i], qc[i], out, acc);
-                if constexpr (SRC == SRC_UPD) unew[j] = uc;
+                if constexpr (SRC == SRC_UPD || SRC == SRC_PSET) unew[j] = uc;
             }
         }
         if (!ZU) {
@@ -1532,6 +1560,42 @@ template void launch_prolong_set<float, float>(const LevelGeom &, const cf *, cf
                                                hipStream_t);
 template void launch_prolong_set<float, double>(const LevelGeom &, const cf *, cd *, const double *, double,
                                                 hipStream_t);
+
+// The last step of the FP32 full multigrid start fused with the initial
+// residual of the refinement (3D): u = s P e_c written, and
+// r32 = (b - A u) / ctl->scale_next with the block sums of |b - A u|^2, the
+// bits of k_prolong_set<float, double, 3> followed by the FP64 residual pass.
+template <bool PW>
+__global__ __launch_bounds__(256) void k_fmg_resid3d(const cf *__restrict__ ec, const cd *__restrict__ b,
+                                                     const cd *__restrict__ q, cd *__restrict__ u,
+                                                     cf *__restrict__ r32, Stencil<double> P, int tiles_x,
+                                                     int tiles_y, int tz, double *__restrict__ partial,
+                                                     const SolveCtl *__restrict__ ctl,
+                                                     const double *__restrict__ bnorm2, double inv_sqN,
+                                                     const cd *__restrict__ pwf)
+{
+    const double rscale = 1.0 / ctl->scale_next;
+    PsetArgs ps;
+    ps.ec = ec;
+    ps.sc = fmg_scale(bnorm2, inv_sqN);
+    stencil3d_body<double, float, MODE_RESID, SRC_PSET, PW>(nullptr, nullptr, b, q, r32, P, rscale, tiles_x, tiles_y,
+                                                            tz, partial, nullptr, 0.0, u, pwf, ps);
+}
+
+void launch_fmg_resid3d(const LevelGeom &g, const Stencil<double> &P, const cf *ec, const cd *b, const cd *q, cd *u,
+                        cf *r32, const SolveCtl *ctl, double *partial, const double *bnorm2, const cd *pwf,
+                        hipStream_t s)
+{
+    int nb, tx, ty, tz;
+    grid_of(g, nb, tx, ty, tz);
+    const double inv_sqN = 1.0 / sqrt((double)g.N());
+    if (b)
+        hipLaunchKernelGGL(k_fmg_resid3d<false>, dim3(nb), dim3(256), 0, s, ec, b, q, u, r32, P, tx, ty, tz, partial,
+                           ctl, bnorm2, inv_sqN, nullptr);
+    else
+        hipLaunchKernelGGL(k_fmg_resid3d<true>, dim3(nb), dim3(256), 0, s, ec, nullptr, q, u, r32, P, tx, ty, tz,
+                           partial, ctl, bnorm2, inv_sqN, pwf);
+}
 
 template <typename To, typename Ti>
 __global__ __launch_bounds__(256) void k_convert(const cx<Ti> *__restrict__ in, cx<To> *__restrict__ out, size_t N)
