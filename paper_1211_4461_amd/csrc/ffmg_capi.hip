@@ -625,7 +625,9 @@ ffmg_status setup_impl(ffmg_handle *h)
 // Enqueue one cycle of the solve loop (V-cycle, residual / refinement step,
 // control update).  ucur/ualt: FP64 iterate ping-pong of the fused
 // refinement step (swapped by the caller).
-void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *stop)
+// start_ec: the 3D start s P e_c was not stored; this (first) step forms it
+// from e_c in its refinement pass.
+void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *stop, const cf *start_ec = nullptr)
 {
     Level &l0 = h->L[0];
     if (h->opt.precision == FFMG_FP64) {
@@ -644,10 +646,15 @@ void enqueue_step(ffmg_handle *h, const cd *b, cd *ucur, cd *ualt, const int *st
         prof_kernel_end(h, PROF_REFINE, pi);
         launch_ctl_update(h->d_ctl, h->d_parts, fused2d_blocks(l0.g), h->stream);
     } else if (l0.g.dim == 3 && h->opt.tile_config != TILE_REFERENCE) {
-        int pi = prof_begin(h, PROF_REFINE);
-        launch_refine3d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop,
-                        h->pw_f);
-        prof_end(h, PROF_REFINE, pi);
+        if (start_ec) {   // (not bracketed: PROF_REFINE times the 64-byte-per-point pass)
+            launch_refine3d_start(l0.g, l0.P64, start_ec, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts,
+                                  h->stream, stop, h->pw_f, h->d_scalar);
+        } else {
+            int pi = prof_begin(h, PROF_REFINE);
+            launch_refine3d(l0.g, l0.P64, ucur, l0.u32, b, l0.q, ualt, l0.b32, h->d_ctl, h->d_parts, h->stream, stop,
+                            h->pw_f);
+            prof_end(h, PROF_REFINE, pi);
+        }
         launch_ctl_update(h->d_ctl, h->d_parts, stencil_blocks(l0.g), h->stream);
     } else {
         launch_refine_update(l0.u32, ucur, h->d_ctl, l0.g.N(), h->stream, stop);
@@ -885,7 +892,8 @@ ffmg_status enqueue_batch(ffmg_handle *h, int nb)
     PendingSolve &p = h->pend;
     const int *stop = &h->d_ctl->done;
     for (int i = 0; i < nb; ++i) {
-        enqueue_step(h, p.b, p.ua, p.ub, stop);
+        enqueue_step(h, p.b, p.ua, p.ub, stop, p.start_ec);
+        p.start_ec = nullptr;
         if (fp32_pingpong(h)) std::swap(p.ua, p.ub);
     }
     p.queued += nb;
@@ -1364,9 +1372,16 @@ ffmg_status mg_solve_begin(ffmg_handle *h, const void *bv, void *uv, double tol)
     // initial residual (cycle 0)
     if (h->opt.precision == FFMG_FP64)
         launch_stencil<double>(MODE_RNORM, l0.g, l0.P64, u0, b, l0.q, (cd *)nullptr, h->d_parts, h->stream);
-    else if (fused_start)
-        launch_fmg_resid3d(l0.g, l0.P64, h->L[1].u32, b, l0.q, u0, l0.b32, h->d_ctl, h->d_parts, h->d_scalar,
+    else if (fused_start) {
+        // the start's first-level solution is kept (the first step's V-cycles
+        // reuse the level's buffers); u0 is formed again by that step's
+        // refinement pass, so it is stored only if no step completes
+        const size_t n1 = h->L[1].g.N();
+        if (!h->fmg_e1) TRY(dalloc(h, &h->fmg_e1, n1 * sizeof(cf)));
+        HIPCHK(h, hipMemcpyAsync(h->fmg_e1, h->L[1].u32, n1 * sizeof(cf), hipMemcpyDeviceToDevice, h->stream));
+        launch_fmg_resid3d(l0.g, l0.P64, h->fmg_e1, b, l0.q, nullptr, l0.b32, h->d_ctl, h->d_parts, h->d_scalar,
                            h->pw_f, h->stream);
+    }
     else if (!b)
         launch_resid_pw(l0.g, l0.P64, u0, l0.q, l0.b32, h->d_ctl, h->d_parts, h->pw_f, h->stream);
     else
@@ -1378,6 +1393,8 @@ ffmg_status mg_solve_begin(ffmg_handle *h, const void *bv, void *uv, double tol)
     p.ua = u0;
     p.ub = p.flip ? u : l0.t;
     p.queued = 0;
+    p.start_ec = fused_start ? h->fmg_e1 : nullptr;
+    p.start_unstored = fused_start;
     // the first batch: as many steps as the previous solve took (4 at first)
     const int batch = std::min(h->last_cycles > 0 ? h->last_cycles : 4, h->opt.max_cycles);
     TRY(enqueue_batch(h, batch));
@@ -1421,6 +1438,11 @@ ffmg_status mg_solve_end(ffmg_handle *h, ffmg_solve_info *info)
         HIPCHK(h, hipStreamSynchronize(h->stream));
         c = *h->h_ctl;
     }
+    // a start formed only inside the refinement passes, with no step
+    // completed: store it in the start buffer
+    if (p.start_unstored && c.k <= 0)
+        launch_prolong_set<float, double>(l0.g, h->fmg_e1, p.flip ? l0.t : p.u, h->d_scalar,
+                                          1.0 / sqrt((double)l0.g.N()), h->stream);
     // the fused refinement step alternates the iterate between the start
     // buffer and the other one: after an odd number of completed steps it is
     // in the other

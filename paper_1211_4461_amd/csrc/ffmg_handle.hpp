@@ -47,6 +47,8 @@ struct PendingSolve {
     cd *ua = nullptr, *ub = nullptr; // current iterate / the other buffer of the FP32 2D step
     int queued = 0;                  // steps queued so far
     bool flip = false;               // the start was written into l0.t instead of u
+    const ffmg::cf *start_ec = nullptr; // the 3D start s P e_c not stored: its first step forms it from e_c
+    bool start_unstored = false;     // that start is stored at the end if no step completed
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 }  // namespace ffmg
@@ -93,6 +95,7 @@ struct ffmg_handle {
     ffmg::cd *pw_f = nullptr;
     bool pw_set = false;
     ffmg::cd *pw_b = nullptr;
+    ffmg::cf *fmg_e1 = nullptr;      // the FP32 start's first-level solution, kept for the first 3D step
     ffmg::cd *d_F = nullptr;         // far-field staging
     int d_F_cap = 0;
     // ionisation observables: workspace slots grown on demand, freed at destroy

@@ -190,11 +190,18 @@ void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, 
                      const int *stop, const cd *pwf = nullptr);
 // The FP32 full multigrid start's last interpolation fused with the initial
 // residual (3D): u = s P ec (s from bnorm2, as launch_prolong_set<float,
-// double>) and r32 = (b - A u) / ctl->scale_next with the block sums of
-// launch_resid_to_f32_ctl (b = null: the plane wave's q u_in from pwf).
+// double>; u = null: not stored) and r32 = (b - A u) / ctl->scale_next with
+// the block sums of launch_resid_to_f32_ctl (b = null: the plane wave's q u_in
+// from pwf).
 void launch_fmg_resid3d(const LevelGeom &g, const Stencil<double> &P, const cf *ec, const cd *b, const cd *q, cd *u,
                         cf *r32, const SolveCtl *ctl, double *partial, const double *bnorm2, const cd *pwf,
                         hipStream_t s);
+// The first refinement step after that fused start (3D): the iterate
+// s P ec formed from the staged FP32 coarse planes instead of read, then as
+// launch_refine3d (unew = s P ec + scale d, its scaled residual and sums).
+void launch_refine3d_start(const LevelGeom &g, const Stencil<double> &P, const cf *ec, const cf *d, const cd *b,
+                           const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
+                           const int *stop, const cd *pwf, const double *bnorm2);
 // r32 = (q u_in - A u) / ctl->scale_next with block sums of its FP64 square
 // (the blocks of launch_resid_to_f32_ctl)
 void launch_resid_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,

@@ -270,14 +270,27 @@ __device__ __forceinline__ cx<T> prolong_at(const cx<T> *__restrict__ ec, int ix
 //             with the FP32 correction d (the residual of the updated
 //             iterate is formed in the same pass, and the updated iterate
 //             written to unew at the block's own points).
-enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2, SRC_UPD = 3, SRC_PSET = 4 };
+enum { SRC_MEM = 0, SRC_ZERO2 = 1, SRC_PROL = 2, SRC_UPD = 3, SRC_PSET = 4, SRC_PSETUPD = 5 };
 
 // SRC_PSET: u = s P e_c, the full multigrid start's interpolation of the FP32
 // first-level solution e_c scaled by s (the arithmetic of k_prolong_set<float,
-// double, 3>), formed in the pass and stored.
+// double, 3>), formed in the pass and stored.  SRC_PSETUPD: the first
+// refinement step's update of that start, s P e_c + scale d (SRC_UPD with the
+// iterate formed instead of read).
+// Full multigrid transfers.  The scale s = sqrt(bnorm2) / sqrt(N) (the RMS
+// of the finest right-hand side; 1 without bnorm2) keeps an FP32 hierarchy
+// at unit size: the start is computed for b / s and multiplied back by s.
+__device__ __forceinline__ double fmg_scale(const double *bnorm2, double inv_sqN)
+{
+    if (!bnorm2) return 1.0;
+    double s = sqrt(bnorm2[0]) * inv_sqN;
+    return (s > 0.0 && isfinite(s)) ? s : 1.0;
+}
+
 struct PsetArgs {
     const cf *ec = nullptr;
-    double sc = 1.0;
+    const double *bnorm2 = nullptr;   // the scale s = fmg_scale(bnorm2, inv_sqN)
+    double inv_sqN = 1.0;
 };
 template <int SRC, typename T>
 struct CoarseType {
@@ -285,6 +298,10 @@ struct CoarseType {
 };
 template <typename T>
 struct CoarseType<SRC_PSET, T> {
+    using type = float;
+};
+template <typename T>
+struct CoarseType<SRC_PSETUPD, T> {
     using type = float;
 };
 
@@ -308,9 +325,11 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                                                PsetArgs pset = PsetArgs())
 {
     static_assert(!PW || (sizeof(T) == 8 && MODE != MODE_APPLY && SRC != SRC_ZERO2), "plane-wave b: FP64 residuals");
-    static_assert(SRC != SRC_PSET || sizeof(T) == 8, "the start's interpolation: FP64 residuals");
+    static_assert((SRC != SRC_PSET && SRC != SRC_PSETUPD) || sizeof(T) == 8, "the start's interpolation: FP64");
     using TC = typename CoarseType<SRC, T>::type;   // number type of the staged coarse planes
-    constexpr bool STAGE = (SRC == SRC_PROL || SRC == SRC_PSET);
+    const double psc = (SRC == SRC_PSET || SRC == SRC_PSETUPD) ? fmg_scale(pset.bnorm2, pset.inv_sqN) : 1.0;
+    constexpr bool STAGE = (SRC == SRC_PROL || SRC == SRC_PSET || SRC == SRC_PSETUPD);
+    constexpr bool PSET = (SRC == SRC_PSET || SRC == SRC_PSETUPD);
     constexpr int PY = TY3 / 4;
     constexpr int NH = 2 * TY3 + 2 * 66;   // halo values of a plane: the x sides, then the y rows
     // coarse tile of the fine tile plus its one-point halo: 34 x (TY3/2 + 2)
@@ -341,7 +360,7 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
             const int ax = cx0 + xx, ay = cy0 + yy;
             const bool in = a >= 0 && a < mzc && ax >= 0 && ax < mxc && ay >= 0 && ay < myc;
             const size_t ci = ((size_t)a * myc + ay) * mxc + ax;
-            if constexpr (SRC == SRC_PSET) cs[a & (NCS - 1)][yy][xx] = ld_masked(pset.ec, ci, in);
+            if constexpr (PSET) cs[a & (NCS - 1)][yy][xx] = ld_masked(pset.ec, ci, in);
             else cs[a & (NCS - 1)][yy][xx] = ld_masked(ec, ci, in);
         }
     };
@@ -404,6 +423,11 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
             r.c = ld_buf<T>(buf_rsrc(q + o, nb), off);
         } else if constexpr (SRC == SRC_PSET) {
             r.a = zero;   // u is formed from the staged coarse planes
+        } else if constexpr (SRC == SRC_PSETUPD) {
+            r.a = zero;   // u is formed from the staged coarse planes, d is read
+            const unsigned offd = (off == BUF_OOB) ? BUF_OOB : off / 2u;
+            const cf dj = ld_buf<float>(buf_rsrc(dcorr + o, nb / 2u), offd);
+            r.c = cx<T>{(T)dj.re, (T)dj.im};
         } else {
             r.a = ld_buf<T>(buf_rsrc(u + o, nb), off);
             if constexpr (SRC == SRC_UPD) {
@@ -423,7 +447,12 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
         } else if constexpr (SRC == SRC_PSET) {
             if (!in) return zero;
             const cx<TC> v = interp(x, y, z);
-            return cx<T>{(T)v.re * pset.sc, (T)v.im * pset.sc};
+            return cx<T>{(T)v.re * psc, (T)v.im * psc};
+        } else if constexpr (SRC == SRC_PSETUPD) {
+            if (!in) return zero;
+            const cx<TC> v = interp(x, y, z);
+            const cx<T> uo = {(T)v.re * psc, (T)v.im * psc};
+            return cx<T>{uo.re + dscale * r.c.re, uo.im + dscale * r.c.im};
         } else if constexpr (SRC == SRC_UPD) {
             return in ? cx<T>{r.a.re + dscale * r.c.re, r.a.im + dscale * r.c.im} : r.a;
         } else {
@@ -538,7 +567,9 @@ __device__ __forceinline__ void stencil3d_body(const cx<T> *__restrict__ u, cons
                     }
                 }
                 point_update_v<T, TO, MODE>(P, rscale, uc, lap, j, bc[i], qc[i], out, acc);
-                if constexpr (SRC == SRC_UPD || SRC == SRC_PSET) unew[j] = uc;
+                if constexpr (SRC == SRC_UPD || SRC == SRC_PSETUPD) unew[j] = uc;
+                if constexpr (SRC == SRC_PSET)
+                    if (unew) unew[j] = uc;
             }
         }
         if (!ZU) {
@@ -855,18 +886,20 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
 // (s = ctl->scale_cur) into unew, and the residual b - A u' written as FP32
 // scaled by 1 / ctl->scale_next, with the per-block FP64 sums of |b - A u'|^2.
 // The same arithmetic as k_refine_update followed by the FP64 residual.
-template <bool PW>
+// START: the iterate is the full multigrid start s P e_c (PsetArgs), formed
+// from the staged FP32 coarse planes instead of read.
+template <bool PW, bool START = false>
 __global__ __launch_bounds__(256) void k_refine3d(const cd *__restrict__ u, const cf *__restrict__ d,
                                                   const cd *__restrict__ b, const cd *__restrict__ q,
                                                   cd *__restrict__ unew, cf *__restrict__ r32, Stencil<double> P,
                                                   int tiles_x, int tiles_y, int tz, double *__restrict__ partial,
                                                   const SolveCtl *__restrict__ ctl, const int *__restrict__ stop,
-                                                  const cd *__restrict__ pwf)
+                                                  const cd *__restrict__ pwf, PsetArgs ps)
 {
     if (stop && *stop) return;
     const double rscale = 1.0 / ctl->scale_next;
-    stencil3d_body<double, float, MODE_RESID, SRC_UPD, PW>(u, nullptr, b, q, r32, P, rscale, tiles_x, tiles_y, tz,
-                                                           partial, d, ctl->scale_cur, unew, pwf);
+    stencil3d_body<double, float, MODE_RESID, START ? SRC_PSETUPD : SRC_UPD, PW>(
+        u, nullptr, b, q, r32, P, rscale, tiles_x, tiles_y, tz, partial, d, ctl->scale_cur, unew, pwf, ps);
 }
 
 // The FP64 residual of the plane-wave right-hand side written as scaled FP32
@@ -1037,11 +1070,11 @@ void launch_refine3d(const LevelGeom &g, const Stencil<double> &P, const cd *u, 
     int nb, tx, ty, tz;
     grid_of(g, nb, tx, ty, tz);
     if (b)
-        hipLaunchKernelGGL(k_refine3d<false>, dim3(nb), dim3(256), 0, s, u, d, b, q, unew, r32, P, tx, ty, tz,
-                           partial, ctl, stop, nullptr);
+        hipLaunchKernelGGL((k_refine3d<false>), dim3(nb), dim3(256), 0, s, u, d, b, q, unew, r32, P, tx, ty, tz,
+                           partial, ctl, stop, nullptr, PsetArgs());
     else
-        hipLaunchKernelGGL(k_refine3d<true>, dim3(nb), dim3(256), 0, s, u, d, nullptr, q, unew, r32, P, tx, ty, tz,
-                           partial, ctl, stop, pwf);
+        hipLaunchKernelGGL((k_refine3d<true>), dim3(nb), dim3(256), 0, s, u, d, nullptr, q, unew, r32, P, tx, ty, tz,
+                           partial, ctl, stop, pwf, PsetArgs());
 }
 
 __global__ __launch_bounds__(256) void k_resid2d_pw(const cd *__restrict__ u, const cd *__restrict__ q,
@@ -1052,6 +1085,24 @@ __global__ __launch_bounds__(256) void k_resid2d_pw(const cd *__restrict__ u, co
     const double rscale = 1.0 / ctl->scale_next;
     stencil2d_body<double, float, MODE_RESID, true>(u, nullptr, q, r32, P, rscale, tiles_x,
                                                     xcd_tile(blockIdx.x, gridDim.x), partial + blockIdx.x, pwf);
+}
+
+void launch_refine3d_start(const LevelGeom &g, const Stencil<double> &P, const cf *ec, const cf *d, const cd *b,
+                           const cd *q, cd *unew, cf *r32, const SolveCtl *ctl, double *partial, hipStream_t s,
+                           const int *stop, const cd *pwf, const double *bnorm2)
+{
+    int nb, tx, ty, tz;
+    grid_of(g, nb, tx, ty, tz);
+    PsetArgs ps;
+    ps.ec = ec;
+    ps.bnorm2 = bnorm2;
+    ps.inv_sqN = 1.0 / sqrt((double)g.N());
+    if (b)
+        hipLaunchKernelGGL((k_refine3d<false, true>), dim3(nb), dim3(256), 0, s, nullptr, d, b, q, unew, r32, P, tx,
+                           ty, tz, partial, ctl, stop, nullptr, ps);
+    else
+        hipLaunchKernelGGL((k_refine3d<true, true>), dim3(nb), dim3(256), 0, s, nullptr, d, nullptr, q, unew, r32, P,
+                           tx, ty, tz, partial, ctl, stop, pwf, ps);
 }
 
 void launch_resid_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,
@@ -1474,15 +1525,6 @@ void launch_inject(const LevelGeom &f, const cx<T> *qf, cx<T> *qc, hipStream_t s
 template void launch_inject<double>(const LevelGeom &, const cd *, cd *, hipStream_t);
 template void launch_inject<float>(const LevelGeom &, const cf *, cf *, hipStream_t);
 
-// Full multigrid transfers.  The scale s = sqrt(bnorm2) / sqrt(N) (the RMS
-// of the finest right-hand side; 1 without bnorm2) keeps an FP32 hierarchy
-// at unit size: the start is computed for b / s and multiplied back by s.
-__device__ __forceinline__ double fmg_scale(const double *bnorm2, double inv_sqN)
-{
-    if (!bnorm2) return 1.0;
-    double s = sqrt(bnorm2[0]) * inv_sqN;
-    return (s > 0.0 && isfinite(s)) ? s : 1.0;
-}
 
 // b_1 = b_0 / s at the coarse nodes (injection of the finest right-hand side).
 // (bf = null: b is the plane-wave right-hand side q u_in, formed from q and
@@ -1562,9 +1604,10 @@ template void launch_prolong_set<float, double>(const LevelGeom &, const cf *, c
                                                 hipStream_t);
 
 // The last step of the FP32 full multigrid start fused with the initial
-// residual of the refinement (3D): u = s P e_c written, and
-// r32 = (b - A u) / ctl->scale_next with the block sums of |b - A u|^2, the
-// bits of k_prolong_set<float, double, 3> followed by the FP64 residual pass.
+// residual of the refinement (3D): u = s P e_c written (u = null: not
+// stored), and r32 = (b - A u) / ctl->scale_next with the block sums of
+// |b - A u|^2, the bits of k_prolong_set<float, double, 3> followed by the
+// FP64 residual pass.
 template <bool PW>
 __global__ __launch_bounds__(256) void k_fmg_resid3d(const cf *__restrict__ ec, const cd *__restrict__ b,
                                                      const cd *__restrict__ q, cd *__restrict__ u,
@@ -1577,7 +1620,8 @@ __global__ __launch_bounds__(256) void k_fmg_resid3d(const cf *__restrict__ ec, 
     const double rscale = 1.0 / ctl->scale_next;
     PsetArgs ps;
     ps.ec = ec;
-    ps.sc = fmg_scale(bnorm2, inv_sqN);
+    ps.bnorm2 = bnorm2;
+    ps.inv_sqN = inv_sqN;
     stencil3d_body<double, float, MODE_RESID, SRC_PSET, PW>(nullptr, nullptr, b, q, r32, P, rscale, tiles_x, tiles_y,
                                                             tz, partial, nullptr, 0.0, u, pwf, ps);
 }

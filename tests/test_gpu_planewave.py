@@ -83,3 +83,28 @@ def test_plane_wave_solve_needs_a_plane_wave(ff):
     assert e.value.status == ff.FFMG_EINVAL
     assert ff.mg_solve_end(h).status == 0
     h.destroy()
+
+
+def test_start_met_at_once_is_stored(ff):
+    """The 3D FP32-in-FP64 solve forms its full multigrid start inside the
+    first refinement pass instead of storing it; when the start already meets
+    the tolerance no step runs and the start is stored at the end: u equals
+    mg_fmg's start bit for bit, after an even and an odd previous step count
+    (the start buffer alternates between u and the handle's other buffer)."""
+    w = W.gauss_3d(n=64, n_az=4, n_pol=2)
+    h = ff.setup_workload(w, options=ff.default_options(precision=1, fmg_cycles=2))[0]
+    b = ff.mg_rhs_plane_wave(h, w.eta, torch.empty(w.shape, dtype=torch.complex128, device="cuda"))
+    u0 = torch.empty_like(b)
+    ff.mg_fmg(h, b, u0, 2)
+    bn = float(torch.linalg.vector_norm(b).item())
+    rel0 = ff.mg_residual_norm(h, b, u0) / bn
+    assert 0 < rel0 < 0.99, rel0
+    for prev_tol in (1e-3, 1e-6, 1e-9):   # previous solves with different step counts
+        u = torch.zeros_like(b)
+        ff.mg_solve(h, b, u, tol=prev_tol)
+        u = torch.full_like(b, 3.0)
+        info = ff.mg_solve(h, b, u, tol=min(0.999, 1.01 * rel0))
+        torch.cuda.synchronize()
+        assert info.status == 0 and info.cycles == 0, (prev_tol, info.cycles)
+        assert torch.equal(u, u0), prev_tol
+    h.destroy()
