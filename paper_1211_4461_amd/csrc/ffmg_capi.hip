@@ -136,6 +136,9 @@ __global__ __launch_bounds__(256) void k_norm2_pw(const cd *__restrict__ q, cons
     double acc = 0.0;
     const size_t j0 = (size_t)blockIdx.x * 256 + threadIdx.x, S = (size_t)gridDim.x * 256;
     GridWalk w(j0, S, mx, my);
+    // unrolled so that the loads of later points are issued early; the sum
+    // stays in the order of k_norm2
+#pragma unroll 4
     for (size_t j = j0; j < N; j += S, w.step()) acc += abs2(q[j] * pw_uin(f, w.x, w.y, w.z, mx, my, dim));
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
