@@ -788,10 +788,41 @@ ffmg_status farfield_map_batched(ffmg_handle *const *hs, int count, const double
         }
         Fd = h0->d_F;
     }
+    // 2D split-BF16 maps: every instance's stages in shared launches on
+    // hs[0]'s stream, once each operator's plan is prepared for the directions
+    bool batched = true;
+    for (int i = 0; i < count && batched; ++i) {
+        ffmg_handle *h = hs[i];
+        if (!h) return fail(h0, FFMG_EINVAL, "hs[%d] is null", i);
+        batched = h->prob.dim == 2 && h->opt.ff_precision == h0->opt.ff_precision &&
+                  h->opt.ff_precision != FFMG_FF_FP64 && !h->pend.active;
+    }
+    if (batched) {
+        std::vector<FFBInst> in(count);
+        std::vector<uint64_t> key;
+        std::vector<ffmg_handle *> seen;
+        for (int i = 0; i < count; ++i) {
+            ffmg_handle *h = hs[i];
+            if (std::find(seen.begin(), seen.end(), h) == seen.end()) {
+                TRY(farfield_prepare(h, etas + 3 * i, n_dirs, dirs));
+                seen.push_back(h);
+            }
+            const LevelGeom &g = h->L[0].g;
+            in[i] = FFBInst{h->ff, &g, h->L[0].q, u ? (const cd *)u[i] : nullptr, Fd + (size_t)i * n_dirs,
+                            {etas[3 * i], etas[3 * i + 1], 0.0}, h->k0, h->prob.gamma};
+            key.push_back(h->serial);
+        }
+        key.push_back((uint64_t)n_dirs);
+        for (ffmg_handle *h : seen)
+            if (h->stream != h0->stream) HIPCHK(h0, hipStreamSynchronize(h->stream));
+        HIPCHK(h0, ff_batch_run(&h0->ffbatch, key, in, n_dirs, h0->stream));
+        if (!on_device) HIPCHK(h0, hipMemcpyAsync(F, Fd, tot * sizeof(cd), hipMemcpyDeviceToHost, h0->stream));
+        HIPCHK(h0, hipStreamSynchronize(h0->stream));
+        return FFMG_OK;
+    }
     std::vector<hipStream_t> streams;
     for (int i = 0; i < count; ++i) {
         ffmg_handle *h = hs[i];
-        if (!h) return fail(h0, FFMG_EINVAL, "hs[%d] is null", i);
         TRY(farfield_enqueue(h, etas + 3 * i, u ? u[i] : nullptr, n_dirs, dirs, Fd + (size_t)i * n_dirs));
         if (std::find(streams.begin(), streams.end(), h->stream) == streams.end()) streams.push_back(h->stream);
         if (h != h0 && h->err.size()) h0->err = h->err;

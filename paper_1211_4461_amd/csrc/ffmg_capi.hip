@@ -1050,6 +1050,7 @@ void mg_destroy(ffmg_handle *h)
     if (h->pend.e1) (void)hipEventDestroy(h->pend.e1);
     if (h->ff) ff_plan_destroy(h->ff);
     if (h->batch) batch_destroy(h->batch);
+    if (h->ffbatch) ff_batch_destroy(h->ffbatch);
     for (void *p : h->allocs) (void)hipFree(p);
     for (void *p : h->ion_buf)
         if (p) (void)hipFree(p);
@@ -1519,6 +1520,19 @@ static ffmg_status ff_begin(ffmg_handle *h, const double eta[3], const void *u, 
 }  // extern "C"
 
 namespace ffmg {
+
+// Validation and the plan for the directions, without the map (the batched
+// far field runs the stages itself).
+ffmg_status farfield_prepare(ffmg_handle *h, const double eta[3], int n_dirs, const double *dirs)
+{
+    TRY(ff_check_args(h, eta, n_dirs, dirs, h ? h->opt.ff_precision : FFMG_FF_FP64));
+    if (!h->ff) {
+        h->ff = ff_plan_create();
+        ff_plan_set_variant(h->ff, h->ff_variant);
+    }
+    HIPCHK(h, ff_plan_prepare(h->ff, h->L[0].g, h->k0, h->prob.gamma, n_dirs, dirs, h->opt.ff_precision, h->stream));
+    return FFMG_OK;
+}
 
 ffmg_status farfield_enqueue(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
                              cd *Fd)

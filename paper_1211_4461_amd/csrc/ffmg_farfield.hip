@@ -756,6 +756,7 @@ struct FarFieldPlan {
     int kb1 = 0, kb2 = 0;
     long ldP1 = 0, ldP2 = 0, ps1 = 0, ps2 = 0, gs2 = 0;
     GemmLaunchB B1, B2;
+    GemmGroupB h_B2g{};            // 2D: the host copy of the one GEMM group (batched maps)
     template <typename P>
     hipError_t alloc(P **p, size_t bytes)
     {
@@ -964,6 +965,7 @@ hipError_t ff_plan_prepare(FarFieldPlan *p, const LevelGeom &g, double k0, doubl
         }
         GemmGroupB *dg = nullptr;
         FF_CHECK(upload(p, &dg, gr));
+        if (d == 2) p->h_B2g = gr[0];
         if (d == 3) {
             p->B1 = GemmLaunchB{dg, 1, ks1, (int)round_up(ceil_div(2L * NG, 16), BF_RT_PAD), p->ldP1};
             p->B2 = GemmLaunchB{dg + 1, NG, ks_y, maxrt, p->ldP2};
@@ -1031,6 +1033,220 @@ hipError_t ff_plan_finish(FarFieldPlan *p, const LevelGeom &g, double gamma, cd 
     cd pre = {vol * cos(d * gamma), vol * sin(d * gamma)};
     hipLaunchKernelGGL(k_ff_final, dim3(M), dim3(256), 0, s, p->d_Plast, p->d_T2, M, mx, pre, p->d_F);
     hipLaunchKernelGGL(k_unpermute, dim3(ceil_div(M, 256)), dim3(256), 0, s, p->d_F, p->d_perm, M, F_out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Far fields of many 2D instances with the split-BF16 contraction in one
+// launch per stage (farfield_map_batched): the instances' axis factors, their
+// integrand planes, the GEMMs of every instance of one grid size (one group
+// per instance, each with its operator's factor planes), the final dot
+// products and the reordering.  Each stage keeps the per-instance block
+// structure of the single-map kernels, so every map equals farfield_map's.
+struct FFBJob {
+    const cd *q, *u;          // the operator's finest q, the instance's solution (null: the Born term)
+    cd *E;                    // its plane-wave factors (mx + my)
+    us8 *planes;              // its integrand planes
+    cd *T, *Fs;               // its GEMM result (M x mx) and sorted map
+    cd *F;                    // the output row (the caller's direction order)
+    const cd *Plast;          // the operator's x factors (M x mx, sorted order)
+    const int *perm;
+    int mx, my, kb_tot;
+    long ldP, pstride;
+    double lo[2], h[2], cr[2], ci[2];
+    cd pre;
+};
+
+__global__ __launch_bounds__(256) void k_ffb_axis(const FFBJob *__restrict__ jobs)
+{
+    const FFBJob &J = jobs[blockIdx.y];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int ax = i < J.mx ? 0 : 1, k = i < J.mx ? i : i - J.mx;
+    if (i >= J.mx + J.my) return;
+    const double x = J.lo[ax] + (double)(k + 1) * J.h[ax];
+    const double mag = exp(J.cr[ax] * x), ph = J.ci[ax] * x;
+    J.E[i] = cd{mag * cos(ph), mag * sin(ph)};
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_ffb_integrand(const FFBJob *__restrict__ jobs)
+{
+    const FFBJob &J = jobs[blockIdx.y];
+    const int mx = J.mx, my = J.my;
+    const cd *Ex = J.E, *Ey = J.E + mx;
+    const long ncols = J.ldP / 2;
+    const long tot = (long)J.kb_tot * ncols;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+        const long n = e % ncols;
+        const int kb = (int)(e / ncols);
+        const bool colin = n < mx;
+        const int ix = (int)(colin ? n : 0);
+        cd v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = 8 * kb + i;
+            const bool in = colin && k < my;
+            const size_t j = in ? (size_t)k * mx + n : 0;
+            const cd uin = Ex[ix] * Ey[in ? k : 0];
+            const cd t = J.u ? uin + J.u[j] : uin;
+            const cd sv = J.q[j] * t;
+            v[i] = in ? sv : cd{0.0, 0.0};
+        }
+        store_split8<NS>(v, J.planes, J.pstride, (long)kb * J.ldP + 2 * n);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ffb_final(const FFBJob *__restrict__ jobs, int M)
+{
+    const FFBJob &J = jobs[blockIdx.y];
+    __shared__ double red[2][4];
+    const int m = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (m >= M) return;
+    const int K = J.mx;
+    double re = 0.0, im = 0.0;
+    const cd *pr = J.Plast + (size_t)m * K, *tr = J.T + (size_t)m * K;
+    for (int k = threadIdx.x; k < K; k += 256) {
+        cd v = pr[k] * tr[k];
+        re += v.re;
+        im += v.im;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        re += __shfl_down(re, off, 64);
+        im += __shfl_down(im, off, 64);
+    }
+    if (lane == 0) {
+        red[0][wave] = re;
+        red[1][wave] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        J.Fs[m] = J.pre * cd{(red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
+                             (red[1][0] + red[1][1]) + (red[1][2] + red[1][3])};
+}
+
+__global__ __launch_bounds__(256) void k_ffb_unpermute(const FFBJob *__restrict__ jobs, int M)
+{
+    const FFBJob &J = jobs[blockIdx.y];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < M) J.F[J.perm[i]] = J.Fs[i];
+}
+
+struct FFBatch {
+    std::vector<uint64_t> key;    // the operators' serials per instance, then M
+    std::vector<void *> bufs;
+    FFBJob *d_jobs = nullptr;
+    std::vector<FFBJob> jobs;
+    // one GEMM launch per grid size: its groups (uploaded) and shape
+    std::vector<GemmLaunchB> gl;
+    std::vector<int> gl_variant;
+    int M = 0, ns = 0, max_cols = 0, max_ax = 0;
+    ~FFBatch()
+    {
+        for (void *b : bufs) (void)hipFree(b);
+    }
+    template <typename P>
+    hipError_t alloc(P **p, size_t bytes)
+    {
+        void *v = nullptr;
+        hipError_t e = hipMalloc(&v, bytes ? bytes : 16);
+        if (e != hipSuccess) return e;
+        bufs.push_back(v);
+        *p = (P *)v;
+        return hipSuccess;
+    }
+};
+
+void ff_batch_destroy(FFBatch *b) { delete b; }
+
+hipError_t ff_batch_run(FFBatch **cache, const std::vector<uint64_t> &key, const std::vector<FFBInst> &in, int M,
+                        hipStream_t s)
+{
+    const int n = (int)in.size();
+    FFBatch *B = *cache;
+    if (!B || B->key != key) {
+        if (B) {
+            FF_CHECK(hipStreamSynchronize(s));
+            delete B;
+        }
+        B = new FFBatch();
+        *cache = B;
+        B->key = key;
+        B->M = M;
+        B->ns = in[0].plan->ns;
+        B->jobs.resize(n);
+        // grid-size classes (the GEMM needs one ksteps and row stride per launch)
+        std::vector<std::vector<int>> classes;
+        std::vector<std::pair<int, int>> shapes;
+        for (int i = 0; i < n; ++i) {
+            const FarFieldPlan *p = in[i].plan;
+            const LevelGeom &g = *in[i].g;
+            FFBJob &J = B->jobs[i];
+            J.mx = g.m[0];
+            J.my = g.m[1];
+            J.kb_tot = p->kb1;
+            J.ldP = p->ldP1;
+            J.pstride = p->ps1;
+            J.Plast = p->d_Plast;
+            J.perm = p->d_perm;
+            FF_CHECK(B->alloc(&J.E, (size_t)(J.mx + J.my) * sizeof(cd)));
+            FF_CHECK(B->alloc(&J.planes, (size_t)p->ns * p->ps1 * sizeof(us8)));
+            FF_CHECK(B->alloc(&J.T, (size_t)M * J.mx * sizeof(cd)));
+            FF_CHECK(B->alloc(&J.Fs, (size_t)M * sizeof(cd)));
+            B->max_cols = std::max<int>(B->max_cols, (int)(p->kb1 * (p->ldP1 / 2)));
+            B->max_ax = std::max(B->max_ax, J.mx + J.my);
+            const std::pair<int, int> sh(J.mx, J.my);
+            int c = (int)(std::find(shapes.begin(), shapes.end(), sh) - shapes.begin());
+            if (c == (int)shapes.size()) {
+                shapes.push_back(sh);
+                classes.emplace_back();
+            }
+            classes[c].push_back(i);
+        }
+        for (const std::vector<int> &cl : classes) {
+            std::vector<GemmGroupB> gr;
+            int maxrt = 0;
+            for (int i : cl) {
+                const FarFieldPlan *p = in[i].plan;
+                const GemmGroupB &G0 = p->h_B2g;   // the plan's own group (its factor planes)
+                gr.push_back(GemmGroupB{G0.A, G0.a_split, (const bf8 *)B->jobs[i].planes, p->ps1, B->jobs[i].T,
+                                        (long)B->jobs[i].mx, G0.M, G0.Nc, G0.rtiles});
+                maxrt = std::max(maxrt, G0.rtiles);
+            }
+            GemmGroupB *dg = nullptr;
+            FF_CHECK(B->alloc(&dg, gr.size() * sizeof(GemmGroupB)));
+            FF_CHECK(hipMemcpy(dg, gr.data(), gr.size() * sizeof(GemmGroupB), hipMemcpyHostToDevice));
+            const FarFieldPlan *p0 = in[cl[0]].plan;
+            B->gl.push_back(GemmLaunchB{dg, (int)cl.size(), p0->B2.ksteps, maxrt, p0->ldP1});
+            B->gl_variant.push_back(p0->variant);
+        }
+        FF_CHECK(B->alloc(&B->d_jobs, (size_t)n * sizeof(FFBJob)));
+    }
+    // per call: the directions' plane waves, solutions and output rows
+    for (int i = 0; i < n; ++i) {
+        FFBJob &J = B->jobs[i];
+        const LevelGeom &g = *in[i].g;
+        J.q = in[i].q;
+        J.u = in[i].u;
+        J.F = in[i].F;
+        const double ar = -(in[i].k0 * sin(in[i].gamma)), ai = in[i].k0 * cos(in[i].gamma);
+        for (int k = 0; k < 2; ++k) {
+            J.lo[k] = g.lo[k];
+            J.h[k] = g.h[k];
+            J.cr[k] = ar * in[i].eta[k];
+            J.ci[k] = ai * in[i].eta[k];
+        }
+        const double vol = g.h[0] * g.h[1];
+        J.pre = cd{vol * cos(2 * in[i].gamma), vol * sin(2 * in[i].gamma)};
+    }
+    FF_CHECK(hipMemcpyAsync(B->d_jobs, B->jobs.data(), (size_t)n * sizeof(FFBJob), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_ffb_axis, dim3(ceil_div(B->max_ax, 256), n), dim3(256), 0, s, B->d_jobs);
+    const dim3 gi(std::min<unsigned>(grid_for(B->max_cols), 4096u), (unsigned)n);
+    if (B->ns == 3) hipLaunchKernelGGL(k_ffb_integrand<3>, gi, dim3(256), 0, s, B->d_jobs);
+    else hipLaunchKernelGGL(k_ffb_integrand<2>, gi, dim3(256), 0, s, B->d_jobs);
+    for (size_t c = 0; c < B->gl.size(); ++c) launch_gemm_bf16(B->gl[c], B->ns, B->gl_variant[c], s);
+    hipLaunchKernelGGL(k_ffb_final, dim3(M, n), dim3(256), 0, s, B->d_jobs, M);
+    hipLaunchKernelGGL(k_ffb_unpermute, dim3(ceil_div(M, 256), n), dim3(256), 0, s, B->d_jobs, M);
     return hipGetLastError();
 }
 

@@ -107,6 +107,7 @@ struct ffmg_handle {
     double rho_jacobi = 0.0;             // Jacobi V-cycle convergence factor (the reference)
     bool learned_on = false;             // learned smoother in use
     ffmg::Batch *batch = nullptr;    // batched-solve workspace for a list of handles starting with this one
+    ffmg::FFBatch *ffbatch = nullptr; // batched far-field workspace, likewise
     std::vector<void *> allocs;
     std::string err;
     // optional event timing of selected kernels (benchmark instrumentation)
@@ -143,6 +144,8 @@ double exponent_budget(const ffmg_handle *h);
 // far-field map into device memory F on the handle's stream, no synchronisation
 ffmg_status farfield_enqueue(ffmg_handle *h, const double eta[3], const void *u, int n_dirs, const double *dirs,
                              cd *F);
+// the checks and the plan of farfield_enqueue without the map
+ffmg_status farfield_prepare(ffmg_handle *h, const double eta[3], int n_dirs, const double *dirs);
 void batch_destroy(Batch *b);
 // one learned smoothing step on level l, in place on u
 void learned_step(ffmg_handle *h, int l, const cd *b, cd *u, const int *stop);

@@ -416,6 +416,23 @@ hipError_t ff_plan_integrand(FarFieldPlan *p, const LevelGeom &g, const cd *q, c
                              hipStream_t s);
 hipError_t ff_plan_contract(FarFieldPlan *p, const LevelGeom &g, hipStream_t s);
 hipError_t ff_plan_finish(FarFieldPlan *p, const LevelGeom &g, double gamma, cd *F_out, hipStream_t s);
+// Batched 2D split-BF16 far fields (farfield_map_batched): instance i has
+// its operator's plan (prepared for the same M directions), grid, finest q,
+// solution u (null: the Born term), output row F (device), direction eta and
+// the operator's k0 and gamma.  The workspace is cached in *cache for the
+// list key and rebuilt when it changes; everything is queued on s.
+struct FFBInst {
+    const FarFieldPlan *plan;
+    const LevelGeom *g;
+    const cd *q, *u;
+    cd *F;
+    double eta[3];
+    double k0, gamma;
+};
+struct FFBatch;
+void ff_batch_destroy(FFBatch *b);
+hipError_t ff_batch_run(FFBatch **cache, const std::vector<uint64_t> &key, const std::vector<FFBInst> &in, int M,
+                        hipStream_t s);
 // split-GEMM tile variants (autotuning)
 int ff_plan_variants();
 int ff_plan_default_variant();

@@ -152,6 +152,15 @@ def test_batch_reuse_and_far_fields(ff, orc):
     ff.farfield_map_batched(hs, etas2, us, dirs, out=Fd)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(Fd.cpu().numpy(), F)
+    # the Born terms (u = None), and a second direction set (the batched
+    # workspace is rebuilt for it), equal the per-instance maps too
+    F0 = ff.farfield_map_batched(hs, etas2, None, dirs)
+    for i in range(len(insts)):
+        np.testing.assert_array_equal(F0[i], ff.farfield_map(hs[i], etas2[i], None, dirs))
+    dirs2 = dirs[::3]
+    F2 = ff.farfield_map_batched(hs, etas2, us, dirs2)
+    for i in range(len(insts)):
+        np.testing.assert_array_equal(F2[i], ff.farfield_map(hs[i], etas2[i], us[i], dirs2))
     # a sub-list of the handles: rebuilt workspace, same answers
     sub = [0, 2, 4]
     us2 = [torch.empty_like(us[i]) for i in sub]
