@@ -34,10 +34,7 @@ constexpr int NSLOT_D = GMRES_MAX_M + 1;
 
 __device__ __forceinline__ void grid_coords(size_t j, int mx, int my, int &ix, int &iy, int &iz)
 {
-    ix = (int)(j % mx);
-    size_t r = j / mx;
-    iy = (int)(r % my);
-    iz = (int)(r / my);
+    split3(j, mx, my, ix, iy, iz);   // 32-bit divisions where j fits
 }
 
 // (A z)_j from the five (seven) stencil values, zero outside the grid: the

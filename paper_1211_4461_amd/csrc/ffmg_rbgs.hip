@@ -24,9 +24,8 @@ __global__ __launch_bounds__(256) void k_rbgs_half(cx<T> *__restrict__ u, const 
     const int mx = P.mx, my = P.my, mz = P.mz;
     const size_t rows = (size_t)my * mz;
     if (t >= (size_t)half_x * rows) return;
-    const int k = (int)(t % half_x);
-    const size_t row = t / half_x;
-    const int iy = (int)(row % my), iz = (int)(row / my);
+    int k, iy, iz;
+    split3(t, half_x, my, k, iy, iz);   // 32-bit divisions where t fits
     const int ix = 2 * k + ((iy + iz + color) & 1);
     if (ix >= mx) return;
     const size_t j = ((size_t)iz * my + iy) * mx + ix;
