@@ -568,8 +568,8 @@ ffmg_status setup_impl(ffmg_handle *h)
         }
         if (h->opt.smoother == FFMG_SMOOTH_GMRES && l + 1 < h->L.size()) {
             const int mk = h->opt.krylov_m > 0 ? h->opt.krylov_m : 3;
-            TRY(dalloc(h, &lv.gz, (size_t)(mk + 1) * N * sizeof(cd)));
-            if (ir) TRY(dalloc(h, &lv.gz32, (size_t)(mk + 1) * N * sizeof(cf)));
+            TRY(dalloc(h, &lv.gz, (size_t)(mk + 2) * N * sizeof(cd)));
+            if (ir) TRY(dalloc(h, &lv.gz32, (size_t)(mk + 2) * N * sizeof(cf)));
         }
         if (ir) {
             TRY(dalloc(h, &lv.q32, N * sizeof(cf)));
@@ -724,7 +724,7 @@ static void other_smooth_step(ffmg_handle *h, Level &lv, const cx<T> *b, cx<T> *
     using LP = LvlPtr<T>;
     if (h->opt.smoother == FFMG_SMOOTH_GMRES) {
         launch_gmres_step<T>(lv.g, LP::P(lv), b, LP::q(lv), u, zero, h->krylov_m, LP::gz(lv), h->d_gm, h->d_gm_parts,
-                             h->stream, stop);
+                             h->stream, stop, h->opt.tile_config != TILE_REFERENCE);
     } else {
         if (zero) launch_zero<T>(u, lv.g.N(), h->stream, stop);
         launch_rbgs_sweep<T>(lv.g, LP::P(lv), b, LP::q(lv), u, h->stream, stop);
@@ -1178,7 +1178,7 @@ ffmg_status mg_gmres_smooth(ffmg_handle *h, const void *b, void *u)
     if (h->L.size() < 2) return fail(h, FFMG_EINVAL, "a one-level hierarchy is solved exactly, not smoothed");
     Level &l0 = h->L[0];
     launch_gmres_step<double>(l0.g, l0.P64, (const cd *)b, l0.q, (cd *)u, false, h->krylov_m, l0.gz, h->d_gm,
-                              h->d_gm_parts, h->stream, nullptr);
+                              h->d_gm_parts, h->stream, nullptr, h->opt.tile_config != TILE_REFERENCE);
     HIPCHK(h, hipGetLastError());
     return FFMG_OK;
 }

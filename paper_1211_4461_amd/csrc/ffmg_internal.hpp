@@ -142,10 +142,11 @@ constexpr int GM_C = GM_D + 2 * GMRES_MAX_M * GMRES_MAX_M;
 constexpr int GM_S = GM_C + 2 * GMRES_MAX_M;
 constexpr int GM_PARTS = (GMRES_MAX_M + 1 + 2 * GMRES_MAX_M * GMRES_MAX_M) * 1024;
 // One GMRES(m) smoothing step in place on a level (zero: u is 0 on entry);
-// Z: m + 1 vectors of the level, S: GM_S doubles, parts: GM_PARTS doubles.
+// Z: m + 2 vectors of the level, S: GM_S doubles, parts: GM_PARTS doubles;
+// fused: m + 3 launches, else the reference 4 m + 3.
 template <typename T>
 void launch_gmres_step(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero,
-                       int m, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop);
+                       int m, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop, bool fused);
 
 // One red-black Gauss-Seidel sweep in place on a level (red points, then
 // black; ffmg_rbgs.hip).

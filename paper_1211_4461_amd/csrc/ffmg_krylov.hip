@@ -14,11 +14,17 @@
 // complex Givens rotations (FP64), and u += sum_j (y_j / sqrt(n_j)) Z_j.
 //
 // Kernels (one point per thread, grid-stride, neighbours read from global
-// memory): the residual with its partial norm; A Z_j fused with the partial
-// products <Z_i, A Z_j>; the orthogonalisation with its partial norm; the
-// update, each partial sum finished by a one-block kernel that adds the
-// blocks' partials in block order (the last one also solves the small
-// problem): 4 m + 3 launches per step.  Partial sums are FP64 in both
+// memory): the residual with its partial norm; A Z_0 with the partial
+// product <Z_0, A Z_0>; for j = 1 .. m - 1 one pass that forms Z_j from
+// W = A Z_{j-1} and Z_0 .. Z_{j-1} (at the point and at its stencil
+// neighbours, so that the orthogonalisation needs no pass of its own) and
+// applies A to it, with the partial |Z_j|^2 and <Z_i, A Z_j>; the norm of
+// Z_m (not stored); the small problem and the update.  Each pass adds the
+// previous passes' partial sums itself, in block order (every block the same
+// sums, so no pass waits on a one-block kernel): m + 3 launches per step.
+// The reference kernel path (a pass per product and one for the
+// orthogonalisation, each finished by a one-block kernel: 4 m + 3 launches)
+// computes the same values in the same order, so both give the same bits.  Partial sums are FP64 in both
 // precisions.  A level of at most GM_BLOCK_MAX_POINTS points runs the whole
 // step in one 1024-thread workgroup.
 #include "ffmg_internal.hpp"
@@ -38,23 +44,29 @@ __device__ __forceinline__ void grid_coords(size_t j, int mx, int my, int &ix, i
 }
 
 // (A z)_j from the five (seven) stencil values, zero outside the grid: the
-// point functions of every other kernel, so the bits agree with them.
-template <typename T, int DIM>
-__device__ __forceinline__ cx<T> apply_at(const Stencil<T> &P, const cx<T> *__restrict__ z, cx<T> qj, size_t j)
+// point functions of every other kernel, so the bits agree with them.  zat(k)
+// gives z at point k (a load, or a value formed on the fly); zc = zat(j).
+template <typename T, int DIM, typename ZAt>
+__device__ __forceinline__ cx<T> apply_at_f(const Stencil<T> &P, ZAt zat, cx<T> zc, cx<T> qj, size_t j)
 {
     int ix, iy, iz;
     grid_coords(j, P.mx, P.my, ix, iy, iz);
     const cx<T> zero = {T(0), T(0)};
     const size_t sx = 1, sy = (size_t)P.mx, sz = (size_t)P.mx * P.my;
-    cx<T> uc = z[j];
-    cx<T> w = ix > 0 ? z[j - sx] : zero, e = ix < P.mx - 1 ? z[j + sx] : zero;
-    cx<T> s = iy > 0 ? z[j - sy] : zero, n = iy < P.my - 1 ? z[j + sy] : zero;
-    cx<T> L = lap_xy(P, uc, w, e, s, n);
+    cx<T> w = ix > 0 ? zat(j - sx) : zero, e = ix < P.mx - 1 ? zat(j + sx) : zero;
+    cx<T> s = iy > 0 ? zat(j - sy) : zero, n = iy < P.my - 1 ? zat(j + sy) : zero;
+    cx<T> L = lap_xy(P, zc, w, e, s, n);
     if (DIM == 3) {
-        cx<T> d = iz > 0 ? z[j - sz] : zero, up = iz < P.mz - 1 ? z[j + sz] : zero;
-        L = lap_add_z(P, L, uc, d, up);
+        cx<T> d = iz > 0 ? zat(j - sz) : zero, up = iz < P.mz - 1 ? zat(j + sz) : zero;
+        L = lap_add_z(P, L, zc, d, up);
     }
-    return apply_point(P, L, uc, qj);
+    return apply_point(P, L, zc, qj);
+}
+
+template <typename T, int DIM>
+__device__ __forceinline__ cx<T> apply_at(const Stencil<T> &P, const cx<T> *__restrict__ z, cx<T> qj, size_t j)
+{
+    return apply_at_f<T, DIM>(P, [&](size_t k) { return z[k]; }, z[j], qj, j);
 }
 
 // Sums of NV doubles per thread of a 256-thread block into
@@ -75,6 +87,20 @@ __device__ __forceinline__ void block_partials(double (&acc)[NV], const int (&sl
     if (threadIdx.x < NV) {
         const int v = threadIdx.x;
         parts[(size_t)slot[v] * GM_BLOCKS + blockIdx.x] = (red[0][v] + red[1][v]) + (red[2][v] + red[3][v]);
+    }
+}
+
+// The sum over the nb blocks of the partials of slot slot0 + v into out[v],
+// v < nv, in block order (lane-strided, then a wave tree; one wave per value):
+// the order of k_gm_reduce.
+__device__ __forceinline__ void reduce_slots(const double *parts, int nb, int slot0, int nv, double *out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int v = wv; v < nv; v += 4) {
+        double a = 0.0;
+        for (int i = lane; i < nb; i += 64) a += parts[(size_t)(slot0 + v) * GM_BLOCKS + i];
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
+        if (lane == 0) out[v] = a;
     }
 }
 
@@ -151,7 +177,7 @@ __device__ void gm_solve_small(const double *n, const double *d, int m, double *
     }
 }
 
-// Z0 = b - A u (zero: u is 0 and is set to 0), n_0 = |Z0|^2.
+// Z0 = b - A u (zero: u is 0 and is set to 0), partial n_0 = |Z0|^2.
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_gm_resid(cx<T> *__restrict__ u, int zero, const cx<T> *__restrict__ b,
                                                   const cx<T> *__restrict__ q, cx<T> *__restrict__ z0, Stencil<T> P,
@@ -174,16 +200,16 @@ __global__ __launch_bounds__(256) void k_gm_resid(cx<T> *__restrict__ u, int zer
     block_partials<1>(acc, slot, parts);
 }
 
-// W = A Z_j into Z_{j+1}'s slot; d_ij = <Z_i, W> for i <= j (j = NJ - 1).
+// W = A Z_j into w (the reference path: Z_{j+1}'s slot); partial d_ij =
+// <Z_i, W> for i <= j (j = NJ - 1).
 template <typename T, int DIM, int NJ>
-__global__ __launch_bounds__(256) void k_gm_apply_dots(cx<T> *__restrict__ Z, size_t N, const cx<T> *__restrict__ q,
-                                                       Stencil<T> P, double *__restrict__ parts,
-                                                       const int *__restrict__ stop)
+__global__ __launch_bounds__(256) void k_gm_apply_dots(cx<T> *__restrict__ Z, cx<T> *__restrict__ w, size_t N,
+                                                       const cx<T> *__restrict__ q, Stencil<T> P,
+                                                       double *__restrict__ parts, const int *__restrict__ stop)
 {
     if (stop && *stop) return;
     constexpr int j = NJ - 1;
     const cx<T> *zj = Z + (size_t)j * N;
-    cx<T> *w = Z + (size_t)NJ * N;
     double acc[2 * NJ];
 #pragma unroll
     for (int v = 0; v < 2 * NJ; ++v) acc[v] = 0.0;
@@ -204,29 +230,165 @@ __global__ __launch_bounds__(256) void k_gm_apply_dots(cx<T> *__restrict__ Z, si
     block_partials<2 * NJ>(acc, slot, parts);
 }
 
+// The coefficients of the orthogonalisation of A Z_{J-1} against Z_0 ..
+// Z_{J-1}: g_i = d_{i,J-1} / n_i (zero where n_i is).
+template <typename T, int J>
+__device__ __forceinline__ void orth_coeffs(const double *__restrict__ S, cx<T> (&g)[J])
+{
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        const double ni = S[i];
+        const double dr = S[GM_D + 2 * ((J - 1) * GMRES_MAX_M + i)], di = S[GM_D + 2 * ((J - 1) * GMRES_MAX_M + i) + 1];
+        g[i] = cx<T>{T(ni > 0.0 ? dr / ni : 0.0), T(ni > 0.0 ? di / ni : 0.0)};
+    }
+}
+
+// Z_J = W - sum_{i<J} g_i Z_i at point p (W = A Z_{J-1}).
+template <typename T, int J>
+__device__ __forceinline__ cx<T> orth_at(const cx<T> *__restrict__ W, const cx<T> *__restrict__ Z, size_t N,
+                                         const cx<T> (&g)[J], size_t p)
+{
+    cx<T> v = W[p];
+#pragma unroll
+    for (int i = 0; i < J; ++i) {
+        const cx<T> zi = Z[(size_t)i * N + p];
+        v = cx<T>{v.re - (g[i].re * zi.re - g[i].im * zi.im), v.im - (g[i].re * zi.im + g[i].im * zi.re)};
+    }
+    return v;
+}
+
+// The scalars a fused pass needs to orthogonalise A Z_{J-1} (the previous
+// passes' results), into the block's copy Sl of the S layout: n_i (i < J - 1)
+// from S, where the first block of an earlier pass left them; n_{J-1} and
+// d_{i,J-1} (i < J) summed from the previous passes' partials in the order of
+// k_gm_reduce (every block sums them; the first block also stores them in S
+// for the later passes).
+template <int J>
+__device__ __forceinline__ void step_scalars(const double *__restrict__ parts, int nb, double *__restrict__ S,
+                                             double *Sl)
+{
+    constexpr int dcol = GM_D + 2 * ((J - 1) * GMRES_MAX_M);
+    if (threadIdx.x < J - 1) Sl[threadIdx.x] = S[threadIdx.x];
+    reduce_slots(parts, nb, J - 1, 1, Sl + (J - 1));
+    reduce_slots(parts, nb, NSLOT_D + 2 * ((J - 1) * GMRES_MAX_M), 2 * J, Sl + dcol);
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) S[J - 1] = Sl[J - 1];
+        if (threadIdx.x < 2 * J) S[dcol + threadIdx.x] = Sl[dcol + threadIdx.x];
+    }
+}
+
+// One pass for 1 <= J < m: Z_J = A Z_{J-1} - sum_{i<J} g_i Z_i, formed from
+// wprev = A Z_{J-1} at the point and its stencil neighbours and stored; wout
+// = A Z_J; the partial |Z_J|^2 and <Z_i, A Z_J> (i <= J).  The values and
+// partial sums of k_gm_orth<J> followed by k_gm_apply_dots<J + 1>.
+template <typename T, int DIM, int J>
+__global__ __launch_bounds__(256) void k_gm_orth_apply(cx<T> *__restrict__ Z, const cx<T> *__restrict__ wprev,
+                                                       cx<T> *__restrict__ wout, size_t N,
+                                                       const cx<T> *__restrict__ q, Stencil<T> P,
+                                                       double *__restrict__ S, double *__restrict__ parts,
+                                                       const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    __shared__ double Sl[GM_S];
+    step_scalars<J>(parts, gridDim.x, S, Sl);
+    cx<T> g[J];
+    orth_coeffs<T, J>(Sl, g);
+    cx<T> *zJ = Z + (size_t)J * N;
+    constexpr int NV = 1 + 2 * (J + 1);   // |Z_J|^2, then <Z_i, A Z_J> (re, im) for i <= J
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
+        const cx<T> zc = orth_at<T, J>(wprev, Z, N, g, p);
+        const cx<T> Wp = apply_at_f<T, DIM>(P, [&](size_t k) { return orth_at<T, J>(wprev, Z, N, g, k); }, zc, q[p], p);
+        zJ[p] = zc;
+        wout[p] = Wp;
+        acc[0] += (double)zc.re * (double)zc.re + (double)zc.im * (double)zc.im;
+        const double wr = Wp.re, wi = Wp.im;
+#pragma unroll
+        for (int i = 0; i <= J; ++i) {
+            const cx<T> zi = (i < J) ? Z[(size_t)i * N + p] : zc;
+            acc[1 + 2 * i] += (double)zi.re * wr + (double)zi.im * wi;
+            acc[2 + 2 * i] += (double)zi.re * wi - (double)zi.im * wr;
+        }
+    }
+    int slot[NV];
+    slot[0] = J;
+#pragma unroll
+    for (int v = 1; v < NV; ++v) slot[v] = NSLOT_D + 2 * (J * GMRES_MAX_M) + (v - 1);
+    block_partials<NV>(acc, slot, parts);
+}
+
+// The last Arnoldi vector's partial norm: n_M = |A Z_{M-1} - sum_{i<M} g_i
+// Z_i|^2 (the vector itself is not needed).
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_gm_orth_norm(const cx<T> *__restrict__ Z, const cx<T> *__restrict__ wprev,
+                                                      size_t N, double *__restrict__ S, double *__restrict__ parts,
+                                                      const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    __shared__ double Sl[GM_S];
+    step_scalars<M>(parts, gridDim.x, S, Sl);
+    cx<T> g[M];
+    orth_coeffs<T, M>(Sl, g);
+    double acc[1] = {0.0};
+    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
+        const cx<T> v = orth_at<T, M>(wprev, Z, N, g, p);
+        acc[0] += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    }
+    const int slot[1] = {M};
+    block_partials<1>(acc, slot, parts);
+}
+
+// The small problem and the update u += sum_j c_j Z_j in one pass: every
+// block sums n_M from the partials, takes the other scalars from S and solves
+// the small problem (the first block also stores n_M and the coefficients).
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_gm_solve_update(cx<T> *__restrict__ u, const cx<T> *__restrict__ Z,
+                                                         size_t N, double *__restrict__ S,
+                                                         const double *__restrict__ parts,
+                                                         const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    __shared__ double Sl[GM_S];
+    __shared__ GmWork W;
+    if (threadIdx.x < M) Sl[threadIdx.x] = S[threadIdx.x];
+    for (int t = threadIdx.x; t < 2 * M * GMRES_MAX_M; t += 256) Sl[GM_D + t] = S[GM_D + t];
+    reduce_slots(parts, gridDim.x, M, 1, Sl + M);
+    __syncthreads();
+    if (threadIdx.x == 0) gm_solve_small(Sl, Sl + GM_D, M, Sl + GM_C, W);
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) S[M] = Sl[M];
+        if (threadIdx.x < 2 * M) S[GM_C + threadIdx.x] = Sl[GM_C + threadIdx.x];
+    }
+    cx<T> c[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) c[j] = cx<T>{T(Sl[GM_C + 2 * j]), T(Sl[GM_C + 2 * j + 1])};
+    for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
+        cx<T> v = u[p];
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            const cx<T> zj = Z[(size_t)j * N + p];
+            v = cx<T>{v.re + (c[j].re * zj.re - c[j].im * zj.im), v.im + (c[j].re * zj.im + c[j].im * zj.re)};
+        }
+        u[p] = v;
+    }
+}
+
 // Z_{j+1} = W - sum_{i<=j} (d_ij / n_i) Z_i in place, partial |Z_{j+1}|^2.
 template <typename T, int NJ>
 __global__ __launch_bounds__(256) void k_gm_orth(cx<T> *__restrict__ Z, size_t N, const double *__restrict__ S,
                                                  double *__restrict__ parts, const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    constexpr int j = NJ - 1;
     cx<T> g[NJ];
-#pragma unroll
-    for (int i = 0; i < NJ; ++i) {
-        const double ni = S[i];
-        const double dr = S[GM_D + 2 * (j * GMRES_MAX_M + i)], di = S[GM_D + 2 * (j * GMRES_MAX_M + i) + 1];
-        g[i] = cx<T>{T(ni > 0.0 ? dr / ni : 0.0), T(ni > 0.0 ? di / ni : 0.0)};
-    }
+    orth_coeffs<T, NJ>(S, g);
     cx<T> *w = Z + (size_t)NJ * N;
     double acc[1] = {0.0};
     for (size_t p = (size_t)blockIdx.x * 256 + threadIdx.x; p < N; p += (size_t)gridDim.x * 256) {
-        cx<T> v = w[p];
-#pragma unroll
-        for (int i = 0; i < NJ; ++i) {
-            const cx<T> zi = Z[(size_t)i * N + p];
-            v = cx<T>{v.re - (g[i].re * zi.re - g[i].im * zi.im), v.im - (g[i].re * zi.im + g[i].im * zi.re)};
-        }
+        const cx<T> v = orth_at<T, NJ>(w, Z, N, g, p);
         w[p] = v;
         acc[0] += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
     }
@@ -235,19 +397,16 @@ __global__ __launch_bounds__(256) void k_gm_orth(cx<T> *__restrict__ Z, size_t N
 }
 
 // out[v] = sum over the nb blocks of the partials of slot0 + v, in block order
-// (one block, one wave per value); solve_m > 0: then the small problem.
+// (one block, one wave per value), and likewise out1[v] from slot1 + v for
+// v < nv1; solve_m > 0: then the small problem.
 __global__ __launch_bounds__(256) void k_gm_reduce(const double *__restrict__ parts, int nb, int slot0, int nv,
                                                    double *__restrict__ out, int solve_m, double *__restrict__ S,
-                                                   const int *__restrict__ stop)
+                                                   const int *__restrict__ stop, int slot1 = 0, int nv1 = 0,
+                                                   double *__restrict__ out1 = nullptr)
 {
     if (stop && *stop) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int v = wv; v < nv; v += 4) {
-        double a = 0.0;
-        for (int i = lane; i < nb; i += 64) a += parts[(size_t)(slot0 + v) * GM_BLOCKS + i];
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_down(a, off, 64);
-        if (lane == 0) out[v] = a;
-    }
+    reduce_slots(parts, nb, slot0, nv, out);
+    if (nv1 > 0) reduce_slots(parts, nb, slot1, nv1, out1);
     if (solve_m > 0) {
         __shared__ GmWork W;
         __syncthreads();
@@ -397,17 +556,33 @@ void launch_arnoldi_all(cx<T> *Z, size_t N, const cx<T> *q, const Stencil<T> &P,
                         hipStream_t s, const int *stop)
 {
     constexpr int j = NJ - 1;
-    hipLaunchKernelGGL((k_gm_apply_dots<T, DIM, NJ>), dim3(nb), dim3(256), 0, s, Z, N, q, P, parts, stop);
+    hipLaunchKernelGGL((k_gm_apply_dots<T, DIM, NJ>), dim3(nb), dim3(256), 0, s, Z, Z + (size_t)NJ * N, N, q, P,
+                       parts, stop);
     hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, NSLOT_D + 2 * (j * GMRES_MAX_M), 2 * NJ,
-                       S + GM_D + 2 * (j * GMRES_MAX_M), 0, S, stop);
+                       S + GM_D + 2 * (j * GMRES_MAX_M), 0, S, stop, 0, 0, nullptr);
     hipLaunchKernelGGL((k_gm_orth<T, NJ>), dim3(nb), dim3(256), 0, s, Z, N, S, parts, stop);
-    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, NJ, 1, S + NJ, NJ == M ? M : 0, S, stop);
+    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, NJ, 1, S + NJ, NJ == M ? M : 0, S, stop, 0, 0,
+                       nullptr);
     if constexpr (NJ < M) launch_arnoldi_all<T, DIM, NJ + 1, M>(Z, N, q, P, S, parts, nb, s, stop);
+}
+
+// The fused passes for J = 1 .. M - 1 (A Z_{J-1} in slot M + ((J - 1) & 1),
+// A Z_J into the other of the two).
+template <typename T, int DIM, int J, int M>
+void launch_orth_apply_all(cx<T> *Z, size_t N, const cx<T> *q, const Stencil<T> &P, double *S, double *parts, int nb,
+                           hipStream_t s, const int *stop)
+{
+    if constexpr (J < M) {
+        hipLaunchKernelGGL((k_gm_orth_apply<T, DIM, J>), dim3(nb), dim3(256), 0, s, Z,
+                           Z + (size_t)(M + ((J - 1) & 1)) * N, Z + (size_t)(M + (J & 1)) * N, N, q, P, S, parts,
+                           stop);
+        launch_orth_apply_all<T, DIM, J + 1, M>(Z, N, q, P, S, parts, nb, s, stop);
+    }
 }
 
 template <typename T, int DIM, int M>
 void launch_step_m(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero,
-                   cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop)
+                   cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop, bool fused)
 {
     const size_t N = g.N();
     if (N <= GM_BLOCK_MAX_POINTS) {   // small level: the whole step in one workgroup
@@ -417,42 +592,52 @@ void launch_step_m(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, cons
     }
     const int nb = (int)std::min<size_t>((N + 255) / 256, GM_BLOCKS);
     hipLaunchKernelGGL((k_gm_resid<T, DIM>), dim3(nb), dim3(256), 0, s, u, zero ? 1 : 0, b, q, Z, P, N, parts, stop);
-    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, 0, 1, S, 0, S, stop);
+    if (fused) {
+        hipLaunchKernelGGL((k_gm_apply_dots<T, DIM, 1>), dim3(nb), dim3(256), 0, s, Z, Z + (size_t)M * N, N, q, P,
+                           parts, stop);
+        launch_orth_apply_all<T, DIM, 1, M>(Z, N, q, P, S, parts, nb, s, stop);
+        hipLaunchKernelGGL((k_gm_orth_norm<T, M>), dim3(nb), dim3(256), 0, s, Z, Z + (size_t)(M + ((M - 1) & 1)) * N,
+                           N, S, parts, stop);
+        hipLaunchKernelGGL((k_gm_solve_update<T, M>), dim3(nb), dim3(256), 0, s, u, Z, N, S, parts, stop);
+        return;
+    }
+    hipLaunchKernelGGL(k_gm_reduce, dim3(1), dim3(256), 0, s, parts, nb, 0, 1, S, 0, S, stop, 0, 0, nullptr);
     launch_arnoldi_all<T, DIM, 1, M>(Z, N, q, P, S, parts, nb, s, stop);
     hipLaunchKernelGGL((k_gm_update<T, M>), dim3(nb), dim3(256), 0, s, u, Z, N, S, stop);
 }
 
 template <typename T, int DIM>
 void launch_step_dim(int m, const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u,
-                     bool zero, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop)
+                     bool zero, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop, bool fused)
 {
     switch (m) {
-    case 1: launch_step_m<T, DIM, 1>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
-    case 2: launch_step_m<T, DIM, 2>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
-    case 3: launch_step_m<T, DIM, 3>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
-    case 4: launch_step_m<T, DIM, 4>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
-    case 5: launch_step_m<T, DIM, 5>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
-    case 6: launch_step_m<T, DIM, 6>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
-    case 7: launch_step_m<T, DIM, 7>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
-    default: launch_step_m<T, DIM, 8>(g, P, b, q, u, zero, Z, S, parts, s, stop); break;
+    case 1: launch_step_m<T, DIM, 1>(g, P, b, q, u, zero, Z, S, parts, s, stop, fused); break;
+    case 2: launch_step_m<T, DIM, 2>(g, P, b, q, u, zero, Z, S, parts, s, stop, fused); break;
+    case 3: launch_step_m<T, DIM, 3>(g, P, b, q, u, zero, Z, S, parts, s, stop, fused); break;
+    case 4: launch_step_m<T, DIM, 4>(g, P, b, q, u, zero, Z, S, parts, s, stop, fused); break;
+    case 5: launch_step_m<T, DIM, 5>(g, P, b, q, u, zero, Z, S, parts, s, stop, fused); break;
+    case 6: launch_step_m<T, DIM, 6>(g, P, b, q, u, zero, Z, S, parts, s, stop, fused); break;
+    case 7: launch_step_m<T, DIM, 7>(g, P, b, q, u, zero, Z, S, parts, s, stop, fused); break;
+    default: launch_step_m<T, DIM, 8>(g, P, b, q, u, zero, Z, S, parts, s, stop, fused); break;
     }
 }
 
 }  // namespace
 
-// One GMRES(m) smoothing step in place on a level: Z holds m + 1 vectors of
+// One GMRES(m) smoothing step in place on a level: Z holds m + 2 vectors of
 // N points, S the step's scalars (GM_S doubles), parts the partial sums
-// (GM_PARTS doubles).  zero: u is 0 on entry (not read).
+// (GM_PARTS doubles).  zero: u is 0 on entry (not read).  fused: the
+// m + 3-launch passes, else the reference passes.
 template <typename T>
 void launch_gmres_step(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero,
-                       int m, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop)
+                       int m, cx<T> *Z, double *S, double *parts, hipStream_t s, const int *stop, bool fused)
 {
-    if (g.dim == 3) launch_step_dim<T, 3>(m, g, P, b, q, u, zero, Z, S, parts, s, stop);
-    else launch_step_dim<T, 2>(m, g, P, b, q, u, zero, Z, S, parts, s, stop);
+    if (g.dim == 3) launch_step_dim<T, 3>(m, g, P, b, q, u, zero, Z, S, parts, s, stop, fused);
+    else launch_step_dim<T, 2>(m, g, P, b, q, u, zero, Z, S, parts, s, stop, fused);
 }
 template void launch_gmres_step<double>(const LevelGeom &, const Stencil<double> &, const cd *, const cd *, cd *, bool,
-                                        int, cd *, double *, double *, hipStream_t, const int *);
+                                        int, cd *, double *, double *, hipStream_t, const int *, bool);
 template void launch_gmres_step<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *, cf *, bool,
-                                       int, cf *, double *, double *, hipStream_t, const int *);
+                                       int, cf *, double *, double *, hipStream_t, const int *, bool);
 
 }  // namespace ffmg

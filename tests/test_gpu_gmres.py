@@ -96,6 +96,52 @@ def test_gmres_vcycle_iterates_match_oracle(ff, orc, name, mk, tile):
     h.destroy()
 
 
+BIG = [
+    ("2d-255", lambda: at_angle(W.bumps_2d(n=256, seed=2, M=24), 10)),
+    ("3d-63", lambda: W.radial_3d(64, L=6.0, n_az=8, n_pol=5)),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("m", [1, 2, 3])
+@pytest.mark.parametrize("name,mk", BIG, ids=[c[0] for c in BIG])
+def test_fused_gmres_passes_equal_reference_passes(ff, orc, name, mk, m, prec):
+    """The m + 3-launch GMRES(m) step (the orthogonalisation formed inside the
+    next application of A, each pass summing the previous passes' partials
+    itself) and the reference passes (4 m + 3 launches)
+    give the same bits: two FP64 steps on the finest level, V-cycle iterates,
+    and a solve (cycles, residual, iterate).  The levels above 4096 points
+    take the multi-block passes, the smaller ones the one-workgroup step."""
+    w = mk()
+    hs = [problem(ff, orc, w, krylov_m=m, nu1=1, nu2=1, precision=prec, tile_config=t)[0] for t in (0, 1)]
+    g = orc.Grid(w.dim, w.n, w.lo, w.hi)
+    kappa, q, k0 = orc.problem(w.kind, w.k0, w.energy, w.coef)
+    bd = dev(orc.rhs_plane_wave(g, w.gamma, k0, q, w.eta))
+    u0 = dev(crand(5, g.shape))
+    us = [u0.clone() for _ in hs]
+    for h, u in zip(hs, us):
+        ff.mg_gmres_smooth(h, bd, u)
+        ff.mg_gmres_smooth(h, bd, u)
+    torch.cuda.synchronize()
+    assert torch.equal(us[0], us[1])
+    vs = [torch.zeros_like(bd) for _ in hs]
+    for k in range(2):
+        for h, v in zip(hs, vs):
+            ff.mg_vcycle(h, bd, v)
+        torch.cuda.synchronize()
+        assert torch.equal(vs[0], vs[1]), f"cycle {k + 1}"
+    infos = []
+    for h, v in zip(hs, vs):
+        v.zero_()
+        infos.append(ff.mg_solve(h, bd, v, tol=1e-9))
+    torch.cuda.synchronize()
+    assert infos[0].status == 0 and infos[0].cycles == infos[1].cycles
+    assert infos[0].rel_residual == infos[1].rel_residual
+    assert torch.equal(vs[0], vs[1])
+    for h in hs:
+        h.destroy()
+
+
 @pytest.mark.parametrize("deg", [10, 30])
 def test_gmres_solve_below_the_jacobi_angle(ff, orc, deg):
     """At 10 degrees Jacobi V(2,2) diverges (ENOCONV on both sides) and
