@@ -352,7 +352,11 @@ ffmg_status mg_solve_batched(ffmg_handle *const *hs, int count, const double *et
 /* Far-field maps of count instances (hs[i], etas[3i..], u[i]; u may be NULL:
  * Born terms) at the same n_dirs directions, into F (complex128
  * [count][n_dirs], HOST or DEVICE) without synchronising between instances;
- * each row equals farfield_map on that instance.  Synchronises. */
+ * each row equals farfield_map on that instance.  2D split-precision handles
+ * run each stage of all instances in one launch (per grid size for the
+ * contraction); their workspace is owned by hs[0] and rebuilt whenever the
+ * handle list, a handle's direction plan (other directions or precision) or
+ * its tile variant changed since the last call.  Synchronises. */
 ffmg_status farfield_map_batched(ffmg_handle *const *hs, int count, const double *etas, void *const *u, int n_dirs,
                                  const double *dirs, void *F);
 

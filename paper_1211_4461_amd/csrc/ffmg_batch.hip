@@ -812,6 +812,12 @@ ffmg_status farfield_map_batched(ffmg_handle *const *hs, int count, const double
                             {etas[3 * i], etas[3 * i + 1], 0.0}, h->k0, h->prob.gamma};
             key.push_back(h->serial);
         }
+        // the workspace keeps pointers into each plan (factor planes, direction
+        // order): it is rebuilt when a plan was, or a tile variant changed
+        for (ffmg_handle *h : seen) {
+            key.push_back(ff_plan_generation(h->ff));
+            key.push_back((uint64_t)ff_plan_variant(h->ff));
+        }
         key.push_back((uint64_t)n_dirs);
         for (ffmg_handle *h : seen)
             if (h->stream != h0->stream) HIPCHK(h0, hipStreamSynchronize(h->stream));

@@ -739,6 +739,7 @@ struct FarFieldPlan {
     int prec = -1;                 // ffmg_ff_precision of the built factors
     int ns = 0;                    // BF16 parts (split precisions)
     int variant = BF_DEFAULT_VARIANT;
+    uint64_t gen = 0;              // rebuilds so far (every rebuild frees and reallocates the buffers below)
     std::vector<double> dirs;      // cache key
     std::vector<int> perm;         // sorted position -> direction index
     std::vector<int> gstart;       // group start in sorted order
@@ -790,6 +791,7 @@ int ff_plan_variants() { return BF_NVARIANTS; }
 int ff_plan_default_variant() { return BF_DEFAULT_VARIANT; }
 void ff_plan_set_variant(FarFieldPlan *p, int v) { p->variant = (v >= 0 && v < BF_NVARIANTS) ? v : BF_DEFAULT_VARIANT; }
 int ff_plan_variant(const FarFieldPlan *p) { return p->variant; }
+uint64_t ff_plan_generation(const FarFieldPlan *p) { return p->gen; }
 
 #define FF_CHECK(x)                                                                                                  \
     do {                                                                                                             \
@@ -814,6 +816,7 @@ hipError_t ff_plan_prepare(FarFieldPlan *p, const LevelGeom &g, double k0, doubl
     if (p->M == M && p->dim == d && p->dirs == key && p->prec == prec) return hipSuccess;
     FF_CHECK(hipStreamSynchronize(s));
     p->release();
+    ++p->gen;
     p->dim = d;
     p->M = M;
     p->dirs = key;

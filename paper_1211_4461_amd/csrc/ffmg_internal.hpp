@@ -439,6 +439,9 @@ int ff_plan_variants();
 int ff_plan_default_variant();
 void ff_plan_set_variant(FarFieldPlan *p, int v);
 int ff_plan_variant(const FarFieldPlan *p);
+// Number of times the plan was rebuilt (its buffers freed and reallocated):
+// a workspace that keeps pointers into the plan is valid for one generation.
+uint64_t ff_plan_generation(const FarFieldPlan *p);
 void launch_axis_exp(cd *out, int m, double lo, double h, double cr, double ci, hipStream_t s);
 // FP64 MFMA contraction C[m][n] = sum_k A[m][k] S[k][n] for a complex table A
 // (M x K, row stride K) and S (K x Nc), C (M x Nc); ws: table_gemm_ws_bytes.

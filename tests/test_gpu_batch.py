@@ -161,6 +161,17 @@ def test_batch_reuse_and_far_fields(ff, orc):
     F2 = ff.farfield_map_batched(hs, etas2, us, dirs2)
     for i in range(len(insts)):
         np.testing.assert_array_equal(F2[i], ff.farfield_map(hs[i], etas2[i], us[i], dirs2))
+    # another direction set of the same size rebuilds every plan: the batched
+    # workspace, which points into the plans, is rebuilt with them (also when
+    # the plans were rebuilt in between by single maps of other directions)
+    t3 = np.arctan2(dirs2[:, 1], dirs2[:, 0]) + 0.01
+    dirs3 = np.stack([np.cos(t3), np.sin(t3)], axis=1)
+    for D in (dirs3, dirs2):
+        FB = ff.farfield_map_batched(hs, etas2, us, D)
+        for i in range(len(insts)):
+            np.testing.assert_array_equal(FB[i], ff.farfield_map(hs[i], etas2[i], us[i], D))
+        for i in range(len(insts)):
+            ff.farfield_map(hs[i], etas2[i], us[i], dirs)
     # a sub-list of the handles: rebuilt workspace, same answers
     sub = [0, 2, 4]
     us2 = [torch.empty_like(us[i]) for i in sub]
