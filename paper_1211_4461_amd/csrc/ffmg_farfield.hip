@@ -29,6 +29,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -819,8 +820,7 @@ hipError_t ff_plan_prepare(FarFieldPlan *p, const LevelGeom &g, double k0, doubl
     ++p->gen;
     p->dim = d;
     p->M = M;
-    p->dirs = key;
-    p->prec = prec;
+    p->prec = prec;   // the directions (the cache key) are recorded once the build has succeeded
     p->ns = (prec == 2) ? 3 : (prec == 1) ? 2 : 0;
     // group directions by their last component (exact equality) in 3D
     p->perm.resize(M);
@@ -977,7 +977,9 @@ hipError_t ff_plan_prepare(FarFieldPlan *p, const LevelGeom &g, double k0, doubl
         }
     }
     FF_CHECK(hipGetLastError());
-    return hipStreamSynchronize(s);
+    FF_CHECK(hipStreamSynchronize(s));
+    p->dirs = key;
+    return hipSuccess;
 }
 
 // Integrand s = q (u_in + u) (u may be null: Born term), in FP64 or as BF16
@@ -1171,10 +1173,12 @@ hipError_t ff_batch_run(FFBatch **cache, const std::vector<uint64_t> &key, const
         if (B) {
             FF_CHECK(hipStreamSynchronize(s));
             delete B;
+            *cache = nullptr;
         }
-        B = new FFBatch();
-        *cache = B;
-        B->key = key;
+        // built aside and published (with its key) only once complete, so a
+        // failed build leaves no workspace behind
+        std::unique_ptr<FFBatch> nb(new FFBatch());
+        B = nb.get();
         B->M = M;
         B->ns = in[0].plan->ns;
         B->jobs.resize(n);
@@ -1224,6 +1228,8 @@ hipError_t ff_batch_run(FFBatch **cache, const std::vector<uint64_t> &key, const
             B->gl_variant.push_back(p0->variant);
         }
         FF_CHECK(B->alloc(&B->d_jobs, (size_t)n * sizeof(FFBJob)));
+        B->key = key;
+        *cache = nb.release();
     }
     // per call: the directions' plane waves, solutions and output rows
     for (int i = 0; i < n; ++i) {
