@@ -752,6 +752,109 @@ def run_literal_gmres(ff, torch, W, reps=2):
     return out
 
 
+def run_literal_batch(ff, torch, W, lanes_per_op=1, reps=2):
+    """The batched workload as written, with its literal potential: the 96
+    instances of the schrodinger_batch law (32 directions x 3 energies, each
+    on a seed-drawn 255^2 / 511^2 / 1023^2 grid, seed 3) with the deep wells
+    (B = 2, D ~ U[0.5, 2]), solved with GMRES(3) V(1,1) smoothing in mixed
+    precision to LITERAL_TOL.  The batched kernels are weighted Jacobi only,
+    so the instances are single solves kept in flight: one handle (and
+    stream) per operator, solves begun on every free handle before the oldest
+    is finished (mg_solve_begin / mg_solve_end), then one farfield_map_batched
+    for all 96 maps.  Beside it the same maps one after another; every map of
+    the two runs is compared bit for bit."""
+    import numpy as np
+    insts = W.schrodinger_batch(seed=3)
+    dirs = insts[0].dirs
+    pots = {n: torch.from_numpy(W.schrodinger_potential(n, seed=3, deep=True)).cuda() for n in sorted({w.n for w in insts})}
+    ops, streams = {}, {}
+    for w in insts:
+        for lane in range(lanes_per_op):
+            key = (w.energy, w.n, lane)
+            if key in ops:
+                continue
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                o = ff.default_options(smoother=ff.SMOOTH_GMRES, krylov_m=3, nu1=1, nu2=1, precision=ff.FP32_IR,
+                                       ff_precision=ff.FF_BF16X6, fmg_cycles=FMG_K)
+                ops[key] = ff.mg_setup(2, [w.n, w.n], [w.lo] * 2, [w.hi] * 2, w.gamma, pots[w.n],
+                                       kind=ff.SCHRODINGER, energy=w.energy, options=o)
+            streams[key] = st
+    torch.cuda.synchronize()
+    # instances interleaved over the operators (and lanes), so that consecutive solves use different handles
+    by_op = {}
+    for i, w in enumerate(insts):
+        by_op.setdefault((w.energy, w.n), []).append(i)
+    slots = []
+    for k, idx in by_op.items():
+        for j, i in enumerate(idx):
+            slots.append((j // lanes_per_op, i, (k[0], k[1], j % lanes_per_op)))
+    order = [(i, key) for _, i, key in sorted(slots)]
+    us = [torch.empty(w.shape, dtype=torch.complex128, device="cuda") for w in insts]
+    etas = [w.eta for w in insts]
+    hs = [None] * len(insts)
+    for i, key in order:
+        hs[i] = ops[key]
+    F = torch.empty((len(insts), len(dirs)), dtype=torch.complex128, device="cuda")
+    infos = [None] * len(insts)
+
+    def in_flight():
+        pending = []   # (handle key, instance), oldest first
+        busy = set()
+        for i, key in order:
+            while key in busy:
+                k0, i0 = pending.pop(0)
+                infos[i0] = ff.mg_solve_end(ops[k0])
+                busy.discard(k0)
+            h = ops[key]
+            ff.mg_rhs_plane_wave(h, etas[i], None)
+            ff.mg_solve_begin(h, None, us[i], tol=LITERAL_TOL)
+            pending.append((key, i))
+            busy.add(key)
+        for k0, i0 in pending:
+            infos[i0] = ff.mg_solve_end(ops[k0])
+        ff.farfield_map_batched(hs, etas, us, dirs, out=F)
+
+    def one_by_one(Fs):
+        for i, key in order:
+            h = ops[key]
+            ff.mg_rhs_plane_wave(h, etas[i], None)
+            ff.mg_solve(h, None, us[i], tol=LITERAL_TOL)
+            ff.farfield_map(h, etas[i], us[i], dirs, out=Fs[i])
+
+    in_flight()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        in_flight()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    F_fl = F.clone()
+    F1 = torch.empty_like(F)
+    one_by_one(F1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one_by_one(F1)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    same = bool(torch.equal(F_fl, F1))
+    steps = [i.cycles for i in infos]
+    for h in ops.values():
+        h.destroy()
+    ns = [w.n - 1 for w in insts]
+    return {"workload": "schrodinger_batch law (96 instances: 32 directions x E in {0.5, 1, 2}, grids drawn by "
+                        "seed 3 from 255^2 / 511^2 / 1023^2) with the literal depths (B = 2, D ~ U[0.5, 2]), "
+                        "360 angles; GMRES(3) V(1,1) smoothing, FP32 cycles in FP64 refinement, full multigrid "
+                        f"start, residual reduction {LITERAL_TOL}",
+            "grids": {f"{m}^2": ns.count(m) for m in sorted(set(ns))},
+            "maps_per_s": round(len(insts) / dt, 2), "ms_per_batch": round(1e3 * dt, 3),
+            "one_after_another_maps_per_s": round(len(insts) / dt1, 2),
+            "operators": len({(w.energy, w.n) for w in insts}), "handles_per_operator": lanes_per_op,
+            "refinement_steps": [min(steps), max(steps)],
+            "max_rel_residual": max(i.rel_residual for i in infos),
+            "maps_equal_to_one_after_another": same}
+
+
 def run_learned(ff, torch, W, reps=3):
     """The learned-smoother workload: a network trained on the GPU (the
     library's kernels) from weighted Jacobi on (error, residual) patches of
@@ -1103,6 +1206,7 @@ def main():
         line["learned"] = run_learned(ffmg, torch, W)
     if not args.no_batch:
         line["literal_batch_potential_gmres"] = run_literal_gmres(ffmg, torch, W)
+        line["literal_batch_as_written"] = run_literal_batch(ffmg, torch, W, lanes_per_op=2)
     if not args.no_ion:
         line["ionization"] = run_ionization(ffmg, torch, W)
     if not args.no_cpu_baseline:

@@ -50,6 +50,8 @@ CASES = [
     ("2d-fp64", lambda: W.small_2d(n=128, M=24), dict(precision=0)),
     ("3d-fp32-fmg", lambda: W.gauss_3d(n=32, n_az=8, n_pol=4), dict(precision=1, fmg_cycles=2)),
     ("2d-gmres", lambda: W.small_2d(n=128, M=24), dict(precision=0, smoother=2, krylov_m=3, nu1=1, nu2=1)),
+    ("2d-gmres-fp32-fmg", lambda: W.bumps_2d(n=256, seed=9, M=24),
+     dict(precision=1, smoother=2, krylov_m=3, nu1=1, nu2=1, fmg_cycles=2)),
     ("2d-rbgs", lambda: W.small_2d(n=128, M=24), dict(precision=1, smoother=3, nu1=1, nu2=1)),
 ]
 
