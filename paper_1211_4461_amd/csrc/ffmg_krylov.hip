@@ -26,7 +26,9 @@
 // orthogonalisation, each finished by a one-block kernel: 4 m + 3 launches)
 // computes the same values in the same order, so both give the same bits.  Partial sums are FP64 in both
 // precisions.  A level of at most GM_BLOCK_MAX_POINTS points runs the whole
-// step in one 1024-thread workgroup.
+// step in one 1024-thread workgroup (for small m with the vectors in
+// registers and the stencil's input staged in LDS; the reference path reads
+// and writes them in global memory).
 #include "ffmg_internal.hpp"
 #include "ffmg_point.hpp"
 
@@ -551,6 +553,155 @@ __global__ __launch_bounds__(1024) void k_gm_step_block(const cx<T> *__restrict_
     }
 }
 
+// The same step with the level's vectors held in registers (thread t holds
+// the points p = t + 1024 k, k < GM_REG_PTS) and only the vector that A is
+// applied to staged in LDS (dynamic shared memory, N values): no global
+// traffic inside the step but the loads of b, q, u and the store of u.  The
+// values, the sums and their order are those of k_gm_step_block.
+constexpr int GM_REG_PTS = (int)(GM_BLOCK_MAX_POINTS / GM_BLOCK_THREADS);
+
+template <typename T, int DIM, int NJ, int M>
+__device__ __forceinline__ void gm_reg_arnoldi(cx<T> (&Z)[M + 1][GM_REG_PTS], const cx<T> (&qv)[GM_REG_PTS],
+                                               cx<T> *stage, const Stencil<T> &P, int N, double *n, double *d,
+                                               double (*red)[2 * GMRES_MAX_M])
+{
+    constexpr int j = NJ - 1;
+    // the reduction before ended with a barrier: every thread is past its reads of the stage
+#pragma unroll
+    for (int k = 0; k < GM_REG_PTS; ++k) {
+        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        if (p < N) stage[p] = Z[j][k];
+    }
+    __syncthreads();
+    double acc[2 * NJ];
+#pragma unroll
+    for (int v = 0; v < 2 * NJ; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int k = 0; k < GM_REG_PTS; ++k) {
+        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        if (p < N) {
+            const cx<T> Wp = apply_at_f<T, DIM>(P, [&](size_t i) { return stage[i]; }, Z[j][k], qv[k], (size_t)p);
+            Z[NJ][k] = Wp;
+            const double wr = Wp.re, wi = Wp.im;
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+                const cx<T> zi = Z[i][k];
+                acc[2 * i] += (double)zi.re * wr + (double)zi.im * wi;
+                acc[2 * i + 1] += (double)zi.re * wi - (double)zi.im * wr;
+            }
+        }
+    }
+    block_reduce_1024<2 * NJ>(acc, d + 2 * (j * GMRES_MAX_M), red);
+    cx<T> g[NJ];
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+        const double ni = n[i];
+        const double dr = d[2 * (j * GMRES_MAX_M + i)], di = d[2 * (j * GMRES_MAX_M + i) + 1];
+        g[i] = cx<T>{T(ni > 0.0 ? dr / ni : 0.0), T(ni > 0.0 ? di / ni : 0.0)};
+    }
+    double nacc[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < GM_REG_PTS; ++k) {
+        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        if (p < N) {
+            cx<T> v = Z[NJ][k];
+#pragma unroll
+            for (int i = 0; i < NJ; ++i) {
+                const cx<T> zi = Z[i][k];
+                v = cx<T>{v.re - (g[i].re * zi.re - g[i].im * zi.im), v.im - (g[i].re * zi.im + g[i].im * zi.re)};
+            }
+            Z[NJ][k] = v;
+            nacc[0] += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+        }
+    }
+    block_reduce_1024<1>(nacc, n + NJ, red);
+    if constexpr (NJ < M) gm_reg_arnoldi<T, DIM, NJ + 1, M>(Z, qv, stage, P, N, n, d, red);
+}
+
+template <typename T, int DIM, int M>
+__global__ __launch_bounds__(1024) void k_gm_step_reg(const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+                                                      cx<T> *__restrict__ u, int zero, Stencil<T> P, int N,
+                                                      const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    extern __shared__ __attribute__((aligned(16))) unsigned char gm_stage_raw[];
+    cx<T> *stage = reinterpret_cast<cx<T> *>(gm_stage_raw);
+    __shared__ double red[GM_BLOCK_THREADS / 64][2 * GMRES_MAX_M];
+    __shared__ double n[GMRES_MAX_M + 1], d[2 * GMRES_MAX_M * GMRES_MAX_M], c[2 * GMRES_MAX_M];
+    __shared__ GmWork W;
+    const cx<T> zc = {T(0), T(0)};
+    cx<T> qv[GM_REG_PTS], uv[GM_REG_PTS], Z[M + 1][GM_REG_PTS];
+#pragma unroll
+    for (int k = 0; k < GM_REG_PTS; ++k) {
+        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        qv[k] = uv[k] = zc;
+#pragma unroll
+        for (int j = 0; j <= M; ++j) Z[j][k] = zc;
+        if (p < N) {
+            qv[k] = q[p];
+            if (!zero) {
+                uv[k] = u[p];
+                stage[p] = uv[k];
+            }
+        }
+    }
+    __syncthreads();
+    double acc[1] = {0.0};
+#pragma unroll
+    for (int k = 0; k < GM_REG_PTS; ++k) {
+        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        if (p < N) {
+            cx<T> r = b[p];
+            if (!zero) {
+                const cx<T> Au = apply_at_f<T, DIM>(P, [&](size_t i) { return stage[i]; }, uv[k], qv[k], (size_t)p);
+                r = cx<T>{r.re - Au.re, r.im - Au.im};
+            }
+            Z[0][k] = r;
+            acc[0] += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
+        }
+    }
+    block_reduce_1024<1>(acc, n, red);
+    gm_reg_arnoldi<T, DIM, 1, M>(Z, qv, stage, P, N, n, d, red);
+    if (threadIdx.x == 0) gm_solve_small(n, d, M, c, W);
+    __syncthreads();
+    cx<T> cc[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) cc[j] = cx<T>{T(c[2 * j]), T(c[2 * j + 1])};
+#pragma unroll
+    for (int k = 0; k < GM_REG_PTS; ++k) {
+        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        if (p < N) {
+            cx<T> v = uv[k];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const cx<T> zj = Z[j][k];
+                v = cx<T>{v.re + (cc[j].re * zj.re - cc[j].im * zj.im), v.im + (cc[j].re * zj.im + cc[j].im * zj.re)};
+            }
+            u[p] = v;
+        }
+    }
+}
+
+// Whether a step on a level of at most GM_BLOCK_MAX_POINTS points keeps its
+// vectors in registers: small m (the m + 1 vectors, four points each, within
+// the 128 registers a thread of a 1024-thread workgroup has).
+template <typename T, int M>
+constexpr bool gm_reg_step() { return sizeof(T) == 4 ? M <= 4 : M <= 3; }
+
+template <typename T, int DIM, int M>
+static void launch_step_reg(const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero, const Stencil<T> &P, size_t N,
+                            hipStream_t s, const int *stop)
+{
+    static const bool attr_set = [] {
+        (void)hipFuncSetAttribute((const void *)k_gm_step_reg<T, DIM, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(GM_BLOCK_MAX_POINTS * sizeof(cx<T>)));
+        return true;
+    }();
+    (void)attr_set;
+    hipLaunchKernelGGL((k_gm_step_reg<T, DIM, M>), dim3(1), dim3(GM_BLOCK_THREADS), N * sizeof(cx<T>), s, b, q, u,
+                       zero ? 1 : 0, P, (int)N, stop);
+}
+
 template <typename T, int DIM, int NJ, int M>
 void launch_arnoldi_all(cx<T> *Z, size_t N, const cx<T> *q, const Stencil<T> &P, double *S, double *parts, int nb,
                         hipStream_t s, const int *stop)
@@ -586,6 +737,12 @@ void launch_step_m(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, cons
 {
     const size_t N = g.N();
     if (N <= GM_BLOCK_MAX_POINTS) {   // small level: the whole step in one workgroup
+        if constexpr (gm_reg_step<T, M>()) {
+            if (fused) {
+                launch_step_reg<T, DIM, M>(b, q, u, zero, P, N, s, stop);
+                return;
+            }
+        }
         hipLaunchKernelGGL((k_gm_step_block<T, DIM, M>), dim3(1), dim3(GM_BLOCK_THREADS), 0, s, b, q, u,
                            zero ? 1 : 0, Z, P, N, stop);
         return;
