@@ -938,6 +938,30 @@ def run_learned(ff, torch, W, reps=3):
 
 
 # ---------------------------------------------------------------------------
+# A plain device copy on the same GPU: what streaming HBM traffic reaches here
+
+def copy_rate(torch, gib=1, reps=5):
+    """Bytes read + written per second (GB/s, best of reps) by a device copy
+    of `gib` GiB (torch y.copy_(x)), timed with events on the current stream."""
+    n = (gib << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        y.copy_(x)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * (gib << 30) / (best * 1e-3) / 1e9
+
+
+# ---------------------------------------------------------------------------
 # CPU baseline (child process: the oracle, built for this host)
 
 def cpu_model():
@@ -1126,6 +1150,10 @@ def main():
                 "ranked_by": "largest time per map among the bracketed finest-level kernels; "
                              "profiles/kernels_gauss3d_512_mixed.md ranks every kernel of a map (rocprofv3)",
                 "working_set": "HBM-resident: one FP32 field is 1.07 GB, far above the 256 MB Infinity Cache"}
+        cr = copy_rate(torch)
+        roof["device_copy_GBs"] = round(cr, 1)
+        roof["frac_of_device_copy"] = round(dk["GB_s"] / cr, 4)
+        roof["device_copy"] = "1 GiB torch copy on this GPU, read + write bytes over the best of 5 event-timed copies"
         line = {
             "metric": "far-field maps/sec at 1e-6 rel error: plain FP64 MG vs mixed-prec/learned MG",
             "value": round(mixed["maps_per_s"], 3),
