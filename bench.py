@@ -92,7 +92,7 @@ TRAFFIC = {3: (os.path.join(ROOT, "profiles", "traffic_gauss3d_512.json"), os.pa
 TRAFFIC_FILE, STENCIL_SRC = TRAFFIC[2]
 
 # PROF_* ids of the kernels the library brackets (mg_profile_*)
-KERNELS = {"pre": 0, "ff": 1, "post": 2, "refine": 3, "ffgemm": 4, "net": 5, "rr": 6}
+KERNELS = {"pre": 0, "ff": 1, "post": 2, "refine": 3, "ffgemm": 4, "net": 5, "rr": 6, "srr": 7, "srr0": 8}
 # Algorithmic bytes per finest-level point of the bracketed kernels (complex
 # values: FP32 8 B, FP64 16 B; the coarse level has 1/8 (3D) or 1/4 (2D) of
 # the points):
@@ -103,12 +103,17 @@ KERNELS = {"pre": 0, "ff": 1, "post": 2, "refine": 3, "ffgemm": 4, "net": 5, "rr
 # from a guess, 4e) and is reported, not ranked.
 # (the refinement pass forms the plane-wave right-hand side from q instead of
 # reading it: read u, q (16 B each), d (8); write u, r (16 + 8))
-BPP = {3: {"mixed": {"post": 33.0, "rr": 25.0, "refine": 64.0}, "plain": {"post": 66.0, "rr": 50.0}},
+BPP = {3: {"mixed": {"post": 33.0, "rr": 25.0, "refine": 64.0, "srr": 33.0, "srr0": 25.0},
+           "plain": {"post": 66.0, "rr": 50.0}},
        2: {"mixed": {"post": 34.0, "refine": 64.0}, "plain": {"post": 68.0}}}
 KERNEL_NAMES = {
     3: {"post": "k_sweep2_3d<%s, SRC_PROL> (finest level: interpolation of the coarse correction + two Jacobi sweeps "
                 "in one z-marching pass)",
         "rr": "k_resid_restrict3d<%s> (finest level: residual + full weighting in one pass)",
+        "srr": "k_sweep2rr_3d<%s, from a guess> (finest level: two Jacobi sweeps + residual + full weighting in one "
+               "z-marching pass)",
+        "srr0": "k_sweep2rr_3d<%s, from zero> (finest level: two Jacobi sweeps from a zero guess + residual + full "
+                "weighting in one z-marching pass)",
         "refine": "k_refine3d<true> (FP64 update + residual of the refinement step, one pass; the plane-wave "
                   "right-hand side formed from q)",
         "pre": "k_sweep2_3d<%s, SRC_ZERO2 / SRC_MEM> (finest level: two Jacobi sweeps per pass)"},
@@ -289,7 +294,7 @@ def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp, to
     one()
     torch.cuda.synchronize()
     mask = 0
-    for k in ("pre", "post", "refine", "rr", "ff", "ffgemm"):
+    for k in ("pre", "post", "refine", "rr", "srr", "srr0", "ff", "ffgemm"):
         mask |= 1 << KERNELS[k]
     ff.mg_profile_enable(h, mask)
     for k in KERNELS.values():
@@ -298,7 +303,7 @@ def kernel_pass(ff, torch, w, precision, ff_precision, maps, fmg_cycles, bpp, to
         info = one()
     torch.cuda.synchronize()
     stats = {}
-    for name in ("pre", "post", "refine", "rr", "ff", "ffgemm"):
+    for name in ("pre", "post", "refine", "rr", "srr", "srr0", "ff", "ffgemm"):
         d = ff.mg_profile_durations(h, KERNELS[name])
         if d.size == 0:
             continue

@@ -444,7 +444,10 @@ ffmg_status mg_residual_norm(ffmg_handle *h, const void *b, const void *u, doubl
  * interpolation + post-smoothing, 3 FP64 update + residual of the
  * mixed-precision refinement, 4 the far-field GEMM stages alone, 5 the
  * learned smoother's network on the finest level, 6 the finest-level
- * residual + restriction (3D).  mask = 0 disables.  mg_profile_read
+ * residual + restriction (3D), 7 and 8 the finest-level pass of two
+ * pre-smoothing sweeps, the residual and its full weighting (3D,
+ * FFMG_TUNE_SWEEP3D variant 4; 7 from a guess, 8 from a zero guess, whose
+ * launches are then not counted under 0 and 6).  mask = 0 disables.  mg_profile_read
  * synchronises, returns the summed duration (ms) and launch count of one
  * kernel, and clears its record.  mg_profile_durations does the same but
  * writes each launch's duration (ms, in launch order) into ms[0 .. cap - 1]
@@ -480,8 +483,9 @@ ffmg_status mg_profile_durations(ffmg_handle *h, int kernel, double *ms, int64_t
  * with 64-point-wide tiles of 8 rows in FP32 and 4 in FP64 (variant 0) or 16
  * and 8 (variant 2), 32-point-wide tiles of 16 and 8 rows for the pass that
  * interpolates the coarse correction and the variant-0 tiles for the others
- * (variant 3), or one pass per sweep (variant 1); one variant for 2D and
- * tile_config 1.
+ * (variant 3), variant 3 with the two FP32 pre-smoothing sweeps, the residual
+ * and its full weighting in one pass (variant 4; FP64 levels as variant 3),
+ * or one pass per sweep (variant 1); one variant for 2D and tile_config 1.
  * FFMG_TUNE_BATCH (set on the first handle of a batch, 2D FFMG_FP32_IR fused
  * handles): the tile heights of mg_solve_batched's smoothing and one-pass
  * pre-smoothing launches, (8, 16) rows (variant 0), (4, 16) (1), (16, 16) (2)

@@ -812,15 +812,30 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
         // t, coarse correction, interpolation fused into post-smoothing t -> u
         cx<T> *t = LP::t(lv), *scratch = LP::r(lv);
         cx<T> *cur = u;
+        bool restricted = false;
         if (nu1 > 0) {
-            smooth_chain3d<T>(h, lv, b, u, t, scratch, nu1, zero_guess, nullptr, PROF_PRE, stop);
+            if constexpr (sizeof(T) == 4) {
+                // variant 4: the two pre-smoothing sweeps, the residual and its
+                // full weighting in one pass
+                if (nu1 == 2 && h->sweep3d_variant == 4 && sweep2rr_3d_fits(lv.g)) {
+                    const int pk = zero_guess ? PROF_SRR0 : PROF_SRR;
+                    const int pi = (l == 0) ? prof_begin(h, pk) : -1;
+                    launch_sweep2rr_3d<T>(lv.g, LP::P(lv), zero_guess ? nullptr : u, b, LP::q(lv), t, LP::b(lc),
+                                          h->stream, stop);
+                    prof_end(h, pk, pi);
+                    restricted = true;
+                }
+            }
+            if (!restricted) smooth_chain3d<T>(h, lv, b, u, t, scratch, nu1, zero_guess, nullptr, PROF_PRE, stop);
             cur = t;
         } else if (zero_guess) {
             launch_zero<T>(u, lv.g.N(), h->stream, stop);
         }
-        const int pr = (l == 0) ? prof_begin(h, PROF_RR) : -1;
-        launch_resid_restrict3d<T>(lv.g, LP::P(lv), cur, b, LP::q(lv), LP::b(lc), h->stream, stop);
-        prof_end(h, PROF_RR, pr);
+        if (!restricted) {
+            const int pr = (l == 0) ? prof_begin(h, PROF_RR) : -1;
+            launch_resid_restrict3d<T>(lv.g, LP::P(lv), cur, b, LP::q(lv), LP::b(lc), h->stream, stop);
+            prof_end(h, PROF_RR, pr);
+        }
         vcycle<T>(h, l + 1, LP::b(lc), LP::u(lc), true, stop);
         if (nu2 > 0) {
             smooth_chain3d<T>(h, lv, b, cur, u, scratch, nu2, false, LP::u(lc), PROF_POST, stop);
@@ -1670,7 +1685,7 @@ int mg_tune_variants(const ffmg_handle *h, int tunable)
     case FFMG_TUNE_PRE: return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? 3 : 1;
     case FFMG_TUNE_SMOOTH_COARSE:
         return (h->prob.dim == 2 && h->opt.tile_config != TILE_REFERENCE) ? SMOOTH_VARIANTS : 1;
-    case FFMG_TUNE_SWEEP3D: return (h->prob.dim == 3 && h->opt.tile_config != TILE_REFERENCE) ? 4 : 1;
+    case FFMG_TUNE_SWEEP3D: return (h->prob.dim == 3 && h->opt.tile_config != TILE_REFERENCE) ? 5 : 1;
     case FFMG_TUNE_BATCH:
         return (h->prob.dim == 2 && h->opt.precision == FFMG_FP32_IR && h->opt.tile_config == TILE_FUSED)
                    ? BATCH_TUNE_VARIANTS

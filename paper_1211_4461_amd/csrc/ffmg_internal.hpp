@@ -29,7 +29,9 @@ enum ProfKernel {
     PROF_FFGEMM = 4,   // far-field GEMM stages alone
     PROF_NET = 5,      // learned-smoother network application (finest level)
     PROF_RR = 6,       // finest-level residual + full-weighting restriction (3D)
-    PROF_N = 7
+    PROF_SRR = 7,      // finest-level pre-smoothing pair from a guess + residual + restriction in one pass (3D)
+    PROF_SRR0 = 8,     // the same from a zero guess
+    PROF_N = 9
 };
 
 // Device-resident state of one solve (residual-reduction stopping test of
@@ -208,11 +210,18 @@ void launch_refine3d_start(const LevelGeom &g, const Stencil<double> &P, const c
 void launch_resid_pw(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *q, cf *r32,
                      const SolveCtl *ctl, double *partial, const cd *pwf, hipStream_t s);
 // two Jacobi sweeps in one 3D pass from u (ec: from u + P ec; zero: from a zero guess, u not read);
-// shape: the tile, as FFMG_TUNE_SWEEP3D variants 0, 2, 3 (the same bits with every tile)
+// shape: the tile, as FFMG_TUNE_SWEEP3D variants 0, 2, 3 and 4 (the same bits with every tile)
 template <typename T>
 void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec, const cx<T> *b,
                       const cx<T> *q, cx<T> *out, hipStream_t s, bool finest, const int *stop, bool zero = false,
                       int shape = 0);
+// two Jacobi sweeps from u (null: from a zero guess) into out, then the
+// residual of the result and its full weighting into bc, in one 3D pass (FP32;
+// the bits of launch_sweep2_3d followed by launch_resid_restrict3d)
+bool sweep2rr_3d_fits(const LevelGeom &g);
+template <typename T>
+void launch_sweep2rr_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b, const cx<T> *q,
+                        cx<T> *out, cx<T> *bc, hipStream_t s, const int *stop);
 void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
                          cf *r32, double inv_scale, double *partial, hipStream_t s);
 void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,

@@ -1053,7 +1053,7 @@ void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, c
 {
     if (shape == 2)
         launch_sweep2_3d_tile<T, sweep2_rows<T>(2), sweep2_width(2)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
-    else if (shape == 3 && ec && !zero)
+    else if ((shape == 3 || shape == 4) && ec && !zero)
         launch_sweep2_3d_tile<T, sweep2_rows<T>(3), sweep2_width(3)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
     else
         launch_sweep2_3d_tile<T, sweep2_rows<T>(0), sweep2_width(0)>(g, P, u, ec, b, q, out, s, finest, stop, zero);
@@ -1340,6 +1340,276 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restric
         }
     }
 }
+
+// Pre-smoothing + residual + full weighting in one z-marching pass (the 3D
+// form of k_smooth_rr2d): two weighted-Jacobi sweeps from u (or from a zero
+// guess), written to out on the block's tile, then the residual of the
+// smoothed iterate and its full weighting into the coarse right-hand side.
+// A block owns a fine tile of TXW x TY points (x0 and y0 even) and tz fine
+// planes (tz even), and so the coarse tile of TXW/2 x TY/2 points and tz/2
+// planes whose full weighting reads the fine residual on [x0, x0 + TXW] x
+// [y0, y0 + TY] (one point beyond the tile on the high sides).  Five stages
+// march up through the planes, each a plane behind the one before:
+//   stage 0  the input at plane z (u; nothing from a zero guess),
+//   stage 1  the first sweep at z - 1 (region: the residual's plus 2),
+//   stage 2  the second sweep at z - 2 (plus 1), written out on the tile,
+//   stage 3  the residual at z - 3 (the residual region) into an LDS plane,
+//   stage 4  the residual plane z - 4 weighted into the coarse plane it
+//            belongs to: one running sum per coarse point, the planes 2K,
+//            2K + 1, 2K + 2 in turn, written when 2K + 2 is added.
+// Every stage's current plane goes through LDS (two buffers by parity, one
+// barrier per plane); each thread keeps its columns' last three planes of
+// stages 0-2 and the b, q of the planes stages 1-3 take in registers.  The
+// sweeps are those of k_sweep2_3d and the residual and the weighted sum
+// (terms and order) those of k_resid_restrict3d, so out and bc are bit for
+// bit those of the two passes.
+template <typename T, bool ZERO, int TY, int TXW>
+__global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+                                                     const cx<T> *__restrict__ q, cx<T> *__restrict__ out,
+                                                     cx<T> *__restrict__ bc, Stencil<T> P, int tiles_x, int tiles_y,
+                                                     int tz, const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    constexpr int W = TXW + 7, H = TY + 7, NP = W * H, NS = (NP + 255) / 256;
+    constexpr int RW = TXW + 1, RH = TY + 1;          // the fine residual region
+    constexpr int CXN = TXW / 2, CYN = TY / 2;        // the coarse tile
+    static_assert(CXN * CYN <= 256, "one coarse point per thread");
+    __shared__ cx<T> L0[ZERO ? 1 : 2][ZERO ? 1 : NP], L1[2][NP], L2[2][NP];
+    __shared__ cx<T> R[2][RH * RW];
+    const int mx = P.mx, my = P.my, mz = P.mz;
+    const int mxc = (mx - 1) / 2, myc = (my - 1) / 2, mzc = (mz - 1) / 2;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int txi = tile % tiles_x, rest = tile / tiles_x;
+    const int tyi = rest % tiles_y, tzi = rest / tiles_y;
+    const int x0 = txi * TXW, y0 = tyi * TY, z0 = tzi * tz, z1 = min(z0 + tz, mz);
+    const size_t plane = (size_t)mx * my;
+    const cx<T> zero = {T(0), T(0)};
+    const T w3[3] = {T(0.25), T(0.5), T(0.25)};
+
+    // slot k: region row r, column c, grid point (x0 - 3 + c, y0 - 3 + r)
+    int ofs[NS];
+    unsigned offu[NS], offbq[NS];
+    unsigned ing = 0, st1 = 0, st2 = 0, st3 = 0, own = 0;
+    int rofs[NS];   // index of the slot in the residual plane (stage 3)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int t = threadIdx.x + 256 * k;
+        const int r = t / W, c = t - r * W;
+        const int gx = x0 - 3 + c, gy = y0 - 3 + r;
+        const bool v = t < NP;
+        const bool in = v && gx >= 0 && gx < mx && gy >= 0 && gy < my;
+        const bool s1 = v && r >= 1 && r < H - 1 && c >= 1 && c < W - 1;
+        ofs[k] = in ? gy * mx + gx : 0;
+        offu[k] = in ? (unsigned)ofs[k] * (unsigned)sizeof(cx<T>) : BUF_OOB;
+        offbq[k] = (in && s1) ? offu[k] : BUF_OOB;
+        ing |= (unsigned)in << k;
+        st1 |= (unsigned)s1 << k;
+        st2 |= (unsigned)(v && r >= 2 && r < H - 2 && c >= 2 && c < W - 2) << k;
+        st3 |= (unsigned)(v && r >= 3 && r < H - 3 && c >= 3 && c < W - 3) << k;
+        own |= (unsigned)(in && r >= 3 && r < 3 + TY && c >= 3 && c < 3 + TXW) << k;
+        rofs[k] = (r - 3) * RW + (c - 3);
+    }
+    auto slot_in = [&](unsigned m, int k) { return ((m >> k) & 1u) != 0u; };
+    const unsigned pbytes = (unsigned)(plane * sizeof(cx<T>));
+
+    cx<T> pu[NS], pb[NS], pq[NS];
+    auto fetch_u = [&](int z) {
+        const bool zin = z >= 0 && z < mz;
+        const auto ru = buf_rsrc(u + (zin ? (size_t)z * plane : 0), zin ? pbytes : 0u);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) pu[k] = ld_buf<T>(ru, offu[k]);
+    };
+    auto fetch_bq = [&](int z) {
+        const bool zin = z >= 0 && z < mz;
+        const size_t o = zin ? (size_t)z * plane : 0;
+        const auto rb = buf_rsrc(b + o, zin ? pbytes : 0u), rq = buf_rsrc(q + o, zin ? pbytes : 0u);
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            pb[k] = ld_buf<T>(rb, offbq[k]);
+            pq[k] = ld_buf<T>(rq, offbq[k]);
+        }
+    };
+
+    // the coarse point of this thread (stage 4) and its running sum
+    const int cyy = (int)threadIdx.x / CXN, cxx = (int)threadIdx.x - cyy * CXN;
+    const int ci = x0 / 2 + cxx, cj = y0 / 2 + cyy;
+    const bool cown = (int)threadIdx.x < CXN * CYN && ci < mxc && cj < myc;
+    cx<T> cacc = zero;
+
+    const int zb = z0 - 3, ze = z0 + tz + 4;   // input planes of the march (stage 4 ends at z0 + tz)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) pu[k] = pb[k] = pq[k] = zero;
+    if (!ZERO) fetch_u(zb);
+
+    cx<T> a0[NS], a1[NS], a2[NS];   // stage 0 at planes z - 2, z - 1, z
+    cx<T> c0[NS], c1[NS], c2[NS];   // stage 1 at planes z - 3, z - 2, z - 1
+    cx<T> e0[NS], e1[NS], e2[NS];   // stage 2 at planes z - 4, z - 3, z - 2
+    cx<T> bB[NS], qB[NS];           // b, q at plane z - 2 (stage 2)
+    cx<T> b3[NS], q3[NS];           // b, q at plane z - 3 (stage 3)
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        a0[k] = a1[k] = a2[k] = zero;
+        c0[k] = c1[k] = c2[k] = zero;
+        e0[k] = e1[k] = e2[k] = zero;
+        bB[k] = qB[k] = b3[k] = q3[k] = zero;
+    }
+    for (int z = zb; z <= ze; ++z) {
+        cx<T> un[NS], bn[NS], qn[NS];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            un[k] = pu[k];
+            bn[k] = pb[k];
+            qn[k] = pq[k];
+        }
+        if (!ZERO && z + 1 <= z0 + tz + 3) fetch_u(z + 1);
+        if (z >= z0 - 2 && z <= z0 + tz + 2) fetch_bq(z);   // b, q of plane z: stage 1 of the next iteration
+        // stage 0: the input at plane z
+        if (!ZERO) {
+            cx<T> *l0w = L0[z & 1];
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int t = threadIdx.x + 256 * k;
+                a0[k] = a1[k];
+                a1[k] = a2[k];
+                a2[k] = un[k];
+                if (t < NP) l0w[t] = un[k];
+            }
+        }
+        // stage 1: the first sweep at plane p1 = z - 1
+        const int p1 = z - 1;
+        if (p1 >= z0 - 2 && p1 <= z0 + tz + 2) {
+            const cx<T> *l0r = L0[ZERO ? 0 : (p1 & 1)];
+            cx<T> *l1w = L1[p1 & 1];
+            const bool pin = p1 >= 0 && p1 < mz;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int t = threadIdx.x + 256 * k;
+                c0[k] = c1[k];
+                c1[k] = c2[k];
+                cx<T> v = zero;
+                if (pin && slot_in(ing & st1, k)) {
+                    const cx<T> wj = jweight(P, qn[k]);
+                    if (ZERO) {
+                        v = jacobi0_w(bn[k], wj);
+                    } else {
+                        cx<T> N = nsum_xy(P, l0r[t - 1], l0r[t + 1], l0r[t - W], l0r[t + W]);
+                        N = nsum_add_z(P, N, a0[k], a2[k]);
+                        v = jacobi_n(P, N, a1[k], bn[k], wj);
+                    }
+                }
+                c2[k] = v;
+                if (slot_in(st1, k)) l1w[t] = v;
+            }
+        }
+        // stage 2: the second sweep at plane p2 = z - 2, written out on the tile
+        const int p2 = z - 2;
+        if (p2 >= z0 - 1 && p2 <= z0 + tz + 1) {
+            const cx<T> *l1r = L1[p2 & 1];
+            cx<T> *l2w = L2[p2 & 1];
+            const bool pin = p2 >= 0 && p2 < mz;
+            const bool wr = p2 >= z0 && p2 < z1;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int t = threadIdx.x + 256 * k;
+                e0[k] = e1[k];
+                e1[k] = e2[k];
+                cx<T> v = zero;
+                if (pin && slot_in(ing & st2, k)) {
+                    cx<T> N = nsum_xy(P, l1r[t - 1], l1r[t + 1], l1r[t - W], l1r[t + W]);
+                    N = nsum_add_z(P, N, c0[k], c2[k]);
+                    v = jacobi_n(P, N, c1[k], bB[k], jweight(P, qB[k]));
+                    if (wr && slot_in(own, k)) out[(size_t)p2 * plane + ofs[k]] = v;
+                }
+                e2[k] = v;
+                if (slot_in(st2, k)) l2w[t] = v;
+            }
+        }
+        // stage 3: the residual at plane p3 = z - 3 (zero outside the grid)
+        const int p3 = z - 3;
+        if (p3 >= z0 && p3 <= z0 + tz) {
+            const cx<T> *l2r = L2[p3 & 1];
+            cx<T> *rw = R[p3 & 1];
+            const bool pin = p3 < mz;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) {
+                const int t = threadIdx.x + 256 * k;
+                if (slot_in(st3, k)) {
+                    cx<T> r = zero;
+                    if (pin && slot_in(ing, k)) {
+                        const cx<T> uc = e1[k];
+                        cx<T> lap = lap_xy(P, uc, l2r[t - 1], l2r[t + 1], l2r[t - W], l2r[t + W]);
+                        lap = lap_add_z(P, lap, uc, e0[k], e2[k]);
+                        r = resid_from(P, lap, uc, b3[k], q3[k]);
+                    }
+                    rw[rofs[k]] = r;
+                }
+            }
+        }
+        // stage 4: residual plane p4 = z - 4 into the running coarse sums:
+        // plane 2K + 2 ends coarse plane K, 2K starts it, 2K + 1 is its middle
+        const int p4 = z - 4;
+        if (p4 >= z0 && p4 <= z0 + tz && cown) {
+            const cx<T> *rr = R[p4 & 1];
+            const int odd = p4 & 1;
+            if (!odd && p4 > z0) {   // dz = +1 of K = p4 / 2 - 1, then K is complete
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx)
+                        cacc = cacc + ((w3[dx + 1] * w3[dy + 1]) * w3[2]) * rr[(2 * cyy + 1 + dy) * RW + 2 * cxx + 1 + dx];
+                const int K = p4 / 2 - 1;
+                if (K < mzc) bc[((size_t)K * myc + cj) * mxc + ci] = cacc;
+            }
+            if (!odd && p4 < z0 + tz) {   // dz = -1 of K = p4 / 2: a new sum
+                cacc = zero;
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx)
+                        cacc = cacc + ((w3[dx + 1] * w3[dy + 1]) * w3[0]) * rr[(2 * cyy + 1 + dy) * RW + 2 * cxx + 1 + dx];
+            }
+            if (odd) {   // dz = 0
+#pragma unroll
+                for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+                    for (int dx = -1; dx <= 1; ++dx)
+                        cacc = cacc + ((w3[dx + 1] * w3[dy + 1]) * w3[1]) * rr[(2 * cyy + 1 + dy) * RW + 2 * cxx + 1 + dx];
+            }
+        }
+        // b, q move one stage on: plane z - 1 serves stage 2, z - 2 stage 3 next iteration
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            b3[k] = bB[k];
+            q3[k] = qB[k];
+            bB[k] = bn[k];
+            qB[k] = qn[k];
+        }
+        lds_barrier();
+    }
+}
+
+// Tile of the fused pre-smoothing + residual + restriction pass.
+constexpr int SRR3_TXW = 32, SRR3_TY = 8;   // measured at 511^3: 32 x 8, 32 x 12 and 16 x 16 alike, 32 x 16 (two waves per SIMD) and 48 x 8 slower
+
+bool sweep2rr_3d_fits(const LevelGeom &g) { return g.dim == 3 && g.m[0] >= 3 && g.m[1] >= 3 && g.m[2] >= 3; }
+
+template <typename T>
+void launch_sweep2rr_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b, const cx<T> *q,
+                        cx<T> *out, cx<T> *bc, hipStream_t s, const int *stop)
+{
+    const int tx = (g.m[0] + SRR3_TXW - 1) / SRR3_TXW, ty = (g.m[1] + SRR3_TY - 1) / SRR3_TY;
+    int tz = planes_per_block((long)tx * ty, g.m[2], TZ3);
+    tz = std::max(2, tz & ~1);   // even: the coarse planes of a block are whole
+    const int nb = tx * ty * ((g.m[2] + tz - 1) / tz);
+    if (!u)
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, true, SRR3_TY, SRR3_TXW>), dim3(nb), dim3(256), 0, s, b, b, q, out, bc, P,
+                           tx, ty, tz, stop);
+    else
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, false, SRR3_TY, SRR3_TXW>), dim3(nb), dim3(256), 0, s, u, b, q, out, bc,
+                           P, tx, ty, tz, stop);
+}
+template void launch_sweep2rr_3d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *, const cf *,
+                                        cf *, cf *, hipStream_t, const int *);
 
 template <typename T>
 void launch_resid_restrict3d(const LevelGeom &f, const Stencil<T> &P, const cx<T> *u, const cx<T> *b, const cx<T> *q,

@@ -590,7 +590,7 @@ def mg_destroy(h: Handle):
 KERNEL_SWEEP, KERNEL_FARFIELD = 0, 1
 
 
-PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE, PROF_FFGEMM, PROF_NET, PROF_RR = 0, 1, 2, 3, 4, 5, 6
+PROF_PRE, PROF_FF, PROF_POST, PROF_REFINE, PROF_FFGEMM, PROF_NET, PROF_RR, PROF_SRR, PROF_SRR0 = range(9)
 
 
 def mg_profile_durations(h: Handle, kernel, cap=1 << 16):
@@ -603,7 +603,7 @@ def mg_profile_durations(h: Handle, kernel, cap=1 << 16):
     return buf[: min(n.value, cap)].copy()
 
 
-def mg_profile_enable(h: Handle, mask=0x7F):
+def mg_profile_enable(h: Handle, mask=0x1FF):
     """Time kernel k when bit k of mask is set (0 disables)."""
     h._check(lib().mg_profile_enable(h.ptr, int(mask)), "mg_profile_enable")
 

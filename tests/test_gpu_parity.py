@@ -312,8 +312,9 @@ def test_fused_3d_path_is_bitwise_identical(ff, orc, n):
     """The fused 3D sweeps (two sweeps from a zero guess in one pass; two
     sweeps from a nonzero guess in one pass with the first sweep's planes in
     LDS with any of three tile shapes, or one pass per sweep; the
-    interpolation formed inside the first
-    post-smoothing pass) and the one-pass FP64 refinement step (update +
+    interpolation formed inside the first post-smoothing pass; the FP32
+    pre-smoothing pair, residual and full weighting in one pass) and the
+    one-pass FP64 refinement step (update +
     residual, iterate ping-ponged between two buffers) perform the per-point
     arithmetic of the one-operation kernels: iterates agree bit for bit with
     the reference path, for FP64 V-cycles with several (nu1, nu2) and for
@@ -326,9 +327,9 @@ def test_fused_3d_path_is_bitwise_identical(ff, orc, n):
         ur = torch.zeros_like(b)
         for _ in range(2):
             ff.mg_vcycle(hr, b, ur)
-        for v in range(4):
+        for v in range(5):
             hf, _, _, _, _, _ = setup(ff, orc, w, nu1=nu1, nu2=nu2)
-            assert ff.mg_tune_variants(hf, ff.TUNE_SWEEP3D) == 4
+            assert ff.mg_tune_variants(hf, ff.TUNE_SWEEP3D) == 5
             ff.mg_tune_set(hf, v, ff.TUNE_SWEEP3D)
             uf = torch.zeros_like(b)
             for _ in range(2):
@@ -339,7 +340,7 @@ def test_fused_3d_path_is_bitwise_identical(ff, orc, n):
         hr, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, tile_config=1, fmg_cycles=fk)
         ur = torch.zeros_like(b)
         i2 = ff.mg_solve(hr, b, ur)
-        for v in range(4):
+        for v in range(5):
             hf, _, _, _, _, _ = setup(ff, orc, w, precision=ff.FP32_IR, fmg_cycles=fk)
             ff.mg_tune_set(hf, v, ff.TUNE_SWEEP3D)
             for rep in range(2):          # the second solve starts from the other buffer when the count is odd
