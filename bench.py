@@ -141,9 +141,14 @@ def measured_traffic(kernel, key, dim=2):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("src_sha") != src_hash(src) or t.get("kernel") != kernel:
+    if t.get("src_sha") != src_hash(src):
         return None
-    v = t.get("per_tile_rows", {}).get(str(key))
+    if "per_kernel" in t:   # records of several kernels of one source
+        v = t["per_kernel"].get(kernel, {}).get(str(key))
+    elif t.get("kernel") == kernel:
+        v = t.get("per_tile_rows", {}).get(str(key))
+    else:
+        v = None
     return None if v is None else v.get("bytes_per_launch")
 
 

@@ -821,7 +821,7 @@ void vcycle(ffmg_handle *h, int l, const cx<T> *b, cx<T> *u, bool zero_guess, co
                     const int pk = zero_guess ? PROF_SRR0 : PROF_SRR;
                     const int pi = (l == 0) ? prof_begin(h, pk) : -1;
                     launch_sweep2rr_3d<T>(lv.g, LP::P(lv), zero_guess ? nullptr : u, b, LP::q(lv), t, LP::b(lc),
-                                          h->stream, stop);
+                                          h->stream, l == 0, stop);
                     prof_end(h, pk, pi);
                     restricted = true;
                 }

@@ -221,7 +221,7 @@ void launch_sweep2_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, c
 bool sweep2rr_3d_fits(const LevelGeom &g);
 template <typename T>
 void launch_sweep2rr_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b, const cx<T> *q,
-                        cx<T> *out, cx<T> *bc, hipStream_t s, const int *stop);
+                        cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop);
 void launch_resid_to_f32(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,
                          cf *r32, double inv_scale, double *partial, hipStream_t s);
 void launch_resid_to_f32_ctl(const LevelGeom &g, const Stencil<double> &P, const cd *u, const cd *b, const cd *q,

@@ -1363,7 +1363,8 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restric
 // sweeps are those of k_sweep2_3d and the residual and the weighted sum
 // (terms and order) those of k_resid_restrict3d, so out and bc are bit for
 // bit those of the two passes.
-template <typename T, bool ZERO, int TY, int TXW>
+// TAG: 1 for the finest level (a symbol of its own in profiles), else 0.
+template <typename T, bool ZERO, int TY, int TXW, int TAG>
 __global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
                                                      const cx<T> *__restrict__ q, cx<T> *__restrict__ out,
                                                      cx<T> *__restrict__ bc, Stencil<T> P, int tiles_x, int tiles_y,
@@ -1595,21 +1596,27 @@ bool sweep2rr_3d_fits(const LevelGeom &g) { return g.dim == 3 && g.m[0] >= 3 && 
 
 template <typename T>
 void launch_sweep2rr_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b, const cx<T> *q,
-                        cx<T> *out, cx<T> *bc, hipStream_t s, const int *stop)
+                        cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop)
 {
     const int tx = (g.m[0] + SRR3_TXW - 1) / SRR3_TXW, ty = (g.m[1] + SRR3_TY - 1) / SRR3_TY;
     int tz = planes_per_block((long)tx * ty, g.m[2], TZ3);
     tz = std::max(2, tz & ~1);   // even: the coarse planes of a block are whole
     const int nb = tx * ty * ((g.m[2] + tz - 1) / tz);
-    if (!u)
-        hipLaunchKernelGGL((k_sweep2rr_3d<T, true, SRR3_TY, SRR3_TXW>), dim3(nb), dim3(256), 0, s, b, b, q, out, bc, P,
-                           tx, ty, tz, stop);
-    else
-        hipLaunchKernelGGL((k_sweep2rr_3d<T, false, SRR3_TY, SRR3_TXW>), dim3(nb), dim3(256), 0, s, u, b, q, out, bc,
+    if (!u && finest)
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, true, SRR3_TY, SRR3_TXW, 1>), dim3(nb), dim3(256), 0, s, b, b, q, out, bc,
                            P, tx, ty, tz, stop);
+    else if (!u)
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, true, SRR3_TY, SRR3_TXW, 0>), dim3(nb), dim3(256), 0, s, b, b, q, out, bc,
+                           P, tx, ty, tz, stop);
+    else if (finest)
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, false, SRR3_TY, SRR3_TXW, 1>), dim3(nb), dim3(256), 0, s, u, b, q, out,
+                           bc, P, tx, ty, tz, stop);
+    else
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, false, SRR3_TY, SRR3_TXW, 0>), dim3(nb), dim3(256), 0, s, u, b, q, out,
+                           bc, P, tx, ty, tz, stop);
 }
 template void launch_sweep2rr_3d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *, const cf *,
-                                        cf *, cf *, hipStream_t, const int *);
+                                        cf *, cf *, hipStream_t, bool, const int *);
 
 template <typename T>
 void launch_resid_restrict3d(const LevelGeom &f, const Stencil<T> &P, const cx<T> *u, const cx<T> *b, const cx<T> *q,
