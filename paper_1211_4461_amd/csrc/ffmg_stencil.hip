@@ -1364,17 +1364,17 @@ __global__ __launch_bounds__(256) void k_resid_restrict3d(const cx<T> *__restric
 // (terms and order) those of k_resid_restrict3d, so out and bc are bit for
 // bit those of the two passes.
 // TAG: 1 for the finest level (a symbol of its own in profiles), else 0.
-template <typename T, bool ZERO, int TY, int TXW, int TAG>
-__global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
+template <typename T, bool ZERO, int TY, int TXW, int TAG, int NT>
+__global__ __launch_bounds__(NT) void k_sweep2rr_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ b,
                                                      const cx<T> *__restrict__ q, cx<T> *__restrict__ out,
                                                      cx<T> *__restrict__ bc, Stencil<T> P, int tiles_x, int tiles_y,
                                                      int tz, const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    constexpr int W = TXW + 7, H = TY + 7, NP = W * H, NS = (NP + 255) / 256;
+    constexpr int W = TXW + 7, H = TY + 7, NP = W * H, NS = (NP + NT - 1) / NT;
     constexpr int RW = TXW + 1, RH = TY + 1;          // the fine residual region
     constexpr int CXN = TXW / 2, CYN = TY / 2;        // the coarse tile
-    static_assert(CXN * CYN <= 256, "one coarse point per thread");
+    static_assert(CXN * CYN <= NT, "one coarse point per thread");
     __shared__ cx<T> L0[ZERO ? 1 : 2][ZERO ? 1 : NP], L1[2][NP], L2[2][NP];
     __shared__ cx<T> R[2][RH * RW];
     const int mx = P.mx, my = P.my, mz = P.mz;
@@ -1394,7 +1394,7 @@ __global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u
     int rofs[NS];   // index of the slot in the residual plane (stage 3)
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        const int t = threadIdx.x + 256 * k;
+        const int t = threadIdx.x + NT * k;
         const int r = t / W, c = t - r * W;
         const int gx = x0 - 3 + c, gy = y0 - 3 + r;
         const bool v = t < NP;
@@ -1469,7 +1469,7 @@ __global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u
             cx<T> *l0w = L0[z & 1];
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                const int t = threadIdx.x + 256 * k;
+                const int t = threadIdx.x + NT * k;
                 a0[k] = a1[k];
                 a1[k] = a2[k];
                 a2[k] = un[k];
@@ -1484,7 +1484,7 @@ __global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u
             const bool pin = p1 >= 0 && p1 < mz;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                const int t = threadIdx.x + 256 * k;
+                const int t = threadIdx.x + NT * k;
                 c0[k] = c1[k];
                 c1[k] = c2[k];
                 cx<T> v = zero;
@@ -1511,7 +1511,7 @@ __global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u
             const bool wr = p2 >= z0 && p2 < z1;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                const int t = threadIdx.x + 256 * k;
+                const int t = threadIdx.x + NT * k;
                 e0[k] = e1[k];
                 e1[k] = e2[k];
                 cx<T> v = zero;
@@ -1533,7 +1533,7 @@ __global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u
             const bool pin = p3 < mz;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                const int t = threadIdx.x + 256 * k;
+                const int t = threadIdx.x + NT * k;
                 if (slot_in(st3, k)) {
                     cx<T> r = zero;
                     if (pin && slot_in(ing, k)) {
@@ -1589,8 +1589,8 @@ __global__ __launch_bounds__(256) void k_sweep2rr_3d(const cx<T> *__restrict__ u
     }
 }
 
-// Tile of the fused pre-smoothing + residual + restriction pass.
-constexpr int SRR3_TXW = 32, SRR3_TY = 8;   // measured at 511^3: 32 x 8, 32 x 12 and 16 x 16 alike, 32 x 16 (two waves per SIMD) and 48 x 8 slower
+// Tile and block size of the fused pre-smoothing + residual + restriction pass.
+constexpr int SRR3_TXW = 32, SRR3_TY = 16, SRR3_NT = 512;   // measured at 511^3 (solve): 24.24 ms against 24.68 with 32 x 8 tiles of 256 threads, 24.64 with 1024 threads; 32 x 24 and 48 x 8 slower
 
 bool sweep2rr_3d_fits(const LevelGeom &g) { return g.dim == 3 && g.m[0] >= 3 && g.m[1] >= 3 && g.m[2] >= 3; }
 
@@ -1598,22 +1598,23 @@ template <typename T>
 void launch_sweep2rr_3d(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *b, const cx<T> *q,
                         cx<T> *out, cx<T> *bc, hipStream_t s, bool finest, const int *stop)
 {
-    const int tx = (g.m[0] + SRR3_TXW - 1) / SRR3_TXW, ty = (g.m[1] + SRR3_TY - 1) / SRR3_TY;
+    constexpr int TX = SRR3_TXW, TY = SRR3_TY, NT = SRR3_NT;
+    const int tx = (g.m[0] + TX - 1) / TX, ty = (g.m[1] + TY - 1) / TY;
     int tz = planes_per_block((long)tx * ty, g.m[2], TZ3);
     tz = std::max(2, tz & ~1);   // even: the coarse planes of a block are whole
     const int nb = tx * ty * ((g.m[2] + tz - 1) / tz);
     if (!u && finest)
-        hipLaunchKernelGGL((k_sweep2rr_3d<T, true, SRR3_TY, SRR3_TXW, 1>), dim3(nb), dim3(256), 0, s, b, b, q, out, bc,
-                           P, tx, ty, tz, stop);
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, true, TY, TX, 1, NT>), dim3(nb), dim3(NT), 0, s, b, b, q, out, bc, P, tx,
+                           ty, tz, stop);
     else if (!u)
-        hipLaunchKernelGGL((k_sweep2rr_3d<T, true, SRR3_TY, SRR3_TXW, 0>), dim3(nb), dim3(256), 0, s, b, b, q, out, bc,
-                           P, tx, ty, tz, stop);
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, true, TY, TX, 0, NT>), dim3(nb), dim3(NT), 0, s, b, b, q, out, bc, P, tx,
+                           ty, tz, stop);
     else if (finest)
-        hipLaunchKernelGGL((k_sweep2rr_3d<T, false, SRR3_TY, SRR3_TXW, 1>), dim3(nb), dim3(256), 0, s, u, b, q, out,
-                           bc, P, tx, ty, tz, stop);
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, false, TY, TX, 1, NT>), dim3(nb), dim3(NT), 0, s, u, b, q, out, bc, P,
+                           tx, ty, tz, stop);
     else
-        hipLaunchKernelGGL((k_sweep2rr_3d<T, false, SRR3_TY, SRR3_TXW, 0>), dim3(nb), dim3(256), 0, s, u, b, q, out,
-                           bc, P, tx, ty, tz, stop);
+        hipLaunchKernelGGL((k_sweep2rr_3d<T, false, TY, TX, 0, NT>), dim3(nb), dim3(NT), 0, s, u, b, q, out, bc, P,
+                           tx, ty, tz, stop);
 }
 template void launch_sweep2rr_3d<float>(const LevelGeom &, const Stencil<float> &, const cf *, const cf *, const cf *,
                                         cf *, cf *, hipStream_t, bool, const int *);
