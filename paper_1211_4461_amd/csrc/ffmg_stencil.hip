@@ -608,9 +608,9 @@ __global__ __launch_bounds__(256) void k_sweep3d(const cx<T> *__restrict__ u, co
 }
 
 // Two weighted-Jacobi sweeps in one z-marching pass (temporal blocking).  A
-// block owns a TXW x TY output tile of tz planes.  Its 256 threads cover the
+// block owns a TXW x TY output tile of tz planes.  Its NT threads cover the
 // tile with a two-point halo, (TXW + 4) x (TY + 4) columns, thread t taking
-// the columns t, t + 256, ...; every thread keeps a column's last three
+// the columns t, t + NT, ...; every thread keeps a column's last three
 // values of each stage in registers (the z-neighbours) and the stage's
 // current plane goes through LDS for the x/y neighbours:
 //   stage 0  the input at plane z: u (SRC_MEM) or u + P e_c (SRC_PROL, the
@@ -628,17 +628,17 @@ __global__ __launch_bounds__(256) void k_sweep3d(const cx<T> *__restrict__ u, co
 // a column are read at stage 1 and kept for stage 2.  The per-point
 // arithmetic and its order are those of the single sweeps, so the result is
 // bit for bit that of two k_stencil3d / k_sweep3d passes.
-template <typename T, int SRC, int TY, int TAG, int TXW>
-__global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
+template <typename T, int SRC, int TY, int TAG, int TXW, int NT = 256>
+__global__ __launch_bounds__(NT) void k_sweep2_3d(const cx<T> *__restrict__ u, const cx<T> *__restrict__ ec,
                                                    const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                    cx<T> *__restrict__ out, Stencil<T> P, int tiles_x, int tiles_y,
                                                    int tz, const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    constexpr int W = TXW + 4, H = TY + 4, NP = W * H, NS = (NP + 255) / 256;
+    constexpr int W = TXW + 4, H = TY + 4, NP = W * H, NS = (NP + NT - 1) / NT;
     constexpr bool PROL = (SRC == SRC_PROL), ZERO = (SRC == SRC_ZERO2);
     constexpr int CW = TXW / 2 + 4, CH = TY / 2 + 4, NCS = PROL ? 4 : 1;
-    constexpr int NCL = PROL ? (CH * CW + 255) / 256 : 1;   // coarse values per thread and plane
+    constexpr int NCL = PROL ? (CH * CW + NT - 1) / NT : 1;   // coarse values per thread and plane
     __shared__ cx<T> L0[ZERO ? 1 : 2][ZERO ? 1 : NP], L1[2][NP];
     __shared__ cx<T> cs[NCS][PROL ? CH : 1][PROL ? CW : 1];
     // the coarse correction combined in z for a fine plane (the first step of
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
     unsigned ing = 0, st1 = 0, st2 = 0;   // per slot: in the grid (x, y), stage-1 region, output
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        const int t = threadIdx.x + 256 * k;
+        const int t = threadIdx.x + NT * k;
         const int r = t / W, c = t - r * W;
         const int gx = x0 - 2 + c, gy = y0 - 2 + r;
         const bool v = t < NP;
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
     unsigned offc[NCL];
 #pragma unroll
     for (int i = 0; i < NCL; ++i) {
-        const int t = threadIdx.x + 256 * i;
+        const int t = threadIdx.x + NT * i;
         const int yy = t / CW, xx = t - yy * CW;
         const int ax = cx0 + xx, ay = cy0 + yy;
         const bool in = t < CH * CW && ax >= 0 && ax < mxc && ay >= 0 && ay < myc;
@@ -700,7 +700,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
         cx<T> *dst = &cs[a & (NCS - 1)][0][0];
 #pragma unroll
         for (int i = 0; i < NCL; ++i) {
-            const int t = threadIdx.x + 256 * i;
+            const int t = threadIdx.x + NT * i;
             if (t < CH * CW) dst[t] = creg[i];
         }
     };
@@ -711,7 +711,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
         const int az = ((z + 1) >> 1) - 1;
         const cx<T> *c0 = &cs[az & (NCS - 1)][0][0], *c1 = &cs[(az + 1) & (NCS - 1)][0][0];
         cx<T> *dst = ezs[z & 1];
-        for (int t = threadIdx.x; t < CH * CW; t += 256) dst[t] = zpair(wz[0], c0[t], wz[1], c1[t]);
+        for (int t = threadIdx.x; t < CH * CW; t += NT) dst[t] = zpair(wz[0], c0[t], wz[1], c1[t]);
     };
     // the x/y step at slot k: sum over (y, x) neighbours of (wx wy) ez, y outer
     // The weights depend only on the parities of the fine coordinates (x0 and
@@ -721,7 +721,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
     unsigned par = 0;    // bits 2k, 2k + 1: parity of fx, fy of slot k
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
-        const int t = threadIdx.x + 256 * k;
+        const int t = threadIdx.x + NT * k;
         const int r = t / W, c = t - r * W;
         const int fx = x0 - 2 + c + 1, fy = y0 - 2 + r + 1;
         eoff[k] = (t < NP) ? ((fy >> 1) - 1 - cy0) * CW + ((fx >> 1) - 1 - cx0) : 0;
@@ -818,7 +818,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
             const bool zin = z >= 0 && z < mz;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                const int t = threadIdx.x + 256 * k;
+                const int t = threadIdx.x + NT * k;
                 cx<T> v = un[k];
                 if (PROL && zin && slot_in(ing, k)) v = v + interp_xy(k, ezs[z & 1]);
                 a0[k] = a1[k];
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
             const bool pin = p1 >= 0 && p1 < mz;
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                const int t = threadIdx.x + 256 * k;
+                const int t = threadIdx.x + NT * k;
                 c0[k] = c1[k];
                 c1[k] = c2[k];
                 cx<T> v = zero, wj = zero;
@@ -860,7 +860,7 @@ __global__ __launch_bounds__(256) void k_sweep2_3d(const cx<T> *__restrict__ u, 
             const cx<T> *l1r = L1[p2 & 1];
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                const int t = threadIdx.x + 256 * k;
+                const int t = threadIdx.x + NT * k;
                 if (slot_in(st2, k)) {
                     cx<T> N = nsum_xy(P, l1r[t - 1], l1r[t + 1], l1r[t - W], l1r[t + W]);
                     N = nsum_add_z(P, N, c0[k], c2[k]);
@@ -1014,7 +1014,7 @@ template <typename T> constexpr int sweep2_rows(int shape)
 }
 constexpr int sweep2_width(int shape) { return shape == 3 ? 32 : 64; }
 
-template <typename T, int TY, int TXW>
+template <typename T, int TY, int TXW, int NT = 256>
 static void launch_sweep2_3d_tile(const LevelGeom &g, const Stencil<T> &P, const cx<T> *u, const cx<T> *ec,
                                   const cx<T> *b, const cx<T> *q, cx<T> *out, hipStream_t s, bool finest,
                                   const int *stop, bool zero)
@@ -1025,24 +1025,24 @@ static void launch_sweep2_3d_tile(const LevelGeom &g, const Stencil<T> &P, const
     if (zero) {
         // u is not read: any valid pointer serves the unused loads' base
         if (finest)
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 1, TXW>), dim3(nb), dim3(256), 0, s, b, ec, b, q, out,
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 1, TXW, NT>), dim3(nb), dim3(NT), 0, s, b, ec, b, q, out,
                                P, tx, ty, tz, stop);
         else
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 0, TXW>), dim3(nb), dim3(256), 0, s, b, ec, b, q, out,
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_ZERO2, TY, 0, TXW, NT>), dim3(nb), dim3(NT), 0, s, b, ec, b, q, out,
                                P, tx, ty, tz, stop);
     } else if (ec) {
         if (finest)
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 1, TXW>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out,
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 1, TXW, NT>), dim3(nb), dim3(NT), 0, s, u, ec, b, q, out,
                                P, tx, ty, tz, stop);
         else
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 0, TXW>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out,
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_PROL, TY, 0, TXW, NT>), dim3(nb), dim3(NT), 0, s, u, ec, b, q, out,
                                P, tx, ty, tz, stop);
     } else {
         if (finest)
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 1, TXW>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P,
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 1, TXW, NT>), dim3(nb), dim3(NT), 0, s, u, ec, b, q, out, P,
                                tx, ty, tz, stop);
         else
-            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 0, TXW>), dim3(nb), dim3(256), 0, s, u, ec, b, q, out, P,
+            hipLaunchKernelGGL((k_sweep2_3d<T, SRC_MEM, TY, 0, TXW, NT>), dim3(nb), dim3(NT), 0, s, u, ec, b, q, out, P,
                                tx, ty, tz, stop);
     }
 }
