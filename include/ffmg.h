@@ -484,8 +484,9 @@ ffmg_status mg_profile_durations(ffmg_handle *h, int kernel, double *ms, int64_t
  * and 8 (variant 2), 32-point-wide tiles of 16 and 8 rows for the pass that
  * interpolates the coarse correction and the variant-0 tiles for the others
  * (variant 3), variant 3 with the two FP32 pre-smoothing sweeps, the residual
- * and its full weighting in one pass (variant 4; FP64 levels as variant 3),
- * or one pass per sweep (variant 1); one variant for 2D and tile_config 1.
+ * and its full weighting in one pass (variant 4, the default of FFMG_FP32_IR
+ * handles; FP64 levels as variant 3), or one pass per sweep (variant 1); one
+ * variant for 2D and tile_config 1.
  * FFMG_TUNE_BATCH (set on the first handle of a batch, 2D FFMG_FP32_IR fused
  * handles): the tile heights of mg_solve_batched's smoothing and one-pass
  * pre-smoothing launches, (8, 16) rows (variant 0), (4, 16) (1), (16, 16) (2)

@@ -83,7 +83,9 @@ struct ffmg_handle {
     int smooth_coarse_variant = 0;   // index into SMOOTH_TH, coarser levels (autotuned)
     int pre_variant = 0;             // FFMG_TUNE_PRE: 0 fused pre-smoothing + residual + restriction (autotuned)
     int batch_variant = 0;           // FFMG_TUNE_BATCH: tile heights of batched solves led by this handle
-    int sweep3d_variant = 0;         // FFMG_TUNE_SWEEP3D: 0/2/3 two sweeps per 3D pass (tile shapes), 1 one (autotuned)
+    int sweep3d_variant = 0;         // FFMG_TUNE_SWEEP3D: 0/2/3 two sweeps per 3D pass (tile shapes), 1 one, 4 the
+                                     // FP32 pre-smoothing pair fused with residual + restriction (4 for 3D FP32_IR
+                                     // handles at setup; autotuned)
     ffmg::TailParams<double> tail64{};
     ffmg::TailParams<float> tail32{};
     ffmg::FarFieldPlan *ff = nullptr;
