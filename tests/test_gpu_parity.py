@@ -350,6 +350,54 @@ def test_fused_3d_path_is_bitwise_identical(ff, orc, n):
                 assert torch.equal(uf, ur), (fk, v, rep)
 
 
+def test_fused_3d_path_on_an_anisotropic_grid(ff):
+    """Every 3D kernel variant on a grid of 63 x 31 x 31 interior points (x
+    over two ragged tiles, y and z over one; a 15 x 7 x 7 coarsest level): FP64
+    V-cycles and FP32-in-FP64 solves (the default variant: the pre-smoothing
+    pair, residual and restriction in one pass) equal the reference kernels'
+    bit for bit."""
+    n = [64, 32, 32]
+    shape = (n[2] - 1, n[1] - 1, n[0] - 1)
+    z = [np.linspace(-4.0, 4.0, m + 1)[1:-1] for m in n]
+    Z, Y, X = np.meshgrid(z[2], z[1], z[0], indexing="ij")
+    coef = torch.from_numpy(0.6 * np.exp(-(X * X + Y * Y + Z * Z) / 3.0) + 0.0j).cuda()
+
+    def handle(**opt):
+        return ff.mg_setup(3, n, [-4.0] * 3, [4.0] * 3, math.pi / 6, coef, k0=1.1,
+                           options=ff.default_options(**opt))
+
+    eta = [0.6, 0.0, 0.8]
+    hr = handle(tile_config=1)
+    b = ff.mg_rhs_plane_wave(hr, eta, torch.empty(shape, dtype=torch.complex128, device="cuda"))
+    ur = torch.zeros_like(b)
+    for _ in range(2):
+        ff.mg_vcycle(hr, b, ur)
+    for v in range(5):
+        hf = handle()
+        ff.mg_tune_set(hf, v, ff.TUNE_SWEEP3D)
+        uf = torch.zeros_like(b)
+        for _ in range(2):
+            ff.mg_vcycle(hf, b, uf)
+        torch.cuda.synchronize()
+        assert torch.equal(uf, ur), v
+        hf.destroy()
+    hr.destroy()
+    hr = handle(tile_config=1, precision=ff.FP32_IR, fmg_cycles=2)
+    ur = torch.zeros_like(b)
+    ir = ff.mg_solve(hr, b, ur, tol=1e-9)
+    hf = handle(precision=ff.FP32_IR, fmg_cycles=2)
+    assert ff.mg_tune_get(hf, ff.TUNE_SWEEP3D) == 4
+    for v in (4, 3, 0):
+        ff.mg_tune_set(hf, v, ff.TUNE_SWEEP3D)
+        uf = torch.zeros_like(b)
+        i1 = ff.mg_solve(hf, b, uf, tol=1e-9)
+        torch.cuda.synchronize()
+        assert ir.status == 0 and i1.cycles == ir.cycles and i1.rel_residual == ir.rel_residual, v
+        assert torch.equal(uf, ur), v
+    hf.destroy()
+    hr.destroy()
+
+
 @pytest.mark.parametrize("n", [256, 512])
 def test_tail_variants_are_bitwise_identical_and_tuned(ff, orc, n, tmp_path):
     """The LDS tail runs the per-point arithmetic of the grid-wide kernels, so
