@@ -24,11 +24,12 @@
 // sums, so no pass waits on a one-block kernel): m + 3 launches per step.
 // The reference kernel path (a pass per product and one for the
 // orthogonalisation, each finished by a one-block kernel: 4 m + 3 launches)
-// computes the same values in the same order, so both give the same bits.  Partial sums are FP64 in both
-// precisions.  A level of at most GM_BLOCK_MAX_POINTS points runs the whole
-// step in one 1024-thread workgroup (for small m with the vectors in
-// registers and the stencil's input staged in LDS; the reference path reads
-// and writes them in global memory).
+// computes the same values in the same order, so both give the same bits.
+// Partial sums are FP64 in both precisions.  A level of at most
+// GM_BLOCK_MAX_POINTS points runs the whole step in one workgroup, of 256
+// threads up to 1024 points and 1024 threads above (for small m with the
+// vectors in registers and the stencil's input staged in LDS; the reference
+// path reads and writes them in global memory).
 #include "ffmg_internal.hpp"
 #include "ffmg_point.hpp"
 
@@ -436,15 +437,17 @@ __global__ __launch_bounds__(256) void k_gm_update(cx<T> *__restrict__ u, const 
     }
 }
 
-// A whole GMRES(M) step on a small level in one 1024-thread workgroup: the
+// A whole GMRES(M) step on a small level in one workgroup of BT threads: the
 // same passes, separated by workgroup barriers (global memory written before
 // a barrier is seen after it within the workgroup), the sums reduced in LDS
 // and the small solve by thread 0.
 constexpr int GM_BLOCK_THREADS = 1024;
+constexpr int GM_SMALL_THREADS = 256;
+constexpr size_t GM_SMALL_POINTS = 1024;   // = GM_REG_PTS * GM_SMALL_THREADS
 constexpr size_t GM_BLOCK_MAX_POINTS = 4096;
 
-template <int NV>
-__device__ __forceinline__ void block_reduce_1024(double (&acc)[NV], double *out, double (*red)[2 * GMRES_MAX_M])
+template <int NV, int BT>
+__device__ __forceinline__ void block_reduce_bt(double (&acc)[NV], double *out, double (*red)[2 * GMRES_MAX_M])
 {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -456,13 +459,13 @@ __device__ __forceinline__ void block_reduce_1024(double (&acc)[NV], double *out
     __syncthreads();
     if (threadIdx.x < NV) {
         double a = 0.0;
-        for (int w_ = 0; w_ < GM_BLOCK_THREADS / 64; ++w_) a += red[w_][threadIdx.x];
+        for (int w_ = 0; w_ < BT / 64; ++w_) a += red[w_][threadIdx.x];
         out[threadIdx.x] = a;
     }
     __syncthreads();
 }
 
-template <typename T, int DIM, int NJ>
+template <typename T, int DIM, int NJ, int BT>
 __device__ __forceinline__ void gm_block_arnoldi(cx<T> *__restrict__ Z, size_t N, const cx<T> *__restrict__ q,
                                                  const Stencil<T> &P, double *n, double *d,
                                                  double (*red)[2 * GMRES_MAX_M])
@@ -473,7 +476,7 @@ __device__ __forceinline__ void gm_block_arnoldi(cx<T> *__restrict__ Z, size_t N
     double acc[2 * NJ];
 #pragma unroll
     for (int v = 0; v < 2 * NJ; ++v) acc[v] = 0.0;
-    for (size_t p = threadIdx.x; p < N; p += GM_BLOCK_THREADS) {
+    for (size_t p = threadIdx.x; p < N; p += BT) {
         cx<T> Wp = apply_at<T, DIM>(P, zj, q[p], p);
         w[p] = Wp;
         const double wr = Wp.re, wi = Wp.im;
@@ -484,7 +487,7 @@ __device__ __forceinline__ void gm_block_arnoldi(cx<T> *__restrict__ Z, size_t N
             acc[2 * i + 1] += (double)zi.re * wi - (double)zi.im * wr;
         }
     }
-    block_reduce_1024<2 * NJ>(acc, d + 2 * (j * GMRES_MAX_M), red);
+    block_reduce_bt<2 * NJ, BT>(acc, d + 2 * (j * GMRES_MAX_M), red);
     cx<T> g[NJ];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
@@ -493,7 +496,7 @@ __device__ __forceinline__ void gm_block_arnoldi(cx<T> *__restrict__ Z, size_t N
         g[i] = cx<T>{T(ni > 0.0 ? dr / ni : 0.0), T(ni > 0.0 ? di / ni : 0.0)};
     }
     double nacc[1] = {0.0};
-    for (size_t p = threadIdx.x; p < N; p += GM_BLOCK_THREADS) {
+    for (size_t p = threadIdx.x; p < N; p += BT) {
         cx<T> v = w[p];
 #pragma unroll
         for (int i = 0; i < NJ; ++i) {
@@ -503,28 +506,28 @@ __device__ __forceinline__ void gm_block_arnoldi(cx<T> *__restrict__ Z, size_t N
         w[p] = v;
         nacc[0] += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
     }
-    block_reduce_1024<1>(nacc, n + NJ, red);
+    block_reduce_bt<1, BT>(nacc, n + NJ, red);
 }
 
-template <typename T, int DIM, int NJ, int M>
+template <typename T, int DIM, int NJ, int M, int BT>
 __device__ __forceinline__ void gm_block_arnoldi_all(cx<T> *Z, size_t N, const cx<T> *q, const Stencil<T> &P,
                                                      double *n, double *d, double (*red)[2 * GMRES_MAX_M])
 {
-    gm_block_arnoldi<T, DIM, NJ>(Z, N, q, P, n, d, red);
-    if constexpr (NJ < M) gm_block_arnoldi_all<T, DIM, NJ + 1, M>(Z, N, q, P, n, d, red);
+    gm_block_arnoldi<T, DIM, NJ, BT>(Z, N, q, P, n, d, red);
+    if constexpr (NJ < M) gm_block_arnoldi_all<T, DIM, NJ + 1, M, BT>(Z, N, q, P, n, d, red);
 }
 
-template <typename T, int DIM, int M>
-__global__ __launch_bounds__(1024) void k_gm_step_block(const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+template <typename T, int DIM, int M, int BT>
+__global__ __launch_bounds__(BT) void k_gm_step_block(const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                         cx<T> *__restrict__ u, int zero, cx<T> *__restrict__ Z,
                                                         Stencil<T> P, size_t N, const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    __shared__ double red[GM_BLOCK_THREADS / 64][2 * GMRES_MAX_M];
+    __shared__ double red[BT / 64][2 * GMRES_MAX_M];
     __shared__ double n[GMRES_MAX_M + 1], d[2 * GMRES_MAX_M * GMRES_MAX_M], c[2 * GMRES_MAX_M];
     __shared__ GmWork W;
     double acc[1] = {0.0};
-    for (size_t p = threadIdx.x; p < N; p += GM_BLOCK_THREADS) {
+    for (size_t p = threadIdx.x; p < N; p += BT) {
         cx<T> r = b[p];
         if (zero) {
             u[p] = cx<T>{T(0), T(0)};
@@ -535,14 +538,14 @@ __global__ __launch_bounds__(1024) void k_gm_step_block(const cx<T> *__restrict_
         Z[p] = r;
         acc[0] += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
     }
-    block_reduce_1024<1>(acc, n, red);
-    gm_block_arnoldi_all<T, DIM, 1, M>(Z, N, q, P, n, d, red);
+    block_reduce_bt<1, BT>(acc, n, red);
+    gm_block_arnoldi_all<T, DIM, 1, M, BT>(Z, N, q, P, n, d, red);
     if (threadIdx.x == 0) gm_solve_small(n, d, M, c, W);
     __syncthreads();
     cx<T> cc[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) cc[j] = cx<T>{T(c[2 * j]), T(c[2 * j + 1])};
-    for (size_t p = threadIdx.x; p < N; p += GM_BLOCK_THREADS) {
+    for (size_t p = threadIdx.x; p < N; p += BT) {
         cx<T> v = u[p];
 #pragma unroll
         for (int j = 0; j < M; ++j) {
@@ -554,13 +557,13 @@ __global__ __launch_bounds__(1024) void k_gm_step_block(const cx<T> *__restrict_
 }
 
 // The same step with the level's vectors held in registers (thread t holds
-// the points p = t + 1024 k, k < GM_REG_PTS) and only the vector that A is
+// the points p = t + BT k, k < GM_REG_PTS) and only the vector that A is
 // applied to staged in LDS (dynamic shared memory, N values): no global
 // traffic inside the step but the loads of b, q, u and the store of u.  The
 // values, the sums and their order are those of k_gm_step_block.
-constexpr int GM_REG_PTS = (int)(GM_BLOCK_MAX_POINTS / GM_BLOCK_THREADS);
+constexpr int GM_REG_PTS = (int)(GM_BLOCK_MAX_POINTS / GM_BLOCK_THREADS);   // also for the small blocks
 
-template <typename T, int DIM, int NJ, int M>
+template <typename T, int DIM, int NJ, int M, int BT>
 __device__ __forceinline__ void gm_reg_arnoldi(cx<T> (&Z)[M + 1][GM_REG_PTS], const cx<T> (&qv)[GM_REG_PTS],
                                                cx<T> *stage, const Stencil<T> &P, int N, double *n, double *d,
                                                double (*red)[2 * GMRES_MAX_M])
@@ -569,7 +572,7 @@ __device__ __forceinline__ void gm_reg_arnoldi(cx<T> (&Z)[M + 1][GM_REG_PTS], co
     // the reduction before ended with a barrier: every thread is past its reads of the stage
 #pragma unroll
     for (int k = 0; k < GM_REG_PTS; ++k) {
-        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        const int p = (int)threadIdx.x + BT * k;
         if (p < N) stage[p] = Z[j][k];
     }
     __syncthreads();
@@ -578,7 +581,7 @@ __device__ __forceinline__ void gm_reg_arnoldi(cx<T> (&Z)[M + 1][GM_REG_PTS], co
     for (int v = 0; v < 2 * NJ; ++v) acc[v] = 0.0;
 #pragma unroll
     for (int k = 0; k < GM_REG_PTS; ++k) {
-        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        const int p = (int)threadIdx.x + BT * k;
         if (p < N) {
             const cx<T> Wp = apply_at_f<T, DIM>(P, [&](size_t i) { return stage[i]; }, Z[j][k], qv[k], (size_t)p);
             Z[NJ][k] = Wp;
@@ -591,7 +594,7 @@ __device__ __forceinline__ void gm_reg_arnoldi(cx<T> (&Z)[M + 1][GM_REG_PTS], co
             }
         }
     }
-    block_reduce_1024<2 * NJ>(acc, d + 2 * (j * GMRES_MAX_M), red);
+    block_reduce_bt<2 * NJ, BT>(acc, d + 2 * (j * GMRES_MAX_M), red);
     cx<T> g[NJ];
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
@@ -602,7 +605,7 @@ __device__ __forceinline__ void gm_reg_arnoldi(cx<T> (&Z)[M + 1][GM_REG_PTS], co
     double nacc[1] = {0.0};
 #pragma unroll
     for (int k = 0; k < GM_REG_PTS; ++k) {
-        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        const int p = (int)threadIdx.x + BT * k;
         if (p < N) {
             cx<T> v = Z[NJ][k];
 #pragma unroll
@@ -614,26 +617,26 @@ __device__ __forceinline__ void gm_reg_arnoldi(cx<T> (&Z)[M + 1][GM_REG_PTS], co
             nacc[0] += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
         }
     }
-    block_reduce_1024<1>(nacc, n + NJ, red);
-    if constexpr (NJ < M) gm_reg_arnoldi<T, DIM, NJ + 1, M>(Z, qv, stage, P, N, n, d, red);
+    block_reduce_bt<1, BT>(nacc, n + NJ, red);
+    if constexpr (NJ < M) gm_reg_arnoldi<T, DIM, NJ + 1, M, BT>(Z, qv, stage, P, N, n, d, red);
 }
 
-template <typename T, int DIM, int M>
-__global__ __launch_bounds__(1024) void k_gm_step_reg(const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
+template <typename T, int DIM, int M, int BT>
+__global__ __launch_bounds__(BT) void k_gm_step_reg(const cx<T> *__restrict__ b, const cx<T> *__restrict__ q,
                                                       cx<T> *__restrict__ u, int zero, Stencil<T> P, int N,
                                                       const int *__restrict__ stop)
 {
     if (stop && *stop) return;
     extern __shared__ __attribute__((aligned(16))) unsigned char gm_stage_raw[];
     cx<T> *stage = reinterpret_cast<cx<T> *>(gm_stage_raw);
-    __shared__ double red[GM_BLOCK_THREADS / 64][2 * GMRES_MAX_M];
+    __shared__ double red[BT / 64][2 * GMRES_MAX_M];
     __shared__ double n[GMRES_MAX_M + 1], d[2 * GMRES_MAX_M * GMRES_MAX_M], c[2 * GMRES_MAX_M];
     __shared__ GmWork W;
     const cx<T> zc = {T(0), T(0)};
     cx<T> qv[GM_REG_PTS], uv[GM_REG_PTS], Z[M + 1][GM_REG_PTS];
 #pragma unroll
     for (int k = 0; k < GM_REG_PTS; ++k) {
-        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        const int p = (int)threadIdx.x + BT * k;
         qv[k] = uv[k] = zc;
 #pragma unroll
         for (int j = 0; j <= M; ++j) Z[j][k] = zc;
@@ -649,7 +652,7 @@ __global__ __launch_bounds__(1024) void k_gm_step_reg(const cx<T> *__restrict__ 
     double acc[1] = {0.0};
 #pragma unroll
     for (int k = 0; k < GM_REG_PTS; ++k) {
-        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        const int p = (int)threadIdx.x + BT * k;
         if (p < N) {
             cx<T> r = b[p];
             if (!zero) {
@@ -660,8 +663,8 @@ __global__ __launch_bounds__(1024) void k_gm_step_reg(const cx<T> *__restrict__ 
             acc[0] += (double)r.re * (double)r.re + (double)r.im * (double)r.im;
         }
     }
-    block_reduce_1024<1>(acc, n, red);
-    gm_reg_arnoldi<T, DIM, 1, M>(Z, qv, stage, P, N, n, d, red);
+    block_reduce_bt<1, BT>(acc, n, red);
+    gm_reg_arnoldi<T, DIM, 1, M, BT>(Z, qv, stage, P, N, n, d, red);
     if (threadIdx.x == 0) gm_solve_small(n, d, M, c, W);
     __syncthreads();
     cx<T> cc[M];
@@ -669,7 +672,7 @@ __global__ __launch_bounds__(1024) void k_gm_step_reg(const cx<T> *__restrict__ 
     for (int j = 0; j < M; ++j) cc[j] = cx<T>{T(c[2 * j]), T(c[2 * j + 1])};
 #pragma unroll
     for (int k = 0; k < GM_REG_PTS; ++k) {
-        const int p = (int)threadIdx.x + GM_BLOCK_THREADS * k;
+        const int p = (int)threadIdx.x + BT * k;
         if (p < N) {
             cx<T> v = uv[k];
 #pragma unroll
@@ -688,18 +691,19 @@ __global__ __launch_bounds__(1024) void k_gm_step_reg(const cx<T> *__restrict__ 
 template <typename T, int M>
 constexpr bool gm_reg_step() { return sizeof(T) == 4 ? M <= 4 : M <= 3; }
 
-template <typename T, int DIM, int M>
+template <typename T, int DIM, int M, int BT>
 static void launch_step_reg(const cx<T> *b, const cx<T> *q, cx<T> *u, bool zero, const Stencil<T> &P, size_t N,
                             hipStream_t s, const int *stop)
 {
     static const bool attr_set = [] {
-        (void)hipFuncSetAttribute((const void *)k_gm_step_reg<T, DIM, M>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(GM_BLOCK_MAX_POINTS * sizeof(cx<T>)));
+        (void)hipFuncSetAttribute((const void *)k_gm_step_reg<T, DIM, M, BT>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(GM_REG_PTS * BT * sizeof(cx<T>)));
         return true;
     }();
     (void)attr_set;
-    hipLaunchKernelGGL((k_gm_step_reg<T, DIM, M>), dim3(1), dim3(GM_BLOCK_THREADS), N * sizeof(cx<T>), s, b, q, u,
-                       zero ? 1 : 0, P, (int)N, stop);
+    hipLaunchKernelGGL((k_gm_step_reg<T, DIM, M, BT>), dim3(1), dim3(BT), N * sizeof(cx<T>), s, b, q, u, zero ? 1 : 0,
+                       P, (int)N, stop);
 }
 
 template <typename T, int DIM, int NJ, int M>
@@ -737,14 +741,22 @@ void launch_step_m(const LevelGeom &g, const Stencil<T> &P, const cx<T> *b, cons
 {
     const size_t N = g.N();
     if (N <= GM_BLOCK_MAX_POINTS) {   // small level: the whole step in one workgroup
+        // levels of at most GM_SMALL_POINTS points in a 256-thread workgroup (its
+        // block-wide sums take 4 waves instead of 16)
+        const bool small = N <= GM_SMALL_POINTS;
         if constexpr (gm_reg_step<T, M>()) {
             if (fused) {
-                launch_step_reg<T, DIM, M>(b, q, u, zero, P, N, s, stop);
+                if (small) launch_step_reg<T, DIM, M, GM_SMALL_THREADS>(b, q, u, zero, P, N, s, stop);
+                else launch_step_reg<T, DIM, M, GM_BLOCK_THREADS>(b, q, u, zero, P, N, s, stop);
                 return;
             }
         }
-        hipLaunchKernelGGL((k_gm_step_block<T, DIM, M>), dim3(1), dim3(GM_BLOCK_THREADS), 0, s, b, q, u,
-                           zero ? 1 : 0, Z, P, N, stop);
+        if (small)
+            hipLaunchKernelGGL((k_gm_step_block<T, DIM, M, GM_SMALL_THREADS>), dim3(1), dim3(GM_SMALL_THREADS), 0, s,
+                               b, q, u, zero ? 1 : 0, Z, P, N, stop);
+        else
+            hipLaunchKernelGGL((k_gm_step_block<T, DIM, M, GM_BLOCK_THREADS>), dim3(1), dim3(GM_BLOCK_THREADS), 0, s,
+                               b, q, u, zero ? 1 : 0, Z, P, N, stop);
         return;
     }
     const int nb = (int)std::min<size_t>((N + 255) / 256, GM_BLOCKS);
